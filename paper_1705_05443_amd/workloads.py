@@ -1,0 +1,82 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle runs.
+
+This module holds no arithmetic of the method: it only draws point sets and
+right-hand sides (NumPy PCG64) with the shapes and distributions of the
+paper's tests (uniform boxes as in Sec. 6.2, clustered volumes, the
+Chebyshev / shifted point pairs of the Cauchy-like tests of Sec. 6.3).  It
+imports nothing from the rest of the package.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def uniform(n: int, d: int, seed: int = 0) -> np.ndarray:
+    """n points uniform in [0,1)^d, FP64, row-major (n, d)."""
+    return np.random.default_rng(seed).random((n, d))
+
+
+def clusters(n: int, d: int = 3, seed: int = 0, ncl: int = 8, sigma: float = 0.02,
+             frac: float = 0.9) -> np.ndarray:
+    """Mixture: frac of the points from ncl equal-weight Gaussian clusters
+    (per-axis std sigma, centers uniform in [0.1,0.9]^d; samples falling
+    outside the unit cube are redrawn), the rest uniform in [0,1)^d."""
+    rng = np.random.default_rng(seed)
+    centers = 0.1 + 0.8 * rng.random((ncl, d))
+    nc = int(round(frac * n))
+    lab = rng.integers(0, ncl, size=nc)
+    pts = centers[lab] + sigma * rng.standard_normal((nc, d))
+    bad = np.any((pts < 0.0) | (pts >= 1.0), axis=1)
+    while bad.any():
+        pts[bad] = centers[lab[bad]] + sigma * rng.standard_normal((int(bad.sum()), d))
+        bad = np.any((pts < 0.0) | (pts >= 1.0), axis=1)
+    out = np.concatenate([pts, rng.random((n - nc, d))], axis=0)
+    return out[rng.permutation(n)]
+
+
+def chebyshev_pair(n: int, seed: int = 0, shift: float = 1e-3, shift_x: bool = False):
+    """(x, y) in 1D: one set at cos(pi(2i+1)/(2n)), the other shifted by
+    shift*U(0,1).  Default: x = roots, y = x + shift*U.  With shift_x the
+    roles swap (y = roots, x = roots + shift*U), which makes K.1 known in
+    closed form for the 1/(x-y) kernel."""
+    rng = np.random.default_rng(seed)
+    roots = np.cos(np.pi * (2.0 * np.arange(n) + 1.0) / (2.0 * n))
+    moved = roots + shift * rng.random(n)
+    if shift_x:
+        return moved[:, None].copy(), roots[:, None].copy()
+    return roots[:, None].copy(), moved[:, None].copy()
+
+
+def rhs(n: int, nrhs: int, seed: int = 0) -> np.ndarray:
+    """Right-hand sides N(0,1), (n, nrhs) row-major, drawn from seed + 100."""
+    return np.random.default_rng(seed + 100).standard_normal((n, nrhs))
+
+
+# The five workloads (sizes, kernels and parameters).  The point sets are
+# drawn by the functions above from the given seed.
+CONFIGS = {
+    "hss1d_inv_r_2048": dict(kind="uniform", n=2048, d=1, kernel="inv_r", adm=0, leaf=32,
+                             order=10, tol=1e-10, eps_svd=1e-10, tau=0.6, nrhs=1,
+                             root=((0.0,), 1.0), apply="f64"),
+    "h2_2d_log_65536": dict(kind="uniform", n=65536, d=2, kernel="log_r", adm=1, leaf=64,
+                            order=8, tol=1e-8, tau=0.7, nrhs=16, root=((0.0, 0.0), 1.0),
+                            apply="f64"),
+    "h2_3d_inv_r_clusters_1m": dict(kind="clusters", n=1 << 20, d=3, kernel="inv_r", adm=1,
+                                    leaf=128, order=5, tol=1e-6, tau=0.7, nrhs=64,
+                                    root=((0.0, 0.0, 0.0), 1.0), apply="f32"),
+    "hss1d_cauchy_1m": dict(kind="chebyshev_pair", n=1 << 20, d=1, kernel="cauchy", adm=0,
+                            leaf=64, order=16, tol=1e-8, eps_svd=1e-9, tau=0.6, nrhs=256,
+                            root=None, apply="f32"),
+}
+
+
+def points(cfg: dict, seed: int = 0, n: int | None = None):
+    """(x, y) for a workload dict; y is None when Y = X."""
+    n = cfg["n"] if n is None else n
+    if cfg["kind"] == "uniform":
+        return uniform(n, cfg["d"], seed), None
+    if cfg["kind"] == "clusters":
+        return clusters(n, cfg["d"], seed), None
+    if cfg["kind"] == "chebyshev_pair":
+        return chebyshev_pair(n, seed)
+    raise ValueError(cfg["kind"])

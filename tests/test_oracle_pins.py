@@ -1,0 +1,631 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: each test checks it against a
+closed form, a library routine, brute force on tiny inputs, an invariant
+that characterises the paper's definition, or a value the paper prints
+(fixtures in tests/golden/).
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.interpolate
+import scipy.linalg
+
+from oracle import oracle as O
+from paper_1705_05443_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def gold(name):
+    with open(os.path.join(GOLD, name)) as fh:
+        return json.load(fh)
+
+
+# --------------------------------------------------------------------------
+# kernel / dense reference
+# --------------------------------------------------------------------------
+def _cheb_logderiv(xs, N, dps=40):
+    """T_N'(x)/T_N(x) in high precision: with x = cos t, N sin(Nt)/(sin t cos(Nt));
+    with x = +-cosh t beyond [-1, 1], the hyperbolic form."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    out = []
+    for xi in np.asarray(xs).reshape(-1):
+        X = mp.mpf(float(xi))
+        if abs(X) <= 1:
+            t = mp.acos(X)
+            out.append(float(N * mp.sin(N * t) / (mp.sin(t) * mp.cos(N * t))))
+        else:
+            t = mp.acosh(abs(X))
+            v = N * mp.sinh(N * t) / (mp.sinh(t) * mp.cosh(N * t))
+            out.append(float(v if X > 0 else -v))
+    return np.array(out)
+
+
+def test_dense_cauchy_closed_form():
+    """Sum_j 1/(x - y_j) over the roots y_j of T_N equals T_N'(x)/T_N(x)
+    (logarithmic derivative of T_N), evaluated here in 40-digit arithmetic."""
+    N = 257
+    x, y = W.chebyshev_pair(N, seed=3, shift=1e-3, shift_x=True)
+    z = O.dense_matvec(x, y, np.ones(N), "cauchy")
+    ref = _cheb_logderiv(x, N)
+    assert np.max(np.abs(z - ref) / np.abs(ref)) < 1e-9
+
+
+def test_dense_diag_value_and_symmetry():
+    x = W.uniform(50, 2, 1)
+    B = O.kernel_block(x, x, "inv_r", diag=0.0)
+    assert np.all(np.diag(B) == 0.0)
+    assert np.array_equal(B, B.T)
+    B2 = O.kernel_block(x, x, "exp_r")
+    assert np.all(np.diag(B2) == 1.0)
+    # duplicate points are "x = y" (every coordinate equal)
+    xd = np.vstack([x[:3], x[:1]])
+    B3 = O.kernel_block(xd, xd, "log_r", diag=7.0)
+    assert B3[0, 3] == 7.0 and B3[3, 0] == 7.0
+    d = np.linalg.norm(x[0] - x[1])
+    assert abs(B3[0, 1] - np.log(d)) < 1e-15 * 10
+
+
+# --------------------------------------------------------------------------
+# adaptive partition (Sec. 3.1, Remark A.1)
+# --------------------------------------------------------------------------
+def _dyadic_bits(v, nbits):
+    """binary expansion bits of v in [0,1), exact via Fractions."""
+    f = Fraction(float(v))
+    out = []
+    for _ in range(nbits):
+        f *= 2
+        b = int(f >= 1)
+        out.append(b)
+        f -= b
+    return out
+
+
+def test_point_key_is_binary_expansion_on_unit_box():
+    """On the unit box every bisection midpoint is dyadic, so the half-box
+    choice at stage s along an axis is bit s+1 of the coordinate's binary
+    expansion; the key interleaves them axis 0 first (Morton)."""
+    rng = np.random.default_rng(5)
+    for d, adm in ((1, 0), (2, 1), (3, 1), (2, 0), (3, 0)):
+        stages = 10
+        for _ in range(40):
+            xv = rng.random(d)
+            key = O.point_key_of(xv, adm, np.zeros(d), np.ones(d), stages)
+            bits = [_dyadic_bits(xv[t], stages) for t in range(d)]
+            ref = 0
+            if adm == 1:
+                for s in range(stages):
+                    for t in range(d):
+                        ref = (ref << 1) | bits[t][s]
+            else:
+                depth = [0] * d
+                for s in range(stages):
+                    t = s % d
+                    ref = (ref << 1) | bits[t][depth[t]]
+                    depth[t] += 1
+            assert key == ref
+
+
+def _check_tree(o, x, y, leaf, adm, root=None):
+    nd = o.nodes()
+    bx = o.boxes()
+    sz = o.sizes()
+    d = sz["d"]
+    px, py = o.export(O.EX_PERM_X), o.export(O.EX_PERM_Y)
+    assert sorted(px.tolist()) == list(range(x.shape[0]))
+    assert sorted(py.tolist()) == list(range(y.shape[0]))
+    lv = o.export(O.EX_LEVELS)
+    assert nd[0, 0] == 1 and nd[0, 1] == -1
+    assert nd[0, 4:8].tolist() == [0, x.shape[0], 0, y.shape[0]]
+    nlev = sz["nlevels"]
+    assert lv[0] == 0 and lv[-1] == nd.shape[0] and len(lv) == nlev + 1
+    for l in range(1, nlev + 1):
+        assert np.all(nd[lv[l - 1]:lv[l], 0] == l)
+    for i in range(nd.shape[0]):
+        lev, par, fc, nc, xb, xe, yb, ye = nd[i]
+        assert xe >= xb and ye >= yb and (xe > xb or ye > yb)
+        if nc == 0:
+            assert (xe - xb) <= leaf and (ye - yb) <= leaf  # no depth cap hit here
+        else:
+            assert (xe - xb) > leaf or (ye - yb) > leaf
+            assert 1 <= nc <= (2 if adm == 0 else 2 ** d)
+            ch = list(range(fc, fc + nc))
+            assert nd[ch[0], 4] == xb and nd[ch[-1], 5] == xe
+            assert nd[ch[0], 6] == yb and nd[ch[-1], 7] == ye
+            for a, b in zip(ch[:-1], ch[1:]):
+                assert nd[a, 5] == nd[b, 4] and nd[a, 7] == nd[b, 6]
+            for c in ch:
+                assert nd[c, 1] == i and nd[c, 0] == lev + 1
+                # child box = parent box with one bound moved to the midpoint
+                axes = [(lev - 1) % d] if adm == 0 else list(range(d))
+                for t in range(d):
+                    lo, hi = bx[i, t], bx[i, 3 + t]
+                    mid = 0.5 * (lo + hi)
+                    clo, chi = bx[c, t], bx[c, 3 + t]
+                    if t in axes:
+                        assert (clo, chi) in ((lo, mid), (mid, hi))
+                    else:
+                        assert (clo, chi) == (lo, hi)
+        # points inside the box: lo <= v and (v < hi or hi is the root bound)
+        for pts, perm, b, e in ((x, px, xb, xe), (y, py, yb, ye)):
+            P = pts[perm[b:e]]
+            for t in range(d):
+                lo, hi = bx[i, t], bx[i, 3 + t]
+                assert np.all(P[:, t] >= lo)
+                assert np.all((P[:, t] < hi) | (hi == bx[0, 3 + t]))
+
+
+@pytest.mark.parametrize("case", [
+    dict(n=3000, d=1, adm=0, leaf=20, kind="uniform"),
+    dict(n=3000, d=2, adm=1, leaf=30, kind="uniform"),
+    dict(n=4000, d=3, adm=1, leaf=40, kind="clusters"),
+    dict(n=2000, d=2, adm=0, leaf=25, kind="uniform"),
+    dict(n=2500, d=3, adm=0, leaf=25, kind="clusters"),
+])
+def test_tree_invariants(case):
+    if case["kind"] == "uniform":
+        x = W.uniform(case["n"], case["d"], 11)
+    else:
+        x = W.clusters(case["n"], case["d"], 12)
+    o = O.Oracle(x, kernel="inv_r", leaf=case["leaf"], order=3, adm=case["adm"], tol=1e-3,
+                 root=(np.zeros(case["d"]), 1.0))
+    _check_tree(o, x, x, case["leaf"], case["adm"])
+
+
+def test_tree_invariants_x_ne_y_bounding_cube():
+    x, y = W.chebyshev_pair(3000, seed=2)
+    o = O.Oracle(x, y, kernel="cauchy", leaf=40, order=4, adm=0, tol=1e-4)
+    _check_tree(o, x, y, 40, 0)
+    b = o.boxes()[0]
+    assert b[0] == min(x.min(), y.min())
+    assert b[3] == b[0] + (max(x.max(), y.max()) - b[0])
+
+
+def test_leaf_order_is_full_bisection_order():
+    """Inside a leaf points follow their complete bisection path (then input
+    index); on the unit box that is the Morton order of the binary digits."""
+    x = W.uniform(1500, 2, 4)
+    o = O.Oracle(x, kernel="log_r", leaf=40, order=3, adm=1, tol=1e-3, root=((0, 0), 1.0))
+    px = o.export(O.EX_PERM_X)
+    keys = []
+    for a in range(x.shape[0]):
+        bits = [_dyadic_bits(x[a, t], 31) for t in range(2)]
+        k = 0
+        for s in range(31):
+            for t in range(2):
+                k = (k << 1) | bits[t][s]
+        keys.append((k, a))
+    ref = [a for _, a in sorted(keys)]
+    assert px.tolist() == ref
+
+
+# --------------------------------------------------------------------------
+# separation (Def. 2.1) and pair lists (3.3)-(3.5), (A.1)
+# --------------------------------------------------------------------------
+def test_fig2_1_worked_example():
+    g = gold("fig2_1_separated_intervals.json")
+    assert O.well_separated(g["box_i"]["lo"], g["box_i"]["hi"], g["box_j"]["lo"],
+                            g["box_j"]["hi"], g["tau"]) == g["separated"]
+    # slightly closer intervals are not separated
+    assert not O.well_separated([0.0], [1.0], [1.99], [2.99], 0.5)
+
+
+def test_well_separated_matches_sqrt_form_off_ties():
+    rng = np.random.default_rng(9)
+    n = 0
+    for _ in range(4000):
+        d = int(rng.integers(1, 4))
+        lo_i = rng.random(d) * 4
+        lo_j = rng.random(d) * 4
+        wi = rng.random() * 0.7
+        wj = rng.random() * 0.7
+        hi_i, hi_j = lo_i + wi, lo_j + wj
+        tau = float(rng.uniform(0.3, 0.9))
+        di = 0.5 * np.linalg.norm(hi_i - lo_i)
+        dj = 0.5 * np.linalg.norm(hi_j - lo_j)
+        D = np.linalg.norm(0.5 * (lo_i + hi_i) - 0.5 * (lo_j + hi_j))
+        if abs(di + dj - tau * D) < 1e-9:
+            continue
+        n += 1
+        assert O.well_separated(lo_i, hi_i, lo_j, hi_j, tau) == (di + dj <= tau * D)
+    assert n > 3900
+
+
+def _expand_cover(o, pairs, nx, ny):
+    nd = o.nodes()
+    cnt = np.zeros((nx, ny), dtype=np.int32)
+    for i, j in pairs:
+        cnt[nd[i, 4]:nd[i, 5], nd[j, 6]:nd[j, 7]] += 1
+    return cnt
+
+
+def _sep_sqrt(bx, i, j, tau, d):
+    di = 0.5 * np.linalg.norm(bx[i, 3:3 + d] - bx[i, :d])
+    dj = 0.5 * np.linalg.norm(bx[j, 3:3 + d] - bx[j, :d])
+    D = np.linalg.norm(0.5 * (bx[i, :d] + bx[i, 3:3 + d]) - 0.5 * (bx[j, :d] + bx[j, 3:3 + d]))
+    return di + dj - tau * D
+
+
+@pytest.mark.parametrize("d,kind,leaf", [(1, "uniform", 8), (2, "uniform", 16), (3, "clusters", 24),
+                                         (2, "clusters", 12)])
+def test_h2_pairs_tile_and_minimal(d, kind, leaf):
+    """(3.3)/(3.4): every (x, y) index pair is covered by exactly one block of
+    L or L^-; L pairs are distinct separated nodes whose parent pair is not
+    separated; L^- pairs are leaves that are not separated."""
+    n = 700
+    x = W.uniform(n, d, 21) if kind == "uniform" else W.clusters(n, d, 22)
+    tau = 0.7
+    o = O.Oracle(x, kernel="inv_r", leaf=leaf, order=2, adm=1, tol=1e-2, tau=tau,
+                 root=(np.zeros(d), 1.0))
+    L, Lm = o.L(), o.Lm()
+    nd, bx = o.nodes(), o.boxes()
+    cnt = _expand_cover(o, np.vstack([L, Lm]), n, n)
+    assert np.all(cnt == 1)
+    leaf_of = lambda i: nd[i, 3] == 0  # noqa: E731
+    for i, j in L:
+        assert i != j
+        assert _sep_sqrt(bx, i, j, tau, d) <= 1e-12
+        pi, pj = nd[i, 1], nd[j, 1]
+        if nd[i, 0] == nd[j, 0]:
+            assert _sep_sqrt(bx, pi, pj, tau, d) > -1e-12 or pi == pj
+        elif nd[i, 0] < nd[j, 0]:
+            assert leaf_of(i) and (_sep_sqrt(bx, i, pj, tau, d) > -1e-12)
+        else:
+            assert leaf_of(j) and (_sep_sqrt(bx, pi, j, tau, d) > -1e-12)
+    for i, j in Lm:
+        assert leaf_of(i) and leaf_of(j)
+        assert i == j or _sep_sqrt(bx, i, j, tau, d) > -1e-12
+    # sorted by (i, j)
+    P = np.vstack([L, Lm])
+    for A in (L, Lm):
+        assert np.all(np.lexsort((A[:, 1], A[:, 0])) == np.arange(A.shape[0]))
+    assert P.shape[0] == o.sizes()["nL"] + o.sizes()["nLm"]
+
+
+def test_hss_pairs_tile():
+    n = 900
+    x = W.uniform(n, 1, 31)
+    o = O.Oracle(x, kernel="inv_r", leaf=10, order=4, adm=0, tol=1e-4, root=((0.0,), 1.0))
+    nd = o.nodes()
+    L, Lm = o.L(), o.Lm()
+    cnt = _expand_cover(o, np.vstack([L, Lm]), n, n)
+    assert np.all(cnt == 1)
+    for i, j in L:
+        assert nd[i, 1] == nd[j, 1] and i != j
+    for i, j in Lm:
+        assert i == j and nd[i, 3] == 0
+
+
+def test_hss_near_sets_1d_characterisation():
+    """In 1D separation passes from parents to children, so (A.1) reduces to:
+    N_i = {nodes on i's level, not i, not separated from i} together with
+    {coarser leaves not separated from i}.  Checked by brute force."""
+    x = W.clusters(1200, 1, 41, ncl=3, sigma=0.05)
+    tau = 0.6
+    o = O.Oracle(x, kernel="inv_r", leaf=12, order=4, adm=0, tol=1e-4, tau=tau,
+                 root=((0.0,), 1.0))
+    nd, bx = o.nodes(), o.boxes()
+    ptr, idx = o.export(O.EX_NEAR_PTR), o.export(O.EX_NEAR_IDX)
+    nn = nd.shape[0]
+    assert ptr[1] == 0
+    for i in range(1, nn):
+        got = sorted(idx[ptr[i]:ptr[i + 1]].tolist())
+        ref = []
+        for k in range(1, nn):
+            if k == i:
+                continue
+            same = nd[k, 0] == nd[i, 0]
+            coarse_leaf = nd[k, 0] < nd[i, 0] and nd[k, 3] == 0
+            if (same or coarse_leaf) and _sep_sqrt(bx, i, k, tau, 1) > 0:
+                ref.append(k)
+        assert got == sorted(ref), i
+
+
+def test_appendix_a_near_set_size():
+    g = gold("appendix_a_near_sets.json")
+    n = g["n"]
+    x = ((np.arange(n) + 0.5) / n)[:, None]
+    o = O.Oracle(x, kernel="inv_r", leaf=g["leaf"], order=4, adm=0, tol=1e-4, tau=g["tau"],
+                 root=((0.0,), 1.0))
+    sz = o.sizes()
+    nd = o.nodes()
+    assert sz["nlevels"] == g["perfect_binary_levels"]
+    assert sz["nnodes"] == 2 ** g["perfect_binary_levels"] - 1
+    assert np.all(nd[nd[:, 3] == 0, 0] == sz["nlevels"])
+    ptr = o.export(O.EX_NEAR_PTR)
+    sizes = np.diff(ptr)[1:]
+    assert sizes.max() == g["max_near_set_size"]
+
+
+# --------------------------------------------------------------------------
+# interpolation basis (2.2)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("d,p", [(1, 7), (1, 16), (2, 5), (3, 4)])
+def test_basis_matches_scipy_barycentric(d, p):
+    rng = np.random.default_rng(d * 10 + p)
+    lo = rng.random(d) - 0.5
+    hi = lo + rng.random(d) + 0.1
+    pts = lo + (hi - lo) * rng.random((40, d))
+    U = O.interp_basis(pts, lo, hi, p)
+    # first-kind Chebyshev points from numpy (ascending) -> descending order
+    ref_nodes = np.polynomial.chebyshev.chebpts1(p)[::-1]
+    fac = []
+    for t in range(d):
+        nodes = 0.5 * (lo[t] + hi[t]) + 0.5 * (hi[t] - lo[t]) * ref_nodes
+        Lt = np.zeros((pts.shape[0], p))
+        for k in range(p):
+            e = np.zeros(p)
+            e[k] = 1.0
+            Lt[:, k] = scipy.interpolate.BarycentricInterpolator(nodes, e)(pts[:, t])
+        fac.append(Lt)
+    ref = fac[0]
+    for t in range(1, d):
+        ref = (ref[:, :, None] * fac[t][:, None, :]).reshape(pts.shape[0], -1)
+    assert np.max(np.abs(U - ref)) < 1e-11
+
+
+def test_basis_partition_of_unity_and_node_hit():
+    lo, hi = np.array([0.25]), np.array([0.75])
+    p = 9
+    nodes = 0.5 + 0.25 * np.cos(np.pi * (2 * np.arange(p) + 1) / (2 * p))
+    U = O.interp_basis(np.linspace(0.25, 0.75, 33), lo, hi, p)
+    assert np.allclose(U.sum(axis=1), 1.0, atol=1e-13)
+    # an exact node hit gives the Kronecker delta (when the node is representable)
+    Uh = O.interp_basis(np.array([nodes[3]]), lo, hi, p)
+    assert Uh[0, 3] == 1.0 and np.count_nonzero(Uh) == 1
+
+
+# --------------------------------------------------------------------------
+# compr: strong RRQR interpolative decomposition (Thm. 2.4, (2.11), (2.14))
+# --------------------------------------------------------------------------
+def _vol(M, cols):
+    S = M[:, cols]
+    return np.sqrt(max(np.linalg.det(S.T @ S), 0.0))
+
+
+def _lowrank(m, c, sing, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    s = np.zeros(min(m, c))
+    s[:len(sing)] = sing
+    return (U[:, :len(s)] * s) @ V[:len(s), :]
+
+
+def test_compr_reconstruction_and_bounds():
+    """C = P [I; G] C|_skel exactly for an exactly-rank-k matrix, and
+    |G|_max <= f (Thm. 2.4 with s = f = 2)."""
+    rng = np.random.default_rng(1)
+    m, c, k = 60, 25, 12
+    A = rng.standard_normal((m, k)) @ rng.standard_normal((k, c))
+    kk, sk, rs, G, ns = O.compr(A, 1e-12, 2.0)
+    assert kk == k
+    assert np.all(np.diff(sk) > 0) and np.all(np.diff(rs) > 0)
+    assert sorted(np.concatenate([sk, rs]).tolist()) == list(range(m))
+    rec = G @ A[sk]
+    assert np.linalg.norm(rec - A[rs]) <= 1e-12 * np.linalg.norm(A)
+    assert np.max(np.abs(G)) <= 2.0 + 1e-12
+    # G is the least-squares solution: rows rs expressed in rows sk (library lstsq)
+    Gl = np.linalg.lstsq(A[sk].T, A[rs].T, rcond=None)[0].T
+    assert np.max(np.abs(G - Gl)) < 1e-9
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_compr_gu_eisenstat_volume_condition(seed):
+    """Gu-Eisenstat: rho_ij equals the factor by which swapping skeleton i
+    with column j changes the k-volume of the chosen columns of M = C^T.
+    After compr no single swap can raise it by more than f (brute force)."""
+    rng = np.random.default_rng(100 + seed)
+    m, c = 30, 10
+    # rows with strongly varying scale make plain pivoting non-optimal
+    A = rng.standard_normal((m, c)) * np.exp(rng.standard_normal((m, 1)) * 2.0)
+    A[:, 6:] *= 1e-4
+    for tol in (1e-14, 1e-3):
+        k, sk, rs, G, ns = O.compr(A, tol, 2.0)
+        M = A.T
+        v0 = _vol(M, sk)
+        worst = 0.0
+        for a in range(k):
+            for b in rs:
+                cols = sk.copy()
+                cols[a] = b
+                worst = max(worst, _vol(M, cols) / v0)
+        assert worst <= 2.0 * (1 + 1e-8), (tol, worst, ns)
+        assert np.max(np.abs(G)) <= 2.0 * (1 + 1e-8)
+
+
+def test_compr_swaps_happen_and_fix_a_bad_pivot_choice():
+    """A matrix where column pivoting alone leaves |R11^-1 R12| > 2: the
+    swap loop must run and end within the bound."""
+    found = False
+    for seed in range(200):
+        rng = np.random.default_rng(seed)
+        m, c = 12, 4
+        A = rng.standard_normal((m, c))
+        A[:4] = A[4:8] * (1 + 1e-2 * rng.standard_normal((4, c)))
+        k, sk, rs, G, ns = O.compr(A, 1e-14, 1.01)
+        if ns > 0:
+            found = True
+            assert np.max(np.abs(G)) <= 1.01 * (1 + 1e-8)
+            break
+    assert found
+
+
+def test_compr_pivots_match_lapack_geqp3_without_swaps():
+    """With well separated column norms and a loose f the skeleton equals the
+    first k pivots of LAPACK's column-pivoted QR of C^T."""
+    rng = np.random.default_rng(7)
+    hits = 0
+    for trial in range(30):
+        m, c = 40, 12
+        A = _lowrank(m, c, np.geomspace(1, 1e-8, 12), 200 + trial)
+        k, sk, rs, G, ns = O.compr(A, 1e-6, 1e6)
+        Q, R, piv = scipy.linalg.qr(A.T, pivoting=True)
+        nr = np.abs(np.diag(R))
+        kref = int(np.sum(nr > 1e-6 * nr[0]))
+        assert k == kref
+        # ignore near ties of LAPACK's downdated norms
+        if np.all(np.abs(np.diff(nr[:k + 1])) > 1e-8 * nr[0]):
+            hits += 1
+            assert sorted(piv[:k].tolist()) == sk.tolist()
+    assert hits > 10
+
+
+def test_compr_rank_from_tolerance():
+    """k counts pivoted-QR diagonals above tol * |R_11| (bounded by the
+    tol-rank of the singular values times the RRQR factor)."""
+    sing = np.geomspace(1.0, 1e-12, 20)
+    A = _lowrank(50, 20, sing, 3)
+    for tol in (1e-2, 1e-5, 1e-9):
+        k, *_ = O.compr(A, tol, 2.0)
+        r_eps = int(np.sum(sing >= tol))
+        assert r_eps - 3 <= k <= r_eps + 3
+
+
+def test_compr_trivial_and_empty_cases():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((5, 9))  # fewer rows than columns: full rank -> all rows
+    k, sk, rs, G, ns = O.compr(A, 1e-12, 2.0)
+    assert k == 5 and sk.tolist() == [0, 1, 2, 3, 4] and G.shape == (0, 5)
+    Z = np.zeros((4, 3))
+    k, sk, rs, G, ns = O.compr(Z, 1e-12, 2.0)
+    assert k == 0 and rs.tolist() == [0, 1, 2, 3]
+
+
+# --------------------------------------------------------------------------
+# truncated SVD of near-field block rows ((3.7)-(3.8), Def. 6.1)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n", [(12, 30), (20, 20), (25, 9)])
+def test_left_svd_matches_lapack(m, n):
+    rng = np.random.default_rng(m * n)
+    A = rng.standard_normal((m, n)) @ np.diag(np.geomspace(1, 1e-13, n)) @ \
+        np.linalg.qr(rng.standard_normal((n, n)))[0]
+    eps = 1e-8
+    S, sig = O.left_svd(A, eps)
+    U, s, _ = np.linalg.svd(A)
+    r = int(np.sum(s >= eps * s[0]))
+    assert S.shape == (m, r)
+    assert np.allclose(sig[:min(m, n)], s[:min(m, n)], rtol=1e-10, atol=1e-13 * s[0])
+    P = S @ S.T
+    Pr = U[:, :r] @ U[:, :r].T
+    assert np.max(np.abs(P - Pr)) < 1e-7
+
+
+# --------------------------------------------------------------------------
+# whole construction + product
+# --------------------------------------------------------------------------
+def _relerr(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def test_single_leaf_is_exact():
+    x = W.uniform(60, 2, 3)
+    o = O.Oracle(x, kernel="log_r", leaf=100, order=4, adm=1, tol=1e-4, root=((0, 0), 1.0))
+    assert o.sizes()["nnodes"] == 1 and o.Lm().tolist() == [[0, 0]]
+    q = W.rhs(60, 3)
+    assert _relerr(o.matvec(q), O.dense_matvec(x, x, q, "log_r")) < 1e-14
+
+
+@pytest.mark.parametrize("adm,d,n,leaf,p", [(0, 1, 24, 4, 16), (1, 2, 64, 8, 8), (1, 1, 20, 4, 20)])
+def test_trivial_ids_are_exact(adm, d, n, leaf, p):
+    """Every grid fits in the basis (|grid| <= p^d) and tol = 0: all IDs keep
+    every row, so the representation reproduces A to rounding."""
+    x = W.uniform(n, d, 8)
+    o = O.Oracle(x, kernel="inv_r", leaf=leaf, order=p, adm=adm, tol=0.0, eps_svd=0.0,
+                 root=(np.zeros(d), 1.0))
+    rk = o.ranks()
+    assert rk[:, 0].max() <= p ** d
+    assert np.all(rk[1:, 1] == rk[1:, 0])
+    q = W.rhs(n, 2)
+    assert _relerr(o.matvec(q), O.dense_matvec(x, x, q, "inv_r")) < 1e-13
+
+
+def test_config_hss1d_matches_dense():
+    cfg = W.CONFIGS["hss1d_inv_r_2048"]
+    x, _ = W.points(cfg)
+    o = O.Oracle(x, kernel="inv_r", leaf=32, order=10, adm=0, tol=1e-10, eps_svd=1e-10,
+                 tau=0.6, root=((0.0,), 1.0))
+    q = W.rhs(cfg["n"], 1)
+    assert _relerr(o.matvec(q), O.dense_matvec(x, x, q, "inv_r")) < 1e-9
+
+
+def test_cauchy_hss_closed_form():
+    """K.1 for 1/(x - y) with y the Chebyshev roots is T_N'(x)/T_N(x); the HSS
+    approximation (eps_svd 1e-9, tol 1e-8, p 16, leaf 64) must reproduce it."""
+    N = 4096
+    x, y = W.chebyshev_pair(N, seed=0, shift_x=True)
+    o = O.Oracle(x, y, kernel="cauchy", leaf=64, order=16, adm=0, tol=1e-8, eps_svd=1e-9,
+                 tau=0.6)
+    z = o.matvec(np.ones(N))
+    ref = _cheb_logderiv(x, N, dps=30)
+    assert _relerr(z, ref) < 1e-7
+
+
+def test_error_decays_with_order():
+    """Error falls roughly geometrically in the interpolation order until
+    the tolerance floor (far-field bounds (2.9), Thm. 4.7)."""
+    x = W.uniform(6000, 2, 13)
+    q = W.rhs(6000, 1)
+    zd = O.dense_matvec(x, x, q, "log_r")
+    errs = []
+    for p in (3, 5, 7, 9):
+        o = O.Oracle(x, kernel="log_r", leaf=40, order=p, adm=1, tol=1e-14, tau=0.7,
+                     root=((0, 0), 1.0))
+        errs.append(_relerr(o.matvec(q), zd))
+    assert all(b < a * 0.5 for a, b in zip(errs[:-1], errs[1:])), errs
+    assert errs[-1] < 1e-6
+
+
+def test_symmetric_kernel_gives_symmetric_operator():
+    x = W.clusters(3000, 3, 17)
+    o = O.Oracle(x, kernel="inv_r", leaf=50, order=4, adm=1, tol=1e-6, root=((0, 0, 0), 1.0))
+    u, v = W.rhs(3000, 2, 5).T
+    a = u @ o.matvec(v)
+    b = v @ o.matvec(u)
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b))
+
+
+def test_generator_norm_bound_lemma_4_1():
+    x = W.uniform(5000, 2, 19)
+    o = O.Oracle(x, kernel="log_r", leaf=50, order=6, adm=1, tol=1e-8, root=((0, 0), 1.0))
+    for grid, sel, G in o.per_node("row")[1:]:
+        m, k = grid.shape[0], G.shape[1]
+        if k == 0 or G.size == 0:
+            continue
+        assert np.max(np.abs(G)) <= 2.0 * (1 + 1e-9)
+        assert np.sqrt(k + np.sum(G * G)) <= 2.0 * np.sqrt(m * k)
+
+
+def test_row_and_column_sides_differ_for_x_ne_y():
+    x, y = W.chebyshev_pair(2000, seed=1)
+    o = O.Oracle(x, y, kernel="cauchy", leaf=32, order=12, adm=0, tol=1e-8, eps_svd=1e-9)
+    q = W.rhs(2000, 2)
+    assert _relerr(o.matvec(q), O.dense_matvec(x, y, q, "cauchy")) < 1e-7
+    # transposed problem: A(y, x) = -A(x, y)^T for 1/(x - y)
+    ot = O.Oracle(y, x, kernel="cauchy", leaf=32, order=12, adm=0, tol=1e-8, eps_svd=1e-9)
+    u, v = q.T
+    a = u @ o.matvec(v)
+    b = -(v @ ot.matvec(u))
+    assert abs(a - b) <= 1e-6 * abs(a)
+
+
+def test_invalid_arguments_raise():
+    x = W.uniform(10, 2, 0)
+    with pytest.raises(O.OracleError):
+        O.Oracle(x, kernel="cauchy", leaf=4, order=3, adm=1, tol=1e-3)
+    with pytest.raises(O.OracleError):
+        O.Oracle(x * 2.0, kernel="inv_r", leaf=4, order=3, adm=1, tol=1e-3, root=((0, 0), 1.0))
+    xb = x.copy()
+    xb[3, 1] = np.nan
+    with pytest.raises(O.OracleError):
+        O.Oracle(xb, kernel="inv_r", leaf=4, order=3, adm=1, tol=1e-3)
+
+
+def test_sec6_1_order_rule_worked_values():
+    for c in gold("sec6_1_order_rule.json")["cases"]:
+        assert O.order_rule(c["eps"], c["tau"]) == c["r"], c
