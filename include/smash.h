@@ -1,0 +1,174 @@
+/*
+ * smash.h -- C ABI of libsmash: SMASH H^2 / HSS construction and product on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: D. Cai, E. Chow, Y. Saad, Y. Xi, "SMASH: Structured Matrix
+ * Approximation by Separation and Hierarchy" (arXiv 1705.05443).  Given a
+ * kernel kappa and point sets X, Y, build an H^2 (strong admissibility) or
+ * HSS (weak admissibility) approximation A-hat of A = [kappa(x, y)]
+ * (Sec. 3, statement of the construction problem) and apply it to blocks
+ * of vectors (Sec. 3.4).
+ *
+ * Conventions for every entry point:
+ *  - Pointers named "device" must point to device memory of the current HIP
+ *    device; "host" pointers to host memory.  Row-major layouts throughout.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued on it; inputs are borrowed and must stay valid until
+ *    the stream has passed the call (as for hipMemcpyAsync).
+ *  - Return value: SMASH_OK (0) or a negative error code.  No exception
+ *    crosses the ABI; on failure output handles are left NULL and nothing
+ *    leaks.  smash_last_error() gives a thread-local message.
+ *  - A handle owns every device allocation it makes and is freed by
+ *    smash_destroy.  Calls on different handles may run on different host
+ *    threads; one handle serves one product call at a time.
+ */
+#ifndef SMASH_H
+#define SMASH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---- */
+#define SMASH_OK 0
+#define SMASH_E_INVALID_ARG -1 /* bad size, pointer, parameter or option    */
+#define SMASH_E_UNSUPPORTED -2 /* e.g. the 1/(x-y) kernel with dim != 1     */
+#define SMASH_E_OOM -3         /* device or host allocation failed          */
+#define SMASH_E_DEVICE -4      /* a HIP runtime call failed                 */
+#define SMASH_E_NUMERIC -5     /* non-finite input, or the RRQR swap cap hit */
+
+/* ---- kernels (Sec. 2, eq. (2.1) and the radial kernels of the tests) ---- */
+#define SMASH_KERNEL_INV_R 0  /* 1/|x-y|,   kappa(x,x) = diag_value          */
+#define SMASH_KERNEL_LOG_R 1  /* log|x-y|,  kappa(x,x) = diag_value          */
+#define SMASH_KERNEL_EXP_R 2  /* exp(-|x-y|), its own value 1 at x = y       */
+#define SMASH_KERNEL_CAUCHY 3 /* 1/(x-y) on the real line (dim 1 only), eq. (2.1) */
+
+/* ---- admissibility (Sec. 3.2) ---- */
+#define SMASH_ADM_WEAK 0   /* HSS: binary tree, (i,j) admissible iff i != j  */
+#define SMASH_ADM_STRONG 1 /* H^2: 2^d-tree, admissible iff well separated (Def. 2.1) */
+
+/* ---- precisions ---- */
+#define SMASH_F64 0
+#define SMASH_F32 1
+
+typedef struct smash_handle_s *smash_handle;
+
+/* Options.  Initialise with smash_default_options(); a NULL options pointer
+ * means the defaults.
+ *   tau          separation ratio of Def. 2.1; default 0.6 for dim 1, else 0.7
+ *   eps_svd      HSS near-field SVD relative truncation (eq. (3.8)); < 0: = tol
+ *   srrqr_f      Gu-Eisenstat bound f = s of Thm. 2.4; default 2
+ *   diag_value   d_x of eq. (2.1) for singular kernels; default 0
+ *   eval_prec    precision of the stored coupling / near-field blocks
+ *   apply_prec   precision of the product (G copies, vectors); SMASH_F64 or SMASH_F32
+ *   has_root_box root box [root_lo, root_lo + root_side]^dim instead of the
+ *                bounding cube of X and Y (points outside: SMASH_E_INVALID_ARG)
+ *   max_depth    > 0 caps the number of tree levels (root = level 1)
+ *   batched      1: all nodes of a level in one launch per phase (default);
+ *                0: one launch per node (the plain per-node form)
+ */
+typedef struct smash_options {
+  uint32_t struct_size; /* sizeof(smash_options) */
+  double tau;
+  double eps_svd;
+  double srrqr_f;
+  double diag_value;
+  int32_t eval_prec;
+  int32_t apply_prec;
+  int32_t has_root_box;
+  double root_lo[3];
+  double root_side;
+  int32_t max_depth;
+  int32_t batched;
+} smash_options;
+
+int smash_default_options(smash_options *opt);
+
+/* Construction (Sec. 3.1 partition, Sec. 3.3.1 HSS or Sec. 3.3.2 H^2
+ * level-wise compression, eqs. (3.15), (3.19), (3.20) blocks), with Y = X.
+ *   points        device, n x dim FP64
+ *   kernel_id     SMASH_KERNEL_*
+ *   leaf_size     nu_0: a box holding more than nu_0 points of X or Y is bisected
+ *   interp_order  p: Chebyshev points per axis of the interpolation basis (2.2)
+ *   admissibility SMASH_ADM_WEAK or SMASH_ADM_STRONG
+ *   tol           relative rank tolerance of the strong RRQR (Thm. 2.4)
+ *   out           receives the handle (NULL on failure)
+ * Synchronises `stream` a few times (level sizes, list lengths); the handle
+ * is ready when the call returns. */
+int smash_build(const double *points, int64_t n, int32_t dim, int32_t kernel_id,
+                int32_t leaf_size, int32_t interp_order, int32_t admissibility, double tol,
+                const smash_options *opt, void *stream, smash_handle *out);
+
+/* Same with distinct X (nx x dim) and Y (ny x dim), both device FP64. */
+int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int32_t dim,
+                   int32_t kernel_id, int32_t leaf_size, int32_t interp_order,
+                   int32_t admissibility, double tol, const smash_options *opt, void *stream,
+                   smash_handle *out);
+
+/* Product Y = A-hat X (Sec. 3.4) in the ORIGINAL point order.
+ *   X  device, ny x nrhs, leading dimension ldx (>= nrhs)
+ *   Y  device, nx x nrhs, leading dimension ldy (>= nrhs); fully overwritten
+ *   dtype  SMASH_F64 or SMASH_F32; must equal the handle's apply precision
+ * Asynchronous on `stream`; workspaces are owned by the handle. */
+int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
+                 void *Y, int64_t ldy, void *stream);
+
+/* Sizes and statistics of a construction (host struct). */
+typedef struct smash_info_t {
+  int64_t nx, ny;
+  int32_t dim, nlevels;
+  int64_t nnodes, nleaves;
+  int64_t n_admissible;   /* |L|   */
+  int64_t n_inadmissible; /* |L^-| */
+  int64_t sum_rank_row, sum_rank_col; /* sum over nodes of |i-hat| */
+  int32_t max_rank_row, max_rank_col;
+  int64_t coupling_entries; /* sum over L of k_i k_j     */
+  int64_t near_entries;     /* sum over L^- of |i| |j|   */
+  int64_t g_entries_row, g_entries_col; /* sum (|i-bar| - k) k */
+  int64_t index_entries;    /* stored int32 index entries */
+  int64_t device_bytes;     /* bytes held by the handle   */
+  int64_t total_swaps;      /* Gu-Eisenstat swaps performed */
+  int32_t apply_prec, eval_prec;
+  int32_t symmetric_reuse;  /* column side taken from the row side */
+  double build_ms;          /* wall time of the last build on its stream */
+} smash_info_t;
+
+int smash_info(smash_handle h, smash_info_t *info);
+
+/* Copy parts of the construction to host memory for inspection.  With
+ * host_buf == NULL, *count receives the number of elements and nothing is
+ * copied; otherwise *count must hold the buffer capacity in elements.
+ * Element type is int32 unless stated. */
+#define SMASH_EX_PERM_X 1   /* nx: original index of each permuted X point */
+#define SMASH_EX_PERM_Y 2
+#define SMASH_EX_NODES 3    /* nnodes x 8: level, parent, first_child (-1), nchild, xb, xe, yb, ye */
+#define SMASH_EX_BOXES 4    /* nnodes x 6 FP64: lo[3], hi[3] */
+#define SMASH_EX_L 5        /* |L| x 2 (i, j) sorted */
+#define SMASH_EX_LM 6       /* |L^-| x 2 sorted */
+#define SMASH_EX_NEAR_PTR 7 /* HSS: nnodes+1 CSR pointer of N_i (eq. (A.1)) */
+#define SMASH_EX_NEAR_IDX 8
+#define SMASH_EX_RANKS 9    /* nnodes x 6: m_row, k_row, m_col, k_col, ks_row, ks_col */
+#define SMASH_EX_ROW_SEL 10 /* per non-root node, m entries: skeleton positions asc, then the rest asc */
+#define SMASH_EX_ROW_G 11   /* FP64, per non-root node (m-k) x k */
+#define SMASH_EX_COL_SEL 12
+#define SMASH_EX_COL_G 13
+#define SMASH_EX_ROW_GRID 14 /* per non-root node, m permuted point ids */
+#define SMASH_EX_COL_GRID 15
+#define SMASH_EX_SIZES 16    /* nx, ny, nnodes, nlevels, |L|, |L^-|, dim, admissibility */
+#define SMASH_EX_LEVELS 17   /* nlevels+1: first node of each level, then nnodes */
+#define SMASH_EX_COUPLING 18 /* apply-precision entries of all B_ij over L, pair order, row-major */
+#define SMASH_EX_NEAR 19     /* apply-precision entries of all near blocks over L^- */
+int smash_export(smash_handle h, int32_t what, void *host_buf, int64_t *count);
+
+int smash_destroy(smash_handle h);
+
+/* Thread-local description of the last failure on this thread. */
+const char *smash_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMASH_H */

@@ -1,0 +1,202 @@
+"""Thin ctypes binding of libsmash (include/smash.h).
+
+Argument marshalling only: torch device tensors become raw pointers and the
+current torch stream becomes the hipStream_t; every step of the construction
+and of the product runs in the HIP library.  If the library is not built,
+``lib()`` raises -- there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsmash.so")
+
+KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3}
+ADM = {"weak": 0, "hss": 0, "strong": 1, "h2": 1}
+PREC = {"f64": 0, "f32": 1}
+
+EX = dict(perm_x=1, perm_y=2, nodes=3, boxes=4, L=5, Lm=6, near_ptr=7, near_idx=8, ranks=9,
+          row_sel=10, row_G=11, col_sel=12, col_G=13, row_grid=14, col_grid=15, sizes=16,
+          levels=17, coupling=18, near=19)
+_F64_EXPORTS = {"boxes", "row_G", "col_G"}
+
+
+class SmashError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("smash error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("struct_size", C.c_uint32), ("tau", C.c_double), ("eps_svd", C.c_double),
+                ("srrqr_f", C.c_double), ("diag_value", C.c_double), ("eval_prec", C.c_int32),
+                ("apply_prec", C.c_int32), ("has_root_box", C.c_int32),
+                ("root_lo", C.c_double * 3), ("root_side", C.c_double), ("max_depth", C.c_int32),
+                ("batched", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("nx", C.c_int64), ("ny", C.c_int64), ("dim", C.c_int32), ("nlevels", C.c_int32),
+                ("nnodes", C.c_int64), ("nleaves", C.c_int64), ("n_admissible", C.c_int64),
+                ("n_inadmissible", C.c_int64), ("sum_rank_row", C.c_int64),
+                ("sum_rank_col", C.c_int64), ("max_rank_row", C.c_int32),
+                ("max_rank_col", C.c_int32), ("coupling_entries", C.c_int64),
+                ("near_entries", C.c_int64), ("g_entries_row", C.c_int64),
+                ("g_entries_col", C.c_int64), ("index_entries", C.c_int64),
+                ("device_bytes", C.c_int64), ("total_swaps", C.c_int64),
+                ("apply_prec", C.c_int32), ("eval_prec", C.c_int32),
+                ("symmetric_reuse", C.c_int32), ("build_ms", C.c_double)]
+
+
+_lib = None
+EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
+            "smash_info", "smash_export", "smash_destroy", "smash_last_error"]
+
+
+def lib():
+    """Load libsmash.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsmash.so is not built (run python -m "
+                               "paper_1705_05443_amd.build_lib); there is no fallback path")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.smash_default_options.argtypes = [C.POINTER(Options)]
+        L.smash_build.argtypes = [vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_int32, C.c_double, C.POINTER(Options), vp, C.POINTER(vp)]
+        L.smash_build_xy.argtypes = [vp, C.c_int64, vp, C.c_int64, C.c_int32, C.c_int32,
+                                     C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                     C.POINTER(Options), vp, C.POINTER(vp)]
+        L.smash_matvec.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, vp]
+        L.smash_info.argtypes = [vp, C.POINTER(Info)]
+        L.smash_export.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int64)]
+        L.smash_destroy.argtypes = [vp]
+        L.smash_last_error.restype = C.c_char_p
+        for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
+                  "smash_info", "smash_export", "smash_destroy"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise SmashError(rc, lib().smash_last_error().decode())
+
+
+def _stream_ptr(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Smash:
+    """A device-resident SMASH construction (the C handle)."""
+
+    def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
+                 tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
+                 root=None, max_depth=0, batched=True, stream=None):
+        import torch
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
+            raise TypeError("x must be a CUDA float64 tensor")
+        x = x.contiguous()
+        if x.dim() == 1:
+            x = x[:, None]
+        if y is not None:
+            y = y.contiguous()
+            if y.dim() == 1:
+                y = y[:, None]
+        opt = Options()
+        lib().smash_default_options(C.byref(opt))
+        if tau is not None:
+            opt.tau = tau
+        if eps_svd is not None:
+            opt.eps_svd = eps_svd
+        opt.srrqr_f = f
+        opt.diag_value = diag
+        opt.eval_prec = PREC[eval_prec]
+        opt.apply_prec = PREC[apply_prec]
+        if root is not None:
+            opt.has_root_box = 1
+            lo = list(np.atleast_1d(np.asarray(root[0], dtype=np.float64)))
+            for t, v in enumerate(lo[:3]):
+                opt.root_lo[t] = v
+            opt.root_side = float(root[1])
+        opt.max_depth = max_depth
+        opt.batched = 1 if batched else 0
+        self.apply_prec = apply_prec
+        self.nx = x.shape[0]
+        self.ny = x.shape[0] if y is None else y.shape[0]
+        self._keep = (x, y)
+        h = C.c_void_p()
+        kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        a = ADM[adm] if isinstance(adm, str) else int(adm)
+        sp = _stream_ptr(stream)
+        if y is None:
+            rc = lib().smash_build(C.c_void_p(x.data_ptr()), x.shape[0], x.shape[1], kid,
+                                   leaf, order, a, tol, C.byref(opt), sp, C.byref(h))
+        else:
+            rc = lib().smash_build_xy(C.c_void_p(x.data_ptr()), x.shape[0],
+                                      C.c_void_p(y.data_ptr()), y.shape[0], x.shape[1], kid,
+                                      leaf, order, a, tol, C.byref(opt), sp, C.byref(h))
+        _check(rc)
+        self._h = h
+
+    def matvec(self, X, out=None, stream=None):
+        """Y = A-hat X, original point order; X: (ny, nrhs) or (ny,)."""
+        import torch
+        dt = torch.float64 if self.apply_prec == "f64" else torch.float32
+        vec = X.dim() == 1
+        if vec:
+            X = X[:, None]
+        if X.dtype != dt or not X.is_cuda:
+            raise TypeError("X must be a CUDA tensor of the apply precision")
+        if X.stride(1) != 1:
+            X = X.contiguous()
+        R = X.shape[1]
+        if out is None:
+            out = torch.empty((self.nx, R), dtype=dt, device=X.device)
+        _check(lib().smash_matvec(self._h, C.c_void_p(X.data_ptr()), X.stride(0), R,
+                                  PREC[self.apply_prec], C.c_void_p(out.data_ptr()),
+                                  out.stride(0), _stream_ptr(stream)))
+        return out[:, 0] if vec else out
+
+    def info(self):
+        inf = Info()
+        _check(lib().smash_info(self._h, C.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def export(self, what):
+        n = C.c_int64(0)
+        code = EX[what]
+        _check(lib().smash_export(self._h, code, None, C.byref(n)))
+        if what in ("coupling", "near"):
+            dt = np.float64 if self.apply_prec == "f64" else np.float32
+        else:
+            dt = np.float64 if what in _F64_EXPORTS else np.int32
+        out = np.zeros(max(n.value, 1), dtype=dt)
+        _check(lib().smash_export(self._h, code, out.ctypes.data_as(C.c_void_p), C.byref(n)))
+        return out[: n.value]
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().smash_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

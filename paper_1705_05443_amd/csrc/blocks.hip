@@ -1,0 +1,167 @@
+// blocks.hip -- coupling blocks B_ij = A|(i-hat x j-hat) over the admissible
+// leaves L (eqs. (3.15), (3.19)) and near-field blocks A|(i x j) over the
+// inadmissible leaves L^- (eqs. (3.15), (3.20)), evaluated from the kernel
+// and stored in the apply precision.  Each block is stored column-major
+// (row index fastest) so that the product reads it with unit stride.
+#include "common.cuh"
+
+namespace smash {
+
+__global__ void k_block_sizes(int64_t n, const int *pi, const int *pj, const int *ki,
+                              const int *kj, int64_t *cnt) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < n) cnt[a] = (int64_t)ki[pi[a]] * kj[pj[a]];
+}
+
+__global__ void k_near_sizes(int64_t n, const int *pi, const int *pj, const int *xb,
+                             const int *xe, const int *yb, const int *ye, int64_t *cnt) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a < n) cnt[a] = (int64_t)(xe[pi[a]] - xb[pi[a]]) * (ye[pj[a]] - yb[pj[a]]);
+}
+
+struct EvalArgs {
+  int64_t npairs;
+  const int *pi, *pj;
+  const int64_t *off;
+  // row points of block e: Xp[rid[rbeg[i] + a]] (rid == null: Xp[rbeg[i] + a])
+  const int64_t *rbeg;
+  const int *rbeg32;
+  const int *rcnt_k;  // rows per node (k or point count via rend32)
+  const int *rend32;
+  const int *rid;
+  const int64_t *cbeg;
+  const int *cbeg32;
+  const int *ccnt_k;
+  const int *cend32;
+  const int *cid;
+  const double *Xp, *Yp;
+  int d, kid;
+  double diag;
+};
+
+template <class T, bool F32MATH>
+__global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
+  for (int64_t e = blockIdx.x; e < A.npairs; e += gridDim.x) {
+    int i = A.pi[e], j = A.pj[e];
+    int64_t r0, c0;
+    int nr, nc;
+    if (A.rbeg) {
+      r0 = A.rbeg[i];
+      nr = A.rcnt_k[i];
+    } else {
+      r0 = A.rbeg32[i];
+      nr = A.rend32[i] - A.rbeg32[i];
+    }
+    if (A.cbeg) {
+      c0 = A.cbeg[j];
+      nc = A.ccnt_k[j];
+    } else {
+      c0 = A.cbeg32[j];
+      nc = A.cend32[j] - A.cbeg32[j];
+    }
+    T *B = out + A.off[e];
+    int tot = nr * nc;
+    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+      int b = q / nr, a = q - b * nr;  // column-major: row fastest
+      int64_t xr = A.rid ? A.rid[r0 + a] : r0 + a;
+      int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
+      const double *xp = A.Xp + xr * A.d, *yp = A.Yp + yc * A.d;
+      if (F32MATH)
+        B[q] = (T)kernel_f32(A.kid, xp, yp, A.d, (float)A.diag);
+      else
+        B[q] = (T)kernel_f64(A.kid, xp, yp, A.d, A.diag);
+    }
+  }
+}
+
+template <class T>
+static void eval_launch(Handle &h, EvalArgs &ea, T *out, bool f32math) {
+  int nblk = ea.npairs < (1 << 20) ? (int)ea.npairs : (1 << 20);
+  if (nblk <= 0) return;
+  if (f32math)
+    k_eval_blocks<T, true><<<nblk, 256, 0, h.stream>>>(ea, out);
+  else
+    k_eval_blocks<T, false><<<nblk, 256, 0, h.stream>>>(ea, out);
+  SMASH_CHECK_LAUNCH();
+}
+
+void build_blocks(Handle &h) {
+  hipStream_t s = h.stream;
+  DeviceArena tmp;
+  tmp.stream = s;
+  try {
+    Side &R = h.row, &C = *h.col;
+    size_t es = h.apply_prec == SMASH_F64 ? sizeof(double) : sizeof(float);
+    bool f32math = h.eval_prec == SMASH_F32;
+    // coupling
+    int64_t *cnt = tmp.alloc_n<int64_t>(h.nL);
+    h.boff = h.mem.alloc_n<int64_t>(h.nL + 1);
+    if (h.nL > 0) {
+      k_block_sizes<<<ceil_div(h.nL, 256), 256, 0, s>>>(h.nL, h.Li, h.Lj, R.k, C.k, cnt);
+      SMASH_CHECK_LAUNCH();
+    }
+    scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
+    SMASH_HIP(hipMemcpyAsync(&h.b_entries, h.boff + h.nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    // near field
+    int64_t *ncnt = tmp.alloc_n<int64_t>(h.nLm);
+    h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
+    if (h.nLm > 0) {
+      k_near_sizes<<<ceil_div(h.nLm, 256), 256, 0, s>>>(h.nLm, h.Lmi, h.Lmj, h.xb, h.xe, h.yb,
+                                                        h.ye, ncnt);
+      SMASH_CHECK_LAUNCH();
+    }
+    scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
+    SMASH_HIP(hipMemcpyAsync(&h.n_entries, h.nboff + h.nLm, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SMASH_HIP(hipStreamSynchronize(s));
+    h.B = h.mem.alloc(es * (size_t)(h.b_entries > 0 ? h.b_entries : 1));
+    h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
+    EvalArgs ea{};
+    ea.d = h.d;
+    ea.kid = h.kid;
+    ea.diag = h.diag;
+    ea.Xp = h.Xp;
+    ea.Yp = h.Yp;
+    // B_ij = A(X at i-hat, Y at j-hat): skeleton slots of both sides
+    ea.npairs = h.nL;
+    ea.pi = h.Li;
+    ea.pj = h.Lj;
+    ea.off = h.boff;
+    ea.rbeg = R.hbeg;
+    ea.rcnt_k = R.k;
+    ea.rid = R.slot_id;
+    ea.cbeg = C.hbeg;
+    ea.ccnt_k = C.k;
+    ea.cid = C.slot_id;
+    if (h.apply_prec == SMASH_F64)
+      eval_launch(h, ea, (double *)h.B, f32math);
+    else
+      eval_launch(h, ea, (float *)h.B, f32math);
+    // near blocks: A(X at i, Y at j), point ranges
+    EvalArgs en{};
+    en.d = h.d;
+    en.kid = h.kid;
+    en.diag = h.diag;
+    en.Xp = h.Xp;
+    en.Yp = h.Yp;
+    en.npairs = h.nLm;
+    en.pi = h.Lmi;
+    en.pj = h.Lmj;
+    en.off = h.nboff;
+    en.rbeg32 = h.xb;
+    en.rend32 = h.xe;
+    en.cbeg32 = h.yb;
+    en.cend32 = h.ye;
+    if (h.apply_prec == SMASH_F64)
+      eval_launch(h, en, (double *)h.Bn, f32math);
+    else
+      eval_launch(h, en, (float *)h.Bn, f32math);
+    SMASH_HIP(hipStreamSynchronize(s));
+    tmp.release();
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    throw;
+  }
+}
+
+}  // namespace smash

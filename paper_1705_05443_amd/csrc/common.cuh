@@ -1,0 +1,105 @@
+// common.cuh -- device helpers shared by the libsmash kernels.
+#pragma once
+
+#include "internal.h"
+
+namespace smash {
+
+constexpr int WAVE = 64;
+
+// Exclusive block scan of one int64 per thread (blockDim a multiple of 64).
+// lds must hold blockDim/64 + 1 entries.  Ends with a barrier, so lds may be
+// reused right after.
+__device__ inline int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *lds) {
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  const int nw = blockDim.x / WAVE;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int64_t y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == WAVE - 1) lds[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int w = 0; w < nw; w++) {
+      int64_t t = lds[w];
+      lds[w] = s;
+      s += t;
+    }
+    lds[nw] = s;
+  }
+  __syncthreads();
+  int64_t r = x - v + lds[wid];
+  *total = lds[nw];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ kernels
+// kappa(x, y) in FP64.  "x = y" means every coordinate equal (eq. (2.1):
+// the diagonal value d_x is then returned for the singular kernels).
+__device__ inline double kernel_f64(int kid, const double *x, const double *y, int d,
+                                    double diag) {
+  double r2 = 0.0;
+  bool same = true;
+  for (int t = 0; t < d; t++) {
+    double df = x[t] - y[t];
+    same = same && (x[t] == y[t]);
+    r2 += df * df;
+  }
+  if (kid == SMASH_KERNEL_EXP_R) return exp(-sqrt(r2));
+  if (same) return diag;
+  if (kid == SMASH_KERNEL_INV_R) return 1.0 / sqrt(r2);
+  if (kid == SMASH_KERNEL_LOG_R) return 0.5 * log(r2);
+  return 1.0 / (x[0] - y[0]);
+}
+
+// FP32 evaluation: coordinate differences are formed in FP64 (points may be
+// closer than FP32 resolution), the rest in FP32.
+__device__ inline float kernel_f32(int kid, const double *x, const double *y, int d,
+                                   float diag) {
+  float r2 = 0.0f;
+  bool same = true;
+  float dx0 = 0.0f;
+  for (int t = 0; t < d; t++) {
+    double df = x[t] - y[t];
+    same = same && (x[t] == y[t]);
+    float f = (float)df;
+    if (t == 0) dx0 = f;
+    r2 += f * f;
+  }
+  if (kid == SMASH_KERNEL_EXP_R) return __expf(-sqrtf(r2));
+  if (same) return diag;
+  if (kid == SMASH_KERNEL_INV_R) return rsqrtf(r2);
+  if (kid == SMASH_KERNEL_LOG_R) return 0.5f * __logf(r2);
+  return 1.0f / dx0;
+}
+
+// Def. 2.1, eq. (2.3) on boxes: delta_i + delta_j <= tau |c_i - c_j| with c
+// the box centre and delta half its diagonal, decided exactly without a
+// square root: e = tau^2 D^2 - delta_i^2 - delta_j^2 >= 0 and
+// 4 delta_i^2 delta_j^2 <= e^2.  The library is compiled without FP
+// contraction, so this is the same rounding sequence on every run.
+__device__ inline bool well_separated(const double *lo, const double *hi, int i, int j, int d,
+                                      double tau) {
+  double di2 = 0.0, dj2 = 0.0, D2 = 0.0;
+  for (int t = 0; t < d; t++) {
+    double wi = hi[3 * i + t] - lo[3 * i + t];
+    double wj = hi[3 * j + t] - lo[3 * j + t];
+    di2 += wi * wi;
+    dj2 += wj * wj;
+    double ci = 0.5 * (lo[3 * i + t] + hi[3 * i + t]);
+    double cj = 0.5 * (lo[3 * j + t] + hi[3 * j + t]);
+    double dc = ci - cj;
+    D2 += dc * dc;
+  }
+  di2 = 0.25 * di2;
+  dj2 = 0.25 * dj2;
+  double e = tau * tau * D2 - di2 - dj2;
+  if (e < 0.0) return false;
+  return 4.0 * di2 * dj2 <= e * e;
+}
+
+}  // namespace smash

@@ -1,0 +1,898 @@
+// compress.hip -- level-wise construction of the nested bases (Sec. 3.3):
+// for l = L, ..., 2 every node of level l, in one launch per phase,
+//   * forms its current grid (leaf points, eq. (3.6); else the children's
+//     skeletons, eqs. (3.14), (3.18)),
+//   * (HSS) takes the truncated SVD of its near-field block row, eqs.
+//     (3.7)-(3.8) / (3.11)-(3.12), keeping sigma >= eps_svd * sigma_1,
+//   * evaluates the interpolation basis U-hat of eq. (2.2) on the grid
+//     (tensor Lagrange basis on first-kind Chebyshev points of its box),
+//   * runs compr (eq. (2.14)): strong rank-revealing QR (Thm. 2.4) of
+//     M = C^T with C = U-hat or [U-hat, S], giving the skeleton i-hat and
+//     G with U = P [I; G] (eq. (2.11)), stored canonically (both index sets
+//     ascending).
+//
+// One workgroup of NT threads owns one node at a time (persistent grid
+// striding over the level's nodes).  M = C^T lives in a per-workgroup tile
+// W (c rows x m columns, row-major, column a = grid point a) in global
+// memory that stays L2-resident; each thread owns grid columns a = tid,
+// tid + NT, ... so every row access is coalesced.  Column norms for the
+// pivot choice are recomputed from the transformed columns after each
+// Householder step (no downdating), the argmax is a wavefront shuffle
+// reduction, and ties go to the lowest position.  All arithmetic is FP64.
+#include "common.cuh"
+
+namespace smash {
+
+constexpr int ID_NT = 256;
+constexpr int ID_CMAX = 512;  // largest basis width c (p^d plus HSS near vectors)
+constexpr int ID_PMAX = 64;   // largest interpolation order
+
+struct IdArgs {
+  int nb, ne;  // node range
+  const double *lo, *hi;
+  int d, p, c0;
+  const int *m;
+  const int64_t *gbeg;
+  const int *slot_id;
+  const double *P;  // permuted coordinates of this side, n x d
+  const int64_t *selo, *go;
+  int *sel_out;
+  double *G_out;
+  int *k_out;
+  const double *S;  // HSS near-field vectors, per node m x ks (row-major) at S_off
+  const int64_t *S_off;
+  const int *ks;
+  double tol, f;
+  double *scratch;  // per workgroup: W (c x ldw), F (d*p x ldw), Nrm (ldw), Ri (c*c)
+  int ldw;
+  int64_t wg_stride;
+  int *iscratch;  // per workgroup: perm (ldw), pos (ldw)
+  int64_t wg_istride;
+  int *swaps;    // total swap count (atomic)
+  int *err;      // set to 1 when the swap cap is hit
+};
+
+// ---- block reductions --------------------------------------------------
+struct ArgMax {
+  double v;
+  int a;
+};
+
+// larger value wins; ties: smaller index (NaN never wins)
+__device__ inline ArgMax amax_pick(ArgMax x, ArgMax y) {
+  if (y.v > x.v || (y.v == x.v && y.a < x.a && y.a >= 0)) return y;
+  if (x.a < 0) return y;
+  return x;
+}
+
+__device__ inline ArgMax block_argmax(ArgMax x, ArgMax *lds) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    ArgMax y;
+    y.v = __shfl_xor(x.v, o, WAVE);
+    y.a = __shfl_xor(x.a, o, WAVE);
+    x = amax_pick(x, y);
+  }
+  const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  __syncthreads();
+  if (lane == 0) lds[wid] = x;
+  __syncthreads();
+  ArgMax r = lds[0];
+  for (int w = 1; w < (int)(blockDim.x / WAVE); w++) r = amax_pick(r, lds[w]);
+  return r;
+}
+
+__device__ inline double block_sum(double v, double *lds) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  __syncthreads();
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < (int)(blockDim.x / WAVE); w++) r += lds[w];
+  return r;
+}
+
+// ---- interpolation basis column ----------------------------------------
+// Column a of M = C^T: the c0 tensor Lagrange values at grid point a
+// (barycentric form; an exact node hit gives the Kronecker delta), then the
+// ks near-field vector entries of row a.
+__device__ inline void basis_column(const IdArgs &A, int i, int a, int src_a, double *W,
+                                    double *F, int ldw, int ks, const double *xi,
+                                    const double *wk) {
+  const int d = A.d, p = A.p;
+  int64_t id = A.slot_id[A.gbeg[i] + src_a];
+  for (int t = 0; t < d; t++) {
+    double x = A.P[id * d + t];
+    double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+    double *Ft = F + (int64_t)(t * p) * ldw + a;
+    if (hi - lo == 0.0) {
+      for (int k = 0; k < p; k++) Ft[(int64_t)k * ldw] = k == 0 ? 1.0 : 0.0;
+      continue;
+    }
+    int hit = -1;
+    double den = 0.0;
+    for (int k = 0; k < p; k++) {
+      double xk = xi[t * ID_PMAX + k];
+      if (x == xk) {
+        hit = k;
+        break;
+      }
+      double v = wk[k] / (x - xk);
+      Ft[(int64_t)k * ldw] = v;
+      den += v;
+    }
+    if (hit >= 0) {
+      for (int k = 0; k < p; k++) Ft[(int64_t)k * ldw] = k == hit ? 1.0 : 0.0;
+    } else {
+      for (int k = 0; k < p; k++) Ft[(int64_t)k * ldw] = Ft[(int64_t)k * ldw] / den;
+    }
+  }
+  for (int r = 0; r < A.c0; r++) {
+    int q = r;
+    double v = 1.0;
+    for (int t = d - 1; t >= 0; t--) {
+      v *= F[(int64_t)(t * p + q % p) * ldw + a];
+      q /= p;
+    }
+    W[(int64_t)r * ldw + a] = v;
+  }
+  if (ks > 0) {
+    const double *Sa = A.S + A.S_off[i - A.nb] + (int64_t)src_a * ks;
+    for (int q = 0; q < ks; q++) W[(int64_t)(A.c0 + q) * ldw + a] = Sa[q];
+  }
+}
+
+// ---- Householder step on column t (rows t..c-1), applied to columns
+// t+1..m-1; with `norms`, the new residual norms over rows t+1..c-1 are
+// stored in Nrm.  v lives in LDS.  alpha = residual norm of column t.
+__device__ inline void householder(double *W, int ldw, int c, int m, int t, double alpha,
+                                   double *v, double *red, double *Nrm, bool norms) {
+  const int tid = threadIdx.x;
+  double x0 = W[(int64_t)t * ldw + t];
+  double rtt = x0 >= 0.0 ? -alpha : alpha;
+  for (int r = t + 1 + tid; r < c; r += blockDim.x) v[r - t] = W[(int64_t)r * ldw + t];
+  double part = 0.0;
+  for (int r = t + 1 + tid; r < c; r += blockDim.x) {
+    double y = W[(int64_t)r * ldw + t];
+    part += y * y;
+  }
+  double rest = block_sum(part, red);  // ends with barriers
+  double v0 = x0 - rtt;
+  double vn = rest + v0 * v0;
+  if (tid == 0) v[0] = v0;
+  __syncthreads();
+  if (alpha != 0.0 && vn > 0.0) {
+    for (int a = t + 1 + tid; a < m; a += blockDim.x) {
+      double w = 0.0;
+      for (int r = t; r < c; r++) w = fma(v[r - t], W[(int64_t)r * ldw + a], w);
+      double sc = 2.0 * w / vn;
+      double s2 = 0.0;
+      for (int r = t; r < c; r++) {
+        double y = fma(-sc, v[r - t], W[(int64_t)r * ldw + a]);
+        W[(int64_t)r * ldw + a] = y;
+        if (r > t) s2 = fma(y, y, s2);
+      }
+      if (norms) Nrm[a] = sqrt(s2);
+    }
+  } else if (norms) {
+    for (int a = t + 1 + tid; a < m; a += blockDim.x) {
+      double s2 = 0.0;
+      for (int r = t + 1; r < c; r++) {
+        double y = W[(int64_t)r * ldw + a];
+        s2 = fma(y, y, s2);
+      }
+      Nrm[a] = sqrt(s2);
+    }
+  }
+  __syncthreads();
+  if (alpha != 0.0) {
+    for (int r = t + tid; r < c; r += blockDim.x) W[(int64_t)r * ldw + t] = r == t ? rtt : 0.0;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
+  __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
+  __shared__ double v[ID_CMAX + 1], rinv[ID_CMAX];
+  __shared__ double red[ID_NT / WAVE + 1];
+  __shared__ ArgMax ared[ID_NT / WAVE + 1];
+  __shared__ int64_t sred[ID_NT / WAVE + 1];
+  const int tid = threadIdx.x;
+  const int p = A.p;
+  if (tid < p) {
+    double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
+    chc[tid] = cos(th);
+    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
+  }
+  double *W = A.scratch + (int64_t)blockIdx.x * A.wg_stride;
+  const int ldw = A.ldw;
+  int *perm = A.iscratch + (int64_t)blockIdx.x * A.wg_istride;
+  int *pos = perm + ldw;
+  for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
+    const int m = A.m[i];
+    const int ks = A.S ? A.ks[i] : 0;
+    const int c = A.c0 + ks;
+    double *F = W + (int64_t)c * ldw;
+    double *Nrm = F + (int64_t)A.d * p * ldw;
+    double *Ri = Nrm + ldw;
+    __syncthreads();
+    if (tid < A.d * p) {
+      int t = tid / p, k = tid % p;
+      double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+      xi[t * ID_PMAX + k] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[k];
+    }
+    __syncthreads();
+    if (m == 0) {
+      if (tid == 0) A.k_out[i] = 0;
+      continue;
+    }
+    // 1. C^T into W, initial column norms
+    for (int a = tid; a < m; a += ID_NT) {
+      basis_column(A, i, a, a, W, F, ldw, ks, xi, wk);
+      perm[a] = a;
+      double s2 = 0.0;
+      for (int r = 0; r < c; r++) {
+        double y = W[(int64_t)r * ldw + a];
+        s2 = fma(y, y, s2);
+      }
+      Nrm[a] = sqrt(s2);
+    }
+    __syncthreads();
+    // 2. Householder QR with column pivoting; rank by tol * |R_11|
+    const int kmax = m < c ? m : c;
+    int k = 0;
+    double r00 = 0.0;
+    for (int t = 0; t < kmax; t++) {
+      ArgMax am{-1.0, -1};
+      for (int a = t + tid; a < m; a += ID_NT) am = amax_pick(am, ArgMax{Nrm[a], a});
+      am = block_argmax(am, ared);
+      double bn = am.v;
+      if (t == 0) {
+        r00 = bn;
+        if (!(r00 > 0.0)) break;
+      } else if (!(bn > A.tol * r00)) {
+        break;
+      }
+      int best = am.a;
+      if (best != t) {
+        for (int r = tid; r < c; r += ID_NT) {
+          double tmp = W[(int64_t)r * ldw + t];
+          W[(int64_t)r * ldw + t] = W[(int64_t)r * ldw + best];
+          W[(int64_t)r * ldw + best] = tmp;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int tp = perm[t];
+          perm[t] = perm[best];
+          perm[best] = tp;
+          double tn = Nrm[t];
+          Nrm[t] = Nrm[best];
+          Nrm[best] = tn;
+        }
+      }
+      __syncthreads();
+      householder(W, ldw, c, m, t, bn, v, red, Nrm, true);
+      k = t + 1;
+    }
+    // 3. Gu-Eisenstat swaps
+    const int nr = m - k;
+    int nsw = 0;
+    bool failed = false;
+    if (k > 0 && nr > 0) {
+      for (;;) {
+        // N = R11^{-1} R12 (over R12, in place) and gamma_j = |R22 column j|
+        for (int a = k + tid; a < m; a += ID_NT) {
+          for (int ii = k - 1; ii >= 0; ii--) {
+            double s = W[(int64_t)ii * ldw + a];
+            for (int q = ii + 1; q < k; q++)
+              s = fma(-W[(int64_t)ii * ldw + q], W[(int64_t)q * ldw + a], s);
+            W[(int64_t)ii * ldw + a] = s / W[(int64_t)ii * ldw + ii];
+          }
+          double g2 = 0.0;
+          for (int r = k; r < c; r++) {
+            double y = W[(int64_t)r * ldw + a];
+            g2 = fma(y, y, g2);
+          }
+          Nrm[a] = sqrt(g2);
+        }
+        // R11^{-1}, column j per thread
+        for (int j = tid; j < k; j += ID_NT) {
+          for (int ii = k - 1; ii >= 0; ii--) {
+            double s = ii == j ? 1.0 : 0.0;
+            for (int q = ii + 1; q < k; q++)
+              s = fma(-W[(int64_t)ii * ldw + q], Ri[(int64_t)q * k + j], s);
+            Ri[(int64_t)ii * k + j] = s / W[(int64_t)ii * ldw + ii];
+          }
+        }
+        __syncthreads();
+        for (int ii = tid; ii < k; ii += ID_NT) {
+          double s = 0.0;
+          for (int j = 0; j < k; j++) {
+            double y = Ri[(int64_t)ii * k + j];
+            s = fma(y, y, s);
+          }
+          rinv[ii] = sqrt(s);
+        }
+        __syncthreads();
+        // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
+        // smallest j, then smallest i (pair index j*k + i)
+        ArgMax am{-1.0, -1};
+        for (int a = k + tid; a < m; a += ID_NT) {
+          double g = Nrm[a];
+          for (int ii = 0; ii < k; ii++) {
+            double nv = W[(int64_t)ii * ldw + a];
+            double b = g * rinv[ii];
+            double rho = sqrt(nv * nv + b * b);
+            am = amax_pick(am, ArgMax{rho, (a - k) * k + ii});
+          }
+        }
+        am = block_argmax(am, ared);
+        if (!(am.v > A.f)) break;
+        if (++nsw > 64 * k) {
+          failed = true;
+          break;
+        }
+        const int bj = am.a / k, bi = am.a % k;
+        __syncthreads();
+        if (tid == 0) {
+          int tp = perm[bi];
+          perm[bi] = perm[k + bj];
+          perm[k + bj] = tp;
+        }
+        __syncthreads();
+        // refactor the new column order without pivoting
+        for (int a = tid; a < m; a += ID_NT) basis_column(A, i, a, perm[a], W, F, ldw, ks, xi, wk);
+        __syncthreads();
+        for (int t = 0; t < k; t++) {
+          double part = 0.0;
+          for (int r = t + tid; r < c; r += ID_NT) {
+            double y = W[(int64_t)r * ldw + t];
+            part = fma(y, y, part);
+          }
+          double alpha = sqrt(block_sum(part, red));
+          householder(W, ldw, c, m, t, alpha, v, red, Nrm, false);
+        }
+      }
+    } else if (k > 0) {
+      // k == m: nothing to solve
+    }
+    if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+    if (failed) {
+      if (tid == 0) atomicOr(A.err, 1);
+      k = 0;
+    }
+    // 4. canonical output: skeleton positions ascending, then the rest
+    __syncthreads();
+    for (int a = tid; a < m; a += ID_NT) pos[a] = 0;
+    __syncthreads();
+    for (int q = tid; q < k; q += ID_NT) pos[perm[q]] = 1;
+    __syncthreads();
+    {
+      const int chunk = (m + ID_NT - 1) / ID_NT;
+      const int a0 = tid * chunk;
+      int64_t cnt = 0;
+      for (int u = 0; u < chunk; u++)
+        if (a0 + u < m) cnt += pos[a0 + u];
+      int64_t tot;
+      int64_t ex = block_excl_scan_i64(cnt, &tot, sred);
+      int *sel = A.sel_out + A.selo[i];
+      for (int u = 0; u < chunk; u++) {
+        int a = a0 + u;
+        if (a >= m) break;
+        int fl = pos[a];
+        if (fl)
+          sel[ex] = a;
+        else
+          sel[k + (a - ex)] = a;
+        pos[a] = fl ? (int)ex : -(int)(a - ex) - 1;  // skeleton rank, or -(rest rank)-1
+        ex += fl;
+      }
+    }
+    __syncthreads();
+    if (k > 0 && nr > 0) {
+      double *G = A.G_out + A.go[i];
+      for (int a = k + tid; a < m; a += ID_NT) {
+        int row = -pos[perm[a]] - 1;
+        for (int ii = 0; ii < k; ii++) G[(int64_t)row * k + pos[perm[ii]]] = W[(int64_t)ii * ldw + a];
+      }
+    }
+    if (tid == 0) A.k_out[i] = k;
+  }
+}
+
+// ------------------------------------------------------------------------
+// HSS near-field SVD, one workgroup per node: one-sided (Hestenes) Jacobi
+// on the rows of A_i (m x nc), parallel round-robin pair ordering (m/2
+// disjoint rotations per round, SV_G threads per rotation), sweeps until no
+// pair has |a_p . a_q| > 1e-15 |a_p||a_q|.  The accumulated rotations are
+// the left singular vectors; the kept ones (sigma >= eps * sigma_1, by
+// decreasing sigma) are written as S (m x ks row-major).
+// ------------------------------------------------------------------------
+constexpr int SV_NT = 256, SV_G = 8, SV_MMAX = 512;  // largest near-field row count
+
+struct SvdArgs {
+  int nb, ne;
+  const int *m_me;
+  const int64_t *gbeg_me;
+  const int *slot_me;
+  const double *P_me;
+  const int *m_ot;
+  const int64_t *gbeg_ot;
+  const int *slot_ot;
+  const double *P_ot;
+  const int *Nrow, *Ncol;
+  int rowside;
+  int kid, d;
+  double diag, eps;
+  double *scratch;  // per workgroup: A (mpad x ldn), V (mpad x mpad)
+  int ldn;
+  int64_t wg_stride;
+  double *S;  // output
+  const int64_t *S_off;
+  int *ks_out;
+};
+
+__global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
+  __shared__ double sg[SV_MMAX];
+  __shared__ int ord[SV_MMAX];
+  __shared__ int any_rot;
+  const int tid = threadIdx.x;
+  double *Am = A.scratch + (int64_t)blockIdx.x * A.wg_stride;
+  for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
+    const int m = A.m_me[i];
+    int nc = 0;
+    for (int q = A.Nrow[i]; q < A.Nrow[i + 1]; q++) nc += A.m_ot[A.Ncol[q]];
+    const int ldn = A.ldn;
+    const int mp = m + (m & 1);  // even row count (a zero row pads odd m)
+    double *V = Am + (int64_t)mp * ldn;
+    __syncthreads();
+    if (m == 0 || nc == 0) {
+      if (tid == 0) A.ks_out[i] = 0;
+      continue;
+    }
+    // block row: column o <-> point of the other side's grid, N_i order
+    {
+      int o = 0;
+      for (int q = A.Nrow[i]; q < A.Nrow[i + 1]; q++) {
+        int j = A.Ncol[q];
+        int mj = A.m_ot[j];
+        int64_t gj = A.gbeg_ot[j];
+        for (int e = tid; e < mj * mp; e += SV_NT) {
+          int b = e / mp, r = e % mp;
+          double val = 0.0;
+          if (r < m) {
+            const double *pme = A.P_me + (int64_t)A.slot_me[A.gbeg_me[i] + r] * A.d;
+            const double *pot = A.P_ot + (int64_t)A.slot_ot[gj + b] * A.d;
+            val = A.rowside ? kernel_f64(A.kid, pme, pot, A.d, A.diag)
+                            : kernel_f64(A.kid, pot, pme, A.d, A.diag);
+          }
+          Am[(int64_t)r * ldn + o + b] = val;
+        }
+        o += mj;
+      }
+      for (int e = tid; e < mp * mp; e += SV_NT) V[e] = (e / mp == e % mp) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // Jacobi sweeps
+    const int g = tid / SV_G, gl = tid % SV_G;
+    const int npairs = mp / 2;
+    for (int sweep = 0; sweep < 80; sweep++) {
+      if (tid == 0) any_rot = 0;
+      __syncthreads();
+      for (int round = 0; round < mp - 1; round++) {
+        for (int pr = g; pr < npairs; pr += SV_NT / SV_G) {
+          // round-robin: position 0 fixed, others rotate
+          int a0 = pr, b0 = mp - 1 - pr;
+          auto rr = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + round) % (mp - 1); };
+          int pp = rr(a0), qq = rr(b0);
+          if (pp > qq) {
+            int t = pp;
+            pp = qq;
+            qq = t;
+          }
+          double *ap = Am + (int64_t)pp * ldn, *aq = Am + (int64_t)qq * ldn;
+          double al = 0.0, be = 0.0, ga = 0.0;
+          for (int t = gl; t < nc; t += SV_G) {
+            double x = ap[t], y = aq[t];
+            al = fma(x, x, al);
+            be = fma(y, y, be);
+            ga = fma(x, y, ga);
+          }
+          for (int o = SV_G / 2; o > 0; o >>= 1) {
+            al += __shfl_xor(al, o, SV_G);
+            be += __shfl_xor(be, o, SV_G);
+            ga += __shfl_xor(ga, o, SV_G);
+          }
+          if (al == 0.0 || be == 0.0) continue;
+          if (fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
+          if (gl == 0) any_rot = 1;
+          double zeta = (be - al) / (2.0 * ga);
+          double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double cs = 1.0 / sqrt(1.0 + tt * tt);
+          double sn = cs * tt;
+          for (int t = gl; t < nc; t += SV_G) {
+            double x = ap[t], y = aq[t];
+            ap[t] = cs * x - sn * y;
+            aq[t] = sn * x + cs * y;
+          }
+          for (int t = gl; t < mp; t += SV_G) {
+            double x = V[(int64_t)t * mp + pp], y = V[(int64_t)t * mp + qq];
+            V[(int64_t)t * mp + pp] = cs * x - sn * y;
+            V[(int64_t)t * mp + qq] = sn * x + cs * y;
+          }
+        }
+        __syncthreads();
+      }
+      if (!any_rot) break;
+      __syncthreads();
+    }
+    // singular values, order by decreasing sigma (ties: index)
+    for (int a = tid; a < mp; a += SV_NT) {
+      double s = 0.0;
+      for (int t = 0; t < nc; t++) s = fma(Am[(int64_t)a * ldn + t], Am[(int64_t)a * ldn + t], s);
+      sg[a] = a < m ? sqrt(s) : -1.0;
+    }
+    __syncthreads();
+    for (int a = tid; a < mp; a += SV_NT) {
+      int rank = 0;
+      for (int b = 0; b < mp; b++)
+        if (sg[b] > sg[a] || (sg[b] == sg[a] && b < a)) rank++;
+      ord[rank] = a;
+    }
+    __syncthreads();
+    double s1 = sg[ord[0]];
+    int ks = 0;
+    if (s1 > 0.0)
+      for (int a = 0; a < m; a++)
+        if (sg[ord[a]] >= A.eps * s1) ks = a + 1;
+    double *S = A.S + A.S_off[i - A.nb];
+    for (int e = tid; e < m * ks; e += SV_NT) {
+      int r = e / ks, q = e % ks;
+      S[e] = V[(int64_t)r * mp + ord[q]];
+    }
+    if (tid == 0) A.ks_out[i] = ks;
+  }
+}
+
+// ------------------------------------------------------------------------
+// level bookkeeping
+// ------------------------------------------------------------------------
+struct PrepArgs {
+  int nb, ne;
+  const int *nchild, *first_child;
+  const int *xb, *xe;  // point range of this side
+  int *m;
+  int64_t *gbeg;
+  const int *k;
+  const int64_t *hbeg;
+  int c0, hss;
+  int64_t *cm, *cg;  // out: m and G capacity per node (for scans)
+  int *mmax;
+};
+
+__global__ void k_leaf_init(int nnodes, const int *nchild, const int *xb, const int *xe, int *m,
+                            int64_t *gbeg, int *k) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes) return;
+  if (i == 0) {
+    m[0] = 0;
+    k[0] = 0;
+    gbeg[0] = 0;
+  } else if (nchild[i] == 0) {
+    m[i] = xe[i] - xb[i];
+    gbeg[i] = xb[i];
+  }
+}
+
+__global__ void k_level_prep(PrepArgs A) {
+  int i = A.nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.ne) return;
+  int m;
+  if (A.nchild[i] > 0) {
+    int fc = A.first_child[i];
+    m = 0;
+    for (int c = 0; c < A.nchild[i]; c++) m += A.k[fc + c];
+    A.m[i] = m;
+    A.gbeg[i] = A.hbeg[fc];
+  } else {
+    m = A.m[i];
+  }
+  int64_t mm = m;
+  int64_t cap;
+  if (A.hss)
+    cap = mm * mm / 4;
+  else
+    cap = (2 * A.c0 >= mm) ? mm * mm / 4 : (mm - A.c0) * A.c0;
+  A.cm[i - A.nb] = mm;
+  A.cg[i - A.nb] = cap;
+  atomicMax(A.mmax, m);
+}
+
+__global__ void k_kcopy(int nb, int ne, const int *k, int64_t *out) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ne) out[i - nb] = k[i];
+}
+
+__global__ void k_set_hbeg(int nb, int ne, const int64_t *off, int64_t *hbeg) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ne) hbeg[i] = off[i - nb];
+}
+
+__global__ void k_set_rel(int nb, int ne, const int64_t *off, int64_t *dst) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ne) dst[i] = off[i - nb];
+}
+
+// skeleton slots: slot_id[hbeg + t] = slot_id[gbeg + sel[t]]
+__global__ void k_slot_ids(int nb, int ne, const int *k, const int64_t *hbeg,
+                           const int64_t *gbeg, const int64_t *selo, const int *sel,
+                           int *slot_id) {
+  int i = nb + blockIdx.x;
+  if (i >= ne) return;
+  const int *s = sel + selo[i];
+  for (int t = threadIdx.x; t < k[i]; t += blockDim.x)
+    slot_id[hbeg[i] + t] = slot_id[gbeg[i] + s[t]];
+}
+
+__global__ void k_iota(int *a, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = (int)i;
+}
+
+__global__ void k_near_cols(int nb, int ne, const int *Nrow, const int *Ncol, const int *m_ot,
+                            const int *m_me, int *ncmax, int64_t *s_cap) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  int nc = 0;
+  for (int q = Nrow[i]; q < Nrow[i + 1]; q++) nc += m_ot[Ncol[q]];
+  atomicMax(ncmax, nc);
+  int64_t mm = m_me[i];
+  s_cap[i - nb] = mm * mm;
+}
+
+__global__ void k_to_f32(const double *in, float *out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = (float)in[i];
+}
+
+// ------------------------------------------------------------------------
+static void alloc_side(Handle &h, Side &S) {
+  int nn = h.nnodes;
+  S.m = h.mem.alloc_n<int>(nn);
+  S.k = h.mem.alloc_n<int>(nn);
+  S.ks = h.mem.alloc_n<int>(nn);
+  S.gbeg = h.mem.alloc_n<int64_t>(nn);
+  S.hbeg = h.mem.alloc_n<int64_t>(nn);
+  S.selo = h.mem.alloc_n<int64_t>(nn);
+  S.go = h.mem.alloc_n<int64_t>(nn);
+  SMASH_HIP(hipMemsetAsync(S.m, 0, sizeof(int) * nn, h.stream));
+  SMASH_HIP(hipMemsetAsync(S.k, 0, sizeof(int) * nn, h.stream));
+  SMASH_HIP(hipMemsetAsync(S.ks, 0, sizeof(int) * nn, h.stream));
+  SMASH_HIP(hipMemsetAsync(S.hbeg, 0, sizeof(int64_t) * nn, h.stream));
+  SMASH_HIP(hipMemsetAsync(S.selo, 0, sizeof(int64_t) * nn, h.stream));
+  SMASH_HIP(hipMemsetAsync(S.go, 0, sizeof(int64_t) * nn, h.stream));
+  S.lv.assign(h.nlevels + 1, LevelSide{});
+}
+
+static void grow_slots(Handle &h, Side &S, int64_t need) {
+  if (need <= S.slot_cap) return;
+  int64_t nc = S.slot_cap > 0 ? S.slot_cap : 1024;
+  while (nc < need) nc *= 2;
+  int *q = h.mem.alloc_n<int>(nc);
+  if (S.slot_id)
+    SMASH_HIP(hipMemcpyAsync(q, S.slot_id, sizeof(int) * S.nslots, hipMemcpyDeviceToDevice, h.stream));
+  S.slot_id = q;
+  S.slot_cap = nc;
+}
+
+struct SideCtx {
+  Side *S;
+  bool rowside;
+  const int *xb, *xe;
+  const double *P;
+  int64_t n;
+  // per level
+  int64_t *cm = nullptr, *cg = nullptr;
+  int mmax = 0;
+  double *Svec = nullptr;
+  int64_t *S_off = nullptr;
+};
+
+void build_generators(Handle &h) {
+  hipStream_t s = h.stream;
+  DeviceArena tmp;
+  tmp.stream = s;
+  try {
+    const int c0 = [&] {
+      int c = 1;
+      for (int t = 0; t < h.d; t++) c *= h.p;
+      return c;
+    }();
+    if (h.p > ID_PMAX) throw Error{SMASH_E_INVALID_ARG, "interpolation order above 64"};
+    if (c0 > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width p^d above 512"};
+    const bool hss = h.adm == SMASH_ADM_WEAK;
+    alloc_side(h, h.row);
+    h.col = h.reuse ? &h.row : &h.col_own;
+    if (!h.reuse) alloc_side(h, h.col_own);
+    std::vector<SideCtx> sides;
+    sides.push_back(SideCtx{&h.row, true, h.xb, h.xe, h.Xp, h.nx});
+    if (!h.reuse) sides.push_back(SideCtx{&h.col_own, false, h.yb, h.ye, h.Yp, h.ny});
+    int nn = h.nnodes;
+    for (auto &sc : sides) {
+      Side &S = *sc.S;
+      grow_slots(h, S, sc.n + 1024);
+      k_iota<<<ceil_div(sc.n, 256), 256, 0, s>>>(S.slot_id, sc.n);
+      SMASH_CHECK_LAUNCH();
+      S.nslots = sc.n;
+      k_leaf_init<<<ceil_div(nn, 256), 256, 0, s>>>(nn, h.nchild, sc.xb, sc.xe, S.m, S.gbeg, S.k);
+      SMASH_CHECK_LAUNCH();
+    }
+    int *dmax = tmp.alloc_n<int>(2);
+    int *dsw = tmp.alloc_n<int>(2);
+    SMASH_HIP(hipMemsetAsync(dsw, 0, 2 * sizeof(int), s));
+    int dev_cus = 256;
+    {
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, h.device) == hipSuccess) dev_cus = prop.multiProcessorCount;
+    }
+    for (int l = h.nlevels; l >= 2; l--) {
+      const int nb = h.level_beg[l - 1], ne = h.level_beg[l], nl = ne - nb;
+      // (a) grids and capacities of both sides
+      for (auto &sc : sides) {
+        Side &S = *sc.S;
+        sc.cm = tmp.alloc_n<int64_t>(nl);
+        sc.cg = tmp.alloc_n<int64_t>(nl);
+        SMASH_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
+        PrepArgs pa{nb, ne, h.nchild, h.first_child, sc.xb, sc.xe, S.m, S.gbeg, S.k, S.hbeg, c0,
+                    hss ? 1 : 0, sc.cm, sc.cg, dmax};
+        k_level_prep<<<ceil_div(nl, 256), 256, 0, s>>>(pa);
+        SMASH_CHECK_LAUNCH();
+        int64_t *o1 = tmp.alloc_n<int64_t>(nl + 1), *o2 = tmp.alloc_n<int64_t>(nl + 1);
+        scan_i64(sc.cm, o1, nl, nullptr, s, tmp);
+        scan_i64(sc.cg, o2, nl, nullptr, s, tmp);
+        k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o1, S.selo);
+        SMASH_CHECK_LAUNCH();
+        k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o2, S.go);
+        SMASH_CHECK_LAUNCH();
+        int64_t hv[2];
+        int mx;
+        SMASH_HIP(hipMemcpyAsync(&hv[0], o1 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipMemcpyAsync(&hv[1], o2 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipMemcpyAsync(&mx, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipStreamSynchronize(s));
+        sc.mmax = mx;
+        LevelSide &L = S.lv[l];
+        L.sel_n = hv[0];
+        L.g_n = hv[1];
+        L.sel = h.mem.alloc_n<int>(hv[0]);
+        L.G = h.mem.alloc_n<double>(hv[1]);
+      }
+      // (b) HSS: near-field SVD of each side
+      if (hss) {
+        for (size_t q = 0; q < sides.size(); q++) {
+          SideCtx &sc = sides[q];
+          SideCtx &ot = sides.size() > 1 ? sides[1 - q] : sides[0];
+          Side &S = *sc.S;
+          Side &O = *ot.S;
+          int64_t *scap = tmp.alloc_n<int64_t>(nl), *soff = tmp.alloc_n<int64_t>(nl + 1);
+          SMASH_HIP(hipMemsetAsync(dmax + 1, 0, sizeof(int), s));
+          k_near_cols<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, h.Nrow, h.Ncol, O.m, S.m, dmax + 1,
+                                                        scap);
+          SMASH_CHECK_LAUNCH();
+          scan_i64(scap, soff, nl, nullptr, s, tmp);
+          int64_t stot;
+          int ncmax;
+          SMASH_HIP(hipMemcpyAsync(&stot, soff + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+          SMASH_HIP(hipMemcpyAsync(&ncmax, dmax + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+          SMASH_HIP(hipStreamSynchronize(s));
+          if (sc.mmax > SV_MMAX)
+            throw Error{SMASH_E_UNSUPPORTED, "HSS grid larger than " + std::to_string(SV_MMAX) +
+                                                 " points (raise leaf resolution)"};
+          sc.Svec = tmp.alloc_n<double>(stot);
+          sc.S_off = soff;
+          int mp = sc.mmax + (sc.mmax & 1);
+          int ldn = ncmax > 0 ? ncmax : 1;
+          int nwg = nl < 4 * dev_cus ? nl : 4 * dev_cus;
+          int64_t wg_stride = (int64_t)mp * ldn + (int64_t)mp * mp + 8;
+          double *scr = tmp.alloc_n<double>((size_t)wg_stride * nwg);
+          SvdArgs sa{nb, ne, S.m, S.gbeg, S.slot_id, sc.P, O.m, O.gbeg, O.slot_id, ot.P, h.Nrow,
+                     h.Ncol, sc.rowside ? 1 : 0, h.kid, h.d, h.diag, h.eps_svd, scr, ldn,
+                     wg_stride, sc.Svec, soff, S.ks};
+          if (h.batched) {
+            k_near_svd<<<nwg, SV_NT, 0, s>>>(sa);
+            SMASH_CHECK_LAUNCH();
+          } else {
+            for (int i = nb; i < ne; i++) {
+              sa.nb = i;
+              sa.ne = i + 1;
+              sa.S_off = soff + (i - nb);
+              k_near_svd<<<1, SV_NT, 0, s>>>(sa);
+              SMASH_CHECK_LAUNCH();
+            }
+          }
+        }
+      }
+      // (c) compr on each side
+      for (auto &sc : sides) {
+        Side &S = *sc.S;
+        LevelSide &L = S.lv[l];
+        int cmax = c0 + (hss ? sc.mmax : 0);
+        if (cmax > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
+        int ldw = (sc.mmax + 1) | 1;  // odd stride
+        int nwg = nl < 2 * dev_cus ? nl : 2 * dev_cus;
+        int64_t wg_stride = (int64_t)cmax * ldw + (int64_t)h.d * h.p * ldw + ldw +
+                            (int64_t)cmax * cmax + 8;
+        double *scr = tmp.alloc_n<double>((size_t)wg_stride * nwg);
+        int *iscr = tmp.alloc_n<int>((size_t)2 * ldw * nwg);
+        IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo, S.go,
+                  L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
+                  h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1};
+        if (h.batched) {
+          k_compr<<<nwg, ID_NT, 0, s>>>(ia);
+          SMASH_CHECK_LAUNCH();
+        } else {
+          for (int i = nb; i < ne; i++) {
+            ia.nb = i;
+            ia.ne = i + 1;
+            if (hss) ia.S_off = sc.S_off + (i - nb);
+            k_compr<<<1, ID_NT, 0, s>>>(ia);
+            SMASH_CHECK_LAUNCH();
+          }
+        }
+      }
+      // (d) skeleton slots of this level
+      for (auto &sc : sides) {
+        Side &S = *sc.S;
+        int64_t *ck = tmp.alloc_n<int64_t>(nl), *ok = tmp.alloc_n<int64_t>(nl + 1);
+        int64_t *base = tmp.alloc_n<int64_t>(1);
+        SMASH_HIP(hipMemcpyAsync(base, &S.nslots, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        k_kcopy<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.k, ck);
+        SMASH_CHECK_LAUNCH();
+        scan_i64(ck, ok, nl, base, s, tmp);
+        k_set_hbeg<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, ok, S.hbeg);
+        SMASH_CHECK_LAUNCH();
+        int64_t end;
+        SMASH_HIP(hipMemcpyAsync(&end, ok + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipStreamSynchronize(s));
+        grow_slots(h, S, end);
+        k_slot_ids<<<nl, 64, 0, s>>>(nb, ne, S.k, S.hbeg, S.gbeg, S.selo, S.lv[l].sel, S.slot_id);
+        SMASH_CHECK_LAUNCH();
+        S.nslots = end;
+      }
+      int herr[2];
+      SMASH_HIP(hipMemcpyAsync(herr, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipStreamSynchronize(s));
+      if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
+      tmp.release();
+      dmax = tmp.alloc_n<int>(2);
+      int *nsw = tmp.alloc_n<int>(2);
+      SMASH_HIP(hipMemcpyAsync(nsw, herr, sizeof(herr), hipMemcpyHostToDevice, s));
+      dsw = nsw;
+    }
+    int herr[2] = {0, 0};
+    SMASH_HIP(hipMemcpyAsync(herr, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
+    SMASH_HIP(hipStreamSynchronize(s));
+    h.total_swaps = herr[0];
+    // apply copies
+    if (h.apply_prec == SMASH_F32) {
+      for (auto &sc : sides) {
+        for (int l = 2; l <= h.nlevels; l++) {
+          LevelSide &L = sc.S->lv[l];
+          L.G32 = h.mem.alloc_n<float>(L.g_n);
+          if (L.g_n > 0) {
+            k_to_f32<<<ceil_div(L.g_n, 256), 256, 0, s>>>(L.G, L.G32, L.g_n);
+            SMASH_CHECK_LAUNCH();
+          }
+        }
+      }
+    }
+    SMASH_HIP(hipStreamSynchronize(s));
+    tmp.release();
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    throw;
+  }
+}
+
+}  // namespace smash

@@ -1,0 +1,145 @@
+// internal.h -- shared declarations of libsmash (not part of the ABI).
+//
+// Device data layout (all row-major):
+//  * Points are kept permuted: Xp (nx x d) and Yp (ny x d) FP64, in the
+//    depth-first order of the partition tree, so every node owns a
+//    contiguous range [xb, xe) of X and [yb, ye) of Y.
+//  * Nodes are numbered level by level (root = node 0, level 1), Morton
+//    order inside a level; the children of a node are consecutive.
+//  * Slot space (one per side): slots [0, n) are the permuted points; then
+//    each level l = L, L-1, ..., 2 appends one slot per skeleton point of its
+//    nodes.  A node's current grid (eqs. (3.6), (3.14), (3.18)) is the slot
+//    range [gbeg, gbeg + m) -- a leaf's own points, or the consecutive
+//    skeleton slots of its children -- and its skeleton occupies
+//    [hbeg, hbeg + k).  slot_id maps a slot to its permuted point id.
+//    The product uses the same slot space for q / q-hat (column side) and
+//    z / z-hat (row side).
+//  * Per node and side: sel (m int32: skeleton positions ascending, then the
+//    remaining positions ascending) and G ((m-k) x k), the interpolative
+//    decomposition U = P [I; G] of eq. (2.11), stored per level.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/smash.h"
+
+namespace smash {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+
+#define SMASH_HIP(call)                                                          \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess)                                                        \
+      throw ::smash::Error{SMASH_E_DEVICE, std::string(#call) + ": " +           \
+                                               hipGetErrorString(e_)};           \
+  } while (0)
+
+#define SMASH_CHECK_LAUNCH() SMASH_HIP(hipGetLastError())
+
+inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------- allocator
+// Stream-ordered allocations from the device's default memory pool (kept
+// cached across builds); every pointer is tracked by its owner.
+struct DeviceArena {
+  hipStream_t stream = nullptr;
+  std::vector<void *> ptrs;
+  int64_t bytes = 0;
+  void *alloc(size_t n);
+  template <class T>
+  T *alloc_n(size_t n) {
+    return (T *)alloc(sizeof(T) * (n ? n : 1));
+  }
+  void release();
+};
+
+// ---------------------------------------------------------------- scans / sort
+// Exclusive scan of int64 values: out[i] = base + sum_{j<i} in[i]; out[n] =
+// base + total (out has n+1 entries).  base_dev may be null (then 0).
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, const int64_t *base_dev,
+              hipStream_t s, DeviceArena &tmp);
+// Stable LSD radix sort of (key, value) pairs on bits [0, nbits).  Results
+// land in keys/vals (alt buffers are scratch of the same size).
+void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
+                    int64_t n, int nbits, hipStream_t s, DeviceArena &tmp);
+
+// ---------------------------------------------------------------- handle
+struct LevelSide {
+  int *sel = nullptr;     // concatenated sel of the level's nodes
+  double *G = nullptr;    // concatenated G (FP64 master)
+  float *G32 = nullptr;   // apply copy
+  int64_t sel_n = 0, g_n = 0;
+};
+
+struct Side {
+  int *m = nullptr, *k = nullptr, *ks = nullptr;  // per node
+  int64_t *gbeg = nullptr, *hbeg = nullptr, *selo = nullptr, *go = nullptr;
+  int *slot_id = nullptr;
+  int64_t slot_cap = 0, nslots = 0;
+  std::vector<LevelSide> lv;  // indexed by level (1-based; [0] unused)
+  int64_t sum_k = 0, g_total = 0;
+  int max_k = 0;
+};
+
+struct Handle {
+  // problem
+  int d = 0, kid = 0, adm = 0, leaf = 0, p = 0;
+  double tol = 0, tau = 0, eps_svd = 0, f = 2, diag = 0;
+  int eval_prec = SMASH_F64, apply_prec = SMASH_F64, batched = 1;
+  int64_t nx = 0, ny = 0;
+  bool same_xy = false, reuse = false;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  DeviceArena mem;
+  // permuted points
+  double *Xp = nullptr, *Yp = nullptr;
+  int *perm_x = nullptr, *perm_y = nullptr;
+  // geometry
+  bool has_root = false;
+  double root_lo[3] = {0, 0, 0}, root_hi[3] = {0, 0, 0};
+  int bpl = 1, max_split = 0;
+  // tree
+  int nnodes = 0, nlevels = 0, nleaves = 0;
+  std::vector<int> level_beg;  // size nlevels+1
+  int *level = nullptr, *parent = nullptr, *first_child = nullptr, *nchild = nullptr;
+  int *xb = nullptr, *xe = nullptr, *yb = nullptr, *ye = nullptr;
+  double *lo = nullptr, *hi = nullptr;  // nnodes x 3
+  // pair lists (sorted by (i, j)) and CSR rows
+  int64_t nL = 0, nLm = 0;
+  int *Li = nullptr, *Lj = nullptr, *Lmi = nullptr, *Lmj = nullptr;
+  int *Lrow = nullptr, *Lmrow = nullptr;
+  int *Nrow = nullptr, *Ncol = nullptr;  // HSS N_i
+  int64_t nN = 0;
+  // sides
+  Side row, col_own;
+  Side *col = nullptr;  // == &row when reused
+  // blocks (apply precision)
+  int64_t *boff = nullptr, *nboff = nullptr;
+  void *B = nullptr, *Bn = nullptr;
+  int64_t b_entries = 0, n_entries = 0;
+  int64_t total_swaps = 0;
+  double build_ms = 0;
+  // product workspaces
+  int ws_nrhs = 0;
+  void *qbuf = nullptr, *zbuf = nullptr;
+  DeviceArena ws_mem;
+};
+
+// ---------------------------------------------------------------- stages
+void build_tree(Handle &h, const double *x, const double *y);
+void build_pairs(Handle &h);
+void build_generators(Handle &h);
+void build_blocks(Handle &h);
+void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
+                hipStream_t s);
+
+}  // namespace smash

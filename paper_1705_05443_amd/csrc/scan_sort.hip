@@ -1,0 +1,218 @@
+// scan_sort.hip -- device-wide exclusive scans and a stable LSD radix sort
+// (4-bit digits), the integer building blocks of the partition tree and of
+// the pair lists.  Stability of the sort is what makes the point order and
+// the sorted pair lists bit-exact and reproducible.
+#include "common.cuh"
+
+namespace smash {
+
+void *DeviceArena::alloc(size_t n) {
+  void *p = nullptr;
+  hipError_t e = hipMallocAsync(&p, n, stream);
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    throw Error{SMASH_E_OOM, "device allocation of " + std::to_string(n) + " bytes failed"};
+  }
+  ptrs.push_back(p);
+  bytes += (int64_t)n;
+  return p;
+}
+
+void DeviceArena::release() {
+  for (void *p : ptrs) (void)hipFreeAsync(p, stream);
+  ptrs.clear();
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------ scan
+constexpr int SC_NT = 256, SC_IT = 8, SC_TILE = SC_NT * SC_IT;
+
+__global__ void __launch_bounds__(SC_NT) k_scan_reduce(const int64_t *in, int64_t n,
+                                                       int64_t *bsum) {
+  __shared__ int64_t lds[SC_NT / 64 + 1];
+  int64_t b0 = (int64_t)blockIdx.x * SC_TILE;
+  int64_t s = 0;
+  for (int u = 0; u < SC_IT; u++) {
+    int64_t i = b0 + (int64_t)threadIdx.x * SC_IT + u;
+    if (i < n) s += in[i];
+  }
+  int64_t tot;
+  block_excl_scan_i64(s, &tot, lds);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// exclusive scan of the block sums in one workgroup; writes out[n] = total
+__global__ void __launch_bounds__(1024) k_scan_top(int64_t *bsum, int nb, const int64_t *base_dev,
+                                                   int64_t *out, int64_t n) {
+  __shared__ int64_t lds[1024 / 64 + 1];
+  int per = (nb + 1023) / 1024;
+  int b0 = threadIdx.x * per;
+  int64_t s = 0;
+  for (int u = 0; u < per; u++)
+    if (b0 + u < nb) s += bsum[b0 + u];
+  int64_t tot;
+  int64_t ex = block_excl_scan_i64(s, &tot, lds);
+  int64_t base = base_dev ? *base_dev : 0;
+  ex += base;
+  for (int u = 0; u < per; u++)
+    if (b0 + u < nb) {
+      int64_t v = bsum[b0 + u];
+      bsum[b0 + u] = ex;
+      ex += v;
+    }
+  if (threadIdx.x == 0) out[n] = base + tot;
+}
+
+__global__ void __launch_bounds__(SC_NT) k_scan_down(const int64_t *in, int64_t n,
+                                                     const int64_t *bsum, int64_t *out) {
+  __shared__ int64_t lds[SC_NT / 64 + 1];
+  int64_t b0 = (int64_t)blockIdx.x * SC_TILE + (int64_t)threadIdx.x * SC_IT;
+  int64_t v[SC_IT];
+  int64_t s = 0;
+  for (int u = 0; u < SC_IT; u++) {
+    int64_t i = b0 + u;
+    v[u] = i < n ? in[i] : 0;
+    s += v[u];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan_i64(s, &tot, lds) + bsum[blockIdx.x];
+  for (int u = 0; u < SC_IT; u++) {
+    int64_t i = b0 + u;
+    if (i < n) out[i] = ex;
+    ex += v[u];
+  }
+}
+
+void scan_i64(const int64_t *in, int64_t *out, int64_t n, const int64_t *base_dev,
+              hipStream_t s, DeviceArena &tmp) {
+  int nb = n > 0 ? ceil_div(n, SC_TILE) : 0;
+  int64_t *bsum = tmp.alloc_n<int64_t>(nb + 1);
+  if (nb > 0) {
+    k_scan_reduce<<<nb, SC_NT, 0, s>>>(in, n, bsum);
+    SMASH_CHECK_LAUNCH();
+  }
+  k_scan_top<<<1, 1024, 0, s>>>(bsum, nb, base_dev, out, n);
+  SMASH_CHECK_LAUNCH();
+  if (nb > 0) {
+    k_scan_down<<<nb, SC_NT, 0, s>>>(in, n, bsum, out);
+    SMASH_CHECK_LAUNCH();
+  }
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int RS_NT = 256, RS_IT = 8, RS_TILE = RS_NT * RS_IT, RS_R = 16;
+
+__global__ void __launch_bounds__(RS_NT) k_rs_hist(const uint64_t *keys, int64_t n, int shift,
+                                                   int ntiles, int *hist) {
+  __shared__ int cnt[RS_R];
+  if (threadIdx.x < RS_R) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  int64_t b0 = (int64_t)blockIdx.x * RS_TILE;
+  for (int u = 0; u < RS_IT; u++) {
+    int64_t i = b0 + (int64_t)u * RS_NT + threadIdx.x;
+    if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & (RS_R - 1)], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < RS_R) hist[threadIdx.x * ntiles + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// exclusive scan of the digit-major histogram (RS_R x ntiles), one workgroup
+__global__ void __launch_bounds__(1024) k_rs_scan(int *hist, int total) {
+  __shared__ int64_t lds[1024 / 64 + 1];
+  int per = (total + 1023) / 1024;
+  int b0 = threadIdx.x * per;
+  int64_t s = 0;
+  for (int u = 0; u < per; u++)
+    if (b0 + u < total) s += hist[b0 + u];
+  int64_t tot;
+  int64_t ex = block_excl_scan_i64(s, &tot, lds);
+  for (int u = 0; u < per; u++)
+    if (b0 + u < total) {
+      int v = hist[b0 + u];
+      hist[b0 + u] = (int)ex;
+      ex += v;
+    }
+}
+
+// Each thread owns RS_IT consecutive elements of the tile, so tile order is
+// (thread, item); ranks are (digit, thread, item)-ordered: stable.
+__global__ void __launch_bounds__(RS_NT) k_rs_scatter(const uint64_t *kin, const int32_t *vin,
+                                                      uint64_t *kout, int32_t *vout, int64_t n,
+                                                      int shift, int ntiles, const int *hist) {
+  __shared__ int cnt[RS_R * RS_NT];
+  __shared__ int64_t lds[RS_NT / 64 + 1];
+  __shared__ int dbase[RS_R];
+  const int t = threadIdx.x;
+  for (int r = 0; r < RS_R; r++) cnt[r * RS_NT + t] = 0;
+  int64_t b0 = (int64_t)blockIdx.x * RS_TILE + (int64_t)t * RS_IT;
+  uint64_t kk[RS_IT];
+  int32_t vv[RS_IT];
+  for (int u = 0; u < RS_IT; u++) {
+    int64_t i = b0 + u;
+    if (i < n) {
+      kk[u] = kin[i];
+      vv[u] = vin[i];
+      cnt[((kk[u] >> shift) & (RS_R - 1)) * RS_NT + t]++;
+    }
+  }
+  __syncthreads();
+  // exclusive scan over cnt in (digit, thread) order; thread t owns entries
+  // [t*RS_R, t*RS_R + RS_R) of the flattened array
+  int loc[RS_R];
+  int s = 0;
+  for (int r = 0; r < RS_R; r++) {
+    loc[r] = cnt[t * RS_R + r];
+    s += loc[r];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan_i64(s, &tot, lds);
+  __syncthreads();
+  for (int r = 0; r < RS_R; r++) {
+    cnt[t * RS_R + r] = (int)ex;
+    ex += loc[r];
+  }
+  __syncthreads();
+  // tile-local start of every digit: entry (digit, thread 0)
+  if (t < RS_R) dbase[t] = hist[t * ntiles + blockIdx.x] - cnt[t * RS_NT];
+  __syncthreads();
+  for (int u = 0; u < RS_IT; u++) {
+    int64_t i = b0 + u;
+    if (i < n) {
+      int dg = (int)((kk[u] >> shift) & (RS_R - 1));
+      int pos = dbase[dg] + cnt[dg * RS_NT + t]++;
+      kout[pos] = kk[u];
+      vout[pos] = vv[u];
+    }
+  }
+}
+
+void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
+                    int64_t n, int nbits, hipStream_t s, DeviceArena &tmp) {
+  if (n <= 1 || nbits <= 0) return;
+  int ntiles = ceil_div(n, RS_TILE);
+  int *hist = tmp.alloc_n<int>((size_t)RS_R * ntiles);
+  int passes = (nbits + 3) / 4;
+  uint64_t *ka = keys, *kb = keys_alt;
+  int32_t *va = vals, *vb = vals_alt;
+  for (int ps = 0; ps < passes; ps++) {
+    int shift = 4 * ps;
+    k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ka, n, shift, ntiles, hist);
+    SMASH_CHECK_LAUNCH();
+    k_rs_scan<<<1, 1024, 0, s>>>(hist, RS_R * ntiles);
+    SMASH_CHECK_LAUNCH();
+    k_rs_scatter<<<ntiles, RS_NT, 0, s>>>(ka, va, kb, vb, n, shift, ntiles, hist);
+    SMASH_CHECK_LAUNCH();
+    uint64_t *tk = ka;
+    ka = kb;
+    kb = tk;
+    int32_t *tv = va;
+    va = vb;
+    vb = tv;
+  }
+  if (ka != keys) {
+    SMASH_HIP(hipMemcpyAsync(keys, ka, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    SMASH_HIP(hipMemcpyAsync(vals, va, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+  }
+}
+
+}  // namespace smash

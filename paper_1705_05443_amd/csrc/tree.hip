@@ -1,0 +1,372 @@
+// tree.hip -- adaptive partition of Sec. 3.1 (binary bisection for HSS,
+// Remark A.1) and the point permutation.
+//
+// Every point gets its full bisection key: the sequence of half-box choices
+// (x >= mid goes up, mid = 0.5*(lo+hi)) from the root box down through all
+// bisection stages the 64-bit key allows, most significant first, axis 0
+// first inside a stage.  A stable radix sort by key gives the permutation:
+// every box of the tree is then a contiguous range, and inside a leaf the
+// points keep the order of their finer bisection path (ties: input order).
+// Nodes are then discovered level by level: a node holding more than nu_0
+// points of X or of Y is split into its non-empty children, whose ranges
+// are found by binary search on the key digit of that stage.
+#include "common.cuh"
+
+namespace smash {
+
+struct Geom {
+  double lo[3], hi[3];
+  int d, hss, bpl, max_split;
+};
+
+__global__ void k_keys(const double *__restrict__ pts, int64_t n, Geom g,
+                       uint64_t *__restrict__ keys, int32_t *__restrict__ idx) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  double x[3], lo[3], hi[3];
+  for (int t = 0; t < g.d; t++) {
+    x[t] = pts[a * g.d + t];
+    lo[t] = g.lo[t];
+    hi[t] = g.hi[t];
+  }
+  uint64_t key = 0;
+  for (int s = 0; s < g.max_split; s++) {
+    for (int u = 0; u < g.bpl; u++) {
+      int t = g.hss ? (s % g.d) : u;
+      double mid = 0.5 * (lo[t] + hi[t]);
+      bool up = x[t] >= mid;
+      key = (key << 1) | (uint64_t)up;
+      if (up)
+        lo[t] = mid;
+      else
+        hi[t] = mid;
+    }
+  }
+  keys[a] = key;
+  idx[a] = (int32_t)a;
+}
+
+__global__ void k_gather_points(const double *__restrict__ pts, const int32_t *__restrict__ perm,
+                                int64_t n, int d, double *__restrict__ out) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  int64_t src = perm[a];
+  for (int t = 0; t < d; t++) out[a * d + t] = pts[src * d + t];
+}
+
+__device__ inline int key_digit(uint64_t key, int s, const Geom &g) {
+  int shift = (g.max_split - 1 - s) * g.bpl;
+  return (int)((key >> shift) & ((1ull << g.bpl) - 1ull));
+}
+
+// first index in [b, e) whose stage-s digit exceeds v (digits ascend there)
+__device__ inline int run_end(const uint64_t *keys, int b, int e, int s, int v, const Geom &g) {
+  while (b < e) {
+    int mid = b + (e - b) / 2;
+    if (key_digit(keys[mid], s, g) <= v)
+      b = mid + 1;
+    else
+      e = mid;
+  }
+  return b;
+}
+
+struct NodeArrays {
+  int *level, *parent, *first_child, *nchild, *xb, *xe, *yb, *ye;
+  double *lo, *hi;
+};
+
+__global__ void k_tree_split(NodeArrays N, int nb, int ne, const uint64_t *kx,
+                             const uint64_t *ky, int s, int leaf, Geom g, int64_t *cnt) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
+  bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
+  int c = 0;
+  if (split) {
+    int ax = xb, ay = yb;
+    for (int v = 0; v < (1 << g.bpl); v++) {
+      int bx = run_end(kx, ax, xe, s, v, g), by = run_end(ky, ay, ye, s, v, g);
+      if (bx > ax || by > ay) c++;
+      ax = bx;
+      ay = by;
+    }
+  }
+  cnt[i - nb] = c;
+}
+
+__global__ void k_tree_emit(NodeArrays N, int nb, int ne, const uint64_t *kx,
+                            const uint64_t *ky, int s, int leaf, Geom g, const int64_t *off) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
+  bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
+  int first = (int)off[i - nb];
+  int c = 0;
+  if (split) {
+    int ax = xb, ay = yb;
+    for (int v = 0; v < (1 << g.bpl); v++) {
+      int bx = run_end(kx, ax, xe, s, v, g), by = run_end(ky, ay, ye, s, v, g);
+      if (bx > ax || by > ay) {
+        int ch = first + c;
+        N.level[ch] = N.level[i] + 1;
+        N.parent[ch] = i;
+        N.first_child[ch] = -1;
+        N.nchild[ch] = 0;
+        N.xb[ch] = ax;
+        N.xe[ch] = bx;
+        N.yb[ch] = ay;
+        N.ye[ch] = by;
+        for (int t = 0; t < 3; t++) {
+          N.lo[3 * ch + t] = N.lo[3 * i + t];
+          N.hi[3 * ch + t] = N.hi[3 * i + t];
+        }
+        for (int u = 0; u < g.bpl; u++) {
+          int t = g.hss ? (s % g.d) : u;
+          int up = (v >> (g.bpl - 1 - u)) & 1;
+          double mid = 0.5 * (N.lo[3 * i + t] + N.hi[3 * i + t]);
+          if (up)
+            N.lo[3 * ch + t] = mid;
+          else
+            N.hi[3 * ch + t] = mid;
+        }
+        c++;
+      }
+      ax = bx;
+      ay = by;
+    }
+  }
+  N.nchild[i] = c;
+  N.first_child[i] = c > 0 ? first : -1;
+}
+
+__global__ void k_root(NodeArrays N, int nx, int ny, Geom g) {
+  N.level[0] = 1;
+  N.parent[0] = -1;
+  N.first_child[0] = -1;
+  N.nchild[0] = 0;
+  N.xb[0] = 0;
+  N.xe[0] = nx;
+  N.yb[0] = 0;
+  N.ye[0] = ny;
+  for (int t = 0; t < 3; t++) {
+    N.lo[t] = t < g.d ? g.lo[t] : 0.0;
+    N.hi[t] = t < g.d ? g.hi[t] : 0.0;
+  }
+}
+
+// min / max of one coordinate over a point set (root bounding cube)
+__global__ void k_minmax(const double *pts, int64_t n, int d, double *out /* 2*d */) {
+  __shared__ double smin[256], smax[256];
+  for (int t = 0; t < d; t++) {
+    double mn = INFINITY, mx = -INFINITY;
+    for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+      double v = pts[a * d + t];
+      mn = fmin(mn, v);
+      mx = fmax(mx, v);
+    }
+    smin[threadIdx.x] = mn;
+    smax[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) {
+        smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + o]);
+        smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + o]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      out[2 * t] = smin[0];
+      out[2 * t + 1] = smax[0];
+    }
+    __syncthreads();
+  }
+}
+
+// counts of non-finite coordinates and of coordinates outside [lo, hi]
+__global__ void k_check_points(const double *pts, int64_t n, int d, Geom g, int use_box,
+                               int *bad) {
+  int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  for (int t = 0; t < d; t++) {
+    double v = pts[a * d + t];
+    if (!isfinite(v)) atomicOr(&bad[0], 1);
+    if (use_box && !(v >= g.lo[t] && v <= g.hi[t])) atomicOr(&bad[1], 1);
+  }
+}
+
+static void grow_nodes(Handle &h, int &cap, int need) {
+  if (need <= cap) return;
+  int nc = cap > 0 ? cap : 1024;
+  while (nc < need) nc *= 2;
+  auto regrow_i = [&](int *&p) {
+    int *q = h.mem.alloc_n<int>(nc);
+    if (p) SMASH_HIP(hipMemcpyAsync(q, p, sizeof(int) * cap, hipMemcpyDeviceToDevice, h.stream));
+    p = q;
+  };
+  auto regrow_d = [&](double *&p) {
+    double *q = h.mem.alloc_n<double>(3 * (size_t)nc);
+    if (p)
+      SMASH_HIP(hipMemcpyAsync(q, p, sizeof(double) * 3 * cap, hipMemcpyDeviceToDevice, h.stream));
+    p = q;
+  };
+  regrow_i(h.level);
+  regrow_i(h.parent);
+  regrow_i(h.first_child);
+  regrow_i(h.nchild);
+  regrow_i(h.xb);
+  regrow_i(h.xe);
+  regrow_i(h.yb);
+  regrow_i(h.ye);
+  regrow_d(h.lo);
+  regrow_d(h.hi);
+  cap = nc;
+}
+
+template <class T>
+static T readback(Handle &h, const T *dev) {
+  T v;
+  SMASH_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, h.stream));
+  SMASH_HIP(hipStreamSynchronize(h.stream));
+  return v;
+}
+
+void build_tree(Handle &h, const double *x, const double *y) {
+  hipStream_t s = h.stream;
+  DeviceArena tmp;
+  tmp.stream = s;
+  try {
+    Geom g;
+    g.d = h.d;
+    g.hss = h.adm == SMASH_ADM_WEAK;
+    g.bpl = h.bpl;
+    g.max_split = h.max_split;
+    for (int t = 0; t < 3; t++) {
+      g.lo[t] = h.root_lo[t];
+      g.hi[t] = h.root_hi[t];
+    }
+    // validate the points (and compute the bounding cube if no root box)
+    int *bad = tmp.alloc_n<int>(2);
+    SMASH_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
+    k_check_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, h.nx, h.d, g, 0, bad);
+    SMASH_CHECK_LAUNCH();
+    if (!h.same_xy) {
+      k_check_points<<<ceil_div(h.ny, 256), 256, 0, s>>>(y, h.ny, h.d, g, 0, bad);
+      SMASH_CHECK_LAUNCH();
+    }
+    int hb[2];
+    SMASH_HIP(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+    SMASH_HIP(hipStreamSynchronize(s));
+    if (hb[0]) throw Error{SMASH_E_NUMERIC, "non-finite point coordinate"};
+    tmp.release();
+    if (!h.has_root) {
+      // bounding cube of X and Y: lo = min, side = largest extent
+      double *mm = tmp.alloc_n<double>(12);
+      k_minmax<<<1, 256, 0, s>>>(x, h.nx, h.d, mm);
+      SMASH_CHECK_LAUNCH();
+      k_minmax<<<1, 256, 0, s>>>(y, h.ny, h.d, mm + 6);
+      SMASH_CHECK_LAUNCH();
+      double hm[12];
+      SMASH_HIP(hipMemcpyAsync(hm, mm, sizeof(hm), hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipStreamSynchronize(s));
+      double side = 0.0;
+      for (int t = 0; t < h.d; t++) {
+        double mn = hm[2 * t] < hm[6 + 2 * t] ? hm[2 * t] : hm[6 + 2 * t];
+        double mx = hm[2 * t + 1] > hm[6 + 2 * t + 1] ? hm[2 * t + 1] : hm[6 + 2 * t + 1];
+        h.root_lo[t] = mn;
+        if (mx - mn > side) side = mx - mn;
+      }
+      for (int t = 0; t < h.d; t++) h.root_hi[t] = h.root_lo[t] + side;
+      for (int t = 0; t < 3; t++) {
+        g.lo[t] = h.root_lo[t];
+        g.hi[t] = h.root_hi[t];
+      }
+    } else {
+      SMASH_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
+      k_check_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, h.nx, h.d, g, 1, bad);
+      SMASH_CHECK_LAUNCH();
+      if (!h.same_xy) {
+        k_check_points<<<ceil_div(h.ny, 256), 256, 0, s>>>(y, h.ny, h.d, g, 1, bad);
+        SMASH_CHECK_LAUNCH();
+      }
+      SMASH_HIP(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipStreamSynchronize(s));
+      if (hb[1]) throw Error{SMASH_E_INVALID_ARG, "a point lies outside the root box"};
+    }
+
+    // keys and stable sort (X, then Y unless Y is X)
+    int keybits = g.max_split * g.bpl;
+    auto sort_side = [&](const double *pts, int64_t n, uint64_t *&keys_out, int *&perm,
+                         double *&P) {
+      uint64_t *k1 = tmp.alloc_n<uint64_t>(n), *k2 = tmp.alloc_n<uint64_t>(n);
+      int32_t *v2 = tmp.alloc_n<int32_t>(n);
+      perm = h.mem.alloc_n<int>(n);
+      k_keys<<<ceil_div(n, 256), 256, 0, s>>>(pts, n, g, k1, perm);
+      SMASH_CHECK_LAUNCH();
+      radix_sort_u64(k1, perm, k2, v2, n, keybits, s, tmp);
+      P = h.mem.alloc_n<double>((size_t)n * h.d);
+      k_gather_points<<<ceil_div(n, 256), 256, 0, s>>>(pts, perm, n, h.d, P);
+      SMASH_CHECK_LAUNCH();
+      keys_out = k1;
+    };
+    uint64_t *kx = nullptr, *ky = nullptr;
+    sort_side(x, h.nx, kx, h.perm_x, h.Xp);
+    if (h.same_xy) {
+      ky = kx;
+      h.perm_y = h.perm_x;
+      h.Yp = h.Xp;
+    } else {
+      sort_side(y, h.ny, ky, h.perm_y, h.Yp);
+    }
+
+    // nodes, level by level
+    int cap = 0;
+    grow_nodes(h, cap, 1024);
+    NodeArrays N;
+    auto refresh = [&]() {
+      N = NodeArrays{h.level, h.parent, h.first_child, h.nchild, h.xb, h.xe, h.yb, h.ye,
+                     h.lo, h.hi};
+    };
+    refresh();
+    k_root<<<1, 1, 0, s>>>(N, (int)h.nx, (int)h.ny, g);
+    SMASH_CHECK_LAUNCH();
+    h.level_beg.assign(1, 0);
+    int nb = 0, ne = 1, lev = 1;
+    for (;;) {
+      h.level_beg.push_back(ne);
+      int cnt_n = ne - nb;
+      int64_t *cnt = tmp.alloc_n<int64_t>(cnt_n);
+      int64_t *off = tmp.alloc_n<int64_t>(cnt_n + 1);
+      int64_t *base = tmp.alloc_n<int64_t>(1);
+      int64_t hbase = ne;
+      SMASH_HIP(hipMemcpyAsync(base, &hbase, sizeof(int64_t), hipMemcpyHostToDevice, s));
+      k_tree_split<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
+                                                        cnt);
+      SMASH_CHECK_LAUNCH();
+      scan_i64(cnt, off, cnt_n, base, s, tmp);
+      int64_t total = readback(h, off + cnt_n) - ne;
+      if (total > 0) {
+        if (ne + total > (int64_t)INT32_MAX) throw Error{SMASH_E_UNSUPPORTED, "too many nodes"};
+        grow_nodes(h, cap, (int)(ne + total));
+        refresh();
+      }
+      k_tree_emit<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
+                                                       off);
+      SMASH_CHECK_LAUNCH();
+      if (total == 0) break;
+      nb = ne;
+      ne = (int)(ne + total);
+      lev++;
+    }
+    h.nlevels = lev;
+    h.nnodes = ne;
+    SMASH_HIP(hipStreamSynchronize(s));
+    tmp.release();
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    tmp.release();
+    throw;
+  }
+}
+
+}  // namespace smash

@@ -1,0 +1,71 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad arguments before touching any device."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1705_05443_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "smash.h")).read()
+    return sorted(set(re.findall(r"\b(smash_[a-z_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(api.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = api.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    L = api.lib()
+    opt = api.Options()
+    assert L.smash_default_options(C.byref(opt)) == 0
+    assert opt.struct_size == C.sizeof(api.Options)
+    h = C.c_void_p()
+    dummy = C.c_void_p(16)  # never dereferenced: validation fails first
+    # dim out of range
+    assert L.smash_build(dummy, 10, 4, 0, 8, 4, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    # 1/(x-y) needs dim 1
+    assert L.smash_build(dummy, 10, 2, 3, 8, 4, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -2
+    # order out of range, leaf < 1, bad admissibility, bad tol
+    assert L.smash_build(dummy, 10, 2, 0, 8, 0, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    assert L.smash_build(dummy, 10, 2, 0, 0, 4, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    assert L.smash_build(dummy, 10, 2, 0, 8, 4, 7, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, -1.0, C.byref(opt), None, C.byref(h)) == -1
+    # NULL points, n < 1
+    assert L.smash_build(None, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    assert L.smash_build(dummy, 0, 2, 0, 8, 4, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    # options: wrong struct size, tau outside (0,1), f <= 1, unknown precision
+    bad = api.Options()
+    L.smash_default_options(C.byref(bad))
+    bad.struct_size = 3
+    assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(bad), None, C.byref(h)) == -1
+    for field, val in (("tau", 1.5), ("srrqr_f", 1.0), ("apply_prec", 9), ("eval_prec", 9)):
+        L.smash_default_options(C.byref(bad))
+        setattr(bad, field, val)
+        assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(bad), None, C.byref(h)) == -1
+    assert h.value is None
+    assert b"tau" in L.smash_last_error() or len(L.smash_last_error()) > 0
+    # NULL handle everywhere
+    assert L.smash_matvec(None, dummy, 1, 1, 0, dummy, 1, None) == -1
+    info = api.Info()
+    assert L.smash_info(None, C.byref(info)) == -1
+    n = C.c_int64(0)
+    assert L.smash_export(None, 1, None, C.byref(n)) == -1
+    assert L.smash_destroy(None) == 0
+
+
+def test_binding_refuses_cpu_tensors():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(TypeError):
+        api.Smash(torch.zeros(4, 2, dtype=torch.float64))

@@ -1,0 +1,242 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
+
+Integer outputs (permutation, tree, pair lists, near sets, ranks, skeleton
+sets) must be bit-exact.  FP64 construction: interpolative-decomposition
+coefficients G within 1e-9 of the oracle's (relative to max(1, |G|) per node,
+see below) and products within 1e-10 relative Frobenius.  FP32 apply: within
+1e-5 relative Frobenius of the oracle's FP64 product on the FP32-rounded
+right-hand sides.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O  # noqa: E402
+from paper_1705_05443_amd import api  # noqa: E402
+from paper_1705_05443_amd import workloads as W  # noqa: E402
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = {
+    # name: (points(), kwargs)
+    "hss1d_small": (lambda: (W.uniform(700, 1, 3), None),
+                    dict(kernel="inv_r", leaf=16, order=8, adm="weak", tol=1e-9, eps_svd=1e-9,
+                         tau=0.6, root=((0.0,), 1.0))),
+    "hss1d_cfg": (lambda: W.points(W.CONFIGS["hss1d_inv_r_2048"]),
+                  dict(kernel="inv_r", leaf=32, order=10, adm="weak", tol=1e-10, eps_svd=1e-10,
+                       tau=0.6, root=((0.0,), 1.0))),
+    "h2_2d_log": (lambda: (W.uniform(5000, 2, 5), None),
+                  dict(kernel="log_r", leaf=64, order=8, adm="strong", tol=1e-8, tau=0.7,
+                       root=((0.0, 0.0), 1.0))),
+    "h2_3d_clusters": (lambda: (W.clusters(6000, 3, 6), None),
+                       dict(kernel="inv_r", leaf=128, order=5, adm="strong", tol=1e-6, tau=0.7,
+                            root=((0.0, 0.0, 0.0), 1.0))),
+    "h2_1d_exp": (lambda: (W.uniform(3000, 1, 8), None),
+                  dict(kernel="exp_r", leaf=40, order=9, adm="strong", tol=1e-10, tau=0.6)),
+    "hss_cauchy_xy": (lambda: W.chebyshev_pair(3000, 4),
+                      dict(kernel="cauchy", leaf=64, order=16, adm="weak", tol=1e-8,
+                           eps_svd=1e-9, tau=0.6)),
+}
+
+
+def _oracle_kwargs(kw):
+    ok = dict(kw)
+    ok["adm"] = api.ADM[kw["adm"]]
+    return ok
+
+
+_cache = {}
+
+
+def pair_for(name):
+    if name not in _cache:
+        mk, kw = CASES[name]
+        x, y = mk()
+        o = O.Oracle(x, y, **_oracle_kwargs(kw))
+        g = api.Smash(dev(x), None if y is None else dev(y), **kw)
+        _cache[name] = (x, y, o, g)
+    return _cache[name]
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tree_and_lists_bit_exact(name):
+    x, y, o, g = pair_for(name)
+    print("case", name, flush=True)
+    assert np.array_equal(o.export(O.EX_SIZES), g.export("sizes"))
+    assert np.array_equal(o.export(O.EX_LEVELS), g.export("levels"))
+    assert np.array_equal(o.export(O.EX_PERM_X), g.export("perm_x"))
+    assert np.array_equal(o.export(O.EX_PERM_Y), g.export("perm_y"))
+    assert np.array_equal(o.nodes(), g.export("nodes").reshape(-1, 8))
+    assert np.array_equal(o.boxes(), g.export("boxes").reshape(-1, 6))
+    assert np.array_equal(o.L(), g.export("L").reshape(-1, 2))
+    assert np.array_equal(o.Lm(), g.export("Lm").reshape(-1, 2))
+    if CASES[name][1]["adm"] == "weak":
+        assert np.array_equal(o.export(O.EX_NEAR_PTR), g.export("near_ptr"))
+        assert np.array_equal(o.export(O.EX_NEAR_IDX), g.export("near_idx"))
+
+
+def _split(arr, sizes):
+    out, o = [], 0
+    for s in sizes:
+        out.append(arr[o:o + s])
+        o += s
+    return out
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_ranks_skeletons_and_G(name):
+    x, y, o, g = pair_for(name)
+    print("case", name, flush=True)
+    ro, rg = o.ranks(), g.export("ranks").reshape(-1, 6)
+    sides = [("row", 0, O.EX_ROW_SEL, O.EX_ROW_G, O.EX_ROW_GRID)]
+    if not (y is None and CASES[name][1]["kernel"] != "cauchy"):
+        sides.append(("col", 2, O.EX_COL_SEL, O.EX_COL_G, O.EX_COL_GRID))
+    for side, c, exs, exg, exgrid in sides:
+        m_o, k_o = ro[1:, c], ro[1:, c + 1]
+        m_g, k_g = rg[1:, c], rg[1:, c + 1]
+        # grids and ranks follow from the skeleton choices below them
+        bad = np.nonzero((m_o != m_g) | (k_o != k_g))[0]
+        assert bad.size == 0, (side, "first differing node", 1 + bad[:5])
+        if CASES[name][1]["adm"] == "weak":
+            assert np.array_equal(ro[1:, 4 + c // 2], rg[1:, 4 + c // 2]), "SVD ranks"
+        sel_o, sel_g = o.export(exs), g.export(side + "_sel")
+        assert np.array_equal(o.export(exgrid), g.export(side + "_grid"))
+        assert np.array_equal(sel_o, sel_g), side
+        Go = _split(o.export(exg), (m_o - k_o) * k_o)
+        Gg = _split(g.export(side + "_G"), (m_g - k_g) * k_g)
+        worst = 0.0
+        for a, b in zip(Go, Gg):
+            if a.size:
+                worst = max(worst, float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a)))))
+        assert worst < 1e-9, (side, worst)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_coupling_blocks_are_kernel_entries(name):
+    """B_ij = A(X at i-hat, Y at j-hat) over L, stored column-major."""
+    x, y, o, g = pair_for(name)
+    yy = x if y is None else y
+    kw = CASES[name][1]
+    L = g.export("L").reshape(-1, 2)
+    B = g.export("coupling")
+    rk = g.export("ranks").reshape(-1, 6)
+    px, py = g.export("perm_x"), g.export("perm_y")
+    per_r = O.Oracle.per_node(o, "row")
+    reuse = y is None and kw["kernel"] != "cauchy"
+    per_c = per_r if reuse else O.Oracle.per_node(o, "col")
+    off = 0
+    rng = np.random.default_rng(0)
+    pick = set(rng.choice(len(L), size=min(len(L), 200), replace=False).tolist())
+    for e, (i, j) in enumerate(L):
+        ki, kj = rk[i, 1], rk[j, 3]
+        if e in pick:
+            gi, si, _ = per_r[i]
+            gj, sj, _ = per_c[j]
+            rows = x[px[gi[si[:ki]]]]
+            cols = yy[py[gj[sj[:kj]]]]
+            ref = O.kernel_block(rows, cols, kw["kernel"])
+            blk = B[off:off + ki * kj].reshape(kj, ki).T
+            assert np.max(np.abs(blk - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
+        off += ki * kj
+    assert off == B.size
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("nrhs", [1, 3, 16, 70])
+def test_matvec_fp64_parity(name, nrhs):
+    x, y, o, g = pair_for(name)
+    print("case", name, nrhs, flush=True)
+    q = W.rhs(g.ny, nrhs, seed=nrhs)
+    z_o = o.matvec(q)
+    z_g = g.matvec(dev(q)).cpu().numpy()
+    assert relerr(z_g, z_o) < 1e-10
+
+
+def test_matvec_strided_input_and_vector():
+    x, y, o, g = pair_for("h2_2d_log")
+    q = W.rhs(g.ny, 24, seed=7)
+    Q = dev(q)
+    z = g.matvec(Q[:, 4:20])  # leading dimension 24 > nrhs
+    assert relerr(z.cpu().numpy(), o.matvec(q[:, 4:20])) < 1e-10
+    zv = g.matvec(Q[:, 5].contiguous())
+    assert relerr(zv.cpu().numpy(), o.matvec(q[:, 5])) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["h2_2d_log", "hss1d_small", "h2_3d_clusters"])
+def test_plain_per_node_form_equals_batched(name):
+    x, y, o, g = pair_for(name)
+    kw = dict(CASES[name][1])
+    gp = api.Smash(dev(x), None if y is None else dev(y), batched=False, **kw)
+    for what in ("perm_x", "nodes", "L", "Lm", "ranks", "row_sel"):
+        assert np.array_equal(gp.export(what), g.export(what))
+    assert np.array_equal(gp.export("row_G"), g.export("row_G"))
+    q = dev(W.rhs(g.ny, 5, seed=2))
+    assert torch.equal(gp.matvec(q), g.matvec(q))
+
+
+@pytest.mark.parametrize("name", ["h2_2d_log", "h2_3d_clusters", "hss_cauchy_xy"])
+def test_matvec_fp32_apply(name):
+    mk, kw = CASES[name]
+    x, y = mk()
+    o = O.Oracle(x, y, **_oracle_kwargs(kw))
+    g = api.Smash(dev(x), None if y is None else dev(y), apply_prec="f32", **kw)
+    for nrhs in (1, 16, 64):
+        q32 = W.rhs(g.ny, nrhs, seed=3).astype(np.float32)
+        z_o = o.matvec(q32.astype(np.float64))
+        z_g = g.matvec(torch.from_numpy(q32).cuda()).cpu().numpy().astype(np.float64)
+        assert relerr(z_g, z_o) < 1e-5, nrhs
+
+
+def test_full_size_h2_2d_log_65536():
+    """The benchmark workload at full size: bit-exact tree/lists/skeletons,
+    FP64 product within 1e-10 of the oracle, and within the tolerance of
+    exact rows of A Q."""
+    cfg = W.CONFIGS["h2_2d_log_65536"]
+    x, _ = W.points(cfg)
+    kw = dict(kernel="log_r", leaf=64, order=8, adm="strong", tol=1e-8, tau=0.7,
+              root=((0.0, 0.0), 1.0))
+    o = O.Oracle(x, **_oracle_kwargs(kw))
+    g = api.Smash(dev(x), **kw)
+    for what, ex in (("perm_x", O.EX_PERM_X), ("levels", O.EX_LEVELS), ("L", O.EX_L),
+                     ("Lm", O.EX_LM), ("row_sel", O.EX_ROW_SEL)):
+        assert np.array_equal(o.export(ex), g.export(what)), what
+    q = W.rhs(cfg["n"], cfg["nrhs"])
+    z_o = o.matvec(q)
+    z_g = g.matvec(dev(q)).cpu().numpy()
+    assert relerr(z_g, z_o) < 1e-10
+    rows = np.arange(0, cfg["n"], 257)
+    zr = O.dense_rows(x, x, rows, q, "log_r")
+    assert relerr(z_g[rows], zr) < 1e-6
+
+
+def test_single_leaf_and_tiny_inputs():
+    for n in (1, 2, 7, 64):
+        x = W.uniform(n, 2, n)
+        g = api.Smash(dev(x), kernel="inv_r", leaf=64, order=4, adm="strong", tol=1e-6,
+                      root=((0.0, 0.0), 1.0))
+        q = W.rhs(n, 2)
+        zd = O.dense_matvec(x, x, q, "inv_r")
+        assert relerr(g.matvec(dev(q)).cpu().numpy(), zd) < 1e-14
+
+
+def test_errors_from_device_checks():
+    x = W.uniform(100, 2, 0) * 2.0
+    with pytest.raises(api.SmashError) as e:
+        api.Smash(dev(x), kernel="inv_r", leaf=8, order=4, adm="strong", tol=1e-6,
+                  root=((0.0, 0.0), 1.0))
+    assert e.value.code == -1
+    x = W.uniform(100, 2, 0)
+    x[5, 1] = np.nan
+    with pytest.raises(api.SmashError) as e:
+        api.Smash(dev(x), kernel="inv_r", leaf=8, order=4, adm="strong", tol=1e-6)
+    assert e.value.code == -5
