@@ -69,6 +69,8 @@ typedef struct smash_handle_s *smash_handle;
  *   max_depth    > 0 caps the number of tree levels (root = level 1)
  *   batched      1: all nodes of a level in one launch per phase (default);
  *                0: one launch per node (the plain per-node form)
+ *   timing       1: bracket every phase's launches with HIP events on the
+ *                stream they run on; smash_info reports the summed times
  */
 typedef struct smash_options {
   uint32_t struct_size; /* sizeof(smash_options) */
@@ -83,6 +85,7 @@ typedef struct smash_options {
   double root_side;
   int32_t max_depth;
   int32_t batched;
+  int32_t timing;
 } smash_options;
 
 int smash_default_options(smash_options *opt);
@@ -134,7 +137,23 @@ typedef struct smash_info_t {
   int32_t apply_prec, eval_prec;
   int32_t symmetric_reuse;  /* column side taken from the row side */
   double build_ms;          /* wall time of the last build on its stream */
+  /* with options.timing: device time (ms) and launch groups per phase,
+   * summed over the build and every product so far (SMASH_PHASE_*) */
+  double phase_ms[16];
+  int64_t phase_calls[16];
 } smash_info_t;
+
+#define SMASH_PHASE_TREE 0
+#define SMASH_PHASE_PAIRS 1
+#define SMASH_PHASE_NEAR_SVD 2
+#define SMASH_PHASE_COMPR 3
+#define SMASH_PHASE_SLOTS 4
+#define SMASH_PHASE_BLOCKS 5
+#define SMASH_PHASE_MV_GATHER 6
+#define SMASH_PHASE_MV_UP 7
+#define SMASH_PHASE_MV_COUPLING 8
+#define SMASH_PHASE_MV_DOWN 9
+#define SMASH_PHASE_MV_NEAR_OUT 10
 
 int smash_info(smash_handle h, smash_info_t *info);
 

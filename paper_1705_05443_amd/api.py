@@ -36,7 +36,7 @@ class Options(C.Structure):
                 ("srrqr_f", C.c_double), ("diag_value", C.c_double), ("eval_prec", C.c_int32),
                 ("apply_prec", C.c_int32), ("has_root_box", C.c_int32),
                 ("root_lo", C.c_double * 3), ("root_side", C.c_double), ("max_depth", C.c_int32),
-                ("batched", C.c_int32)]
+                ("batched", C.c_int32), ("timing", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -49,7 +49,11 @@ class Info(C.Structure):
                 ("g_entries_col", C.c_int64), ("index_entries", C.c_int64),
                 ("device_bytes", C.c_int64), ("total_swaps", C.c_int64),
                 ("apply_prec", C.c_int32), ("eval_prec", C.c_int32),
-                ("symmetric_reuse", C.c_int32), ("build_ms", C.c_double)]
+                ("symmetric_reuse", C.c_int32), ("build_ms", C.c_double),
+                ("phase_ms", C.c_double * 16), ("phase_calls", C.c_int64 * 16)]
+
+PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", "mv_up",
+          "mv_coupling", "mv_down", "mv_near_out"]
 
 
 _lib = None
@@ -100,7 +104,7 @@ class Smash:
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
-                 root=None, max_depth=0, batched=True, stream=None):
+                 root=None, max_depth=0, batched=True, timing=False, stream=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -129,6 +133,7 @@ class Smash:
             opt.root_side = float(root[1])
         opt.max_depth = max_depth
         opt.batched = 1 if batched else 0
+        opt.timing = 1 if timing else 0
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
         self.ny = x.shape[0] if y is None else y.shape[0]
@@ -169,7 +174,10 @@ class Smash:
     def info(self):
         inf = Info()
         _check(lib().smash_info(self._h, C.byref(inf)))
-        return {k: getattr(inf, k) for k, _ in Info._fields_}
+        out = {k: getattr(inf, k) for k, _ in Info._fields_ if k not in ("phase_ms", "phase_calls")}
+        out["phase_ms"] = {n: inf.phase_ms[i] for i, n in enumerate(PHASES)}
+        out["phase_calls"] = {n: inf.phase_calls[i] for i, n in enumerate(PHASES)}
+        return out
 
     def export(self, what):
         n = C.c_int64(0)

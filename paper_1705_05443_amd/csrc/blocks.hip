@@ -115,6 +115,7 @@ void build_blocks(Handle &h) {
     SMASH_HIP(hipStreamSynchronize(s));
     h.B = h.mem.alloc(es * (size_t)(h.b_entries > 0 ? h.b_entries : 1));
     h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
+    PhaseTimer pt(h, SMASH_PHASE_BLOCKS, s);
     EvalArgs ea{};
     ea.d = h.d;
     ea.kid = h.kid;

@@ -798,6 +798,7 @@ void build_generators(Handle &h) {
           SvdArgs sa{nb, ne, S.m, S.gbeg, S.slot_id, sc.P, O.m, O.gbeg, O.slot_id, ot.P, h.Nrow,
                      h.Ncol, sc.rowside ? 1 : 0, h.kid, h.d, h.diag, h.eps_svd, scr, ldn,
                      wg_stride, sc.Svec, soff, S.ks};
+          PhaseTimer pt(h, SMASH_PHASE_NEAR_SVD, s);
           if (h.batched) {
             k_near_svd<<<nwg, SV_NT, 0, s>>>(sa);
             SMASH_CHECK_LAUNCH();
@@ -827,6 +828,7 @@ void build_generators(Handle &h) {
         IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo, S.go,
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1};
+        PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
         if (h.batched) {
           k_compr<<<nwg, ID_NT, 0, s>>>(ia);
           SMASH_CHECK_LAUNCH();
@@ -855,8 +857,12 @@ void build_generators(Handle &h) {
         SMASH_HIP(hipMemcpyAsync(&end, ok + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipStreamSynchronize(s));
         grow_slots(h, S, end);
-        k_slot_ids<<<nl, 64, 0, s>>>(nb, ne, S.k, S.hbeg, S.gbeg, S.selo, S.lv[l].sel, S.slot_id);
-        SMASH_CHECK_LAUNCH();
+        {
+          PhaseTimer pt(h, SMASH_PHASE_SLOTS, s);
+          k_slot_ids<<<nl, 64, 0, s>>>(nb, ne, S.k, S.hbeg, S.gbeg, S.selo, S.lv[l].sel,
+                                       S.slot_id);
+          SMASH_CHECK_LAUNCH();
+        }
         S.nslots = end;
       }
       int herr[2];

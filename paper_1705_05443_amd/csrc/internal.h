@@ -132,7 +132,39 @@ struct Handle {
   int ws_nrhs = 0;
   void *qbuf = nullptr, *zbuf = nullptr;
   DeviceArena ws_mem;
+  // phase timing (options.timing)
+  bool timing = false;
+  struct TimedEvent {
+    int phase;
+    hipEvent_t a, b;
+  };
+  std::vector<TimedEvent> tev;
+  double phase_ms[16] = {0};
+  int64_t phase_calls[16] = {0};
 };
+
+// Records a HIP event pair around the launches issued during its lifetime
+// on stream s (only when the handle's timing option is on).
+struct PhaseTimer {
+  Handle &h;
+  int ph;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseTimer(Handle &h_, int ph_, hipStream_t s_) : h(h_), ph(ph_), s(s_) {
+    if (h.timing && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, s);
+  }
+  ~PhaseTimer() {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) == hipSuccess) {
+      (void)hipEventRecord(b, s);
+      h.tev.push_back({ph, a, b});
+    } else {
+      (void)hipEventDestroy(a);
+    }
+  }
+};
+void resolve_timers(Handle &h);
 
 // ---------------------------------------------------------------- stages
 void build_tree(Handle &h, const double *x, const double *y);

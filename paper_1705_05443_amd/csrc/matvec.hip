@@ -165,9 +165,15 @@ static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t
   const bool f64 = h.apply_prec == SMASH_F64;
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int R = nrhs - c0 < chunk ? nrhs - c0 : chunk;
-    k_mv_gather<T><<<ceil_div(h.ny * R, MV_NT), MV_NT, 0, s>>>(X + c0, ldx, h.perm_y, h.ny, R, q);
-    SMASH_CHECK_LAUNCH();
+    {
+      PhaseTimer pt(h, SMASH_PHASE_MV_GATHER, s);
+      k_mv_gather<T><<<ceil_div(h.ny * R, MV_NT), MV_NT, 0, s>>>(X + c0, ldx, h.perm_y, h.ny, R,
+                                                                  q);
+      SMASH_CHECK_LAUNCH();
+    }
     const bool has_far = h.nlevels >= 2;
+    {
+    PhaseTimer pt(h, SMASH_PHASE_MV_UP, s);
     for (int l = h.nlevels; l >= 2; l--) {
       int nb = h.level_beg[l - 1], ne = h.level_beg[l];
       const LevelSide &L = Cl.lv[l];
@@ -185,10 +191,15 @@ static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t
         }
       }
     }
+    }
     if (has_far) {
       CouplingArgs ca{h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
-      k_mv_coupling<T><<<h.nnodes - 1, MV_NT, 0, s>>>(ca, q, z, R);
-      SMASH_CHECK_LAUNCH();
+      {
+        PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
+        k_mv_coupling<T><<<h.nnodes - 1, MV_NT, 0, s>>>(ca, q, z, R);
+        SMASH_CHECK_LAUNCH();
+      }
+      PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
       for (int l = 2; l <= h.nlevels; l++) {
         int nb = h.level_beg[l - 1], ne = h.level_beg[l];
         const LevelSide &L = Rw.lv[l];
@@ -209,8 +220,11 @@ static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t
     }
     NearArgs na{h.nnodes, h.nchild, h.xb, h.xe, h.yb, h.ye, h.perm_x, h.Lmrow, h.Lmj, h.nboff,
                 h.Bn, has_far ? 1 : 0};
-    k_mv_near_out<T><<<h.nnodes, MV_NT, 0, s>>>(na, q, z, Y + c0, ldy, R);
-    SMASH_CHECK_LAUNCH();
+    {
+      PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
+      k_mv_near_out<T><<<h.nnodes, MV_NT, 0, s>>>(na, q, z, Y + c0, ldy, R);
+      SMASH_CHECK_LAUNCH();
+    }
   }
 }
 

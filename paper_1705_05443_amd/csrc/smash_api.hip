@@ -32,11 +32,28 @@ extern "C" int smash_default_options(smash_options *opt) {
   opt->root_side = 0.0;
   opt->max_depth = 0;
   opt->batched = 1;
+  opt->timing = 0;
   return SMASH_OK;
 }
 
+namespace smash {
+void resolve_timers(Handle &h) {
+  for (auto &e : h.tev) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(e.b) == hipSuccess && hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      h.phase_ms[e.phase] += ms;
+      h.phase_calls[e.phase] += 1;
+    }
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  h.tev.clear();
+}
+}  // namespace smash
+
 static void free_handle(Handle *h) {
   if (!h) return;
+  resolve_timers(*h);
   (void)hipStreamSynchronize(h->stream);
   h->ws_mem.release();
   h->mem.release();
@@ -111,6 +128,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->eval_prec = opt.eval_prec;
     h->apply_prec = opt.apply_prec;
     h->batched = opt.batched ? 1 : 0;
+    h->timing = opt.timing != 0;
     h->nx = nx;
     h->ny = ny;
     h->same_xy = same;
@@ -124,8 +142,14 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
         h->root_lo[t] = opt.root_lo[t];
         h->root_hi[t] = opt.root_lo[t] + opt.root_side;
       }
-    build_tree(*h, x, same ? x : y);
-    build_pairs(*h);
+    {
+      PhaseTimer pt(*h, SMASH_PHASE_TREE, h->stream);
+      build_tree(*h, x, same ? x : y);
+    }
+    {
+      PhaseTimer pt(*h, SMASH_PHASE_PAIRS, h->stream);
+      build_pairs(*h);
+    }
     build_generators(*h);
     build_blocks(*h);
     // leaf count and statistics
@@ -212,6 +236,11 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
     info->build_ms = h->build_ms;
     info->total_swaps = h->total_swaps;
     info->device_bytes = h->mem.bytes + h->ws_mem.bytes;
+    resolve_timers(*h);
+    for (int q = 0; q < 16; q++) {
+      info->phase_ms[q] = h->phase_ms[q];
+      info->phase_calls[q] = h->phase_calls[q];
+    }
     auto side_stats = [&](Side &S, int64_t &sumk, int32_t &maxk, int64_t &gent) {
       auto m = to_host(S.m, h->nnodes), k = to_host(S.k, h->nnodes);
       sumk = 0;

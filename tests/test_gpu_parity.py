@@ -1,9 +1,10 @@
 """GPU parity: the HIP library against the FP64 CPU oracle, through the C ABI.
 
 Integer outputs (permutation, tree, pair lists, near sets, ranks, skeleton
-sets) must be bit-exact.  FP64 construction: interpolative-decomposition
-coefficients G within 1e-9 of the oracle's (relative to max(1, |G|) per node,
-see below) and products within 1e-10 relative Frobenius.  FP32 apply: within
+sets) must be bit-exact.  FP64 construction: H^2 interpolative-decomposition
+coefficients G within 1e-9 of the oracle's (relative to max(1, |G|) per node;
+HSS G by the properties in _check_hss_ids) and products within 1e-10
+relative Frobenius.  FP32 apply: within
 1e-5 relative Frobenius of the oracle's FP64 product on the FP32-rounded
 right-hand sides.
 """
@@ -114,11 +115,44 @@ def test_ranks_skeletons_and_G(name):
         assert np.array_equal(sel_o, sel_g), side
         Go = _split(o.export(exg), (m_o - k_o) * k_o)
         Gg = _split(g.export(side + "_G"), (m_g - k_g) * k_g)
-        worst = 0.0
-        for a, b in zip(Go, Gg):
-            if a.size:
-                worst = max(worst, float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a)))))
-        assert worst < 1e-9, (side, worst)
+        if CASES[name][1]["adm"] == "strong":
+            worst = 0.0
+            for a, b in zip(Go, Gg):
+                if a.size:
+                    worst = max(worst, float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a)))))
+            assert worst < 1e-9, (side, worst)
+        else:
+            _check_hss_ids(x, y, g, side, m_o, k_o, sel_o, Go, Gg, CASES[name][1]["order"])
+
+
+def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order):
+    """HSS: C = [U-hat, S] contains near-field singular vectors whose trailing
+    members (sigma near eps_svd * sigma_1) are fixed only to about
+    eps_mach / eps_svd, so two correct implementations agree on the skeleton
+    sets (checked above) but not on G to 1e-9.  Checked instead: the
+    Gu-Eisenstat bound |G| <= f, and that G reproduces the far-field basis
+    U-hat on the node's grid as well as the oracle's G does (ID residual,
+    eq. (2.11)).  The product itself is held to 1e-10 elsewhere."""
+    P = x if side == "row" else (x if y is None else y)
+    perm = g.export("perm_x" if side == "row" else "perm_y")
+    grid = _split(g.export(side + "_grid"), m)
+    sels = _split(sel, m)
+    bx = g.export("boxes").reshape(-1, 6)
+    for i in range(len(m)):
+        kk, mm = int(k[i]), int(m[i])
+        if kk == 0 or kk == mm:
+            continue
+        node = i + 1
+        assert np.max(np.abs(Gg[i])) <= 2.0 * (1 + 1e-8)
+        pts = P[perm[grid[i]]]
+        U = O.interp_basis(pts, bx[node, :1], bx[node, 3:4], order)
+        sk, rs = sels[i][:kk], sels[i][kk:]
+        Gg_ = Gg[i].reshape(mm - kk, kk)
+        Go_ = Go[i].reshape(mm - kk, kk)
+        nrm = np.linalg.norm(U)
+        r_g = np.linalg.norm(U[rs] - Gg_ @ U[sk])
+        r_o = np.linalg.norm(U[rs] - Go_ @ U[sk])
+        assert r_g <= 10.0 * r_o + 1e-12 * nrm, (node, r_g, r_o)
 
 
 @pytest.mark.parametrize("name", list(CASES))
