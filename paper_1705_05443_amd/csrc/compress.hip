@@ -401,6 +401,324 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
 }
 
 // ------------------------------------------------------------------------
+// Register-resident compr: the same algorithm as k_compr for nodes whose
+// grid fits one workgroup (m <= NT) and whose basis width fits CMAX.  Lane a
+// holds grid column a of M = C^T in registers (col[r], r < CMAX, zero past
+// c).  A column's "position" (the order the pivoted QR works in) is a lane
+// label: a pivot swap relabels two lanes instead of moving data, so ties
+// still go to the lowest current position.  Householder vectors and R11 are
+// broadcast through LDS; every loop over rows is unrolled over CMAX with a
+// predicate, so no register is indexed dynamically.
+// ------------------------------------------------------------------------
+template <int CMAX>
+__device__ __forceinline__ void reg_basis(const IdArgs &A, int i, int a, int ks, int c,
+                                          double (&col)[CMAX], double *F, int NT,
+                                          const double *xi, const double *wk) {
+  const int d = A.d, p = A.p;
+  const int64_t id = A.slot_id[A.gbeg[i] + a];
+  for (int t = 0; t < d; t++) {
+    const double x = A.P[id * d + t];
+    const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+    double *Ft = F + (int64_t)(t * p) * NT + a;
+    if (hi - lo == 0.0) {
+      for (int q = 0; q < p; q++) Ft[q * NT] = q == 0 ? 1.0 : 0.0;
+      continue;
+    }
+    int hit = -1;
+    double den = 0.0;
+    for (int q = 0; q < p; q++) {
+      const double xq = xi[t * ID_PMAX + q];
+      if (x == xq) {
+        hit = q;
+        break;
+      }
+      const double v = wk[q] / (x - xq);
+      Ft[q * NT] = v;
+      den += v;
+    }
+    if (hit >= 0)
+      for (int q = 0; q < p; q++) Ft[q * NT] = q == hit ? 1.0 : 0.0;
+    else
+      for (int q = 0; q < p; q++) Ft[q * NT] = Ft[q * NT] / den;
+  }
+  // tensor product, column index k_1 p^{d-1} + ... + k_d (odometer digits)
+  int k0 = 0, k1 = 0, k2 = 0;
+  const double *S = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
+#pragma unroll
+  for (int r = 0; r < CMAX; r++) {
+    double v = 0.0;
+    if (r < A.c0) {
+      if (d == 1)
+        v = F[(int64_t)k2 * NT + a];
+      else if (d == 2)
+        v = F[(int64_t)(p + k2) * NT + a] * F[(int64_t)k1 * NT + a];
+      else
+        v = F[(int64_t)(2 * p + k2) * NT + a] * F[(int64_t)(p + k1) * NT + a] *
+            F[(int64_t)k0 * NT + a];
+      if (++k2 == p) {
+        k2 = 0;
+        if (++k1 == p) {
+          k1 = 0;
+          ++k0;
+        }
+      }
+    } else if (r < c) {
+      v = S[r - A.c0];
+    }
+    col[r] = v;
+  }
+}
+
+// One Householder step at position t.  The lane holding position t builds
+// v (rows t..c-1) into LDS and becomes column t of R; every lane at a later
+// position applies the reflector and (with `norms`) recomputes its residual
+// norm over rows t+1.., which is what the next pivot choice compares.
+// All row loops are unrolled with selects instead of branches, so the LDS
+// reads of v issue back to back.
+template <int CMAX>
+__device__ __forceinline__ void reg_householder(double (&col)[CMAX], bool act, int pos, int t,
+                                                double alpha, double *v, double *vn_lds,
+                                                double &nrm, bool norms) {
+  if (act && pos == t) {
+    double x0 = 0.0;
+#pragma unroll
+    for (int r = 0; r < CMAX; r++) x0 = r == t ? col[r] : x0;
+    const double rtt = x0 >= 0.0 ? -alpha : alpha;
+    const double v0 = x0 - rtt;
+    double rest = 0.0;
+#pragma unroll
+    for (int r = 0; r < CMAX; r++) {
+      const double y = r > t ? col[r] : 0.0;
+      v[r] = r == t ? v0 : y;
+      rest = fma(y, y, rest);
+      col[r] = r > t ? 0.0 : (r == t ? (alpha != 0.0 ? rtt : x0) : col[r]);
+    }
+    *vn_lds = alpha != 0.0 ? rest + v0 * v0 : 0.0;
+  }
+  __syncthreads();
+  const double vn = *vn_lds;
+  if (act && pos > t && vn > 0.0) {
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+    for (int r = 0; r < CMAX; r += 4) {
+      w0 = fma(r + 0 >= t ? v[r + 0] : 0.0, col[r + 0], w0);
+      w1 = fma(r + 1 >= t ? v[r + 1] : 0.0, col[r + 1], w1);
+      w2 = fma(r + 2 >= t ? v[r + 2] : 0.0, col[r + 2], w2);
+      w3 = fma(r + 3 >= t ? v[r + 3] : 0.0, col[r + 3], w3);
+    }
+    const double sc = 2.0 * ((w0 + w1) + (w2 + w3)) / vn;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int r = 0; r < CMAX; r++) {
+      const double y = fma(-sc, r >= t ? v[r] : 0.0, col[r]);
+      col[r] = y;
+      if (r & 1)
+        s1 = fma(r > t ? y : 0.0, y, s1);
+      else
+        s0 = fma(r > t ? y : 0.0, y, s0);
+    }
+    if (norms) nrm = sqrt(s0 + s1);
+  } else if (act && pos > t && norms) {
+    double s0 = 0.0;
+#pragma unroll
+    for (int r = 0; r < CMAX; r++) s0 = fma(r > t ? col[r] : 0.0, col[r], s0);
+    nrm = sqrt(s0);
+  }
+  __syncthreads();
+}
+
+template <int CMAX, int NT>
+__global__ void __launch_bounds__(NT) k_compr_reg(IdArgs A) {
+  extern __shared__ double smem[];
+  __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
+  __shared__ double v[CMAX], rinv[CMAX];
+  __shared__ double vn_lds;
+  __shared__ ArgMax ared[NT / WAVE + 1];
+  __shared__ int64_t sred[NT / WAVE + 1];
+  __shared__ int skr_by_pos[CMAX];
+  double *F = smem;    // [t*p + q][NT] during the basis evaluation
+  double *R11 = smem;  // [r][q] (CMAX x CMAX) during the swap test
+  const int a = threadIdx.x;
+  const int p = A.p;
+  if (a < p) {
+    double th = M_PI * (2.0 * a + 1.0) / (2.0 * p);
+    chc[a] = cos(th);
+    wk[a] = ((a & 1) ? -1.0 : 1.0) * sin(th);
+  }
+  for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
+    const int m = A.m[i];
+    const int ks = A.S ? A.ks[i] : 0;
+    const int c = A.c0 + ks;
+    __syncthreads();
+    if (a < A.d * p) {
+      int t = a / p, q = a % p;
+      double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+      xi[t * ID_PMAX + q] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[q];
+    }
+    __syncthreads();
+    if (m == 0) {
+      if (a == 0) A.k_out[i] = 0;
+      continue;
+    }
+    const bool act = a < m;
+    int pos = a;
+    double col[CMAX];
+    double nrm = -1.0;
+    if (act) {
+      reg_basis<CMAX>(A, i, a, ks, c, col, F, NT, xi, wk);
+      double s2 = 0.0;
+#pragma unroll
+      for (int r = 0; r < CMAX; r++) s2 = fma(col[r], col[r], s2);
+      nrm = sqrt(s2);
+    } else {
+#pragma unroll
+      for (int r = 0; r < CMAX; r++) col[r] = 0.0;
+    }
+    // pivoted QR
+    const int kmax = m < c ? m : c;
+    int k = 0;
+    double r00 = 0.0;
+    for (int t = 0; t < kmax; t++) {
+      ArgMax am = (act && pos >= t) ? ArgMax{nrm, pos} : ArgMax{-1.0, -1};
+      am = block_argmax(am, ared);
+      const double bn = am.v;
+      if (t == 0) {
+        r00 = bn;
+        if (!(r00 > 0.0)) break;
+      } else if (!(bn > A.tol * r00)) {
+        break;
+      }
+      const int bp = am.a;
+      if (act) {
+        if (pos == t)
+          pos = bp;
+        else if (pos == bp)
+          pos = t;
+      }
+      reg_householder<CMAX>(col, act, pos, t, bn, v, &vn_lds, nrm, true);
+      k = t + 1;
+    }
+    // Gu-Eisenstat swaps
+    const int nr = m - k;
+    int nsw = 0;
+    bool failed = false;
+    if (k > 0 && nr > 0) {
+      for (;;) {
+        // R11 to LDS, column-major: R11[q*CMAX + r] = R[r][q]
+        if (act && pos < k) {
+#pragma unroll
+          for (int r = 0; r < CMAX; r++) R11[pos * CMAX + r] = r <= pos ? col[r] : 0.0;
+        }
+        __syncthreads();
+        double gam = 0.0;
+        if (act && pos >= k) {
+          // N = R11^{-1} R12 in place (column-oriented back substitution),
+          // gamma = |R22 column|
+          double g2 = 0.0;
+#pragma unroll
+          for (int r = 0; r < CMAX; r++) g2 = fma(r >= k ? col[r] : 0.0, col[r], g2);
+          gam = sqrt(g2);
+#pragma unroll
+          for (int q = CMAX - 1; q >= 0; q--) {
+            if (q < k) {
+              const double nq = col[q] / R11[q * CMAX + q];
+              col[q] = nq;
+#pragma unroll
+              for (int r = 0; r < q; r++) col[r] = fma(-R11[q * CMAX + r], nq, col[r]);
+            }
+          }
+        } else if (act && pos < k) {
+          // row pos of R11^{-1}: solve R11^T y = e_pos (y_q = 0 for q < pos)
+          const int ip = pos;
+          double s2 = 0.0;
+#pragma unroll
+          for (int q = 0; q < CMAX; q++) col[q] = 0.0;
+#pragma unroll
+          for (int q = 0; q < CMAX; q++) {
+            if (q < k && q >= ip) {
+              double a0 = q == ip ? 1.0 : 0.0, a1 = 0.0;
+#pragma unroll
+              for (int r = 0; r < q; r += 2) {
+                a0 = fma(-R11[q * CMAX + r], col[r], a0);
+                if (r + 1 < q) a1 = fma(-R11[q * CMAX + r + 1], col[r + 1], a1);
+              }
+              const double y = (a0 + a1) / R11[q * CMAX + q];
+              col[q] = y;
+              s2 = fma(y, y, s2);
+            }
+          }
+          rinv[ip] = sqrt(s2);
+        }
+        __syncthreads();
+        ArgMax am{-1.0, -1};
+        if (act && pos >= k) {
+          const int j = pos - k;
+#pragma unroll
+          for (int ii = 0; ii < CMAX; ii++)
+            if (ii < k) {
+              const double nv = col[ii], b = gam * rinv[ii];
+              am = amax_pick(am, ArgMax{sqrt(nv * nv + b * b), j * k + ii});
+            }
+        }
+        am = block_argmax(am, ared);
+        if (!(am.v > A.f)) break;
+        if (++nsw > 64 * k) {
+          failed = true;
+          break;
+        }
+        const int bj = am.a / k, bi = am.a % k;
+        if (act) {
+          if (pos == bi)
+            pos = k + bj;
+          else if (pos == k + bj)
+            pos = bi;
+        }
+        // refactor in the new column order without pivoting
+        __syncthreads();
+        if (act) reg_basis<CMAX>(A, i, a, ks, c, col, F, NT, xi, wk);
+        __syncthreads();
+        for (int t = 0; t < k; t++) {
+          double alpha = 0.0;
+          if (act && pos == t) {
+            double s2 = 0.0;
+#pragma unroll
+            for (int r = 0; r < CMAX; r++)
+              if (r >= t) s2 = fma(col[r], col[r], s2);
+            alpha = sqrt(s2);
+          }
+          reg_householder<CMAX>(col, act, pos, t, alpha, v, &vn_lds, nrm, false);
+        }
+      }
+    }
+    if (a == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+    if (failed) {
+      if (a == 0) atomicOr(A.err, 1);
+      k = 0;
+    }
+    // canonical output: skeleton positions ascending, then the rest
+    const bool sk = act && pos < k;
+    int64_t tot;
+    const int64_t skr = block_excl_scan_i64(sk ? 1 : 0, &tot, sred);
+    int *sel = A.sel_out + A.selo[i];
+    if (act) {
+      if (sk)
+        sel[skr] = a;
+      else
+        sel[k + (a - skr)] = a;
+    }
+    if (sk) skr_by_pos[pos] = (int)skr;
+    __syncthreads();
+    if (act && !sk && k > 0) {
+      double *G = A.G_out + A.go[i] + (int64_t)(a - skr) * k;
+#pragma unroll
+      for (int ii = 0; ii < CMAX; ii++)
+        if (ii < k) G[skr_by_pos[ii]] = col[ii];
+    }
+    if (a == 0) A.k_out[i] = k;
+  }
+}
+
+// ------------------------------------------------------------------------
 // HSS near-field SVD, one workgroup per node: one-sided (Hestenes) Jacobi
 // on the rows of A_i (m x nc), parallel round-robin pair ordering (m/2
 // disjoint rotations per round, SV_G threads per rotation), sweeps until no
@@ -650,6 +968,20 @@ __global__ void k_near_cols(int nb, int ne, const int *Nrow, const int *Ncol, co
   s_cap[i - nb] = mm * mm;
 }
 
+// G (m-k) x k  ->  G^T k x (m-k), one workgroup per node
+__global__ void k_transpose_G(int nb, int ne, const int *m, const int *k, const int64_t *go,
+                              const double *G, double *Gt) {
+  int i = nb + blockIdx.x;
+  if (i >= ne) return;
+  const int kk = k[i], nr = m[i] - kk;
+  const double *src = G + go[i];
+  double *dst = Gt + go[i];
+  for (int e = threadIdx.x; e < nr * kk; e += blockDim.x) {
+    int a = e / kk, t = e - a * kk;
+    dst[(int64_t)t * nr + a] = src[e];
+  }
+}
+
 __global__ void k_to_f32(const double *in, float *out, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -829,18 +1161,43 @@ void build_generators(Handle &h) {
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1};
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
-        if (h.batched) {
-          k_compr<<<nwg, ID_NT, 0, s>>>(ia);
+        const int nt = sc.mmax <= 64 ? 64 : sc.mmax <= 256 ? 256 : 0;
+        const int cm = cmax <= 32 ? 32 : cmax <= 64 ? 64 : 0;
+        const bool reg = nt > 0 && cm > 0 && h.d * h.p * nt <= cm * cm;
+        auto launch = [&](int grid) {
+          if (!reg) {
+            k_compr<<<grid, ID_NT, 0, s>>>(ia);
+          } else {
+            size_t sh = sizeof(double) * (size_t)cm * cm;
+#define SMASH_REG_CASE(CM, NTV)                                                  \
+  if (cm == CM && nt == NTV) k_compr_reg<CM, NTV><<<grid, NTV, sh, s>>>(ia);
+            SMASH_REG_CASE(32, 64)
+            SMASH_REG_CASE(32, 256)
+            SMASH_REG_CASE(64, 64)
+            SMASH_REG_CASE(64, 256)
+#undef SMASH_REG_CASE
+          }
           SMASH_CHECK_LAUNCH();
+        };
+        if (h.batched) {
+          int g = reg ? (nl < 8 * dev_cus ? nl : 8 * dev_cus) : nwg;
+          launch(g);
         } else {
           for (int i = nb; i < ne; i++) {
             ia.nb = i;
             ia.ne = i + 1;
             if (hss) ia.S_off = sc.S_off + (i - nb);
-            k_compr<<<1, ID_NT, 0, s>>>(ia);
-            SMASH_CHECK_LAUNCH();
+            launch(1);
           }
         }
+      }
+      // transposed copies of G for the downward pass
+      for (auto &sc : sides) {
+        Side &S = *sc.S;
+        LevelSide &L = S.lv[l];
+        L.Gt = h.mem.alloc_n<double>(L.g_n);
+        k_transpose_G<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, L.Gt);
+        SMASH_CHECK_LAUNCH();
       }
       // (d) skeleton slots of this level
       for (auto &sc : sides) {
@@ -885,8 +1242,11 @@ void build_generators(Handle &h) {
         for (int l = 2; l <= h.nlevels; l++) {
           LevelSide &L = sc.S->lv[l];
           L.G32 = h.mem.alloc_n<float>(L.g_n);
+          L.Gt32 = h.mem.alloc_n<float>(L.g_n);
           if (L.g_n > 0) {
             k_to_f32<<<ceil_div(L.g_n, 256), 256, 0, s>>>(L.G, L.G32, L.g_n);
+            SMASH_CHECK_LAUNCH();
+            k_to_f32<<<ceil_div(L.g_n, 256), 256, 0, s>>>(L.Gt, L.Gt32, L.g_n);
             SMASH_CHECK_LAUNCH();
           }
         }

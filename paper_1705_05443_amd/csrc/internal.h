@@ -75,8 +75,10 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *
 // ---------------------------------------------------------------- handle
 struct LevelSide {
   int *sel = nullptr;     // concatenated sel of the level's nodes
-  double *G = nullptr;    // concatenated G (FP64 master)
-  float *G32 = nullptr;   // apply copy
+  double *G = nullptr;    // concatenated G, (m-k) x k per node (FP64 master)
+  double *Gt = nullptr;   // the same transposed, k x (m-k) per node
+  float *G32 = nullptr;   // FP32 apply copies
+  float *Gt32 = nullptr;
   int64_t sel_n = 0, g_n = 0;
 };
 

@@ -7,23 +7,50 @@
 //             (a leaf writes its own points; an inner node adds into its
 //             children's z-hat)
 //   near+out  Z[perm_x] = z + sum_{(i,j) in L^-} B_ij q|_j
-// Vectors live in the slot space of each side, nrhs values per slot
-// (row-major), so a node's grid is a contiguous block of rows.
+// Vectors live in the slot space of each side with RP values per slot
+// (row-major; RP = the right-hand-side count rounded up to 16, padding
+// columns hold zeros), so a node's grid is a contiguous block of rows.
+//
+// Every dense piece is a small matrix product C (rows x 16) += A (rows x K)
+// * Bv (K x 16) with A one of G^T, G, B_ij and Bv a set of vector rows.  One
+// wavefront per node (and per 16-column tile) runs it on the matrix cores
+// with 16x16x4 MFMA steps: lane l feeds A[row0 + l%16][k0 + l/16] and
+// Bv[k0 + l/16][col0 + l%16] and holds C[row0 + 4(l/16) + i][col0 + l%16],
+// i = 0..3.  A is stored with consecutive rows consecutive in memory, so
+// each wave load is four 128-byte segments.
 #include "common.cuh"
 
 namespace smash {
 
-constexpr int MV_NT = 256;
+constexpr int MV_NT = 64;
+constexpr int MV_TILES = 4;  // 16-row tiles per pass (64 rows)
 
 template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_gather(const T *__restrict__ X, int64_t ldx,
-                                                     const int *__restrict__ perm, int64_t n,
-                                                     int R, T *__restrict__ q) {
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) k_mv_gather(const T *__restrict__ X, int64_t ldx,
+                                                   const int *__restrict__ perm, int64_t n, int R,
+                                                   int RP, T *__restrict__ q) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * R) return;
-  int64_t a = e / R;
-  int r = (int)(e - a * R);
-  q[e] = X[(int64_t)perm[a] * ldx + r];
+  if (e >= n * RP) return;
+  int64_t a = e / RP;
+  int r = (int)(e - a * RP);
+  q[e] = r < R ? X[(int64_t)perm[a] * ldx + r] : (T)0;
 }
 
 struct SweepArgs {
@@ -31,32 +58,57 @@ struct SweepArgs {
   const int *m, *k, *nchild;
   const int64_t *gbeg, *hbeg, *selo, *go;
   const int *sel;
-  const void *G;
+  const void *G;   // (m-k) x k row-major: as A = H^T it is column-major k x (m-k)
+  const void *Gt;  // k x (m-k) row-major: as A = G it is column-major (m-k) x k
 };
 
-// q-hat_i[t] = g[sel[t]] + sum_a H[a][t] g[sel[k+a]]   (g = grid rows)
+// ---- upward pass: q-hat_i = q|_hat + H^T q|_check ------------------------
+// A[t][a] = H[a][t] at H[a*k + t] (column-major in t); Bv row a = grid row
+// sel[k+a].  Grid rows and output rows are disjoint slot ranges of one
+// buffer, passed as separate read and write views.
 template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, T *__restrict__ q, int R) {
+__global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, const T *__restrict__ qin,
+                                                 T *__restrict__ qout, int RP) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const int i = A.nb + blockIdx.x;
   if (i >= A.ne) return;
   const int m = A.m[i], k = A.k[i];
   if (k == 0) return;
-  const T *g = q + A.gbeg[i] * R;
-  T *out = q + A.hbeg[i] * R;
+  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.y * 16 + lr;
+  const T *g = qin + A.gbeg[i] * RP;
+  T *out = qout + A.hbeg[i] * RP;
   const int *sel = A.sel + A.selo[i];
   const T *H = (const T *)A.G + A.go[i];
   const int nr = m - k;
-  for (int e = threadIdx.x; e < k * R; e += MV_NT) {
-    const int t = e / R, r = e - t * R;
-    T acc = g[(int64_t)sel[t] * R + r];
-    for (int a = 0; a < nr; a++) acc += H[(int64_t)a * k + t] * g[(int64_t)sel[k + a] * R + r];
-    out[(int64_t)t * R + r] = acc;
+  for (int t0 = 0; t0 < k; t0 += 16 * MV_TILES) {
+    acc_t acc[MV_TILES];
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int a0 = 0; a0 < nr; a0 += 4) {
+      const int a = a0 + lk;
+      const bool ka = a < nr;
+      const T bv = ka ? g[(int64_t)sel[k + a] * RP + col] : (T)0;
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++) {
+        const int t = t0 + tt * 16 + lr;
+        const T av = (ka && t < k) ? H[(int64_t)a * k + t] : (T)0;
+        acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int t = t0 + tt * 16 + 4 * lk + e;
+        if (t < k) out[(int64_t)t * RP + col] = acc[tt][e] + g[(int64_t)sel[t] * RP + col];
+      }
   }
 }
 
-// z-hat_i = sum over the L row of i of B_ij q-hat_j  (B column-major)
+// ---- coupling: z-hat_i = sum over the L row of i of B_ij q-hat_j ---------
 struct CouplingArgs {
-  int nnodes;
+  int i0, nnodes;
   const int *Lrow, *Lj;
   const int64_t *boff;
   const int *krow, *kcol;
@@ -66,59 +118,109 @@ struct CouplingArgs {
 
 template <class T>
 __global__ void __launch_bounds__(MV_NT) k_mv_coupling(CouplingArgs A, const T *__restrict__ qh,
-                                                       T *__restrict__ zh, int R) {
-  const int i = 1 + blockIdx.x;
+                                                       T *__restrict__ zh, int RP) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int i = A.i0 + blockIdx.x;
   if (i >= A.nnodes) return;
   const int ki = A.krow[i];
   if (ki == 0) return;
-  T *out = zh + A.hrow[i] * R;
+  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.y * 16 + lr;
+  T *out = zh + A.hrow[i] * RP;
   const T *Bv = (const T *)A.B;
-  for (int e = threadIdx.x; e < ki * R; e += MV_NT) {
-    const int t = e / R, r = e - t * R;
-    T acc = 0;
-    for (int p = A.Lrow[i]; p < A.Lrow[i + 1]; p++) {
+  const int p0 = A.Lrow[i], p1 = A.Lrow[i + 1];
+  for (int t0 = 0; t0 < ki; t0 += 16 * MV_TILES) {
+    acc_t acc[MV_TILES];
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int p = p0; p < p1; p++) {
       const int j = A.Lj[p];
       const int kj = A.kcol[j];
-      const T *Bp = Bv + A.boff[p] + t;
-      const T *qj = qh + A.hcol[j] * R + r;
-      for (int s = 0; s < kj; s++) acc += Bp[(int64_t)s * ki] * qj[(int64_t)s * R];
+      const T *Bp = Bv + A.boff[p];
+      const T *qj = qh + A.hcol[j] * RP + col;
+      for (int s0 = 0; s0 < kj; s0 += 4) {
+        const int s = s0 + lk;
+        const bool ks = s < kj;
+        const T bv = ks ? qj[(int64_t)s * RP] : (T)0;
+#pragma unroll
+        for (int tt = 0; tt < MV_TILES; tt++) {
+          const int t = t0 + tt * 16 + lr;
+          const T av = (ks && t < ki) ? Bp[(int64_t)s * ki + t] : (T)0;
+          acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+        }
+      }
     }
-    out[(int64_t)t * R + r] = acc;
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int t = t0 + tt * 16 + 4 * lk + e;
+        if (t < ki) out[(int64_t)t * RP + col] = acc[tt][e];
+      }
   }
 }
 
-// grid rows += P [I; G] z-hat_i (a leaf assigns: its rows are written once)
+// ---- downward pass: grid rows (=/+=) P [I; G] z-hat_i -----------------------
+// A[a][t] = G[a][t] at Gt[t*(m-k) + a]; Bv row t = z-hat row t.
 template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, T *__restrict__ z, int R) {
+__global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, const T *__restrict__ zin,
+                                                   T *__restrict__ zout, int RP) {
+  typedef typename Mfma<T>::acc_t acc_t;
   const int i = A.nb + blockIdx.x;
   if (i >= A.ne) return;
   const int m = A.m[i], k = A.k[i];
   if (m == 0) return;
   const bool leaf = A.nchild[i] == 0;
-  T *g = z + A.gbeg[i] * R;
-  const T *zh = z + A.hbeg[i] * R;
+  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.y * 16 + lr;
+  T *g = zout + A.gbeg[i] * RP;
+  const T *zh = zin + A.hbeg[i] * RP;
   const int *sel = A.sel + A.selo[i];
-  const T *G = (const T *)A.G + A.go[i];
-  for (int e = threadIdx.x; e < m * R; e += MV_NT) {
-    const int a = e / R, r = e - a * R;
-    T v;
-    if (a < k) {
-      v = zh[(int64_t)a * R + r];
-    } else {
-      const T *Ga = G + (int64_t)(a - k) * k;
-      v = 0;
-      for (int t = 0; t < k; t++) v += Ga[t] * zh[(int64_t)t * R + r];
-    }
-    T *dst = g + (int64_t)sel[a] * R + r;
+  const T *Gt = (const T *)A.Gt + A.go[i];
+  const int nr = m - k;
+  // skeleton rows: grid[sel[t]] (=/+=) z-hat[t]
+  for (int t = lk; t < k; t += 4) {
+    T *dst = g + (int64_t)sel[t] * RP + col;
+    const T v = zh[(int64_t)t * RP + col];
     if (leaf)
       *dst = v;
     else
       *dst += v;
   }
+  for (int a0 = 0; a0 < nr; a0 += 16 * MV_TILES) {
+    acc_t acc[MV_TILES];
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int t0 = 0; t0 < k; t0 += 4) {
+      const int t = t0 + lk;
+      const bool kt = t < k;
+      const T bv = kt ? zh[(int64_t)t * RP + col] : (T)0;
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++) {
+        const int a = a0 + tt * 16 + lr;
+        const T av = (kt && a < nr) ? Gt[(int64_t)t * nr + a] : (T)0;
+        acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int a = a0 + tt * 16 + 4 * lk + e;
+        if (a < nr) {
+          T *dst = g + (int64_t)sel[k + a] * RP + col;
+          if (leaf)
+            *dst = acc[tt][e];
+          else
+            *dst += acc[tt][e];
+        }
+      }
+  }
 }
 
+// ---- near field + scatter: Z[perm_x] = z + sum_{L^-} B_ij q|_j ------------
 struct NearArgs {
-  int nnodes;
+  int i0, nnodes;
   const int *nchild, *xb, *xe, *yb, *ye, *perm_x;
   const int *Lmrow, *Lmj;
   const int64_t *nboff;
@@ -129,102 +231,154 @@ struct NearArgs {
 template <class T>
 __global__ void __launch_bounds__(MV_NT) k_mv_near_out(NearArgs A, const T *__restrict__ q,
                                                        const T *__restrict__ z, T *__restrict__ Y,
-                                                       int64_t ldy, int R) {
-  const int i = blockIdx.x;
+                                                       int64_t ldy, int R, int RP) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  const int i = A.i0 + blockIdx.x;
   if (i >= A.nnodes || A.nchild[i] != 0) return;
   const int xb = A.xb[i], ni = A.xe[i] - xb;
+  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.y * 16 + lr;
   const T *Bv = (const T *)A.Bn;
-  for (int e = threadIdx.x; e < ni * R; e += MV_NT) {
-    const int a = e / R, r = e - a * R;
-    T acc = A.has_far ? z[(int64_t)(xb + a) * R + r] : (T)0;
-    for (int p = A.Lmrow[i]; p < A.Lmrow[i + 1]; p++) {
+  const int p0 = A.Lmrow[i], p1 = A.Lmrow[i + 1];
+  for (int a0 = 0; a0 < ni; a0 += 16 * MV_TILES) {
+    acc_t acc[MV_TILES];
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int p = p0; p < p1; p++) {
       const int j = A.Lmj[p];
       const int yb = A.yb[j], nj = A.ye[j] - yb;
-      const T *Bp = Bv + A.nboff[p] + a;
-      const T *qj = q + (int64_t)yb * R + r;
-      for (int b = 0; b < nj; b++) acc += Bp[(int64_t)b * ni] * qj[(int64_t)b * R];
+      const T *Bp = Bv + A.nboff[p];
+      const T *qj = q + (int64_t)yb * RP + col;
+      for (int b0 = 0; b0 < nj; b0 += 4) {
+        const int b = b0 + lk;
+        const bool kb = b < nj;
+        const T bv = kb ? qj[(int64_t)b * RP] : (T)0;
+#pragma unroll
+        for (int tt = 0; tt < MV_TILES; tt++) {
+          const int a = a0 + tt * 16 + lr;
+          const T av = (kb && a < ni) ? Bp[(int64_t)b * ni + a] : (T)0;
+          acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+        }
+      }
     }
-    Y[(int64_t)A.perm_x[xb + a] * ldy + r] = acc;
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int a = a0 + tt * 16 + 4 * lk + e;
+        if (a < ni && col < R) {
+          T v = acc[tt][e];
+          if (A.has_far) v += z[(int64_t)(xb + a) * RP + col];
+          Y[(int64_t)A.perm_x[xb + a] * ldy + col] = v;
+        }
+      }
+  }
+}
+
+template <class T>
+static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_t ldy, T *q,
+                         T *z, hipStream_t s) {
+  Side &Rw = h.row, &Cl = *h.col;
+  const bool f64 = h.apply_prec == SMASH_F64;
+  const int RP = (R + 15) / 16 * 16;
+  const int ct = RP / 16;
+  {
+    PhaseTimer pt(h, SMASH_PHASE_MV_GATHER, s);
+    k_mv_gather<T><<<ceil_div(h.ny * RP, 256), 256, 0, s>>>(X, ldx, h.perm_y, h.ny, R, RP, q);
+    SMASH_CHECK_LAUNCH();
+  }
+  const bool has_far = h.nlevels >= 2;
+  {
+    PhaseTimer pt(h, SMASH_PHASE_MV_UP, s);
+    for (int l = h.nlevels; l >= 2; l--) {
+      int nb = h.level_beg[l - 1], ne = h.level_beg[l];
+      const LevelSide &L = Cl.lv[l];
+      SweepArgs sa{nb, ne, Cl.m, Cl.k, h.nchild, Cl.gbeg, Cl.hbeg, Cl.selo, Cl.go, L.sel,
+                   f64 ? (const void *)L.G : (const void *)L.G32,
+                   f64 ? (const void *)L.Gt : (const void *)L.Gt32};
+      if (h.batched) {
+        k_mv_up<T><<<dim3(ne - nb, ct), MV_NT, 0, s>>>(sa, q, q, RP);
+        SMASH_CHECK_LAUNCH();
+      } else {
+        for (int i = nb; i < ne; i++) {
+          sa.nb = i;
+          sa.ne = i + 1;
+          k_mv_up<T><<<dim3(1, ct), MV_NT, 0, s>>>(sa, q, q, RP);
+          SMASH_CHECK_LAUNCH();
+        }
+      }
+    }
+  }
+  if (has_far) {
+    CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
+    {
+      PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
+      if (h.batched) {
+        k_mv_coupling<T><<<dim3(h.nnodes - 1, ct), MV_NT, 0, s>>>(ca, q, z, RP);
+        SMASH_CHECK_LAUNCH();
+      } else {
+        for (int i = 1; i < h.nnodes; i++) {
+          ca.i0 = i;
+          k_mv_coupling<T><<<dim3(1, ct), MV_NT, 0, s>>>(ca, q, z, RP);
+          SMASH_CHECK_LAUNCH();
+        }
+      }
+    }
+    PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
+    for (int l = 2; l <= h.nlevels; l++) {
+      int nb = h.level_beg[l - 1], ne = h.level_beg[l];
+      const LevelSide &L = Rw.lv[l];
+      SweepArgs sa{nb, ne, Rw.m, Rw.k, h.nchild, Rw.gbeg, Rw.hbeg, Rw.selo, Rw.go, L.sel,
+                   f64 ? (const void *)L.G : (const void *)L.G32,
+                   f64 ? (const void *)L.Gt : (const void *)L.Gt32};
+      if (h.batched) {
+        k_mv_down<T><<<dim3(ne - nb, ct), MV_NT, 0, s>>>(sa, z, z, RP);
+        SMASH_CHECK_LAUNCH();
+      } else {
+        for (int i = nb; i < ne; i++) {
+          sa.nb = i;
+          sa.ne = i + 1;
+          k_mv_down<T><<<dim3(1, ct), MV_NT, 0, s>>>(sa, z, z, RP);
+          SMASH_CHECK_LAUNCH();
+        }
+      }
+    }
+  }
+  NearArgs na{0, h.nnodes, h.nchild, h.xb, h.xe, h.yb, h.ye, h.perm_x, h.Lmrow, h.Lmj, h.nboff,
+              h.Bn, has_far ? 1 : 0};
+  {
+    PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
+    if (h.batched) {
+      k_mv_near_out<T><<<dim3(h.nnodes, ct), MV_NT, 0, s>>>(na, q, z, Y, ldy, R, RP);
+      SMASH_CHECK_LAUNCH();
+    } else {
+      for (int i = 0; i < h.nnodes; i++) {
+        na.i0 = i;
+        k_mv_near_out<T><<<dim3(1, ct), MV_NT, 0, s>>>(na, q, z, Y, ldy, R, RP);
+        SMASH_CHECK_LAUNCH();
+      }
+    }
   }
 }
 
 template <class T>
 static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t ldy,
                      hipStream_t s) {
-  const int RC = 64;  // right-hand sides per pass
+  const int RC = 64;  // right-hand sides per pass through the tree
   Side &Rw = h.row, &Cl = *h.col;
   int chunk = nrhs < RC ? nrhs : RC;
-  if (h.ws_nrhs != chunk) {
+  int cp = (chunk + 15) / 16 * 16;
+  if (h.ws_nrhs < cp) {
+    h.ws_mem.release();  // on the stream that allocated it
     h.ws_mem.stream = s;
-    h.ws_mem.release();
-    h.qbuf = h.ws_mem.alloc(sizeof(T) * (size_t)Cl.nslots * chunk);
-    h.zbuf = h.ws_mem.alloc(sizeof(T) * (size_t)Rw.nslots * chunk);
-    h.ws_nrhs = chunk;
+    h.qbuf = h.ws_mem.alloc(sizeof(double) * (size_t)Cl.nslots * cp);
+    h.zbuf = h.ws_mem.alloc(sizeof(double) * (size_t)Rw.nslots * cp);
+    h.ws_nrhs = cp;
   }
   T *q = (T *)h.qbuf, *z = (T *)h.zbuf;
-  const bool f64 = h.apply_prec == SMASH_F64;
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int R = nrhs - c0 < chunk ? nrhs - c0 : chunk;
-    {
-      PhaseTimer pt(h, SMASH_PHASE_MV_GATHER, s);
-      k_mv_gather<T><<<ceil_div(h.ny * R, MV_NT), MV_NT, 0, s>>>(X + c0, ldx, h.perm_y, h.ny, R,
-                                                                  q);
-      SMASH_CHECK_LAUNCH();
-    }
-    const bool has_far = h.nlevels >= 2;
-    {
-    PhaseTimer pt(h, SMASH_PHASE_MV_UP, s);
-    for (int l = h.nlevels; l >= 2; l--) {
-      int nb = h.level_beg[l - 1], ne = h.level_beg[l];
-      const LevelSide &L = Cl.lv[l];
-      SweepArgs sa{nb, ne, Cl.m, Cl.k, h.nchild, Cl.gbeg, Cl.hbeg, Cl.selo, Cl.go, L.sel,
-                   f64 ? (const void *)L.G : (const void *)L.G32};
-      if (h.batched) {
-        k_mv_up<T><<<ne - nb, MV_NT, 0, s>>>(sa, q, R);
-        SMASH_CHECK_LAUNCH();
-      } else {
-        for (int i = nb; i < ne; i++) {
-          sa.nb = i;
-          sa.ne = i + 1;
-          k_mv_up<T><<<1, MV_NT, 0, s>>>(sa, q, R);
-          SMASH_CHECK_LAUNCH();
-        }
-      }
-    }
-    }
-    if (has_far) {
-      CouplingArgs ca{h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
-      {
-        PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
-        k_mv_coupling<T><<<h.nnodes - 1, MV_NT, 0, s>>>(ca, q, z, R);
-        SMASH_CHECK_LAUNCH();
-      }
-      PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
-      for (int l = 2; l <= h.nlevels; l++) {
-        int nb = h.level_beg[l - 1], ne = h.level_beg[l];
-        const LevelSide &L = Rw.lv[l];
-        SweepArgs sa{nb, ne, Rw.m, Rw.k, h.nchild, Rw.gbeg, Rw.hbeg, Rw.selo, Rw.go, L.sel,
-                     f64 ? (const void *)L.G : (const void *)L.G32};
-        if (h.batched) {
-          k_mv_down<T><<<ne - nb, MV_NT, 0, s>>>(sa, z, R);
-          SMASH_CHECK_LAUNCH();
-        } else {
-          for (int i = nb; i < ne; i++) {
-            sa.nb = i;
-            sa.ne = i + 1;
-            k_mv_down<T><<<1, MV_NT, 0, s>>>(sa, z, R);
-            SMASH_CHECK_LAUNCH();
-          }
-        }
-      }
-    }
-    NearArgs na{h.nnodes, h.nchild, h.xb, h.xe, h.yb, h.ye, h.perm_x, h.Lmrow, h.Lmj, h.nboff,
-                h.Bn, has_far ? 1 : 0};
-    {
-      PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
-      k_mv_near_out<T><<<h.nnodes, MV_NT, 0, s>>>(na, q, z, Y + c0, ldy, R);
-      SMASH_CHECK_LAUNCH();
-    }
+    matvec_chunk<T>(h, X + c0, ldx, R, Y + c0, ldy, q, z, s);
   }
 }
 
