@@ -19,6 +19,8 @@
 // pivot choice are recomputed from the transformed columns after each
 // Householder step (no downdating), the argmax is a wavefront shuffle
 // reduction, and ties go to the lowest position.  All arithmetic is FP64.
+#include <algorithm>
+
 #include "common.cuh"
 
 namespace smash {
@@ -402,26 +404,67 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
 
 // ------------------------------------------------------------------------
 // Register-resident compr: the same algorithm as k_compr for nodes whose
-// grid fits one workgroup (m <= NT) and whose basis width fits CMAX.  Lane a
-// holds grid column a of M = C^T in registers (col[r], r < CMAX, zero past
-// c).  A column's "position" (the order the pivoted QR works in) is a lane
-// label: a pivot swap relabels two lanes instead of moving data, so ties
-// still go to the lowest current position.  Householder vectors and R11 are
-// broadcast through LDS; every loop over rows is unrolled over CMAX with a
-// predicate, so no register is indexed dynamically.
+// grid fits one workgroup (m <= NT/4) and whose basis width fits 4*RPL.
+// Grid column a of M = C^T is held by the four lanes of group a, lane
+// s of the group holding rows s*RPL .. s*RPL + RPL - 1 in registers; sums
+// over a column finish with two xor shuffles.  A column's "position" (the
+// order the pivoted QR works in) is a group label: a pivot swap relabels
+// two groups instead of moving data, so ties still go to the lowest
+// current position.  Householder vectors and R11 go through LDS; row loops
+// are unrolled over RPL with selects.
 // ------------------------------------------------------------------------
-template <int CMAX>
-__device__ __forceinline__ void reg_basis(const IdArgs &A, int i, int a, int ks, int c,
-                                          double (&col)[CMAX], double *F, int NT,
-                                          const double *xi, const double *wk) {
+template <int RPL>
+__device__ __forceinline__ double group_sum(double x) {
+  x += __shfl_xor(x, 1, WAVE);
+  x += __shfl_xor(x, 2, WAVE);
+  return x;
+}
+
+template <int RPL>
+__device__ __forceinline__ void g4_basis(const IdArgs &A, int i, int a, int sq, int ks, int c,
+                                         double (&col)[RPL], const double *F, int NG,
+                                         int src_a) {
   const int d = A.d, p = A.p;
-  const int64_t id = A.slot_id[A.gbeg[i] + a];
+  const int r0 = sq * RPL;
+  int k2 = r0 % p, k1 = (r0 / p) % p, k0 = r0 / (p * p);
+  const double *S = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)src_a * ks : nullptr;
+#pragma unroll
+  for (int u = 0; u < RPL; u++) {
+    const int r = r0 + u;
+    double v = 0.0;
+    if (r < A.c0) {
+      if (d == 1)
+        v = F[k2 * NG + a];
+      else if (d == 2)
+        v = F[(p + k2) * NG + a] * F[k1 * NG + a];
+      else
+        v = F[(2 * p + k2) * NG + a] * F[(p + k1) * NG + a] * F[k0 * NG + a];
+      if (++k2 == p) {
+        k2 = 0;
+        if (++k1 == p) {
+          k1 = 0;
+          ++k0;
+        }
+      }
+    } else if (r < c) {
+      v = S[r - A.c0];
+    }
+    col[u] = v;
+  }
+}
+
+// one-dimensional Lagrange factors of grid point src_a, written to
+// F[(t*p + q)*NG + a] by lane 0 of the group
+__device__ __forceinline__ void g4_factors(const IdArgs &A, int i, int a, int src_a, double *F,
+                                           int NG, const double *xi, const double *wk) {
+  const int d = A.d, p = A.p;
+  const int64_t id = A.slot_id[A.gbeg[i] + src_a];
   for (int t = 0; t < d; t++) {
     const double x = A.P[id * d + t];
     const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
-    double *Ft = F + (int64_t)(t * p) * NT + a;
+    double *Ft = F + (t * p) * NG + a;
     if (hi - lo == 0.0) {
-      for (int q = 0; q < p; q++) Ft[q * NT] = q == 0 ? 1.0 : 0.0;
+      for (int q = 0; q < p; q++) Ft[q * NG] = q == 0 ? 1.0 : 0.0;
       continue;
     }
     int hit = -1;
@@ -433,102 +476,71 @@ __device__ __forceinline__ void reg_basis(const IdArgs &A, int i, int a, int ks,
         break;
       }
       const double v = wk[q] / (x - xq);
-      Ft[q * NT] = v;
+      Ft[q * NG] = v;
       den += v;
     }
     if (hit >= 0)
-      for (int q = 0; q < p; q++) Ft[q * NT] = q == hit ? 1.0 : 0.0;
+      for (int q = 0; q < p; q++) Ft[q * NG] = q == hit ? 1.0 : 0.0;
     else
-      for (int q = 0; q < p; q++) Ft[q * NT] = Ft[q * NT] / den;
-  }
-  // tensor product, column index k_1 p^{d-1} + ... + k_d (odometer digits)
-  int k0 = 0, k1 = 0, k2 = 0;
-  const double *S = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
-#pragma unroll
-  for (int r = 0; r < CMAX; r++) {
-    double v = 0.0;
-    if (r < A.c0) {
-      if (d == 1)
-        v = F[(int64_t)k2 * NT + a];
-      else if (d == 2)
-        v = F[(int64_t)(p + k2) * NT + a] * F[(int64_t)k1 * NT + a];
-      else
-        v = F[(int64_t)(2 * p + k2) * NT + a] * F[(int64_t)(p + k1) * NT + a] *
-            F[(int64_t)k0 * NT + a];
-      if (++k2 == p) {
-        k2 = 0;
-        if (++k1 == p) {
-          k1 = 0;
-          ++k0;
-        }
-      }
-    } else if (r < c) {
-      v = S[r - A.c0];
-    }
-    col[r] = v;
+      for (int q = 0; q < p; q++) Ft[q * NG] = Ft[q * NG] / den;
   }
 }
 
-// One Householder step at position t.  The lane holding position t builds
-// v (rows t..c-1) into LDS and becomes column t of R; every lane at a later
-// position applies the reflector and (with `norms`) recomputes its residual
-// norm over rows t+1.., which is what the next pivot choice compares.
-// All row loops are unrolled with selects instead of branches, so the LDS
-// reads of v issue back to back.
-template <int CMAX>
-__device__ __forceinline__ void reg_householder(double (&col)[CMAX], bool act, int pos, int t,
-                                                double alpha, double *v, double *vn_lds,
-                                                double &nrm, bool norms) {
+// Householder step at position t (see householder() for the algorithm).
+template <int RPL>
+__device__ __forceinline__ void g4_householder(double (&col)[RPL], bool act, int pos, int sq,
+                                               int t, double alpha, double *v, double *vn_lds,
+                                               double &nrm, bool norms) {
+  const int r0 = sq * RPL;
   if (act && pos == t) {
-    double x0 = 0.0;
+    double xl = 0.0, rest = 0.0;
 #pragma unroll
-    for (int r = 0; r < CMAX; r++) x0 = r == t ? col[r] : x0;
+    for (int u = 0; u < RPL; u++) {
+      xl = (r0 + u == t) ? col[u] : xl;
+      rest = fma(r0 + u > t ? col[u] : 0.0, col[u], rest);
+    }
+    const int own = t / RPL;
+    const double x0 = __shfl(xl, (threadIdx.x & (WAVE - 1) & ~3) + own, WAVE);
+    rest = group_sum<RPL>(rest);
     const double rtt = x0 >= 0.0 ? -alpha : alpha;
     const double v0 = x0 - rtt;
-    double rest = 0.0;
 #pragma unroll
-    for (int r = 0; r < CMAX; r++) {
-      const double y = r > t ? col[r] : 0.0;
-      v[r] = r == t ? v0 : y;
-      rest = fma(y, y, rest);
-      col[r] = r > t ? 0.0 : (r == t ? (alpha != 0.0 ? rtt : x0) : col[r]);
+    for (int u = 0; u < RPL; u++) {
+      const int r = r0 + u;
+      v[r] = r == t ? v0 : (r > t ? col[u] : 0.0);
+      col[u] = r > t ? 0.0 : (r == t ? (alpha != 0.0 ? rtt : x0) : col[u]);
     }
-    *vn_lds = alpha != 0.0 ? rest + v0 * v0 : 0.0;
+    if (sq == 0) *vn_lds = alpha != 0.0 ? rest + v0 * v0 : 0.0;
   }
   __syncthreads();
   const double vn = *vn_lds;
   if (act && pos > t && vn > 0.0) {
-    double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+    double w = 0.0;
 #pragma unroll
-    for (int r = 0; r < CMAX; r += 4) {
-      w0 = fma(r + 0 >= t ? v[r + 0] : 0.0, col[r + 0], w0);
-      w1 = fma(r + 1 >= t ? v[r + 1] : 0.0, col[r + 1], w1);
-      w2 = fma(r + 2 >= t ? v[r + 2] : 0.0, col[r + 2], w2);
-      w3 = fma(r + 3 >= t ? v[r + 3] : 0.0, col[r + 3], w3);
-    }
-    const double sc = 2.0 * ((w0 + w1) + (w2 + w3)) / vn;
-    double s0 = 0.0, s1 = 0.0;
+    for (int u = 0; u < RPL; u++) w = fma(r0 + u >= t ? v[r0 + u] : 0.0, col[u], w);
+    w = group_sum<RPL>(w);
+    const double sc = 2.0 * w / vn;
+    double s2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < CMAX; r++) {
-      const double y = fma(-sc, r >= t ? v[r] : 0.0, col[r]);
-      col[r] = y;
-      if (r & 1)
-        s1 = fma(r > t ? y : 0.0, y, s1);
-      else
-        s0 = fma(r > t ? y : 0.0, y, s0);
+    for (int u = 0; u < RPL; u++) {
+      const double y = fma(-sc, r0 + u >= t ? v[r0 + u] : 0.0, col[u]);
+      col[u] = y;
+      s2 = fma(r0 + u > t ? y : 0.0, y, s2);
     }
-    if (norms) nrm = sqrt(s0 + s1);
+    s2 = group_sum<RPL>(s2);
+    if (norms) nrm = sqrt(s2);
   } else if (act && pos > t && norms) {
-    double s0 = 0.0;
+    double s2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < CMAX; r++) s0 = fma(r > t ? col[r] : 0.0, col[r], s0);
-    nrm = sqrt(s0);
+    for (int u = 0; u < RPL; u++) s2 = fma(r0 + u > t ? col[u] : 0.0, col[u], s2);
+    nrm = sqrt(group_sum<RPL>(s2));
   }
   __syncthreads();
 }
 
-template <int CMAX, int NT>
-__global__ void __launch_bounds__(NT) k_compr_reg(IdArgs A) {
+template <int RPL, int NT>
+__global__ void __launch_bounds__(NT) k_compr_g4(IdArgs A, int ldr) {
+  constexpr int NG = NT / 4, CMAX = 4 * RPL;
   extern __shared__ double smem[];
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
   __shared__ double v[CMAX], rinv[CMAX];
@@ -536,43 +548,47 @@ __global__ void __launch_bounds__(NT) k_compr_reg(IdArgs A) {
   __shared__ ArgMax ared[NT / WAVE + 1];
   __shared__ int64_t sred[NT / WAVE + 1];
   __shared__ int skr_by_pos[CMAX];
-  double *F = smem;    // [t*p + q][NT] during the basis evaluation
-  double *R11 = smem;  // [r][q] (CMAX x CMAX) during the swap test
-  const int a = threadIdx.x;
+  double *F = smem;    // [t*p + q][NG] during basis evaluation
+  double *R11 = smem;  // column-major, ldr x ldr, during the swap test
+  const int tid = threadIdx.x, a = tid / 4, sq = tid & 3;
+  const int gl0 = (tid & (WAVE - 1)) & ~3;  // wave lane of this group's lane 0
+  const int r0 = sq * RPL;
   const int p = A.p;
-  if (a < p) {
-    double th = M_PI * (2.0 * a + 1.0) / (2.0 * p);
-    chc[a] = cos(th);
-    wk[a] = ((a & 1) ? -1.0 : 1.0) * sin(th);
+  if (tid < p) {
+    double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
+    chc[tid] = cos(th);
+    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
   }
   for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
     const int m = A.m[i];
     const int ks = A.S ? A.ks[i] : 0;
     const int c = A.c0 + ks;
     __syncthreads();
-    if (a < A.d * p) {
-      int t = a / p, q = a % p;
+    if (tid < A.d * p) {
+      int t = tid / p, q = tid % p;
       double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
       xi[t * ID_PMAX + q] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[q];
     }
     __syncthreads();
     if (m == 0) {
-      if (a == 0) A.k_out[i] = 0;
+      if (tid == 0) A.k_out[i] = 0;
       continue;
     }
     const bool act = a < m;
     int pos = a;
-    double col[CMAX];
+    double col[RPL];
     double nrm = -1.0;
+    if (act && sq == 0) g4_factors(A, i, a, a, F, NG, xi, wk);
+    __syncthreads();
     if (act) {
-      reg_basis<CMAX>(A, i, a, ks, c, col, F, NT, xi, wk);
+      g4_basis<RPL>(A, i, a, sq, ks, c, col, F, NG, a);
       double s2 = 0.0;
 #pragma unroll
-      for (int r = 0; r < CMAX; r++) s2 = fma(col[r], col[r], s2);
-      nrm = sqrt(s2);
+      for (int u = 0; u < RPL; u++) s2 = fma(col[u], col[u], s2);
+      nrm = sqrt(group_sum<RPL>(s2));
     } else {
 #pragma unroll
-      for (int r = 0; r < CMAX; r++) col[r] = 0.0;
+      for (int u = 0; u < RPL; u++) col[u] = 0.0;
     }
     // pivoted QR
     const int kmax = m < c ? m : c;
@@ -595,7 +611,7 @@ __global__ void __launch_bounds__(NT) k_compr_reg(IdArgs A) {
         else if (pos == bp)
           pos = t;
       }
-      reg_householder<CMAX>(col, act, pos, t, bn, v, &vn_lds, nrm, true);
+      g4_householder<RPL>(col, act, pos, sq, t, bn, v, &vn_lds, nrm, true);
       k = t + 1;
     }
     // Gu-Eisenstat swaps
@@ -604,61 +620,64 @@ __global__ void __launch_bounds__(NT) k_compr_reg(IdArgs A) {
     bool failed = false;
     if (k > 0 && nr > 0) {
       for (;;) {
-        // R11 to LDS, column-major: R11[q*CMAX + r] = R[r][q]
+        __syncthreads();
         if (act && pos < k) {
 #pragma unroll
-          for (int r = 0; r < CMAX; r++) R11[pos * CMAX + r] = r <= pos ? col[r] : 0.0;
+          for (int u = 0; u < RPL; u++)
+            if (r0 + u <= pos) R11[pos * ldr + r0 + u] = col[u];
         }
         __syncthreads();
         double gam = 0.0;
         if (act && pos >= k) {
-          // N = R11^{-1} R12 in place (column-oriented back substitution),
-          // gamma = |R22 column|
           double g2 = 0.0;
 #pragma unroll
-          for (int r = 0; r < CMAX; r++) g2 = fma(r >= k ? col[r] : 0.0, col[r], g2);
-          gam = sqrt(g2);
+          for (int u = 0; u < RPL; u++) g2 = fma(r0 + u >= k ? col[u] : 0.0, col[u], g2);
+          gam = sqrt(group_sum<RPL>(g2));
+          // N = R11^{-1} R12 in place, column-oriented back substitution
+#pragma unroll 1
+          for (int q = k - 1; q >= 0; q--) {
+            const int own = q / RPL, uq = q - own * RPL;
+            double cq = 0.0;
 #pragma unroll
-          for (int q = CMAX - 1; q >= 0; q--) {
-            if (q < k) {
-              const double nq = col[q] / R11[q * CMAX + q];
-              col[q] = nq;
+            for (int u = 0; u < RPL; u++) cq = u == uq ? col[u] : cq;
+            const double nq = __shfl(cq / R11[q * ldr + q], gl0 + own, WAVE);
 #pragma unroll
-              for (int r = 0; r < q; r++) col[r] = fma(-R11[q * CMAX + r], nq, col[r]);
+            for (int u = 0; u < RPL; u++) {
+              const int r = r0 + u;
+              col[u] = r < q ? fma(-R11[q * ldr + r], nq, col[u]) : (r == q ? nq : col[u]);
             }
           }
         } else if (act && pos < k) {
-          // row pos of R11^{-1}: solve R11^T y = e_pos (y_q = 0 for q < pos)
-          const int ip = pos;
+          // row pos of R11^{-1}: forward solve R11^T y = e_pos, y in col
+#pragma unroll
+          for (int u = 0; u < RPL; u++) col[u] = 0.0;
           double s2 = 0.0;
+#pragma unroll 1
+          for (int q = pos; q < k; q++) {
+            double part = 0.0;
 #pragma unroll
-          for (int q = 0; q < CMAX; q++) col[q] = 0.0;
+            for (int u = 0; u < RPL; u++)
+              part = fma(r0 + u < q ? R11[q * ldr + r0 + u] : 0.0, col[u], part);
+            part = group_sum<RPL>(part);
+            const double y = ((q == pos ? 1.0 : 0.0) - part) / R11[q * ldr + q];
 #pragma unroll
-          for (int q = 0; q < CMAX; q++) {
-            if (q < k && q >= ip) {
-              double a0 = q == ip ? 1.0 : 0.0, a1 = 0.0;
-#pragma unroll
-              for (int r = 0; r < q; r += 2) {
-                a0 = fma(-R11[q * CMAX + r], col[r], a0);
-                if (r + 1 < q) a1 = fma(-R11[q * CMAX + r + 1], col[r + 1], a1);
-              }
-              const double y = (a0 + a1) / R11[q * CMAX + q];
-              col[q] = y;
-              s2 = fma(y, y, s2);
-            }
+            for (int u = 0; u < RPL; u++) col[u] = r0 + u == q ? y : col[u];
+            s2 = fma(y, y, s2);
           }
-          rinv[ip] = sqrt(s2);
+          if (sq == 0) rinv[pos] = sqrt(s2);
         }
         __syncthreads();
         ArgMax am{-1.0, -1};
         if (act && pos >= k) {
           const int j = pos - k;
 #pragma unroll
-          for (int ii = 0; ii < CMAX; ii++)
+          for (int u = 0; u < RPL; u++) {
+            const int ii = r0 + u;
             if (ii < k) {
-              const double nv = col[ii], b = gam * rinv[ii];
-              am = amax_pick(am, ArgMax{sqrt(nv * nv + b * b), j * k + ii});
+              const double nv = col[u], bb = gam * rinv[ii];
+              am = amax_pick(am, ArgMax{sqrt(nv * nv + bb * bb), j * k + ii});
             }
+          }
         }
         am = block_argmax(am, ared);
         if (!(am.v > A.f)) break;
@@ -675,46 +694,44 @@ __global__ void __launch_bounds__(NT) k_compr_reg(IdArgs A) {
         }
         // refactor in the new column order without pivoting
         __syncthreads();
-        if (act) reg_basis<CMAX>(A, i, a, ks, c, col, F, NT, xi, wk);
+        if (act && sq == 0) g4_factors(A, i, a, a, F, NG, xi, wk);
         __syncthreads();
+        if (act) g4_basis<RPL>(A, i, a, sq, ks, c, col, F, NG, a);
         for (int t = 0; t < k; t++) {
-          double alpha = 0.0;
-          if (act && pos == t) {
-            double s2 = 0.0;
+          double part = 0.0;
 #pragma unroll
-            for (int r = 0; r < CMAX; r++)
-              if (r >= t) s2 = fma(col[r], col[r], s2);
-            alpha = sqrt(s2);
-          }
-          reg_householder<CMAX>(col, act, pos, t, alpha, v, &vn_lds, nrm, false);
+          for (int u = 0; u < RPL; u++) part = fma(r0 + u >= t ? col[u] : 0.0, col[u], part);
+          const double alpha = sqrt(group_sum<RPL>(part));
+          g4_householder<RPL>(col, act, pos, sq, t, alpha, v, &vn_lds, nrm, false);
         }
       }
     }
-    if (a == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+    if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
     if (failed) {
-      if (a == 0) atomicOr(A.err, 1);
+      if (tid == 0) atomicOr(A.err, 1);
       k = 0;
     }
     // canonical output: skeleton positions ascending, then the rest
     const bool sk = act && pos < k;
     int64_t tot;
-    const int64_t skr = block_excl_scan_i64(sk ? 1 : 0, &tot, sred);
+    int64_t skr = block_excl_scan_i64((sk && sq == 0) ? 1 : 0, &tot, sred);
+    skr = __shfl(skr, gl0, WAVE);
     int *sel = A.sel_out + A.selo[i];
-    if (act) {
+    if (act && sq == 0) {
       if (sk)
         sel[skr] = a;
       else
         sel[k + (a - skr)] = a;
     }
-    if (sk) skr_by_pos[pos] = (int)skr;
+    if (sk && sq == 0) skr_by_pos[pos] = (int)skr;
     __syncthreads();
     if (act && !sk && k > 0) {
       double *G = A.G_out + A.go[i] + (int64_t)(a - skr) * k;
 #pragma unroll
-      for (int ii = 0; ii < CMAX; ii++)
-        if (ii < k) G[skr_by_pos[ii]] = col[ii];
+      for (int u = 0; u < RPL; u++)
+        if (r0 + u < k) G[skr_by_pos[r0 + u]] = col[u];
     }
-    if (a == 0) A.k_out[i] = k;
+    if (tid == 0) A.k_out[i] = k;
   }
 }
 
@@ -1161,21 +1178,29 @@ void build_generators(Handle &h) {
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1};
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
-        const int nt = sc.mmax <= 64 ? 64 : sc.mmax <= 256 ? 256 : 0;
-        const int cm = cmax <= 32 ? 32 : cmax <= 64 ? 64 : 0;
-        const bool reg = nt > 0 && cm > 0 && h.d * h.p * nt <= cm * cm;
+        // register-resident form when the grid fits one workgroup (4 lanes
+        // per grid point) and the basis width fits 4*RPL
+        const int nt = sc.mmax <= 64 ? 256 : sc.mmax <= 128 ? 512 : sc.mmax <= 256 ? 1024 : 0;
+        const int rpl = cmax <= 32 ? 8 : cmax <= 64 ? 16 : cmax <= 128 ? 32 : 0;
+        const int kcap = (cmax < sc.mmax ? cmax : sc.mmax);
+        const int ldr = kcap > 0 ? kcap : 1;
+        const size_t sh = sizeof(double) * (size_t)std::max(h.d * h.p * (nt / 4), ldr * ldr);
+        const bool reg = nt > 0 && rpl > 0 && !(rpl == 32 && nt == 1024) && sh <= 96 * 1024;
         auto launch = [&](int grid) {
           if (!reg) {
             k_compr<<<grid, ID_NT, 0, s>>>(ia);
           } else {
-            size_t sh = sizeof(double) * (size_t)cm * cm;
-#define SMASH_REG_CASE(CM, NTV)                                                  \
-  if (cm == CM && nt == NTV) k_compr_reg<CM, NTV><<<grid, NTV, sh, s>>>(ia);
-            SMASH_REG_CASE(32, 64)
-            SMASH_REG_CASE(32, 256)
-            SMASH_REG_CASE(64, 64)
-            SMASH_REG_CASE(64, 256)
-#undef SMASH_REG_CASE
+#define SMASH_G4_CASE(RP, NTV)                                                   \
+  if (rpl == RP && nt == NTV) k_compr_g4<RP, NTV><<<grid, NTV, sh, s>>>(ia, ldr);
+            SMASH_G4_CASE(8, 256)
+            SMASH_G4_CASE(8, 512)
+            SMASH_G4_CASE(8, 1024)
+            SMASH_G4_CASE(16, 256)
+            SMASH_G4_CASE(16, 512)
+            SMASH_G4_CASE(16, 1024)
+            SMASH_G4_CASE(32, 256)
+            SMASH_G4_CASE(32, 512)
+#undef SMASH_G4_CASE
           }
           SMASH_CHECK_LAUNCH();
         };

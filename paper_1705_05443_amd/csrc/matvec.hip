@@ -15,9 +15,11 @@
 // * Bv (K x 16) with A one of G^T, G, B_ij and Bv a set of vector rows.  One
 // wavefront per node (and per 16-column tile) runs it on the matrix cores
 // with 16x16x4 MFMA steps: lane l feeds A[row0 + l%16][k0 + l/16] and
-// Bv[k0 + l/16][col0 + l%16] and holds C[row0 + 4(l/16) + i][col0 + l%16],
-// i = 0..3.  A is stored with consecutive rows consecutive in memory, so
-// each wave load is four 128-byte segments.
+// Bv[k0 + l/16][col0 + l%16] and holds four results C[row][col0 + l%16]:
+// row = row0 + 4(l/16) + e for the FP32 instruction and row0 + 4e + l/16
+// for the FP64 one (e = 0..3; measured on gfx950).  A is stored with
+// consecutive rows consecutive in memory, so each wave load is four
+// 128-byte segments.
 #include "common.cuh"
 
 namespace smash {
@@ -33,6 +35,8 @@ struct Mfma<double> {
   static __device__ __forceinline__ acc_t op(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  // output row (within the 16-row tile) of result e held by lane group lk
+  static __device__ __forceinline__ int row(int lk, int e) { return 4 * e + lk; }
 };
 template <>
 struct Mfma<float> {
@@ -40,6 +44,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ acc_t op(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lk, int e) { return 4 * lk + e; }
 };
 
 template <class T>
@@ -100,7 +105,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, const T *__restric
     for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const int t = t0 + tt * 16 + 4 * lk + e;
+        const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
         if (t < k) out[(int64_t)t * RP + col] = acc[tt][e] + g[(int64_t)sel[t] * RP + col];
       }
   }
@@ -138,23 +143,32 @@ __global__ void __launch_bounds__(MV_NT) k_mv_coupling(CouplingArgs A, const T *
       const int kj = A.kcol[j];
       const T *Bp = Bv + A.boff[p];
       const T *qj = qh + A.hcol[j] * RP + col;
-      for (int s0 = 0; s0 < kj; s0 += 4) {
-        const int s = s0 + lk;
-        const bool ks = s < kj;
-        const T bv = ks ? qj[(int64_t)s * RP] : (T)0;
+      // K in chunks of 16: every load of four MFMA steps is in flight
+      // before the first of them issues
+      for (int s0 = 0; s0 < kj; s0 += 16) {
+        T bv[4], av[4][MV_TILES];
 #pragma unroll
-        for (int tt = 0; tt < MV_TILES; tt++) {
-          const int t = t0 + tt * 16 + lr;
-          const T av = (ks && t < ki) ? Bp[(int64_t)s * ki + t] : (T)0;
-          acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+        for (int u = 0; u < 4; u++) {
+          const int s = s0 + 4 * u + lk;
+          const bool ks = s < kj;
+          bv[u] = ks ? qj[(int64_t)s * RP] : (T)0;
+#pragma unroll
+          for (int tt = 0; tt < MV_TILES; tt++) {
+            const int t = t0 + tt * 16 + lr;
+            av[u][tt] = (ks && t < ki) ? Bp[(int64_t)s * ki + t] : (T)0;
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+          for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
       }
     }
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const int t = t0 + tt * 16 + 4 * lk + e;
+        const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
         if (t < ki) out[(int64_t)t * RP + col] = acc[tt][e];
       }
   }
@@ -206,7 +220,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, const T *__restr
     for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const int a = a0 + tt * 16 + 4 * lk + e;
+        const int a = a0 + tt * 16 + Mfma<T>::row(lk, e);
         if (a < nr) {
           T *dst = g + (int64_t)sel[k + a] * RP + col;
           if (leaf)
@@ -249,23 +263,30 @@ __global__ void __launch_bounds__(MV_NT) k_mv_near_out(NearArgs A, const T *__re
       const int yb = A.yb[j], nj = A.ye[j] - yb;
       const T *Bp = Bv + A.nboff[p];
       const T *qj = q + (int64_t)yb * RP + col;
-      for (int b0 = 0; b0 < nj; b0 += 4) {
-        const int b = b0 + lk;
-        const bool kb = b < nj;
-        const T bv = kb ? qj[(int64_t)b * RP] : (T)0;
+      for (int b0 = 0; b0 < nj; b0 += 16) {
+        T bv[4], av[4][MV_TILES];
 #pragma unroll
-        for (int tt = 0; tt < MV_TILES; tt++) {
-          const int a = a0 + tt * 16 + lr;
-          const T av = (kb && a < ni) ? Bp[(int64_t)b * ni + a] : (T)0;
-          acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+        for (int u = 0; u < 4; u++) {
+          const int b = b0 + 4 * u + lk;
+          const bool kb = b < nj;
+          bv[u] = kb ? qj[(int64_t)b * RP] : (T)0;
+#pragma unroll
+          for (int tt = 0; tt < MV_TILES; tt++) {
+            const int a = a0 + tt * 16 + lr;
+            av[u][tt] = (kb && a < ni) ? Bp[(int64_t)b * ni + a] : (T)0;
+          }
         }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+          for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
       }
     }
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
       for (int e = 0; e < 4; e++) {
-        const int a = a0 + tt * 16 + 4 * lk + e;
+        const int a = a0 + tt * 16 + Mfma<T>::row(lk, e);
         if (a < ni && col < R) {
           T v = acc[tt][e];
           if (A.has_far) v += z[(int64_t)(xb + a) * RP + col];
