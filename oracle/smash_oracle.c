@@ -126,6 +126,7 @@ typedef struct {
   int *sel;       /* m local positions: k skeleton asc, then rest asc   */
   double *G;      /* (m-k) x k row-major                                */
   int ks;         /* HSS: number of kept singular vectors               */
+  int nsw;        /* Gu-Eisenstat swaps performed                       */
 } side_t;
 
 typedef struct {
@@ -912,6 +913,7 @@ static int compress_node(oracle_t *h, int i, int rowside) {
   if (!s->G) return OR_ENOMEM;
   int nsw = 0;
   int rc = compr(C, m, c, h->tol, h->f, &s->k, s->sel, s->G, &nsw);
+  s->nsw = nsw;
   free(C);
   free(pts);
   free(S);
@@ -1239,7 +1241,7 @@ enum {
   EX_PERM_X = 1, EX_PERM_Y = 2, EX_NODES = 3, EX_BOXES = 4, EX_L = 5, EX_LM = 6,
   EX_NEAR_PTR = 7, EX_NEAR_IDX = 8, EX_RANKS = 9, EX_ROW_SEL = 10, EX_ROW_G = 11,
   EX_COL_SEL = 12, EX_COL_G = 13, EX_ROW_GRID = 14, EX_COL_GRID = 15, EX_SIZES = 16,
-  EX_LEVELS = 17
+  EX_LEVELS = 17, EX_SWAPS = 18
 };
 
 int oracle_export(void *hv, int what, void *buf, int64_t *count) {
@@ -1312,6 +1314,14 @@ int oracle_export(void *hv, int what, void *buf, int64_t *count) {
           int *o = ib + (size_t)i * 6;
           o[0] = h->row[i].m; o[1] = h->row[i].k; o[2] = h->col[i].m; o[3] = h->col[i].k;
           o[4] = h->row[i].ks; o[5] = h->col[i].ks;
+        }
+      break;
+    case EX_SWAPS: /* int32 x 2: swaps of the row and column side per node */
+      n = (int64_t)nn * 2;
+      if (buf)
+        for (int i = 0; i < nn; i++) {
+          ib[2 * i] = h->row[i].nsw;
+          ib[2 * i + 1] = h->col[i].nsw;
         }
       break;
     case EX_ROW_SEL:

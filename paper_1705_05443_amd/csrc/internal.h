@@ -48,12 +48,17 @@ struct Error {
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 // ---------------------------------------------------------------- allocator
-// Stream-ordered allocations from the device's default memory pool (kept
-// cached across builds); every pointer is tracked by its owner.
+// Bump allocation (256-byte aligned) inside chunks taken stream-ordered from
+// the device's default memory pool (kept cached across builds), so a build
+// makes a handful of pool calls instead of one per array.  release() returns
+// every chunk.
 struct DeviceArena {
   hipStream_t stream = nullptr;
-  std::vector<void *> ptrs;
-  int64_t bytes = 0;
+  std::vector<void *> ptrs;  // chunks
+  char *cur = nullptr;
+  size_t left = 0;
+  size_t chunk = (size_t)32 << 20;
+  int64_t bytes = 0;  // bytes handed out
   void *alloc(size_t n);
   template <class T>
   T *alloc_n(size_t n) {

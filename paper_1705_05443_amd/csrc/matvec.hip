@@ -90,16 +90,29 @@ __global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, const T *__restric
     acc_t acc[MV_TILES];
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-    for (int a0 = 0; a0 < nr; a0 += 4) {
-      const int a = a0 + lk;
-      const bool ka = a < nr;
-      const T bv = ka ? g[(int64_t)sel[k + a] * RP + col] : (T)0;
+    for (int a0 = 0; a0 < nr; a0 += 16) {
+      int srow[4];
 #pragma unroll
-      for (int tt = 0; tt < MV_TILES; tt++) {
-        const int t = t0 + tt * 16 + lr;
-        const T av = (ka && t < k) ? H[(int64_t)a * k + t] : (T)0;
-        acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+      for (int u = 0; u < 4; u++) {
+        const int a = a0 + 4 * u + lk;
+        srow[u] = a < nr ? sel[k + a] : 0;
       }
+      T bv[4], av[4][MV_TILES];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int a = a0 + 4 * u + lk;
+        const bool ka = a < nr;
+        bv[u] = ka ? g[(int64_t)srow[u] * RP + col] : (T)0;
+#pragma unroll
+        for (int tt = 0; tt < MV_TILES; tt++) {
+          const int t = t0 + tt * 16 + lr;
+          av[u][tt] = (ka && t < k) ? H[(int64_t)a * k + t] : (T)0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
     }
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++)
@@ -205,16 +218,23 @@ __global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, const T *__restr
     acc_t acc[MV_TILES];
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-    for (int t0 = 0; t0 < k; t0 += 4) {
-      const int t = t0 + lk;
-      const bool kt = t < k;
-      const T bv = kt ? zh[(int64_t)t * RP + col] : (T)0;
+    for (int t0 = 0; t0 < k; t0 += 16) {
+      T bv[4], av[4][MV_TILES];
 #pragma unroll
-      for (int tt = 0; tt < MV_TILES; tt++) {
-        const int a = a0 + tt * 16 + lr;
-        const T av = (kt && a < nr) ? Gt[(int64_t)t * nr + a] : (T)0;
-        acc[tt] = Mfma<T>::op(av, bv, acc[tt]);
+      for (int u = 0; u < 4; u++) {
+        const int t = t0 + 4 * u + lk;
+        const bool kt = t < k;
+        bv[u] = kt ? zh[(int64_t)t * RP + col] : (T)0;
+#pragma unroll
+        for (int tt = 0; tt < MV_TILES; tt++) {
+          const int a = a0 + tt * 16 + lr;
+          av[u][tt] = (kt && a < nr) ? Gt[(int64_t)t * nr + a] : (T)0;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+#pragma unroll
+        for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
     }
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++)

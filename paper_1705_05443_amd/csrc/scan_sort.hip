@@ -7,20 +7,31 @@
 namespace smash {
 
 void *DeviceArena::alloc(size_t n) {
-  void *p = nullptr;
-  hipError_t e = hipMallocAsync(&p, n, stream);
-  if (e != hipSuccess || !p) {
-    (void)hipGetLastError();
-    throw Error{SMASH_E_OOM, "device allocation of " + std::to_string(n) + " bytes failed"};
+  n = (n + 255) & ~(size_t)255;
+  if (n > left) {
+    size_t sz = n > chunk ? n : chunk;
+    void *p = nullptr;
+    hipError_t e = hipMallocAsync(&p, sz, stream);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error{SMASH_E_OOM, "device allocation of " + std::to_string(sz) + " bytes failed"};
+    }
+    ptrs.push_back(p);
+    cur = (char *)p;
+    left = sz;
   }
-  ptrs.push_back(p);
+  void *r = cur;
+  cur += n;
+  left -= n;
   bytes += (int64_t)n;
-  return p;
+  return r;
 }
 
 void DeviceArena::release() {
   for (void *p : ptrs) (void)hipFreeAsync(p, stream);
   ptrs.clear();
+  cur = nullptr;
+  left = 0;
   bytes = 0;
 }
 
