@@ -193,6 +193,140 @@ __device__ inline void householder(double *W, int ldw, int c, int m, int t, doub
   __syncthreads();
 }
 
+// Steps 3-4 of compr on the workgroup tile W (c x m, columns in position
+// order, perm[pos] = grid index), after a pivoted QR that kept k columns:
+// the Gu-Eisenstat swap loop, then the canonical output (sel, G, k).
+__device__ void compr_tail(const IdArgs &A, int i, int m, int c, int ks, int k, double *W,
+                           double *F, double *Nrm, double *Ri, int *perm, int *pos, int ldw,
+                           const double *xi, const double *wk, double *v, double *rinv,
+                           double *red, ArgMax *ared, int64_t *sred) {
+  const int tid = threadIdx.x;
+  const int NTB = blockDim.x;
+  // 3. Gu-Eisenstat swaps
+  const int nr = m - k;
+  int nsw = 0;
+  bool failed = false;
+  if (k > 0 && nr > 0) {
+    for (;;) {
+      // N = R11^{-1} R12 (over R12, in place) and gamma_j = |R22 column j|
+      for (int a = k + tid; a < m; a += NTB) {
+        for (int ii = k - 1; ii >= 0; ii--) {
+          double s = W[(int64_t)ii * ldw + a];
+          for (int q = ii + 1; q < k; q++)
+            s = fma(-W[(int64_t)ii * ldw + q], W[(int64_t)q * ldw + a], s);
+          W[(int64_t)ii * ldw + a] = s / W[(int64_t)ii * ldw + ii];
+        }
+        double g2 = 0.0;
+        for (int r = k; r < c; r++) {
+          double y = W[(int64_t)r * ldw + a];
+          g2 = fma(y, y, g2);
+        }
+        Nrm[a] = sqrt(g2);
+      }
+      // R11^{-1}, column j per thread
+      for (int j = tid; j < k; j += NTB) {
+        for (int ii = k - 1; ii >= 0; ii--) {
+          double s = ii == j ? 1.0 : 0.0;
+          for (int q = ii + 1; q < k; q++)
+            s = fma(-W[(int64_t)ii * ldw + q], Ri[(int64_t)q * k + j], s);
+          Ri[(int64_t)ii * k + j] = s / W[(int64_t)ii * ldw + ii];
+        }
+      }
+      __syncthreads();
+      for (int ii = tid; ii < k; ii += NTB) {
+        double s = 0.0;
+        for (int j = 0; j < k; j++) {
+          double y = Ri[(int64_t)ii * k + j];
+          s = fma(y, y, s);
+        }
+        rinv[ii] = sqrt(s);
+      }
+      __syncthreads();
+      // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
+      // smallest j, then smallest i (pair index j*k + i)
+      ArgMax am{-1.0, -1};
+      for (int a = k + tid; a < m; a += NTB) {
+        double g = Nrm[a];
+        for (int ii = 0; ii < k; ii++) {
+          double nv = W[(int64_t)ii * ldw + a];
+          double b = g * rinv[ii];
+          double rho = sqrt(nv * nv + b * b);
+          am = amax_pick(am, ArgMax{rho, (a - k) * k + ii});
+        }
+      }
+      am = block_argmax(am, ared);
+      if (!(am.v > A.f)) break;
+      if (++nsw > 64 * k) {
+        failed = true;
+        break;
+      }
+      const int bj = am.a / k, bi = am.a % k;
+      __syncthreads();
+      if (tid == 0) {
+        int tp = perm[bi];
+        perm[bi] = perm[k + bj];
+        perm[k + bj] = tp;
+      }
+      __syncthreads();
+      // refactor the new column order without pivoting
+      for (int a = tid; a < m; a += NTB) basis_column(A, i, a, perm[a], W, F, ldw, ks, xi, wk);
+      __syncthreads();
+      for (int t = 0; t < k; t++) {
+        double part = 0.0;
+        for (int r = t + tid; r < c; r += NTB) {
+          double y = W[(int64_t)r * ldw + t];
+          part = fma(y, y, part);
+        }
+        double alpha = sqrt(block_sum(part, red));
+        householder(W, ldw, c, m, t, alpha, v, red, Nrm, false);
+      }
+    }
+  } else if (k > 0) {
+    // k == m: nothing to solve
+  }
+  if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+  if (failed) {
+    if (tid == 0) atomicOr(A.err, 1);
+    k = 0;
+  }
+  // 4. canonical output: skeleton positions ascending, then the rest
+  __syncthreads();
+  for (int a = tid; a < m; a += NTB) pos[a] = 0;
+  __syncthreads();
+  for (int q = tid; q < k; q += NTB) pos[perm[q]] = 1;
+  __syncthreads();
+  {
+    const int chunk = (m + NTB - 1) / NTB;
+    const int a0 = tid * chunk;
+    int64_t cnt = 0;
+    for (int u = 0; u < chunk; u++)
+      if (a0 + u < m) cnt += pos[a0 + u];
+    int64_t tot;
+    int64_t ex = block_excl_scan_i64(cnt, &tot, sred);
+    int *sel = A.sel_out + A.selo[i];
+    for (int u = 0; u < chunk; u++) {
+      int a = a0 + u;
+      if (a >= m) break;
+      int fl = pos[a];
+      if (fl)
+        sel[ex] = a;
+      else
+        sel[k + (a - ex)] = a;
+      pos[a] = fl ? (int)ex : -(int)(a - ex) - 1;  // skeleton rank, or -(rest rank)-1
+      ex += fl;
+    }
+  }
+  __syncthreads();
+  if (k > 0 && nr > 0) {
+    double *G = A.G_out + A.go[i];
+    for (int a = k + tid; a < m; a += NTB) {
+      int row = -pos[perm[a]] - 1;
+      for (int ii = 0; ii < k; ii++) G[(int64_t)row * k + pos[perm[ii]]] = W[(int64_t)ii * ldw + a];
+    }
+  }
+  if (tid == 0) A.k_out[i] = k;
+}
+
 __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
   __shared__ double v[ID_CMAX + 1], rinv[ID_CMAX];
@@ -276,326 +410,133 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
       householder(W, ldw, c, m, t, bn, v, red, Nrm, true);
       k = t + 1;
     }
-    // 3. Gu-Eisenstat swaps
-    const int nr = m - k;
-    int nsw = 0;
-    bool failed = false;
-    if (k > 0 && nr > 0) {
-      for (;;) {
-        // N = R11^{-1} R12 (over R12, in place) and gamma_j = |R22 column j|
-        for (int a = k + tid; a < m; a += ID_NT) {
-          for (int ii = k - 1; ii >= 0; ii--) {
-            double s = W[(int64_t)ii * ldw + a];
-            for (int q = ii + 1; q < k; q++)
-              s = fma(-W[(int64_t)ii * ldw + q], W[(int64_t)q * ldw + a], s);
-            W[(int64_t)ii * ldw + a] = s / W[(int64_t)ii * ldw + ii];
-          }
-          double g2 = 0.0;
-          for (int r = k; r < c; r++) {
-            double y = W[(int64_t)r * ldw + a];
-            g2 = fma(y, y, g2);
-          }
-          Nrm[a] = sqrt(g2);
-        }
-        // R11^{-1}, column j per thread
-        for (int j = tid; j < k; j += ID_NT) {
-          for (int ii = k - 1; ii >= 0; ii--) {
-            double s = ii == j ? 1.0 : 0.0;
-            for (int q = ii + 1; q < k; q++)
-              s = fma(-W[(int64_t)ii * ldw + q], Ri[(int64_t)q * k + j], s);
-            Ri[(int64_t)ii * k + j] = s / W[(int64_t)ii * ldw + ii];
-          }
-        }
-        __syncthreads();
-        for (int ii = tid; ii < k; ii += ID_NT) {
-          double s = 0.0;
-          for (int j = 0; j < k; j++) {
-            double y = Ri[(int64_t)ii * k + j];
-            s = fma(y, y, s);
-          }
-          rinv[ii] = sqrt(s);
-        }
-        __syncthreads();
-        // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
-        // smallest j, then smallest i (pair index j*k + i)
-        ArgMax am{-1.0, -1};
-        for (int a = k + tid; a < m; a += ID_NT) {
-          double g = Nrm[a];
-          for (int ii = 0; ii < k; ii++) {
-            double nv = W[(int64_t)ii * ldw + a];
-            double b = g * rinv[ii];
-            double rho = sqrt(nv * nv + b * b);
-            am = amax_pick(am, ArgMax{rho, (a - k) * k + ii});
-          }
-        }
-        am = block_argmax(am, ared);
-        if (!(am.v > A.f)) break;
-        if (++nsw > 64 * k) {
-          failed = true;
-          break;
-        }
-        const int bj = am.a / k, bi = am.a % k;
-        __syncthreads();
-        if (tid == 0) {
-          int tp = perm[bi];
-          perm[bi] = perm[k + bj];
-          perm[k + bj] = tp;
-        }
-        __syncthreads();
-        // refactor the new column order without pivoting
-        for (int a = tid; a < m; a += ID_NT) basis_column(A, i, a, perm[a], W, F, ldw, ks, xi, wk);
-        __syncthreads();
-        for (int t = 0; t < k; t++) {
-          double part = 0.0;
-          for (int r = t + tid; r < c; r += ID_NT) {
-            double y = W[(int64_t)r * ldw + t];
-            part = fma(y, y, part);
-          }
-          double alpha = sqrt(block_sum(part, red));
-          householder(W, ldw, c, m, t, alpha, v, red, Nrm, false);
-        }
-      }
-    } else if (k > 0) {
-      // k == m: nothing to solve
-    }
-    if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
-    if (failed) {
-      if (tid == 0) atomicOr(A.err, 1);
-      k = 0;
-    }
-    // 4. canonical output: skeleton positions ascending, then the rest
-    __syncthreads();
-    for (int a = tid; a < m; a += ID_NT) pos[a] = 0;
-    __syncthreads();
-    for (int q = tid; q < k; q += ID_NT) pos[perm[q]] = 1;
-    __syncthreads();
-    {
-      const int chunk = (m + ID_NT - 1) / ID_NT;
-      const int a0 = tid * chunk;
-      int64_t cnt = 0;
-      for (int u = 0; u < chunk; u++)
-        if (a0 + u < m) cnt += pos[a0 + u];
-      int64_t tot;
-      int64_t ex = block_excl_scan_i64(cnt, &tot, sred);
-      int *sel = A.sel_out + A.selo[i];
-      for (int u = 0; u < chunk; u++) {
-        int a = a0 + u;
-        if (a >= m) break;
-        int fl = pos[a];
-        if (fl)
-          sel[ex] = a;
-        else
-          sel[k + (a - ex)] = a;
-        pos[a] = fl ? (int)ex : -(int)(a - ex) - 1;  // skeleton rank, or -(rest rank)-1
-        ex += fl;
-      }
-    }
-    __syncthreads();
-    if (k > 0 && nr > 0) {
-      double *G = A.G_out + A.go[i];
-      for (int a = k + tid; a < m; a += ID_NT) {
-        int row = -pos[perm[a]] - 1;
-        for (int ii = 0; ii < k; ii++) G[(int64_t)row * k + pos[perm[ii]]] = W[(int64_t)ii * ldw + a];
-      }
-    }
-    if (tid == 0) A.k_out[i] = k;
+    compr_tail(A, i, m, c, ks, k, W, F, Nrm, Ri, perm, pos, ldw, xi, wk, v, rinv, red, ared,
+               sred);
   }
 }
 
 // ------------------------------------------------------------------------
-// Register-resident compr: the same algorithm as k_compr for nodes whose
-// grid fits one workgroup (m <= NT/4) and whose basis width fits 4*RPL.
-// Grid column a of M = C^T is held by the four lanes of group a, lane
-// s of the group holding rows s*RPL .. s*RPL + RPL - 1 in registers; sums
-// over a column finish with two xor shuffles.  A column's "position" (the
-// order the pivoted QR works in) is a group label: a pivot swap relabels
-// two groups instead of moving data, so ties still go to the lowest
-// current position.  Householder vectors and R11 go through LDS; row loops
-// are unrolled over RPL with selects.
+// Register-resident pivoted QR: the same algorithm as k_compr for nodes
+// whose grid fits one workgroup (m <= NT) and whose basis width fits CMAX.
+// Lane a holds grid column a of M = C^T in registers (col[r], r < CMAX,
+// zero past c), so each Householder step costs one block arg-max, one LDS
+// broadcast of v and a register update.  A column's "position" (the order
+// the pivoted QR works in) is a lane label: a pivot swap relabels two lanes
+// instead of moving data, so ties still go to the lowest current position.
+// After the QR the factor is written to the workgroup tile in position
+// order and compr_tail finishes (swap test, rare swaps, output).
 // ------------------------------------------------------------------------
-template <int RPL>
-__device__ __forceinline__ double group_sum(double x) {
-  x += __shfl_xor(x, 1, WAVE);
-  x += __shfl_xor(x, 2, WAVE);
-  return x;
-}
-
-template <int RPL>
-__device__ __forceinline__ void g4_basis(const IdArgs &A, int i, int a, int sq, int ks, int c,
-                                         double (&col)[RPL], const double *F, int NG,
-                                         int src_a) {
-  const int d = A.d, p = A.p;
-  const int r0 = sq * RPL;
-  int k2 = r0 % p, k1 = (r0 / p) % p, k0 = r0 / (p * p);
-  const double *S = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)src_a * ks : nullptr;
-#pragma unroll
-  for (int u = 0; u < RPL; u++) {
-    const int r = r0 + u;
-    double v = 0.0;
-    if (r < A.c0) {
-      if (d == 1)
-        v = F[k2 * NG + a];
-      else if (d == 2)
-        v = F[(p + k2) * NG + a] * F[k1 * NG + a];
-      else
-        v = F[(2 * p + k2) * NG + a] * F[(p + k1) * NG + a] * F[k0 * NG + a];
-      if (++k2 == p) {
-        k2 = 0;
-        if (++k1 == p) {
-          k1 = 0;
-          ++k0;
-        }
-      }
-    } else if (r < c) {
-      v = S[r - A.c0];
-    }
-    col[u] = v;
-  }
-}
-
-// one-dimensional Lagrange factors of grid point src_a, written to
-// F[(t*p + q)*NG + a] by lane 0 of the group
-__device__ __forceinline__ void g4_factors(const IdArgs &A, int i, int a, int src_a, double *F,
-                                           int NG, const double *xi, const double *wk) {
-  const int d = A.d, p = A.p;
-  const int64_t id = A.slot_id[A.gbeg[i] + src_a];
-  for (int t = 0; t < d; t++) {
-    const double x = A.P[id * d + t];
-    const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
-    double *Ft = F + (t * p) * NG + a;
-    if (hi - lo == 0.0) {
-      for (int q = 0; q < p; q++) Ft[q * NG] = q == 0 ? 1.0 : 0.0;
-      continue;
-    }
-    int hit = -1;
-    double den = 0.0;
-    for (int q = 0; q < p; q++) {
-      const double xq = xi[t * ID_PMAX + q];
-      if (x == xq) {
-        hit = q;
-        break;
-      }
-      const double v = wk[q] / (x - xq);
-      Ft[q * NG] = v;
-      den += v;
-    }
-    if (hit >= 0)
-      for (int q = 0; q < p; q++) Ft[q * NG] = q == hit ? 1.0 : 0.0;
-    else
-      for (int q = 0; q < p; q++) Ft[q * NG] = Ft[q * NG] / den;
-  }
-}
-
-// Householder step at position t (see householder() for the algorithm).
-template <int RPL>
-__device__ __forceinline__ void g4_householder(double (&col)[RPL], bool act, int pos, int sq,
-                                               int t, double alpha, double *v, double *vn_lds,
-                                               double &nrm, bool norms) {
-  const int r0 = sq * RPL;
-  if (act && pos == t) {
-    double xl = 0.0, rest = 0.0;
-#pragma unroll
-    for (int u = 0; u < RPL; u++) {
-      xl = (r0 + u == t) ? col[u] : xl;
-      rest = fma(r0 + u > t ? col[u] : 0.0, col[u], rest);
-    }
-    const int own = t / RPL;
-    const double x0 = __shfl(xl, (threadIdx.x & (WAVE - 1) & ~3) + own, WAVE);
-    rest = group_sum<RPL>(rest);
-    const double rtt = x0 >= 0.0 ? -alpha : alpha;
-    const double v0 = x0 - rtt;
-#pragma unroll
-    for (int u = 0; u < RPL; u++) {
-      const int r = r0 + u;
-      v[r] = r == t ? v0 : (r > t ? col[u] : 0.0);
-      col[u] = r > t ? 0.0 : (r == t ? (alpha != 0.0 ? rtt : x0) : col[u]);
-    }
-    if (sq == 0) *vn_lds = alpha != 0.0 ? rest + v0 * v0 : 0.0;
-  }
-  __syncthreads();
-  const double vn = *vn_lds;
-  if (act && pos > t && vn > 0.0) {
-    double w = 0.0;
-#pragma unroll
-    for (int u = 0; u < RPL; u++) w = fma(r0 + u >= t ? v[r0 + u] : 0.0, col[u], w);
-    w = group_sum<RPL>(w);
-    const double sc = 2.0 * w / vn;
-    double s2 = 0.0;
-#pragma unroll
-    for (int u = 0; u < RPL; u++) {
-      const double y = fma(-sc, r0 + u >= t ? v[r0 + u] : 0.0, col[u]);
-      col[u] = y;
-      s2 = fma(r0 + u > t ? y : 0.0, y, s2);
-    }
-    s2 = group_sum<RPL>(s2);
-    if (norms) nrm = sqrt(s2);
-  } else if (act && pos > t && norms) {
-    double s2 = 0.0;
-#pragma unroll
-    for (int u = 0; u < RPL; u++) s2 = fma(r0 + u > t ? col[u] : 0.0, col[u], s2);
-    nrm = sqrt(group_sum<RPL>(s2));
-  }
-  __syncthreads();
-}
-
-template <int RPL, int NT>
-__global__ void __launch_bounds__(NT) k_compr_g4(IdArgs A, int ldr) {
-  constexpr int NG = NT / 4, CMAX = 4 * RPL;
-  extern __shared__ double smem[];
+template <int CMAX, int NT>
+__global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
+  extern __shared__ double Fl[];  // one-dimensional factors [t*p + q][NT]
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
-  __shared__ double v[CMAX], rinv[CMAX];
-  __shared__ double vn_lds;
+  __shared__ double v[ID_CMAX + 1], rinv[ID_CMAX];
+  __shared__ double red[NT / WAVE + 1];
   __shared__ ArgMax ared[NT / WAVE + 1];
   __shared__ int64_t sred[NT / WAVE + 1];
-  __shared__ int skr_by_pos[CMAX];
-  double *F = smem;    // [t*p + q][NG] during basis evaluation
-  double *R11 = smem;  // column-major, ldr x ldr, during the swap test
-  const int tid = threadIdx.x, a = tid / 4, sq = tid & 3;
-  const int gl0 = (tid & (WAVE - 1)) & ~3;  // wave lane of this group's lane 0
-  const int r0 = sq * RPL;
-  const int p = A.p;
-  if (tid < p) {
-    double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
-    chc[tid] = cos(th);
-    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
+  __shared__ double vn_lds;
+  const int a = threadIdx.x;
+  const int p = A.p, d = A.d;
+  if (a < p) {
+    double th = M_PI * (2.0 * a + 1.0) / (2.0 * p);
+    chc[a] = cos(th);
+    wk[a] = ((a & 1) ? -1.0 : 1.0) * sin(th);
   }
+  double *W = A.scratch + (int64_t)blockIdx.x * A.wg_stride;
+  const int ldw = A.ldw;
+  int *perm = A.iscratch + (int64_t)blockIdx.x * A.wg_istride;
+  int *pos = perm + ldw;
   for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
     const int m = A.m[i];
     const int ks = A.S ? A.ks[i] : 0;
     const int c = A.c0 + ks;
+    double *F = W + (int64_t)c * ldw;
+    double *Nrm = F + (int64_t)d * p * ldw;
+    double *Ri = Nrm + ldw;
     __syncthreads();
-    if (tid < A.d * p) {
-      int t = tid / p, q = tid % p;
+    if (a < d * p) {
+      int t = a / p, q = a % p;
       double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
       xi[t * ID_PMAX + q] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[q];
     }
     __syncthreads();
     if (m == 0) {
-      if (tid == 0) A.k_out[i] = 0;
+      if (a == 0) A.k_out[i] = 0;
       continue;
     }
     const bool act = a < m;
-    int pos = a;
-    double col[RPL];
+    int pa = a;  // current position of this lane's column
+    double col[CMAX];
     double nrm = -1.0;
-    if (act && sq == 0) g4_factors(A, i, a, a, F, NG, xi, wk);
-    __syncthreads();
+    // basis column: one-dimensional factors in LDS, then tensor products
     if (act) {
-      g4_basis<RPL>(A, i, a, sq, ks, c, col, F, NG, a);
-      double s2 = 0.0;
+      const int64_t id = A.slot_id[A.gbeg[i] + a];
+      for (int t = 0; t < d; t++) {
+        const double x = A.P[id * d + t];
+        const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+        double *Ft = Fl + (t * p) * NT + a;
+        if (hi - lo == 0.0) {
+          for (int q = 0; q < p; q++) Ft[q * NT] = q == 0 ? 1.0 : 0.0;
+          continue;
+        }
+        int hit = -1;
+        double den = 0.0;
+        for (int q = 0; q < p; q++) {
+          const double xq = xi[t * ID_PMAX + q];
+          if (x == xq) {
+            hit = q;
+            break;
+          }
+          const double w = wk[q] / (x - xq);
+          Ft[q * NT] = w;
+          den += w;
+        }
+        if (hit >= 0)
+          for (int q = 0; q < p; q++) Ft[q * NT] = q == hit ? 1.0 : 0.0;
+        else
+          for (int q = 0; q < p; q++) Ft[q * NT] = Ft[q * NT] / den;
+      }
+      int k0 = 0, k1 = 0, k2 = 0;
+      const double *Sa = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
 #pragma unroll
-      for (int u = 0; u < RPL; u++) s2 = fma(col[u], col[u], s2);
-      nrm = sqrt(group_sum<RPL>(s2));
+      for (int r = 0; r < CMAX; r++) {
+        double val = 0.0;
+        if (r < A.c0) {
+          if (d == 1)
+            val = Fl[k2 * NT + a];
+          else if (d == 2)
+            val = Fl[(p + k2) * NT + a] * Fl[k1 * NT + a];
+          else
+            val = Fl[(2 * p + k2) * NT + a] * Fl[(p + k1) * NT + a] * Fl[k0 * NT + a];
+          if (++k2 == p) {
+            k2 = 0;
+            if (++k1 == p) {
+              k1 = 0;
+              ++k0;
+            }
+          }
+        } else if (r < c) {
+          val = Sa[r - A.c0];
+        }
+        col[r] = val;
+      }
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int r = 0; r < CMAX; r += 2) {
+        s0 = fma(col[r], col[r], s0);
+        s1 = fma(col[r + 1], col[r + 1], s1);
+      }
+      nrm = sqrt(s0 + s1);
     } else {
 #pragma unroll
-      for (int u = 0; u < RPL; u++) col[u] = 0.0;
+      for (int r = 0; r < CMAX; r++) col[r] = 0.0;
     }
-    // pivoted QR
+    // Householder QR with column pivoting; rank by tol * |R_11|
     const int kmax = m < c ? m : c;
     int k = 0;
     double r00 = 0.0;
     for (int t = 0; t < kmax; t++) {
-      ArgMax am = (act && pos >= t) ? ArgMax{nrm, pos} : ArgMax{-1.0, -1};
+      ArgMax am = (act && pa >= t) ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
       am = block_argmax(am, ared);
       const double bn = am.v;
       if (t == 0) {
@@ -606,132 +547,65 @@ __global__ void __launch_bounds__(NT) k_compr_g4(IdArgs A, int ldr) {
       }
       const int bp = am.a;
       if (act) {
-        if (pos == t)
-          pos = bp;
-        else if (pos == bp)
-          pos = t;
+        if (pa == t)
+          pa = bp;
+        else if (pa == bp)
+          pa = t;
       }
-      g4_householder<RPL>(col, act, pos, sq, t, bn, v, &vn_lds, nrm, true);
+      if (act && pa == t) {
+        // the pivot column: v (rows t..), R_tt; every entry of v is written
+        double x0 = 0.0, rest = 0.0;
+#pragma unroll
+        for (int r = 0; r < CMAX; r++) {
+          x0 = r == t ? col[r] : x0;
+          const double y = r > t ? col[r] : 0.0;
+          rest = fma(y, y, rest);
+        }
+        const double rtt = x0 >= 0.0 ? -bn : bn;
+        const double v0 = x0 - rtt;
+#pragma unroll
+        for (int r = 0; r < CMAX; r++) {
+          v[r] = r == t ? v0 : (r > t ? col[r] : 0.0);
+          col[r] = r > t ? 0.0 : (r == t ? rtt : col[r]);
+        }
+        vn_lds = rest + v0 * v0;
+      }
+      __syncthreads();
+      const double vn = vn_lds;
+      if (act && pa > t && vn > 0.0) {
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+        for (int r = 0; r < CMAX; r += 4) {
+          w0 = fma(v[r], col[r], w0);
+          w1 = fma(v[r + 1], col[r + 1], w1);
+          w2 = fma(v[r + 2], col[r + 2], w2);
+          w3 = fma(v[r + 3], col[r + 3], w3);
+        }
+        const double sc = 2.0 * ((w0 + w1) + (w2 + w3)) / vn;
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int r = 0; r < CMAX; r += 2) {
+          const double y0 = fma(-sc, v[r], col[r]), y1 = fma(-sc, v[r + 1], col[r + 1]);
+          col[r] = y0;
+          col[r + 1] = y1;
+          const double z0 = r > t ? y0 : 0.0, z1 = r + 1 > t ? y1 : 0.0;
+          s0 = fma(z0, z0, s0);
+          s1 = fma(z1, z1, s1);
+        }
+        nrm = sqrt(s0 + s1);
+      }
+      __syncthreads();
       k = t + 1;
     }
-    // Gu-Eisenstat swaps
-    const int nr = m - k;
-    int nsw = 0;
-    bool failed = false;
-    if (k > 0 && nr > 0) {
-      for (;;) {
-        __syncthreads();
-        if (act && pos < k) {
+    // the factor in position order to the tile, then the common tail
+    if (act) {
 #pragma unroll
-          for (int u = 0; u < RPL; u++)
-            if (r0 + u <= pos) R11[pos * ldr + r0 + u] = col[u];
-        }
-        __syncthreads();
-        double gam = 0.0;
-        if (act && pos >= k) {
-          double g2 = 0.0;
-#pragma unroll
-          for (int u = 0; u < RPL; u++) g2 = fma(r0 + u >= k ? col[u] : 0.0, col[u], g2);
-          gam = sqrt(group_sum<RPL>(g2));
-          // N = R11^{-1} R12 in place, column-oriented back substitution
-#pragma unroll 1
-          for (int q = k - 1; q >= 0; q--) {
-            const int own = q / RPL, uq = q - own * RPL;
-            double cq = 0.0;
-#pragma unroll
-            for (int u = 0; u < RPL; u++) cq = u == uq ? col[u] : cq;
-            const double nq = __shfl(cq / R11[q * ldr + q], gl0 + own, WAVE);
-#pragma unroll
-            for (int u = 0; u < RPL; u++) {
-              const int r = r0 + u;
-              col[u] = r < q ? fma(-R11[q * ldr + r], nq, col[u]) : (r == q ? nq : col[u]);
-            }
-          }
-        } else if (act && pos < k) {
-          // row pos of R11^{-1}: forward solve R11^T y = e_pos, y in col
-#pragma unroll
-          for (int u = 0; u < RPL; u++) col[u] = 0.0;
-          double s2 = 0.0;
-#pragma unroll 1
-          for (int q = pos; q < k; q++) {
-            double part = 0.0;
-#pragma unroll
-            for (int u = 0; u < RPL; u++)
-              part = fma(r0 + u < q ? R11[q * ldr + r0 + u] : 0.0, col[u], part);
-            part = group_sum<RPL>(part);
-            const double y = ((q == pos ? 1.0 : 0.0) - part) / R11[q * ldr + q];
-#pragma unroll
-            for (int u = 0; u < RPL; u++) col[u] = r0 + u == q ? y : col[u];
-            s2 = fma(y, y, s2);
-          }
-          if (sq == 0) rinv[pos] = sqrt(s2);
-        }
-        __syncthreads();
-        ArgMax am{-1.0, -1};
-        if (act && pos >= k) {
-          const int j = pos - k;
-#pragma unroll
-          for (int u = 0; u < RPL; u++) {
-            const int ii = r0 + u;
-            if (ii < k) {
-              const double nv = col[u], bb = gam * rinv[ii];
-              am = amax_pick(am, ArgMax{sqrt(nv * nv + bb * bb), j * k + ii});
-            }
-          }
-        }
-        am = block_argmax(am, ared);
-        if (!(am.v > A.f)) break;
-        if (++nsw > 64 * k) {
-          failed = true;
-          break;
-        }
-        const int bj = am.a / k, bi = am.a % k;
-        if (act) {
-          if (pos == bi)
-            pos = k + bj;
-          else if (pos == k + bj)
-            pos = bi;
-        }
-        // refactor in the new column order without pivoting
-        __syncthreads();
-        if (act && sq == 0) g4_factors(A, i, a, a, F, NG, xi, wk);
-        __syncthreads();
-        if (act) g4_basis<RPL>(A, i, a, sq, ks, c, col, F, NG, a);
-        for (int t = 0; t < k; t++) {
-          double part = 0.0;
-#pragma unroll
-          for (int u = 0; u < RPL; u++) part = fma(r0 + u >= t ? col[u] : 0.0, col[u], part);
-          const double alpha = sqrt(group_sum<RPL>(part));
-          g4_householder<RPL>(col, act, pos, sq, t, alpha, v, &vn_lds, nrm, false);
-        }
-      }
+      for (int r = 0; r < CMAX; r++)
+        if (r < c) W[(int64_t)r * ldw + pa] = col[r];
+      perm[pa] = a;
     }
-    if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
-    if (failed) {
-      if (tid == 0) atomicOr(A.err, 1);
-      k = 0;
-    }
-    // canonical output: skeleton positions ascending, then the rest
-    const bool sk = act && pos < k;
-    int64_t tot;
-    int64_t skr = block_excl_scan_i64((sk && sq == 0) ? 1 : 0, &tot, sred);
-    skr = __shfl(skr, gl0, WAVE);
-    int *sel = A.sel_out + A.selo[i];
-    if (act && sq == 0) {
-      if (sk)
-        sel[skr] = a;
-      else
-        sel[k + (a - skr)] = a;
-    }
-    if (sk && sq == 0) skr_by_pos[pos] = (int)skr;
     __syncthreads();
-    if (act && !sk && k > 0) {
-      double *G = A.G_out + A.go[i] + (int64_t)(a - skr) * k;
-#pragma unroll
-      for (int u = 0; u < RPL; u++)
-        if (r0 + u < k) G[skr_by_pos[r0 + u]] = col[u];
-    }
-    if (tid == 0) A.k_out[i] = k;
+    compr_tail(A, i, m, c, ks, k, W, F, Nrm, Ri, perm, pos, ldw, xi, wk, v, rinv, red, ared, sred);
   }
 }
 
@@ -1169,7 +1043,14 @@ void build_generators(Handle &h) {
         int cmax = c0 + (hss ? sc.mmax : 0);
         if (cmax > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
         int ldw = (sc.mmax + 1) | 1;  // odd stride
-        int nwg = nl < 2 * dev_cus ? nl : 2 * dev_cus;
+        // register-resident QR when the grid fits one workgroup (a lane per
+        // grid point) and the basis width fits CMAX; otherwise the tile form
+        const int nt = sc.mmax <= 64 ? 64 : sc.mmax <= 128 ? 128 : sc.mmax <= 256 ? 256 : 0;
+        const int cm = cmax <= 32 ? 32 : cmax <= 64 ? 64 : 0;
+        const size_t sh = sizeof(double) * (size_t)h.d * h.p * (nt > 0 ? nt : 1);
+        const bool reg = nt > 0 && cm > 0 && h.d * h.p <= nt && sh <= 64 * 1024;
+        const int wcap = reg ? 8 * dev_cus : 2 * dev_cus;
+        const int nwg = !h.batched ? 1 : nl < wcap ? nl : wcap;
         int64_t wg_stride = (int64_t)cmax * ldw + (int64_t)h.d * h.p * ldw + ldw +
                             (int64_t)cmax * cmax + 8;
         double *scr = tmp.alloc_n<double>((size_t)wg_stride * nwg);
@@ -1178,35 +1059,24 @@ void build_generators(Handle &h) {
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1};
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
-        // register-resident form when the grid fits one workgroup (4 lanes
-        // per grid point) and the basis width fits 4*RPL
-        const int nt = sc.mmax <= 64 ? 256 : sc.mmax <= 128 ? 512 : sc.mmax <= 256 ? 1024 : 0;
-        const int rpl = cmax <= 32 ? 8 : cmax <= 64 ? 16 : cmax <= 128 ? 32 : 0;
-        const int kcap = (cmax < sc.mmax ? cmax : sc.mmax);
-        const int ldr = kcap > 0 ? kcap : 1;
-        const size_t sh = sizeof(double) * (size_t)std::max(h.d * h.p * (nt / 4), ldr * ldr);
-        const bool reg = nt > 0 && rpl > 0 && !(rpl == 32 && nt == 1024) && sh <= 96 * 1024;
         auto launch = [&](int grid) {
           if (!reg) {
             k_compr<<<grid, ID_NT, 0, s>>>(ia);
           } else {
-#define SMASH_G4_CASE(RP, NTV)                                                   \
-  if (rpl == RP && nt == NTV) k_compr_g4<RP, NTV><<<grid, NTV, sh, s>>>(ia, ldr);
-            SMASH_G4_CASE(8, 256)
-            SMASH_G4_CASE(8, 512)
-            SMASH_G4_CASE(8, 1024)
-            SMASH_G4_CASE(16, 256)
-            SMASH_G4_CASE(16, 512)
-            SMASH_G4_CASE(16, 1024)
-            SMASH_G4_CASE(32, 256)
-            SMASH_G4_CASE(32, 512)
-#undef SMASH_G4_CASE
+#define SMASH_W_CASE(CM, NTV)                                                    \
+  if (cm == CM && nt == NTV) k_compr_w<CM, NTV><<<grid, NTV, sh, s>>>(ia);
+            SMASH_W_CASE(32, 64)
+            SMASH_W_CASE(32, 128)
+            SMASH_W_CASE(32, 256)
+            SMASH_W_CASE(64, 64)
+            SMASH_W_CASE(64, 128)
+            SMASH_W_CASE(64, 256)
+#undef SMASH_W_CASE
           }
           SMASH_CHECK_LAUNCH();
         };
         if (h.batched) {
-          int g = reg ? (nl < 8 * dev_cus ? nl : 8 * dev_cus) : nwg;
-          launch(g);
+          launch(nwg);
         } else {
           for (int i = nb; i < ne; i++) {
             ia.nb = i;

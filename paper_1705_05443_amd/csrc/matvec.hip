@@ -134,15 +134,40 @@ struct CouplingArgs {
   const void *B;
 };
 
+// Sum of the MV_WAVES partial accumulator tiles of a workgroup into wave 0
+// (LDS, one slot per wave, tile, result and lane).
+constexpr int MV_WAVES = 4;
+
 template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_coupling(CouplingArgs A, const T *__restrict__ qh,
-                                                       T *__restrict__ zh, int RP) {
+__device__ __forceinline__ void reduce_waves(typename Mfma<T>::acc_t (&acc)[MV_TILES], T *red) {
+  const int w = threadIdx.x / MV_NT, l = threadIdx.x & (MV_NT - 1);
+  __syncthreads();
+  if (w > 0)
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) red[(((w - 1) * MV_TILES + tt) * 4 + e) * MV_NT + l] = acc[tt][e];
+  __syncthreads();
+  if (w == 0)
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        for (int v = 0; v < MV_WAVES - 1; v++) acc[tt][e] += red[((v * MV_TILES + tt) * 4 + e) * MV_NT + l];
+}
+
+template <class T>
+__global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
+                                                                 const T *__restrict__ qh,
+                                                                 T *__restrict__ zh, int RP) {
   typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T red[(MV_WAVES - 1) * MV_TILES * 4 * MV_NT];
   const int i = A.i0 + blockIdx.x;
   if (i >= A.nnodes) return;
   const int ki = A.krow[i];
   if (ki == 0) return;
-  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
   const int col = blockIdx.y * 16 + lr;
   T *out = zh + A.hrow[i] * RP;
   const T *Bv = (const T *)A.B;
@@ -151,7 +176,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_coupling(CouplingArgs A, const T *
     acc_t acc[MV_TILES];
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-    for (int p = p0; p < p1; p++) {
+    for (int p = p0 + w; p < p1; p += MV_WAVES) {
       const int j = A.Lj[p];
       const int kj = A.kcol[j];
       const T *Bp = Bv + A.boff[p];
@@ -177,13 +202,15 @@ __global__ void __launch_bounds__(MV_NT) k_mv_coupling(CouplingArgs A, const T *
           for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
       }
     }
+    reduce_waves<T>(acc, red);
+    if (w == 0)
 #pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++)
+      for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
-        if (t < ki) out[(int64_t)t * RP + col] = acc[tt][e];
-      }
+        for (int e = 0; e < 4; e++) {
+          const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
+          if (t < ki) out[(int64_t)t * RP + col] = acc[tt][e];
+        }
   }
 }
 
@@ -263,14 +290,18 @@ struct NearArgs {
 };
 
 template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_near_out(NearArgs A, const T *__restrict__ q,
-                                                       const T *__restrict__ z, T *__restrict__ Y,
-                                                       int64_t ldy, int R, int RP) {
+__global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_near_out(NearArgs A,
+                                                                 const T *__restrict__ q,
+                                                                 const T *__restrict__ z,
+                                                                 T *__restrict__ Y, int64_t ldy,
+                                                                 int R, int RP) {
   typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T red[(MV_WAVES - 1) * MV_TILES * 4 * MV_NT];
   const int i = A.i0 + blockIdx.x;
   if (i >= A.nnodes || A.nchild[i] != 0) return;
   const int xb = A.xb[i], ni = A.xe[i] - xb;
-  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
   const int col = blockIdx.y * 16 + lr;
   const T *Bv = (const T *)A.Bn;
   const int p0 = A.Lmrow[i], p1 = A.Lmrow[i + 1];
@@ -278,7 +309,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_near_out(NearArgs A, const T *__re
     acc_t acc[MV_TILES];
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-    for (int p = p0; p < p1; p++) {
+    for (int p = p0 + w; p < p1; p += MV_WAVES) {
       const int j = A.Lmj[p];
       const int yb = A.yb[j], nj = A.ye[j] - yb;
       const T *Bp = Bv + A.nboff[p];
@@ -302,6 +333,8 @@ __global__ void __launch_bounds__(MV_NT) k_mv_near_out(NearArgs A, const T *__re
           for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
       }
     }
+    reduce_waves<T>(acc, red);
+    if (w == 0)
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
@@ -355,12 +388,12 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
     {
       PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
       if (h.batched) {
-        k_mv_coupling<T><<<dim3(h.nnodes - 1, ct), MV_NT, 0, s>>>(ca, q, z, RP);
+        k_mv_coupling<T><<<dim3(h.nnodes - 1, ct), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP);
         SMASH_CHECK_LAUNCH();
       } else {
         for (int i = 1; i < h.nnodes; i++) {
           ca.i0 = i;
-          k_mv_coupling<T><<<dim3(1, ct), MV_NT, 0, s>>>(ca, q, z, RP);
+          k_mv_coupling<T><<<dim3(1, ct), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP);
           SMASH_CHECK_LAUNCH();
         }
       }
@@ -390,12 +423,12 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
   {
     PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
     if (h.batched) {
-      k_mv_near_out<T><<<dim3(h.nnodes, ct), MV_NT, 0, s>>>(na, q, z, Y, ldy, R, RP);
+      k_mv_near_out<T><<<dim3(h.nnodes, ct), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP);
       SMASH_CHECK_LAUNCH();
     } else {
       for (int i = 0; i < h.nnodes; i++) {
         na.i0 = i;
-        k_mv_near_out<T><<<dim3(1, ct), MV_NT, 0, s>>>(na, q, z, Y, ldy, R, RP);
+        k_mv_near_out<T><<<dim3(1, ct), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP);
         SMASH_CHECK_LAUNCH();
       }
     }
