@@ -416,22 +416,36 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
 }
 
 // ------------------------------------------------------------------------
-// Register-resident pivoted QR: the same algorithm as k_compr for nodes
-// whose grid fits one workgroup (m <= NT) and whose basis width fits CMAX.
-// Lane a holds grid column a of M = C^T in registers (col[r], r < CMAX,
-// zero past c), so each Householder step costs one block arg-max, one LDS
-// broadcast of v and a register update.  A column's "position" (the order
-// the pivoted QR works in) is a lane label: a pivot swap relabels two lanes
-// instead of moving data, so ties still go to the lowest current position.
-// After the QR the factor is written to the workgroup tile in position
-// order and compr_tail finishes (swap test, rare swaps, output).
+// Register-resident compr for nodes whose grid fits one workgroup (m <= NT)
+// and whose basis width fits CMAX (CMAX <= NT).  Lane a holds grid column a
+// of M = C^T in registers (col[r], r < CMAX, zero past c) for the whole
+// algorithm, so
+//   * a Householder step is one block arg-max, one LDS broadcast of v and a
+//     register update of every remaining column;
+//   * a column's position (the order the QR works in) is a lane label: a
+//     pivot or a Gu-Eisenstat swap relabels two lanes instead of moving
+//     data, and ties still go to the lowest current position;
+//   * the swap test solves R11 in place in every lane at once: the lane at
+//     position j < k solves R11 x = e_j (a column of R11^-1, for the row
+//     norms 1/omega_i), a lane at position >= k solves R11 n = R12 e_j (a
+//     column of N), by back substitution against R11 held in LDS, padded
+//     to [R11 0; 0 I] so that the unrolled loops need no bounds;
+//   * grid order is lane order, so the canonical output (skeleton indices
+//     ascending, then the rest) is one block scan of the skeleton flags.
+// A swap relabels, rebuilds the columns from the basis and refactors the
+// first k positions without pivoting, as k_compr does.
 // ------------------------------------------------------------------------
 template <int CMAX, int NT>
 __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
-  extern __shared__ double Fl[];  // one-dimensional factors [t*p + q][NT]
+  // dynamic LDS: the one-dimensional basis factors [d*p][NT] while the basis
+  // is built, then R11 padded [CMAX][CMAX] and R11^-1 [CMAX][CMAX]
+  extern __shared__ double dyn[];
+  double *const Fl = dyn;
+  double *const Rs = dyn;
+  double *const Ris = dyn + CMAX * CMAX;
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
-  __shared__ double v[ID_CMAX + 1], rinv[ID_CMAX];
-  __shared__ double red[NT / WAVE + 1];
+  __shared__ double v[CMAX], rinv[CMAX];
+  __shared__ int srank[CMAX];
   __shared__ ArgMax ared[NT / WAVE + 1];
   __shared__ int64_t sred[NT / WAVE + 1];
   __shared__ double vn_lds;
@@ -442,17 +456,10 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
     chc[a] = cos(th);
     wk[a] = ((a & 1) ? -1.0 : 1.0) * sin(th);
   }
-  double *W = A.scratch + (int64_t)blockIdx.x * A.wg_stride;
-  const int ldw = A.ldw;
-  int *perm = A.iscratch + (int64_t)blockIdx.x * A.wg_istride;
-  int *pos = perm + ldw;
   for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
     const int m = A.m[i];
     const int ks = A.S ? A.ks[i] : 0;
     const int c = A.c0 + ks;
-    double *F = W + (int64_t)c * ldw;
-    double *Nrm = F + (int64_t)d * p * ldw;
-    double *Ri = Nrm + ldw;
     __syncthreads();
     if (a < d * p) {
       int t = a / p, q = a % p;
@@ -468,144 +475,244 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
     int pa = a;  // current position of this lane's column
     double col[CMAX];
     double nrm = -1.0;
-    // basis column: one-dimensional factors in LDS, then tensor products
-    if (act) {
-      const int64_t id = A.slot_id[A.gbeg[i] + a];
-      for (int t = 0; t < d; t++) {
-        const double x = A.P[id * d + t];
-        const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
-        double *Ft = Fl + (t * p) * NT + a;
-        if (hi - lo == 0.0) {
-          for (int q = 0; q < p; q++) Ft[q * NT] = q == 0 ? 1.0 : 0.0;
-          continue;
-        }
-        int hit = -1;
-        double den = 0.0;
-        for (int q = 0; q < p; q++) {
-          const double xq = xi[t * ID_PMAX + q];
-          if (x == xq) {
-            hit = q;
-            break;
-          }
-          const double w = wk[q] / (x - xq);
-          Ft[q * NT] = w;
-          den += w;
-        }
-        if (hit >= 0)
-          for (int q = 0; q < p; q++) Ft[q * NT] = q == hit ? 1.0 : 0.0;
-        else
-          for (int q = 0; q < p; q++) Ft[q * NT] = Ft[q * NT] / den;
-      }
-      int k0 = 0, k1 = 0, k2 = 0;
-      const double *Sa = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
-#pragma unroll
-      for (int r = 0; r < CMAX; r++) {
-        double val = 0.0;
-        if (r < A.c0) {
-          if (d == 1)
-            val = Fl[k2 * NT + a];
-          else if (d == 2)
-            val = Fl[(p + k2) * NT + a] * Fl[k1 * NT + a];
-          else
-            val = Fl[(2 * p + k2) * NT + a] * Fl[(p + k1) * NT + a] * Fl[k0 * NT + a];
-          if (++k2 == p) {
-            k2 = 0;
-            if (++k1 == p) {
-              k1 = 0;
-              ++k0;
-            }
-          }
-        } else if (r < c) {
-          val = Sa[r - A.c0];
-        }
-        col[r] = val;
-      }
-      double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-      for (int r = 0; r < CMAX; r += 2) {
-        s0 = fma(col[r], col[r], s0);
-        s1 = fma(col[r + 1], col[r + 1], s1);
-      }
-      nrm = sqrt(s0 + s1);
-    } else {
-#pragma unroll
-      for (int r = 0; r < CMAX; r++) col[r] = 0.0;
-    }
-    // Householder QR with column pivoting; rank by tol * |R_11|
-    const int kmax = m < c ? m : c;
-    int k = 0;
-    double r00 = 0.0;
-    for (int t = 0; t < kmax; t++) {
-      ArgMax am = (act && pa >= t) ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
-      am = block_argmax(am, ared);
-      const double bn = am.v;
-      if (t == 0) {
-        r00 = bn;
-        if (!(r00 > 0.0)) break;
-      } else if (!(bn > A.tol * r00)) {
-        break;
-      }
-      const int bp = am.a;
+
+    // column a of C^T from the basis (barycentric tensor Lagrange values,
+    // then the near-field vector entries), and its norm
+    auto build_column = [&]() {
       if (act) {
-        if (pa == t)
-          pa = bp;
-        else if (pa == bp)
-          pa = t;
-      }
-      if (act && pa == t) {
-        // the pivot column: v (rows t..), R_tt; every entry of v is written
-        double x0 = 0.0, rest = 0.0;
+        const int64_t id = A.slot_id[A.gbeg[i] + a];
+        for (int t = 0; t < d; t++) {
+          const double x = A.P[id * d + t];
+          const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+          double *Ft = Fl + (t * p) * NT + a;
+          if (hi - lo == 0.0) {
+            for (int q = 0; q < p; q++) Ft[q * NT] = q == 0 ? 1.0 : 0.0;
+            continue;
+          }
+          int hit = -1;
+          double den = 0.0;
+          for (int q = 0; q < p; q++) {
+            const double xq = xi[t * ID_PMAX + q];
+            if (x == xq) {
+              hit = q;
+              break;
+            }
+            const double w = wk[q] / (x - xq);
+            Ft[q * NT] = w;
+            den += w;
+          }
+          if (hit >= 0)
+            for (int q = 0; q < p; q++) Ft[q * NT] = q == hit ? 1.0 : 0.0;
+          else
+            for (int q = 0; q < p; q++) Ft[q * NT] = Ft[q * NT] / den;
+        }
+        int k0 = 0, k1 = 0, k2 = 0;
+        const double *Sa = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
 #pragma unroll
         for (int r = 0; r < CMAX; r++) {
-          x0 = r == t ? col[r] : x0;
-          const double y = r > t ? col[r] : 0.0;
-          rest = fma(y, y, rest);
+          double val = 0.0;
+          if (r < A.c0) {
+            if (d == 1)
+              val = Fl[k2 * NT + a];
+            else if (d == 2)
+              val = Fl[(p + k2) * NT + a] * Fl[k1 * NT + a];
+            else
+              val = Fl[(2 * p + k2) * NT + a] * Fl[(p + k1) * NT + a] * Fl[k0 * NT + a];
+            if (++k2 == p) {
+              k2 = 0;
+              if (++k1 == p) {
+                k1 = 0;
+                ++k0;
+              }
+            }
+          } else if (r < c) {
+            val = Sa[r - A.c0];
+          }
+          col[r] = val;
         }
-        const double rtt = x0 >= 0.0 ? -bn : bn;
-        const double v0 = x0 - rtt;
-#pragma unroll
-        for (int r = 0; r < CMAX; r++) {
-          v[r] = r == t ? v0 : (r > t ? col[r] : 0.0);
-          col[r] = r > t ? 0.0 : (r == t ? rtt : col[r]);
-        }
-        vn_lds = rest + v0 * v0;
-      }
-      __syncthreads();
-      const double vn = vn_lds;
-      if (act && pa > t && vn > 0.0) {
-        double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-#pragma unroll
-        for (int r = 0; r < CMAX; r += 4) {
-          w0 = fma(v[r], col[r], w0);
-          w1 = fma(v[r + 1], col[r + 1], w1);
-          w2 = fma(v[r + 2], col[r + 2], w2);
-          w3 = fma(v[r + 3], col[r + 3], w3);
-        }
-        const double sc = 2.0 * ((w0 + w1) + (w2 + w3)) / vn;
         double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int r = 0; r < CMAX; r += 2) {
-          const double y0 = fma(-sc, v[r], col[r]), y1 = fma(-sc, v[r + 1], col[r + 1]);
-          col[r] = y0;
-          col[r + 1] = y1;
-          const double z0 = r > t ? y0 : 0.0, z1 = r + 1 > t ? y1 : 0.0;
-          s0 = fma(z0, z0, s0);
-          s1 = fma(z1, z1, s1);
+          s0 = fma(col[r], col[r], s0);
+          s1 = fma(col[r + 1], col[r + 1], s1);
         }
         nrm = sqrt(s0 + s1);
+      } else {
+#pragma unroll
+        for (int r = 0; r < CMAX; r++) col[r] = 0.0;
+      }
+    };
+
+    // Householder QR over positions 0..kend-1: with pivoting the pivot of
+    // step t is the largest remaining norm and the loop stops at the rank
+    // test (|R_tt| <= tol * |R_00|); without, the pivot is position t.
+    auto householder_qr = [&](bool pivoting, int kend) -> int {
+      int kk = 0;
+      double r00 = 0.0;
+      for (int t = 0; t < kend; t++) {
+        const bool cand = act && (pivoting ? pa >= t : pa == t);
+        ArgMax am = cand ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
+        am = block_argmax(am, ared);
+        const double bn = am.v;
+        if (pivoting) {
+          if (t == 0) {
+            r00 = bn;
+            if (!(r00 > 0.0)) break;
+          } else if (!(bn > A.tol * r00)) {
+            break;
+          }
+        }
+        const int bp = am.a;
+        if (act) {
+          if (pa == t)
+            pa = bp;
+          else if (pa == bp)
+            pa = t;
+        }
+        if (act && pa == t) {
+          // the pivot column: v (rows t..), R_tt; every entry of v is written
+          double x0 = 0.0, rest = 0.0;
+#pragma unroll
+          for (int r = 0; r < CMAX; r++) {
+            x0 = r == t ? col[r] : x0;
+            const double y = r > t ? col[r] : 0.0;
+            rest = fma(y, y, rest);
+          }
+          const double rtt = x0 >= 0.0 ? -bn : bn;
+          const double v0 = x0 - rtt;
+#pragma unroll
+          for (int r = 0; r < CMAX; r++) {
+            v[r] = r == t ? v0 : (r > t ? col[r] : 0.0);
+            col[r] = r > t ? 0.0 : (r == t ? rtt : col[r]);
+          }
+          vn_lds = rest + v0 * v0;
+        }
+        __syncthreads();
+        const double vn = vn_lds;
+        if (act && pa > t && vn > 0.0) {
+          double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+          for (int r = 0; r < CMAX; r += 4) {
+            w0 = fma(v[r], col[r], w0);
+            w1 = fma(v[r + 1], col[r + 1], w1);
+            w2 = fma(v[r + 2], col[r + 2], w2);
+            w3 = fma(v[r + 3], col[r + 3], w3);
+          }
+          const double sc = 2.0 * ((w0 + w1) + (w2 + w3)) / vn;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int r = 0; r < CMAX; r += 2) {
+            const double y0 = fma(-sc, v[r], col[r]), y1 = fma(-sc, v[r + 1], col[r + 1]);
+            col[r] = y0;
+            col[r + 1] = y1;
+            const double z0 = r > t ? y0 : 0.0, z1 = r + 1 > t ? y1 : 0.0;
+            s0 = fma(z0, z0, s0);
+            s1 = fma(z1, z1, s1);
+          }
+          nrm = sqrt(s0 + s1);
+        }
+        __syncthreads();
+        kk = t + 1;
+      }
+      return kk;
+    };
+
+    build_column();
+    int k = householder_qr(true, m < c ? m : c);
+    const int nr = m - k;
+    int nsw = 0;
+    bool failed = false;
+    int64_t ex = 0;
+    for (;;) {
+      // skeleton ranks: grid order is lane order
+      const int fl = (act && pa < k) ? 1 : 0;
+      int64_t tot;
+      ex = block_excl_scan_i64(fl, &tot, sred);
+      if (fl) srank[pa] = (int)ex;
+      if (k == 0 || nr == 0) break;
+      // R11 padded to [R11 0; 0 I]: every position < CMAX has one lane
+      if (pa < CMAX) {
+#pragma unroll
+        for (int r = 0; r < CMAX; r++)
+          Rs[r * CMAX + pa] = pa < k ? (r <= pa ? col[r] : 0.0) : (r == pa ? 1.0 : 0.0);
       }
       __syncthreads();
-      k = t + 1;
-    }
-    // the factor in position order to the tile, then the common tail
-    if (act) {
+      // right-hand side e_j at positions j < k; R12 columns stay in place
+      if (pa < k) {
 #pragma unroll
-      for (int r = 0; r < CMAX; r++)
-        if (r < c) W[(int64_t)r * ldw + pa] = col[r];
-      perm[pa] = a;
+        for (int r = 0; r < CMAX; r++) col[r] = r == pa ? 1.0 : 0.0;
+      }
+      // back substitution in every lane (rows >= k: identity, no change)
+#pragma unroll
+      for (int ii = CMAX - 1; ii >= 0; ii--) {
+        double s = col[ii];
+#pragma unroll
+        for (int q = ii + 1; q < CMAX; q++) s = fma(-Rs[ii * CMAX + q], col[q], s);
+        col[ii] = s / Rs[ii * CMAX + ii];
+      }
+      if (pa < k) {
+#pragma unroll
+        for (int r = 0; r < CMAX; r++) Ris[r * CMAX + pa] = col[r];
+      }
+      __syncthreads();
+      // row norms of R11^-1
+      if (a < k) {
+        double sq = 0.0;
+        for (int j = 0; j < k; j++) {
+          const double y = Ris[a * CMAX + j];
+          sq = fma(y, y, sq);
+        }
+        rinv[a] = sqrt(sq);
+      }
+      __syncthreads();
+      // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
+      // smallest j, then smallest i (pair index j*k + i).  G rows are
+      // written on every pass; the last pass leaves the final ones.
+      ArgMax am{-1.0, -1};
+      if (act && pa >= k) {
+        double *Gr = A.G_out + A.go[i] + (int64_t)(a - ex) * k;
+        const int base = (pa - k) * k;
+#pragma unroll
+        for (int ii = 0; ii < CMAX; ii++) {
+          if (ii < k) {
+            const double gw = nrm * rinv[ii];
+            const double rho = sqrt(col[ii] * col[ii] + gw * gw);
+            am = amax_pick(am, ArgMax{rho, base + ii});
+            Gr[srank[ii]] = col[ii];
+          }
+        }
+      }
+      am = block_argmax(am, ared);
+      if (!(am.v > A.f)) break;
+      if (++nsw > 64 * k) {
+        failed = true;
+        break;
+      }
+      const int bj = am.a / k, bi = am.a % k;
+      if (pa == bi)
+        pa = k + bj;
+      else if (pa == k + bj)
+        pa = bi;
+      __syncthreads();  // R11 / R11^-1 reads done before the factors reuse LDS
+      build_column();
+      householder_qr(false, k);
     }
-    __syncthreads();
-    compr_tail(A, i, m, c, ks, k, W, F, Nrm, Ri, perm, pos, ldw, xi, wk, v, rinv, red, ared, sred);
+    if (a == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+    if (failed) {
+      if (a == 0) atomicOr(A.err, 1);
+      k = 0;
+      ex = 0;
+    }
+    // canonical output: skeleton indices ascending, then the rest
+    if (act) {
+      int *sel = A.sel_out + A.selo[i];
+      const bool sk = !failed && pa < k;
+      if (sk)
+        sel[ex] = a;
+      else
+        sel[k + (a - ex)] = a;
+    }
+    if (a == 0) A.k_out[i] = k;
   }
 }
 
@@ -953,11 +1060,13 @@ void build_generators(Handle &h) {
     int *dmax = tmp.alloc_n<int>(2);
     int *dsw = tmp.alloc_n<int>(2);
     SMASH_HIP(hipMemsetAsync(dsw, 0, 2 * sizeof(int), s));
-    int dev_cus = 256;
-    {
-      hipDeviceProp_t prop;
-      if (hipGetDeviceProperties(&prop, h.device) == hipSuccess) dev_cus = prop.multiProcessorCount;
-    }
+    int dev_cus = 256, dev_lds = 64 * 1024;
+    if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, h.device) !=
+        hipSuccess)
+      dev_cus = 256;
+    if (hipDeviceGetAttribute(&dev_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h.device) !=
+        hipSuccess)
+      dev_lds = 64 * 1024;
     for (int l = h.nlevels; l >= 2; l--) {
       const int nb = h.level_beg[l - 1], ne = h.level_beg[l], nl = ne - nb;
       // (a) grids and capacities of both sides
@@ -1047,8 +1156,11 @@ void build_generators(Handle &h) {
         // grid point) and the basis width fits CMAX; otherwise the tile form
         const int nt = sc.mmax <= 64 ? 64 : sc.mmax <= 128 ? 128 : sc.mmax <= 256 ? 256 : 0;
         const int cm = cmax <= 32 ? 32 : cmax <= 64 ? 64 : 0;
-        const size_t sh = sizeof(double) * (size_t)h.d * h.p * (nt > 0 ? nt : 1);
-        const bool reg = nt > 0 && cm > 0 && h.d * h.p <= nt && sh <= 64 * 1024;
+        const size_t sh = sizeof(double) * std::max((size_t)h.d * h.p * (nt > 0 ? nt : 1),
+                                                    (size_t)2 * cm * cm);
+        // (dynamic LDS plus at most 8 KB of static LDS within the device limit)
+        const bool reg = nt > 0 && cm > 0 && cm <= nt && h.d * h.p <= nt && sh <= 64 * 1024 &&
+                         sh + 8 * 1024 <= (size_t)dev_lds;
         const int wcap = reg ? 8 * dev_cus : 2 * dev_cus;
         const int nwg = !h.batched ? 1 : nl < wcap ? nl : wcap;
         int64_t wg_stride = (int64_t)cmax * ldw + (int64_t)h.d * h.p * ldw + ldw +
