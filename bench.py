@@ -54,6 +54,9 @@ def main():
                     help="target seconds of oracle work for cpu_baseline (0: skip)")
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="steps of the plain per-node form timed for comparison (0: skip)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="only run a plain device copy of this many MiB five times (the "
+                         "calibration kernel for the HBM byte counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -61,6 +64,16 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.copy_mib > 0:
+        a = torch.empty(args.copy_mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 8, "copy_bytes_written": b.numel() * 8,
+                          "launches": 5}), flush=True)
+        return
 
     from paper_1705_05443_amd import api
     from paper_1705_05443_amd import workloads as W

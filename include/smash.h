@@ -71,6 +71,10 @@ typedef struct smash_handle_s *smash_handle;
  *                0: one launch per node (the plain per-node form)
  *   timing       1: bracket every phase's launches with HIP events on the
  *                stream they run on; smash_info reports the summed times
+ *   mv_split_nodes  launch shape of the product sweeps: a tree level with at
+ *                most this many nodes runs each node on four wavefronts
+ *                (long grids, few nodes), a larger one on one wavefront per
+ *                node; default 1024, 0 never splits
  */
 typedef struct smash_options {
   uint32_t struct_size; /* sizeof(smash_options) */
@@ -86,6 +90,7 @@ typedef struct smash_options {
   int32_t max_depth;
   int32_t batched;
   int32_t timing;
+  int32_t mv_split_nodes;
 } smash_options;
 
 int smash_default_options(smash_options *opt);

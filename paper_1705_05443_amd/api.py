@@ -36,7 +36,8 @@ class Options(C.Structure):
                 ("srrqr_f", C.c_double), ("diag_value", C.c_double), ("eval_prec", C.c_int32),
                 ("apply_prec", C.c_int32), ("has_root_box", C.c_int32),
                 ("root_lo", C.c_double * 3), ("root_side", C.c_double), ("max_depth", C.c_int32),
-                ("batched", C.c_int32), ("timing", C.c_int32)]
+                ("batched", C.c_int32), ("timing", C.c_int32),
+                ("mv_split_nodes", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -104,7 +105,8 @@ class Smash:
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
-                 root=None, max_depth=0, batched=True, timing=False, stream=None):
+                 root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
+                 stream=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -134,6 +136,8 @@ class Smash:
         opt.max_depth = max_depth
         opt.batched = 1 if batched else 0
         opt.timing = 1 if timing else 0
+        if mv_split_nodes is not None:
+            opt.mv_split_nodes = int(mv_split_nodes)
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
         self.ny = x.shape[0] if y is None else y.shape[0]

@@ -26,6 +26,7 @@ namespace smash {
 
 constexpr int MV_NT = 64;
 constexpr int MV_TILES = 4;  // 16-row tiles per pass (64 rows)
+constexpr int MV_WAVES = 4;  // wavefronts per node in the coupling and near products
 
 template <class T>
 struct Mfma;
@@ -67,19 +68,41 @@ struct SweepArgs {
   const void *Gt;  // k x (m-k) row-major: as A = G it is column-major (m-k) x k
 };
 
+// Sum of the W partial accumulator tiles of a workgroup into wave 0 (LDS,
+// one slot per wave, tile, result and lane).
+template <class T, int W>
+__device__ __forceinline__ void reduce_waves(typename Mfma<T>::acc_t (&acc)[MV_TILES], T *red) {
+  const int w = threadIdx.x / MV_NT, l = threadIdx.x & (MV_NT - 1);
+  __syncthreads();
+  if (w > 0)
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) red[(((w - 1) * MV_TILES + tt) * 4 + e) * MV_NT + l] = acc[tt][e];
+  __syncthreads();
+  if (w == 0)
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        for (int v = 0; v < W - 1; v++) acc[tt][e] += red[((v * MV_TILES + tt) * 4 + e) * MV_NT + l];
+}
+
 // ---- upward pass: q-hat_i = q|_hat + H^T q|_check ------------------------
 // A[t][a] = H[a][t] at H[a*k + t] (column-major in t); Bv row a = grid row
 // sel[k+a].  Grid rows and output rows are disjoint slot ranges of one
 // buffer, passed as separate read and write views.
-template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, const T *__restrict__ qin,
-                                                 T *__restrict__ qout, int RP) {
+template <class T, int W>
+__global__ void __launch_bounds__(MV_NT *W) k_mv_up(SweepArgs A, const T *__restrict__ qin,
+                                                    T *__restrict__ qout, int RP) {
   typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T red[(W > 1 ? W - 1 : 1) * MV_TILES * 4 * MV_NT];
   const int i = A.nb + blockIdx.x;
   if (i >= A.ne) return;
   const int m = A.m[i], k = A.k[i];
   if (k == 0) return;
-  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
   const int col = blockIdx.y * 16 + lr;
   const T *g = qin + A.gbeg[i] * RP;
   T *out = qout + A.hbeg[i] * RP;
@@ -90,7 +113,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, const T *__restric
     acc_t acc[MV_TILES];
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
-    for (int a0 = 0; a0 < nr; a0 += 16) {
+    for (int a0 = 16 * w; a0 < nr; a0 += 16 * W) {
       int srow[4];
 #pragma unroll
       for (int u = 0; u < 4; u++) {
@@ -114,13 +137,15 @@ __global__ void __launch_bounds__(MV_NT) k_mv_up(SweepArgs A, const T *__restric
 #pragma unroll
         for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
     }
+    if (W > 1) reduce_waves<T, W>(acc, red);
+    if (w == 0)
 #pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++)
+      for (int tt = 0; tt < MV_TILES; tt++)
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
-        if (t < k) out[(int64_t)t * RP + col] = acc[tt][e] + g[(int64_t)sel[t] * RP + col];
-      }
+        for (int e = 0; e < 4; e++) {
+          const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
+          if (t < k) out[(int64_t)t * RP + col] = acc[tt][e] + g[(int64_t)sel[t] * RP + col];
+        }
   }
 }
 
@@ -133,28 +158,6 @@ struct CouplingArgs {
   const int64_t *hrow, *hcol;
   const void *B;
 };
-
-// Sum of the MV_WAVES partial accumulator tiles of a workgroup into wave 0
-// (LDS, one slot per wave, tile, result and lane).
-constexpr int MV_WAVES = 4;
-
-template <class T>
-__device__ __forceinline__ void reduce_waves(typename Mfma<T>::acc_t (&acc)[MV_TILES], T *red) {
-  const int w = threadIdx.x / MV_NT, l = threadIdx.x & (MV_NT - 1);
-  __syncthreads();
-  if (w > 0)
-#pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++)
-#pragma unroll
-      for (int e = 0; e < 4; e++) red[(((w - 1) * MV_TILES + tt) * 4 + e) * MV_NT + l] = acc[tt][e];
-  __syncthreads();
-  if (w == 0)
-#pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++)
-#pragma unroll
-      for (int e = 0; e < 4; e++)
-        for (int v = 0; v < MV_WAVES - 1; v++) acc[tt][e] += red[((v * MV_TILES + tt) * 4 + e) * MV_NT + l];
-}
 
 template <class T>
 __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
@@ -202,7 +205,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
           for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
       }
     }
-    reduce_waves<T>(acc, red);
+    reduce_waves<T, MV_WAVES>(acc, red);
     if (w == 0)
 #pragma unroll
       for (int tt = 0; tt < MV_TILES; tt++)
@@ -216,16 +219,17 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
 
 // ---- downward pass: grid rows (=/+=) P [I; G] z-hat_i -----------------------
 // A[a][t] = G[a][t] at Gt[t*(m-k) + a]; Bv row t = z-hat row t.
-template <class T>
-__global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, const T *__restrict__ zin,
-                                                   T *__restrict__ zout, int RP) {
+template <class T, int W>
+__global__ void __launch_bounds__(MV_NT *W) k_mv_down(SweepArgs A, const T *__restrict__ zin,
+                                                      T *__restrict__ zout, int RP) {
   typedef typename Mfma<T>::acc_t acc_t;
   const int i = A.nb + blockIdx.x;
   if (i >= A.ne) return;
   const int m = A.m[i], k = A.k[i];
   if (m == 0) return;
   const bool leaf = A.nchild[i] == 0;
-  const int l = threadIdx.x, lr = l & 15, lk = l >> 4;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
   const int col = blockIdx.y * 16 + lr;
   T *g = zout + A.gbeg[i] * RP;
   const T *zh = zin + A.hbeg[i] * RP;
@@ -233,7 +237,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, const T *__restr
   const T *Gt = (const T *)A.Gt + A.go[i];
   const int nr = m - k;
   // skeleton rows: grid[sel[t]] (=/+=) z-hat[t]
-  for (int t = lk; t < k; t += 4) {
+  for (int t = 4 * w + lk; t < k; t += 4 * W) {
     T *dst = g + (int64_t)sel[t] * RP + col;
     const T v = zh[(int64_t)t * RP + col];
     if (leaf)
@@ -241,7 +245,7 @@ __global__ void __launch_bounds__(MV_NT) k_mv_down(SweepArgs A, const T *__restr
     else
       *dst += v;
   }
-  for (int a0 = 0; a0 < nr; a0 += 16 * MV_TILES) {
+  for (int a0 = 16 * MV_TILES * w; a0 < nr; a0 += 16 * MV_TILES * W) {
     acc_t acc[MV_TILES];
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_near_out(NearArgs A,
           for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
       }
     }
-    reduce_waves<T>(acc, red);
+    reduce_waves<T, MV_WAVES>(acc, red);
     if (w == 0)
 #pragma unroll
     for (int tt = 0; tt < MV_TILES; tt++)
@@ -370,15 +374,23 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
       SweepArgs sa{nb, ne, Cl.m, Cl.k, h.nchild, Cl.gbeg, Cl.hbeg, Cl.selo, Cl.go, L.sel,
                    f64 ? (const void *)L.G : (const void *)L.G32,
                    f64 ? (const void *)L.Gt : (const void *)L.Gt32};
-      if (h.batched) {
-        k_mv_up<T><<<dim3(ne - nb, ct), MV_NT, 0, s>>>(sa, q, q, RP);
+      // few nodes with long grids: split each node over four waves (the
+      // plain form uses the same shape per level, so both round alike)
+      const bool split = ne - nb <= h.mv_split_nodes;
+      auto up = [&](int nodes) {
+        if (split)
+          k_mv_up<T, 4><<<dim3(nodes, ct), 4 * MV_NT, 0, s>>>(sa, q, q, RP);
+        else
+          k_mv_up<T, 1><<<dim3(nodes, ct), MV_NT, 0, s>>>(sa, q, q, RP);
         SMASH_CHECK_LAUNCH();
+      };
+      if (h.batched) {
+        up(ne - nb);
       } else {
         for (int i = nb; i < ne; i++) {
           sa.nb = i;
           sa.ne = i + 1;
-          k_mv_up<T><<<dim3(1, ct), MV_NT, 0, s>>>(sa, q, q, RP);
-          SMASH_CHECK_LAUNCH();
+          up(1);
         }
       }
     }
@@ -405,15 +417,21 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
       SweepArgs sa{nb, ne, Rw.m, Rw.k, h.nchild, Rw.gbeg, Rw.hbeg, Rw.selo, Rw.go, L.sel,
                    f64 ? (const void *)L.G : (const void *)L.G32,
                    f64 ? (const void *)L.Gt : (const void *)L.Gt32};
-      if (h.batched) {
-        k_mv_down<T><<<dim3(ne - nb, ct), MV_NT, 0, s>>>(sa, z, z, RP);
+      const bool split = ne - nb <= h.mv_split_nodes;
+      auto down = [&](int nodes) {
+        if (split)
+          k_mv_down<T, 4><<<dim3(nodes, ct), 4 * MV_NT, 0, s>>>(sa, z, z, RP);
+        else
+          k_mv_down<T, 1><<<dim3(nodes, ct), MV_NT, 0, s>>>(sa, z, z, RP);
         SMASH_CHECK_LAUNCH();
+      };
+      if (h.batched) {
+        down(ne - nb);
       } else {
         for (int i = nb; i < ne; i++) {
           sa.nb = i;
           sa.ne = i + 1;
-          k_mv_down<T><<<dim3(1, ct), MV_NT, 0, s>>>(sa, z, z, RP);
-          SMASH_CHECK_LAUNCH();
+          down(1);
         }
       }
     }

@@ -33,6 +33,7 @@ extern "C" int smash_default_options(smash_options *opt) {
   opt->max_depth = 0;
   opt->batched = 1;
   opt->timing = 0;
+  opt->mv_split_nodes = 1024;
   return SMASH_OK;
 }
 
@@ -105,6 +106,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     return fail(SMASH_E_INVALID_ARG, "eval_prec must be SMASH_F64 or SMASH_F32");
   if (opt.has_root_box && !(opt.root_side >= 0.0 && std::isfinite(opt.root_side)))
     return fail(SMASH_E_INVALID_ARG, "root_side must be finite and >= 0");
+  if (opt.mv_split_nodes < 0) return fail(SMASH_E_INVALID_ARG, "mv_split_nodes must be >= 0");
 
   Handle *h = nullptr;
   auto t0 = std::chrono::steady_clock::now();
@@ -129,6 +131,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->apply_prec = opt.apply_prec;
     h->batched = opt.batched ? 1 : 0;
     h->timing = opt.timing != 0;
+    h->mv_split_nodes = opt.mv_split_nodes;
     h->nx = nx;
     h->ny = ny;
     h->same_xy = same;
