@@ -12,9 +12,10 @@
 // columns hold zeros), so a node's grid is a contiguous block of rows.
 //
 // Every dense piece is a small matrix product C (rows x 16) += A (rows x K)
-// * Bv (K x 16) with A one of G^T, G, B_ij and Bv a set of vector rows.  One
-// wavefront per node (and per 16-column tile) runs it on the matrix cores
-// with 16x16x4 MFMA steps: lane l feeds A[row0 + l%16][k0 + l/16] and
+// * Bv (K x 16) with A one of G^T, G, B_ij and Bv a set of vector rows.  The
+// sweeps run one to four wavefronts per node and 16-column tile; the
+// coupling and near products one workgroup per node whose waves each cover
+// every column tile, so each block is read once.  All use 16x16x4 MFMA: lane l feeds A[row0 + l%16][k0 + l/16] and
 // Bv[k0 + l/16][col0 + l%16] and holds four results C[row][col0 + l%16]:
 // row = row0 + 4(l/16) + e for the FP32 instruction and row0 + 4e + l/16
 // for the FP64 one (e = 0..3; measured on gfx950).  A is stored with
@@ -26,7 +27,6 @@ namespace smash {
 
 constexpr int MV_NT = 64;
 constexpr int MV_TILES = 4;  // 16-row tiles per pass (64 rows)
-constexpr int MV_WAVES = 4;  // wavefronts per node in the coupling and near products
 
 template <class T>
 struct Mfma;
@@ -159,60 +159,116 @@ struct CouplingArgs {
   const void *B;
 };
 
-template <class T>
+// Workgroups are dealt to the eight XCDs round-robin.  This maps them so
+// that each XCD (and its L2) takes runs of XCD_RUN consecutive items --
+// spatial neighbours in the tree order, which read the same vector rows --
+// while the runs still interleave over the XCDs in item order, which keeps
+// the levels (and so the work) balanced between them.
+constexpr int XCD_RUN = 16;
+__device__ __forceinline__ int xcd_item(int b) {
+  const int q = b >> 3;
+  return (q / XCD_RUN) * (8 * XCD_RUN) + (b & 7) * XCD_RUN + q % XCD_RUN;
+}
+__device__ __forceinline__ int item_of_block(int b, int nitems) {
+  return nitems < 8 * XCD_RUN ? b : xcd_item(b);
+}
+static inline int xcd_grid(int nitems) {
+  return nitems < 8 * XCD_RUN ? nitems : (nitems + 8 * XCD_RUN - 1) / (8 * XCD_RUN) * (8 * XCD_RUN);
+}
+
+// Sum of the W partial accumulator tiles of a workgroup into wave 0.
+template <class T, int W, int NA>
+__device__ __forceinline__ void reduce_waves_n(typename Mfma<T>::acc_t *acc, T *red) {
+  const int w = threadIdx.x / MV_NT, l = threadIdx.x & (MV_NT - 1);
+  __syncthreads();
+  if (w > 0)
+#pragma unroll
+    for (int x = 0; x < NA; x++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) red[(((w - 1) * NA + x) * 4 + e) * MV_NT + l] = acc[x][e];
+  __syncthreads();
+  if (w == 0)
+#pragma unroll
+    for (int x = 0; x < NA; x++)
+#pragma unroll
+      for (int e = 0; e < 4; e++)
+        for (int v = 0; v < W - 1; v++) acc[x][e] += red[((v * NA + x) * 4 + e) * MV_NT + l];
+}
+
+constexpr int MV_WAVES = 4;  // wavefronts per node in the coupling and near products
+
+// 16-row tiles per pass: four for one column tile (FP32: two), else two, so
+// that accumulators and operands stay within 128 registers
+template <class T, int CT>
+struct MvShape {
+  static constexpr int TT = (CT >= 3 || (sizeof(T) == 8 && CT >= 2)) ? 2 : 4;
+};
+
+// One workgroup per row node: MV_WAVES waves split its pairs, and each wave
+// covers TT 16-row tiles and all CT 16-column tiles of the right-hand sides
+// per pass, so a block B_ij is read once and every A operand it loads feeds
+// CT matrix-core steps (with many right-hand sides the product is bound by
+// the matrix cores, not by HBM).
+template <class T, int TT, int CT>
 __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
                                                                  const T *__restrict__ qh,
-                                                                 T *__restrict__ zh, int RP) {
+                                                                 T *__restrict__ zh, int RP,
+                                                                 int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T red[(MV_WAVES - 1) * MV_TILES * 4 * MV_NT];
-  const int i = A.i0 + blockIdx.x;
-  if (i >= A.nnodes) return;
+  __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
+  const int it = item_of_block(blockIdx.x, nitems);
+  if (it >= nitems) return;
+  const int i = A.i0 + it;
   const int ki = A.krow[i];
   if (ki == 0) return;
   const int w = threadIdx.x / MV_NT;
   const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
-  const int col = blockIdx.y * 16 + lr;
-  T *out = zh + A.hrow[i] * RP;
+  T *out = zh + A.hrow[i] * RP + lr;
   const T *Bv = (const T *)A.B;
   const int p0 = A.Lrow[i], p1 = A.Lrow[i + 1];
-  for (int t0 = 0; t0 < ki; t0 += 16 * MV_TILES) {
-    acc_t acc[MV_TILES];
+  for (int t0 = 0; t0 < ki; t0 += 16 * TT) {
+    acc_t acc[TT * CT];
 #pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int x = 0; x < TT * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
     for (int p = p0 + w; p < p1; p += MV_WAVES) {
       const int j = A.Lj[p];
       const int kj = A.kcol[j];
       const T *Bp = Bv + A.boff[p];
-      const T *qj = qh + A.hcol[j] * RP + col;
-      // K in chunks of 16: every load of four MFMA steps is in flight
-      // before the first of them issues
+      const T *qj = qh + A.hcol[j] * RP + lr;
+      // K in chunks of 16: all loads of four MFMA steps are issued first
       for (int s0 = 0; s0 < kj; s0 += 16) {
-        T bv[4], av[4][MV_TILES];
+        T bv[4][CT], av[4][TT];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           const int s = s0 + 4 * u + lk;
           const bool ks = s < kj;
-          bv[u] = ks ? qj[(int64_t)s * RP] : (T)0;
 #pragma unroll
-          for (int tt = 0; tt < MV_TILES; tt++) {
+          for (int c = 0; c < CT; c++) bv[u][c] = ks ? qj[(int64_t)s * RP + 16 * c] : (T)0;
+#pragma unroll
+          for (int tt = 0; tt < TT; tt++) {
             const int t = t0 + tt * 16 + lr;
-            av[u][tt] = (ks && t < ki) ? Bp[(int64_t)s * ki + t] : (T)0;
+            av[u][tt] = (ks && t < ki) ? Bp[s * ki + t] : (T)0;
           }
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
 #pragma unroll
-          for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
+          for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+            for (int c = 0; c < CT; c++)
+              acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
       }
     }
-    reduce_waves<T, MV_WAVES>(acc, red);
+    reduce_waves_n<T, MV_WAVES, TT * CT>(acc, red);
     if (w == 0)
 #pragma unroll
-      for (int tt = 0; tt < MV_TILES; tt++)
+      for (int tt = 0; tt < TT; tt++)
 #pragma unroll
         for (int e = 0; e < 4; e++) {
           const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
-          if (t < ki) out[(int64_t)t * RP + col] = acc[tt][e];
+          if (t < ki)
+#pragma unroll
+            for (int c = 0; c < CT; c++) out[(int64_t)t * RP + 16 * c] = acc[tt * CT + c][e];
         }
   }
 }
@@ -293,64 +349,92 @@ struct NearArgs {
   int has_far;
 };
 
-template <class T>
+template <class T, int TT, int CT>
 __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_near_out(NearArgs A,
                                                                  const T *__restrict__ q,
                                                                  const T *__restrict__ z,
                                                                  T *__restrict__ Y, int64_t ldy,
-                                                                 int R, int RP) {
+                                                                 int R, int RP, int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T red[(MV_WAVES - 1) * MV_TILES * 4 * MV_NT];
-  const int i = A.i0 + blockIdx.x;
-  if (i >= A.nnodes || A.nchild[i] != 0) return;
+  __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
+  const int it = item_of_block(blockIdx.x, nitems);
+  if (it >= nitems) return;
+  const int i = A.i0 + it;
+  if (A.nchild[i] != 0) return;
   const int xb = A.xb[i], ni = A.xe[i] - xb;
   const int w = threadIdx.x / MV_NT;
   const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
-  const int col = blockIdx.y * 16 + lr;
   const T *Bv = (const T *)A.Bn;
   const int p0 = A.Lmrow[i], p1 = A.Lmrow[i + 1];
-  for (int a0 = 0; a0 < ni; a0 += 16 * MV_TILES) {
-    acc_t acc[MV_TILES];
+  for (int a0 = 0; a0 < ni; a0 += 16 * TT) {
+    acc_t acc[TT * CT];
 #pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = acc_t{0, 0, 0, 0};
+    for (int x = 0; x < TT * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
     for (int p = p0 + w; p < p1; p += MV_WAVES) {
       const int j = A.Lmj[p];
       const int yb = A.yb[j], nj = A.ye[j] - yb;
       const T *Bp = Bv + A.nboff[p];
-      const T *qj = q + (int64_t)yb * RP + col;
+      const T *qj = q + (int64_t)yb * RP + lr;
       for (int b0 = 0; b0 < nj; b0 += 16) {
-        T bv[4], av[4][MV_TILES];
+        T bv[4][CT], av[4][TT];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           const int b = b0 + 4 * u + lk;
           const bool kb = b < nj;
-          bv[u] = kb ? qj[(int64_t)b * RP] : (T)0;
 #pragma unroll
-          for (int tt = 0; tt < MV_TILES; tt++) {
+          for (int c = 0; c < CT; c++) bv[u][c] = kb ? qj[(int64_t)b * RP + 16 * c] : (T)0;
+#pragma unroll
+          for (int tt = 0; tt < TT; tt++) {
             const int a = a0 + tt * 16 + lr;
-            av[u][tt] = (kb && a < ni) ? Bp[(int64_t)b * ni + a] : (T)0;
+            av[u][tt] = (kb && a < ni) ? Bp[b * ni + a] : (T)0;
           }
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
 #pragma unroll
-          for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = Mfma<T>::op(av[u][tt], bv[u], acc[tt]);
+          for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+            for (int c = 0; c < CT; c++)
+              acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
       }
     }
-    reduce_waves<T, MV_WAVES>(acc, red);
+    reduce_waves_n<T, MV_WAVES, TT * CT>(acc, red);
     if (w == 0)
 #pragma unroll
-    for (int tt = 0; tt < MV_TILES; tt++)
+      for (int tt = 0; tt < TT; tt++)
 #pragma unroll
-      for (int e = 0; e < 4; e++) {
-        const int a = a0 + tt * 16 + Mfma<T>::row(lk, e);
-        if (a < ni && col < R) {
-          T v = acc[tt][e];
-          if (A.has_far) v += z[(int64_t)(xb + a) * RP + col];
-          Y[(int64_t)A.perm_x[xb + a] * ldy + col] = v;
+        for (int e = 0; e < 4; e++) {
+          const int a = a0 + tt * 16 + Mfma<T>::row(lk, e);
+          if (a < ni) {
+            const int64_t yrow = (int64_t)A.perm_x[xb + a] * ldy;
+#pragma unroll
+            for (int c = 0; c < CT; c++) {
+              const int col = 16 * c + lr;
+              if (col < R) {
+                T v = acc[tt * CT + c][e];
+                if (A.has_far) v += z[(int64_t)(xb + a) * RP + col];
+                Y[yrow + col] = v;
+              }
+            }
+          }
         }
-      }
   }
+}
+
+template <class T, int CT>
+static void launch_coupling(const CouplingArgs &ca, const T *q, T *z, int RP, int nitems,
+                            hipStream_t s) {
+  k_mv_coupling<T, MvShape<T, CT>::TT, CT>
+      <<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP, nitems);
+  SMASH_CHECK_LAUNCH();
+}
+
+template <class T, int CT>
+static void launch_near(const NearArgs &na, const T *q, const T *z, T *Y, int64_t ldy, int R,
+                        int RP, int nitems, hipStream_t s) {
+  k_mv_near_out<T, MvShape<T, CT>::TT, CT>
+      <<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP, nitems);
+  SMASH_CHECK_LAUNCH();
 }
 
 template <class T>
@@ -399,14 +483,20 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
     CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
     {
       PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
+      auto coupling = [&](int nitems) {
+        switch (ct) {
+          case 1: launch_coupling<T, 1>(ca, q, z, RP, nitems, s); break;
+          case 2: launch_coupling<T, 2>(ca, q, z, RP, nitems, s); break;
+          case 3: launch_coupling<T, 3>(ca, q, z, RP, nitems, s); break;
+          default: launch_coupling<T, 4>(ca, q, z, RP, nitems, s); break;
+        }
+      };
       if (h.batched) {
-        k_mv_coupling<T><<<dim3(h.nnodes - 1, ct), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP);
-        SMASH_CHECK_LAUNCH();
+        coupling(h.nnodes - 1);
       } else {
         for (int i = 1; i < h.nnodes; i++) {
           ca.i0 = i;
-          k_mv_coupling<T><<<dim3(1, ct), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP);
-          SMASH_CHECK_LAUNCH();
+          coupling(1);
         }
       }
     }
@@ -440,14 +530,20 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
               h.Bn, has_far ? 1 : 0};
   {
     PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
+    auto near = [&](int nitems) {
+      switch (ct) {
+        case 1: launch_near<T, 1>(na, q, z, Y, ldy, R, RP, nitems, s); break;
+        case 2: launch_near<T, 2>(na, q, z, Y, ldy, R, RP, nitems, s); break;
+        case 3: launch_near<T, 3>(na, q, z, Y, ldy, R, RP, nitems, s); break;
+        default: launch_near<T, 4>(na, q, z, Y, ldy, R, RP, nitems, s); break;
+      }
+    };
     if (h.batched) {
-      k_mv_near_out<T><<<dim3(h.nnodes, ct), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP);
-      SMASH_CHECK_LAUNCH();
+      near(h.nnodes);
     } else {
       for (int i = 0; i < h.nnodes; i++) {
         na.i0 = i;
-        k_mv_near_out<T><<<dim3(1, ct), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP);
-        SMASH_CHECK_LAUNCH();
+        near(1);
       }
     }
   }
