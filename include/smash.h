@@ -53,6 +53,7 @@ extern "C" {
 /* ---- precisions ---- */
 #define SMASH_F64 0
 #define SMASH_F32 1
+#define SMASH_BF16 2 /* apply only: BF16 matrices, FP32 vectors and accumulation */
 
 typedef struct smash_handle_s *smash_handle;
 
@@ -63,7 +64,11 @@ typedef struct smash_handle_s *smash_handle;
  *   srrqr_f      Gu-Eisenstat bound f = s of Thm. 2.4; default 2
  *   diag_value   d_x of eq. (2.1) for singular kernels; default 0
  *   eval_prec    precision of the stored coupling / near-field blocks
- *   apply_prec   precision of the product (G copies, vectors); SMASH_F64 or SMASH_F32
+ *   apply_prec   precision of the product: SMASH_F64 or SMASH_F32 (G copies,
+ *                blocks and vectors of that type), or SMASH_BF16 (G copies and
+ *                blocks stored in BF16 and multiplied on the BF16 matrix cores
+ *                with FP32 accumulation; vectors FP32).  The construction
+ *                itself (basis, near-field SVD, RRQR) is FP64 in every case.
  *   has_root_box root box [root_lo, root_lo + root_side]^dim instead of the
  *                bounding cube of X and Y (points outside: SMASH_E_INVALID_ARG)
  *   max_depth    > 0 caps the number of tree levels (root = level 1)
@@ -119,7 +124,8 @@ int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int
 /* Product Y = A-hat X (Sec. 3.4) in the ORIGINAL point order.
  *   X  device, ny x nrhs, leading dimension ldx (>= nrhs)
  *   Y  device, nx x nrhs, leading dimension ldy (>= nrhs); fully overwritten
- *   dtype  SMASH_F64 or SMASH_F32; must equal the handle's apply precision
+ *   dtype  type of X and Y: SMASH_F64 for an FP64-apply handle, SMASH_F32 for
+ *          an FP32- or BF16-apply handle
  * Asynchronous on `stream`; workspaces are owned by the handle. */
 int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
                  void *Y, int64_t ldy, void *stream);
@@ -183,8 +189,10 @@ int smash_info(smash_handle h, smash_info_t *info);
 #define SMASH_EX_COL_GRID 15
 #define SMASH_EX_SIZES 16    /* nx, ny, nnodes, nlevels, |L|, |L^-|, dim, admissibility */
 #define SMASH_EX_LEVELS 17   /* nlevels+1: first node of each level, then nnodes */
-#define SMASH_EX_COUPLING 18 /* apply-precision entries of all B_ij over L, pair order, row-major */
-#define SMASH_EX_NEAR 19     /* apply-precision entries of all near blocks over L^- */
+#define SMASH_EX_COUPLING 18 /* entries of all B_ij over L in pair order, each block  */
+                             /* column-major (row index fastest), F64 or F32 per the */
+                             /* apply precision; a BF16 handle: SMASH_E_UNSUPPORTED  */
+#define SMASH_EX_NEAR 19     /* the same for the near blocks over L^-                */
 int smash_export(smash_handle h, int32_t what, void *host_buf, int64_t *count);
 
 int smash_destroy(smash_handle h);

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsmash.so")
 
 KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3}
 ADM = {"weak": 0, "hss": 0, "strong": 1, "h2": 1}
-PREC = {"f64": 0, "f32": 1}
+PREC = {"f64": 0, "f32": 1, "bf16": 2}
 
 EX = dict(perm_x=1, perm_y=2, nodes=3, boxes=4, L=5, Lm=6, near_ptr=7, near_idx=8, ranks=9,
           row_sel=10, row_G=11, col_sel=12, col_G=13, row_grid=14, col_grid=15, sizes=16,
@@ -125,6 +125,8 @@ class Smash:
             opt.eps_svd = eps_svd
         opt.srrqr_f = f
         opt.diag_value = diag
+        if eval_prec not in ("f64", "f32"):
+            raise ValueError("eval_prec must be 'f64' or 'f32'")
         opt.eval_prec = PREC[eval_prec]
         opt.apply_prec = PREC[apply_prec]
         if root is not None:
@@ -157,7 +159,8 @@ class Smash:
         self._h = h
 
     def matvec(self, X, out=None, stream=None):
-        """Y = A-hat X, original point order; X: (ny, nrhs) or (ny,)."""
+        """Y = A-hat X, original point order; X: (ny, nrhs) or (ny,), float64 for an
+        FP64-apply handle, float32 for FP32 and BF16 apply."""
         import torch
         dt = torch.float64 if self.apply_prec == "f64" else torch.float32
         vec = X.dim() == 1
@@ -171,7 +174,8 @@ class Smash:
         if out is None:
             out = torch.empty((self.nx, R), dtype=dt, device=X.device)
         _check(lib().smash_matvec(self._h, C.c_void_p(X.data_ptr()), X.stride(0), R,
-                                  PREC[self.apply_prec], C.c_void_p(out.data_ptr()),
+                                  PREC["f64" if self.apply_prec == "f64" else "f32"],
+                                  C.c_void_p(out.data_ptr()),
                                   out.stride(0), _stream_ptr(stream)))
         return out[:, 0] if vec else out
 

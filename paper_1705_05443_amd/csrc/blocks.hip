@@ -7,16 +7,23 @@
 
 namespace smash {
 
+// entries per block; pad8: columns rounded up to a multiple of 8 (the BF16
+// matrix-core operand order)
 __global__ void k_block_sizes(int64_t n, const int *pi, const int *pj, const int *ki,
-                              const int *kj, int64_t *cnt) {
+                              const int *kj, int pad8, int64_t *cnt) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a < n) cnt[a] = (int64_t)ki[pi[a]] * kj[pj[a]];
+  if (a >= n) return;
+  const int c = kj[pj[a]];
+  cnt[a] = (int64_t)ki[pi[a]] * (pad8 ? (c + 7) & ~7 : c);
 }
 
 __global__ void k_near_sizes(int64_t n, const int *pi, const int *pj, const int *xb,
-                             const int *xe, const int *yb, const int *ye, int64_t *cnt) {
+                             const int *xe, const int *yb, const int *ye, int pad8,
+                             int64_t *cnt) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a < n) cnt[a] = (int64_t)(xe[pi[a]] - xb[pi[a]]) * (ye[pj[a]] - yb[pj[a]]);
+  if (a >= n) return;
+  const int c = ye[pj[a]] - yb[pj[a]];
+  cnt[a] = (int64_t)(xe[pi[a]] - xb[pi[a]]) * (pad8 ? (c + 7) & ~7 : c);
 }
 
 struct EvalArgs {
@@ -74,6 +81,56 @@ __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
   }
 }
 
+// BF16 blocks in the matrix-core operand order: entry (a, b) of an nr x nc
+// block at ((b/8) * nr + a) * 8 + b%8, columns padded with zeros to a
+// multiple of 8, so eight consecutive columns of one row are one 16-byte load.
+template <bool F32MATH>
+__global__ void __launch_bounds__(256) k_eval_blocks_bf16(EvalArgs A, unsigned short *out) {
+  for (int64_t e = blockIdx.x; e < A.npairs; e += gridDim.x) {
+    int i = A.pi[e], j = A.pj[e];
+    int64_t r0, c0;
+    int nr, nc;
+    if (A.rbeg) {
+      r0 = A.rbeg[i];
+      nr = A.rcnt_k[i];
+    } else {
+      r0 = A.rbeg32[i];
+      nr = A.rend32[i] - A.rbeg32[i];
+    }
+    if (A.cbeg) {
+      c0 = A.cbeg[j];
+      nc = A.ccnt_k[j];
+    } else {
+      c0 = A.cbeg32[j];
+      nc = A.cend32[j] - A.cbeg32[j];
+    }
+    unsigned short *B = out + A.off[e];
+    const int tot = nr * ((nc + 7) & ~7);
+    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
+      const int b8 = q / (nr * 8), r = q - b8 * nr * 8, a = r >> 3, b = b8 * 8 + (r & 7);
+      float v = 0.0f;
+      if (b < nc) {
+        int64_t xr = A.rid ? A.rid[r0 + a] : r0 + a;
+        int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
+        const double *xp = A.Xp + xr * A.d, *yp = A.Yp + yc * A.d;
+        v = F32MATH ? kernel_f32(A.kid, xp, yp, A.d, (float)A.diag)
+                    : (float)kernel_f64(A.kid, xp, yp, A.d, A.diag);
+      }
+      B[q] = bf16_bits(v);
+    }
+  }
+}
+
+static void eval_launch_bf16(Handle &h, EvalArgs &ea, unsigned short *out, bool f32math) {
+  int nblk = ea.npairs < (1 << 20) ? (int)ea.npairs : (1 << 20);
+  if (nblk <= 0) return;
+  if (f32math)
+    k_eval_blocks_bf16<true><<<nblk, 256, 0, h.stream>>>(ea, out);
+  else
+    k_eval_blocks_bf16<false><<<nblk, 256, 0, h.stream>>>(ea, out);
+  SMASH_CHECK_LAUNCH();
+}
+
 template <class T>
 static void eval_launch(Handle &h, EvalArgs &ea, T *out, bool f32math) {
   int nblk = ea.npairs < (1 << 20) ? (int)ea.npairs : (1 << 20);
@@ -91,13 +148,17 @@ void build_blocks(Handle &h) {
   tmp.stream = s;
   try {
     Side &R = h.row, &C = *h.col;
-    size_t es = h.apply_prec == SMASH_F64 ? sizeof(double) : sizeof(float);
+    const bool bf = h.apply_prec == SMASH_BF16;
+    size_t es = h.apply_prec == SMASH_F64 ? sizeof(double)
+                : bf                      ? sizeof(unsigned short)
+                                          : sizeof(float);
     bool f32math = h.eval_prec == SMASH_F32;
     // coupling
     int64_t *cnt = tmp.alloc_n<int64_t>(h.nL);
     h.boff = h.mem.alloc_n<int64_t>(h.nL + 1);
     if (h.nL > 0) {
-      k_block_sizes<<<ceil_div(h.nL, 256), 256, 0, s>>>(h.nL, h.Li, h.Lj, R.k, C.k, cnt);
+      k_block_sizes<<<ceil_div(h.nL, 256), 256, 0, s>>>(h.nL, h.Li, h.Lj, R.k, C.k, bf ? 1 : 0,
+                                                        cnt);
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
@@ -107,7 +168,7 @@ void build_blocks(Handle &h) {
     h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
     if (h.nLm > 0) {
       k_near_sizes<<<ceil_div(h.nLm, 256), 256, 0, s>>>(h.nLm, h.Lmi, h.Lmj, h.xb, h.xe, h.yb,
-                                                        h.ye, ncnt);
+                                                        h.ye, bf ? 1 : 0, ncnt);
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
@@ -135,6 +196,8 @@ void build_blocks(Handle &h) {
     ea.cid = C.slot_id;
     if (h.apply_prec == SMASH_F64)
       eval_launch(h, ea, (double *)h.B, f32math);
+    else if (bf)
+      eval_launch_bf16(h, ea, (unsigned short *)h.B, f32math);
     else
       eval_launch(h, ea, (float *)h.B, f32math);
     // near blocks: A(X at i, Y at j), point ranges
@@ -154,6 +217,8 @@ void build_blocks(Handle &h) {
     en.cend32 = h.ye;
     if (h.apply_prec == SMASH_F64)
       eval_launch(h, en, (double *)h.Bn, f32math);
+    else if (bf)
+      eval_launch_bf16(h, en, (unsigned short *)h.Bn, f32math);
     else
       eval_launch(h, en, (float *)h.Bn, f32math);
     SMASH_HIP(hipStreamSynchronize(s));

@@ -7,6 +7,14 @@ namespace smash {
 
 constexpr int WAVE = 64;
 
+// BF16 operands of the 16x16x32 matrix-core step (eight per lane) and the
+// FP32 accumulator tile.  Conversions round to nearest even.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ unsigned short bf16_bits(float x) {
+  return __builtin_bit_cast(unsigned short, (__bf16)x);
+}
+
 // Exclusive block scan of one int64 per thread (blockDim a multiple of 64).
 // lds must hold blockDim/64 + 1 entries.  Ends with a barrier, so lds may be
 // reused right after.

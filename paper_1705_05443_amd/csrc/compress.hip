@@ -980,6 +980,36 @@ __global__ void k_transpose_G(int nb, int ne, const int *m, const int *k, const 
   }
 }
 
+// BF16 copies of G for the matrix-core product (layouts in LevelSide)
+__global__ void k_gb_sizes(int nb, int ne, const int *m, const int *k, int64_t *cu, int64_t *cd) {
+  int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ne) return;
+  const int kk = k[i], nr = m[i] - kk;
+  cu[i - nb] = (int64_t)kk * ((nr + 7) & ~7);
+  cd[i - nb] = (int64_t)nr * ((kk + 7) & ~7);
+}
+
+__global__ void __launch_bounds__(256) k_g_to_bf16(int nb, int ne, const int *m, const int *k,
+                                                   const int64_t *go, const double *G,
+                                                   const int64_t *gobu, const int64_t *gobd,
+                                                   unsigned short *Gbu, unsigned short *Gbd) {
+  const int i = nb + blockIdx.x;
+  if (i >= ne) return;
+  const int kk = k[i], nr = m[i] - kk;
+  if (kk == 0 || nr == 0) return;
+  const double *Gi = G + go[i];  // (m-k) x k row-major
+  const int nr8 = (nr + 7) & ~7, k8 = (kk + 7) & ~7;
+  unsigned short *U = Gbu + gobu[i], *D = Gbd + gobd[i];
+  for (int q = threadIdx.x; q < kk * nr8; q += blockDim.x) {
+    const int a8 = q / (kk * 8), r = q - a8 * kk * 8, t = r >> 3, a = a8 * 8 + (r & 7);
+    U[q] = bf16_bits(a < nr ? (float)Gi[(int64_t)a * kk + t] : 0.0f);
+  }
+  for (int q = threadIdx.x; q < nr * k8; q += blockDim.x) {
+    const int t8 = q / (nr * 8), r = q - t8 * nr * 8, a = r >> 3, t = t8 * 8 + (r & 7);
+    D[q] = bf16_bits(t < kk ? (float)Gi[(int64_t)a * kk + t] : 0.0f);
+  }
+}
+
 __global__ void k_to_f32(const double *in, float *out, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = (float)in[i];
@@ -1256,6 +1286,38 @@ void build_generators(Handle &h) {
             k_to_f32<<<ceil_div(L.g_n, 256), 256, 0, s>>>(L.Gt, L.Gt32, L.g_n);
             SMASH_CHECK_LAUNCH();
           }
+        }
+      }
+    }
+    if (h.apply_prec == SMASH_BF16) {
+      for (auto &sc : sides) {
+        Side &S = *sc.S;
+        S.gobu = h.mem.alloc_n<int64_t>(h.nnodes);
+        S.gobd = h.mem.alloc_n<int64_t>(h.nnodes);
+        for (int l = 2; l <= h.nlevels; l++) {
+          const int nb = h.level_beg[l - 1], ne = h.level_beg[l], nl = ne - nb;
+          LevelSide &L = S.lv[l];
+          int64_t *cu = tmp.alloc_n<int64_t>(nl), *cd = tmp.alloc_n<int64_t>(nl);
+          int64_t *ou = tmp.alloc_n<int64_t>(nl + 1), *od = tmp.alloc_n<int64_t>(nl + 1);
+          k_gb_sizes<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.m, S.k, cu, cd);
+          SMASH_CHECK_LAUNCH();
+          scan_i64(cu, ou, nl, nullptr, s, tmp);
+          scan_i64(cd, od, nl, nullptr, s, tmp);
+          k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, ou, S.gobu);
+          SMASH_CHECK_LAUNCH();
+          k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, od, S.gobd);
+          SMASH_CHECK_LAUNCH();
+          int64_t tot[2];
+          SMASH_HIP(hipMemcpyAsync(&tot[0], ou + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+          SMASH_HIP(hipMemcpyAsync(&tot[1], od + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+          SMASH_HIP(hipStreamSynchronize(s));
+          L.gbu_n = tot[0];
+          L.gbd_n = tot[1];
+          L.Gbu = h.mem.alloc_n<unsigned short>(tot[0]);
+          L.Gbd = h.mem.alloc_n<unsigned short>(tot[1]);
+          k_g_to_bf16<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, S.gobu, S.gobd, L.Gbu,
+                                         L.Gbd);
+          SMASH_CHECK_LAUNCH();
         }
       }
     }

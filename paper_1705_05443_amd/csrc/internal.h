@@ -84,12 +84,18 @@ struct LevelSide {
   double *Gt = nullptr;   // the same transposed, k x (m-k) per node
   float *G32 = nullptr;   // FP32 apply copies
   float *Gt32 = nullptr;
-  int64_t sel_n = 0, g_n = 0;
+  // BF16 apply copies in the matrix-core operand order (eight consecutive
+  // K entries per 16-byte load): up  = H^T, k x (m-k), K = grid row a,
+  // stored [a/8][t][a%8]; down = G, (m-k) x k, K = skeleton index t, stored
+  // [t/8][a][t%8]; K padded with zeros to a multiple of 8
+  unsigned short *Gbu = nullptr, *Gbd = nullptr;
+  int64_t sel_n = 0, g_n = 0, gbu_n = 0, gbd_n = 0;
 };
 
 struct Side {
   int *m = nullptr, *k = nullptr, *ks = nullptr;  // per node
   int64_t *gbeg = nullptr, *hbeg = nullptr, *selo = nullptr, *go = nullptr;
+  int64_t *gobu = nullptr, *gobd = nullptr;  // BF16 copy offsets per node
   int *slot_id = nullptr;
   int64_t slot_cap = 0, nslots = 0;
   std::vector<LevelSide> lv;  // indexed by level (1-based; [0] unused)

@@ -437,6 +437,377 @@ static void launch_near(const NearArgs &na, const T *q, const T *z, T *Y, int64_
   SMASH_CHECK_LAUNCH();
 }
 
+// ======================================================================
+// BF16 apply: the matrices (H^T, G, B_ij, near blocks) are BF16 in the
+// matrix-core operand order, vectors stay FP32 and are rounded to BF16 as
+// they enter a 16x16x32 step (eight K entries per lane: lane l feeds
+// A[l%16][8(l/16) + j] and Bv[8(l/16) + j][l%16], j < 8; results as in the
+// FP32 16x16x4 step, row 4(l/16) + e), accumulation FP32.
+// ======================================================================
+struct SweepArgsB {
+  int nb, ne;
+  const int *m, *k, *nchild;
+  const int64_t *gbeg, *hbeg, *selo, *gou, *god;
+  const int *sel;
+  const unsigned short *Gu, *Gd;
+};
+
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 load_bf16x8(const unsigned short *p) {
+  return __builtin_bit_cast(bf16x8, *(const uint4 *)p);
+}
+__device__ __forceinline__ bf16x8 zero_bf16x8() {
+  return __builtin_bit_cast(bf16x8, uint4{0u, 0u, 0u, 0u});
+}
+
+// up: q-hat_i = q|_hat + H^T q|_check; K = grid rows in chunks of 32 per wave
+template <int W>
+__global__ void __launch_bounds__(MV_NT *W) k_mvb_up(SweepArgsB A, const float *__restrict__ qin,
+                                                     float *__restrict__ qout, int RP) {
+  __shared__ float red[(W > 1 ? W - 1 : 1) * MV_TILES * 4 * MV_NT];
+  const int i = A.nb + blockIdx.x;
+  if (i >= A.ne) return;
+  const int m = A.m[i], k = A.k[i];
+  if (k == 0) return;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.y * 16 + lr;
+  const float *g = qin + A.gbeg[i] * RP;
+  float *out = qout + A.hbeg[i] * RP;
+  const int *sel = A.sel + A.selo[i];
+  const unsigned short *H = A.Gu + A.gou[i];
+  const int nr = m - k;
+  for (int t0 = 0; t0 < k; t0 += 16 * MV_TILES) {
+    f32x4 acc[MV_TILES];
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = f32x4{0, 0, 0, 0};
+    for (int a0 = 32 * w; a0 < nr; a0 += 32 * W) {
+      const int kb = a0 + 8 * lk;
+      bf16x8 bv;
+#pragma unroll
+      for (int j = 0; j < 8; j++)
+        bv[j] = (__bf16)(kb + j < nr ? g[(int64_t)sel[k + kb + j] * RP + col] : 0.0f);
+      bf16x8 av[MV_TILES];
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++) {
+        const int t = t0 + tt * 16 + lr;
+        av[tt] = (kb < nr && t < k) ? load_bf16x8(H + ((int64_t)(kb >> 3) * k + t) * 8)
+                                    : zero_bf16x8();
+      }
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = mfma_bf16(av[tt], bv, acc[tt]);
+    }
+    if (W > 1) reduce_waves<float, W>(acc, red);
+    if (w == 0)
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int t = t0 + tt * 16 + 4 * lk + e;
+          if (t < k) out[(int64_t)t * RP + col] = acc[tt][e] + g[(int64_t)sel[t] * RP + col];
+        }
+  }
+}
+
+// down: grid rows (=/+=) P [I; G] z-hat_i; K = skeleton index in chunks of 32
+template <int W>
+__global__ void __launch_bounds__(MV_NT *W) k_mvb_down(SweepArgsB A, const float *__restrict__ zin,
+                                                       float *__restrict__ zout, int RP) {
+  const int i = A.nb + blockIdx.x;
+  if (i >= A.ne) return;
+  const int m = A.m[i], k = A.k[i];
+  if (m == 0) return;
+  const bool leaf = A.nchild[i] == 0;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
+  const int col = blockIdx.y * 16 + lr;
+  float *g = zout + A.gbeg[i] * RP;
+  const float *zh = zin + A.hbeg[i] * RP;
+  const int *sel = A.sel + A.selo[i];
+  const unsigned short *Gd = A.Gd + A.god[i];
+  const int nr = m - k;
+  for (int t = 4 * w + lk; t < k; t += 4 * W) {
+    float *dst = g + (int64_t)sel[t] * RP + col;
+    const float v = zh[(int64_t)t * RP + col];
+    if (leaf)
+      *dst = v;
+    else
+      *dst += v;
+  }
+  for (int a0 = 16 * MV_TILES * w; a0 < nr; a0 += 16 * MV_TILES * W) {
+    f32x4 acc[MV_TILES];
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = f32x4{0, 0, 0, 0};
+    for (int t0 = 0; t0 < k; t0 += 32) {
+      const int kb = t0 + 8 * lk;
+      bf16x8 bv;
+#pragma unroll
+      for (int j = 0; j < 8; j++) bv[j] = (__bf16)(kb + j < k ? zh[(int64_t)(kb + j) * RP + col] : 0.0f);
+      bf16x8 av[MV_TILES];
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++) {
+        const int a = a0 + tt * 16 + lr;
+        av[tt] = (kb < k && a < nr) ? load_bf16x8(Gd + ((int64_t)(kb >> 3) * nr + a) * 8)
+                                    : zero_bf16x8();
+      }
+#pragma unroll
+      for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = mfma_bf16(av[tt], bv, acc[tt]);
+    }
+#pragma unroll
+    for (int tt = 0; tt < MV_TILES; tt++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int a = a0 + tt * 16 + 4 * lk + e;
+        if (a < nr) {
+          float *dst = g + (int64_t)sel[k + a] * RP + col;
+          if (leaf)
+            *dst = acc[tt][e];
+          else
+            *dst += acc[tt][e];
+        }
+      }
+  }
+}
+
+// coupling: as k_mv_coupling, K in chunks of 32
+template <int TT, int CT>
+__global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_coupling(CouplingArgs A,
+                                                                  const float *__restrict__ qh,
+                                                                  float *__restrict__ zh, int RP,
+                                                                  int nitems) {
+  __shared__ float red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
+  const int it = item_of_block(blockIdx.x, nitems);
+  if (it >= nitems) return;
+  const int i = A.i0 + it;
+  const int ki = A.krow[i];
+  if (ki == 0) return;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
+  float *out = zh + A.hrow[i] * RP + lr;
+  const unsigned short *Bv = (const unsigned short *)A.B;
+  const int p0 = A.Lrow[i], p1 = A.Lrow[i + 1];
+  for (int t0 = 0; t0 < ki; t0 += 16 * TT) {
+    f32x4 acc[TT * CT];
+#pragma unroll
+    for (int x = 0; x < TT * CT; x++) acc[x] = f32x4{0, 0, 0, 0};
+    for (int p = p0 + w; p < p1; p += MV_WAVES) {
+      const int j = A.Lj[p];
+      const int kj = A.kcol[j];
+      const unsigned short *Bp = Bv + A.boff[p];
+      const float *qj = qh + A.hcol[j] * RP + lr;
+      for (int s0 = 0; s0 < kj; s0 += 32) {
+        const int kb = s0 + 8 * lk;
+        bf16x8 bv[CT], av[TT];
+#pragma unroll
+        for (int c = 0; c < CT; c++)
+#pragma unroll
+          for (int jj = 0; jj < 8; jj++)
+            bv[c][jj] = (__bf16)(kb + jj < kj ? qj[(int64_t)(kb + jj) * RP + 16 * c] : 0.0f);
+#pragma unroll
+        for (int tt = 0; tt < TT; tt++) {
+          const int t = t0 + tt * 16 + lr;
+          av[tt] = (kb < kj && t < ki) ? load_bf16x8(Bp + ((kb >> 3) * ki + t) * 8) : zero_bf16x8();
+        }
+#pragma unroll
+        for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+          for (int c = 0; c < CT; c++) acc[tt * CT + c] = mfma_bf16(av[tt], bv[c], acc[tt * CT + c]);
+      }
+    }
+    reduce_waves_n<float, MV_WAVES, TT * CT>(acc, red);
+    if (w == 0)
+#pragma unroll
+      for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int t = t0 + tt * 16 + 4 * lk + e;
+          if (t < ki)
+#pragma unroll
+            for (int c = 0; c < CT; c++) out[(int64_t)t * RP + 16 * c] = acc[tt * CT + c][e];
+        }
+  }
+}
+
+// near field + scatter: as k_mv_near_out, K in chunks of 32
+template <int TT, int CT>
+__global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_near_out(NearArgs A,
+                                                                  const float *__restrict__ q,
+                                                                  const float *__restrict__ z,
+                                                                  float *__restrict__ Y,
+                                                                  int64_t ldy, int R, int RP,
+                                                                  int nitems) {
+  __shared__ float red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
+  const int it = item_of_block(blockIdx.x, nitems);
+  if (it >= nitems) return;
+  const int i = A.i0 + it;
+  if (A.nchild[i] != 0) return;
+  const int xb = A.xb[i], ni = A.xe[i] - xb;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
+  const unsigned short *Bv = (const unsigned short *)A.Bn;
+  const int p0 = A.Lmrow[i], p1 = A.Lmrow[i + 1];
+  for (int a0 = 0; a0 < ni; a0 += 16 * TT) {
+    f32x4 acc[TT * CT];
+#pragma unroll
+    for (int x = 0; x < TT * CT; x++) acc[x] = f32x4{0, 0, 0, 0};
+    for (int p = p0 + w; p < p1; p += MV_WAVES) {
+      const int j = A.Lmj[p];
+      const int yb = A.yb[j], nj = A.ye[j] - yb;
+      const unsigned short *Bp = Bv + A.nboff[p];
+      const float *qj = q + (int64_t)yb * RP + lr;
+      for (int b0 = 0; b0 < nj; b0 += 32) {
+        const int kb = b0 + 8 * lk;
+        bf16x8 bv[CT], av[TT];
+#pragma unroll
+        for (int c = 0; c < CT; c++)
+#pragma unroll
+          for (int jj = 0; jj < 8; jj++)
+            bv[c][jj] = (__bf16)(kb + jj < nj ? qj[(int64_t)(kb + jj) * RP + 16 * c] : 0.0f);
+#pragma unroll
+        for (int tt = 0; tt < TT; tt++) {
+          const int a = a0 + tt * 16 + lr;
+          av[tt] = (kb < nj && a < ni) ? load_bf16x8(Bp + ((kb >> 3) * ni + a) * 8) : zero_bf16x8();
+        }
+#pragma unroll
+        for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+          for (int c = 0; c < CT; c++) acc[tt * CT + c] = mfma_bf16(av[tt], bv[c], acc[tt * CT + c]);
+      }
+    }
+    reduce_waves_n<float, MV_WAVES, TT * CT>(acc, red);
+    if (w == 0)
+#pragma unroll
+      for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int a = a0 + tt * 16 + 4 * lk + e;
+          if (a < ni) {
+            const int64_t yrow = (int64_t)A.perm_x[xb + a] * ldy;
+#pragma unroll
+            for (int c = 0; c < CT; c++) {
+              const int col = 16 * c + lr;
+              if (col < R) {
+                float v = acc[tt * CT + c][e];
+                if (A.has_far) v += z[(int64_t)(xb + a) * RP + col];
+                Y[yrow + col] = v;
+              }
+            }
+          }
+        }
+  }
+}
+
+template <int CT>
+static void launch_bf16_blocks(const CouplingArgs *ca, const NearArgs *na, const float *q,
+                               float *z, float *Y, int64_t ldy, int R, int RP, int nitems,
+                               hipStream_t s) {
+  constexpr int TT = CT >= 3 ? 2 : 4;
+  if (ca)
+    k_mvb_coupling<TT, CT><<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(*ca, q, z, RP, nitems);
+  else
+    k_mvb_near_out<TT, CT>
+        <<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(*na, q, z, Y, ldy, R, RP, nitems);
+  SMASH_CHECK_LAUNCH();
+}
+
+static void matvec_chunk_bf16(Handle &h, const float *X, int64_t ldx, int R, float *Y,
+                              int64_t ldy, float *q, float *z, hipStream_t s) {
+  Side &Rw = h.row, &Cl = *h.col;
+  const int RP = (R + 15) / 16 * 16;
+  const int ct = RP / 16;
+  {
+    PhaseTimer pt(h, SMASH_PHASE_MV_GATHER, s);
+    k_mv_gather<float><<<ceil_div(h.ny * RP, 256), 256, 0, s>>>(X, ldx, h.perm_y, h.ny, R, RP, q);
+    SMASH_CHECK_LAUNCH();
+  }
+  auto blocks = [&](const CouplingArgs *ca, const NearArgs *na, int nitems) {
+    switch (ct) {
+      case 1: launch_bf16_blocks<1>(ca, na, q, z, Y, ldy, R, RP, nitems, s); break;
+      case 2: launch_bf16_blocks<2>(ca, na, q, z, Y, ldy, R, RP, nitems, s); break;
+      case 3: launch_bf16_blocks<3>(ca, na, q, z, Y, ldy, R, RP, nitems, s); break;
+      default: launch_bf16_blocks<4>(ca, na, q, z, Y, ldy, R, RP, nitems, s); break;
+    }
+  };
+  const bool has_far = h.nlevels >= 2;
+  if (has_far) {
+    {
+      PhaseTimer pt(h, SMASH_PHASE_MV_UP, s);
+      for (int l = h.nlevels; l >= 2; l--) {
+        const int nb = h.level_beg[l - 1], ne = h.level_beg[l];
+        const LevelSide &L = Cl.lv[l];
+        SweepArgsB sa{nb, ne, Cl.m, Cl.k, h.nchild, Cl.gbeg, Cl.hbeg, Cl.selo, Cl.gobu, Cl.gobd,
+                      L.sel, L.Gbu, L.Gbd};
+        const bool split = ne - nb <= h.mv_split_nodes;
+        auto up = [&](int nodes) {
+          if (split)
+            k_mvb_up<4><<<dim3(nodes, ct), 4 * MV_NT, 0, s>>>(sa, q, q, RP);
+          else
+            k_mvb_up<1><<<dim3(nodes, ct), MV_NT, 0, s>>>(sa, q, q, RP);
+          SMASH_CHECK_LAUNCH();
+        };
+        if (h.batched) {
+          up(ne - nb);
+        } else {
+          for (int i = nb; i < ne; i++) {
+            sa.nb = i;
+            sa.ne = i + 1;
+            up(1);
+          }
+        }
+      }
+    }
+    CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
+    {
+      PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
+      if (h.batched) {
+        blocks(&ca, nullptr, h.nnodes - 1);
+      } else {
+        for (int i = 1; i < h.nnodes; i++) {
+          ca.i0 = i;
+          blocks(&ca, nullptr, 1);
+        }
+      }
+    }
+    PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
+    for (int l = 2; l <= h.nlevels; l++) {
+      const int nb = h.level_beg[l - 1], ne = h.level_beg[l];
+      const LevelSide &L = Rw.lv[l];
+      SweepArgsB sa{nb, ne, Rw.m, Rw.k, h.nchild, Rw.gbeg, Rw.hbeg, Rw.selo, Rw.gobu, Rw.gobd,
+                    L.sel, L.Gbu, L.Gbd};
+      const bool split = ne - nb <= h.mv_split_nodes;
+      auto down = [&](int nodes) {
+        if (split)
+          k_mvb_down<4><<<dim3(nodes, ct), 4 * MV_NT, 0, s>>>(sa, z, z, RP);
+        else
+          k_mvb_down<1><<<dim3(nodes, ct), MV_NT, 0, s>>>(sa, z, z, RP);
+        SMASH_CHECK_LAUNCH();
+      };
+      if (h.batched) {
+        down(ne - nb);
+      } else {
+        for (int i = nb; i < ne; i++) {
+          sa.nb = i;
+          sa.ne = i + 1;
+          down(1);
+        }
+      }
+    }
+  }
+  NearArgs na{0, h.nnodes, h.nchild, h.xb, h.xe, h.yb, h.ye, h.perm_x, h.Lmrow, h.Lmj, h.nboff,
+              h.Bn, has_far ? 1 : 0};
+  PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
+  if (h.batched) {
+    blocks(nullptr, &na, h.nnodes);
+  } else {
+    for (int i = 0; i < h.nnodes; i++) {
+      na.i0 = i;
+      blocks(nullptr, &na, 1);
+    }
+  }
+}
+
 template <class T>
 static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_t ldy, T *q,
                          T *z, hipStream_t s) {
@@ -566,7 +937,11 @@ static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t
   T *q = (T *)h.qbuf, *z = (T *)h.zbuf;
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int R = nrhs - c0 < chunk ? nrhs - c0 : chunk;
-    matvec_chunk<T>(h, X + c0, ldx, R, Y + c0, ldy, q, z, s);
+    if (h.apply_prec == SMASH_BF16)
+      matvec_chunk_bf16(h, (const float *)(X + c0), ldx, R, (float *)(Y + c0), ldy, (float *)q,
+                        (float *)z, s);
+    else
+      matvec_chunk<T>(h, X + c0, ldx, R, Y + c0, ldy, q, z, s);
   }
 }
 

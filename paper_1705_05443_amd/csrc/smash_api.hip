@@ -100,8 +100,8 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
   double tau = opt.tau > 0.0 ? opt.tau : (dim == 1 ? 0.6 : 0.7);
   if (!(tau > 0.0 && tau < 1.0)) return fail(SMASH_E_INVALID_ARG, "tau must lie in (0, 1)");
   if (!(opt.srrqr_f > 1.0)) return fail(SMASH_E_INVALID_ARG, "srrqr_f must exceed 1");
-  if (opt.apply_prec != SMASH_F64 && opt.apply_prec != SMASH_F32)
-    return fail(SMASH_E_INVALID_ARG, "apply_prec must be SMASH_F64 or SMASH_F32");
+  if (opt.apply_prec != SMASH_F64 && opt.apply_prec != SMASH_F32 && opt.apply_prec != SMASH_BF16)
+    return fail(SMASH_E_INVALID_ARG, "apply_prec must be SMASH_F64, SMASH_F32 or SMASH_BF16");
   if (opt.eval_prec != SMASH_F64 && opt.eval_prec != SMASH_F32)
     return fail(SMASH_E_INVALID_ARG, "eval_prec must be SMASH_F64 or SMASH_F32");
   if (opt.has_root_box && !(opt.root_side >= 0.0 && std::isfinite(opt.root_side)))
@@ -199,8 +199,8 @@ extern "C" int smash_matvec(smash_handle hv, const void *X, int64_t ldx, int32_t
   if (!X || !Y) return fail(SMASH_E_INVALID_ARG, "X or Y is NULL");
   if (nrhs < 1) return fail(SMASH_E_INVALID_ARG, "nrhs must be >= 1");
   if (ldx < nrhs || ldy < nrhs) return fail(SMASH_E_INVALID_ARG, "leading dimension < nrhs");
-  if (dtype != h->apply_prec)
-    return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's apply precision");
+  if (dtype != (h->apply_prec == SMASH_F64 ? SMASH_F64 : SMASH_F32))
+    return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's vector precision");
   try {
     run_matvec(*h, X, ldx, nrhs, Y, ldy, (hipStream_t)stream);
     return SMASH_OK;
@@ -396,6 +396,8 @@ extern "C" int smash_export(smash_handle hv, int32_t what, void *buf, int64_t *c
       case SMASH_EX_COUPLING:
       case SMASH_EX_NEAR: {
         kind = 2;
+        if (h->apply_prec == SMASH_BF16)
+          return fail(SMASH_E_UNSUPPORTED, "blocks of a BF16-apply handle are not exported");
         int64_t n = what == SMASH_EX_COUPLING ? h->b_entries : h->n_entries;
         const void *src = what == SMASH_EX_COUPLING ? h->B : h->Bn;
         if (h->apply_prec == SMASH_F64)

@@ -231,6 +231,29 @@ def test_matvec_fp32_apply(name):
         assert relerr(z_g, z_o) < 1e-5, nrhs
 
 
+@pytest.mark.parametrize("name", ["h2_2d_log", "h2_3d_clusters", "hss_cauchy_xy", "hss1d_cfg"])
+def test_matvec_bf16_apply(name):
+    """BF16 G copies and blocks on the BF16 matrix cores with FP32 vectors and
+    accumulation.  BF16 keeps 8 significand bits (unit roundoff 2^-9), so the
+    product is expected within a few 1e-3 of the FP64 oracle; the bound is
+    2e-2.  The construction is the FP64 one: skeletons equal the oracle's."""
+    mk, kw = CASES[name]
+    x, y = mk()
+    o = O.Oracle(x, y, **_oracle_kwargs(kw))
+    g = api.Smash(dev(x), None if y is None else dev(y), apply_prec="bf16", eval_prec="f32",
+                  **kw)
+    assert np.array_equal(g.export("ranks").reshape(-1, 6)[1:, :4], o.ranks()[1:, :4])
+    errs = []
+    for nrhs in (1, 16, 40, 64):
+        q32 = W.rhs(g.ny, nrhs, seed=4).astype(np.float32)
+        z_o = o.matvec(q32.astype(np.float64))
+        z_g = g.matvec(torch.from_numpy(q32).cuda()).cpu().numpy().astype(np.float64)
+        assert np.isfinite(z_g).all()
+        errs.append(relerr(z_g, z_o))
+    print(name, "BF16 apply rel. error vs FP64 oracle", ["%.2e" % e for e in errs])
+    assert max(errs) < 2e-2, errs
+
+
 def test_full_size_h2_2d_log_65536():
     """The benchmark workload at full size: bit-exact tree/lists/skeletons,
     FP64 product within 1e-10 of the oracle, and within the tolerance of
