@@ -485,10 +485,10 @@ __global__ void __launch_bounds__(MV_NT *W) k_mvb_up(SweepArgsB A, const float *
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = f32x4{0, 0, 0, 0};
     for (int a0 = 32 * w; a0 < nr; a0 += 32 * W) {
       const int kb = a0 + 8 * lk;
-      bf16x8 bv;
+      float xv[8];
 #pragma unroll
-      for (int j = 0; j < 8; j++)
-        bv[j] = (__bf16)(kb + j < nr ? g[(int64_t)sel[k + kb + j] * RP + col] : 0.0f);
+      for (int j = 0; j < 8; j++) xv[j] = g[(int64_t)sel[k + (kb + j < nr ? kb + j : 0)] * RP + col];
+      bf16x8 bv;
       bf16x8 av[MV_TILES];
 #pragma unroll
       for (int tt = 0; tt < MV_TILES; tt++) {
@@ -496,6 +496,8 @@ __global__ void __launch_bounds__(MV_NT *W) k_mvb_up(SweepArgsB A, const float *
         av[tt] = (kb < nr && t < k) ? load_bf16x8(H + ((int64_t)(kb >> 3) * k + t) * 8)
                                     : zero_bf16x8();
       }
+#pragma unroll
+      for (int j = 0; j < 8; j++) bv[j] = (__bf16)(kb + j < nr ? xv[j] : 0.0f);
 #pragma unroll
       for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = mfma_bf16(av[tt], bv, acc[tt]);
     }
@@ -542,9 +544,10 @@ __global__ void __launch_bounds__(MV_NT *W) k_mvb_down(SweepArgsB A, const float
     for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = f32x4{0, 0, 0, 0};
     for (int t0 = 0; t0 < k; t0 += 32) {
       const int kb = t0 + 8 * lk;
-      bf16x8 bv;
+      float xv[8];
 #pragma unroll
-      for (int j = 0; j < 8; j++) bv[j] = (__bf16)(kb + j < k ? zh[(int64_t)(kb + j) * RP + col] : 0.0f);
+      for (int j = 0; j < 8; j++) xv[j] = zh[(int64_t)(kb + j < k ? kb + j : 0) * RP + col];
+      bf16x8 bv;
       bf16x8 av[MV_TILES];
 #pragma unroll
       for (int tt = 0; tt < MV_TILES; tt++) {
@@ -552,6 +555,8 @@ __global__ void __launch_bounds__(MV_NT *W) k_mvb_down(SweepArgsB A, const float
         av[tt] = (kb < k && a < nr) ? load_bf16x8(Gd + ((int64_t)(kb >> 3) * nr + a) * 8)
                                     : zero_bf16x8();
       }
+#pragma unroll
+      for (int j = 0; j < 8; j++) bv[j] = (__bf16)(kb + j < k ? xv[j] : 0.0f);
 #pragma unroll
       for (int tt = 0; tt < MV_TILES; tt++) acc[tt] = mfma_bf16(av[tt], bv, acc[tt]);
     }
@@ -599,17 +604,24 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_coupling(CouplingArgs A
       const float *qj = qh + A.hcol[j] * RP + lr;
       for (int s0 = 0; s0 < kj; s0 += 32) {
         const int kb = s0 + 8 * lk;
-        bf16x8 bv[CT], av[TT];
+        float xv[CT][8];
 #pragma unroll
         for (int c = 0; c < CT; c++)
 #pragma unroll
           for (int jj = 0; jj < 8; jj++)
-            bv[c][jj] = (__bf16)(kb + jj < kj ? qj[(int64_t)(kb + jj) * RP + 16 * c] : 0.0f);
+            xv[c][jj] = qj[(int64_t)(kb + jj < kj ? kb + jj : 0) * RP + 16 * c];
+        bf16x8 bv[CT], av[TT];
 #pragma unroll
         for (int tt = 0; tt < TT; tt++) {
           const int t = t0 + tt * 16 + lr;
           av[tt] = (kb < kj && t < ki) ? load_bf16x8(Bp + ((kb >> 3) * ki + t) * 8) : zero_bf16x8();
         }
+        // vector rows are loaded unconditionally (index clamped into the
+        // block) and masked when converted, so no load waits on a branch
+#pragma unroll
+        for (int c = 0; c < CT; c++)
+#pragma unroll
+          for (int jj = 0; jj < 8; jj++) bv[c][jj] = (__bf16)(kb + jj < kj ? xv[c][jj] : 0.0f);
 #pragma unroll
         for (int tt = 0; tt < TT; tt++)
 #pragma unroll
@@ -659,17 +671,22 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_near_out(NearArgs A,
       const float *qj = q + (int64_t)yb * RP + lr;
       for (int b0 = 0; b0 < nj; b0 += 32) {
         const int kb = b0 + 8 * lk;
-        bf16x8 bv[CT], av[TT];
+        float xv[CT][8];
 #pragma unroll
         for (int c = 0; c < CT; c++)
 #pragma unroll
           for (int jj = 0; jj < 8; jj++)
-            bv[c][jj] = (__bf16)(kb + jj < nj ? qj[(int64_t)(kb + jj) * RP + 16 * c] : 0.0f);
+            xv[c][jj] = qj[(int64_t)(kb + jj < nj ? kb + jj : 0) * RP + 16 * c];
+        bf16x8 bv[CT], av[TT];
 #pragma unroll
         for (int tt = 0; tt < TT; tt++) {
           const int a = a0 + tt * 16 + lr;
           av[tt] = (kb < nj && a < ni) ? load_bf16x8(Bp + ((kb >> 3) * ni + a) * 8) : zero_bf16x8();
         }
+#pragma unroll
+        for (int c = 0; c < CT; c++)
+#pragma unroll
+          for (int jj = 0; jj < 8; jj++) bv[c][jj] = (__bf16)(kb + jj < nj ? xv[c][jj] : 0.0f);
 #pragma unroll
         for (int tt = 0; tt < TT; tt++)
 #pragma unroll
