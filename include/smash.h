@@ -80,6 +80,10 @@ typedef struct smash_handle_s *smash_handle;
  *                most this many nodes runs each node on four wavefronts
  *                (long grids, few nodes), a larger one on one wavefront per
  *                node; default 1024, 0 never splits
+ *   graphs       1 (default): smash_matvec captures its launch sequence into a
+ *                HIP graph on the second call with the same (X, ldx, nrhs, Y,
+ *                ldy) and replays it from then on (the eight most recent
+ *                argument sets are kept; not with timing); 0: always eager
  */
 typedef struct smash_options {
   uint32_t struct_size; /* sizeof(smash_options) */
@@ -96,6 +100,7 @@ typedef struct smash_options {
   int32_t batched;
   int32_t timing;
   int32_t mv_split_nodes;
+  int32_t graphs;
 } smash_options;
 
 int smash_default_options(smash_options *opt);
@@ -152,6 +157,7 @@ typedef struct smash_info_t {
    * summed over the build and every product so far (SMASH_PHASE_*) */
   double phase_ms[16];
   int64_t phase_calls[16];
+  int64_t graph_captures, graph_replays; /* products captured / replayed as graphs */
 } smash_info_t;
 
 #define SMASH_PHASE_TREE 0

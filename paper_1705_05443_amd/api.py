@@ -37,7 +37,7 @@ class Options(C.Structure):
                 ("apply_prec", C.c_int32), ("has_root_box", C.c_int32),
                 ("root_lo", C.c_double * 3), ("root_side", C.c_double), ("max_depth", C.c_int32),
                 ("batched", C.c_int32), ("timing", C.c_int32),
-                ("mv_split_nodes", C.c_int32)]
+                ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -51,7 +51,8 @@ class Info(C.Structure):
                 ("device_bytes", C.c_int64), ("total_swaps", C.c_int64),
                 ("apply_prec", C.c_int32), ("eval_prec", C.c_int32),
                 ("symmetric_reuse", C.c_int32), ("build_ms", C.c_double),
-                ("phase_ms", C.c_double * 16), ("phase_calls", C.c_int64 * 16)]
+                ("phase_ms", C.c_double * 16), ("phase_calls", C.c_int64 * 16),
+                ("graph_captures", C.c_int64), ("graph_replays", C.c_int64)]
 
 PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", "mv_up",
           "mv_coupling", "mv_down", "mv_near_out"]
@@ -106,7 +107,7 @@ class Smash:
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
                  root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
-                 stream=None):
+                 graphs=True, stream=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -140,6 +141,7 @@ class Smash:
         opt.timing = 1 if timing else 0
         if mv_split_nodes is not None:
             opt.mv_split_nodes = int(mv_split_nodes)
+        opt.graphs = 1 if graphs else 0
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
         self.ny = x.shape[0] if y is None else y.shape[0]
@@ -173,6 +175,10 @@ class Smash:
         R = X.shape[1]
         if out is None:
             out = torch.empty((self.nx, R), dtype=dt, device=X.device)
+        elif (not out.is_cuda or out.dtype != dt or out.dim() != 2
+              or tuple(out.shape) != (self.nx, R) or out.stride(1) != 1):
+            raise TypeError("out must be a CUDA (nx, nrhs) tensor of the vector precision "
+                            "with unit column stride")
         _check(lib().smash_matvec(self._h, C.c_void_p(X.data_ptr()), X.stride(0), R,
                                   PREC["f64" if self.apply_prec == "f64" else "f32"],
                                   C.c_void_p(out.data_ptr()),

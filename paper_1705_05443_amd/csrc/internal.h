@@ -103,6 +103,16 @@ struct Side {
   int max_k = 0;
 };
 
+struct GraphEntry {
+  const void *X;
+  int64_t ldx;
+  int nrhs;
+  void *Y;
+  int64_t ldy;
+  int calls;
+  hipGraphExec_t exec;
+};
+
 struct Handle {
   // problem
   int d = 0, kid = 0, adm = 0, leaf = 0, p = 0;
@@ -142,6 +152,11 @@ struct Handle {
   int64_t total_swaps = 0;
   double build_ms = 0;
   // product workspaces
+  // captured products (options.graphs): one executable graph per argument set
+  int use_graphs = 1;
+  std::vector<GraphEntry> graphs;
+  hipStream_t cap_stream = nullptr;
+  int64_t graph_captures = 0, graph_replays = 0;
   int ws_nrhs = 0;
   void *qbuf = nullptr, *zbuf = nullptr;
   DeviceArena ws_mem;
@@ -186,5 +201,6 @@ void build_generators(Handle &h);
 void build_blocks(Handle &h);
 void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                 hipStream_t s);
+void drop_graphs(Handle &h);  // destroys captured products (synchronizes the device)
 
 }  // namespace smash

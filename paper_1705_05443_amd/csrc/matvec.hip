@@ -937,20 +937,26 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
   }
 }
 
+// Workspace: q and z in slot space, 64 right-hand sides per pass.  Returns
+// true when it was (re)allocated, which invalidates captured graphs.
+static bool ensure_workspace(Handle &h, int nrhs, hipStream_t s) {
+  const int RC = 64;
+  const int chunk = nrhs < RC ? nrhs : RC;
+  const int cp = (chunk + 15) / 16 * 16;
+  if (h.ws_nrhs >= cp) return false;
+  h.ws_mem.release();  // on the stream that allocated it
+  h.ws_mem.stream = s;
+  h.qbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.col->nslots * cp);
+  h.zbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.row.nslots * cp);
+  h.ws_nrhs = cp;
+  return true;
+}
+
 template <class T>
 static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t ldy,
                      hipStream_t s) {
   const int RC = 64;  // right-hand sides per pass through the tree
-  Side &Rw = h.row, &Cl = *h.col;
-  int chunk = nrhs < RC ? nrhs : RC;
-  int cp = (chunk + 15) / 16 * 16;
-  if (h.ws_nrhs < cp) {
-    h.ws_mem.release();  // on the stream that allocated it
-    h.ws_mem.stream = s;
-    h.qbuf = h.ws_mem.alloc(sizeof(double) * (size_t)Cl.nslots * cp);
-    h.zbuf = h.ws_mem.alloc(sizeof(double) * (size_t)Rw.nslots * cp);
-    h.ws_nrhs = cp;
-  }
+  const int chunk = nrhs < RC ? nrhs : RC;
   T *q = (T *)h.qbuf, *z = (T *)h.zbuf;
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int R = nrhs - c0 < chunk ? nrhs - c0 : chunk;
@@ -962,12 +968,71 @@ static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t
   }
 }
 
-void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
-                hipStream_t s) {
+static void launch_sequence(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y,
+                            int64_t ldy, hipStream_t s) {
   if (h.apply_prec == SMASH_F64)
     matvec_t<double>(h, (const double *)X, ldx, nrhs, (double *)Y, ldy, s);
   else
     matvec_t<float>(h, (const float *)X, ldx, nrhs, (float *)Y, ldy, s);
+}
+
+void drop_graphs(Handle &h) {
+  if (h.graphs.empty()) return;
+  (void)hipDeviceSynchronize();  // a replay may still run on any stream
+  for (auto &g : h.graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  h.graphs.clear();
+}
+
+// The product.  Eager launches, or -- with the graphs option and timing off
+// -- the same launch sequence captured once into a HIP graph on the second
+// call with the same arguments and replayed from then on (one graph launch
+// instead of 2 + 2(levels - 1) + 2 kernel launches per 64 right-hand sides).
+void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
+                hipStream_t s) {
+  if (ensure_workspace(h, nrhs, s)) drop_graphs(h);
+  if (!h.use_graphs || h.timing) {
+    launch_sequence(h, X, ldx, nrhs, Y, ldy, s);
+    return;
+  }
+  GraphEntry *e = nullptr;
+  for (auto &g : h.graphs)
+    if (g.X == X && g.ldx == ldx && g.nrhs == nrhs && g.Y == Y && g.ldy == ldy) e = &g;
+  if (!e) {
+    if (h.graphs.size() >= 8) {  // keep the eight most recent argument sets
+      (void)hipDeviceSynchronize();
+      if (h.graphs.front().exec) (void)hipGraphExecDestroy(h.graphs.front().exec);
+      h.graphs.erase(h.graphs.begin());
+    }
+    h.graphs.push_back(GraphEntry{X, ldx, nrhs, Y, ldy, 0, nullptr});
+    e = &h.graphs.back();
+  }
+  e->calls++;
+  if (!e->exec && e->calls < 2) {
+    launch_sequence(h, X, ldx, nrhs, Y, ldy, s);
+    return;
+  }
+  if (!e->exec) {
+    if (!h.cap_stream) SMASH_HIP(hipStreamCreateWithFlags(&h.cap_stream, hipStreamNonBlocking));
+    SMASH_HIP(hipStreamBeginCapture(h.cap_stream, hipStreamCaptureModeThreadLocal));
+    hipGraph_t g = nullptr;
+    try {
+      launch_sequence(h, X, ldx, nrhs, Y, ldy, h.cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(h.cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    SMASH_HIP(hipStreamEndCapture(h.cap_stream, &g));
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    SMASH_HIP(ie);
+    e->exec = ex;
+    h.graph_captures++;
+  }
+  SMASH_HIP(hipGraphLaunch(e->exec, s));
+  h.graph_replays++;
 }
 
 }  // namespace smash

@@ -34,6 +34,7 @@ extern "C" int smash_default_options(smash_options *opt) {
   opt->batched = 1;
   opt->timing = 0;
   opt->mv_split_nodes = 1024;
+  opt->graphs = 1;
   return SMASH_OK;
 }
 
@@ -55,6 +56,8 @@ void resolve_timers(Handle &h) {
 static void free_handle(Handle *h) {
   if (!h) return;
   resolve_timers(*h);
+  drop_graphs(*h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   (void)hipStreamSynchronize(h->stream);
   h->ws_mem.release();
   h->mem.release();
@@ -132,6 +135,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->batched = opt.batched ? 1 : 0;
     h->timing = opt.timing != 0;
     h->mv_split_nodes = opt.mv_split_nodes;
+    h->use_graphs = opt.graphs ? 1 : 0;
     h->nx = nx;
     h->ny = ny;
     h->same_xy = same;
@@ -239,6 +243,8 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
     info->build_ms = h->build_ms;
     info->total_swaps = h->total_swaps;
     info->device_bytes = h->mem.bytes + h->ws_mem.bytes;
+    info->graph_captures = h->graph_captures;
+    info->graph_replays = h->graph_replays;
     resolve_timers(*h);
     for (int q = 0; q < 16; q++) {
       info->phase_ms[q] = h->phase_ms[q];

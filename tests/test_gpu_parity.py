@@ -297,3 +297,33 @@ def test_errors_from_device_checks():
     with pytest.raises(api.SmashError) as e:
         api.Smash(dev(x), kernel="inv_r", leaf=8, order=4, adm="strong", tol=1e-6)
     assert e.value.code == -5
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_matvec_graph_replays_match_eager(prec):
+    """The product replayed from its captured HIP graph equals the eager
+    launch sequence bit for bit, on every replay, with eager work and
+    synchronizations in between; a new argument set or a larger workspace
+    captures again."""
+    mk, kw = CASES["h2_2d_log"]
+    x, _ = mk()
+    dt = torch.float64 if prec == "f64" else torch.float32
+    ev = "f64" if prec == "f64" else "f32"
+    ge = api.Smash(dev(x), apply_prec=prec, eval_prec=ev, graphs=False, **kw)
+    gg = api.Smash(dev(x), apply_prec=prec, eval_prec=ev, graphs=True, **kw)
+    for nrhs in (16, 80):
+        Q = dev(W.rhs(len(x), nrhs, seed=11)).to(dt)
+        Q2 = dev(W.rhs(len(x), nrhs, seed=12)).to(dt)
+        ref = ge.matvec(Q)
+        out = torch.empty_like(ref)
+        for rep in range(5):
+            gg.matvec(Q, out=out)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), (nrhs, rep)
+            other = ge.matvec(Q2)  # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.isfinite(other).all()
+    inf = gg.info()
+    assert inf["graph_captures"] == 2 and inf["graph_replays"] == 8, inf
+    gg.close()
+    ge.close()
