@@ -80,6 +80,9 @@ typedef struct smash_handle_s *smash_handle;
  *                most this many nodes runs each node on four wavefronts
  *                (long grids, few nodes), a larger one on one wavefront per
  *                node; default 1024, 0 never splits
+ *   mv_xcd_run   launch shape of the coupling and near products: workgroups
+ *                go to the 8 XCDs in runs of this many consecutive nodes
+ *                (tree-order neighbours share an L2); default 16, in [1, 4096]
  *   graphs       1 (default): smash_matvec captures its launch sequence into a
  *                HIP graph on the second call with the same (X, ldx, nrhs, Y,
  *                ldy) and replays it from then on (the eight most recent
@@ -101,6 +104,7 @@ typedef struct smash_options {
   int32_t timing;
   int32_t mv_split_nodes;
   int32_t graphs;
+  int32_t mv_xcd_run;
 } smash_options;
 
 int smash_default_options(smash_options *opt);
@@ -134,6 +138,13 @@ int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int
  * Asynchronous on `stream`; workspaces are owned by the handle. */
 int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
                  void *Y, int64_t ldy, void *stream);
+
+/* Launch shape of the products of an existing handle (the options
+ * mv_split_nodes and mv_xcd_run), as an autotuner sets it between timed
+ * products.  The numbers are unchanged up to the summation order of the
+ * split sweeps.  Drops captured graphs (synchronizes the device).
+ * Errors: SMASH_E_INVALID_ARG for a NULL handle or out-of-range values. */
+int smash_set_product_shape(smash_handle h, int32_t mv_split_nodes, int32_t mv_xcd_run);
 
 /* Sizes and statistics of a construction (host struct). */
 typedef struct smash_info_t {

@@ -37,7 +37,8 @@ class Options(C.Structure):
                 ("apply_prec", C.c_int32), ("has_root_box", C.c_int32),
                 ("root_lo", C.c_double * 3), ("root_side", C.c_double), ("max_depth", C.c_int32),
                 ("batched", C.c_int32), ("timing", C.c_int32),
-                ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32)]
+                ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32),
+                ("mv_xcd_run", C.c_int32)]
 
 
 class Info(C.Structure):
@@ -60,7 +61,8 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-            "smash_info", "smash_export", "smash_destroy", "smash_last_error"]
+            "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
+            "smash_last_error"]
 
 
 def lib():
@@ -79,12 +81,13 @@ def lib():
                                      C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                      C.POINTER(Options), vp, C.POINTER(vp)]
         L.smash_matvec.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, vp]
+        L.smash_set_product_shape.argtypes = [vp, C.c_int32, C.c_int32]
         L.smash_info.argtypes = [vp, C.POINTER(Info)]
         L.smash_export.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int64)]
         L.smash_destroy.argtypes = [vp]
         L.smash_last_error.restype = C.c_char_p
         for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-                  "smash_info", "smash_export", "smash_destroy"):
+                  "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -102,12 +105,20 @@ def _stream_ptr(stream):
 
 
 class Smash:
-    """A device-resident SMASH construction (the C handle)."""
+    """A device-resident SMASH construction (the C handle).
+
+    x, y: CUDA float64 point arrays (n x dim); y None means Y = X.  The
+    remaining keywords map onto smash_build's arguments and smash_options
+    (include/smash.h).  tuned: take the product's launch shape from the
+    autotuner table (autotune.lookup) for this size bin, with nrhs_hint as
+    the expected right-hand-side count; explicit mv_split_nodes / mv_xcd_run
+    win.  graphs: replay repeated products from captured HIP graphs.
+    """
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
                  root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
-                 graphs=True, stream=None):
+                 mv_xcd_run=None, graphs=True, tuned=True, nrhs_hint=16, stream=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -139,8 +150,19 @@ class Smash:
         opt.max_depth = max_depth
         opt.batched = 1 if batched else 0
         opt.timing = 1 if timing else 0
+        if tuned and (mv_split_nodes is None or mv_xcd_run is None):
+            from . import autotune
+            ny_ = x.shape[0] if y is None else y.shape[0]
+            shp = autotune.lookup(max(x.shape[0], ny_), x.shape[1], adm, apply_prec, nrhs_hint)
+            if shp:
+                if mv_split_nodes is None:
+                    mv_split_nodes = shp["mv_split_nodes"]
+                if mv_xcd_run is None:
+                    mv_xcd_run = shp["mv_xcd_run"]
         if mv_split_nodes is not None:
             opt.mv_split_nodes = int(mv_split_nodes)
+        if mv_xcd_run is not None:
+            opt.mv_xcd_run = int(mv_xcd_run)
         opt.graphs = 1 if graphs else 0
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
@@ -184,6 +206,10 @@ class Smash:
                                   C.c_void_p(out.data_ptr()),
                                   out.stride(0), _stream_ptr(stream)))
         return out[:, 0] if vec else out
+
+    def set_product_shape(self, mv_split_nodes, mv_xcd_run):
+        """Launch shape of the products (see smash_set_product_shape)."""
+        _check(lib().smash_set_product_shape(self._h, int(mv_split_nodes), int(mv_xcd_run)))
 
     def info(self):
         inf = Info()

@@ -118,6 +118,7 @@ struct Handle {
   int d = 0, kid = 0, adm = 0, leaf = 0, p = 0;
   double tol = 0, tau = 0, eps_svd = 0, f = 2, diag = 0;
   int eval_prec = SMASH_F64, apply_prec = SMASH_F64, batched = 1, mv_split_nodes = 1024;
+  int mv_xcd_run = 16;
   int64_t nx = 0, ny = 0;
   bool same_xy = false, reuse = false;
   int device = 0;

@@ -157,23 +157,22 @@ struct CouplingArgs {
   const int *krow, *kcol;
   const int64_t *hrow, *hcol;
   const void *B;
+  int xrun;
 };
 
 // Workgroups are dealt to the eight XCDs round-robin.  This maps them so
-// that each XCD (and its L2) takes runs of XCD_RUN consecutive items --
+// that each XCD (and its L2) takes runs of `run` consecutive items --
 // spatial neighbours in the tree order, which read the same vector rows --
 // while the runs still interleave over the XCDs in item order, which keeps
-// the levels (and so the work) balanced between them.
-constexpr int XCD_RUN = 16;
-__device__ __forceinline__ int xcd_item(int b) {
+// the levels (and so the work) balanced between them.  The run length is a
+// launch-shape option (mv_xcd_run); fewer than 8 * run items map 1:1.
+__device__ __forceinline__ int item_of_block(int b, int nitems, int run) {
+  if (nitems < 8 * run) return b;
   const int q = b >> 3;
-  return (q / XCD_RUN) * (8 * XCD_RUN) + (b & 7) * XCD_RUN + q % XCD_RUN;
+  return (q / run) * (8 * run) + (b & 7) * run + q % run;
 }
-__device__ __forceinline__ int item_of_block(int b, int nitems) {
-  return nitems < 8 * XCD_RUN ? b : xcd_item(b);
-}
-static inline int xcd_grid(int nitems) {
-  return nitems < 8 * XCD_RUN ? nitems : (nitems + 8 * XCD_RUN - 1) / (8 * XCD_RUN) * (8 * XCD_RUN);
+static inline int xcd_grid(int nitems, int run) {
+  return nitems < 8 * run ? nitems : (nitems + 8 * run - 1) / (8 * run) * (8 * run);
 }
 
 // Sum of the W partial accumulator tiles of a workgroup into wave 0.
@@ -216,7 +215,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
                                                                  int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
-  const int it = item_of_block(blockIdx.x, nitems);
+  const int it = item_of_block(blockIdx.x, nitems, A.xrun);
   if (it >= nitems) return;
   const int i = A.i0 + it;
   const int ki = A.krow[i];
@@ -347,6 +346,7 @@ struct NearArgs {
   const int64_t *nboff;
   const void *Bn;
   int has_far;
+  int xrun;
 };
 
 template <class T, int TT, int CT>
@@ -357,7 +357,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_near_out(NearArgs A,
                                                                  int R, int RP, int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
   __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
-  const int it = item_of_block(blockIdx.x, nitems);
+  const int it = item_of_block(blockIdx.x, nitems, A.xrun);
   if (it >= nitems) return;
   const int i = A.i0 + it;
   if (A.nchild[i] != 0) return;
@@ -425,7 +425,7 @@ template <class T, int CT>
 static void launch_coupling(const CouplingArgs &ca, const T *q, T *z, int RP, int nitems,
                             hipStream_t s) {
   k_mv_coupling<T, MvShape<T, CT>::TT, CT>
-      <<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP, nitems);
+      <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
 
@@ -433,7 +433,7 @@ template <class T, int CT>
 static void launch_near(const NearArgs &na, const T *q, const T *z, T *Y, int64_t ldy, int R,
                         int RP, int nitems, hipStream_t s) {
   k_mv_near_out<T, MvShape<T, CT>::TT, CT>
-      <<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP, nitems);
+      <<<xcd_grid(nitems, na.xrun), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
 
@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_coupling(CouplingArgs A
                                                                   float *__restrict__ zh, int RP,
                                                                   int nitems) {
   __shared__ float red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
-  const int it = item_of_block(blockIdx.x, nitems);
+  const int it = item_of_block(blockIdx.x, nitems, A.xrun);
   if (it >= nitems) return;
   const int i = A.i0 + it;
   const int ki = A.krow[i];
@@ -651,7 +651,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_near_out(NearArgs A,
                                                                   int64_t ldy, int R, int RP,
                                                                   int nitems) {
   __shared__ float red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
-  const int it = item_of_block(blockIdx.x, nitems);
+  const int it = item_of_block(blockIdx.x, nitems, A.xrun);
   if (it >= nitems) return;
   const int i = A.i0 + it;
   if (A.nchild[i] != 0) return;
@@ -722,10 +722,11 @@ static void launch_bf16_blocks(const CouplingArgs *ca, const NearArgs *na, const
                                hipStream_t s) {
   constexpr int TT = CT >= 3 ? 2 : 4;
   if (ca)
-    k_mvb_coupling<TT, CT><<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(*ca, q, z, RP, nitems);
+    k_mvb_coupling<TT, CT>
+        <<<xcd_grid(nitems, ca->xrun), MV_NT * MV_WAVES, 0, s>>>(*ca, q, z, RP, nitems);
   else
     k_mvb_near_out<TT, CT>
-        <<<xcd_grid(nitems), MV_NT * MV_WAVES, 0, s>>>(*na, q, z, Y, ldy, R, RP, nitems);
+        <<<xcd_grid(nitems, na->xrun), MV_NT * MV_WAVES, 0, s>>>(*na, q, z, Y, ldy, R, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
 
@@ -775,7 +776,8 @@ static void matvec_chunk_bf16(Handle &h, const float *X, int64_t ldx, int R, flo
         }
       }
     }
-    CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
+    CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B,
+                    h.mv_xcd_run};
     {
       PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
       if (h.batched) {
@@ -813,7 +815,7 @@ static void matvec_chunk_bf16(Handle &h, const float *X, int64_t ldx, int R, flo
     }
   }
   NearArgs na{0, h.nnodes, h.nchild, h.xb, h.xe, h.yb, h.ye, h.perm_x, h.Lmrow, h.Lmj, h.nboff,
-              h.Bn, has_far ? 1 : 0};
+              h.Bn, has_far ? 1 : 0, h.mv_xcd_run};
   PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
   if (h.batched) {
     blocks(nullptr, &na, h.nnodes);
@@ -868,7 +870,8 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
     }
   }
   if (has_far) {
-    CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B};
+    CouplingArgs ca{1, h.nnodes, h.Lrow, h.Lj, h.boff, Rw.k, Cl.k, Rw.hbeg, Cl.hbeg, h.B,
+                    h.mv_xcd_run};
     {
       PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
       auto coupling = [&](int nitems) {
@@ -915,7 +918,7 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
     }
   }
   NearArgs na{0, h.nnodes, h.nchild, h.xb, h.xe, h.yb, h.ye, h.perm_x, h.Lmrow, h.Lmj, h.nboff,
-              h.Bn, has_far ? 1 : 0};
+              h.Bn, has_far ? 1 : 0, h.mv_xcd_run};
   {
     PhaseTimer pt(h, SMASH_PHASE_MV_NEAR_OUT, s);
     auto near = [&](int nitems) {

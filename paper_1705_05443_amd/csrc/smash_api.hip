@@ -35,6 +35,7 @@ extern "C" int smash_default_options(smash_options *opt) {
   opt->timing = 0;
   opt->mv_split_nodes = 1024;
   opt->graphs = 1;
+  opt->mv_xcd_run = 16;
   return SMASH_OK;
 }
 
@@ -110,6 +111,8 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
   if (opt.has_root_box && !(opt.root_side >= 0.0 && std::isfinite(opt.root_side)))
     return fail(SMASH_E_INVALID_ARG, "root_side must be finite and >= 0");
   if (opt.mv_split_nodes < 0) return fail(SMASH_E_INVALID_ARG, "mv_split_nodes must be >= 0");
+  if (opt.mv_xcd_run < 1 || opt.mv_xcd_run > 4096)
+    return fail(SMASH_E_INVALID_ARG, "mv_xcd_run must lie in [1, 4096]");
 
   Handle *h = nullptr;
   auto t0 = std::chrono::steady_clock::now();
@@ -136,6 +139,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->timing = opt.timing != 0;
     h->mv_split_nodes = opt.mv_split_nodes;
     h->use_graphs = opt.graphs ? 1 : 0;
+    h->mv_xcd_run = opt.mv_xcd_run;
     h->nx = nx;
     h->ny = ny;
     h->same_xy = same;
@@ -210,6 +214,23 @@ extern "C" int smash_matvec(smash_handle hv, const void *X, int64_t ldx, int32_t
     return SMASH_OK;
   } catch (const Error &e) {
     return fail(e.code, e.msg);
+  } catch (...) {
+    return fail(SMASH_E_DEVICE, "unexpected failure");
+  }
+}
+
+extern "C" int smash_set_product_shape(smash_handle hv, int32_t mv_split_nodes,
+                                       int32_t mv_xcd_run) {
+  Handle *h = (Handle *)hv;
+  if (!h) return fail(SMASH_E_INVALID_ARG, "handle is NULL");
+  if (mv_split_nodes < 0) return fail(SMASH_E_INVALID_ARG, "mv_split_nodes must be >= 0");
+  if (mv_xcd_run < 1 || mv_xcd_run > 4096)
+    return fail(SMASH_E_INVALID_ARG, "mv_xcd_run must lie in [1, 4096]");
+  try {
+    drop_graphs(*h);
+    h->mv_split_nodes = mv_split_nodes;
+    h->mv_xcd_run = mv_xcd_run;
+    return SMASH_OK;
   } catch (...) {
     return fail(SMASH_E_DEVICE, "unexpected failure");
   }

@@ -50,7 +50,9 @@ def test_invalid_arguments_are_rejected_without_a_device():
     L.smash_default_options(C.byref(bad))
     bad.struct_size = 3
     assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(bad), None, C.byref(h)) == -1
-    for field, val in (("tau", 1.5), ("srrqr_f", 1.0), ("apply_prec", 9), ("eval_prec", 9)):
+    for field, val in (("tau", 1.5), ("srrqr_f", 1.0), ("apply_prec", 9), ("eval_prec", 9),
+                       ("eval_prec", 2), ("mv_split_nodes", -1), ("mv_xcd_run", 0),
+                       ("mv_xcd_run", 5000)):
         L.smash_default_options(C.byref(bad))
         setattr(bad, field, val)
         assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(bad), None, C.byref(h)) == -1
@@ -62,6 +64,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.smash_info(None, C.byref(info)) == -1
     n = C.c_int64(0)
     assert L.smash_export(None, 1, None, C.byref(n)) == -1
+    assert L.smash_set_product_shape(None, 16, 16) == -1
     assert L.smash_destroy(None) == 0
 
 

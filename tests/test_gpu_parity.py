@@ -327,3 +327,22 @@ def test_matvec_graph_replays_match_eager(prec):
     assert inf["graph_captures"] == 2 and inf["graph_replays"] == 8, inf
     gg.close()
     ge.close()
+
+
+def test_autotuner_shape_keeps_the_product():
+    """The tuner returns one of its candidate shapes, and the product with
+    the tuned shape equals the default-shape product up to the summation
+    order of the split sweeps."""
+    from paper_1705_05443_amd import autotune
+    mk, kw = CASES["h2_2d_log"]
+    x, _ = mk()
+    res = autotune.tune(x, None, nrhs=16, reps=2, **kw)
+    shp = res["shape"]
+    assert shp["mv_split_nodes"] in autotune.KNOBS["mv_split_nodes"]
+    assert shp["mv_xcd_run"] in autotune.KNOBS["mv_xcd_run"]
+    assert len(res["trials"]) == sum(len(v) for v in autotune.KNOBS.values())
+    q = dev(W.rhs(len(x), 16, seed=21))
+    g0 = api.Smash(dev(x), tuned=False, **kw)
+    g1 = api.Smash(dev(x), tuned=False, **kw, **shp)
+    z0, z1 = g0.matvec(q).cpu().numpy(), g1.matvec(q).cpu().numpy()
+    assert relerr(z1, z0) < 1e-13
