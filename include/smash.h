@@ -209,7 +209,22 @@ int smash_info(smash_handle h, smash_info_t *info);
 #define SMASH_EX_COUPLING 18 /* entries of all B_ij over L in pair order, each block  */
                              /* column-major (row index fastest), F64 or F32 per the */
                              /* apply precision; a BF16 handle: SMASH_E_UNSUPPORTED  */
-#define SMASH_EX_NEAR 19     /* the same for the near blocks over L^-                */
+#define SMASH_EX_NEAR 19     /* Admission model for a serving loop: an upper estimate of the device
+ * bytes a handle built with these parameters holds (points, tree, lists,
+ * G copies, coupling and near blocks, a 64-column product workspace), from
+ * the point count alone.  The block counts assume every node carries the
+ * full basis rank min(order^dim, leaf) and the interaction-list sizes of
+ * uniform boxes (H^2: (2*3)^dim - 3^dim far pairs and 3^dim near pairs per
+ * node for tau <= 0.7; HSS: one of each), so real footprints are lower
+ * (2-5x on the workloads measured); a caller may scale it by the ratio it
+ * observes.  Host-only arithmetic: no device is touched.
+ *   apply_prec  SMASH_F64, SMASH_F32 or SMASH_BF16
+ * Errors: SMASH_E_INVALID_ARG for out-of-range parameters or a NULL bytes. */
+int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kernel_id, int32_t leaf_size,
+                             int32_t interp_order, int32_t admissibility, double tol,
+                             int32_t apply_prec, int64_t *bytes);
+
+/* the same for the near blocks over L^-                */
 int smash_export(smash_handle h, int32_t what, void *host_buf, int64_t *count);
 
 int smash_destroy(smash_handle h);

@@ -62,7 +62,7 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
             "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
-            "smash_last_error"]
+            "smash_estimate_footprint", "smash_last_error"]
 
 
 def lib():
@@ -82,12 +82,16 @@ def lib():
                                      C.POINTER(Options), vp, C.POINTER(vp)]
         L.smash_matvec.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, vp]
         L.smash_set_product_shape.argtypes = [vp, C.c_int32, C.c_int32]
+        L.smash_estimate_footprint.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                               C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                               C.POINTER(C.c_int64)]
         L.smash_info.argtypes = [vp, C.POINTER(Info)]
         L.smash_export.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int64)]
         L.smash_destroy.argtypes = [vp]
         L.smash_last_error.restype = C.c_char_p
         for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-                  "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy"):
+                  "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
+                  "smash_estimate_footprint"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -102,6 +106,16 @@ def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def estimate_footprint(n, dim, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
+                       apply_prec="f64"):
+    """Upper estimate of a handle's device bytes (smash_estimate_footprint)."""
+    b = C.c_int64(0)
+    _check(lib().smash_estimate_footprint(int(n), int(dim), KERNELS[kernel], int(leaf),
+                                          int(order), ADM[adm], float(tol), PREC[apply_prec],
+                                          C.byref(b)))
+    return b.value
 
 
 class Smash:

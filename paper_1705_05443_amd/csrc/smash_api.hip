@@ -1,5 +1,6 @@
 // smash_api.hip -- the C ABI (include/smash.h): argument checks, handle
 // lifetime, error translation, info and export.  No exception crosses it.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -465,6 +466,50 @@ extern "C" int smash_export(smash_handle hv, int32_t what, void *buf, int64_t *c
   } catch (...) {
     return fail(SMASH_E_DEVICE, "unexpected failure");
   }
+}
+
+extern "C" int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kid, int32_t leaf,
+                                        int32_t p, int32_t adm, double tol, int32_t apply_prec,
+                                        int64_t *bytes) {
+  if (!bytes) return fail(SMASH_E_INVALID_ARG, "bytes is NULL");
+  if (n < 1 || dim < 1 || dim > 3 || leaf < 1 || p < 1 || p > 64 ||
+      (adm != SMASH_ADM_WEAK && adm != SMASH_ADM_STRONG) || !(tol >= 0.0) ||
+      kid < 0 || kid > 3 ||
+      (apply_prec != SMASH_F64 && apply_prec != SMASH_F32 && apply_prec != SMASH_BF16))
+    return fail(SMASH_E_INVALID_ARG, "parameter out of range");
+  const double es = apply_prec == SMASH_F64 ? 8.0 : apply_prec == SMASH_F32 ? 4.0 : 2.0;
+  const double vs = apply_prec == SMASH_F64 ? 8.0 : 4.0;  // vector element
+  const double dn = (double)n;
+  // leaves hold about leaf / 2^dim points or more on average (1.25 slack);
+  // all levels together add 1 / (2^dim - 1) of that many inner nodes
+  const double twod = (double)(1 << dim);
+  const double leaves = std::max(1.0, dn * twod / (1.25 * (double)leaf));
+  const double nodes = leaves * twod / (twod - 1.0);
+  double pd = 1.0;
+  for (int t = 0; t < dim; t++) pd *= p;
+  const double c = adm == SMASH_ADM_STRONG ? pd : pd + leaf;  // HSS adds near vectors
+  const double r = std::min(c, 0.75 * (double)leaf);
+  double far = 1.0, near = 1.0;
+  if (adm == SMASH_ADM_STRONG) {
+    double s3 = 1.0, s6 = 1.0;
+    for (int t = 0; t < dim; t++) {
+      s3 *= 3.0;
+      s6 *= 6.0;
+    }
+    far = s6 - s3;
+    near = s3;
+  }
+  const double sides = (kid == SMASH_KERNEL_CAUCHY) ? 2.0 : 1.0;  // column side kept
+  double b = 0.0;
+  b += dn * (dim * 8.0 * 2.0 + 64.0);                  // points, permutations, tree
+  b += nodes * (far + near) * 16.0;                    // pair lists and offsets
+  b += sides * nodes * r * r * (8.0 * 2.0 + es * 2.0);  // G master, transpose, copies
+  b += nodes * far * r * r * es;                       // coupling blocks
+  b += leaves * near * (double)leaf * (double)leaf * es;  // near blocks
+  b += 2.0 * (dn + sides * nodes * r) * 64.0 * vs;     // product workspace
+  *bytes = (int64_t)std::min(b, 9.0e18);
+  (void)tol;
+  return SMASH_OK;
 }
 
 extern "C" int smash_destroy(smash_handle hv) {

@@ -1,0 +1,132 @@
+"""CPU tests of the serving scheduler with a host-only executor: admission
+by footprint, slot limits, continuous admission, batching of products on a
+resident matrix, eviction, and rejection of what can never fit."""
+import threading
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+from paper_1705_05443_amd.serve import Engine, Request, latency_stats
+
+
+class FakeExecutor:
+    """Builds take `build_s` seconds and hold real_per_point bytes per point
+    (the estimate is 2 per point); products take `prod_s` seconds and
+    return the right-hand sides times 2.  Tracks concurrency."""
+
+    def __init__(self, slots, build_s=0.02, prod_s=0.005, real_per_point=1):
+        self.pool = ThreadPoolExecutor(max_workers=slots)
+        self.real = real_per_point
+        self.build_s, self.prod_s = build_s, prod_s
+        self.lock = threading.Lock()
+        self.running = 0
+        self.max_running = 0
+        self.released = []
+
+    def estimate(self, req):
+        return 2 * req.rhs.shape[0]
+
+    def prior_ratio(self, req):
+        return 1.0
+
+    def _enter(self):
+        with self.lock:
+            self.running += 1
+            self.max_running = max(self.max_running, self.running)
+
+    def _leave(self):
+        with self.lock:
+            self.running -= 1
+
+    def _build(self, req):
+        self._enter()
+        time.sleep(self.build_s)
+        self._leave()
+        return ("H", req.matrix), self.real * req.rhs.shape[0], [2.0 * req.rhs]
+
+    def _product(self, h, group):
+        self._enter()
+        time.sleep(self.prod_s)
+        self._leave()
+        return [2.0 * r.rhs for r in group]
+
+    def submit_build(self, req):
+        return self.pool.submit(self._build, req)
+
+    def submit_product(self, h, group):
+        return self.pool.submit(self._product, h, group)
+
+    def release(self, h):
+        self.released.append(h)
+
+
+def _req(rid, t, m, n, nrhs=2, build=True):
+    rhs = np.full((n, nrhs), float(rid))
+    pts = np.zeros((n, 2)) if build else None
+    return Request(rid, t, m, rhs, pts, {})
+
+
+def test_all_requests_complete_within_slots_and_budget():
+    ex = FakeExecutor(slots=3)
+    eng = Engine(ex, budget_bytes=10_000, slots=3, margin=1.0)
+    reqs = [_req(i, 0.002 * i, "m%d" % i, 1000 + 100 * i) for i in range(12)]
+    done = eng.run(reqs)
+    assert len(done) == 12 and all(r.error is None for r in done)
+    assert ex.max_running <= 3 and eng.peak_inflight <= 3
+    assert eng.peak_reserved <= 10_000
+    for r in done:
+        assert np.array_equal(r.result, 2.0 * r.rhs)
+        assert r.admitted >= r.arrival and r.done >= r.admitted
+    st = latency_stats(done)
+    assert st["completed"] == 12 and st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_requests_admitted_while_others_run():
+    """Continuous admission: a request arriving while earlier work is on the
+    device starts before that work ends when a slot is free."""
+    ex = FakeExecutor(slots=2, build_s=0.05)
+    eng = Engine(ex, budget_bytes=10**9, slots=2)
+    a, b = _req(0, 0.0, "a", 100), _req(1, 0.01, "b", 100)
+    done = {r.rid: r for r in eng.run([a, b])}
+    assert done[1].admitted < done[0].done
+
+
+def test_products_on_a_resident_matrix_are_batched():
+    ex = FakeExecutor(slots=1, build_s=0.03)
+    eng = Engine(ex, budget_bytes=10**9, slots=1)
+    reqs = [_req(0, 0.0, "m", 500)] + [_req(i, 0.001 * i, "m", 500, nrhs=3, build=False)
+                                       for i in range(1, 6)]
+    done = {r.rid: r for r in eng.run(reqs)}
+    assert all(done[i].error is None for i in range(6))
+    # five products waited for the build and went out as one launch
+    assert [e for e in eng.log if e[0] == "product"] == [("product", "m", 5)]
+    for i in range(1, 6):
+        assert done[i].batch == 5 and np.array_equal(done[i].result, 2.0 * done[i].rhs)
+
+
+def test_idle_residents_are_evicted_to_admit_new_builds():
+    ex = FakeExecutor(slots=1, real_per_point=2)
+    eng = Engine(ex, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0)
+    reqs = [_req(i, 0.0, "m%d" % i, 1000) for i in range(4)]  # 2000 reserved each
+    done = eng.run(reqs)
+    assert all(r.error is None for r in done)
+    assert [e[1] for e in eng.log if e[0] == "evict"] == ["m0", "m1", "m2"]
+    assert eng.peak_reserved <= 3000
+
+
+def test_a_request_that_can_never_fit_is_rejected():
+    ex = FakeExecutor(slots=2)
+    eng = Engine(ex, budget_bytes=1000, slots=2, ratio=1.0, margin=1.0)
+    done = {r.rid: r for r in eng.run([_req(0, 0.0, "big", 5000), _req(1, 0.0, "ok", 100)])}
+    assert done[0].error and "budget" in done[0].error
+    assert done[1].error is None
+
+
+def test_observed_bytes_calibrate_the_reservation():
+    ex = FakeExecutor(slots=1)
+    eng = Engine(ex, budget_bytes=10**9, slots=1, margin=1.0)
+    eng.run([_req(0, 0.0, "a", 1000)])
+    # real bytes are half the estimate: later reservations shrink to match
+    assert abs(eng.ratios[2] - 0.5) < 1e-12
+    assert eng._need(_req(1, 0.0, "b", 1000)) == 1000
