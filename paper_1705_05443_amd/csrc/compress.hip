@@ -444,7 +444,7 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
   double *const Rs = dyn;
   double *const Ris = dyn + CMAX * CMAX;
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
-  __shared__ double v[CMAX], rinv[CMAX];
+  __shared__ double v[CMAX], rinv[CMAX], rdiag[CMAX];
   __shared__ int srank[CMAX];
   __shared__ ArgMax ared[NT / WAVE + 1];
   __shared__ int64_t sred[NT / WAVE + 1];
@@ -546,73 +546,102 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
     // Householder QR over positions 0..kend-1: with pivoting the pivot of
     // step t is the largest remaining norm and the loop stops at the rank
     // test (|R_tt| <= tol * |R_00|); without, the pivot is position t.
+    // Steps run in blocks of eight (tb unrolled): rows below 8 tb are final
+    // in every remaining column, so each step touches rows 8 tb.. only and
+    // masks by the runtime step just the eight rows of its own block.  The
+    // pivot lane keeps its column as it was (rows < t are R's column) and
+    // records R_tt in rdiag.
     auto householder_qr = [&](bool pivoting, int kend) -> int {
       int kk = 0;
       double r00 = 0.0;
-      for (int t = 0; t < kend; t++) {
-        const bool cand = act && (pivoting ? pa >= t : pa == t);
-        ArgMax am = cand ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
-        am = block_argmax(am, ared);
-        const double bn = am.v;
-        if (pivoting) {
-          if (t == 0) {
-            r00 = bn;
-            if (!(r00 > 0.0)) break;
-          } else if (!(bn > A.tol * r00)) {
+      bool stop = kend <= 0;
+#pragma unroll
+      for (int tb = 0; tb < CMAX / 8; tb++) {
+        if (stop) break;
+        const int r0 = 8 * tb;
+        for (int tt = 0; tt < 8; tt++) {
+          const int t = r0 + tt;
+          if (t >= kend) {
+            stop = true;
             break;
           }
-        }
-        const int bp = am.a;
-        if (act) {
-          if (pa == t)
-            pa = bp;
-          else if (pa == bp)
-            pa = t;
-        }
-        if (act && pa == t) {
-          // the pivot column: v (rows t..), R_tt; every entry of v is written
-          double x0 = 0.0, rest = 0.0;
-#pragma unroll
-          for (int r = 0; r < CMAX; r++) {
-            x0 = r == t ? col[r] : x0;
-            const double y = r > t ? col[r] : 0.0;
-            rest = fma(y, y, rest);
+          const bool cand = act && (pivoting ? pa >= t : pa == t);
+          ArgMax am = cand ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
+          am = block_argmax(am, ared);
+          const double bn = am.v;
+          if (pivoting) {
+            if (t == 0) {
+              r00 = bn;
+              if (!(r00 > 0.0)) {
+                stop = true;
+                break;
+              }
+            } else if (!(bn > A.tol * r00)) {
+              stop = true;
+              break;
+            }
           }
-          const double rtt = x0 >= 0.0 ? -bn : bn;
-          const double v0 = x0 - rtt;
-#pragma unroll
-          for (int r = 0; r < CMAX; r++) {
-            v[r] = r == t ? v0 : (r > t ? col[r] : 0.0);
-            col[r] = r > t ? 0.0 : (r == t ? rtt : col[r]);
+          const int bp = am.a;
+          if (act) {
+            if (pa == t)
+              pa = bp;
+            else if (pa == bp)
+              pa = t;
           }
-          vn_lds = rest + v0 * v0;
+          if (act && pa == t) {
+            // the pivot column: v (rows r0..), R_tt
+            double x0 = 0.0, rest = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+              const double y = col[r0 + u];
+              x0 = u == tt ? y : x0;
+              const double z = u > tt ? y : 0.0;
+              rest = fma(z, z, rest);
+            }
+#pragma unroll
+            for (int r = r0 + 8; r < CMAX; r++) rest = fma(col[r], col[r], rest);
+            const double rtt = x0 >= 0.0 ? -bn : bn;
+            const double v0 = x0 - rtt;
+#pragma unroll
+            for (int u = 0; u < 8; u++) v[r0 + u] = u == tt ? v0 : (u > tt ? col[r0 + u] : 0.0);
+#pragma unroll
+            for (int r = r0 + 8; r < CMAX; r++) v[r] = col[r];
+            rdiag[t] = rtt;
+            vn_lds = rest + v0 * v0;
+          }
+          __syncthreads();
+          const double vn = vn_lds;
+          if (act && pa > t && vn > 0.0) {
+            double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+            for (int r = r0; r < CMAX; r += 2) {
+              w0 = fma(v[r], col[r], w0);
+              w1 = fma(v[r + 1], col[r + 1], w1);
+            }
+            const double sc = 2.0 * (w0 + w1) / vn;
+            // v is read again from LDS below rather than kept in registers
+            __asm__ volatile("" ::: "memory");
+            double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+              const double y = fma(-sc, v[r0 + u], col[r0 + u]);
+              col[r0 + u] = y;
+              const double z = u > tt ? y : 0.0;
+              s0 = fma(z, z, s0);
+            }
+#pragma unroll
+            for (int r = r0 + 8; r < CMAX; r += 2) {
+              const double y0 = fma(-sc, v[r], col[r]), y1 = fma(-sc, v[r + 1], col[r + 1]);
+              col[r] = y0;
+              col[r + 1] = y1;
+              s0 = fma(y0, y0, s0);
+              s1 = fma(y1, y1, s1);
+            }
+            nrm = sqrt(s0 + s1);
+          }
+          __syncthreads();
+          kk = t + 1;
         }
-        __syncthreads();
-        const double vn = vn_lds;
-        if (act && pa > t && vn > 0.0) {
-          double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
-#pragma unroll
-          for (int r = 0; r < CMAX; r += 4) {
-            w0 = fma(v[r], col[r], w0);
-            w1 = fma(v[r + 1], col[r + 1], w1);
-            w2 = fma(v[r + 2], col[r + 2], w2);
-            w3 = fma(v[r + 3], col[r + 3], w3);
-          }
-          const double sc = 2.0 * ((w0 + w1) + (w2 + w3)) / vn;
-          double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-          for (int r = 0; r < CMAX; r += 2) {
-            const double y0 = fma(-sc, v[r], col[r]), y1 = fma(-sc, v[r + 1], col[r + 1]);
-            col[r] = y0;
-            col[r + 1] = y1;
-            const double z0 = r > t ? y0 : 0.0, z1 = r + 1 > t ? y1 : 0.0;
-            s0 = fma(z0, z0, s0);
-            s1 = fma(z1, z1, s1);
-          }
-          nrm = sqrt(s0 + s1);
-        }
-        __syncthreads();
-        kk = t + 1;
       }
       return kk;
     };
@@ -634,7 +663,8 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
       if (pa < CMAX) {
 #pragma unroll
         for (int r = 0; r < CMAX; r++)
-          Rs[r * CMAX + pa] = pa < k ? (r <= pa ? col[r] : 0.0) : (r == pa ? 1.0 : 0.0);
+          Rs[r * CMAX + pa] =
+              pa < k ? (r < pa ? col[r] : (r == pa ? rdiag[pa] : 0.0)) : (r == pa ? 1.0 : 0.0);
       }
       __syncthreads();
       // right-hand side e_j at positions j < k; R12 columns stay in place

@@ -54,7 +54,7 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // every chunk.
 struct DeviceArena {
   hipStream_t stream = nullptr;
-  std::vector<void *> ptrs;  // chunks
+  std::vector<std::pair<void *, size_t>> blocks;  // (base, size) of each chunk
   char *cur = nullptr;
   size_t left = 0;
   size_t chunk = (size_t)32 << 20;
@@ -64,7 +64,10 @@ struct DeviceArena {
   T *alloc_n(size_t n) {
     return (T *)alloc(sizeof(T) * (n ? n : 1));
   }
-  void release();
+  // Gives the chunks back.  idle = true: no queued work uses them any more
+  // (the caller synchronized their stream), so they go to the process-wide
+  // chunk cache for the next arena; otherwise hipFreeAsync on `stream`.
+  void release(bool idle = true);
 };
 
 // ---------------------------------------------------------------- scans / sort

@@ -947,7 +947,7 @@ static bool ensure_workspace(Handle &h, int nrhs, hipStream_t s) {
   const int chunk = nrhs < RC ? nrhs : RC;
   const int cp = (chunk + 15) / 16 * 16;
   if (h.ws_nrhs >= cp) return false;
-  h.ws_mem.release();  // on the stream that allocated it
+  h.ws_mem.release(false);  // stream-ordered: earlier products may still run
   h.ws_mem.stream = s;
   h.qbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.col->nslots * cp);
   h.zbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.row.nslots * cp);

@@ -2,21 +2,57 @@
 // (4-bit digits), the integer building blocks of the partition tree and of
 // the pair lists.  Stability of the sort is what makes the point order and
 // the sorted pair lists bit-exact and reproducible.
+#include <map>
+#include <mutex>
+
 #include "common.cuh"
 
 namespace smash {
+
+// Process-wide cache of idle device chunks (per device, best fit within
+// twice the request), so repeated builds reuse memory without allocator
+// calls.  Holds at most CACHE_CAP bytes; the rest is freed.
+namespace {
+constexpr size_t CACHE_CAP = (size_t)48 << 30;
+struct ChunkCache {
+  std::mutex mu;
+  std::multimap<size_t, std::pair<int, void *>> idle;  // size -> (device, base)
+  size_t held = 0;
+};
+ChunkCache &chunk_cache() {
+  static ChunkCache c;
+  return c;
+}
+bool take_cached(int dev, size_t n, void **p, size_t *sz) {
+  ChunkCache &c = chunk_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto it = c.idle.lower_bound(n); it != c.idle.end() && it->first <= 2 * n; ++it) {
+    if (it->second.first != dev) continue;
+    *p = it->second.second;
+    *sz = it->first;
+    c.held -= it->first;
+    c.idle.erase(it);
+    return true;
+  }
+  return false;
+}
+}  // namespace
 
 void *DeviceArena::alloc(size_t n) {
   n = (n + 255) & ~(size_t)255;
   if (n > left) {
     size_t sz = n > chunk ? n : chunk;
     void *p = nullptr;
-    hipError_t e = hipMallocAsync(&p, sz, stream);
-    if (e != hipSuccess || !p) {
-      (void)hipGetLastError();
-      throw Error{SMASH_E_OOM, "device allocation of " + std::to_string(sz) + " bytes failed"};
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (!take_cached(dev, sz, &p, &sz)) {
+      hipError_t e = hipMallocAsync(&p, sz, stream);
+      if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error{SMASH_E_OOM, "device allocation of " + std::to_string(sz) + " bytes failed"};
+      }
     }
-    ptrs.push_back(p);
+    blocks.emplace_back(p, sz);
     cur = (char *)p;
     left = sz;
   }
@@ -27,9 +63,23 @@ void *DeviceArena::alloc(size_t n) {
   return r;
 }
 
-void DeviceArena::release() {
-  for (void *p : ptrs) (void)hipFreeAsync(p, stream);
-  ptrs.clear();
+void DeviceArena::release(bool idle) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  ChunkCache &c = chunk_cache();
+  for (auto &b : blocks) {
+    bool kept = false;
+    if (idle) {
+      std::lock_guard<std::mutex> lk(c.mu);
+      if (c.held + b.second <= CACHE_CAP) {
+        c.idle.emplace(b.second, std::make_pair(dev, b.first));
+        c.held += b.second;
+        kept = true;
+      }
+    }
+    if (!kept) (void)hipFreeAsync(b.first, stream);
+  }
+  blocks.clear();
   cur = nullptr;
   left = 0;
   bytes = 0;

@@ -61,9 +61,9 @@ static void free_handle(Handle *h) {
   drop_graphs(*h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   (void)hipStreamSynchronize(h->stream);
+  if (h->ws_mem.stream != h->stream) (void)hipStreamSynchronize(h->ws_mem.stream);
   h->ws_mem.release();
   h->mem.release();
-  (void)hipStreamSynchronize(h->stream);
   delete h;
 }
 
