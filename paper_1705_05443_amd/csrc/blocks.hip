@@ -46,8 +46,15 @@ struct EvalArgs {
   double diag;
 };
 
+// Coordinates of a block's rows and columns are staged in LDS (up to
+// EV_STAGE points each), and every thread walks its entries with a running
+// (row, column) pair instead of dividing by the row count per entry.
+constexpr int EV_STAGE = 256;
+
 template <class T, bool F32MATH>
 __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
+  __shared__ double xs[EV_STAGE * 3], ys[EV_STAGE * 3];
+  const int d = A.d;
   for (int64_t e = blockIdx.x; e < A.npairs; e += gridDim.x) {
     int i = A.pi[e], j = A.pj[e];
     int64_t r0, c0;
@@ -67,16 +74,47 @@ __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
       nc = A.cend32[j] - A.cbeg32[j];
     }
     T *B = out + A.off[e];
-    int tot = nr * nc;
-    for (int q = threadIdx.x; q < tot; q += blockDim.x) {
-      int b = q / nr, a = q - b * nr;  // column-major: row fastest
-      int64_t xr = A.rid ? A.rid[r0 + a] : r0 + a;
-      int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
-      const double *xp = A.Xp + xr * A.d, *yp = A.Yp + yc * A.d;
+    const int tot = nr * nc;
+    if (tot == 0) continue;
+    const bool staged = nr <= EV_STAGE && nc <= EV_STAGE;
+    __syncthreads();  // the previous pair's readers are done with xs / ys
+    if (staged) {
+      for (int q = threadIdx.x; q < nr * d; q += blockDim.x) {
+        const int a = q / d, t = q - a * d;
+        const int64_t xr = A.rid ? A.rid[r0 + a] : r0 + a;
+        xs[q] = A.Xp[xr * d + t];
+      }
+      for (int q = threadIdx.x; q < nc * d; q += blockDim.x) {
+        const int b = q / d, t = q - b * d;
+        const int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
+        ys[q] = A.Yp[yc * d + t];
+      }
+    }
+    __syncthreads();
+    // column-major: row fastest; (a, b) of entry q advanced by the stride
+    const int st = blockDim.x, sb = st / nr, sa = st - sb * nr;
+    int b = threadIdx.x / nr, a = threadIdx.x - b * nr;
+    for (int q = threadIdx.x; q < tot; q += st) {
+      const double *xp, *yp;
+      if (staged) {
+        xp = xs + a * d;
+        yp = ys + b * d;
+      } else {
+        const int64_t xr = A.rid ? A.rid[r0 + a] : r0 + a;
+        const int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
+        xp = A.Xp + xr * d;
+        yp = A.Yp + yc * d;
+      }
       if (F32MATH)
-        B[q] = (T)kernel_f32(A.kid, xp, yp, A.d, (float)A.diag);
+        B[q] = (T)kernel_f32(A.kid, xp, yp, d, (float)A.diag);
       else
-        B[q] = (T)kernel_f64(A.kid, xp, yp, A.d, A.diag);
+        B[q] = (T)kernel_f64(A.kid, xp, yp, d, A.diag);
+      a += sa;
+      b += sb;
+      if (a >= nr) {
+        a -= nr;
+        b++;
+      }
     }
   }
 }

@@ -144,8 +144,36 @@ __global__ void __launch_bounds__(SC_NT) k_scan_down(const int64_t *in, int64_t 
   }
 }
 
+// one workgroup for short arrays (most per-level scans): a single launch
+constexpr int SC1_NT = 1024, SC1_IT = 8;
+__global__ void __launch_bounds__(SC1_NT) k_scan_one(const int64_t *in, int64_t n,
+                                                     const int64_t *base_dev, int64_t *out) {
+  __shared__ int64_t lds[SC1_NT / 64 + 1];
+  const int64_t b0 = (int64_t)threadIdx.x * SC1_IT;
+  int64_t v[SC1_IT];
+  int64_t sum = 0;
+  for (int u = 0; u < SC1_IT; u++) {
+    v[u] = b0 + u < n ? in[b0 + u] : 0;
+    sum += v[u];
+  }
+  int64_t tot;
+  int64_t ex = block_excl_scan_i64(sum, &tot, lds);
+  const int64_t base = base_dev ? *base_dev : 0;
+  ex += base;
+  for (int u = 0; u < SC1_IT; u++) {
+    if (b0 + u < n) out[b0 + u] = ex;
+    ex += v[u];
+  }
+  if (threadIdx.x == 0) out[n] = base + tot;
+}
+
 void scan_i64(const int64_t *in, int64_t *out, int64_t n, const int64_t *base_dev,
               hipStream_t s, DeviceArena &tmp) {
+  if (n <= (int64_t)SC1_NT * SC1_IT) {
+    k_scan_one<<<1, SC1_NT, 0, s>>>(in, n, base_dev, out);
+    SMASH_CHECK_LAUNCH();
+    return;
+  }
   int nb = n > 0 ? ceil_div(n, SC_TILE) : 0;
   int64_t *bsum = tmp.alloc_n<int64_t>(nb + 1);
   if (nb > 0) {
