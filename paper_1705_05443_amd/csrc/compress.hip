@@ -778,6 +778,11 @@ struct SvdArgs {
   int *ks_out;
 };
 
+// NCL / VCL > 0: a pair's two rows (nc <= 8 NCL entries) and two V columns
+// (mp <= 8 VCL entries) are read into registers at once, rotated there and
+// written back -- the same arithmetic in the same order as the general
+// loops (NCL = VCL = 0), without a chain of dependent loads per entry.
+template <int NCL, int VCL>
 __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
   __shared__ double sg[SV_MMAX];
   __shared__ int ord[SV_MMAX];
@@ -838,11 +843,30 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
           }
           double *ap = Am + (int64_t)pp * ldn, *aq = Am + (int64_t)qq * ldn;
           double al = 0.0, be = 0.0, ga = 0.0;
-          for (int t = gl; t < nc; t += SV_G) {
-            double x = ap[t], y = aq[t];
-            al = fma(x, x, al);
-            be = fma(y, y, be);
-            ga = fma(x, y, ga);
+          double xr[NCL > 0 ? NCL : 1], yr[NCL > 0 ? NCL : 1];
+          if constexpr (NCL > 0) {
+#pragma unroll
+            for (int u = 0; u < NCL; u++) {
+              const int t = gl + SV_G * u;
+              const int tc = t < nc ? t : 0;
+              xr[u] = ap[tc];
+              yr[u] = aq[tc];
+            }
+#pragma unroll
+            for (int u = 0; u < NCL; u++) {
+              if (gl + SV_G * u < nc) {
+                al = fma(xr[u], xr[u], al);
+                be = fma(yr[u], yr[u], be);
+                ga = fma(xr[u], yr[u], ga);
+              }
+            }
+          } else {
+            for (int t = gl; t < nc; t += SV_G) {
+              double x = ap[t], y = aq[t];
+              al = fma(x, x, al);
+              be = fma(y, y, be);
+              ga = fma(x, y, ga);
+            }
           }
           for (int o = SV_G / 2; o > 0; o >>= 1) {
             al += __shfl_xor(al, o, SV_G);
@@ -856,15 +880,45 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
           double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           double cs = 1.0 / sqrt(1.0 + tt * tt);
           double sn = cs * tt;
-          for (int t = gl; t < nc; t += SV_G) {
-            double x = ap[t], y = aq[t];
-            ap[t] = cs * x - sn * y;
-            aq[t] = sn * x + cs * y;
+          if constexpr (NCL > 0) {
+#pragma unroll
+            for (int u = 0; u < NCL; u++) {
+              const int t = gl + SV_G * u;
+              if (t < nc) {
+                ap[t] = cs * xr[u] - sn * yr[u];
+                aq[t] = sn * xr[u] + cs * yr[u];
+              }
+            }
+          } else {
+            for (int t = gl; t < nc; t += SV_G) {
+              double x = ap[t], y = aq[t];
+              ap[t] = cs * x - sn * y;
+              aq[t] = sn * x + cs * y;
+            }
           }
-          for (int t = gl; t < mp; t += SV_G) {
-            double x = V[(int64_t)t * mp + pp], y = V[(int64_t)t * mp + qq];
-            V[(int64_t)t * mp + pp] = cs * x - sn * y;
-            V[(int64_t)t * mp + qq] = sn * x + cs * y;
+          if constexpr (VCL > 0) {
+            double vx[VCL], vy[VCL];
+#pragma unroll
+            for (int u = 0; u < VCL; u++) {
+              const int t = gl + SV_G * u;
+              const int tc = t < mp ? t : 0;
+              vx[u] = V[(int64_t)tc * mp + pp];
+              vy[u] = V[(int64_t)tc * mp + qq];
+            }
+#pragma unroll
+            for (int u = 0; u < VCL; u++) {
+              const int t = gl + SV_G * u;
+              if (t < mp) {
+                V[(int64_t)t * mp + pp] = cs * vx[u] - sn * vy[u];
+                V[(int64_t)t * mp + qq] = sn * vx[u] + cs * vy[u];
+              }
+            }
+          } else {
+            for (int t = gl; t < mp; t += SV_G) {
+              double x = V[(int64_t)t * mp + pp], y = V[(int64_t)t * mp + qq];
+              V[(int64_t)t * mp + pp] = cs * x - sn * y;
+              V[(int64_t)t * mp + qq] = sn * x + cs * y;
+            }
           }
         }
         __syncthreads();
@@ -1191,16 +1245,27 @@ void build_generators(Handle &h) {
                      h.Ncol, sc.rowside ? 1 : 0, h.kid, h.d, h.diag, h.eps_svd, scr, ldn,
                      wg_stride, sc.Svec, soff, S.ks};
           PhaseTimer pt(h, SMASH_PHASE_NEAR_SVD, s);
-          if (h.batched) {
-            k_near_svd<<<nwg, SV_NT, 0, s>>>(sa);
+          // register-staged rotations when a pair's rows and V columns fit
+          const int ncl = ncmax <= 64 ? 8 : ncmax <= 128 ? 16 : ncmax <= 256 ? 32 : 0;
+          const int vcl = mp <= 32 ? 4 : mp <= 64 ? 8 : mp <= 128 ? 16 : 0;
+          auto svd = [&](int grid) {
+#define SMASH_SVD_CASE(NC, VC) \
+  else if (ncl == NC && vcl == VC) k_near_svd<NC, VC><<<grid, SV_NT, 0, s>>>(sa);
+            if (ncl == 0 || vcl == 0) k_near_svd<0, 0><<<grid, SV_NT, 0, s>>>(sa);
+            SMASH_SVD_CASE(8, 4) SMASH_SVD_CASE(8, 8) SMASH_SVD_CASE(8, 16)
+            SMASH_SVD_CASE(16, 4) SMASH_SVD_CASE(16, 8) SMASH_SVD_CASE(16, 16)
+            SMASH_SVD_CASE(32, 4) SMASH_SVD_CASE(32, 8) SMASH_SVD_CASE(32, 16)
+#undef SMASH_SVD_CASE
             SMASH_CHECK_LAUNCH();
+          };
+          if (h.batched) {
+            svd(nwg);
           } else {
             for (int i = nb; i < ne; i++) {
               sa.nb = i;
               sa.ne = i + 1;
               sa.S_off = soff + (i - nb);
-              k_near_svd<<<1, SV_NT, 0, s>>>(sa);
-              SMASH_CHECK_LAUNCH();
+              svd(1);
             }
           }
         }
