@@ -19,6 +19,7 @@ oracle on the host cores.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -33,6 +34,27 @@ METRIC = "build points/s + matvec GB/s at 1e-6 rel err; serve p50/p99 vs plain f
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
+
+
+def stored_traffic(workload):
+    """HBM bytes per launch of the compression kernel and per product, from
+    the counter summary under profiles/ -- each None once its source file
+    has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", workload + "_traffic.json")
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        d = json.load(f)
+
+    def same(rel, sha):
+        with open(os.path.join(ROOT, rel), "rb") as g:
+            return hashlib.sha256(g.read()).hexdigest() == sha
+
+    comp = d["bytes_per_launch"] if same(d["source"], d["source_sha256"]) else None
+    prod = d.get("product_bytes")
+    if prod is not None and not same(d["product_source"], d["product_source_sha256"]):
+        prod = None
+    return comp, prod
 
 
 def compr_flops(m, k, c):
@@ -181,14 +203,19 @@ def main():
 
     compr_ms = ph["compr"]
     dominant = max(ph, key=ph.get)
-    roof = {"kernel": "k_compr (pivoted Householder QR + Gu-Eisenstat, FP64)", "bound": "alu",
+    tr_comp, tr_prod = stored_traffic(args.workload)
+    n_compr = int(infos[0]["phase_calls"]["compr"]) if infos else 0
+    roof = {"kernel": "k_compr_w (pivoted Householder QR + Gu-Eisenstat, FP64)", "bound": "alu",
             "achieved": flops / (compr_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "traffic": None, "launch_ms": compr_ms,
-            "algorithmic_flops": flops}
+            "unit": "TFLOP/s", "traffic": tr_comp,
+            "traffic_note": "HBM bytes per launch (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a "
+                            "256 MiB copy), profiles/%s_traffic.md" % args.workload,
+            "launches_per_build": n_compr, "ms_per_build": compr_ms,
+            "avg_launch_ms": compr_ms / max(n_compr, 1), "algorithmic_flops_per_build": flops}
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof_mv = {"kernel": "product (gather, up, coupling, down, near+scatter)", "bound": "hbm",
                "achieved": mv_bytes / (mv_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "traffic": None, "algorithmic_bytes": mv_bytes, "ms": mv_ms,
+               "traffic": tr_prod, "algorithmic_bytes": mv_bytes, "ms": mv_ms,
                "form": "HIP graph replay (%d replays)" % graph_replays,
                "eager_ms": mv_eager_ms, "eager_phase_ms": mv_ph}
     roof_mv["frac"] = roof_mv["achieved"] / roof_mv["peak"]

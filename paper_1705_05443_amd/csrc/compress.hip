@@ -52,6 +52,7 @@ struct IdArgs {
   int64_t wg_istride;
   int *swaps;    // total swap count (atomic)
   int *err;      // set to 1 when the swap cap is hit
+  int gt_out;    // k_compr_w: write G^T (k x (m-k) row-major) instead of G
 };
 
 // ---- block reductions --------------------------------------------------
@@ -698,9 +699,13 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
       // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
       // smallest j, then smallest i (pair index j*k + i).  G rows are
       // written on every pass; the last pass leaves the final ones.
+      // With gt_out the lanes write G^T: for each skeleton index the rows
+      // of consecutive lanes are consecutive in memory.
       ArgMax am{-1.0, -1};
       if (act && pa >= k) {
-        double *Gr = A.G_out + A.go[i] + (int64_t)(a - ex) * k;
+        const int64_t row = a - ex;
+        double *Gr = A.G_out + A.go[i] + (A.gt_out ? row : row * k);
+        const int64_t cs = A.gt_out ? (int64_t)nr : 1;
         const int base = (pa - k) * k;
 #pragma unroll
         for (int ii = 0; ii < CMAX; ii++) {
@@ -708,7 +713,7 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
             const double gw = nrm * rinv[ii];
             const double rho = sqrt(col[ii] * col[ii] + gw * gw);
             am = amax_pick(am, ArgMax{rho, base + ii});
-            Gr[srank[ii]] = col[ii];
+            Gr[srank[ii] * cs] = col[ii];
           }
         }
       }
@@ -1064,6 +1069,20 @@ __global__ void k_transpose_G(int nb, int ne, const int *m, const int *k, const 
   }
 }
 
+// G^T k x (m-k)  ->  G (m-k) x k, one workgroup per node
+__global__ void k_transpose_Gt(int nb, int ne, const int *m, const int *k, const int64_t *go,
+                               const double *Gt, double *G) {
+  int i = nb + blockIdx.x;
+  if (i >= ne) return;
+  const int kk = k[i], nr = m[i] - kk;
+  const double *src = Gt + go[i];
+  double *dst = G + go[i];
+  for (int e = threadIdx.x; e < nr * kk; e += blockDim.x) {
+    int a = e / kk, t = e - a * kk;
+    dst[e] = src[(int64_t)t * nr + a];
+  }
+}
+
 // BF16 copies of G for the matrix-core product (layouts in LevelSide)
 __global__ void k_gb_sizes(int nb, int ne, const int *m, const int *k, int64_t *cu, int64_t *cd) {
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
@@ -1140,6 +1159,7 @@ struct SideCtx {
   int mmax = 0;
   double *Svec = nullptr;
   int64_t *S_off = nullptr;
+  bool gt_first = false;  // compr wrote G^T (the register kernel)
 };
 
 void build_generators(Handle &h) {
@@ -1212,6 +1232,7 @@ void build_generators(Handle &h) {
         L.g_n = hv[1];
         L.sel = h.mem.alloc_n<int>(hv[0]);
         L.G = h.mem.alloc_n<double>(hv[1]);
+        L.Gt = h.mem.alloc_n<double>(hv[1]);
       }
       // (b) HSS: near-field SVD of each side
       if (hss) {
@@ -1294,7 +1315,10 @@ void build_generators(Handle &h) {
         int *iscr = tmp.alloc_n<int>((size_t)2 * ldw * nwg);
         IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo, S.go,
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
-                  h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1};
+                  h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1,
+                  reg ? 1 : 0};
+        if (reg) ia.G_out = L.Gt;  // the register kernel writes G^T
+        sc.gt_first = reg;
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
         auto launch = [&](int grid) {
           if (!reg) {
@@ -1323,12 +1347,14 @@ void build_generators(Handle &h) {
           }
         }
       }
-      // transposed copies of G for the downward pass
+      // the other orientation of G (the up pass reads G, the down pass G^T)
       for (auto &sc : sides) {
         Side &S = *sc.S;
         LevelSide &L = S.lv[l];
-        L.Gt = h.mem.alloc_n<double>(L.g_n);
-        k_transpose_G<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, L.Gt);
+        if (sc.gt_first)
+          k_transpose_Gt<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.Gt, L.G);
+        else
+          k_transpose_G<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, L.Gt);
         SMASH_CHECK_LAUNCH();
       }
       // (d) skeleton slots of this level
