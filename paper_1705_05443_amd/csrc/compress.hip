@@ -84,6 +84,26 @@ __device__ inline ArgMax block_argmax(ArgMax x, ArgMax *lds) {
   return r;
 }
 
+// The same with one barrier: lds holds two halves of blockDim/64 slots and
+// successive calls alternate (parity).  A half is rewritten two calls after
+// it was read, with the barrier of the call in between.
+__device__ inline ArgMax block_argmax_1b(ArgMax x, ArgMax *lds, int parity) {
+  for (int o = WAVE / 2; o > 0; o >>= 1) {
+    ArgMax y;
+    y.v = __shfl_xor(x.v, o, WAVE);
+    y.a = __shfl_xor(x.a, o, WAVE);
+    x = amax_pick(x, y);
+  }
+  const int nw = blockDim.x / WAVE;
+  const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  ArgMax *h = lds + parity * nw;
+  if (lane == 0) h[wid] = x;
+  __syncthreads();
+  ArgMax r = h[0];
+  for (int w = 1; w < nw; w++) r = amax_pick(r, h[w]);
+  return r;
+}
+
 __device__ inline double block_sum(double v, double *lds) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
   const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
@@ -447,7 +467,7 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
   __shared__ double v[CMAX], rinv[CMAX], rdiag[CMAX];
   __shared__ int srank[CMAX];
-  __shared__ ArgMax ared[NT / WAVE + 1];
+  __shared__ ArgMax ared[NT / WAVE + 1], ared2[2 * (NT / WAVE)];
   __shared__ int64_t sred[NT / WAVE + 1];
   __shared__ double vn_lds;
   const int a = threadIdx.x;
@@ -568,7 +588,7 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
           }
           const bool cand = act && (pivoting ? pa >= t : pa == t);
           ArgMax am = cand ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
-          am = block_argmax(am, ared);
+          am = block_argmax_1b(am, ared2, t & 1);
           const double bn = am.v;
           if (pivoting) {
             if (t == 0) {
@@ -591,16 +611,22 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
           }
           if (act && pa == t) {
             // the pivot column: v (rows r0..), R_tt
-            double x0 = 0.0, rest = 0.0;
+            double x0 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
 #pragma unroll
             for (int u = 0; u < 8; u++) {
               const double y = col[r0 + u];
               x0 = u == tt ? y : x0;
               const double z = u > tt ? y : 0.0;
-              rest = fma(z, z, rest);
+              q0 = fma(z, z, q0);
             }
 #pragma unroll
-            for (int r = r0 + 8; r < CMAX; r++) rest = fma(col[r], col[r], rest);
+            for (int r = r0 + 8; r < CMAX; r += 4) {
+              q0 = fma(col[r], col[r], q0);
+              q1 = fma(col[r + 1], col[r + 1], q1);
+              q2 = fma(col[r + 2], col[r + 2], q2);
+              q3 = fma(col[r + 3], col[r + 3], q3);
+            }
+            const double rest = (q0 + q1) + (q2 + q3);
             const double rtt = x0 >= 0.0 ? -bn : bn;
             const double v0 = x0 - rtt;
 #pragma unroll
@@ -640,10 +666,12 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
             }
             nrm = sqrt(s0 + s1);
           }
-          __syncthreads();
+          // no barrier here: v and vn_lds are next written after the next
+          // step's arg-max barrier, which every reader of them has passed
           kk = t + 1;
         }
       }
+      __syncthreads();
       return kk;
     };
 
