@@ -127,6 +127,7 @@ typedef struct {
   double *G;      /* (m-k) x k row-major                                */
   int ks;         /* HSS: number of kept singular vectors               */
   int nsw;        /* Gu-Eisenstat swaps performed                       */
+  double gap;     /* smallest relative margin of a pivot choice         */
 } side_t;
 
 typedef struct {
@@ -643,8 +644,9 @@ static void householder_step(double *W, int c, int m, int t) {
 }
 
 static int compr(const double *C, int m, int c, double tol, double f, int *k_out, int *sel,
-                 double *G, int *nswaps) {
+                 double *G, int *nswaps, double *min_gap) {
   *nswaps = 0;
+  if (min_gap) *min_gap = 1.0;
   if (m == 0) {
     *k_out = 0;
     return OR_OK;
@@ -661,15 +663,18 @@ static int compr(const double *C, int m, int c, double tol, double f, int *k_out
   double r00 = 0.0;
   for (int t = 0; t < kmax; t++) {
     int best = -1;
-    double bn = -1.0;
+    double bn = -1.0, b2 = -1.0; /* largest and second largest residual norm */
     for (int a = t; a < m; a++) {
       double s = 0.0;
       const double *y = W + (size_t)a * c;
       for (int r = t; r < c; r++) s += y[r] * y[r];
       double nr = sqrt(s);
       if (nr > bn) {
+        b2 = bn;
         bn = nr;
         best = a;
+      } else if (nr > b2) {
+        b2 = nr;
       }
     }
     if (t == 0) {
@@ -678,6 +683,8 @@ static int compr(const double *C, int m, int c, double tol, double f, int *k_out
     } else if (bn <= tol * r00) {
       break;
     }
+    /* relative margin of this pivot choice (a test diagnostic only) */
+    if (min_gap && b2 >= 0.0 && (bn - b2) / bn < *min_gap) *min_gap = (bn - b2) / bn;
     if (best != t) {
       for (int r = 0; r < c; r++) {
         double tmp = W[(size_t)t * c + r];
@@ -912,7 +919,7 @@ static int compress_node(oracle_t *h, int i, int rowside) {
   s->G = (double *)malloc(sizeof(double) * ((size_t)m * c + 1));
   if (!s->G) return OR_ENOMEM;
   int nsw = 0;
-  int rc = compr(C, m, c, h->tol, h->f, &s->k, s->sel, s->G, &nsw);
+  int rc = compr(C, m, c, h->tol, h->f, &s->k, s->sel, s->G, &nsw, &s->gap);
   s->nsw = nsw;
   free(C);
   free(pts);
@@ -1241,7 +1248,7 @@ enum {
   EX_PERM_X = 1, EX_PERM_Y = 2, EX_NODES = 3, EX_BOXES = 4, EX_L = 5, EX_LM = 6,
   EX_NEAR_PTR = 7, EX_NEAR_IDX = 8, EX_RANKS = 9, EX_ROW_SEL = 10, EX_ROW_G = 11,
   EX_COL_SEL = 12, EX_COL_G = 13, EX_ROW_GRID = 14, EX_COL_GRID = 15, EX_SIZES = 16,
-  EX_LEVELS = 17, EX_SWAPS = 18
+  EX_LEVELS = 17, EX_SWAPS = 18, EX_MARGINS = 19
 };
 
 int oracle_export(void *hv, int what, void *buf, int64_t *count) {
@@ -1314,6 +1321,14 @@ int oracle_export(void *hv, int what, void *buf, int64_t *count) {
           int *o = ib + (size_t)i * 6;
           o[0] = h->row[i].m; o[1] = h->row[i].k; o[2] = h->col[i].m; o[3] = h->col[i].k;
           o[4] = h->row[i].ks; o[5] = h->col[i].ks;
+        }
+      break;
+    case EX_MARGINS: /* double x 2: smallest relative pivot margin, row and column side */
+      n = (int64_t)nn * 2;
+      if (buf)
+        for (int i = 0; i < nn; i++) {
+          db[2 * i] = h->row[i].gap;
+          db[2 * i + 1] = h->col[i].gap;
         }
       break;
     case EX_SWAPS: /* int32 x 2: swaps of the row and column side per node */
@@ -1397,7 +1412,7 @@ void oracle_kernel_block(const double *P, const double *Qp, int64_t nr, int64_t 
 
 int oracle_compr(const double *C, int m, int c, double tol, double f, int *k, int *sel,
                  double *G, int *nswaps) {
-  return compr(C, m, c, tol, f, k, sel, G, nswaps);
+  return compr(C, m, c, tol, f, k, sel, G, nswaps, NULL);
 }
 
 void oracle_interp_basis(const double *pts, int m, int d, const double *lo, const double *hi,

@@ -815,20 +815,25 @@ struct SvdArgs {
 // (mp <= 8 VCL entries) are read into registers at once, rotated there and
 // written back -- the same arithmetic in the same order as the general
 // loops (NCL = VCL = 0), without a chain of dependent loads per entry.
-template <int NCL, int VCL>
-__global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
+// LDS: the block lives in dynamic LDS with row stride ldl and V in columns
+// [voff, voff + mp) of the same rows (voff >= every nc of the level);
+// otherwise A and V are in the workgroup's global tile.  Same arithmetic.
+template <int NCL, int VCL, bool LDS>
+__global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int ldl, int voff) {
+  extern __shared__ double dyn_svd[];
   __shared__ double sg[SV_MMAX];
   __shared__ int ord[SV_MMAX];
   __shared__ int any_rot;
   const int tid = threadIdx.x;
-  double *Am = A.scratch + (int64_t)blockIdx.x * A.wg_stride;
+  double *Am = LDS ? dyn_svd : A.scratch + (int64_t)blockIdx.x * A.wg_stride;
   for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
     const int m = A.m_me[i];
     int nc = 0;
     for (int q = A.Nrow[i]; q < A.Nrow[i + 1]; q++) nc += A.m_ot[A.Ncol[q]];
-    const int ldn = A.ldn;
+    const int ldn = LDS ? ldl : A.ldn;
     const int mp = m + (m & 1);  // even row count (a zero row pads odd m)
-    double *V = Am + (int64_t)mp * ldn;
+    double *V = LDS ? Am + voff : Am + (int64_t)mp * ldn;
+    const int64_t ldv = LDS ? ldn : mp;
     __syncthreads();
     if (m == 0 || nc == 0) {
       if (tid == 0) A.ks_out[i] = 0;
@@ -854,8 +859,9 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
         }
         o += mj;
       }
-      for (int e = tid; e < mp * mp; e += SV_NT) V[e] = (e / mp == e % mp) ? 1.0 : 0.0;
     }
+    __syncthreads();
+    for (int e = tid; e < mp * mp; e += SV_NT) V[(e / mp) * ldv + e % mp] = (e / mp == e % mp) ? 1.0 : 0.0;
     __syncthreads();
     // Jacobi sweeps
     const int g = tid / SV_G, gl = tid % SV_G;
@@ -935,22 +941,22 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
             for (int u = 0; u < VCL; u++) {
               const int t = gl + SV_G * u;
               const int tc = t < mp ? t : 0;
-              vx[u] = V[(int64_t)tc * mp + pp];
-              vy[u] = V[(int64_t)tc * mp + qq];
+              vx[u] = V[tc * ldv + pp];
+              vy[u] = V[tc * ldv + qq];
             }
 #pragma unroll
             for (int u = 0; u < VCL; u++) {
               const int t = gl + SV_G * u;
               if (t < mp) {
-                V[(int64_t)t * mp + pp] = cs * vx[u] - sn * vy[u];
-                V[(int64_t)t * mp + qq] = sn * vx[u] + cs * vy[u];
+                V[t * ldv + pp] = cs * vx[u] - sn * vy[u];
+                V[t * ldv + qq] = sn * vx[u] + cs * vy[u];
               }
             }
           } else {
             for (int t = gl; t < mp; t += SV_G) {
-              double x = V[(int64_t)t * mp + pp], y = V[(int64_t)t * mp + qq];
-              V[(int64_t)t * mp + pp] = cs * x - sn * y;
-              V[(int64_t)t * mp + qq] = sn * x + cs * y;
+              double x = V[t * ldv + pp], y = V[t * ldv + qq];
+              V[t * ldv + pp] = cs * x - sn * y;
+              V[t * ldv + qq] = sn * x + cs * y;
             }
           }
         }
@@ -981,7 +987,7 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A) {
     double *S = A.S + A.S_off[i - A.nb];
     for (int e = tid; e < m * ks; e += SV_NT) {
       int r = e / ks, q = e % ks;
-      S[e] = V[(int64_t)r * mp + ord[q]];
+      S[e] = V[r * ldv + ord[q]];
     }
     if (tid == 0) A.ks_out[i] = ks;
   }
@@ -1297,10 +1303,25 @@ void build_generators(Handle &h) {
           // register-staged rotations when a pair's rows and V columns fit
           const int ncl = ncmax <= 64 ? 8 : ncmax <= 128 ? 16 : ncmax <= 256 ? 32 : 0;
           const int vcl = mp <= 32 ? 4 : mp <= 64 ? 8 : mp <= 128 ? 16 : 0;
+          // whole block (and V beside it) in LDS when it fits
+          const int voff = ncmax;
+          const int ldl = (ncmax + mp + 1) | 1;
+          const size_t shl = sizeof(double) * (size_t)mp * ldl;
+          const bool lds = shl + 8 * 1024 <= (size_t)dev_lds;
           auto svd = [&](int grid) {
-#define SMASH_SVD_CASE(NC, VC) \
-  else if (ncl == NC && vcl == VC) k_near_svd<NC, VC><<<grid, SV_NT, 0, s>>>(sa);
-            if (ncl == 0 || vcl == 0) k_near_svd<0, 0><<<grid, SV_NT, 0, s>>>(sa);
+#define SMASH_SVD_CASE(NC, VC)                                              \
+  else if (ncl == NC && vcl == VC) {                                        \
+    if (lds)                                                                \
+      k_near_svd<NC, VC, true><<<grid, SV_NT, shl, s>>>(sa, ldl, voff);           \
+    else                                                                    \
+      k_near_svd<NC, VC, false><<<grid, SV_NT, 0, s>>>(sa, 0, 0);              \
+  }
+            if (ncl == 0 || vcl == 0) {
+              if (lds)
+                k_near_svd<0, 0, true><<<grid, SV_NT, shl, s>>>(sa, ldl, voff);
+              else
+                k_near_svd<0, 0, false><<<grid, SV_NT, 0, s>>>(sa, 0, 0);
+            }
             SMASH_SVD_CASE(8, 4) SMASH_SVD_CASE(8, 8) SMASH_SVD_CASE(8, 16)
             SMASH_SVD_CASE(16, 4) SMASH_SVD_CASE(16, 8) SMASH_SVD_CASE(16, 16)
             SMASH_SVD_CASE(32, 4) SMASH_SVD_CASE(32, 8) SMASH_SVD_CASE(32, 16)
@@ -1308,7 +1329,7 @@ void build_generators(Handle &h) {
             SMASH_CHECK_LAUNCH();
           };
           if (h.batched) {
-            svd(nwg);
+            svd(lds ? std::min(nl, 2 * dev_cus) : nwg);
           } else {
             for (int i = nb; i < ne; i++) {
               sa.nb = i;

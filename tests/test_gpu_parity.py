@@ -94,6 +94,53 @@ def _split(arr, sizes):
     return out
 
 
+# HSS: the near-field vectors in C = [U-hat, S] are fixed only to about
+# eps_mach / eps_svd by any SVD, so a pivot of compr whose oracle margin
+# (relative gap between the best and second-best residual norm) is below
+# this is a genuine near-tie: the two skeleton choices are equally valid.
+HSS_TIE = 1e-5
+
+
+def _gpu_per_node(g, side, nn):
+    rk = g.export("ranks").reshape(-1, 6)
+    mc, kc = (0, 1) if side == "row" else (2, 3)
+    grid, sel, G = g.export(side + "_grid"), g.export(side + "_sel"), g.export(side + "_G")
+    out = [(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros((0, 0)))]
+    og = og2 = 0
+    for i in range(1, nn):
+        m, k = int(rk[i, mc]), int(rk[i, kc])
+        out.append((grid[og:og + m], sel[og:og + m], G[og2:og2 + (m - k) * k].reshape(m - k, k)))
+        og += m
+        og2 += (m - k) * k
+    return out
+
+
+def _hss_tie_subtrees(o, g, side, c):
+    """Nodes whose results may differ from the oracle's: every node whose
+    own pivot decision is a near-tie (oracle margin < HSS_TIE) and differs,
+    and its ancestors (their grids are built from it).  Any other difference
+    fails."""
+    ro, rg = o.ranks(), g.export("ranks").reshape(-1, 6)
+    nodes = g.export("nodes").reshape(-1, 8)
+    nn = nodes.shape[0]
+    margin = o.export(O.EX_MARGINS).reshape(-1, 2)[:, 0 if side == "row" else 1]
+    po, pg = O.Oracle.per_node(o, side), _gpu_per_node(g, side, nn)
+    tainted = np.zeros(nn, bool)
+    for i in range(nn - 1, 0, -1):  # children come after their parents
+        fc, nc_ = nodes[i, 2], nodes[i, 3]
+        below = nc_ > 0 and tainted[fc:fc + nc_].any()
+        same = (ro[i, c] == rg[i, c] and ro[i, c + 1] == rg[i, c + 1]
+                and ro[i, 4 + c // 2] == rg[i, 4 + c // 2]
+                and np.array_equal(po[i][0], pg[i][0]) and np.array_equal(po[i][1], pg[i][1]))
+        if below:
+            tainted[i] = True
+        elif not same:
+            assert margin[i] < HSS_TIE, (side, "node", i, "differs with oracle margin", margin[i])
+            print("near-tie at node", i, side, "margin %.2e" % margin[i], flush=True)
+            tainted[i] = True
+    return tainted
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_ranks_skeletons_and_G(name):
     x, y, o, g = pair_for(name)
@@ -102,37 +149,45 @@ def test_ranks_skeletons_and_G(name):
     sides = [("row", 0, O.EX_ROW_SEL, O.EX_ROW_G, O.EX_ROW_GRID)]
     if not (y is None and CASES[name][1]["kernel"] != "cauchy"):
         sides.append(("col", 2, O.EX_COL_SEL, O.EX_COL_G, O.EX_COL_GRID))
+    weak = CASES[name][1]["adm"] == "weak"
     for side, c, exs, exg, exgrid in sides:
         m_o, k_o = ro[1:, c], ro[1:, c + 1]
         m_g, k_g = rg[1:, c], rg[1:, c + 1]
+        if weak:
+            keep = ~_hss_tie_subtrees(o, g, side, c)[1:]
+        else:
+            keep = np.ones(len(m_o), bool)
         # grids and ranks follow from the skeleton choices below them
-        bad = np.nonzero((m_o != m_g) | (k_o != k_g))[0]
+        bad = np.nonzero(keep & ((m_o != m_g) | (k_o != k_g)))[0]
         assert bad.size == 0, (side, "first differing node", 1 + bad[:5])
-        if CASES[name][1]["adm"] == "weak":
-            assert np.array_equal(ro[1:, 4 + c // 2], rg[1:, 4 + c // 2]), "SVD ranks"
-        sel_o, sel_g = o.export(exs), g.export(side + "_sel")
-        assert np.array_equal(o.export(exgrid), g.export(side + "_grid"))
-        assert np.array_equal(sel_o, sel_g), side
+        if weak:
+            assert np.array_equal(ro[1:, 4 + c // 2][keep], rg[1:, 4 + c // 2][keep]), "SVD ranks"
+        if keep.all():
+            sel_o, sel_g = o.export(exs), g.export(side + "_sel")
+            assert np.array_equal(o.export(exgrid), g.export(side + "_grid"))
+            assert np.array_equal(sel_o, sel_g), side
         Go = _split(o.export(exg), (m_o - k_o) * k_o)
         Gg = _split(g.export(side + "_G"), (m_g - k_g) * k_g)
-        if CASES[name][1]["adm"] == "strong":
+        if not weak:
             worst = 0.0
             for a, b in zip(Go, Gg):
                 if a.size:
                     worst = max(worst, float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a)))))
             assert worst < 1e-9, (side, worst)
         else:
-            _check_hss_ids(x, y, g, side, m_o, k_o, sel_o, Go, Gg, CASES[name][1]["order"])
+            _check_hss_ids(x, y, g, side, m_g, k_g, g.export(side + "_sel"), Go, Gg,
+                           CASES[name][1]["order"], keep)
 
 
-def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order):
+def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep):
     """HSS: C = [U-hat, S] contains near-field singular vectors whose trailing
     members (sigma near eps_svd * sigma_1) are fixed only to about
     eps_mach / eps_svd, so two correct implementations agree on the skeleton
     sets (checked above) but not on G to 1e-9.  Checked instead: the
     Gu-Eisenstat bound |G| <= f, and that G reproduces the far-field basis
     U-hat on the node's grid as well as the oracle's G does (ID residual,
-    eq. (2.11)).  The product itself is held to 1e-10 elsewhere."""
+    eq. (2.11)) -- at nodes inside a near-tie subtree (keep False) against
+    the exact basis alone.  The product itself is held to 1e-10 elsewhere."""
     P = x if side == "row" else (x if y is None else y)
     perm = g.export("perm_x" if side == "row" else "perm_y")
     grid = _split(g.export(side + "_grid"), m)
@@ -148,11 +203,14 @@ def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order):
         U = O.interp_basis(pts, bx[node, :1], bx[node, 3:4], order)
         sk, rs = sels[i][:kk], sels[i][kk:]
         Gg_ = Gg[i].reshape(mm - kk, kk)
-        Go_ = Go[i].reshape(mm - kk, kk)
         nrm = np.linalg.norm(U)
         r_g = np.linalg.norm(U[rs] - Gg_ @ U[sk])
-        r_o = np.linalg.norm(U[rs] - Go_ @ U[sk])
-        assert r_g <= 10.0 * r_o + 1e-12 * nrm, (node, r_g, r_o)
+        if keep[i]:
+            Go_ = Go[i].reshape(mm - kk, kk)
+            r_o = np.linalg.norm(U[rs] - Go_ @ U[sk])
+            assert r_g <= 10.0 * r_o + 1e-12 * nrm, (node, r_g, r_o)
+        else:
+            assert r_g <= 1e-6 * nrm, (node, r_g)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -165,9 +223,11 @@ def test_coupling_blocks_are_kernel_entries(name):
     B = g.export("coupling")
     rk = g.export("ranks").reshape(-1, 6)
     px, py = g.export("perm_x"), g.export("perm_y")
-    per_r = O.Oracle.per_node(o, "row")
+    # at the library's own skeletons (they equal the oracle's, up to the
+    # near-ties allowed above)
     reuse = y is None and kw["kernel"] != "cauchy"
-    per_c = per_r if reuse else O.Oracle.per_node(o, "col")
+    per_r = _gpu_per_node(g, "row", rk.shape[0])
+    per_c = per_r if reuse else _gpu_per_node(g, "col", rk.shape[0])
     off = 0
     rng = np.random.default_rng(0)
     pick = set(rng.choice(len(L), size=min(len(L), 200), replace=False).tolist())
