@@ -196,11 +196,12 @@ __device__ __forceinline__ void reduce_waves_n(typename Mfma<T>::acc_t *acc, T *
 
 constexpr int MV_WAVES = 4;  // wavefronts per node in the coupling and near products
 
-// 16-row tiles per pass: four for one column tile (FP32: two), else two, so
-// that accumulators and operands stay within 128 registers
+// 16-row tiles per pass: four for FP32 with one or two column tiles, else
+// two (FP64: most blocks and leaves have fewer than 32 rows), keeping the
+// operands within 128 registers
 template <class T, int CT>
 struct MvShape {
-  static constexpr int TT = (CT >= 3 || (sizeof(T) == 8 && CT >= 2)) ? 2 : 4;
+  static constexpr int TT = (CT >= 3 || sizeof(T) == 8) ? 2 : 4;
 };
 
 // One workgroup per row node: MV_WAVES waves split its pairs, and each wave
