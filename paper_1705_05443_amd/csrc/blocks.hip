@@ -51,10 +51,10 @@ struct EvalArgs {
 // (row, column) pair instead of dividing by the row count per entry.
 constexpr int EV_STAGE = 256;
 
-template <class T, bool F32MATH>
+template <class T, bool F32MATH, int KID, int D>
 __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
   __shared__ double xs[EV_STAGE * 3], ys[EV_STAGE * 3];
-  const int d = A.d;
+  constexpr int d = D;
   for (int64_t e = blockIdx.x; e < A.npairs; e += gridDim.x) {
     int i = A.pi[e], j = A.pj[e];
     int64_t r0, c0;
@@ -106,9 +106,9 @@ __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
         yp = A.Yp + yc * d;
       }
       if (F32MATH)
-        B[q] = (T)kernel_f32(A.kid, xp, yp, d, (float)A.diag);
+        B[q] = (T)kernel_f32_t<KID, D>(xp, yp, (float)A.diag);
       else
-        B[q] = (T)kernel_f64(A.kid, xp, yp, d, A.diag);
+        B[q] = (T)kernel_f64_t<KID, D>(xp, yp, A.diag);
       a += sa;
       b += sb;
       if (a >= nr) {
@@ -169,14 +169,33 @@ static void eval_launch_bf16(Handle &h, EvalArgs &ea, unsigned short *out, bool 
   SMASH_CHECK_LAUNCH();
 }
 
+template <class T, bool F32MATH, int KID>
+static void eval_launch_k(int nblk, EvalArgs &ea, T *out, hipStream_t s) {
+  switch (ea.d) {
+    case 1: k_eval_blocks<T, F32MATH, KID, 1><<<nblk, 256, 0, s>>>(ea, out); break;
+    case 2: k_eval_blocks<T, F32MATH, KID, 2><<<nblk, 256, 0, s>>>(ea, out); break;
+    default: k_eval_blocks<T, F32MATH, KID, 3><<<nblk, 256, 0, s>>>(ea, out); break;
+  }
+}
+
+template <class T, bool F32MATH>
+static void eval_launch_m(int nblk, EvalArgs &ea, T *out, hipStream_t s) {
+  switch (ea.kid) {
+    case SMASH_KERNEL_INV_R: eval_launch_k<T, F32MATH, SMASH_KERNEL_INV_R>(nblk, ea, out, s); break;
+    case SMASH_KERNEL_LOG_R: eval_launch_k<T, F32MATH, SMASH_KERNEL_LOG_R>(nblk, ea, out, s); break;
+    case SMASH_KERNEL_EXP_R: eval_launch_k<T, F32MATH, SMASH_KERNEL_EXP_R>(nblk, ea, out, s); break;
+    default: eval_launch_k<T, F32MATH, SMASH_KERNEL_CAUCHY>(nblk, ea, out, s); break;
+  }
+}
+
 template <class T>
 static void eval_launch(Handle &h, EvalArgs &ea, T *out, bool f32math) {
   int nblk = ea.npairs < (1 << 20) ? (int)ea.npairs : (1 << 20);
   if (nblk <= 0) return;
   if (f32math)
-    k_eval_blocks<T, true><<<nblk, 256, 0, h.stream>>>(ea, out);
+    eval_launch_m<T, true>(nblk, ea, out, h.stream);
   else
-    k_eval_blocks<T, false><<<nblk, 256, 0, h.stream>>>(ea, out);
+    eval_launch_m<T, false>(nblk, ea, out, h.stream);
   SMASH_CHECK_LAUNCH();
 }
 

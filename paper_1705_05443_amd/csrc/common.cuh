@@ -85,6 +85,46 @@ __device__ inline float kernel_f32(int kid, const double *x, const double *y, in
   return 1.0f / dx0;
 }
 
+// The same two evaluations with the kernel and the dimension fixed at
+// compile time (identical operations in the same order, so identical
+// results); the block evaluation instantiates them per kernel and dim.
+template <int KID, int D>
+__device__ __forceinline__ double kernel_f64_t(const double *x, const double *y, double diag) {
+  double r2 = 0.0;
+  bool same = true;
+#pragma unroll
+  for (int t = 0; t < D; t++) {
+    double df = x[t] - y[t];
+    same = same && (x[t] == y[t]);
+    r2 += df * df;
+  }
+  if (KID == SMASH_KERNEL_EXP_R) return exp(-sqrt(r2));
+  if (same) return diag;
+  if (KID == SMASH_KERNEL_INV_R) return 1.0 / sqrt(r2);
+  if (KID == SMASH_KERNEL_LOG_R) return 0.5 * log(r2);
+  return 1.0 / (x[0] - y[0]);
+}
+
+template <int KID, int D>
+__device__ __forceinline__ float kernel_f32_t(const double *x, const double *y, float diag) {
+  float r2 = 0.0f;
+  bool same = true;
+  float dx0 = 0.0f;
+#pragma unroll
+  for (int t = 0; t < D; t++) {
+    double df = x[t] - y[t];
+    same = same && (x[t] == y[t]);
+    float f = (float)df;
+    if (t == 0) dx0 = f;
+    r2 += f * f;
+  }
+  if (KID == SMASH_KERNEL_EXP_R) return __expf(-sqrtf(r2));
+  if (same) return diag;
+  if (KID == SMASH_KERNEL_INV_R) return rsqrtf(r2);
+  if (KID == SMASH_KERNEL_LOG_R) return 0.5f * __logf(r2);
+  return 1.0f / dx0;
+}
+
 // Def. 2.1, eq. (2.3) on boxes: delta_i + delta_j <= tau |c_i - c_j| with c
 // the box centre and delta half its diagonal, decided exactly without a
 // square root: e = tau^2 D^2 - delta_i^2 - delta_j^2 >= 0 and

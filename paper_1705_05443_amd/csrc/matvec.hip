@@ -196,12 +196,17 @@ __device__ __forceinline__ void reduce_waves_n(typename Mfma<T>::acc_t *acc, T *
 
 constexpr int MV_WAVES = 4;  // wavefronts per node in the coupling and near products
 
-// 16-row tiles per pass: four for FP32 with one or two column tiles, else
-// two (FP64: most blocks and leaves have fewer than 32 rows), keeping the
-// operands within 128 registers
+// 16-row tiles per pass, keeping the operands within 128 registers: the
+// coupling product four (FP64 with more than one column tile, or any with
+// three or four: two); the near field two for FP64 (most leaves hold fewer
+// than 32 points), else as the coupling product
 template <class T, int CT>
 struct MvShape {
-  static constexpr int TT = (CT >= 3 || sizeof(T) == 8) ? 2 : 4;
+  static constexpr int TT = (CT >= 3 || (sizeof(T) == 8 && CT >= 2)) ? 2 : 4;
+};
+template <class T, int CT>
+struct NearShape {
+  static constexpr int TT = sizeof(T) == 8 ? 2 : MvShape<T, CT>::TT;
 };
 
 // One workgroup per row node: MV_WAVES waves split its pairs, and each wave
@@ -433,7 +438,7 @@ static void launch_coupling(const CouplingArgs &ca, const T *q, T *z, int RP, in
 template <class T, int CT>
 static void launch_near(const NearArgs &na, const T *q, const T *z, T *Y, int64_t ldy, int R,
                         int RP, int nitems, hipStream_t s) {
-  k_mv_near_out<T, MvShape<T, CT>::TT, CT>
+  k_mv_near_out<T, NearShape<T, CT>::TT, CT>
       <<<xcd_grid(nitems, na.xrun), MV_NT * MV_WAVES, 0, s>>>(na, q, z, Y, ldy, R, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
