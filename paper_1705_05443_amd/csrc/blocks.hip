@@ -219,7 +219,8 @@ void build_blocks(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
-    SMASH_HIP(hipMemcpyAsync(&h.b_entries, h.boff + h.nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    int64_t *pin = pinned_words();
+    SMASH_HIP(hipMemcpyAsync(pin, h.boff + h.nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     // near field
     int64_t *ncnt = tmp.alloc_n<int64_t>(h.nLm);
     h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
@@ -229,8 +230,10 @@ void build_blocks(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
-    SMASH_HIP(hipMemcpyAsync(&h.n_entries, h.nboff + h.nLm, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    SMASH_HIP(hipMemcpyAsync(pin + 1, h.nboff + h.nLm, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SMASH_HIP(hipStreamSynchronize(s));
+    h.b_entries = pin[0];
+    h.n_entries = pin[1];
     h.B = h.mem.alloc(es * (size_t)(h.b_entries > 0 ? h.b_entries : 1));
     h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
     PhaseTimer pt(h, SMASH_PHASE_BLOCKS, s);

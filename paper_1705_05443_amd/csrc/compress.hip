@@ -1198,8 +1198,9 @@ struct SideCtx {
 
 void build_generators(Handle &h) {
   hipStream_t s = h.stream;
-  DeviceArena tmp;
+  DeviceArena tmp, keep;  // per-level temporaries; counters for the whole build
   tmp.stream = s;
+  keep.stream = s;
   try {
     const int c0 = [&] {
       int c = 1;
@@ -1225,8 +1226,8 @@ void build_generators(Handle &h) {
       k_leaf_init<<<ceil_div(nn, 256), 256, 0, s>>>(nn, h.nchild, sc.xb, sc.xe, S.m, S.gbeg, S.k);
       SMASH_CHECK_LAUNCH();
     }
-    int *dmax = tmp.alloc_n<int>(2);
-    int *dsw = tmp.alloc_n<int>(2);
+    int *dmax = keep.alloc_n<int>(2);
+    int *dsw = keep.alloc_n<int>(2);
     SMASH_HIP(hipMemsetAsync(dsw, 0, 2 * sizeof(int), s));
     int dev_cus = 256, dev_lds = 64 * 1024;
     if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, h.device) !=
@@ -1256,10 +1257,13 @@ void build_generators(Handle &h) {
         SMASH_CHECK_LAUNCH();
         int64_t hv[2];
         int mx;
-        SMASH_HIP(hipMemcpyAsync(&hv[0], o1 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(&hv[1], o2 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(&mx, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
+        int64_t *pin = pinned_words();
+        SMASH_HIP(hipMemcpyAsync(pin, o1 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipMemcpyAsync(pin + 1, o2 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipMemcpyAsync(pin + 2, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipStreamSynchronize(s));
+        std::memcpy(hv, pin, sizeof(hv));
+        std::memcpy(&mx, pin + 2, sizeof(int));
         sc.mmax = mx;
         LevelSide &L = S.lv[l];
         L.sel_n = hv[0];
@@ -1283,9 +1287,12 @@ void build_generators(Handle &h) {
           scan_i64(scap, soff, nl, nullptr, s, tmp);
           int64_t stot;
           int ncmax;
-          SMASH_HIP(hipMemcpyAsync(&stot, soff + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-          SMASH_HIP(hipMemcpyAsync(&ncmax, dmax + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+          int64_t *pin = pinned_words();
+          SMASH_HIP(hipMemcpyAsync(pin, soff + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+          SMASH_HIP(hipMemcpyAsync(pin + 1, dmax + 1, sizeof(int), hipMemcpyDeviceToHost, s));
           SMASH_HIP(hipStreamSynchronize(s));
+          std::memcpy(&stot, pin, sizeof(stot));
+          std::memcpy(&ncmax, pin + 1, sizeof(int));
           if (sc.mmax > SV_MMAX)
             throw Error{SMASH_E_UNSUPPORTED, "HSS grid larger than " + std::to_string(SV_MMAX) +
                                                  " points (raise leaf resolution)"};
@@ -1360,8 +1367,9 @@ void build_generators(Handle &h) {
         const int nwg = !h.batched ? 1 : nl < wcap ? nl : wcap;
         int64_t wg_stride = (int64_t)cmax * ldw + (int64_t)h.d * h.p * ldw + ldw +
                             (int64_t)cmax * cmax + 8;
-        double *scr = tmp.alloc_n<double>((size_t)wg_stride * nwg);
-        int *iscr = tmp.alloc_n<int>((size_t)2 * ldw * nwg);
+        // the tile form's per-workgroup scratch (the register form needs none)
+        double *scr = reg ? nullptr : tmp.alloc_n<double>((size_t)wg_stride * nwg);
+        int *iscr = reg ? nullptr : tmp.alloc_n<int>((size_t)2 * ldw * nwg);
         IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo, S.go,
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1,
@@ -1411,15 +1419,13 @@ void build_generators(Handle &h) {
         Side &S = *sc.S;
         int64_t *ck = tmp.alloc_n<int64_t>(nl), *ok = tmp.alloc_n<int64_t>(nl + 1);
         int64_t *base = tmp.alloc_n<int64_t>(1);
-        SMASH_HIP(hipMemcpyAsync(base, &S.nslots, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        set_i64(base, S.nslots, s);
         k_kcopy<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.k, ck);
         SMASH_CHECK_LAUNCH();
         scan_i64(ck, ok, nl, base, s, tmp);
         k_set_hbeg<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, ok, S.hbeg);
         SMASH_CHECK_LAUNCH();
-        int64_t end;
-        SMASH_HIP(hipMemcpyAsync(&end, ok + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipStreamSynchronize(s));
+        const int64_t end = read_one(s, ok + nl);
         grow_slots(h, S, end);
         {
           PhaseTimer pt(h, SMASH_PHASE_SLOTS, s);
@@ -1429,19 +1435,21 @@ void build_generators(Handle &h) {
         }
         S.nslots = end;
       }
-      int herr[2];
-      SMASH_HIP(hipMemcpyAsync(herr, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
-      SMASH_HIP(hipStreamSynchronize(s));
-      if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
-      tmp.release();
-      dmax = tmp.alloc_n<int>(2);
-      int *nsw = tmp.alloc_n<int>(2);
-      SMASH_HIP(hipMemcpyAsync(nsw, herr, sizeof(herr), hipMemcpyHostToDevice, s));
-      dsw = nsw;
+      // per-level temporaries are dropped once they grow large (the swap
+      // counters and the max cells live in `keep`, allocated once)
+      if (tmp.bytes > ((int64_t)256 << 20)) {
+        SMASH_HIP(hipStreamSynchronize(s));
+        tmp.release();
+      }
     }
     int herr[2] = {0, 0};
-    SMASH_HIP(hipMemcpyAsync(herr, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
-    SMASH_HIP(hipStreamSynchronize(s));
+    {
+      int64_t *pin = pinned_words();
+      SMASH_HIP(hipMemcpyAsync(pin, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipStreamSynchronize(s));
+      std::memcpy(herr, pin, sizeof(herr));
+    }
+    if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
     h.total_swaps = herr[0];
     // apply copies
     if (h.apply_prec == SMASH_F32) {
@@ -1477,10 +1485,11 @@ void build_generators(Handle &h) {
           SMASH_CHECK_LAUNCH();
           k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, od, S.gobd);
           SMASH_CHECK_LAUNCH();
-          int64_t tot[2];
-          SMASH_HIP(hipMemcpyAsync(&tot[0], ou + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-          SMASH_HIP(hipMemcpyAsync(&tot[1], od + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+          int64_t *pin = pinned_words();
+          SMASH_HIP(hipMemcpyAsync(pin, ou + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+          SMASH_HIP(hipMemcpyAsync(pin + 1, od + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
           SMASH_HIP(hipStreamSynchronize(s));
+          const int64_t tot[2] = {pin[0], pin[1]};
           L.gbu_n = tot[0];
           L.gbd_n = tot[1];
           L.Gbu = h.mem.alloc_n<unsigned short>(tot[0]);
@@ -1493,9 +1502,11 @@ void build_generators(Handle &h) {
     }
     SMASH_HIP(hipStreamSynchronize(s));
     tmp.release();
+    keep.release();
   } catch (...) {
     (void)hipStreamSynchronize(s);
     tmp.release();
+    keep.release();
     throw;
   }
 }

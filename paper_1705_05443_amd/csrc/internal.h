@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <cstring>
 #include <vector>
 
 #include "../../include/smash.h"
@@ -79,6 +80,23 @@ void scan_i64(const int64_t *in, int64_t *out, int64_t n, const int64_t *base_de
 // land in keys/vals (alt buffers are scratch of the same size).
 void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
                     int64_t n, int nbits, hipStream_t s, DeviceArena &tmp);
+
+// ---------------------------------------------------------------- host reads
+// A per-thread pinned buffer of 64 words (hipHostMalloc, kept for the life of
+// the thread) for the build's small device-to-host reads: the copies go
+// straight to pinned memory and one stream synchronization covers them.
+int64_t *pinned_words();
+template <class T>
+T read_one(hipStream_t s, const T *dev) {
+  int64_t *p = pinned_words();
+  SMASH_HIP(hipMemcpyAsync(p, dev, sizeof(T), hipMemcpyDeviceToHost, s));
+  SMASH_HIP(hipStreamSynchronize(s));
+  T v;
+  std::memcpy(&v, p, sizeof(T));
+  return v;
+}
+// Sets one device int64 from a kernel argument (no host-memory copy).
+void set_i64(int64_t *dev, int64_t v, hipStream_t s);
 
 // ---------------------------------------------------------------- handle
 struct LevelSide {

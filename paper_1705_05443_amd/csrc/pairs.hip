@@ -188,10 +188,7 @@ __global__ void k_near_emit(TreeView T, int nb, int ne, int *Nrow, int *Ncol, co
 
 template <class T>
 static T readback1(hipStream_t s, const T *dev) {
-  T v;
-  SMASH_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, s));
-  SMASH_HIP(hipStreamSynchronize(s));
-  return v;
+  return read_one(s, dev);
 }
 
 static int bits_for(uint64_t v) {
@@ -240,10 +237,12 @@ void build_pairs(Handle &h) {
         scan_i64(c + nf, o + nf + 1, nf, nullptr, s, tmp);
         scan_i64(c + 2 * nf, o + 2 * (nf + 1), nf, nullptr, s, tmp);
         int64_t tot[3];
-        SMASH_HIP(hipMemcpyAsync(&tot[0], o + nf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(&tot[1], o + 2 * nf + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(&tot[2], o + 3 * nf + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        int64_t *pin = pinned_words();
+        SMASH_HIP(hipMemcpyAsync(pin, o + nf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipMemcpyAsync(pin + 1, o + 2 * nf + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        SMASH_HIP(hipMemcpyAsync(pin + 2, o + 3 * nf + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipStreamSynchronize(s));
+        std::memcpy(tot, pin, sizeof(tot));
         int *li = tmp.alloc_n<int>(tot[0]), *lj = tmp.alloc_n<int>(tot[0]);
         int *mi = tmp.alloc_n<int>(tot[1]), *mj = tmp.alloc_n<int>(tot[1]);
         int *ni = tmp.alloc_n<int>(tot[2]), *nj = tmp.alloc_n<int>(tot[2]);
@@ -309,7 +308,7 @@ void build_pairs(Handle &h) {
         int nb = h.level_beg[l - 1], ne = h.level_beg[l];
         int64_t *cnt = tmp.alloc_n<int64_t>(ne - nb), *off = tmp.alloc_n<int64_t>(ne - nb + 1);
         int64_t *base = tmp.alloc_n<int64_t>(1);
-        SMASH_HIP(hipMemcpyAsync(base, &used, sizeof(int64_t), hipMemcpyHostToDevice, s));
+        set_i64(base, used, s);
         k_near_count<<<ceil_div(ne - nb, 256), 256, 0, s>>>(T, nb, ne, h.Nrow, h.Ncol, h.d, h.tau,
                                                             cnt);
         SMASH_CHECK_LAUNCH();

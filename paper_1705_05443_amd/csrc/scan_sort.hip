@@ -85,6 +85,26 @@ void DeviceArena::release(bool idle) {
   bytes = 0;
 }
 
+int64_t *pinned_words() {
+  thread_local int64_t *buf = nullptr;
+  if (!buf) {
+    void *p = nullptr;
+    if (hipHostMalloc(&p, 64 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error{SMASH_E_OOM, "pinned host buffer allocation failed"};
+    }
+    buf = (int64_t *)p;
+  }
+  return buf;
+}
+
+__global__ void k_set_i64(int64_t *dev, int64_t v) { *dev = v; }
+
+void set_i64(int64_t *dev, int64_t v, hipStream_t s) {
+  k_set_i64<<<1, 1, 0, s>>>(dev, v);
+  SMASH_CHECK_LAUNCH();
+}
+
 // ------------------------------------------------------------------ scan
 constexpr int SC_NT = 256, SC_IT = 8, SC_TILE = SC_NT * SC_IT;
 

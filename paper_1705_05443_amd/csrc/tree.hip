@@ -225,10 +225,7 @@ static void grow_nodes(Handle &h, int &cap, int need) {
 
 template <class T>
 static T readback(Handle &h, const T *dev) {
-  T v;
-  SMASH_HIP(hipMemcpyAsync(&v, dev, sizeof(T), hipMemcpyDeviceToHost, h.stream));
-  SMASH_HIP(hipStreamSynchronize(h.stream));
-  return v;
+  return read_one(h.stream, dev);
 }
 
 void build_tree(Handle &h, const double *x, const double *y) {
@@ -248,27 +245,35 @@ void build_tree(Handle &h, const double *x, const double *y) {
     // validate the points (and compute the bounding cube if no root box)
     int *bad = tmp.alloc_n<int>(2);
     SMASH_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
-    k_check_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, h.nx, h.d, g, 0, bad);
+    // finite coordinates everywhere; inside the root box when one is given
+    const int use_box = h.has_root ? 1 : 0;
+    k_check_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, h.nx, h.d, g, use_box, bad);
     SMASH_CHECK_LAUNCH();
     if (!h.same_xy) {
-      k_check_points<<<ceil_div(h.ny, 256), 256, 0, s>>>(y, h.ny, h.d, g, 0, bad);
+      k_check_points<<<ceil_div(h.ny, 256), 256, 0, s>>>(y, h.ny, h.d, g, use_box, bad);
       SMASH_CHECK_LAUNCH();
     }
-    int hb[2];
-    SMASH_HIP(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
-    SMASH_HIP(hipStreamSynchronize(s));
-    if (hb[0]) throw Error{SMASH_E_NUMERIC, "non-finite point coordinate"};
-    tmp.release();
+    // one read of the flags (and of the bounding box without a root box)
+    int64_t *pin = pinned_words();
+    double *mm = nullptr;
     if (!h.has_root) {
-      // bounding cube of X and Y: lo = min, side = largest extent
-      double *mm = tmp.alloc_n<double>(12);
+      mm = tmp.alloc_n<double>(12);
       k_minmax<<<1, 256, 0, s>>>(x, h.nx, h.d, mm);
       SMASH_CHECK_LAUNCH();
       k_minmax<<<1, 256, 0, s>>>(y, h.ny, h.d, mm + 6);
       SMASH_CHECK_LAUNCH();
+      SMASH_HIP(hipMemcpyAsync(pin + 2, mm, 12 * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    SMASH_HIP(hipMemcpyAsync(pin, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
+    SMASH_HIP(hipStreamSynchronize(s));
+    int hb[2];
+    std::memcpy(hb, pin, sizeof(hb));
+    if (hb[0]) throw Error{SMASH_E_NUMERIC, "non-finite point coordinate"};
+    if (h.has_root && hb[1]) throw Error{SMASH_E_INVALID_ARG, "a point lies outside the root box"};
+    if (!h.has_root) {
+      // bounding cube of X and Y: lo = min, side = largest extent
       double hm[12];
-      SMASH_HIP(hipMemcpyAsync(hm, mm, sizeof(hm), hipMemcpyDeviceToHost, s));
-      SMASH_HIP(hipStreamSynchronize(s));
+      std::memcpy(hm, pin + 2, sizeof(hm));
       double side = 0.0;
       for (int t = 0; t < h.d; t++) {
         double mn = hm[2 * t] < hm[6 + 2 * t] ? hm[2 * t] : hm[6 + 2 * t];
@@ -281,18 +286,8 @@ void build_tree(Handle &h, const double *x, const double *y) {
         g.lo[t] = h.root_lo[t];
         g.hi[t] = h.root_hi[t];
       }
-    } else {
-      SMASH_HIP(hipMemsetAsync(bad, 0, 2 * sizeof(int), s));
-      k_check_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, h.nx, h.d, g, 1, bad);
-      SMASH_CHECK_LAUNCH();
-      if (!h.same_xy) {
-        k_check_points<<<ceil_div(h.ny, 256), 256, 0, s>>>(y, h.ny, h.d, g, 1, bad);
-        SMASH_CHECK_LAUNCH();
-      }
-      SMASH_HIP(hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
-      SMASH_HIP(hipStreamSynchronize(s));
-      if (hb[1]) throw Error{SMASH_E_INVALID_ARG, "a point lies outside the root box"};
     }
+    tmp.release();
 
     // keys and stable sort (X, then Y unless Y is X)
     int keybits = g.max_split * g.bpl;
@@ -338,8 +333,7 @@ void build_tree(Handle &h, const double *x, const double *y) {
       int64_t *cnt = tmp.alloc_n<int64_t>(cnt_n);
       int64_t *off = tmp.alloc_n<int64_t>(cnt_n + 1);
       int64_t *base = tmp.alloc_n<int64_t>(1);
-      int64_t hbase = ne;
-      SMASH_HIP(hipMemcpyAsync(base, &hbase, sizeof(int64_t), hipMemcpyHostToDevice, s));
+      set_i64(base, ne, s);
       k_tree_split<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
                                                         cnt);
       SMASH_CHECK_LAUNCH();
