@@ -30,9 +30,16 @@ FLAGS = [
 ]
 
 
+# per-file additions: compress.hip fully unrolls loops over a register-held
+# column (the back substitution over 64 columns of R11 exceeds the default
+# size limit of an unroll pragma, and a partly unrolled loop would move the
+# columns to scratch memory)
+EXTRA = {"compress.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(OBJ, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, r.stdout, r.stderr))

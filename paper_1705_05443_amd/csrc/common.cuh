@@ -44,6 +44,33 @@ __device__ inline int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t
   __syncthreads();
   return r;
 }
+// the same for a compile-time count NW of wavefronts per workgroup
+template <int NW>
+__device__ inline int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t *lds) {
+  const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < WAVE; o <<= 1) {
+    int64_t y = __shfl_up(x, o, WAVE);
+    if (lane >= o) x += y;
+  }
+  if (lane == WAVE - 1) lds[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t s = 0;
+    for (int w = 0; w < NW; w++) {
+      int64_t t = lds[w];
+      lds[w] = s;
+      s += t;
+    }
+    lds[NW] = s;
+  }
+  __syncthreads();
+  int64_t r = x - v + lds[wid];
+  *total = lds[NW];
+  __syncthreads();
+  return r;
+}
 
 // ------------------------------------------------------------------ kernels
 // kappa(x, y) in FP64.  "x = y" means every coordinate equal (eq. (2.1):

@@ -55,6 +55,49 @@ struct IdArgs {
   int gt_out;    // k_compr_w: write G^T (k x (m-k) row-major) instead of G
 };
 
+// ---- lane exchanges (DPP) ------------------------------------------------
+// update_dpp with old = the lane's own value: lanes outside row_mask keep it
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(x), __double2loint(x), CTRL, ROWM,
+                                             0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(x), __double2hiint(x), CTRL, ROWM,
+                                             0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWM = 0xF>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(x, x, CTRL, ROWM, 0xF, false);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+// sum over the LPC lanes of a group (the same value, bit for bit, in each:
+// every lane adds the same two operands)
+template <int LPC>
+__device__ __forceinline__ double group_sum(double x) {
+  if constexpr (LPC >= 2) x += dpp_f64<0xB1>(x);  // quad_perm [1,0,3,2]
+  if constexpr (LPC >= 4) x += dpp_f64<0x4E>(x);  // quad_perm [2,3,0,1]
+  return x;
+}
+template <int LPC>
+__device__ __forceinline__ int group_max(int x) {
+  if constexpr (LPC >= 2) x = max(x, dpp_i32<0xB1>(x));
+  if constexpr (LPC >= 4) x = max(x, dpp_i32<0x4E>(x));
+  return x;
+}
+// the value of group member HS in every lane of the group
+template <int LPC, int HS>
+__device__ __forceinline__ double group_bcast(double x) {
+  if constexpr (LPC == 1)
+    return x;
+  else if constexpr (LPC == 2)
+    return dpp_f64<HS | (HS << 2) | ((2 + HS) << 4) | ((2 + HS) << 6)>(x);
+  else
+    return dpp_f64<HS | (HS << 2) | (HS << 4) | (HS << 6)>(x);
+}
+
 // ---- block reductions --------------------------------------------------
 struct ArgMax {
   double v;
@@ -68,42 +111,63 @@ __device__ inline ArgMax amax_pick(ArgMax x, ArgMax y) {
   return x;
 }
 
+// arg-max over the wavefront (all 64 lanes active), returned to every lane:
+// the largest value, then the smallest index among the lanes holding it.
+// Values are norms (>= 0) or -1 with index -1 for lanes without a
+// candidate.  Butterfly steps inside quads, mirrors inside half-rows and
+// rows, then the row broadcasts leave the maximum in lane 63.
+__device__ inline ArgMax wave_argmax(ArgMax x) {
+  double v = x.v;
+  v = fmax(v, dpp_f64<0xB1>(v));        // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_f64<0x4E>(v));        // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_f64<0x141>(v));       // row_half_mirror
+  v = fmax(v, dpp_f64<0x140>(v));       // row_mirror
+  v = fmax(v, dpp_f64<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
+  v = fmax(v, dpp_f64<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
+  v = readlane_f64(v, WAVE - 1);
+  int a = (x.v == v && x.a >= 0) ? x.a : 0x7fffffff;
+  a = min(a, dpp_i32<0xB1>(a));
+  a = min(a, dpp_i32<0x4E>(a));
+  a = min(a, dpp_i32<0x141>(a));
+  a = min(a, dpp_i32<0x140>(a));
+  a = min(a, dpp_i32<0x142, 0xA>(a));
+  a = min(a, dpp_i32<0x143, 0xC>(a));
+  a = __builtin_amdgcn_readlane(a, WAVE - 1);
+  return ArgMax{v, a == 0x7fffffff ? -1 : a};
+}
+
+// (NW = wavefronts per workgroup, a compile-time constant: the workgroup
+// size read at run time is a load from the dispatch arguments)
+template <int NW>
 __device__ inline ArgMax block_argmax(ArgMax x, ArgMax *lds) {
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    ArgMax y;
-    y.v = __shfl_xor(x.v, o, WAVE);
-    y.a = __shfl_xor(x.a, o, WAVE);
-    x = amax_pick(x, y);
-  }
+  x = wave_argmax(x);
   const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
   __syncthreads();
   if (lane == 0) lds[wid] = x;
   __syncthreads();
   ArgMax r = lds[0];
-  for (int w = 1; w < (int)(blockDim.x / WAVE); w++) r = amax_pick(r, lds[w]);
+#pragma unroll
+  for (int w = 1; w < NW; w++) r = amax_pick(r, lds[w]);
   return r;
 }
 
-// The same with one barrier: lds holds two halves of blockDim/64 slots and
+// The same with one barrier: lds holds two halves of NW slots and
 // successive calls alternate (parity).  A half is rewritten two calls after
 // it was read, with the barrier of the call in between.
+template <int NW>
 __device__ inline ArgMax block_argmax_1b(ArgMax x, ArgMax *lds, int parity) {
-  for (int o = WAVE / 2; o > 0; o >>= 1) {
-    ArgMax y;
-    y.v = __shfl_xor(x.v, o, WAVE);
-    y.a = __shfl_xor(x.a, o, WAVE);
-    x = amax_pick(x, y);
-  }
-  const int nw = blockDim.x / WAVE;
+  x = wave_argmax(x);
   const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  ArgMax *h = lds + parity * nw;
+  ArgMax *h = lds + parity * NW;
   if (lane == 0) h[wid] = x;
   __syncthreads();
   ArgMax r = h[0];
-  for (int w = 1; w < nw; w++) r = amax_pick(r, h[w]);
+#pragma unroll
+  for (int w = 1; w < NW; w++) r = amax_pick(r, h[w]);
   return r;
 }
 
+template <int NW>
 __device__ inline double block_sum(double v, double *lds) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
   const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
@@ -111,7 +175,7 @@ __device__ inline double block_sum(double v, double *lds) {
   if (lane == 0) lds[wid] = v;
   __syncthreads();
   double r = 0.0;
-  for (int w = 0; w < (int)(blockDim.x / WAVE); w++) r += lds[w];
+  for (int w = 0; w < NW; w++) r += lds[w];
   return r;
 }
 
@@ -173,19 +237,19 @@ __device__ inline void householder(double *W, int ldw, int c, int m, int t, doub
   const int tid = threadIdx.x;
   double x0 = W[(int64_t)t * ldw + t];
   double rtt = x0 >= 0.0 ? -alpha : alpha;
-  for (int r = t + 1 + tid; r < c; r += blockDim.x) v[r - t] = W[(int64_t)r * ldw + t];
+  for (int r = t + 1 + tid; r < c; r += ID_NT) v[r - t] = W[(int64_t)r * ldw + t];
   double part = 0.0;
-  for (int r = t + 1 + tid; r < c; r += blockDim.x) {
+  for (int r = t + 1 + tid; r < c; r += ID_NT) {
     double y = W[(int64_t)r * ldw + t];
     part += y * y;
   }
-  double rest = block_sum(part, red);  // ends with barriers
+  double rest = block_sum<ID_NT / WAVE>(part, red);  // ends with barriers
   double v0 = x0 - rtt;
   double vn = rest + v0 * v0;
   if (tid == 0) v[0] = v0;
   __syncthreads();
   if (alpha != 0.0 && vn > 0.0) {
-    for (int a = t + 1 + tid; a < m; a += blockDim.x) {
+    for (int a = t + 1 + tid; a < m; a += ID_NT) {
       double w = 0.0;
       for (int r = t; r < c; r++) w = fma(v[r - t], W[(int64_t)r * ldw + a], w);
       double sc = 2.0 * w / vn;
@@ -198,7 +262,7 @@ __device__ inline void householder(double *W, int ldw, int c, int m, int t, doub
       if (norms) Nrm[a] = sqrt(s2);
     }
   } else if (norms) {
-    for (int a = t + 1 + tid; a < m; a += blockDim.x) {
+    for (int a = t + 1 + tid; a < m; a += ID_NT) {
       double s2 = 0.0;
       for (int r = t + 1; r < c; r++) {
         double y = W[(int64_t)r * ldw + a];
@@ -209,7 +273,7 @@ __device__ inline void householder(double *W, int ldw, int c, int m, int t, doub
   }
   __syncthreads();
   if (alpha != 0.0) {
-    for (int r = t + tid; r < c; r += blockDim.x) W[(int64_t)r * ldw + t] = r == t ? rtt : 0.0;
+    for (int r = t + tid; r < c; r += ID_NT) W[(int64_t)r * ldw + t] = r == t ? rtt : 0.0;
   }
   __syncthreads();
 }
@@ -222,7 +286,7 @@ __device__ void compr_tail(const IdArgs &A, int i, int m, int c, int ks, int k, 
                            const double *xi, const double *wk, double *v, double *rinv,
                            double *red, ArgMax *ared, int64_t *sred) {
   const int tid = threadIdx.x;
-  const int NTB = blockDim.x;
+  const int NTB = ID_NT;
   // 3. Gu-Eisenstat swaps
   const int nr = m - k;
   int nsw = 0;
@@ -275,7 +339,7 @@ __device__ void compr_tail(const IdArgs &A, int i, int m, int c, int ks, int k, 
           am = amax_pick(am, ArgMax{rho, (a - k) * k + ii});
         }
       }
-      am = block_argmax(am, ared);
+      am = block_argmax<ID_NT / WAVE>(am, ared);
       if (!(am.v > A.f)) break;
       if (++nsw > 64 * k) {
         failed = true;
@@ -298,7 +362,7 @@ __device__ void compr_tail(const IdArgs &A, int i, int m, int c, int ks, int k, 
           double y = W[(int64_t)r * ldw + t];
           part = fma(y, y, part);
         }
-        double alpha = sqrt(block_sum(part, red));
+        double alpha = sqrt(block_sum<ID_NT / WAVE>(part, red));
         householder(W, ldw, c, m, t, alpha, v, red, Nrm, false);
       }
     }
@@ -323,7 +387,7 @@ __device__ void compr_tail(const IdArgs &A, int i, int m, int c, int ks, int k, 
     for (int u = 0; u < chunk; u++)
       if (a0 + u < m) cnt += pos[a0 + u];
     int64_t tot;
-    int64_t ex = block_excl_scan_i64(cnt, &tot, sred);
+    int64_t ex = block_excl_scan_i64<ID_NT / WAVE>(cnt, &tot, sred);
     int *sel = A.sel_out + A.selo[i];
     for (int u = 0; u < chunk; u++) {
       int a = a0 + u;
@@ -402,7 +466,7 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
     for (int t = 0; t < kmax; t++) {
       ArgMax am{-1.0, -1};
       for (int a = t + tid; a < m; a += ID_NT) am = amax_pick(am, ArgMax{Nrm[a], a});
-      am = block_argmax(am, ared);
+      am = block_argmax<ID_NT / WAVE>(am, ared);
       double bn = am.v;
       if (t == 0) {
         r00 = bn;
@@ -437,141 +501,173 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
 }
 
 // ------------------------------------------------------------------------
-// Register-resident compr for nodes whose grid fits one workgroup (m <= NT)
-// and whose basis width fits CMAX (CMAX <= NT).  Lane a holds grid column a
-// of M = C^T in registers (col[r], r < CMAX, zero past c) for the whole
-// algorithm, so
-//   * a Householder step is one block arg-max, one LDS broadcast of v and a
-//     register update of every remaining column;
-//   * a column's position (the order the QR works in) is a lane label: a
-//     pivot or a Gu-Eisenstat swap relabels two lanes instead of moving
-//     data, and ties still go to the lowest current position;
-//   * the swap test solves R11 in place in every lane at once: the lane at
-//     position j < k solves R11 x = e_j (a column of R11^-1, for the row
-//     norms 1/omega_i), a lane at position >= k solves R11 n = R12 e_j (a
-//     column of N), by back substitution against R11 held in LDS, padded
-//     to [R11 0; 0 I] so that the unrolled loops need no bounds;
-//   * grid order is lane order, so the canonical output (skeleton indices
-//     ascending, then the rest) is one block scan of the skeleton flags.
+// Register-resident compr for nodes whose grid fits one workgroup and whose
+// basis width fits CMAX.  Columns of M = C^T are held in registers for the
+// whole algorithm, in groups of LPC consecutive lanes: a group owns J grid
+// columns (a = J cb + j) and lane phase h of the group keeps their rows
+// r = LPC u + h (u < CMAX / LPC).  Each value read from LDS (a reflector
+// entry, an entry of R11) then feeds J columns, and sums over a column are
+// lane exchanges (DPP) inside the group.  So
+//   * a Householder step is one block arg-max of the residual norms, one
+//     LDS copy of the pivot column (the reflector v; v^T v follows from the
+//     pivot norm as 2 beta (beta + |x_t|)), and a register update of every
+//     column (scale 0 for the pivot and finished ones) with the norms of the
+//     remaining ones recomputed;
+//   * a column's position (the order the QR works in) is a label: a pivot
+//     or a Gu-Eisenstat swap relabels two columns instead of moving data,
+//     and ties still go to the lowest current position;
+//   * the swap test solves R11 in every column at once, by column-oriented
+//     back substitution against R11 in LDS padded to [R11 0; 0 I]: a column
+//     at position j < k solves R11 x = e_j (a column of R11^-1, for the row
+//     norms 1/omega_i), a column at position >= k solves R11 n = R12 e_j (a
+//     column of N);
+//   * grid order is column order, so the canonical output (skeleton indices
+//     ascending, then the rest) is one block scan of the skeleton counts.
 // A swap relabels, rebuilds the columns from the basis and refactors the
 // first k positions without pivoting, as k_compr does.
 // ------------------------------------------------------------------------
-template <int CMAX, int NT>
-__global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
-  // dynamic LDS: the one-dimensional basis factors [d*p][NT] while the basis
-  // is built, then R11 padded [CMAX][CMAX] and R11^-1 [CMAX][CMAX]
+template <int CMAX, int NT, int LPC, int J>
+__global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
+  constexpr int RL = CMAX / LPC;  // rows per lane and column
+  constexpr int NC = NT / LPC * J;  // grid columns per workgroup
+  constexpr int VS = RL + 2;      // stride of a row phase in vb (phases on other banks)
+  constexpr int LDI = CMAX + 1;   // row stride of R11^-1
+  // dynamic LDS, one region used in turn: the one-dimensional basis factors
+  // [d*p][NC] while the basis is built; R11 by column j and row phase hh at
+  // ((j*LPC + hh) * RL), zero on and below the diagonal; R11^-1 by rows
   extern __shared__ double dyn[];
   double *const Fl = dyn;
   double *const Rs = dyn;
-  double *const Ris = dyn + CMAX * CMAX;
+  double *const Ris = dyn;
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
-  __shared__ double v[CMAX], rinv[CMAX], rdiag[CMAX];
+  __shared__ double vb[LPC * VS], rdiag[CMAX], rdg[CMAX], rinv[CMAX];
   __shared__ int srank[CMAX];
   __shared__ ArgMax ared[NT / WAVE + 1], ared2[2 * (NT / WAVE)];
   __shared__ int64_t sred[NT / WAVE + 1];
   __shared__ double vn_lds;
-  const int a = threadIdx.x;
+  const int tid = threadIdx.x;
+  const int cb = tid / LPC, h = tid % LPC;  // column group, row phase
   const int p = A.p, d = A.d;
-  if (a < p) {
-    double th = M_PI * (2.0 * a + 1.0) / (2.0 * p);
-    chc[a] = cos(th);
-    wk[a] = ((a & 1) ? -1.0 : 1.0) * sin(th);
+  if (tid < p) {
+    double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
+    chc[tid] = cos(th);
+    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
   }
   for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
     const int m = A.m[i];
     const int ks = A.S ? A.ks[i] : 0;
     const int c = A.c0 + ks;
     __syncthreads();
-    if (a < d * p) {
-      int t = a / p, q = a % p;
+    if (tid < d * p) {
+      int t = tid / p, q = tid % p;
       double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
       xi[t * ID_PMAX + q] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[q];
     }
     __syncthreads();
     if (m == 0) {
-      if (a == 0) A.k_out[i] = 0;
+      if (tid == 0) A.k_out[i] = 0;
       continue;
     }
-    const bool act = a < m;
-    int pa = a;  // current position of this lane's column
-    double col[CMAX];
-    double nrm = -1.0;
+    bool act[J];
+    int pa[J];  // current position of each column
+    double col[J][RL], nrm[J];
+#pragma unroll
+    for (int j = 0; j < J; j++) {
+      act[j] = J * cb + j < m;
+      pa[j] = J * cb + j;
+      nrm[j] = -1.0;
+    }
 
-    // column a of C^T from the basis (barycentric tensor Lagrange values,
-    // then the near-field vector entries), and its norm
+    // the columns of C^T from the basis (barycentric tensor Lagrange values,
+    // then the near-field vector entries), and their norms.  The group
+    // shares the one-dimensional factors: phase h computes nodes q = h
+    // (mod LPC).
     auto build_column = [&]() {
-      if (act) {
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        if (!act[j]) continue;
+        const int a = J * cb + j;
         const int64_t id = A.slot_id[A.gbeg[i] + a];
         for (int t = 0; t < d; t++) {
           const double x = A.P[id * d + t];
           const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
-          double *Ft = Fl + (t * p) * NT + a;
-          if (hi - lo == 0.0) {
-            for (int q = 0; q < p; q++) Ft[q * NT] = q == 0 ? 1.0 : 0.0;
-            continue;
-          }
+          double *Ft = Fl + (t * p) * NC + a;
           int hit = -1;
           double den = 0.0;
-          for (int q = 0; q < p; q++) {
-            const double xq = xi[t * ID_PMAX + q];
-            if (x == xq) {
-              hit = q;
-              break;
+          if (hi - lo == 0.0) {
+            hit = 0;
+          } else {
+            for (int q = h; q < p; q += LPC) {
+              const double xq = xi[t * ID_PMAX + q];
+              if (x == xq) {
+                hit = q;
+                break;
+              }
+              const double w = wk[q] / (x - xq);
+              Ft[q * NC] = w;
+              den += w;
             }
-            const double w = wk[q] / (x - xq);
-            Ft[q * NT] = w;
-            den += w;
           }
+          hit = group_max<LPC>(hit);
+          den = group_sum<LPC>(den);
           if (hit >= 0)
-            for (int q = 0; q < p; q++) Ft[q * NT] = q == hit ? 1.0 : 0.0;
+            for (int q = h; q < p; q += LPC) Ft[q * NC] = q == hit ? 1.0 : 0.0;
           else
-            for (int q = 0; q < p; q++) Ft[q * NT] = Ft[q * NT] / den;
+            for (int q = h; q < p; q += LPC) Ft[q * NC] = Ft[q * NC] / den;
         }
-        int k0 = 0, k1 = 0, k2 = 0;
-        const double *Sa = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
+      }
+      __syncthreads();
 #pragma unroll
-        for (int r = 0; r < CMAX; r++) {
-          double val = 0.0;
-          if (r < A.c0) {
-            if (d == 1)
-              val = Fl[k2 * NT + a];
-            else if (d == 2)
-              val = Fl[(p + k2) * NT + a] * Fl[k1 * NT + a];
-            else
-              val = Fl[(2 * p + k2) * NT + a] * Fl[(p + k1) * NT + a] * Fl[k0 * NT + a];
-            if (++k2 == p) {
-              k2 = 0;
+      for (int j = 0; j < J; j++) {
+        if (act[j]) {
+          const int a = J * cb + j;
+          // row r = (k0 p + k1) p + k2 of the basis, r = LPC u + h
+          int k2 = h % p, k1 = (h / p) % p, k0 = h / (p * p);
+          const double *Sa = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int r = LPC * u + h;
+            double val = 0.0;
+            if (r < A.c0) {
+              if (d == 1)
+                val = Fl[k2 * NC + a];
+              else if (d == 2)
+                val = Fl[(p + k2) * NC + a] * Fl[k1 * NC + a];
+              else
+                val = Fl[(2 * p + k2) * NC + a] * Fl[(p + k1) * NC + a] * Fl[k0 * NC + a];
+            } else if (r < c) {
+              val = Sa[r - A.c0];
+            }
+            col[j][u] = val;
+            k2 += LPC;
+            while (k2 >= p) {
+              k2 -= p;
               if (++k1 == p) {
                 k1 = 0;
                 ++k0;
               }
             }
-          } else if (r < c) {
-            val = Sa[r - A.c0];
           }
-          col[r] = val;
-        }
-        double s0 = 0.0, s1 = 0.0;
+          double s0 = 0.0;
 #pragma unroll
-        for (int r = 0; r < CMAX; r += 2) {
-          s0 = fma(col[r], col[r], s0);
-          s1 = fma(col[r + 1], col[r + 1], s1);
-        }
-        nrm = sqrt(s0 + s1);
-      } else {
+          for (int u = 0; u < RL; u++) s0 = fma(col[j][u], col[j][u], s0);
+          nrm[j] = sqrt(group_sum<LPC>(s0));
+        } else {
 #pragma unroll
-        for (int r = 0; r < CMAX; r++) col[r] = 0.0;
+          for (int u = 0; u < RL; u++) col[j][u] = 0.0;
+        }
       }
+      __syncthreads();  // the factors are read before LDS is reused
     };
 
     // Householder QR over positions 0..kend-1: with pivoting the pivot of
     // step t is the largest remaining norm and the loop stops at the rank
     // test (|R_tt| <= tol * |R_00|); without, the pivot is position t.
-    // Steps run in blocks of eight (tb unrolled): rows below 8 tb are final
-    // in every remaining column, so each step touches rows 8 tb.. only and
-    // masks by the runtime step just the eight rows of its own block.  The
-    // pivot lane keeps its column as it was (rows < t are R's column) and
-    // records R_tt in rdiag.
+    // Steps run in blocks of eight rows (tb unrolled): rows below 8 tb are
+    // final in every remaining column, so a step touches local rows from
+    // 8 tb / LPC on and masks by the runtime step only inside its block.
+    // The pivot column keeps its registers (rows < t are its column of R)
+    // and R_tt goes to rdiag.
     auto householder_qr = [&](bool pivoting, int kend) -> int {
       int kk = 0;
       double r00 = 0.0;
@@ -579,16 +675,21 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
 #pragma unroll
       for (int tb = 0; tb < CMAX / 8; tb++) {
         if (stop) break;
-        const int r0 = 8 * tb;
+        const int r0 = 8 * tb, u0 = r0 / LPC, u1 = u0 + 8 / LPC;
         for (int tt = 0; tt < 8; tt++) {
           const int t = r0 + tt;
           if (t >= kend) {
             stop = true;
             break;
           }
-          const bool cand = act && (pivoting ? pa >= t : pa == t);
-          ArgMax am = cand ? ArgMax{nrm, pa} : ArgMax{-1.0, -1};
-          am = block_argmax_1b(am, ared2, t & 1);
+          ArgMax am{-1.0, -1};
+          if (h == 0) {
+#pragma unroll
+            for (int j = 0; j < J; j++)
+              if (act[j] && (pivoting ? pa[j] >= t : pa[j] == t))
+                am = amax_pick(am, ArgMax{nrm[j], pa[j]});
+          }
+          am = block_argmax_1b<NT / WAVE>(am, ared2, t & 1);
           const double bn = am.v;
           if (pivoting) {
             if (t == 0) {
@@ -603,70 +704,80 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
             }
           }
           const int bp = am.a;
-          if (act) {
-            if (pa == t)
-              pa = bp;
-            else if (pa == bp)
-              pa = t;
+#pragma unroll
+          for (int j = 0; j < J; j++) {
+            if (act[j]) {
+              if (pa[j] == t)
+                pa[j] = bp;
+              else if (pa[j] == bp)
+                pa[j] = t;
+            }
           }
-          if (act && pa == t) {
-            // the pivot column: v (rows r0..), R_tt
-            double x0 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-              const double y = col[r0 + u];
-              x0 = u == tt ? y : x0;
-              const double z = u > tt ? y : 0.0;
-              q0 = fma(z, z, q0);
+          for (int j = 0; j < J; j++) {
+            if (act[j] && pa[j] == t) {
+              // v: zero above row t, x_t - R_tt at row t, the column below
+              double *vh = vb + h * VS;
+#pragma unroll
+              for (int u = u0; u < u1; u++) {
+                const int r = LPC * u + h;
+                double y = r < t ? 0.0 : col[j][u];
+                if (r == t) {
+                  const double rtt = y >= 0.0 ? -bn : bn;
+                  rdiag[t] = rtt;
+                  vn_lds = 2.0 * bn * (bn + fabs(y));
+                  y -= rtt;
+                }
+                vh[u] = y;
+              }
+#pragma unroll
+              for (int u = u1; u < RL; u++) vh[u] = col[j][u];
             }
-#pragma unroll
-            for (int r = r0 + 8; r < CMAX; r += 4) {
-              q0 = fma(col[r], col[r], q0);
-              q1 = fma(col[r + 1], col[r + 1], q1);
-              q2 = fma(col[r + 2], col[r + 2], q2);
-              q3 = fma(col[r + 3], col[r + 3], q3);
-            }
-            const double rest = (q0 + q1) + (q2 + q3);
-            const double rtt = x0 >= 0.0 ? -bn : bn;
-            const double v0 = x0 - rtt;
-#pragma unroll
-            for (int u = 0; u < 8; u++) v[r0 + u] = u == tt ? v0 : (u > tt ? col[r0 + u] : 0.0);
-#pragma unroll
-            for (int r = r0 + 8; r < CMAX; r++) v[r] = col[r];
-            rdiag[t] = rtt;
-            vn_lds = rest + v0 * v0;
           }
           __syncthreads();
           const double vn = vn_lds;
-          if (act && pa > t && vn > 0.0) {
-            double w0 = 0.0, w1 = 0.0;
+          const double *vh = vb + h * VS;
+          double w[J];
 #pragma unroll
-            for (int r = r0; r < CMAX; r += 2) {
-              w0 = fma(v[r], col[r], w0);
-              w1 = fma(v[r + 1], col[r + 1], w1);
-            }
-            const double sc = 2.0 * (w0 + w1) / vn;
-            // v is read again from LDS below rather than kept in registers
-            __asm__ volatile("" ::: "memory");
-            double s0 = 0.0, s1 = 0.0;
+          for (int j = 0; j < J; j++) w[j] = 0.0;
 #pragma unroll
-            for (int u = 0; u < 8; u++) {
-              const double y = fma(-sc, v[r0 + u], col[r0 + u]);
-              col[r0 + u] = y;
-              const double z = u > tt ? y : 0.0;
-              s0 = fma(z, z, s0);
-            }
+          for (int u = u0; u < RL; u++) {
+            const double vu = vh[u];
 #pragma unroll
-            for (int r = r0 + 8; r < CMAX; r += 2) {
-              const double y0 = fma(-sc, v[r], col[r]), y1 = fma(-sc, v[r + 1], col[r + 1]);
-              col[r] = y0;
-              col[r + 1] = y1;
-              s0 = fma(y0, y0, s0);
-              s1 = fma(y1, y1, s1);
-            }
-            nrm = sqrt(s0 + s1);
+            for (int j = 0; j < J; j++) w[j] = fma(vu, col[j][u], w[j]);
           }
-          // no barrier here: v and vn_lds are next written after the next
+          // scale 0 leaves a column as it is (the pivot, finished ones)
+          double sc[J];
+          bool up[J];
+#pragma unroll
+          for (int j = 0; j < J; j++) {
+            up[j] = act[j] && pa[j] > t && vn > 0.0;
+            const double g = group_sum<LPC>(w[j]);
+            sc[j] = up[j] ? 2.0 * g / vn : 0.0;
+          }
+          // v is read again from LDS below rather than kept in registers
+          __asm__ volatile("" ::: "memory");
+          double s[J];
+#pragma unroll
+          for (int j = 0; j < J; j++) s[j] = 0.0;
+#pragma unroll
+          for (int u = u0; u < RL; u++) {
+            const double vu = vh[u];
+            const bool below = u >= u1 || LPC * u + h > t;
+#pragma unroll
+            for (int j = 0; j < J; j++) {
+              const double y = fma(-sc[j], vu, col[j][u]);
+              col[j][u] = y;
+              const double z = below ? y : 0.0;
+              s[j] = fma(z, z, s[j]);
+            }
+          }
+#pragma unroll
+          for (int j = 0; j < J; j++) {
+            const double nn = sqrt(group_sum<LPC>(s[j]));
+            if (up[j]) nrm[j] = nn;
+          }
+          // no barrier here: vb and vn_lds are next written after the next
           // step's arg-max barrier, which every reader of them has passed
           kk = t + 1;
         }
@@ -680,102 +791,163 @@ __global__ void __launch_bounds__(NT) k_compr_w(IdArgs A) {
     const int nr = m - k;
     int nsw = 0;
     bool failed = false;
-    int64_t ex = 0;
+    int exj[J];  // skeleton columns before column j of the group
     for (;;) {
-      // skeleton ranks: grid order is lane order
-      const int fl = (act && pa < k) ? 1 : 0;
-      int64_t tot;
-      ex = block_excl_scan_i64(fl, &tot, sred);
-      if (fl) srank[pa] = (int)ex;
-      if (k == 0 || nr == 0) break;
-      // R11 padded to [R11 0; 0 I]: every position < CMAX has one lane
-      if (pa < CMAX) {
+      // skeleton ranks: grid order is column order
+      int cnt = 0;
 #pragma unroll
-        for (int r = 0; r < CMAX; r++)
-          Rs[r * CMAX + pa] =
-              pa < k ? (r < pa ? col[r] : (r == pa ? rdiag[pa] : 0.0)) : (r == pa ? 1.0 : 0.0);
+      for (int j = 0; j < J; j++) {
+        exj[j] = cnt;
+        cnt += (act[j] && pa[j] < k) ? 1 : 0;
       }
+      int64_t tot;
+      const int ex0 =
+          (int)block_excl_scan_i64<NT / WAVE>(h == 0 ? cnt : 0, &tot, sred) - (h > 0 ? cnt : 0);
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        exj[j] += ex0;
+        if (h == 0 && act[j] && pa[j] < k) srank[pa[j]] = exj[j];
+      }
+      if (k == 0 || nr == 0) break;
+      // R11 padded to [R11 0; 0 I]: strictly upper part by column and row
+      // phase, the reciprocal diagonal (1 past k) in rdg
+      if (k < CMAX) {
+        for (int e = tid; e < CMAX * CMAX; e += NT) Rs[e] = 0.0;
+        __syncthreads();
+      }
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        if (act[j] && pa[j] < k) {
+          double *Rc = Rs + (pa[j] * LPC + h) * RL;
+#pragma unroll
+          for (int u = 0; u < RL; u++) Rc[u] = LPC * u + h < pa[j] ? col[j][u] : 0.0;
+        }
+      }
+      if (tid < CMAX) rdg[tid] = tid < k ? 1.0 / rdiag[tid] : 1.0;
       __syncthreads();
       // right-hand side e_j at positions j < k; R12 columns stay in place
-      if (pa < k) {
 #pragma unroll
-        for (int r = 0; r < CMAX; r++) col[r] = r == pa ? 1.0 : 0.0;
+      for (int j = 0; j < J; j++) {
+        if (pa[j] < k) {
+#pragma unroll
+          for (int u = 0; u < RL; u++) col[j][u] = LPC * u + h == pa[j] ? 1.0 : 0.0;
+        }
       }
-      // back substitution in every lane (rows >= k: identity, no change)
+      // back substitution by columns of R11 in every lane (rows >= k see
+      // the identity and leave the solution unchanged)
 #pragma unroll
-      for (int ii = CMAX - 1; ii >= 0; ii--) {
-        double s = col[ii];
+      for (int jj = CMAX - 1; jj >= 0; jj--) {
+        const int uj = jj / LPC, hj = jj % LPC;
+        const double rj = rdg[jj];
+        double x[J];
 #pragma unroll
-        for (int q = ii + 1; q < CMAX; q++) s = fma(-Rs[ii * CMAX + q], col[q], s);
-        col[ii] = s / Rs[ii * CMAX + ii];
+        for (int j = 0; j < J; j++) {
+          double xv = col[j][uj] * rj;
+          if constexpr (LPC == 4) {
+            xv = hj == 0   ? group_bcast<4, 0>(xv)
+                 : hj == 1 ? group_bcast<4, 1>(xv)
+                 : hj == 2 ? group_bcast<4, 2>(xv)
+                           : group_bcast<4, 3>(xv);
+          } else if constexpr (LPC == 2) {
+            xv = hj == 0 ? group_bcast<2, 0>(xv) : group_bcast<2, 1>(xv);
+          }
+          x[j] = xv;
+          if (h == hj) col[j][uj] = xv;
+        }
+        const double *Rc = Rs + (jj * LPC + h) * RL;
+#pragma unroll
+        for (int u = 0; u <= uj; u++) {
+          const double r = Rc[u];
+#pragma unroll
+          for (int j = 0; j < J; j++) col[j][u] = fma(-r, x[j], col[j][u]);
+        }
       }
-      if (pa < k) {
+      __syncthreads();  // every read of R11 is done before R11^-1 overwrites it
 #pragma unroll
-        for (int r = 0; r < CMAX; r++) Ris[r * CMAX + pa] = col[r];
+      for (int j = 0; j < J; j++) {
+        if (act[j] && pa[j] < k) {
+#pragma unroll
+          for (int u = 0; u < RL; u++) Ris[(LPC * u + h) * LDI + pa[j]] = col[j][u];
+        }
       }
       __syncthreads();
       // row norms of R11^-1
-      if (a < k) {
+      if (tid < k) {
         double sq = 0.0;
-        for (int j = 0; j < k; j++) {
-          const double y = Ris[a * CMAX + j];
+        for (int jc = 0; jc < k; jc++) {
+          const double y = Ris[tid * LDI + jc];
           sq = fma(y, y, sq);
         }
-        rinv[a] = sqrt(sq);
+        rinv[tid] = sqrt(sq);
       }
       __syncthreads();
-      // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
-      // smallest j, then smallest i (pair index j*k + i).  G rows are
-      // written on every pass; the last pass leaves the final ones.
-      // With gt_out the lanes write G^T: for each skeleton index the rows
-      // of consecutive lanes are consecutive in memory.
+      // rho_ij^2 = N_ij^2 + (gamma_j / omega_i)^2; arg-max, ties: smallest
+      // j, then smallest i (pair index j*k + i).  G rows are written on
+      // every pass; the last pass leaves the final ones.  With gt_out the
+      // lanes write G^T: for each skeleton index the rows of consecutive
+      // columns are consecutive in memory.
       ArgMax am{-1.0, -1};
-      if (act && pa >= k) {
-        const int64_t row = a - ex;
-        double *Gr = A.G_out + A.go[i] + (A.gt_out ? row : row * k);
-        const int64_t cs = A.gt_out ? (int64_t)nr : 1;
-        const int base = (pa - k) * k;
 #pragma unroll
-        for (int ii = 0; ii < CMAX; ii++) {
-          if (ii < k) {
-            const double gw = nrm * rinv[ii];
-            const double rho = sqrt(col[ii] * col[ii] + gw * gw);
-            am = amax_pick(am, ArgMax{rho, base + ii});
-            Gr[srank[ii] * cs] = col[ii];
+      for (int j = 0; j < J; j++) {
+        if (act[j] && pa[j] >= k) {
+          const int64_t row = J * cb + j - exj[j];
+          double *Gr = A.G_out + A.go[i] + (A.gt_out ? row : row * k);
+          const int64_t cs = A.gt_out ? (int64_t)nr : 1;
+          const int base = (pa[j] - k) * k;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int ii = LPC * u + h;
+            if (ii < k) {
+              const double gw = nrm[j] * rinv[ii];
+              const double r2 = col[j][u] * col[j][u] + gw * gw;
+              am = amax_pick(am, ArgMax{r2, base + ii});
+              Gr[srank[ii] * cs] = col[j][u];
+            }
           }
         }
       }
-      am = block_argmax(am, ared);
-      if (!(am.v > A.f)) break;
+      am = block_argmax<NT / WAVE>(am, ared);
+      if (!(sqrt(am.v) > A.f)) break;
       if (++nsw > 64 * k) {
         failed = true;
         break;
       }
       const int bj = am.a / k, bi = am.a % k;
-      if (pa == bi)
-        pa = k + bj;
-      else if (pa == k + bj)
-        pa = bi;
-      __syncthreads();  // R11 / R11^-1 reads done before the factors reuse LDS
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        if (act[j]) {
+          if (pa[j] == bi)
+            pa[j] = k + bj;
+          else if (pa[j] == k + bj)
+            pa[j] = bi;
+        }
+      }
+      __syncthreads();  // R11^-1 reads are done before the factors reuse LDS
       build_column();
       householder_qr(false, k);
     }
-    if (a == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
-    if (failed) {
-      if (a == 0) atomicOr(A.err, 1);
-      k = 0;
-      ex = 0;
-    }
+    if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
     // canonical output: skeleton indices ascending, then the rest
-    if (act) {
+    if (h == 0) {
       int *sel = A.sel_out + A.selo[i];
-      const bool sk = !failed && pa < k;
-      if (sk)
-        sel[ex] = a;
-      else
-        sel[k + (a - ex)] = a;
+#pragma unroll
+      for (int j = 0; j < J; j++) {
+        if (act[j]) {
+          const int a = J * cb + j;
+          if (failed)
+            sel[a] = a;
+          else if (pa[j] < k)
+            sel[exj[j]] = a;
+          else
+            sel[k + (a - exj[j])] = a;
+        }
+      }
     }
-    if (a == 0) A.k_out[i] = k;
+    if (failed) {
+      if (tid == 0) atomicOr(A.err, 1);
+      k = 0;
+    }
+    if (tid == 0) A.k_out[i] = k;
   }
 }
 
@@ -1354,12 +1526,15 @@ void build_generators(Handle &h) {
         int cmax = c0 + (hss ? sc.mmax : 0);
         if (cmax > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
         int ldw = (sc.mmax + 1) | 1;  // odd stride
-        // register-resident QR when the grid fits one workgroup (a lane per
-        // grid point) and the basis width fits CMAX; otherwise the tile form
-        const int nt = sc.mmax <= 64 ? 64 : sc.mmax <= 128 ? 128 : sc.mmax <= 256 ? 256 : 0;
+        // register-resident QR when the grid fits one workgroup (two lanes
+        // per grid point) and the basis width fits CMAX; otherwise the tile
+        // form
+        constexpr int lpc = 4, cpg = 2;  // lanes per column group, columns per group
+        const int mw = sc.mmax * lpc / cpg;
+        const int nt = mw <= 64 ? 64 : mw <= 128 ? 128 : mw <= 256 ? 256 : mw <= 512 ? 512 : 0;
         const int cm = cmax <= 32 ? 32 : cmax <= 64 ? 64 : 0;
-        const size_t sh = sizeof(double) * std::max((size_t)h.d * h.p * (nt > 0 ? nt : 1),
-                                                    (size_t)2 * cm * cm);
+        const size_t sh = sizeof(double) * std::max((size_t)h.d * h.p * (nt > 0 ? nt / lpc * cpg : 1),
+                                                    (size_t)cm * (cm + 1));
         // (dynamic LDS plus at most 8 KB of static LDS within the device limit)
         const bool reg = nt > 0 && cm > 0 && cm <= nt && h.d * h.p <= nt && sh <= 64 * 1024 &&
                          sh + 8 * 1024 <= (size_t)dev_lds;
@@ -1382,13 +1557,15 @@ void build_generators(Handle &h) {
             k_compr<<<grid, ID_NT, 0, s>>>(ia);
           } else {
 #define SMASH_W_CASE(CM, NTV)                                                    \
-  if (cm == CM && nt == NTV) k_compr_w<CM, NTV><<<grid, NTV, sh, s>>>(ia);
+  if (cm == CM && nt == NTV) k_compr_w<CM, NTV, lpc, cpg><<<grid, NTV, sh, s>>>(ia);
             SMASH_W_CASE(32, 64)
             SMASH_W_CASE(32, 128)
             SMASH_W_CASE(32, 256)
+            SMASH_W_CASE(32, 512)
             SMASH_W_CASE(64, 64)
             SMASH_W_CASE(64, 128)
             SMASH_W_CASE(64, 256)
+            SMASH_W_CASE(64, 512)
 #undef SMASH_W_CASE
           }
           SMASH_CHECK_LAUNCH();
