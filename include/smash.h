@@ -55,6 +55,16 @@ extern "C" {
 #define SMASH_F32 1
 #define SMASH_BF16 2 /* apply only: BF16 matrices, FP32 vectors and accumulation */
 
+/* ---- storage of the coupling blocks B_ij (Sec. 1.1: a block is fixed by
+ *      its row and column skeleton indices, so it may be stored or
+ *      re-evaluated) ---- */
+#define SMASH_COUPLING_AUTO 0      /* stored when they take at most 3/4 of the free
+                                      device memory at build time, else evaluated */
+#define SMASH_COUPLING_STORED 1    /* evaluated once by the build and kept */
+#define SMASH_COUPLING_EVALUATED 2 /* evaluated by every product, a bounded chunk
+                                      of pairs at a time, right before its
+                                      contraction; nothing O(sum k_i k_j) is kept */
+
 typedef struct smash_handle_s *smash_handle;
 
 /* Options.  Initialise with smash_default_options(); a NULL options pointer
@@ -87,6 +97,12 @@ typedef struct smash_handle_s *smash_handle;
  *                HIP graph on the second call with the same (X, ldx, nrhs, Y,
  *                ldy) and replays it from then on (the eight most recent
  *                argument sets are kept; not with timing); 0: always eager
+ *   coupling_mode SMASH_COUPLING_* (default AUTO).  Both forms give the same
+ *                product bit for bit (the same block values enter the same
+ *                contraction); EVALUATED trades memory for product time
+ *   coupling_chunk  block entries per chunk of the evaluated form (the
+ *                workspace holds one chunk plus at most one node's blocks);
+ *                0 (default): 256 MiB worth of the apply precision
  */
 typedef struct smash_options {
   uint32_t struct_size; /* sizeof(smash_options) */
@@ -105,6 +121,8 @@ typedef struct smash_options {
   int32_t mv_split_nodes;
   int32_t graphs;
   int32_t mv_xcd_run;
+  int32_t coupling_mode;
+  int64_t coupling_chunk;
 } smash_options;
 
 int smash_default_options(smash_options *opt);
@@ -169,6 +187,9 @@ typedef struct smash_info_t {
   double phase_ms[16];
   int64_t phase_calls[16];
   int64_t graph_captures, graph_replays; /* products captured / replayed as graphs */
+  int32_t coupling_evaluated; /* 1: coupling blocks are evaluated inside each product */
+  int32_t coupling_chunks;    /* chunks of pairs per product in that case */
+  int64_t coupling_ws_entries; /* entries of the chunk workspace in that case */
 } smash_info_t;
 
 #define SMASH_PHASE_TREE 0

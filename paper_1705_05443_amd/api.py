@@ -31,6 +31,9 @@ class SmashError(RuntimeError):
         self.code = code
 
 
+COUPLING = {"auto": 0, "stored": 1, "evaluated": 2}
+
+
 class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("tau", C.c_double), ("eps_svd", C.c_double),
                 ("srrqr_f", C.c_double), ("diag_value", C.c_double), ("eval_prec", C.c_int32),
@@ -38,7 +41,8 @@ class Options(C.Structure):
                 ("root_lo", C.c_double * 3), ("root_side", C.c_double), ("max_depth", C.c_int32),
                 ("batched", C.c_int32), ("timing", C.c_int32),
                 ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32),
-                ("mv_xcd_run", C.c_int32)]
+                ("mv_xcd_run", C.c_int32), ("coupling_mode", C.c_int32),
+                ("coupling_chunk", C.c_int64)]
 
 
 class Info(C.Structure):
@@ -53,7 +57,9 @@ class Info(C.Structure):
                 ("apply_prec", C.c_int32), ("eval_prec", C.c_int32),
                 ("symmetric_reuse", C.c_int32), ("build_ms", C.c_double),
                 ("phase_ms", C.c_double * 16), ("phase_calls", C.c_int64 * 16),
-                ("graph_captures", C.c_int64), ("graph_replays", C.c_int64)]
+                ("graph_captures", C.c_int64), ("graph_replays", C.c_int64),
+                ("coupling_evaluated", C.c_int32), ("coupling_chunks", C.c_int32),
+                ("coupling_ws_entries", C.c_int64)]
 
 PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", "mv_up",
           "mv_coupling", "mv_down", "mv_near_out"]
@@ -127,12 +133,16 @@ class Smash:
     autotuner table (autotune.lookup) for this size bin, with nrhs_hint as
     the expected right-hand-side count; explicit mv_split_nodes / mv_xcd_run
     win.  graphs: replay repeated products from captured HIP graphs.
+    coupling: "auto", "stored" or "evaluated" (SMASH_COUPLING_*): keep the
+    coupling blocks, or evaluate them inside every product in chunks of
+    coupling_chunk entries (0: 256 MiB worth).
     """
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
                  root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
-                 mv_xcd_run=None, graphs=True, tuned=True, nrhs_hint=16, stream=None):
+                 mv_xcd_run=None, graphs=True, tuned=True, nrhs_hint=16, coupling="auto",
+                 coupling_chunk=0, stream=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -178,6 +188,10 @@ class Smash:
         if mv_xcd_run is not None:
             opt.mv_xcd_run = int(mv_xcd_run)
         opt.graphs = 1 if graphs else 0
+        if coupling not in COUPLING:
+            raise ValueError("coupling must be 'auto', 'stored' or 'evaluated'")
+        opt.coupling_mode = COUPLING[coupling]
+        opt.coupling_chunk = int(coupling_chunk)
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
         self.ny = x.shape[0] if y is None else y.shape[0]

@@ -159,13 +159,13 @@ __global__ void __launch_bounds__(256) k_eval_blocks_bf16(EvalArgs A, unsigned s
   }
 }
 
-static void eval_launch_bf16(Handle &h, EvalArgs &ea, unsigned short *out, bool f32math) {
+static void eval_launch_bf16(EvalArgs &ea, unsigned short *out, bool f32math, hipStream_t s) {
   int nblk = ea.npairs < (1 << 20) ? (int)ea.npairs : (1 << 20);
   if (nblk <= 0) return;
   if (f32math)
-    k_eval_blocks_bf16<true><<<nblk, 256, 0, h.stream>>>(ea, out);
+    k_eval_blocks_bf16<true><<<nblk, 256, 0, s>>>(ea, out);
   else
-    k_eval_blocks_bf16<false><<<nblk, 256, 0, h.stream>>>(ea, out);
+    k_eval_blocks_bf16<false><<<nblk, 256, 0, s>>>(ea, out);
   SMASH_CHECK_LAUNCH();
 }
 
@@ -189,14 +189,74 @@ static void eval_launch_m(int nblk, EvalArgs &ea, T *out, hipStream_t s) {
 }
 
 template <class T>
-static void eval_launch(Handle &h, EvalArgs &ea, T *out, bool f32math) {
+static void eval_launch(EvalArgs &ea, T *out, bool f32math, hipStream_t s) {
   int nblk = ea.npairs < (1 << 20) ? (int)ea.npairs : (1 << 20);
   if (nblk <= 0) return;
   if (f32math)
-    eval_launch_m<T, true>(nblk, ea, out, h.stream);
+    eval_launch_m<T, true>(nblk, ea, out, s);
   else
-    eval_launch_m<T, false>(nblk, ea, out, h.stream);
+    eval_launch_m<T, false>(nblk, ea, out, s);
   SMASH_CHECK_LAUNCH();
+}
+
+// the coupling pairs [p0, p1): rows at the row side's skeleton slots,
+// columns at the column side's
+static EvalArgs coupling_args(Handle &h, int64_t p0, int64_t p1) {
+  Side &R = h.row, &C = *h.col;
+  EvalArgs ea{};
+  ea.d = h.d;
+  ea.kid = h.kid;
+  ea.diag = h.diag;
+  ea.Xp = h.Xp;
+  ea.Yp = h.Yp;
+  ea.npairs = p1 - p0;
+  ea.pi = h.Li + p0;
+  ea.pj = h.Lj + p0;
+  ea.off = h.boff + p0;
+  ea.rbeg = R.hbeg;
+  ea.rcnt_k = R.k;
+  ea.rid = R.slot_id;
+  ea.cbeg = C.hbeg;
+  ea.ccnt_k = C.k;
+  ea.cid = C.slot_id;
+  return ea;
+}
+
+void eval_coupling_range(Handle &h, int64_t p0, int64_t p1, void *base, hipStream_t s) {
+  if (p1 <= p0) return;
+  EvalArgs ea = coupling_args(h, p0, p1);
+  const bool f32math = h.eval_prec == SMASH_F32;
+  if (h.apply_prec == SMASH_F64)
+    eval_launch(ea, (double *)base, f32math, s);
+  else if (h.apply_prec == SMASH_BF16)
+    eval_launch_bf16(ea, (unsigned short *)base, f32math, s);
+  else
+    eval_launch(ea, (float *)base, f32math, s);
+}
+
+// Chunk boundaries of the evaluated coupling form: boundary c (< nch) is
+// the first row node whose pairs start at or past entry c * cap; the last
+// one is nnodes.  Also the first pair and entry of each chunk.
+__global__ void k_chunk_bounds(int nnodes, const int *Lrow, const int64_t *boff, int64_t cap,
+                               int nch, int *node, int64_t *pair, int64_t *ent) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > nch) return;
+  int lo = 0, hi = nnodes;
+  if (c == nch) {
+    lo = nnodes;
+  } else {
+    const int64_t target = (int64_t)c * cap;
+    while (lo < hi) {
+      const int mid = lo + (hi - lo) / 2;
+      if (boff[Lrow[mid]] >= target)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+  }
+  node[c] = lo;
+  pair[c] = Lrow[lo];
+  ent[c] = boff[Lrow[lo]];
 }
 
 void build_blocks(Handle &h) {
@@ -234,32 +294,46 @@ void build_blocks(Handle &h) {
     SMASH_HIP(hipStreamSynchronize(s));
     h.b_entries = pin[0];
     h.n_entries = pin[1];
-    h.B = h.mem.alloc(es * (size_t)(h.b_entries > 0 ? h.b_entries : 1));
+    // coupling blocks stored, or evaluated by each product in chunks
+    bool evaluated = h.coupling_mode == SMASH_COUPLING_EVALUATED;
+    if (h.coupling_mode == SMASH_COUPLING_AUTO) {
+      size_t fr = 0, tot = 0;
+      if (hipMemGetInfo(&fr, &tot) == hipSuccess)
+        evaluated = (double)es * (double)h.b_entries > 0.75 * (double)fr;
+    }
+    h.coupling_eval = evaluated && h.nL > 0 && h.b_entries > 0;
+    if (h.coupling_eval) {
+      const int64_t cap = h.coupling_chunk > 0
+                              ? h.coupling_chunk
+                              : std::max<int64_t>((int64_t)(256 << 20) / (int64_t)es, 1);
+      const int nch = (int)((h.b_entries + cap - 1) / cap);
+      int *dn = tmp.alloc_n<int>(nch + 1);
+      int64_t *dp = tmp.alloc_n<int64_t>(nch + 1), *de = tmp.alloc_n<int64_t>(nch + 1);
+      k_chunk_bounds<<<ceil_div(nch + 1, 256), 256, 0, s>>>((int)h.nnodes, h.Lrow, h.boff, cap,
+                                                           nch, dn, dp, de);
+      SMASH_CHECK_LAUNCH();
+      h.cchunk_node.assign(nch + 1, 0);
+      h.cchunk_pair.assign(nch + 1, 0);
+      h.cchunk_ent.assign(nch + 1, 0);
+      SMASH_HIP(hipMemcpyAsync(h.cchunk_node.data(), dn, sizeof(int) * (nch + 1),
+                               hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipMemcpyAsync(h.cchunk_pair.data(), dp, sizeof(int64_t) * (nch + 1),
+                               hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipMemcpyAsync(h.cchunk_ent.data(), de, sizeof(int64_t) * (nch + 1),
+                               hipMemcpyDeviceToHost, s));
+      SMASH_HIP(hipStreamSynchronize(s));
+      h.bws_entries = 1;
+      for (int c = 0; c < nch; c++)
+        h.bws_entries = std::max(h.bws_entries, h.cchunk_ent[c + 1] - h.cchunk_ent[c]);
+      h.Bws = h.mem.alloc(es * (size_t)h.bws_entries);
+      h.B = nullptr;
+    } else {
+      h.B = h.mem.alloc(es * (size_t)(h.b_entries > 0 ? h.b_entries : 1));
+    }
     h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
     PhaseTimer pt(h, SMASH_PHASE_BLOCKS, s);
-    EvalArgs ea{};
-    ea.d = h.d;
-    ea.kid = h.kid;
-    ea.diag = h.diag;
-    ea.Xp = h.Xp;
-    ea.Yp = h.Yp;
     // B_ij = A(X at i-hat, Y at j-hat): skeleton slots of both sides
-    ea.npairs = h.nL;
-    ea.pi = h.Li;
-    ea.pj = h.Lj;
-    ea.off = h.boff;
-    ea.rbeg = R.hbeg;
-    ea.rcnt_k = R.k;
-    ea.rid = R.slot_id;
-    ea.cbeg = C.hbeg;
-    ea.ccnt_k = C.k;
-    ea.cid = C.slot_id;
-    if (h.apply_prec == SMASH_F64)
-      eval_launch(h, ea, (double *)h.B, f32math);
-    else if (bf)
-      eval_launch_bf16(h, ea, (unsigned short *)h.B, f32math);
-    else
-      eval_launch(h, ea, (float *)h.B, f32math);
+    if (!h.coupling_eval) eval_coupling_range(h, 0, h.nL, h.B, s);
     // near blocks: A(X at i, Y at j), point ranges
     EvalArgs en{};
     en.d = h.d;
@@ -276,11 +350,11 @@ void build_blocks(Handle &h) {
     en.cbeg32 = h.yb;
     en.cend32 = h.ye;
     if (h.apply_prec == SMASH_F64)
-      eval_launch(h, en, (double *)h.Bn, f32math);
+      eval_launch(en, (double *)h.Bn, f32math, s);
     else if (bf)
-      eval_launch_bf16(h, en, (unsigned short *)h.Bn, f32math);
+      eval_launch_bf16(en, (unsigned short *)h.Bn, f32math, s);
     else
-      eval_launch(h, en, (float *)h.Bn, f32math);
+      eval_launch(en, (float *)h.Bn, f32math, s);
     SMASH_HIP(hipStreamSynchronize(s));
     tmp.release();
   } catch (...) {

@@ -171,6 +171,16 @@ struct Handle {
   int64_t *boff = nullptr, *nboff = nullptr;
   void *B = nullptr, *Bn = nullptr;
   int64_t b_entries = 0, n_entries = 0;
+  // coupling blocks evaluated inside each product (SMASH_COUPLING_EVALUATED):
+  // chunk c covers row nodes [cchunk_node[c], cchunk_node[c+1]), pairs from
+  // cchunk_pair[c] and block entries from cchunk_ent[c]; Bws holds one chunk
+  int coupling_mode = SMASH_COUPLING_AUTO;
+  int64_t coupling_chunk = 0;
+  bool coupling_eval = false;
+  std::vector<int> cchunk_node;
+  std::vector<int64_t> cchunk_pair, cchunk_ent;
+  void *Bws = nullptr;
+  int64_t bws_entries = 0;
   int64_t total_swaps = 0;
   double build_ms = 0;
   // product workspaces
@@ -221,6 +231,9 @@ void build_tree(Handle &h, const double *x, const double *y);
 void build_pairs(Handle &h);
 void build_generators(Handle &h);
 void build_blocks(Handle &h);
+// coupling blocks of pairs [p0, p1) written at base + boff[p] (apply
+// precision, the stored layout) on stream s
+void eval_coupling_range(Handle &h, int64_t p0, int64_t p1, void *base, hipStream_t s);
 void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                 hipStream_t s);
 void drop_graphs(Handle &h);  // destroys captured products (synchronizes the device)

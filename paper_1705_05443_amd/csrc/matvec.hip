@@ -160,6 +160,28 @@ struct CouplingArgs {
   int xrun;
 };
 
+// The coupling product over row nodes [1, nnodes): run(n0, n1) contracts
+// the blocks of row nodes [n0, n1) with ca.B as the block base.  Stored
+// blocks: one call.  Evaluated blocks: per chunk of pairs, the chunk's
+// blocks are first written to the workspace (placed so that block p sits at
+// base + boff[p], as in the stored layout), then contracted.
+template <class Run>
+static void coupling_chunks(Handle &h, CouplingArgs &ca, size_t es, hipStream_t s, Run run) {
+  if (!h.coupling_eval) {
+    ca.B = h.B;
+    run(1, (int)h.nnodes);
+    return;
+  }
+  for (size_t c = 0; c + 1 < h.cchunk_node.size(); c++) {
+    const int n0 = std::max(h.cchunk_node[c], 1), n1 = h.cchunk_node[c + 1];
+    if (n1 <= n0 || h.cchunk_ent[c + 1] <= h.cchunk_ent[c]) continue;
+    void *base = (char *)h.Bws - es * (size_t)h.cchunk_ent[c];
+    eval_coupling_range(h, h.cchunk_pair[c], h.cchunk_pair[c + 1], base, s);
+    ca.B = base;
+    run(n0, n1);
+  }
+}
+
 // Workgroups are dealt to the eight XCDs round-robin.  This maps them so
 // that each XCD (and its L2) takes runs of `run` consecutive items --
 // spatial neighbours in the tree order, which read the same vector rows --
@@ -786,14 +808,17 @@ static void matvec_chunk_bf16(Handle &h, const float *X, int64_t ldx, int R, flo
                     h.mv_xcd_run};
     {
       PhaseTimer pt(h, SMASH_PHASE_MV_COUPLING, s);
-      if (h.batched) {
-        blocks(&ca, nullptr, h.nnodes - 1);
-      } else {
-        for (int i = 1; i < h.nnodes; i++) {
-          ca.i0 = i;
-          blocks(&ca, nullptr, 1);
+      coupling_chunks(h, ca, sizeof(unsigned short), s, [&](int n0, int n1) {
+        if (h.batched) {
+          ca.i0 = n0;
+          blocks(&ca, nullptr, n1 - n0);
+        } else {
+          for (int i = n0; i < n1; i++) {
+            ca.i0 = i;
+            blocks(&ca, nullptr, 1);
+          }
         }
-      }
+      });
     }
     PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
     for (int l = 2; l <= h.nlevels; l++) {
@@ -888,14 +913,17 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
           default: launch_coupling<T, 4>(ca, q, z, RP, nitems, s); break;
         }
       };
-      if (h.batched) {
-        coupling(h.nnodes - 1);
-      } else {
-        for (int i = 1; i < h.nnodes; i++) {
-          ca.i0 = i;
-          coupling(1);
+      coupling_chunks(h, ca, sizeof(T), s, [&](int n0, int n1) {
+        if (h.batched) {
+          ca.i0 = n0;
+          coupling(n1 - n0);
+        } else {
+          for (int i = n0; i < n1; i++) {
+            ca.i0 = i;
+            coupling(1);
+          }
         }
-      }
+      });
     }
     PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
     for (int l = 2; l <= h.nlevels; l++) {

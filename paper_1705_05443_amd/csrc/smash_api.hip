@@ -37,6 +37,7 @@ extern "C" int smash_default_options(smash_options *opt) {
   opt->mv_split_nodes = 1024;
   opt->graphs = 1;
   opt->mv_xcd_run = 16;
+  opt->coupling_mode = SMASH_COUPLING_AUTO;
   return SMASH_OK;
 }
 
@@ -114,6 +115,10 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
   if (opt.mv_split_nodes < 0) return fail(SMASH_E_INVALID_ARG, "mv_split_nodes must be >= 0");
   if (opt.mv_xcd_run < 1 || opt.mv_xcd_run > 4096)
     return fail(SMASH_E_INVALID_ARG, "mv_xcd_run must lie in [1, 4096]");
+  if (opt.coupling_mode != SMASH_COUPLING_AUTO && opt.coupling_mode != SMASH_COUPLING_STORED &&
+      opt.coupling_mode != SMASH_COUPLING_EVALUATED)
+    return fail(SMASH_E_INVALID_ARG, "coupling_mode must be SMASH_COUPLING_AUTO, _STORED or _EVALUATED");
+  if (opt.coupling_chunk < 0) return fail(SMASH_E_INVALID_ARG, "coupling_chunk must be >= 0");
 
   Handle *h = nullptr;
   auto t0 = std::chrono::steady_clock::now();
@@ -141,6 +146,8 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->mv_split_nodes = opt.mv_split_nodes;
     h->use_graphs = opt.graphs ? 1 : 0;
     h->mv_xcd_run = opt.mv_xcd_run;
+    h->coupling_mode = opt.coupling_mode;
+    h->coupling_chunk = opt.coupling_chunk;
     h->nx = nx;
     h->ny = ny;
     h->same_xy = same;
@@ -264,6 +271,9 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
     info->symmetric_reuse = h->reuse ? 1 : 0;
     info->build_ms = h->build_ms;
     info->total_swaps = h->total_swaps;
+    info->coupling_evaluated = h->coupling_eval ? 1 : 0;
+    info->coupling_chunks = h->coupling_eval ? (int32_t)h->cchunk_node.size() - 1 : 0;
+    info->coupling_ws_entries = h->coupling_eval ? h->bws_entries : 0;
     info->device_bytes = h->mem.bytes + h->ws_mem.bytes;
     info->graph_captures = h->graph_captures;
     info->graph_replays = h->graph_replays;
@@ -428,10 +438,30 @@ extern "C" int smash_export(smash_handle hv, int32_t what, void *buf, int64_t *c
           return fail(SMASH_E_UNSUPPORTED, "blocks of a BF16-apply handle are not exported");
         int64_t n = what == SMASH_EX_COUPLING ? h->b_entries : h->n_entries;
         const void *src = what == SMASH_EX_COUPLING ? h->B : h->Bn;
-        if (h->apply_prec == SMASH_F64)
-          dv = to_host((const double *)src, n);
-        else
-          fv = to_host((const float *)src, n);
+        void *tmpb = nullptr;
+        if (what == SMASH_EX_COUPLING && h->coupling_eval && n > 0) {
+          // evaluated blocks: evaluate all of them once, for the copy
+          const size_t es = h->apply_prec == SMASH_F64 ? sizeof(double) : sizeof(float);
+          SMASH_HIP(hipMalloc(&tmpb, es * (size_t)n));
+          try {
+            eval_coupling_range(*h, 0, h->nL, tmpb, h->stream);
+            SMASH_HIP(hipStreamSynchronize(h->stream));
+          } catch (...) {
+            (void)hipFree(tmpb);
+            throw;
+          }
+          src = tmpb;
+        }
+        try {
+          if (h->apply_prec == SMASH_F64)
+            dv = to_host((const double *)src, n);
+          else
+            fv = to_host((const float *)src, n);
+        } catch (...) {
+          if (tmpb) (void)hipFree(tmpb);
+          throw;
+        }
+        if (tmpb) SMASH_HIP(hipFree(tmpb));
         break;
       }
       default:

@@ -31,6 +31,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
     opt = api.Options()
     assert L.smash_default_options(C.byref(opt)) == 0
     assert opt.struct_size == C.sizeof(api.Options)
+    assert opt.coupling_mode == 0 and opt.coupling_chunk == 0  # auto, default chunk
     h = C.c_void_p()
     dummy = C.c_void_p(16)  # never dereferenced: validation fails first
     # dim out of range
@@ -52,7 +53,8 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(bad), None, C.byref(h)) == -1
     for field, val in (("tau", 1.5), ("srrqr_f", 1.0), ("apply_prec", 9), ("eval_prec", 9),
                        ("eval_prec", 2), ("mv_split_nodes", -1), ("mv_xcd_run", 0),
-                       ("mv_xcd_run", 5000)):
+                       ("mv_xcd_run", 5000), ("coupling_mode", 3), ("coupling_mode", -1),
+                       ("coupling_chunk", -5)):
         L.smash_default_options(C.byref(bad))
         setattr(bad, field, val)
         assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(bad), None, C.byref(h)) == -1

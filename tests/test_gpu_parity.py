@@ -314,6 +314,41 @@ def test_matvec_bf16_apply(name):
     assert max(errs) < 2e-2, errs
 
 
+@pytest.mark.parametrize("name", ["h2_2d_log", "hss1d_cfg", "hss_cauchy_xy", "h2_3d_clusters"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_evaluated_coupling_equals_stored(name, prec):
+    """Coupling blocks evaluated inside each product, a chunk of pairs at a
+    time (chunks of 3000 entries here, so every product runs many chunks and
+    chunks end inside a row node's pair range), give the product of the
+    stored blocks bit for bit: the same block values enter the same
+    contraction.  Also checks the chunk bookkeeping through smash_info and
+    that the exported (re-evaluated) blocks equal the stored ones."""
+    mk, kw = CASES[name]
+    x, y = mk()
+    ev = "f64" if prec == "f64" else "f32"
+    X, Y = dev(x), None if y is None else dev(y)
+    gs = api.Smash(X, Y, apply_prec=prec, eval_prec=ev, coupling="stored", **kw)
+    ge = api.Smash(X, Y, apply_prec=prec, eval_prec=ev, coupling="evaluated",
+                   coupling_chunk=3000, **kw)
+    ie, is_ = ge.info(), gs.info()
+    assert is_["coupling_evaluated"] == 0
+    if is_["coupling_entries"] > 0:
+        assert ie["coupling_evaluated"] == 1
+        assert ie["coupling_chunks"] >= is_["coupling_entries"] // 3000
+        assert 3000 <= ie["coupling_ws_entries"] or ie["coupling_chunks"] == 1
+        if ie["coupling_chunks"] > 2:
+            assert ie["coupling_ws_entries"] < is_["coupling_entries"]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    for nrhs in (1, 16, 40):
+        q = torch.from_numpy(W.rhs(gs.ny, nrhs, seed=6)).to(dt).cuda()
+        zs = gs.matvec(q).cpu().numpy()
+        for _ in range(3):  # eager, then captured and replayed
+            ze = ge.matvec(q).cpu().numpy()
+            assert np.array_equal(zs, ze), (name, prec, nrhs)
+    if prec != "bf16":
+        assert np.array_equal(gs.export("coupling"), ge.export("coupling"))
+
+
 def test_full_size_h2_2d_log_65536():
     """The benchmark workload at full size: bit-exact tree/lists/skeletons,
     FP64 product within 1e-10 of the oracle, and within the tolerance of
