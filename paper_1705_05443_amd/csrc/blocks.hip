@@ -291,7 +291,7 @@ void build_blocks(Handle &h) {
     }
     scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
     SMASH_HIP(hipMemcpyAsync(pin + 1, h.nboff + h.nLm, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    SMASH_HIP(hipStreamSynchronize(s));
+    stream_wait(s);
     h.b_entries = pin[0];
     h.n_entries = pin[1];
     // coupling blocks stored, or evaluated by each product in chunks
@@ -321,7 +321,7 @@ void build_blocks(Handle &h) {
                                hipMemcpyDeviceToHost, s));
       SMASH_HIP(hipMemcpyAsync(h.cchunk_ent.data(), de, sizeof(int64_t) * (nch + 1),
                                hipMemcpyDeviceToHost, s));
-      SMASH_HIP(hipStreamSynchronize(s));
+      SMASH_HIP(hipStreamSynchronize(s));  // (pageable destinations)
       h.bws_entries = 1;
       for (int c = 0; c < nch; c++)
         h.bws_entries = std::max(h.bws_entries, h.cchunk_ent[c + 1] - h.cchunk_ent[c]);

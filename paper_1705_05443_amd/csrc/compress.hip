@@ -1433,7 +1433,7 @@ void build_generators(Handle &h) {
         SMASH_HIP(hipMemcpyAsync(pin, o1 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipMemcpyAsync(pin + 1, o2 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipMemcpyAsync(pin + 2, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipStreamSynchronize(s));
+        stream_wait(s);
         std::memcpy(hv, pin, sizeof(hv));
         std::memcpy(&mx, pin + 2, sizeof(int));
         sc.mmax = mx;
@@ -1462,7 +1462,7 @@ void build_generators(Handle &h) {
           int64_t *pin = pinned_words();
           SMASH_HIP(hipMemcpyAsync(pin, soff + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
           SMASH_HIP(hipMemcpyAsync(pin + 1, dmax + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-          SMASH_HIP(hipStreamSynchronize(s));
+          stream_wait(s);
           std::memcpy(&stot, pin, sizeof(stot));
           std::memcpy(&ncmax, pin + 1, sizeof(int));
           if (sc.mmax > SV_MMAX)
@@ -1623,7 +1623,7 @@ void build_generators(Handle &h) {
     {
       int64_t *pin = pinned_words();
       SMASH_HIP(hipMemcpyAsync(pin, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
-      SMASH_HIP(hipStreamSynchronize(s));
+      stream_wait(s);
       std::memcpy(herr, pin, sizeof(herr));
     }
     if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
@@ -1665,7 +1665,7 @@ void build_generators(Handle &h) {
           int64_t *pin = pinned_words();
           SMASH_HIP(hipMemcpyAsync(pin, ou + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
           SMASH_HIP(hipMemcpyAsync(pin + 1, od + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-          SMASH_HIP(hipStreamSynchronize(s));
+          stream_wait(s);
           const int64_t tot[2] = {pin[0], pin[1]};
           L.gbu_n = tot[0];
           L.gbd_n = tot[1];

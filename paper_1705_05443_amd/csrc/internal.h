@@ -86,11 +86,15 @@ void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *
 // the thread) for the build's small device-to-host reads: the copies go
 // straight to pinned memory and one stream synchronization covers them.
 int64_t *pinned_words();
+// Waits until `s` has passed everything enqueued so far by polling an event
+// (a host readback in the build waits for a short tail of small kernels;
+// polling wakes sooner than a blocking synchronisation)
+void stream_wait(hipStream_t s);
 template <class T>
 T read_one(hipStream_t s, const T *dev) {
   int64_t *p = pinned_words();
   SMASH_HIP(hipMemcpyAsync(p, dev, sizeof(T), hipMemcpyDeviceToHost, s));
-  SMASH_HIP(hipStreamSynchronize(s));
+  stream_wait(s);
   T v;
   std::memcpy(&v, p, sizeof(T));
   return v;

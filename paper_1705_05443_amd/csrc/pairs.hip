@@ -241,7 +241,7 @@ void build_pairs(Handle &h) {
         SMASH_HIP(hipMemcpyAsync(pin, o + nf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipMemcpyAsync(pin + 1, o + 2 * nf + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
         SMASH_HIP(hipMemcpyAsync(pin + 2, o + 3 * nf + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipStreamSynchronize(s));
+        stream_wait(s);
         std::memcpy(tot, pin, sizeof(tot));
         int *li = tmp.alloc_n<int>(tot[0]), *lj = tmp.alloc_n<int>(tot[0]);
         int *mi = tmp.alloc_n<int>(tot[1]), *mj = tmp.alloc_n<int>(tot[1]);

@@ -85,6 +85,20 @@ void DeviceArena::release(bool idle) {
   bytes = 0;
 }
 
+void stream_wait(hipStream_t s) {
+  int dev = 0;
+  SMASH_HIP(hipGetDevice(&dev));
+  thread_local std::vector<hipEvent_t> evs;
+  if ((int)evs.size() <= dev) evs.resize(dev + 1, nullptr);
+  if (!evs[dev]) SMASH_HIP(hipEventCreateWithFlags(&evs[dev], hipEventDisableTiming));
+  SMASH_HIP(hipEventRecord(evs[dev], s));
+  for (;;) {
+    const hipError_t e = hipEventQuery(evs[dev]);
+    if (e == hipSuccess) return;
+    if (e != hipErrorNotReady) SMASH_HIP(e);
+  }
+}
+
 int64_t *pinned_words() {
   thread_local int64_t *buf = nullptr;
   if (!buf) {

@@ -265,7 +265,7 @@ void build_tree(Handle &h, const double *x, const double *y) {
       SMASH_HIP(hipMemcpyAsync(pin + 2, mm, 12 * sizeof(double), hipMemcpyDeviceToHost, s));
     }
     SMASH_HIP(hipMemcpyAsync(pin, bad, 2 * sizeof(int), hipMemcpyDeviceToHost, s));
-    SMASH_HIP(hipStreamSynchronize(s));
+    stream_wait(s);
     int hb[2];
     std::memcpy(hb, pin, sizeof(hb));
     if (hb[0]) throw Error{SMASH_E_NUMERIC, "non-finite point coordinate"};
