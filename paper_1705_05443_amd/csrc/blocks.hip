@@ -279,8 +279,6 @@ void build_blocks(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
-    int64_t *pin = pinned_words();
-    SMASH_HIP(hipMemcpyAsync(pin, h.boff + h.nL, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     // near field
     int64_t *ncnt = tmp.alloc_n<int64_t>(h.nLm);
     h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
@@ -290,8 +288,7 @@ void build_blocks(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
-    SMASH_HIP(hipMemcpyAsync(pin + 1, h.nboff + h.nLm, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    stream_wait(s);
+    const int64_t *pin = pick_words(s, {{h.boff + h.nL, 8}, {h.nboff + h.nLm, 8}});
     h.b_entries = pin[0];
     h.n_entries = pin[1];
     // coupling blocks stored, or evaluated by each product in chunks

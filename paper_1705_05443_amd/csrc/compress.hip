@@ -1427,15 +1427,9 @@ void build_generators(Handle &h) {
         SMASH_CHECK_LAUNCH();
         k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o2, S.go);
         SMASH_CHECK_LAUNCH();
-        int64_t hv[2];
-        int mx;
-        int64_t *pin = pinned_words();
-        SMASH_HIP(hipMemcpyAsync(pin, o1 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(pin + 1, o2 + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(pin + 2, dmax, sizeof(int), hipMemcpyDeviceToHost, s));
-        stream_wait(s);
-        std::memcpy(hv, pin, sizeof(hv));
-        std::memcpy(&mx, pin + 2, sizeof(int));
+        const int64_t *pin = pick_words(s, {{o1 + nl, 8}, {o2 + nl, 8}, {dmax, 4}});
+        const int64_t hv[2] = {pin[0], pin[1]};
+        const int mx = (int)pin[2];
         sc.mmax = mx;
         LevelSide &L = S.lv[l];
         L.sel_n = hv[0];
@@ -1457,14 +1451,9 @@ void build_generators(Handle &h) {
                                                         scap);
           SMASH_CHECK_LAUNCH();
           scan_i64(scap, soff, nl, nullptr, s, tmp);
-          int64_t stot;
-          int ncmax;
-          int64_t *pin = pinned_words();
-          SMASH_HIP(hipMemcpyAsync(pin, soff + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-          SMASH_HIP(hipMemcpyAsync(pin + 1, dmax + 1, sizeof(int), hipMemcpyDeviceToHost, s));
-          stream_wait(s);
-          std::memcpy(&stot, pin, sizeof(stot));
-          std::memcpy(&ncmax, pin + 1, sizeof(int));
+          const int64_t *pin = pick_words(s, {{soff + nl, 8}, {dmax + 1, 4}});
+          const int64_t stot = pin[0];
+          const int ncmax = (int)pin[1];
           if (sc.mmax > SV_MMAX)
             throw Error{SMASH_E_UNSUPPORTED, "HSS grid larger than " + std::to_string(SV_MMAX) +
                                                  " points (raise leaf resolution)"};
@@ -1621,10 +1610,9 @@ void build_generators(Handle &h) {
     }
     int herr[2] = {0, 0};
     {
-      int64_t *pin = pinned_words();
-      SMASH_HIP(hipMemcpyAsync(pin, dsw, sizeof(herr), hipMemcpyDeviceToHost, s));
-      stream_wait(s);
-      std::memcpy(herr, pin, sizeof(herr));
+      const int64_t *pin = pick_words(s, {{dsw, 4}, {dsw + 1, 4}});
+      herr[0] = (int)pin[0];
+      herr[1] = (int)pin[1];
     }
     if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
     h.total_swaps = herr[0];
@@ -1662,10 +1650,7 @@ void build_generators(Handle &h) {
           SMASH_CHECK_LAUNCH();
           k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, od, S.gobd);
           SMASH_CHECK_LAUNCH();
-          int64_t *pin = pinned_words();
-          SMASH_HIP(hipMemcpyAsync(pin, ou + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-          SMASH_HIP(hipMemcpyAsync(pin + 1, od + nl, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-          stream_wait(s);
+          const int64_t *pin = pick_words(s, {{ou + nl, 8}, {od + nl, 8}});
           const int64_t tot[2] = {pin[0], pin[1]};
           L.gbu_n = tot[0];
           L.gbd_n = tot[1];

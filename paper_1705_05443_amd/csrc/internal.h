@@ -24,6 +24,8 @@
 
 #include <string>
 #include <cstring>
+#include <initializer_list>
+#include <utility>
 #include <vector>
 
 #include "../../include/smash.h"
@@ -90,6 +92,10 @@ int64_t *pinned_words();
 // (a host readback in the build waits for a short tail of small kernels;
 // polling wakes sooner than a blocking synchronisation)
 void stream_wait(hipStream_t s);
+// Copies up to 16 device words (8-byte, or 4-byte int sign-extended) into
+// pinned_words()[0..n) with one tiny kernel that writes host memory
+// directly, then waits for `s`.  items: (device pointer, 4 or 8).
+int64_t *pick_words(hipStream_t s, std::initializer_list<std::pair<const void *, int>> items);
 template <class T>
 T read_one(hipStream_t s, const T *dev) {
   int64_t *p = pinned_words();

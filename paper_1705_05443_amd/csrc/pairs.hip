@@ -236,13 +236,8 @@ void build_pairs(Handle &h) {
         scan_i64(c, o, nf, nullptr, s, tmp);
         scan_i64(c + nf, o + nf + 1, nf, nullptr, s, tmp);
         scan_i64(c + 2 * nf, o + 2 * (nf + 1), nf, nullptr, s, tmp);
-        int64_t tot[3];
-        int64_t *pin = pinned_words();
-        SMASH_HIP(hipMemcpyAsync(pin, o + nf, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(pin + 1, o + 2 * nf + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        SMASH_HIP(hipMemcpyAsync(pin + 2, o + 3 * nf + 2, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        stream_wait(s);
-        std::memcpy(tot, pin, sizeof(tot));
+        const int64_t *pin = pick_words(s, {{o + nf, 8}, {o + 2 * nf + 1, 8}, {o + 3 * nf + 2, 8}});
+        const int64_t tot[3] = {pin[0], pin[1], pin[2]};
         int *li = tmp.alloc_n<int>(tot[0]), *lj = tmp.alloc_n<int>(tot[0]);
         int *mi = tmp.alloc_n<int>(tot[1]), *mj = tmp.alloc_n<int>(tot[1]);
         int *ni = tmp.alloc_n<int>(tot[2]), *nj = tmp.alloc_n<int>(tot[2]);

@@ -99,6 +99,37 @@ void stream_wait(hipStream_t s) {
   }
 }
 
+struct PickArgs {
+  const void *src[16];
+  int bytes[16];
+  int n;
+  int64_t *dst;  // pinned host memory, written from the device
+};
+
+__global__ void k_pick(PickArgs A) {
+  const int t = threadIdx.x;
+  if (t < A.n)
+    A.dst[t] = A.bytes[t] == 8 ? *(const int64_t *)A.src[t] : (int64_t)*(const int *)A.src[t];
+  __threadfence_system();
+}
+
+int64_t *pick_words(hipStream_t s, std::initializer_list<std::pair<const void *, int>> items) {
+  if (items.size() > 16) throw Error{SMASH_E_INVALID_ARG, "pick_words: at most 16 items"};
+  int64_t *pin = pinned_words();
+  PickArgs A{};
+  A.n = 0;
+  for (const auto &it : items) {
+    A.src[A.n] = it.first;
+    A.bytes[A.n] = it.second;
+    A.n++;
+  }
+  A.dst = pin;
+  k_pick<<<1, 64, 0, s>>>(A);
+  SMASH_CHECK_LAUNCH();
+  stream_wait(s);
+  return pin;
+}
+
 int64_t *pinned_words() {
   thread_local int64_t *buf = nullptr;
   if (!buf) {
