@@ -9,7 +9,8 @@
 // points keep the order of their finer bisection path (ties: input order).
 // Nodes are then discovered level by level: a node holding more than nu_0
 // points of X or of Y is split into its non-empty children, whose ranges
-// are found by binary search on the key digit of that stage.
+// are found by binary searches on the key digit of that stage (one thread
+// per child boundary, all boundaries of a level at once).
 #include "common.cuh"
 
 namespace smash {
@@ -76,17 +77,41 @@ struct NodeArrays {
   double *lo, *hi;
 };
 
-__global__ void k_tree_split(NodeArrays N, int nb, int ne, const uint64_t *kx,
-                             const uint64_t *ky, int s, int leaf, Geom g, int64_t *cnt) {
+// Child boundaries of every splitting node of a level, all searched at once:
+// thread (node, side, v) finds the first index of the node's range whose
+// stage-s digit exceeds v (v < 2^bpl - 1; the last child ends at the range
+// end).  bnd holds nsides * (2^bpl - 1) entries per node of the level.
+__global__ void k_tree_bounds(NodeArrays N, int nb, int ne, const uint64_t *kx,
+                              const uint64_t *ky, int s, int leaf, Geom g, int nsides, int *bnd) {
+  const int nv = (1 << g.bpl) - 1;
+  const int per = nsides * nv;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)(ne - nb) * per) return;
+  const int i = nb + (int)(t / per), r = (int)(t % per), side = r / nv, v = r % nv;
+  const int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
+  const bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
+  if (!split) return;
+  bnd[t] = side ? run_end(ky, yb, ye, s, v, g) : run_end(kx, xb, xe, s, v, g);
+}
+
+// end of child v's X (side 0) or Y range from the searched boundaries
+__device__ inline int child_end(const int *bn, int nsides, int nv, int side, int v, int e) {
+  return v < nv ? bn[(nsides > 1 ? side : 0) * nv + v] : e;
+}
+
+__global__ void k_tree_split(NodeArrays N, int nb, int ne, int s, int leaf, Geom g, int nsides,
+                             const int *bnd, int64_t *cnt) {
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ne) return;
   int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
   bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
   int c = 0;
   if (split) {
+    const int nv = (1 << g.bpl) - 1;
+    const int *bn = bnd + (int64_t)(i - nb) * nsides * nv;
     int ax = xb, ay = yb;
-    for (int v = 0; v < (1 << g.bpl); v++) {
-      int bx = run_end(kx, ax, xe, s, v, g), by = run_end(ky, ay, ye, s, v, g);
+    for (int v = 0; v <= nv; v++) {
+      int bx = child_end(bn, nsides, nv, 0, v, xe), by = child_end(bn, nsides, nv, 1, v, ye);
       if (bx > ax || by > ay) c++;
       ax = bx;
       ay = by;
@@ -95,8 +120,8 @@ __global__ void k_tree_split(NodeArrays N, int nb, int ne, const uint64_t *kx,
   cnt[i - nb] = c;
 }
 
-__global__ void k_tree_emit(NodeArrays N, int nb, int ne, const uint64_t *kx,
-                            const uint64_t *ky, int s, int leaf, Geom g, const int64_t *off) {
+__global__ void k_tree_emit(NodeArrays N, int nb, int ne, int s, int leaf, Geom g, int nsides,
+                            const int *bnd, const int64_t *off) {
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ne) return;
   int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
@@ -104,9 +129,11 @@ __global__ void k_tree_emit(NodeArrays N, int nb, int ne, const uint64_t *kx,
   int first = (int)off[i - nb];
   int c = 0;
   if (split) {
+    const int nv = (1 << g.bpl) - 1;
+    const int *bn = bnd + (int64_t)(i - nb) * nsides * nv;
     int ax = xb, ay = yb;
-    for (int v = 0; v < (1 << g.bpl); v++) {
-      int bx = run_end(kx, ax, xe, s, v, g), by = run_end(ky, ay, ye, s, v, g);
+    for (int v = 0; v <= nv; v++) {
+      int bx = child_end(bn, nsides, nv, 0, v, xe), by = child_end(bn, nsides, nv, 1, v, ye);
       if (bx > ax || by > ay) {
         int ch = first + c;
         N.level[ch] = N.level[i] + 1;
@@ -334,8 +361,16 @@ void build_tree(Handle &h, const double *x, const double *y) {
       int64_t *off = tmp.alloc_n<int64_t>(cnt_n + 1);
       int64_t *base = tmp.alloc_n<int64_t>(1);
       set_i64(base, ne, s);
-      k_tree_split<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
-                                                        cnt);
+      const int nsides = h.same_xy ? 1 : 2;
+      const int64_t nbnd = (int64_t)cnt_n * nsides * ((1 << g.bpl) - 1);
+      int *bnd = tmp.alloc_n<int>(nbnd > 0 ? nbnd : 1);
+      if (nbnd > 0) {
+        k_tree_bounds<<<ceil_div(nbnd, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
+                                                          nsides, bnd);
+        SMASH_CHECK_LAUNCH();
+      }
+      k_tree_split<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, lev - 1, h.leaf, g, nsides,
+                                                        bnd, cnt);
       SMASH_CHECK_LAUNCH();
       scan_i64(cnt, off, cnt_n, base, s, tmp);
       int64_t total = readback(h, off + cnt_n) - ne;
@@ -344,7 +379,7 @@ void build_tree(Handle &h, const double *x, const double *y) {
         grow_nodes(h, cap, (int)(ne + total));
         refresh();
       }
-      k_tree_emit<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
+      k_tree_emit<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, lev - 1, h.leaf, g, nsides, bnd,
                                                        off);
       SMASH_CHECK_LAUNCH();
       if (total == 0) break;
