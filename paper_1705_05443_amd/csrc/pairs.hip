@@ -42,59 +42,112 @@ __global__ void k_front_count(TreeView T, const int *fi, const int *fj, int64_t 
   cE[f] = e;
 }
 
+// o: exclusive scan of the concatenated counts (L, L^-, expansion) of the
+// nf frontier pairs; tL, tLm: the totals of the first and of the first two
+// segments.  L and L^- pairs are written at their offsets in Li/Lj and
+// Lmi/Lmj (the callers' running positions), expansions into ni/nj.
 __global__ void k_front_emit(TreeView T, const int *fi, const int *fj, int64_t nf,
-                             const int64_t *oL, const int64_t *oLm, const int64_t *oE, int *Li,
-                             int *Lj, int *Lmi, int *Lmj, int *ni_out, int *nj_out) {
+                             const int64_t *o, int64_t tL, int64_t tLm, int *Li, int *Lj,
+                             int *Lmi, int *Lmj, int *ni_out, int *nj_out) {
   int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nf) return;
   int i = fi[f], j = fj[f];
-  if (oL[f + 1] > oL[f]) {
-    Li[oL[f]] = i;
-    Lj[oL[f]] = j;
+  if (o[f + 1] > o[f]) {
+    Li[o[f]] = i;
+    Lj[o[f]] = j;
     return;
   }
-  if (oLm[f + 1] > oLm[f]) {
-    Lmi[oLm[f]] = i;
-    Lmj[oLm[f]] = j;
+  if (o[nf + f + 1] > o[nf + f]) {
+    Lmi[o[nf + f] - tL] = i;
+    Lmj[o[nf + f] - tL] = j;
     return;
   }
-  int64_t o = oE[f];
+  int64_t o_ = o[2 * nf + f] - tLm;
   int ni = T.nchild[i], nj = T.nchild[j];
   if (ni > 0 && nj > 0) {
     for (int c = 0; c < ni; c++)
       for (int e = 0; e < nj; e++) {
-        ni_out[o] = T.first_child[i] + c;
-        nj_out[o] = T.first_child[j] + e;
-        o++;
+        ni_out[o_] = T.first_child[i] + c;
+        nj_out[o_] = T.first_child[j] + e;
+        o_++;
       }
   } else if (ni == 0) {
     for (int e = 0; e < nj; e++) {
-      ni_out[o] = i;
-      nj_out[o] = T.first_child[j] + e;
-      o++;
+      ni_out[o_] = i;
+      nj_out[o_] = T.first_child[j] + e;
+      o_++;
     }
   } else {
     for (int c = 0; c < ni; c++) {
-      ni_out[o] = T.first_child[i] + c;
-      nj_out[o] = j;
-      o++;
+      ni_out[o_] = T.first_child[i] + c;
+      nj_out[o_] = j;
+      o_++;
     }
   }
 }
 
-__global__ void k_pair_keys(const int *pi, const int *pj, int64_t n, int nnodes, uint64_t *keys,
-                            int32_t *vals) {
+// Sorting a pair list by (i, j): count per row i, scan, scatter the j's
+// into their row (any order), then sort each row's j's (rows are short: the
+// pairs of one node) and write i and the CSR row pointer.
+__global__ void k_row_hist(const int *pi, int64_t n, int *rc) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
-  keys[a] = (uint64_t)pi[a] * (uint64_t)nnodes + (uint64_t)pj[a];
-  vals[a] = (int32_t)a;
+  if (a < n) atomicAdd(&rc[pi[a]], 1);
 }
 
-__global__ void k_pair_unkey(const uint64_t *keys, int64_t n, int nnodes, int *pi, int *pj) {
+__global__ void k_row_widen(const int *rc, int nnodes, int64_t *out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nnodes) out[i] = rc[i];
+}
+
+__global__ void k_row_scatter(const int *pi, const int *pj, int64_t n, const int64_t *ro,
+                              int *fill, int *sj) {
   int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
-  pi[a] = (int)(keys[a] / (uint64_t)nnodes);
-  pj[a] = (int)(keys[a] % (uint64_t)nnodes);
+  const int i = pi[a];
+  sj[ro[i] + atomicAdd(&fill[i], 1)] = pj[a];
+}
+
+// one workgroup per row: a j's position in its sorted row is the number of
+// the row's entries that precede it in (j, scatter position) order, counted
+// from a copy of the row in LDS; rows longer than RK_MAX (not produced by
+// the separation test with tau < 1 in d <= 3) are sorted by one thread
+constexpr int RK_MAX = 2048;
+__global__ void __launch_bounds__(64) k_row_sort(const int64_t *ro, int nnodes, const int *sj_in,
+                                                 int *si, int *sj, int *row) {
+  __shared__ int v[RK_MAX];
+  const int i = blockIdx.x, t = threadIdx.x;
+  if (t == 0) {
+    row[i] = (int)ro[i];
+    if (i == nnodes - 1) row[nnodes] = (int)ro[nnodes];
+  }
+  const int64_t b = ro[i], e = ro[i + 1];
+  const int r = (int)(e - b);
+  if (r <= RK_MAX) {
+    for (int a = t; a < r; a += 64) v[a] = sj_in[b + a];
+    __syncthreads();
+    for (int a = t; a < r; a += 64) {
+      const int x = v[a];
+      int cnt = 0;
+      for (int c = 0; c < r; c++) {
+        const int y = v[c];
+        cnt += (y < x || (y == x && c < a)) ? 1 : 0;
+      }
+      sj[b + cnt] = x;
+      si[b + cnt] = i;
+    }
+  } else if (t == 0) {
+    for (int64_t a = b; a < e; a++) sj[a] = sj_in[a];
+    for (int64_t a = b + 1; a < e; a++) {
+      const int x = sj[a];
+      int64_t c = a - 1;
+      while (c >= b && sj[c] > x) {
+        sj[c + 1] = sj[c];
+        c--;
+      }
+      sj[c + 1] = x;
+    }
+    for (int64_t a = b; a < e; a++) si[a] = i;
+  }
 }
 
 // CSR row pointer of a list sorted by i: row[i] = first entry with key >= i
@@ -191,27 +244,50 @@ static T readback1(hipStream_t s, const T *dev) {
   return read_one(s, dev);
 }
 
-static int bits_for(uint64_t v) {
-  int b = 0;
-  while (b < 64 && (v >> b) != 0) b++;
-  return b;
-}
-
-static void sort_pairs(Handle &h, int *&pi, int *&pj, int64_t n, DeviceArena &tmp) {
+// the n pairs (pi, pj) sorted by (i, j) into handle memory, with the CSR
+// row pointer (nnodes + 1 entries)
+static void sort_pairs_by_row(Handle &h, const int *pi, const int *pj, int64_t n, int *&oi,
+                              int *&oj, int *&row, DeviceArena &tmp) {
   hipStream_t s = h.stream;
-  int *oi = h.mem.alloc_n<int>(n), *oj = h.mem.alloc_n<int>(n);
+  const int nn = (int)h.nnodes;
+  oi = h.mem.alloc_n<int>(n);
+  oj = h.mem.alloc_n<int>(n);
+  row = h.mem.alloc_n<int>(nn + 1);
+  int *rc = tmp.alloc_n<int>(2 * (int64_t)nn);
+  int *fill = rc + nn;
+  int64_t *rc64 = tmp.alloc_n<int64_t>(nn), *ro = tmp.alloc_n<int64_t>(nn + 1);
+  SMASH_HIP(hipMemsetAsync(rc, 0, sizeof(int) * 2 * (size_t)nn, s));
   if (n > 0) {
-    uint64_t *k1 = tmp.alloc_n<uint64_t>(n), *k2 = tmp.alloc_n<uint64_t>(n);
-    int32_t *v1 = tmp.alloc_n<int32_t>(n), *v2 = tmp.alloc_n<int32_t>(n);
-    k_pair_keys<<<ceil_div(n, 256), 256, 0, s>>>(pi, pj, n, h.nnodes, k1, v1);
-    SMASH_CHECK_LAUNCH();
-    int nb = bits_for((uint64_t)h.nnodes * (uint64_t)h.nnodes);
-    radix_sort_u64(k1, v1, k2, v2, n, nb, s, tmp);
-    k_pair_unkey<<<ceil_div(n, 256), 256, 0, s>>>(k1, n, h.nnodes, oi, oj);
+    k_row_hist<<<ceil_div(n, 256), 256, 0, s>>>(pi, n, rc);
     SMASH_CHECK_LAUNCH();
   }
-  pi = oi;
-  pj = oj;
+  k_row_widen<<<ceil_div(nn, 256), 256, 0, s>>>(rc, nn, rc64);
+  SMASH_CHECK_LAUNCH();
+  scan_i64(rc64, ro, nn, nullptr, s, tmp);
+  int *sc = tmp.alloc_n<int>(n > 0 ? n : 1);
+  if (n > 0) {
+    k_row_scatter<<<ceil_div(n, 256), 256, 0, s>>>(pi, pj, n, ro, fill, sc);
+    SMASH_CHECK_LAUNCH();
+  }
+  k_row_sort<<<nn, 64, 0, s>>>(ro, nn, sc, oi, oj, row);
+  SMASH_CHECK_LAUNCH();
+}
+
+// grows a pair buffer (i and j arrays) to hold `need` entries, keeping the
+// first `used`
+static void grow_pairs(int *&bi, int *&bj, int64_t &cap, int64_t used, int64_t need,
+                       DeviceArena &tmp, hipStream_t s) {
+  if (need <= cap) return;
+  int64_t nc = cap > 0 ? cap : 1024;
+  while (nc < need) nc *= 2;
+  int *ni = tmp.alloc_n<int>(nc), *nj = tmp.alloc_n<int>(nc);
+  if (used > 0) {
+    SMASH_HIP(hipMemcpyAsync(ni, bi, sizeof(int) * used, hipMemcpyDeviceToDevice, s));
+    SMASH_HIP(hipMemcpyAsync(nj, bj, sizeof(int) * used, hipMemcpyDeviceToDevice, s));
+  }
+  bi = ni;
+  bj = nj;
+  cap = nc;
 }
 
 void build_pairs(Handle &h) {
@@ -221,64 +297,41 @@ void build_pairs(Handle &h) {
   TreeView T = view(h);
   try {
     if (h.adm == SMASH_ADM_STRONG) {
-      // frontier expansion
-      std::vector<int *> Lis, Ljs, Lmis, Lmjs;
-      std::vector<int64_t> Lns, Lmns;
+      // frontier expansion; L and L^- pairs appended to growing buffers
+      int *Lbi = nullptr, *Lbj = nullptr, *Mbi = nullptr, *Mbj = nullptr;
+      int64_t capL = 0, capM = 0, nLacc = 0, nMacc = 0;
+      grow_pairs(Lbi, Lbj, capL, 0, 32 * h.nnodes + 1024, tmp, s);
+      grow_pairs(Mbi, Mbj, capM, 0, 8 * h.nnodes + 1024, tmp, s);
       int *fi = tmp.alloc_n<int>(1), *fj = tmp.alloc_n<int>(1);
       SMASH_HIP(hipMemsetAsync(fi, 0, sizeof(int), s));
       SMASH_HIP(hipMemsetAsync(fj, 0, sizeof(int), s));
       int64_t nf = 1;
       while (nf > 0) {
-        int64_t *c = tmp.alloc_n<int64_t>(3 * nf), *o = tmp.alloc_n<int64_t>(3 * (nf + 1));
+        int64_t *c = tmp.alloc_n<int64_t>(3 * nf), *o = tmp.alloc_n<int64_t>(3 * nf + 1);
         k_front_count<<<ceil_div(nf, 256), 256, 0, s>>>(T, fi, fj, nf, h.d, h.tau, c, c + nf,
                                                         c + 2 * nf);
         SMASH_CHECK_LAUNCH();
-        scan_i64(c, o, nf, nullptr, s, tmp);
-        scan_i64(c + nf, o + nf + 1, nf, nullptr, s, tmp);
-        scan_i64(c + 2 * nf, o + 2 * (nf + 1), nf, nullptr, s, tmp);
-        const int64_t *pin = pick_words(s, {{o + nf, 8}, {o + 2 * nf + 1, 8}, {o + 3 * nf + 2, 8}});
-        const int64_t tot[3] = {pin[0], pin[1], pin[2]};
-        int *li = tmp.alloc_n<int>(tot[0]), *lj = tmp.alloc_n<int>(tot[0]);
-        int *mi = tmp.alloc_n<int>(tot[1]), *mj = tmp.alloc_n<int>(tot[1]);
-        int *ni = tmp.alloc_n<int>(tot[2]), *nj = tmp.alloc_n<int>(tot[2]);
-        k_front_emit<<<ceil_div(nf, 256), 256, 0, s>>>(T, fi, fj, nf, o, o + nf + 1,
-                                                       o + 2 * (nf + 1), li, lj, mi, mj, ni, nj);
+        scan_i64(c, o, 3 * nf, nullptr, s, tmp);
+        const int64_t *pin = pick_words(s, {{o + nf, 8}, {o + 2 * nf, 8}, {o + 3 * nf, 8}});
+        const int64_t tL = pin[0], tLm = pin[1], tE = pin[2];
+        const int64_t nLg = tL, nMg = tLm - tL, nEg = tE - tLm;
+        grow_pairs(Lbi, Lbj, capL, nLacc, nLacc + nLg, tmp, s);
+        grow_pairs(Mbi, Mbj, capM, nMacc, nMacc + nMg, tmp, s);
+        int *ni = tmp.alloc_n<int>(nEg), *nj = tmp.alloc_n<int>(nEg);
+        k_front_emit<<<ceil_div(nf, 256), 256, 0, s>>>(T, fi, fj, nf, o, tL, tLm, Lbi + nLacc,
+                                                       Lbj + nLacc, Mbi + nMacc, Mbj + nMacc,
+                                                       ni, nj);
         SMASH_CHECK_LAUNCH();
-        Lis.push_back(li);
-        Ljs.push_back(lj);
-        Lns.push_back(tot[0]);
-        Lmis.push_back(mi);
-        Lmjs.push_back(mj);
-        Lmns.push_back(tot[1]);
+        nLacc += nLg;
+        nMacc += nMg;
         fi = ni;
         fj = nj;
-        nf = tot[2];
+        nf = nEg;
       }
-      // concatenate the generations, then sort
-      auto concat = [&](std::vector<int *> &a, std::vector<int *> &b, std::vector<int64_t> &n,
-                        int *&oi, int *&oj) -> int64_t {
-        int64_t tot = 0;
-        for (auto v : n) tot += v;
-        oi = tmp.alloc_n<int>(tot);
-        oj = tmp.alloc_n<int>(tot);
-        int64_t o = 0;
-        for (size_t g = 0; g < n.size(); g++) {
-          if (n[g] == 0) continue;
-          SMASH_HIP(hipMemcpyAsync(oi + o, a[g], sizeof(int) * n[g], hipMemcpyDeviceToDevice, s));
-          SMASH_HIP(hipMemcpyAsync(oj + o, b[g], sizeof(int) * n[g], hipMemcpyDeviceToDevice, s));
-          o += n[g];
-        }
-        return tot;
-      };
-      int *ai, *aj, *bi, *bj;
-      h.nL = concat(Lis, Ljs, Lns, ai, aj);
-      h.nLm = concat(Lmis, Lmjs, Lmns, bi, bj);
-      sort_pairs(h, ai, aj, h.nL, tmp);
-      sort_pairs(h, bi, bj, h.nLm, tmp);
-      h.Li = ai;
-      h.Lj = aj;
-      h.Lmi = bi;
-      h.Lmj = bj;
+      h.nL = nLacc;
+      h.nLm = nMacc;
+      sort_pairs_by_row(h, Lbi, Lbj, h.nL, h.Li, h.Lj, h.Lrow, tmp);
+      sort_pairs_by_row(h, Mbi, Mbj, h.nLm, h.Lmi, h.Lmj, h.Lmrow, tmp);
     } else {
       int nn = h.nnodes;
       int64_t *c = tmp.alloc_n<int64_t>(2 * nn), *o = tmp.alloc_n<int64_t>(2 * (nn + 1));
@@ -324,12 +377,14 @@ void build_pairs(Handle &h) {
       }
       h.nN = used;
     }
-    h.Lrow = h.mem.alloc_n<int>(h.nnodes + 1);
-    h.Lmrow = h.mem.alloc_n<int>(h.nnodes + 1);
-    k_csr_rows<<<ceil_div(h.nnodes + 1, 256), 256, 0, s>>>(h.Li, h.nL, h.nnodes, h.Lrow);
-    SMASH_CHECK_LAUNCH();
-    k_csr_rows<<<ceil_div(h.nnodes + 1, 256), 256, 0, s>>>(h.Lmi, h.nLm, h.nnodes, h.Lmrow);
-    SMASH_CHECK_LAUNCH();
+    if (h.adm != SMASH_ADM_STRONG) {
+      h.Lrow = h.mem.alloc_n<int>(h.nnodes + 1);
+      h.Lmrow = h.mem.alloc_n<int>(h.nnodes + 1);
+      k_csr_rows<<<ceil_div(h.nnodes + 1, 256), 256, 0, s>>>(h.Li, h.nL, h.nnodes, h.Lrow);
+      SMASH_CHECK_LAUNCH();
+      k_csr_rows<<<ceil_div(h.nnodes + 1, 256), 256, 0, s>>>(h.Lmi, h.nLm, h.nnodes, h.Lmrow);
+      SMASH_CHECK_LAUNCH();
+    }
     SMASH_HIP(hipStreamSynchronize(s));
     tmp.release();
   } catch (...) {
