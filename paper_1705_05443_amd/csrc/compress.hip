@@ -1389,9 +1389,17 @@ void build_generators(Handle &h) {
     sides.push_back(SideCtx{&h.row, true, h.xb, h.xe, h.Xp, h.nx});
     if (!h.reuse) sides.push_back(SideCtx{&h.col_own, false, h.yb, h.ye, h.Yp, h.ny});
     int nn = h.nnodes;
+    // slot capacity for every level at once: a level's grids are disjoint
+    // sets of points, so it adds at most min(n, nodes * c) skeleton slots
+    // (HSS: at most n); the running slot count stays on the device
     for (auto &sc : sides) {
       Side &S = *sc.S;
-      grow_slots(h, S, sc.n + 1024);
+      int64_t bound = sc.n + 1024;
+      for (int l = 2; l <= h.nlevels; l++) {
+        const int64_t nl = h.level_beg[l] - h.level_beg[l - 1];
+        bound += hss ? sc.n : std::min<int64_t>(sc.n, nl * c0);
+      }
+      grow_slots(h, S, bound);
       k_iota<<<ceil_div(sc.n, 256), 256, 0, s>>>(S.slot_id, sc.n);
       SMASH_CHECK_LAUNCH();
       S.nslots = sc.n;
@@ -1400,6 +1408,8 @@ void build_generators(Handle &h) {
     }
     int *dmax = keep.alloc_n<int>(2);
     int *dsw = keep.alloc_n<int>(2);
+    int64_t *dslots = keep.alloc_n<int64_t>(2);  // running slot count per side
+    for (size_t q = 0; q < sides.size(); q++) set_i64(dslots + q, sides[q].S->nslots, s);
     SMASH_HIP(hipMemsetAsync(dsw, 0, 2 * sizeof(int), s));
     int dev_cus = 256, dev_lds = 64 * 1024;
     if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, h.device) !=
@@ -1580,26 +1590,23 @@ void build_generators(Handle &h) {
           k_transpose_G<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, L.Gt);
         SMASH_CHECK_LAUNCH();
       }
-      // (d) skeleton slots of this level
-      for (auto &sc : sides) {
+      // (d) skeleton slots of this level (capacity reserved up front)
+      for (size_t q = 0; q < sides.size(); q++) {
+        SideCtx &sc = sides[q];
         Side &S = *sc.S;
         int64_t *ck = tmp.alloc_n<int64_t>(nl), *ok = tmp.alloc_n<int64_t>(nl + 1);
-        int64_t *base = tmp.alloc_n<int64_t>(1);
-        set_i64(base, S.nslots, s);
         k_kcopy<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.k, ck);
         SMASH_CHECK_LAUNCH();
-        scan_i64(ck, ok, nl, base, s, tmp);
+        scan_i64(ck, ok, nl, dslots + q, s, tmp);
+        copy_i64(dslots + q, ok + nl, s);
         k_set_hbeg<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, ok, S.hbeg);
         SMASH_CHECK_LAUNCH();
-        const int64_t end = read_one(s, ok + nl);
-        grow_slots(h, S, end);
         {
           PhaseTimer pt(h, SMASH_PHASE_SLOTS, s);
           k_slot_ids<<<nl, 64, 0, s>>>(nb, ne, S.k, S.hbeg, S.gbeg, S.selo, S.lv[l].sel,
                                        S.slot_id);
           SMASH_CHECK_LAUNCH();
         }
-        S.nslots = end;
       }
       // per-level temporaries are dropped once they grow large (the swap
       // counters and the max cells live in `keep`, allocated once)
@@ -1610,9 +1617,11 @@ void build_generators(Handle &h) {
     }
     int herr[2] = {0, 0};
     {
-      const int64_t *pin = pick_words(s, {{dsw, 4}, {dsw + 1, 4}});
+      const int64_t *pin =
+          pick_words(s, {{dsw, 4}, {dsw + 1, 4}, {dslots, 8}, {dslots + 1, 8}});
       herr[0] = (int)pin[0];
       herr[1] = (int)pin[1];
+      for (size_t q = 0; q < sides.size(); q++) sides[q].S->nslots = pin[2 + q];
     }
     if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
     h.total_swaps = herr[0];

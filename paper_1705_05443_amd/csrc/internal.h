@@ -107,6 +107,8 @@ T read_one(hipStream_t s, const T *dev) {
 }
 // Sets one device int64 from a kernel argument (no host-memory copy).
 void set_i64(int64_t *dev, int64_t v, hipStream_t s);
+// *dst = *src on the stream (device to device, one value)
+void copy_i64(int64_t *dst, const int64_t *src, hipStream_t s);
 
 // ---------------------------------------------------------------- handle
 struct LevelSide {

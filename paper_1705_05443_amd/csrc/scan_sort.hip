@@ -150,6 +150,13 @@ void set_i64(int64_t *dev, int64_t v, hipStream_t s) {
   SMASH_CHECK_LAUNCH();
 }
 
+__global__ void k_copy_i64(int64_t *dst, const int64_t *src) { *dst = *src; }
+
+void copy_i64(int64_t *dst, const int64_t *src, hipStream_t s) {
+  k_copy_i64<<<1, 1, 0, s>>>(dst, src);
+  SMASH_CHECK_LAUNCH();
+}
+
 // ------------------------------------------------------------------ scan
 constexpr int SC_NT = 256, SC_IT = 8, SC_TILE = SC_NT * SC_IT;
 
