@@ -80,8 +80,9 @@ void scan_i64(const int64_t *in, int64_t *out, int64_t n, const int64_t *base_de
               hipStream_t s, DeviceArena &tmp);
 // Stable LSD radix sort of (key, value) pairs on bits [0, nbits).  Results
 // land in keys/vals (alt buffers are scratch of the same size).
+// stable LSD sort by key bits [lo_bit, nbits) (4 bits per pass)
 void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
-                    int64_t n, int nbits, hipStream_t s, DeviceArena &tmp);
+                    int64_t n, int nbits, hipStream_t s, DeviceArena &tmp, int lo_bit = 0);
 
 // ---------------------------------------------------------------- host reads
 // A per-thread pinned buffer of 64 words (hipHostMalloc, kept for the life of

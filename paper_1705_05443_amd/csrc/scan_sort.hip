@@ -348,15 +348,15 @@ __global__ void __launch_bounds__(RS_NT) k_rs_scatter(const uint64_t *kin, const
 }
 
 void radix_sort_u64(uint64_t *keys, int32_t *vals, uint64_t *keys_alt, int32_t *vals_alt,
-                    int64_t n, int nbits, hipStream_t s, DeviceArena &tmp) {
-  if (n <= 1 || nbits <= 0) return;
+                    int64_t n, int nbits, hipStream_t s, DeviceArena &tmp, int lo_bit) {
+  if (n <= 1 || nbits <= lo_bit) return;
   int ntiles = ceil_div(n, RS_TILE);
   int *hist = tmp.alloc_n<int>((size_t)RS_R * ntiles);
-  int passes = (nbits + 3) / 4;
+  int passes = (nbits - lo_bit + 3) / 4;
   uint64_t *ka = keys, *kb = keys_alt;
   int32_t *va = vals, *vb = vals_alt;
   for (int ps = 0; ps < passes; ps++) {
-    int shift = 4 * ps;
+    int shift = lo_bit + 4 * ps;
     k_rs_hist<<<ntiles, RS_NT, 0, s>>>(ka, n, shift, ntiles, hist);
     SMASH_CHECK_LAUNCH();
     k_rs_scan<<<1, 1024, 0, s>>>(hist, RS_R * ntiles);

@@ -18,6 +18,7 @@ namespace smash {
 struct Geom {
   double lo[3], hi[3];
   int d, hss, bpl, max_split;
+  int split_cap;  // bisection stages the keys are sorted by (<= max_split)
 };
 
 __global__ void k_keys(const double *__restrict__ pts, int64_t n, Geom g,
@@ -89,7 +90,7 @@ __global__ void k_tree_bounds(NodeArrays N, int nb, int ne, const uint64_t *kx,
   if (t >= (int64_t)(ne - nb) * per) return;
   const int i = nb + (int)(t / per), r = (int)(t % per), side = r / nv, v = r % nv;
   const int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
-  const bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
+  const bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.split_cap;
   if (!split) return;
   bnd[t] = side ? run_end(ky, yb, ye, s, v, g) : run_end(kx, xb, xe, s, v, g);
 }
@@ -100,11 +101,14 @@ __device__ inline int child_end(const int *bn, int nsides, int nv, int side, int
 }
 
 __global__ void k_tree_split(NodeArrays N, int nb, int ne, int s, int leaf, Geom g, int nsides,
-                             const int *bnd, int64_t *cnt) {
+                             const int *bnd, int64_t *cnt, int *deeper) {
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ne) return;
   int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
-  bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
+  bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.split_cap;
+  // a node that needs the stages the keys were not sorted by
+  if ((xe - xb > leaf || ye - yb > leaf) && s >= g.split_cap && g.split_cap < g.max_split)
+    atomicOr(deeper, 1);
   int c = 0;
   if (split) {
     const int nv = (1 << g.bpl) - 1;
@@ -125,7 +129,7 @@ __global__ void k_tree_emit(NodeArrays N, int nb, int ne, int s, int leaf, Geom 
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ne) return;
   int xb = N.xb[i], xe = N.xe[i], yb = N.yb[i], ye = N.ye[i];
-  bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.max_split;
+  bool split = (xe - xb > leaf || ye - yb > leaf) && s < g.split_cap;
   int first = (int)off[i - nb];
   int c = 0;
   if (split) {
@@ -165,6 +169,38 @@ __global__ void k_tree_emit(NodeArrays N, int nb, int ne, int s, int leaf, Geom 
   }
   N.nchild[i] = c;
   N.first_child[i] = c > 0 ? first : -1;
+}
+
+// Points of one leaf in the order of their full keys, ties by input index
+// (what one stable sort of the full keys gives), when the keys were sorted
+// only by the leading stages: one workgroup per leaf, the leaf's keys and
+// indices in LDS, each point's position = the number of points before it.
+constexpr int LS_MAX = 1024;
+__global__ void __launch_bounds__(64) k_leaf_sort(const int *nchild, const int *b32,
+                                                  const int *e32, int nnodes, uint64_t *keys,
+                                                  int *perm) {
+  __shared__ uint64_t kk[LS_MAX];
+  __shared__ int pp[LS_MAX];
+  const int i = blockIdx.x, t = threadIdx.x;
+  if (i >= nnodes || nchild[i] != 0) return;
+  const int b = b32[i], r = e32[i] - b;
+  if (r <= 1 || r > LS_MAX) return;  // (the caller guarantees r <= LS_MAX)
+  for (int a = t; a < r; a += 64) {
+    kk[a] = keys[b + a];
+    pp[a] = perm[b + a];
+  }
+  __syncthreads();
+  for (int a = t; a < r; a += 64) {
+    const uint64_t x = kk[a];
+    const int px = pp[a];
+    int cnt = 0;
+    for (int c = 0; c < r; c++) {
+      const uint64_t y = kk[c];
+      cnt += (y < x || (y == x && pp[c] < px)) ? 1 : 0;
+    }
+    keys[b + cnt] = x;
+    perm[b + cnt] = px;
+  }
 }
 
 __global__ void k_root(NodeArrays N, int nx, int ny, Geom g) {
@@ -265,6 +301,7 @@ void build_tree(Handle &h, const double *x, const double *y) {
     g.hss = h.adm == SMASH_ADM_WEAK;
     g.bpl = h.bpl;
     g.max_split = h.max_split;
+    g.split_cap = h.max_split;
     for (int t = 0; t < 3; t++) {
       g.lo[t] = h.root_lo[t];
       g.hi[t] = h.root_hi[t];
@@ -316,32 +353,26 @@ void build_tree(Handle &h, const double *x, const double *y) {
     }
     tmp.release();
 
-    // keys and stable sort (X, then Y unless Y is X)
+    // Keys and stable sort (X, then Y unless Y is X).  First by the leading
+    // stages only (at most 24 key bits); if the tree needs no deeper stage,
+    // each leaf is then put in full-key order by itself, which gives the
+    // permutation of a full sort.  Otherwise the keys are sorted in full and
+    // the tree is rebuilt.
     int keybits = g.max_split * g.bpl;
-    auto sort_side = [&](const double *pts, int64_t n, uint64_t *&keys_out, int *&perm,
-                         double *&P) {
-      uint64_t *k1 = tmp.alloc_n<uint64_t>(n), *k2 = tmp.alloc_n<uint64_t>(n);
-      int32_t *v2 = tmp.alloc_n<int32_t>(n);
-      perm = h.mem.alloc_n<int>(n);
-      k_keys<<<ceil_div(n, 256), 256, 0, s>>>(pts, n, g, k1, perm);
-      SMASH_CHECK_LAUNCH();
-      radix_sort_u64(k1, perm, k2, v2, n, keybits, s, tmp);
-      P = h.mem.alloc_n<double>((size_t)n * h.d);
-      k_gather_points<<<ceil_div(n, 256), 256, 0, s>>>(pts, perm, n, h.d, P);
-      SMASH_CHECK_LAUNCH();
-      keys_out = k1;
-    };
     uint64_t *kx = nullptr, *ky = nullptr;
-    sort_side(x, h.nx, kx, h.perm_x, h.Xp);
-    if (h.same_xy) {
-      ky = kx;
-      h.perm_y = h.perm_x;
-      h.Yp = h.Xp;
-    } else {
-      sort_side(y, h.ny, ky, h.perm_y, h.Yp);
-    }
-
-    // nodes, level by level
+    int32_t *px = nullptr, *py = nullptr;
+    auto make_keys = [&](const double *pts, int64_t n, uint64_t *&k, int32_t *&perm) {
+      k = tmp.alloc_n<uint64_t>(n);
+      perm = h.mem.alloc_n<int>(n);
+      k_keys<<<ceil_div(n, 256), 256, 0, s>>>(pts, n, g, k, perm);
+      SMASH_CHECK_LAUNCH();
+    };
+    auto sort_keys = [&](uint64_t *k, int32_t *perm, int64_t n, int lo_bit) {
+      uint64_t *k2 = tmp.alloc_n<uint64_t>(n);
+      int32_t *v2 = tmp.alloc_n<int32_t>(n);
+      radix_sort_u64(k, perm, k2, v2, n, keybits, s, tmp, lo_bit);
+    };
+    int *deeper = tmp.alloc_n<int>(1);
     int cap = 0;
     grow_nodes(h, cap, 1024);
     NodeArrays N;
@@ -349,43 +380,97 @@ void build_tree(Handle &h, const double *x, const double *y) {
       N = NodeArrays{h.level, h.parent, h.first_child, h.nchild, h.xb, h.xe, h.yb, h.ye,
                      h.lo, h.hi};
     };
-    refresh();
-    k_root<<<1, 1, 0, s>>>(N, (int)h.nx, (int)h.ny, g);
-    SMASH_CHECK_LAUNCH();
-    h.level_beg.assign(1, 0);
     int nb = 0, ne = 1, lev = 1;
-    for (;;) {
-      h.level_beg.push_back(ne);
-      int cnt_n = ne - nb;
-      int64_t *cnt = tmp.alloc_n<int64_t>(cnt_n);
-      int64_t *off = tmp.alloc_n<int64_t>(cnt_n + 1);
-      int64_t *base = tmp.alloc_n<int64_t>(1);
-      set_i64(base, ne, s);
-      const int nsides = h.same_xy ? 1 : 2;
-      const int64_t nbnd = (int64_t)cnt_n * nsides * ((1 << g.bpl) - 1);
-      int *bnd = tmp.alloc_n<int>(nbnd > 0 ? nbnd : 1);
-      if (nbnd > 0) {
-        k_tree_bounds<<<ceil_div(nbnd, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf, g,
-                                                          nsides, bnd);
+    // nodes, level by level; returns whether a node needs stages beyond split_cap
+    auto grow_tree = [&]() -> bool {
+      refresh();
+      SMASH_HIP(hipMemsetAsync(deeper, 0, sizeof(int), s));
+      k_root<<<1, 1, 0, s>>>(N, (int)h.nx, (int)h.ny, g);
+      SMASH_CHECK_LAUNCH();
+      h.level_beg.assign(1, 0);
+      nb = 0;
+      ne = 1;
+      lev = 1;
+      for (;;) {
+        h.level_beg.push_back(ne);
+        int cnt_n = ne - nb;
+        int64_t *cnt = tmp.alloc_n<int64_t>(cnt_n);
+        int64_t *off = tmp.alloc_n<int64_t>(cnt_n + 1);
+        int64_t *base = tmp.alloc_n<int64_t>(1);
+        set_i64(base, ne, s);
+        const int nsides = h.same_xy ? 1 : 2;
+        const int64_t nbnd = (int64_t)cnt_n * nsides * ((1 << g.bpl) - 1);
+        int *bnd = tmp.alloc_n<int>(nbnd > 0 ? nbnd : 1);
+        if (nbnd > 0) {
+          k_tree_bounds<<<ceil_div(nbnd, 256), 256, 0, s>>>(N, nb, ne, kx, ky, lev - 1, h.leaf,
+                                                            g, nsides, bnd);
+          SMASH_CHECK_LAUNCH();
+        }
+        k_tree_split<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, lev - 1, h.leaf, g, nsides,
+                                                          bnd, cnt, deeper);
+        SMASH_CHECK_LAUNCH();
+        scan_i64(cnt, off, cnt_n, base, s, tmp);
+        const int64_t *pin = pick_words(s, {{off + cnt_n, 8}, {deeper, 4}});
+        const int64_t total = pin[0] - ne;
+        if (pin[1]) return true;
+        if (total > 0) {
+          if (ne + total > (int64_t)INT32_MAX) throw Error{SMASH_E_UNSUPPORTED, "too many nodes"};
+          grow_nodes(h, cap, (int)(ne + total));
+          refresh();
+        }
+        k_tree_emit<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, lev - 1, h.leaf, g, nsides,
+                                                         bnd, off);
+        SMASH_CHECK_LAUNCH();
+        if (total == 0) return false;
+        nb = ne;
+        ne = (int)(ne + total);
+        lev++;
+      }
+    };
+    make_keys(x, h.nx, kx, px);
+    if (!h.same_xy) make_keys(y, h.ny, ky, py);
+    const int lead = std::min(g.max_split, std::max(1, 24 / g.bpl));
+    bool full = lead == g.max_split || h.leaf > LS_MAX;
+    g.split_cap = full ? g.max_split : lead;
+    const int lo_bit = keybits - g.split_cap * g.bpl;
+    sort_keys(kx, px, h.nx, lo_bit);
+    if (!h.same_xy) sort_keys(ky, py, h.ny, lo_bit);
+    if (h.same_xy) ky = kx;
+    const bool deep = grow_tree();
+    if (deep) {
+      // a node needs deeper stages: sort the full keys and grow the tree again
+      full = true;
+      g.split_cap = g.max_split;
+      make_keys(x, h.nx, kx, px);
+      sort_keys(kx, px, h.nx, 0);
+      if (!h.same_xy) {
+        make_keys(y, h.ny, ky, py);
+        sort_keys(ky, py, h.ny, 0);
+      } else {
+        ky = kx;
+      }
+      if (grow_tree()) throw Error{SMASH_E_DEVICE, "tree: full keys still too shallow"};
+    }
+    if (!full) {
+      k_leaf_sort<<<ne, 64, 0, s>>>(h.nchild, h.xb, h.xe, ne, kx, px);
+      SMASH_CHECK_LAUNCH();
+      if (!h.same_xy) {
+        k_leaf_sort<<<ne, 64, 0, s>>>(h.nchild, h.yb, h.ye, ne, ky, py);
         SMASH_CHECK_LAUNCH();
       }
-      k_tree_split<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, lev - 1, h.leaf, g, nsides,
-                                                        bnd, cnt);
+    }
+    h.perm_x = px;
+    h.Xp = h.mem.alloc_n<double>((size_t)h.nx * h.d);
+    k_gather_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, px, h.nx, h.d, h.Xp);
+    SMASH_CHECK_LAUNCH();
+    if (h.same_xy) {
+      h.perm_y = h.perm_x;
+      h.Yp = h.Xp;
+    } else {
+      h.perm_y = py;
+      h.Yp = h.mem.alloc_n<double>((size_t)h.ny * h.d);
+      k_gather_points<<<ceil_div(h.ny, 256), 256, 0, s>>>(y, py, h.ny, h.d, h.Yp);
       SMASH_CHECK_LAUNCH();
-      scan_i64(cnt, off, cnt_n, base, s, tmp);
-      int64_t total = readback(h, off + cnt_n) - ne;
-      if (total > 0) {
-        if (ne + total > (int64_t)INT32_MAX) throw Error{SMASH_E_UNSUPPORTED, "too many nodes"};
-        grow_nodes(h, cap, (int)(ne + total));
-        refresh();
-      }
-      k_tree_emit<<<ceil_div(cnt_n, 256), 256, 0, s>>>(N, nb, ne, lev - 1, h.leaf, g, nsides, bnd,
-                                                       off);
-      SMASH_CHECK_LAUNCH();
-      if (total == 0) break;
-      nb = ne;
-      ne = (int)(ne + total);
-      lev++;
     }
     h.nlevels = lev;
     h.nnodes = ne;
