@@ -111,6 +111,29 @@ __device__ inline ArgMax amax_pick(ArgMax x, ArgMax y) {
   return x;
 }
 
+// Index part of an arg-max over the first NL lanes once the maximum v is
+// known: the single lane holding it (the usual case, one ballot), else the
+// smallest index among the lanes that hold it (DPP minimum over NL lanes).
+template <int NL>
+__device__ __forceinline__ int argmax_index(ArgMax x, double v, bool valid) {
+  const bool on = valid && x.v == v && x.a >= 0;
+  const uint64_t hit = __ballot(on);
+  if (hit == 0) return -1;
+  if (__popcll(hit) == 1) return __builtin_amdgcn_readlane(x.a, __ffsll((unsigned long long)hit) - 1);
+  int a = on ? x.a : 0x7fffffff;
+  if constexpr (NL > 1) a = min(a, dpp_i32<0xB1>(a));
+  if constexpr (NL > 2) a = min(a, dpp_i32<0x4E>(a));
+  if constexpr (NL > 4) a = min(a, dpp_i32<0x141>(a));
+  if constexpr (NL > 8) a = min(a, dpp_i32<0x140>(a));
+  if constexpr (NL > 16) {
+    a = min(a, dpp_i32<0x142, 0xA>(a));
+    a = min(a, dpp_i32<0x143, 0xC>(a));
+    return __builtin_amdgcn_readlane(a, WAVE - 1);
+  } else {
+    return __builtin_amdgcn_readlane(a, 0);
+  }
+}
+
 // arg-max over the wavefront (all 64 lanes active), returned to every lane:
 // the largest value, then the smallest index among the lanes holding it.
 // Values are norms (>= 0) or -1 with index -1 for lanes without a
@@ -125,15 +148,20 @@ __device__ inline ArgMax wave_argmax(ArgMax x) {
   v = fmax(v, dpp_f64<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
   v = fmax(v, dpp_f64<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
   v = readlane_f64(v, WAVE - 1);
-  int a = (x.v == v && x.a >= 0) ? x.a : 0x7fffffff;
-  a = min(a, dpp_i32<0xB1>(a));
-  a = min(a, dpp_i32<0x4E>(a));
-  a = min(a, dpp_i32<0x141>(a));
-  a = min(a, dpp_i32<0x140>(a));
-  a = min(a, dpp_i32<0x142, 0xA>(a));
-  a = min(a, dpp_i32<0x143, 0xC>(a));
-  a = __builtin_amdgcn_readlane(a, WAVE - 1);
-  return ArgMax{v, a == 0x7fffffff ? -1 : a};
+  return ArgMax{v, argmax_index<WAVE>(x, v, true)};
+}
+
+// the same over the first NL (<= 16) lanes (the per-wave results of a block)
+template <int NL>
+__device__ inline ArgMax lanes_argmax(ArgMax x) {
+  const bool valid = (int)(threadIdx.x & (WAVE - 1)) < NL;
+  double v = valid ? x.v : -1.0;
+  if constexpr (NL > 1) v = fmax(v, dpp_f64<0xB1>(v));
+  if constexpr (NL > 2) v = fmax(v, dpp_f64<0x4E>(v));
+  if constexpr (NL > 4) v = fmax(v, dpp_f64<0x141>(v));
+  if constexpr (NL > 8) v = fmax(v, dpp_f64<0x140>(v));
+  v = readlane_f64(v, 0);
+  return ArgMax{v, argmax_index<NL>(x, v, valid)};
 }
 
 // (NW = wavefronts per workgroup, a compile-time constant: the workgroup
@@ -141,14 +169,12 @@ __device__ inline ArgMax wave_argmax(ArgMax x) {
 template <int NW>
 __device__ inline ArgMax block_argmax(ArgMax x, ArgMax *lds) {
   x = wave_argmax(x);
+  if constexpr (NW == 1) return x;
   const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
   __syncthreads();
   if (lane == 0) lds[wid] = x;
   __syncthreads();
-  ArgMax r = lds[0];
-#pragma unroll
-  for (int w = 1; w < NW; w++) r = amax_pick(r, lds[w]);
-  return r;
+  return lanes_argmax<NW>(lane < NW ? lds[lane] : ArgMax{-1.0, -1});
 }
 
 // The same with one barrier: lds holds two halves of NW slots and
@@ -157,14 +183,12 @@ __device__ inline ArgMax block_argmax(ArgMax x, ArgMax *lds) {
 template <int NW>
 __device__ inline ArgMax block_argmax_1b(ArgMax x, ArgMax *lds, int parity) {
   x = wave_argmax(x);
+  if constexpr (NW == 1) return x;
   const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
   ArgMax *h = lds + parity * NW;
   if (lane == 0) h[wid] = x;
   __syncthreads();
-  ArgMax r = h[0];
-#pragma unroll
-  for (int w = 1; w < NW; w++) r = amax_pick(r, h[w]);
-  return r;
+  return lanes_argmax<NW>(lane < NW ? h[lane] : ArgMax{-1.0, -1});
 }
 
 template <int NW>
