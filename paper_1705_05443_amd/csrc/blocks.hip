@@ -259,6 +259,91 @@ __global__ void k_chunk_bounds(int nnodes, const int *Lrow, const int64_t *boff,
   ent[c] = boff[Lrow[lo]];
 }
 
+// One second stream and completion event per device and host thread,
+// default priority, created on first use and kept for the process.
+static void side_stream(int dev, hipStream_t &st, hipEvent_t &ready, hipEvent_t &done) {
+  struct Side3 {
+    hipStream_t s = nullptr;
+    hipEvent_t r = nullptr, d = nullptr;
+  };
+  thread_local std::vector<Side3> v;
+  if ((int)v.size() <= dev) v.resize(dev + 1);
+  Side3 &x = v[dev];
+  if (!x.s) {
+    SMASH_HIP(hipStreamCreateWithFlags(&x.s, hipStreamNonBlocking));
+    SMASH_HIP(hipEventCreateWithFlags(&x.r, hipEventDisableTiming));
+    SMASH_HIP(hipEventCreateWithFlags(&x.d, hipEventDisableTiming));
+  }
+  st = x.s;
+  ready = x.r;
+  done = x.d;
+}
+
+// Near-field blocks (eqs. (3.15), (3.20)): they need only the tree and L^-,
+// so they are evaluated on a second stream while the generators are built
+// (whose upper levels occupy few compute units).
+void build_near_blocks(Handle &h) {
+  hipStream_t s = h.stream;
+  DeviceArena tmp;
+  tmp.stream = s;
+  try {
+    const bool bf = h.apply_prec == SMASH_BF16;
+    size_t es = h.apply_prec == SMASH_F64 ? sizeof(double)
+                : bf                      ? sizeof(unsigned short)
+                                          : sizeof(float);
+    bool f32math = h.eval_prec == SMASH_F32;
+    int64_t *ncnt = tmp.alloc_n<int64_t>(h.nLm);
+    h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
+    if (h.nLm > 0) {
+      k_near_sizes<<<ceil_div(h.nLm, 256), 256, 0, s>>>(h.nLm, h.Lmi, h.Lmj, h.xb, h.xe, h.yb,
+                                                        h.ye, bf ? 1 : 0, ncnt);
+      SMASH_CHECK_LAUNCH();
+    }
+    scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
+    h.n_entries = read_one(s, h.nboff + h.nLm);
+    h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
+    int dev = 0;
+    SMASH_HIP(hipGetDevice(&dev));
+    hipEvent_t ready;
+    side_stream(dev, h.side, ready, h.side_done);
+    // everything above (the lists, offsets and Bn) is ordered before the side work
+    SMASH_HIP(hipEventRecord(ready, s));
+    SMASH_HIP(hipStreamWaitEvent(h.side, ready, 0));
+    EvalArgs en{};
+    en.d = h.d;
+    en.kid = h.kid;
+    en.diag = h.diag;
+    en.Xp = h.Xp;
+    en.Yp = h.Yp;
+    en.npairs = h.nLm;
+    en.pi = h.Lmi;
+    en.pj = h.Lmj;
+    en.off = h.nboff;
+    en.rbeg32 = h.xb;
+    en.rend32 = h.xe;
+    en.cbeg32 = h.yb;
+    en.cend32 = h.ye;
+    {
+      PhaseTimer pt(h, SMASH_PHASE_BLOCKS, h.side);
+      if (h.apply_prec == SMASH_F64)
+        eval_launch(en, (double *)h.Bn, f32math, h.side);
+      else if (bf)
+        eval_launch_bf16(en, (unsigned short *)h.Bn, f32math, h.side);
+      else
+        eval_launch(en, (float *)h.Bn, f32math, h.side);
+    }
+    SMASH_HIP(hipEventRecord(h.side_done, h.side));
+    // the temporaries were last used on s (sizes), before the side work
+    SMASH_HIP(hipStreamSynchronize(s));
+    tmp.release();
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    if (h.side) (void)hipStreamSynchronize(h.side);
+    tmp.release();
+    throw;
+  }
+}
+
 void build_blocks(Handle &h) {
   hipStream_t s = h.stream;
   DeviceArena tmp;
@@ -279,18 +364,7 @@ void build_blocks(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
-    // near field
-    int64_t *ncnt = tmp.alloc_n<int64_t>(h.nLm);
-    h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
-    if (h.nLm > 0) {
-      k_near_sizes<<<ceil_div(h.nLm, 256), 256, 0, s>>>(h.nLm, h.Lmi, h.Lmj, h.xb, h.xe, h.yb,
-                                                        h.ye, bf ? 1 : 0, ncnt);
-      SMASH_CHECK_LAUNCH();
-    }
-    scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
-    const int64_t *pin = pick_words(s, {{h.boff + h.nL, 8}, {h.nboff + h.nLm, 8}});
-    h.b_entries = pin[0];
-    h.n_entries = pin[1];
+    h.b_entries = read_one(s, h.boff + h.nL);
     // coupling blocks stored, or evaluated by each product in chunks
     bool evaluated = h.coupling_mode == SMASH_COUPLING_EVALUATED;
     if (h.coupling_mode == SMASH_COUPLING_AUTO) {
@@ -327,35 +401,16 @@ void build_blocks(Handle &h) {
     } else {
       h.B = h.mem.alloc(es * (size_t)(h.b_entries > 0 ? h.b_entries : 1));
     }
-    h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
     PhaseTimer pt(h, SMASH_PHASE_BLOCKS, s);
     // B_ij = A(X at i-hat, Y at j-hat): skeleton slots of both sides
     if (!h.coupling_eval) eval_coupling_range(h, 0, h.nL, h.B, s);
-    // near blocks: A(X at i, Y at j), point ranges
-    EvalArgs en{};
-    en.d = h.d;
-    en.kid = h.kid;
-    en.diag = h.diag;
-    en.Xp = h.Xp;
-    en.Yp = h.Yp;
-    en.npairs = h.nLm;
-    en.pi = h.Lmi;
-    en.pj = h.Lmj;
-    en.off = h.nboff;
-    en.rbeg32 = h.xb;
-    en.rend32 = h.xe;
-    en.cbeg32 = h.yb;
-    en.cend32 = h.ye;
-    if (h.apply_prec == SMASH_F64)
-      eval_launch(en, (double *)h.Bn, f32math, s);
-    else if (bf)
-      eval_launch_bf16(en, (unsigned short *)h.Bn, f32math, s);
-    else
-      eval_launch(en, (float *)h.Bn, f32math, s);
+    // the near-field blocks of the second stream complete before the build ends
+    if (h.side) SMASH_HIP(hipStreamWaitEvent(s, h.side_done, 0));
     SMASH_HIP(hipStreamSynchronize(s));
     tmp.release();
   } catch (...) {
     (void)hipStreamSynchronize(s);
+    if (h.side) (void)hipStreamSynchronize(h.side);
     tmp.release();
     throw;
   }

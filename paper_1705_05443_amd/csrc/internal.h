@@ -184,6 +184,10 @@ struct Handle {
   int64_t *boff = nullptr, *nboff = nullptr;
   void *B = nullptr, *Bn = nullptr;
   int64_t b_entries = 0, n_entries = 0;
+  // the near-field blocks are evaluated on a second stream (same priority)
+  // while the generators are built; side_done marks their completion
+  hipStream_t side = nullptr;
+  hipEvent_t side_done = nullptr;
   // coupling blocks evaluated inside each product (SMASH_COUPLING_EVALUATED):
   // chunk c covers row nodes [cchunk_node[c], cchunk_node[c+1]), pairs from
   // cchunk_pair[c] and block entries from cchunk_ent[c]; Bws holds one chunk
@@ -243,7 +247,8 @@ void resolve_timers(Handle &h);
 void build_tree(Handle &h, const double *x, const double *y);
 void build_pairs(Handle &h);
 void build_generators(Handle &h);
-void build_blocks(Handle &h);
+void build_near_blocks(Handle &h);  // launches the near-field blocks on h.side
+void build_blocks(Handle &h);       // coupling blocks; then waits for the near ones
 // coupling blocks of pairs [p0, p1) written at base + boff[p] (apply
 // precision, the stored layout) on stream s
 void eval_coupling_range(Handle &h, int64_t p0, int64_t p1, void *base, hipStream_t s);

@@ -62,6 +62,7 @@ static void free_handle(Handle *h) {
   drop_graphs(*h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   (void)hipStreamSynchronize(h->stream);
+  if (h->side) (void)hipStreamSynchronize(h->side);  // a failed build may leave work there
   if (h->ws_mem.stream != h->stream) (void)hipStreamSynchronize(h->ws_mem.stream);
   h->ws_mem.release();
   h->mem.release();
@@ -169,6 +170,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
       PhaseTimer pt(*h, SMASH_PHASE_PAIRS, h->stream);
       build_pairs(*h);
     }
+    build_near_blocks(*h);
     build_generators(*h);
     build_blocks(*h);
     // leaf count and statistics
