@@ -76,6 +76,8 @@ def main():
                     help="target seconds of oracle work for cpu_baseline (0: skip)")
     ap.add_argument("--plain-steps", type=int, default=2,
                     help="steps of the plain per-node form timed for comparison (0: skip)")
+    ap.add_argument("--skip-evaluated", action="store_true",
+                    help="skip the product with coupling blocks evaluated inside it")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (the "
                          "calibration kernel for the HBM byte counters) and exit")
@@ -197,23 +199,25 @@ def main():
     hg.close()
     # the same product with the coupling blocks evaluated inside it (no
     # stored B; the result is the stored form's bit for bit)
-    he = api.Smash(X, Yd, timing=False, coupling="evaluated", **kw)
-    Ze = torch.empty_like(Z)
-    for _ in range(3):
-        he.matvec(Q, out=Ze)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(reps):
-        he.matvec(Q, out=Ze)
-    ev1.record()
-    torch.cuda.synchronize()
-    ie = he.info()
-    coupling_evaluated = {"matvec_ms": ev0.elapsed_time(ev1) / reps,
-                          "device_bytes": int(ie["device_bytes"]),
-                          "stored_form_device_bytes": int(stored_bytes),
-                          "chunks": int(ie["coupling_chunks"]),
-                          "same_as_stored": bool(torch.equal(Ze, Zg))}
-    he.close()
+    coupling_evaluated = None
+    he = None if args.skip_evaluated else api.Smash(X, Yd, timing=False, coupling="evaluated", **kw)
+    if he is not None:
+        Ze = torch.empty_like(Z)
+        for _ in range(3):
+            he.matvec(Q, out=Ze)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(reps):
+            he.matvec(Q, out=Ze)
+        ev1.record()
+        torch.cuda.synchronize()
+        ie = he.info()
+        coupling_evaluated = {"matvec_ms": ev0.elapsed_time(ev1) / reps,
+                              "device_bytes": int(ie["device_bytes"]),
+                              "stored_form_device_bytes": int(stored_bytes),
+                              "chunks": int(ie["coupling_chunks"]),
+                              "same_as_stored": bool(torch.equal(Ze, Zg))}
+        he.close()
     # accuracy against exact rows of A Q
     from oracle import oracle as O
     rows = np.arange(0, n, max(1, n // 512))
