@@ -333,9 +333,7 @@ void build_near_blocks(Handle &h) {
         eval_launch(en, (float *)h.Bn, f32math, h.side);
     }
     SMASH_HIP(hipEventRecord(h.side_done, h.side));
-    // the temporaries were last used on s (sizes), before the side work
-    SMASH_HIP(hipStreamSynchronize(s));
-    tmp.release();
+    defer_release(h, tmp);
   } catch (...) {
     (void)hipStreamSynchronize(s);
     if (h.side) (void)hipStreamSynchronize(h.side);

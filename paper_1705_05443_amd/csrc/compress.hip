@@ -1695,9 +1695,8 @@ void build_generators(Handle &h) {
         }
       }
     }
-    SMASH_HIP(hipStreamSynchronize(s));
-    tmp.release();
-    keep.release();
+    defer_release(h, tmp);
+    defer_release(h, keep);
   } catch (...) {
     (void)hipStreamSynchronize(s);
     tmp.release();

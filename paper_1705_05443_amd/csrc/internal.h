@@ -199,6 +199,8 @@ struct Handle {
   void *Bws = nullptr;
   int64_t bws_entries = 0;
   int64_t total_swaps = 0;
+  // stage temporaries, released once the build has synchronised its stream
+  std::vector<DeviceArena> spent;
   double build_ms = 0;
   // product workspaces
   // captured products (options.graphs): one executable graph per argument set
@@ -222,6 +224,17 @@ struct Handle {
 
 // Records a HIP event pair around the launches issued during its lifetime
 // on stream s (only when the handle's timing option is on).
+// Hands a stage's temporaries to the handle: work queued on the build
+// stream may still read them, so they are released (to the chunk cache)
+// only after the build's final stream synchronisation.
+inline void defer_release(Handle &h, DeviceArena &a) {
+  h.spent.push_back(a);
+  a.blocks.clear();
+  a.cur = nullptr;
+  a.left = 0;
+  a.bytes = 0;
+}
+
 struct PhaseTimer {
   Handle &h;
   int ph;

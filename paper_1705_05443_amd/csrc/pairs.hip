@@ -385,8 +385,7 @@ void build_pairs(Handle &h) {
       k_csr_rows<<<ceil_div(h.nnodes + 1, 256), 256, 0, s>>>(h.Lmi, h.nLm, h.nnodes, h.Lmrow);
       SMASH_CHECK_LAUNCH();
     }
-    SMASH_HIP(hipStreamSynchronize(s));
-    tmp.release();
+    defer_release(h, tmp);
   } catch (...) {
     (void)hipStreamSynchronize(s);
     tmp.release();

@@ -63,6 +63,7 @@ static void free_handle(Handle *h) {
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   (void)hipStreamSynchronize(h->stream);
   if (h->side) (void)hipStreamSynchronize(h->side);  // a failed build may leave work there
+  for (auto &a : h->spent) a.release();
   if (h->ws_mem.stream != h->stream) (void)hipStreamSynchronize(h->ws_mem.stream);
   h->ws_mem.release();
   h->mem.release();
@@ -172,7 +173,9 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     }
     build_near_blocks(*h);
     build_generators(*h);
-    build_blocks(*h);
+    build_blocks(*h);  // ends with the stream synchronised
+    for (auto &a : h->spent) a.release();
+    h->spent.clear();
     // leaf count and statistics
     std::vector<int> nch(h->nnodes);
     SMASH_HIP(hipMemcpy(nch.data(), h->nchild, sizeof(int) * h->nnodes, hipMemcpyDeviceToHost));

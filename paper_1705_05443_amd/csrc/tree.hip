@@ -474,8 +474,7 @@ void build_tree(Handle &h, const double *x, const double *y) {
     }
     h.nlevels = lev;
     h.nnodes = ne;
-    SMASH_HIP(hipStreamSynchronize(s));
-    tmp.release();
+    defer_release(h, tmp);
   } catch (...) {
     (void)hipStreamSynchronize(s);
     tmp.release();
