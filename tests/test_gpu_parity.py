@@ -86,6 +86,47 @@ def test_tree_and_lists_bit_exact(name):
         assert np.array_equal(o.export(O.EX_NEAR_IDX), g.export("near_idx"))
 
 
+def _deep_cluster(n, d, m, width, seed):
+    """n uniform points plus m points inside a box of the given width: the
+    tree descends about log2(1/width) stages around the cluster."""
+    rng = np.random.default_rng(seed)
+    x = rng.random((n + m, d))
+    x[n:] = 0.3 + width * rng.random((m, d))
+    return x
+
+
+@pytest.mark.parametrize("case", ["2d_h2", "1d_hss", "1d_h2_xy"])
+def test_tree_past_the_leading_key_bits(case):
+    """The keys are first sorted by their leading 24 bits only (12 stages in
+    2D, 24 in a binary tree); a tree that needs deeper stages is rebuilt from
+    the full sort.  These point sets need 20-30 stages around a tight
+    cluster, so they take that path: tree, permutation and lists must still
+    equal the oracle's bit for bit, and the product its result."""
+    if case == "2d_h2":
+        x, y = _deep_cluster(3000, 2, 200, 1e-7, 21), None
+        kw = dict(kernel="log_r", leaf=16, order=6, adm="strong", tol=1e-8, tau=0.7,
+                  root=((0.0, 0.0), 1.0))
+    elif case == "1d_hss":
+        x, y = _deep_cluster(600, 1, 100, 1e-9, 22), None
+        kw = dict(kernel="inv_r", leaf=8, order=8, adm="weak", tol=1e-9, eps_svd=1e-9,
+                  tau=0.6, root=((0.0,), 1.0))
+    else:
+        x = _deep_cluster(800, 1, 120, 1e-9, 23)
+        y = np.sort(_deep_cluster(700, 1, 90, 1e-9, 24), axis=0)
+        kw = dict(kernel="exp_r", leaf=10, order=8, adm="strong", tol=1e-10, tau=0.6)
+    o = O.Oracle(x, y, **_oracle_kwargs(kw))
+    g = api.Smash(dev(x), None if y is None else dev(y), **kw)
+    assert int(o.sizes()["nlevels"]) > (13 if x.shape[1] == 2 else 25)
+    assert np.array_equal(o.export(O.EX_LEVELS), g.export("levels"))
+    assert np.array_equal(o.export(O.EX_PERM_X), g.export("perm_x"))
+    assert np.array_equal(o.export(O.EX_PERM_Y), g.export("perm_y"))
+    assert np.array_equal(o.nodes(), g.export("nodes").reshape(-1, 8))
+    assert np.array_equal(o.L(), g.export("L").reshape(-1, 2))
+    assert np.array_equal(o.Lm(), g.export("Lm").reshape(-1, 2))
+    q = W.rhs(g.ny, 3, seed=9)
+    assert relerr(g.matvec(dev(q)).cpu().numpy(), o.matvec(q)) < 1e-10
+
+
 def _split(arr, sizes):
     out, o = [], 0
     for s in sizes:
