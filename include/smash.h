@@ -245,6 +245,17 @@ int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kernel_id, int32_t 
                              int32_t interp_order, int32_t admissibility, double tol,
                              int32_t apply_prec, int64_t *bytes);
 
+/* The same for a coupling storage form (SMASH_COUPLING_*; AUTO is estimated
+ * as STORED, the larger): with SMASH_COUPLING_EVALUATED the coupling blocks
+ * are replaced by the product's chunk workspace (at most 256 MiB plus one
+ * node's blocks).  For a serving loop that falls back to the evaluated form
+ * when the stored one does not fit.
+ * Errors: as smash_estimate_footprint, and SMASH_E_INVALID_ARG for an
+ * unknown coupling_mode. */
+int smash_estimate_footprint_mode(int64_t n, int32_t dim, int32_t kernel_id, int32_t leaf_size,
+                                  int32_t interp_order, int32_t admissibility, double tol,
+                                  int32_t apply_prec, int32_t coupling_mode, int64_t *bytes);
+
 /* the same for the near blocks over L^-                */
 int smash_export(smash_handle h, int32_t what, void *host_buf, int64_t *count);
 

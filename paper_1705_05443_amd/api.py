@@ -68,7 +68,7 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
             "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
-            "smash_estimate_footprint", "smash_last_error"]
+            "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_last_error"]
 
 
 def lib():
@@ -91,13 +91,16 @@ def lib():
         L.smash_estimate_footprint.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                                C.c_int32, C.c_int32, C.c_double, C.c_int32,
                                                C.POINTER(C.c_int64)]
+        L.smash_estimate_footprint_mode.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                                    C.c_int32, C.c_int32, C.c_double, C.c_int32,
+                                                    C.c_int32, C.POINTER(C.c_int64)]
         L.smash_info.argtypes = [vp, C.POINTER(Info)]
         L.smash_export.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int64)]
         L.smash_destroy.argtypes = [vp]
         L.smash_last_error.restype = C.c_char_p
         for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
                   "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
-                  "smash_estimate_footprint"):
+                  "smash_estimate_footprint", "smash_estimate_footprint_mode"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -115,12 +118,14 @@ def _stream_ptr(stream):
 
 
 def estimate_footprint(n, dim, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
-                       apply_prec="f64"):
-    """Upper estimate of a handle's device bytes (smash_estimate_footprint)."""
+                       apply_prec="f64", coupling="stored"):
+    """Upper estimate of a handle's device bytes (smash_estimate_footprint_mode)
+    for the stored or the evaluated coupling form."""
     b = C.c_int64(0)
-    _check(lib().smash_estimate_footprint(int(n), int(dim), KERNELS[kernel], int(leaf),
-                                          int(order), ADM[adm], float(tol), PREC[apply_prec],
-                                          C.byref(b)))
+    _check(lib().smash_estimate_footprint_mode(int(n), int(dim), KERNELS[kernel], int(leaf),
+                                               int(order), ADM[adm], float(tol),
+                                               PREC[apply_prec], COUPLING[coupling],
+                                               C.byref(b)))
     return b.value
 
 

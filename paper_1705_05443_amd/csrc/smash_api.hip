@@ -506,7 +506,18 @@ extern "C" int smash_export(smash_handle hv, int32_t what, void *buf, int64_t *c
 extern "C" int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kid, int32_t leaf,
                                         int32_t p, int32_t adm, double tol, int32_t apply_prec,
                                         int64_t *bytes) {
+  return smash_estimate_footprint_mode(n, dim, kid, leaf, p, adm, tol, apply_prec,
+                                       SMASH_COUPLING_STORED, bytes);
+}
+
+extern "C" int smash_estimate_footprint_mode(int64_t n, int32_t dim, int32_t kid, int32_t leaf,
+                                             int32_t p, int32_t adm, double tol,
+                                             int32_t apply_prec, int32_t coupling_mode,
+                                             int64_t *bytes) {
   if (!bytes) return fail(SMASH_E_INVALID_ARG, "bytes is NULL");
+  if (coupling_mode != SMASH_COUPLING_AUTO && coupling_mode != SMASH_COUPLING_STORED &&
+      coupling_mode != SMASH_COUPLING_EVALUATED)
+    return fail(SMASH_E_INVALID_ARG, "unknown coupling_mode");
   if (n < 1 || dim < 1 || dim > 3 || leaf < 1 || p < 1 || p > 64 ||
       (adm != SMASH_ADM_WEAK && adm != SMASH_ADM_STRONG) || !(tol >= 0.0) ||
       kid < 0 || kid > 3 ||
@@ -539,7 +550,12 @@ extern "C" int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kid, int
   b += dn * (dim * 8.0 * 2.0 + 64.0);                  // points, permutations, tree
   b += nodes * (far + near) * 16.0;                    // pair lists and offsets
   b += sides * nodes * r * r * (8.0 * 2.0 + es * 2.0);  // G master, transpose, copies
-  b += nodes * far * r * r * es;                       // coupling blocks
+  const double cb = nodes * far * r * r * es;          // coupling blocks
+  // evaluated inside each product: a chunk workspace of at most 256 MiB
+  // plus one node's blocks instead
+  b += coupling_mode == SMASH_COUPLING_EVALUATED
+           ? std::min(cb, 268435456.0 + far * r * r * es)
+           : cb;
   b += leaves * near * (double)leaf * (double)leaf * es;  // near blocks
   b += 2.0 * (dn + sides * nodes * r) * 64.0 * vs;     // product workspace
   *bytes = (int64_t)std::min(b, 9.0e18);

@@ -11,6 +11,10 @@ on the device (a product only).  The engine
     (smash_estimate_footprint) scaled by the ratio of real to estimated
     bytes seen so far (seeded from the autotuner table), with a margin;
   * evicts idle resident matrices, least recently used first, to make room;
+  * admits a construction whose stored form exceeds the whole budget with
+    its coupling blocks evaluated inside each product instead
+    (SMASH_COUPLING_EVALUATED: the same results, no O(sum k_i k_j) storage,
+    slower products);
   * merges the waiting product requests of one resident matrix into a
     single multi-right-hand-side product (one pass over its blocks);
   * runs admitted work on worker threads, one HIP stream each, so builds
@@ -62,7 +66,8 @@ class Resident:
 
 class Engine:
     def __init__(self, executor, budget_bytes: int, slots: int = 4, margin: float = 1.15,
-                 ratio: float | None = None, max_batch_rhs: int = 64, lookahead: int = 8):
+                 ratio: float | None = None, max_batch_rhs: int = 64, lookahead: int = 8,
+                 allow_evaluated: bool = True):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = int(slots)
@@ -70,6 +75,7 @@ class Engine:
         self.ratios = {} if ratio is None else {None: ratio}  # real / estimated bytes
         self.max_batch_rhs = max_batch_rhs
         self.lookahead = lookahead
+        self.allow_evaluated = allow_evaluated
         self.resident: dict[str, Resident] = collections.OrderedDict()
         self.inflight = []            # (future, kind, requests, reserved bytes, matrix)
         self.reserved = 0             # bytes of resident matrices + builds in flight
@@ -79,15 +85,20 @@ class Engine:
 
     # ---- memory model ---------------------------------------------------
     @staticmethod
-    def _cls(req):
-        return None if req.points is None else req.points.shape[1]
+    def _evaluated(req):
+        return req.params.get("coupling") == "evaluated"
 
-    def _need(self, req):
-        """Bytes reserved for a construction: the estimate times the largest
-        real/estimated ratio seen for its dimension (before any: the
-        executor's prior, else 1), with the margin, never above 1."""
-        est = self.ex.estimate(req)
-        r = self.ratios.get(self._cls(req), self.ratios.get(None))
+    @staticmethod
+    def _cls(req, evaluated=False):
+        return None if req.points is None else (req.points.shape[1], bool(evaluated))
+
+    def _need(self, req, evaluated=False):
+        """Bytes reserved for a construction (stored or evaluated coupling
+        blocks): the estimate times the largest real/estimated ratio seen for
+        its dimension and form (before any: the executor's prior, else 1),
+        with the margin, never above 1."""
+        est = self.ex.estimate(req, evaluated=evaluated)
+        r = self.ratios.get(self._cls(req, evaluated), self.ratios.get(None))
         if r is None:
             r = self.ex.prior_ratio(req)
         return int(est * min(1.0, r * self.margin))
@@ -154,9 +165,10 @@ class Engine:
             if kind == "build":
                 handle, nbytes, results = out
                 building.discard(m)
-                est = self.ex.estimate(group[0])
+                ev = self._evaluated(group[0])
+                est = self.ex.estimate(group[0], evaluated=ev)
                 if est > 0:
-                    c = self._cls(group[0])
+                    c = self._cls(group[0], ev)
                     self.ratios[c] = max(self.ratios.get(c, 0.0), nbytes / est)
                 self.reserved += nbytes - resv
                 self.resident[m] = Resident(m, handle, nbytes, False, t)
@@ -220,15 +232,30 @@ class Engine:
                 progressed = True
                 continue
             need = self._need(req)
-            if need > self.budget:
-                req.error, req.done = "footprint above the memory budget", now()
-                pending.remove(req)
-                done.append(req)
-                progressed = True
+            evaluated = False
+            fits = need <= self.budget and (self.reserved + need <= self.budget or
+                                            self._evict_for(need))
+            if need > self.budget and self.allow_evaluated:
+                # the stored form can never fit: the coupling blocks are
+                # evaluated inside each product instead (slower products,
+                # no stored blocks); a stored form that only has to wait for
+                # memory waits
+                need_e = self._need(req, evaluated=True)
+                if need_e <= self.budget:
+                    need, evaluated = need_e, True
+                    fits = self.reserved + need <= self.budget or self._evict_for(need)
+            if not fits:
+                if need > self.budget:
+                    req.error, req.done = "footprint above the memory budget", now()
+                    pending.remove(req)
+                    done.append(req)
+                    progressed = True
+                else:
+                    idx += 1      # does not fit yet: let smaller ones pass
                 continue
-            if self.reserved + need > self.budget and not self._evict_for(need):
-                idx += 1          # does not fit yet: let smaller ones pass
-                continue
+            if evaluated:
+                req.params = dict(req.params, coupling="evaluated")
+                self.log.append(("evaluated", m))
             pending.remove(req)
             req.admitted = now()
             self.reserved += need
@@ -277,13 +304,14 @@ class GpuExecutor:
             self.local.stream = s
         return s
 
-    def estimate(self, req):
+    def estimate(self, req, evaluated=False):
         from . import api
         p = req.params
         n = max(req.rhs.shape[0], 1 if req.points is None else req.points.shape[0])
         dim = req.points.shape[1] if req.points is not None else p.get("dim", 2)
         return api.estimate_footprint(n, dim, p["kernel"], p["leaf"], p["order"], p["adm"],
-                                      p["tol"], p["apply_prec"])
+                                      p["tol"], p["apply_prec"],
+                                      coupling="evaluated" if evaluated else "stored")
 
     def prior_ratio(self, req):
         return self.prior.get(req.points.shape[1] if req.points is not None else 0, 1.0)

@@ -74,3 +74,19 @@ def test_binding_refuses_cpu_tensors():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         api.Smash(torch.zeros(4, 2, dtype=torch.float64))
+
+
+def test_footprint_estimate_by_coupling_form():
+    """The evaluated form never estimates above the stored one, the AUTO form
+    estimates as the stored one, and an unknown form is rejected."""
+    L = api.lib()
+    b = C.c_int64(0)
+    for n, d, k in ((1000, 1, 0), (65536, 2, 1), (30000, 3, 0), (200000, 3, 2)):
+        s = api.estimate_footprint(n, d, list(api.KERNELS)[k], coupling="stored")
+        e = api.estimate_footprint(n, d, list(api.KERNELS)[k], coupling="evaluated")
+        a = api.estimate_footprint(n, d, list(api.KERNELS)[k], coupling="auto")
+        assert 0 < e <= s and a == s
+        assert L.smash_estimate_footprint(n, d, k, 64, 8, 1, 1e-6, 0, C.byref(b)) == 0
+        assert b.value == s
+    assert L.smash_estimate_footprint_mode(1000, 2, 0, 64, 8, 1, 1e-6, 0, 7, C.byref(b)) == -1
+    assert L.smash_estimate_footprint_mode(1000, 2, 0, 64, 8, 1, 1e-6, 0, 2, None) == -1

@@ -34,3 +34,38 @@ def test_serving_mix_equals_alone():
         h.close()
         err = np.linalg.norm(r.result - z) / np.linalg.norm(z)
         assert err < 1e-5, (r.rid, r.matrix, err)
+
+
+def test_serving_falls_back_to_evaluated_coupling():
+    """A construction whose stored footprint exceeds the whole budget is
+    served with its coupling blocks evaluated inside each product; its
+    products equal those of the stored form built alone."""
+    from paper_1705_05443_amd import workloads as W
+    n, d = 30000, 2
+    params = dict(kernel="log_r", leaf=serve.SERVE_LEAF[d], order=serve.SERVE_ORDER[d],
+                  adm="strong", tol=1e-6, apply_prec="f32", eval_prec="f32",
+                  root=((0.0,) * d, 1.0), dim=d)
+    est = {c: api.estimate_footprint(n, d, params["kernel"], params["leaf"], params["order"],
+                                     "strong", params["tol"], "f32", coupling=c)
+           for c in ("stored", "evaluated")}
+    budget = (est["stored"] + est["evaluated"]) // 2
+    assert est["evaluated"] < budget < est["stored"], est
+    rng = np.random.default_rng(11)
+    pts = W.uniform(n, d, 77)
+    reqs = [serve.Request(0, 0.0, "big", rng.standard_normal((n, 8)), pts, dict(params)),
+            serve.Request(1, 0.001, "big", rng.standard_normal((n, 3)), None, dict(params))]
+    ex = serve.GpuExecutor(slots=2)
+    eng = serve.Engine(ex, budget_bytes=budget, slots=2)
+    done = {r.rid: r for r in eng.run(reqs)}
+    eng.close()
+    ex.shutdown()
+    assert all(r.error is None for r in done.values()), [r.error for r in done.values()]
+    assert ("evaluated", "big") in eng.log
+    p = dict(params)
+    p.pop("dim")
+    h = api.Smash(torch.from_numpy(pts).cuda(), graphs=False, coupling="stored", **p)
+    for r in done.values():
+        z = h.matvec(torch.from_numpy(r.rhs.astype(np.float32)).cuda()).cpu().numpy()
+        err = np.linalg.norm(r.result - z) / np.linalg.norm(z)
+        assert err < 1e-5, (r.rid, err)
+    h.close()

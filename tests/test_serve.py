@@ -24,8 +24,9 @@ class FakeExecutor:
         self.max_running = 0
         self.released = []
 
-    def estimate(self, req):
-        return 2 * req.rhs.shape[0]
+    def estimate(self, req, evaluated=False):
+        # the evaluated coupling form is estimated at a quarter of the stored one
+        return (req.rhs.shape[0] // 2) if evaluated else 2 * req.rhs.shape[0]
 
     def prior_ratio(self, req):
         return 1.0
@@ -43,7 +44,10 @@ class FakeExecutor:
         self._enter()
         time.sleep(self.build_s)
         self._leave()
-        return ("H", req.matrix), self.real * req.rhs.shape[0], [2.0 * req.rhs]
+        nb = self.real * req.rhs.shape[0]
+        if req.params.get("coupling") == "evaluated":
+            nb //= 4
+        return ("H", req.matrix), nb, [2.0 * req.rhs]
 
     def _product(self, h, group):
         self._enter()
@@ -107,7 +111,7 @@ def test_products_on_a_resident_matrix_are_batched():
 
 def test_idle_residents_are_evicted_to_admit_new_builds():
     ex = FakeExecutor(slots=1, real_per_point=2)
-    eng = Engine(ex, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0)
+    eng = Engine(ex, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0, allow_evaluated=False)
     reqs = [_req(i, 0.0, "m%d" % i, 1000) for i in range(4)]  # 2000 reserved each
     done = eng.run(reqs)
     assert all(r.error is None for r in done)
@@ -128,5 +132,24 @@ def test_observed_bytes_calibrate_the_reservation():
     eng = Engine(ex, budget_bytes=10**9, slots=1, margin=1.0)
     eng.run([_req(0, 0.0, "a", 1000)])
     # real bytes are half the estimate: later reservations shrink to match
-    assert abs(eng.ratios[2] - 0.5) < 1e-12
+    assert abs(eng.ratios[(2, False)] - 0.5) < 1e-12
     assert eng._need(_req(1, 0.0, "b", 1000)) == 1000
+
+
+def test_evaluated_coupling_admits_what_the_stored_form_cannot():
+    """A construction whose stored footprint exceeds the budget is admitted
+    with its coupling blocks evaluated inside each product (a quarter of the
+    footprint here); without that fallback it is rejected."""
+    ex = FakeExecutor(slots=1)
+    eng = Engine(ex, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0)
+    done = {r.rid: r for r in eng.run([_req(0, 0.0, "big", 2000), _req(1, 0.01, "big", 2000,
+                                                                        build=False)])}
+    assert done[0].error is None and done[1].error is None
+    assert ("evaluated", "big") in eng.log
+    assert done[0].params.get("coupling") == "evaluated"
+    assert np.array_equal(done[1].result, 2.0 * done[1].rhs)
+    assert eng.peak_reserved <= 3000
+    ex2 = FakeExecutor(slots=1)
+    eng2 = Engine(ex2, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0, allow_evaluated=False)
+    d2 = eng2.run([_req(0, 0.0, "big", 2000)])
+    assert d2[0].error and "budget" in d2[0].error
