@@ -69,6 +69,18 @@ template <int CTRL, int ROWM = 0xF>
 __device__ __forceinline__ int dpp_i32(int x) {
   return __builtin_amdgcn_update_dpp(x, x, CTRL, ROWM, 0xF, false);
 }
+// the same for permutations in which every lane has a source lane (quad
+// permutations, mirrors): no old value to keep, so no copy of x first
+template <int CTRL>
+__device__ __forceinline__ double perm_f64(double x) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ int perm_i32(int x) {
+  return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+}
 __device__ __forceinline__ double readlane_f64(double x, int l) {
   return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
                           __builtin_amdgcn_readlane(__double2loint(x), l));
@@ -77,14 +89,14 @@ __device__ __forceinline__ double readlane_f64(double x, int l) {
 // every lane adds the same two operands)
 template <int LPC>
 __device__ __forceinline__ double group_sum(double x) {
-  if constexpr (LPC >= 2) x += dpp_f64<0xB1>(x);  // quad_perm [1,0,3,2]
-  if constexpr (LPC >= 4) x += dpp_f64<0x4E>(x);  // quad_perm [2,3,0,1]
+  if constexpr (LPC >= 2) x += perm_f64<0xB1>(x);  // quad_perm [1,0,3,2]
+  if constexpr (LPC >= 4) x += perm_f64<0x4E>(x);  // quad_perm [2,3,0,1]
   return x;
 }
 template <int LPC>
 __device__ __forceinline__ int group_max(int x) {
-  if constexpr (LPC >= 2) x = max(x, dpp_i32<0xB1>(x));
-  if constexpr (LPC >= 4) x = max(x, dpp_i32<0x4E>(x));
+  if constexpr (LPC >= 2) x = max(x, perm_i32<0xB1>(x));
+  if constexpr (LPC >= 4) x = max(x, perm_i32<0x4E>(x));
   return x;
 }
 // the value of group member HS in every lane of the group
@@ -93,9 +105,9 @@ __device__ __forceinline__ double group_bcast(double x) {
   if constexpr (LPC == 1)
     return x;
   else if constexpr (LPC == 2)
-    return dpp_f64<HS | (HS << 2) | ((2 + HS) << 4) | ((2 + HS) << 6)>(x);
+    return perm_f64<HS | (HS << 2) | ((2 + HS) << 4) | ((2 + HS) << 6)>(x);
   else
-    return dpp_f64<HS | (HS << 2) | (HS << 4) | (HS << 6)>(x);
+    return perm_f64<HS | (HS << 2) | (HS << 4) | (HS << 6)>(x);
 }
 
 // ---- block reductions --------------------------------------------------
@@ -121,10 +133,10 @@ __device__ __forceinline__ int argmax_index(ArgMax x, double v, bool valid) {
   if (hit == 0) return -1;
   if (__popcll(hit) == 1) return __builtin_amdgcn_readlane(x.a, __ffsll((unsigned long long)hit) - 1);
   int a = on ? x.a : 0x7fffffff;
-  if constexpr (NL > 1) a = min(a, dpp_i32<0xB1>(a));
-  if constexpr (NL > 2) a = min(a, dpp_i32<0x4E>(a));
-  if constexpr (NL > 4) a = min(a, dpp_i32<0x141>(a));
-  if constexpr (NL > 8) a = min(a, dpp_i32<0x140>(a));
+  if constexpr (NL > 1) a = min(a, perm_i32<0xB1>(a));
+  if constexpr (NL > 2) a = min(a, perm_i32<0x4E>(a));
+  if constexpr (NL > 4) a = min(a, perm_i32<0x141>(a));
+  if constexpr (NL > 8) a = min(a, perm_i32<0x140>(a));
   if constexpr (NL > 16) {
     a = min(a, dpp_i32<0x142, 0xA>(a));
     a = min(a, dpp_i32<0x143, 0xC>(a));
@@ -141,10 +153,10 @@ __device__ __forceinline__ int argmax_index(ArgMax x, double v, bool valid) {
 // rows, then the row broadcasts leave the maximum in lane 63.
 __device__ inline ArgMax wave_argmax(ArgMax x) {
   double v = x.v;
-  v = fmax(v, dpp_f64<0xB1>(v));        // quad_perm [1,0,3,2]
-  v = fmax(v, dpp_f64<0x4E>(v));        // quad_perm [2,3,0,1]
-  v = fmax(v, dpp_f64<0x141>(v));       // row_half_mirror
-  v = fmax(v, dpp_f64<0x140>(v));       // row_mirror
+  v = fmax(v, perm_f64<0xB1>(v));       // quad_perm [1,0,3,2]
+  v = fmax(v, perm_f64<0x4E>(v));       // quad_perm [2,3,0,1]
+  v = fmax(v, perm_f64<0x141>(v));      // row_half_mirror
+  v = fmax(v, perm_f64<0x140>(v));      // row_mirror
   v = fmax(v, dpp_f64<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
   v = fmax(v, dpp_f64<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
   v = readlane_f64(v, WAVE - 1);
@@ -156,10 +168,10 @@ template <int NL>
 __device__ inline ArgMax lanes_argmax(ArgMax x) {
   const bool valid = (int)(threadIdx.x & (WAVE - 1)) < NL;
   double v = valid ? x.v : -1.0;
-  if constexpr (NL > 1) v = fmax(v, dpp_f64<0xB1>(v));
-  if constexpr (NL > 2) v = fmax(v, dpp_f64<0x4E>(v));
-  if constexpr (NL > 4) v = fmax(v, dpp_f64<0x141>(v));
-  if constexpr (NL > 8) v = fmax(v, dpp_f64<0x140>(v));
+  if constexpr (NL > 1) v = fmax(v, perm_f64<0xB1>(v));
+  if constexpr (NL > 2) v = fmax(v, perm_f64<0x4E>(v));
+  if constexpr (NL > 4) v = fmax(v, perm_f64<0x141>(v));
+  if constexpr (NL > 8) v = fmax(v, perm_f64<0x140>(v));
   v = readlane_f64(v, 0);
   return ArgMax{v, argmax_index<NL>(x, v, valid)};
 }
@@ -532,11 +544,12 @@ __global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
 // r = LPC u + h (u < CMAX / LPC).  Each value read from LDS (a reflector
 // entry, an entry of R11) then feeds J columns, and sums over a column are
 // lane exchanges (DPP) inside the group.  So
-//   * a Householder step is one block arg-max of the residual norms, one
-//     LDS copy of the pivot column (the reflector v; v^T v follows from the
-//     pivot norm as 2 beta (beta + |x_t|)), and a register update of every
-//     column (scale 0 for the pivot and finished ones) with the norms of the
-//     remaining ones recomputed;
+//   * a Householder step is one block arg-max of the squared residual norms
+//     (one barrier: each wavefront's own winner stages its column in LDS
+//     beforehand), the reflector v read from the winning slot (v^T v follows
+//     from the pivot norm as 2 beta (beta + |x_t|)), and a register update of
+//     every column (scale 0 for the pivot and finished ones) with the squared
+//     norms of the remaining ones recomputed;
 //   * a column's position (the order the QR works in) is a label: a pivot
 //     or a Gu-Eisenstat swap relabels two columns instead of moving data,
 //     and ties still go to the lowest current position;
@@ -554,7 +567,9 @@ template <int CMAX, int NT, int LPC, int J>
 __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
   constexpr int RL = CMAX / LPC;  // rows per lane and column
   constexpr int NC = NT / LPC * J;  // grid columns per workgroup
-  constexpr int VS = RL + 2;      // stride of a row phase in vb (phases on other banks)
+  constexpr int NW = NT / WAVE;   // wavefronts
+  constexpr int VS = RL + 2;      // stride of a row phase in a column slot (phases on other banks)
+  constexpr int SL = LPC * VS;    // one column slot
   constexpr int LDI = CMAX + 1;   // row stride of R11^-1
   // dynamic LDS, one region used in turn: the one-dimensional basis factors
   // [d*p][NC] while the basis is built; R11 by column j and row phase hh at
@@ -564,13 +579,13 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
   double *const Rs = dyn;
   double *const Ris = dyn;
   __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
-  __shared__ double vb[LPC * VS], rdiag[CMAX], rdg[CMAX], rinv[CMAX];
+  __shared__ double pv[2 * NW * SL], rdiag[CMAX], rdg[CMAX], rinv[CMAX];
   __shared__ int srank[CMAX];
-  __shared__ ArgMax ared[NT / WAVE + 1], ared2[2 * (NT / WAVE)];
+  __shared__ ArgMax ared[NW + 1], ared2[2 * NW];
   __shared__ int64_t sred[NT / WAVE + 1];
-  __shared__ double vn_lds;
   const int tid = threadIdx.x;
   const int cb = tid / LPC, h = tid % LPC;  // column group, row phase
+  const int wid = tid / WAVE, lane = tid & (WAVE - 1);
   const int p = A.p, d = A.d;
   if (tid < p) {
     double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
@@ -675,7 +690,7 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
           double s0 = 0.0;
 #pragma unroll
           for (int u = 0; u < RL; u++) s0 = fma(col[j][u], col[j][u], s0);
-          nrm[j] = sqrt(group_sum<LPC>(s0));
+          nrm[j] = group_sum<LPC>(s0);  // squared: the arg-max needs no root
         } else {
 #pragma unroll
           for (int u = 0; u < RL; u++) col[j][u] = 0.0;
@@ -713,8 +728,27 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
               if (act[j] && (pivoting ? pa[j] >= t : pa[j] == t))
                 am = amax_pick(am, ArgMax{nrm[j], pa[j]});
           }
-          am = block_argmax_1b<NT / WAVE>(am, ared2, t & 1);
-          const double bn = am.v;
+          // each wavefront's own winner copies its column into the wave's
+          // slot before the one barrier of the step, so the pivot column is
+          // in LDS as soon as the block arg-max is known.  Slots and arg-max
+          // entries alternate by step parity: a half is rewritten two steps
+          // after it was read, with the barrier of the step in between.
+          const ArgMax wa = wave_argmax(am);
+          double *const slots = pv + (t & 1) * (NW * SL);
+          ArgMax *const ah = ared2 + (t & 1) * NW;
+#pragma unroll
+          for (int j = 0; j < J; j++) {
+            if (act[j] && pa[j] == wa.a) {
+              double *vs = slots + wid * SL + h * VS;
+#pragma unroll
+              for (int u = u0; u < RL; u++) vs[u] = col[j][u];
+            }
+          }
+          if (lane == 0) ah[wid] = wa;
+          __syncthreads();
+          const ArgMax we = lane < NW ? ah[lane] : ArgMax{-1.0, -1};
+          am = lanes_argmax<NW>(we);
+          const double bn = sqrt(am.v);  // the pivot norm (the winner's root only)
           if (pivoting) {
             if (t == 0) {
               r00 = bn;
@@ -728,6 +762,13 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
             }
           }
           const int bp = am.a;
+          if (bp < 0) {  // no column left at this position (uniform)
+            stop = true;
+            break;
+          }
+          // the wavefront whose winner is the pivot (positions are distinct)
+          const uint64_t wins = __ballot(lane < NW && we.a == bp);
+          const int ws = (int)__ffsll((unsigned long long)wins) - 1;
 #pragma unroll
           for (int j = 0; j < J; j++) {
             if (act[j]) {
@@ -737,38 +778,31 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
                 pa[j] = t;
             }
           }
+          // v: zero above row t, x_t - R_tt at row t, the column below;
+          // v^T v = 2 beta (beta + |x_t|) with beta the pivot norm
+          const double *const src = slots + ws * SL;
+          const double xt = src[(t % LPC) * VS + t / LPC];
+          const double rtt = xt >= 0.0 ? -bn : bn;
+          const double vn = 2.0 * bn * (bn + fabs(xt));
+          const double rv = 2.0 / vn;
+          if (tid == 0) rdiag[t] = rtt;
+          const double *vh = src + h * VS;
+          auto vval = [&](int u) -> double {
+            const double y = vh[u];
+            if (u >= u1) return y;
+            const int r = LPC * u + h;
+            return r < t ? 0.0 : (r == t ? y - rtt : y);
+          };
+          // two partial sums per column (even and odd rows of the lane):
+          // half the chain of dependent multiply-adds
+          double w[2][J];
 #pragma unroll
-          for (int j = 0; j < J; j++) {
-            if (act[j] && pa[j] == t) {
-              // v: zero above row t, x_t - R_tt at row t, the column below
-              double *vh = vb + h * VS;
-#pragma unroll
-              for (int u = u0; u < u1; u++) {
-                const int r = LPC * u + h;
-                double y = r < t ? 0.0 : col[j][u];
-                if (r == t) {
-                  const double rtt = y >= 0.0 ? -bn : bn;
-                  rdiag[t] = rtt;
-                  vn_lds = 2.0 * bn * (bn + fabs(y));
-                  y -= rtt;
-                }
-                vh[u] = y;
-              }
-#pragma unroll
-              for (int u = u1; u < RL; u++) vh[u] = col[j][u];
-            }
-          }
-          __syncthreads();
-          const double vn = vn_lds;
-          const double *vh = vb + h * VS;
-          double w[J];
-#pragma unroll
-          for (int j = 0; j < J; j++) w[j] = 0.0;
+          for (int j = 0; j < J; j++) w[0][j] = w[1][j] = 0.0;
 #pragma unroll
           for (int u = u0; u < RL; u++) {
-            const double vu = vh[u];
+            const double vu = vval(u);
 #pragma unroll
-            for (int j = 0; j < J; j++) w[j] = fma(vu, col[j][u], w[j]);
+            for (int j = 0; j < J; j++) w[u & 1][j] = fma(vu, col[j][u], w[u & 1][j]);
           }
           // scale 0 leaves a column as it is (the pivot, finished ones)
           double sc[J];
@@ -776,33 +810,31 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
 #pragma unroll
           for (int j = 0; j < J; j++) {
             up[j] = act[j] && pa[j] > t && vn > 0.0;
-            const double g = group_sum<LPC>(w[j]);
-            sc[j] = up[j] ? 2.0 * g / vn : 0.0;
+            const double g = group_sum<LPC>(w[0][j] + w[1][j]);
+            sc[j] = up[j] ? g * rv : 0.0;
           }
           // v is read again from LDS below rather than kept in registers
           __asm__ volatile("" ::: "memory");
-          double s[J];
+          double s[2][J];
 #pragma unroll
-          for (int j = 0; j < J; j++) s[j] = 0.0;
+          for (int j = 0; j < J; j++) s[0][j] = s[1][j] = 0.0;
 #pragma unroll
           for (int u = u0; u < RL; u++) {
-            const double vu = vh[u];
+            const double vu = vval(u);
             const bool below = u >= u1 || LPC * u + h > t;
 #pragma unroll
             for (int j = 0; j < J; j++) {
               const double y = fma(-sc[j], vu, col[j][u]);
               col[j][u] = y;
               const double z = below ? y : 0.0;
-              s[j] = fma(z, z, s[j]);
+              s[u & 1][j] = fma(z, z, s[u & 1][j]);
             }
           }
 #pragma unroll
           for (int j = 0; j < J; j++) {
-            const double nn = sqrt(group_sum<LPC>(s[j]));
+            const double nn = group_sum<LPC>(s[0][j] + s[1][j]);
             if (up[j]) nrm[j] = nn;
           }
-          // no barrier here: vb and vn_lds are next written after the next
-          // step's arg-max barrier, which every reader of them has passed
           kk = t + 1;
         }
       }
@@ -914,6 +946,7 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
 #pragma unroll
       for (int j = 0; j < J; j++) {
         if (act[j] && pa[j] >= k) {
+          const double gam = sqrt(nrm[j]);  // norm of the column's rows >= k
           const int64_t row = J * cb + j - exj[j];
           double *Gr = A.G_out + A.go[i] + (A.gt_out ? row : row * k);
           const int64_t cs = A.gt_out ? (int64_t)nr : 1;
@@ -922,7 +955,7 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
           for (int u = 0; u < RL; u++) {
             const int ii = LPC * u + h;
             if (ii < k) {
-              const double gw = nrm[j] * rinv[ii];
+              const double gw = gam * rinv[ii];
               const double r2 = col[j][u] * col[j][u] + gw * gw;
               am = amax_pick(am, ArgMax{r2, base + ii});
               Gr[srank[ii] * cs] = col[j][u];
