@@ -75,6 +75,44 @@ __device__ inline int64_t block_excl_scan_i64(int64_t v, int64_t *total, int64_t
 // ------------------------------------------------------------------ kernels
 // kappa(x, y) in FP64.  "x = y" means every coordinate equal (eq. (2.1):
 // the diagonal value d_x is then returned for the singular kernels).
+// Natural logarithm of a positive double for the kernel log|x - y|, by
+// argument reduction and the atanh series: x = 2^e m with m in
+// [sqrt(1/2), sqrt(2)) and log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),
+// s = (m - 1) / (m + 1), |s| < 0.172, so the terms through s^21 leave a
+// truncation below 3e-17 relative; e ln 2 is added in double-double
+// (ln 2 = LN2_HI + LN2_LO, the nearest double and the rest).  A few units in
+// the last place, at about a third of the library routine's instructions;
+// zero, infinity and NaN go to the library routine.
+constexpr double LN2_HI = 0.6931471805599453;     // nearest double to ln 2
+constexpr double LN2_LO = 2.319046813846299558e-17;  // ln 2 - LN2_HI
+__device__ __forceinline__ double log_pos(double x) {
+  if (!(x > 0.0 && x < __builtin_huge_val())) return log(x);
+  double m = __builtin_amdgcn_frexp_mant(x);  // [0.5, 1), exact
+  int e = __builtin_amdgcn_frexp_exp(x);
+  if (m < 0.70710678118654752440) {
+    m += m;
+    e -= 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0);  // m - 1 is exact
+  const double z = s * s;
+  double p = 1.0 / 21.0;
+  p = fma(p, z, 1.0 / 19.0);
+  p = fma(p, z, 1.0 / 17.0);
+  p = fma(p, z, 1.0 / 15.0);
+  p = fma(p, z, 1.0 / 13.0);
+  p = fma(p, z, 1.0 / 11.0);
+  p = fma(p, z, 1.0 / 9.0);
+  p = fma(p, z, 1.0 / 7.0);
+  p = fma(p, z, 1.0 / 5.0);
+  p = fma(p, z, 1.0 / 3.0);
+  const double s2 = s + s;
+  const double lm = fma(s2 * z, p, s2);  // 2 atanh(s)
+  const double de = (double)e;
+  const double hi = de * LN2_HI;
+  const double he = fma(de, LN2_HI, -hi);  // the product's rounding error, exactly
+  return hi + (lm + (he + de * LN2_LO));
+}
+
 __device__ inline double kernel_f64(int kid, const double *x, const double *y, int d,
                                     double diag) {
   double r2 = 0.0;
@@ -87,7 +125,7 @@ __device__ inline double kernel_f64(int kid, const double *x, const double *y, i
   if (kid == SMASH_KERNEL_EXP_R) return exp(-sqrt(r2));
   if (same) return diag;
   if (kid == SMASH_KERNEL_INV_R) return 1.0 / sqrt(r2);
-  if (kid == SMASH_KERNEL_LOG_R) return 0.5 * log(r2);
+  if (kid == SMASH_KERNEL_LOG_R) return 0.5 * log_pos(r2);
   return 1.0 / (x[0] - y[0]);
 }
 
@@ -128,7 +166,7 @@ __device__ __forceinline__ double kernel_f64_t(const double *x, const double *y,
   if (KID == SMASH_KERNEL_EXP_R) return exp(-sqrt(r2));
   if (same) return diag;
   if (KID == SMASH_KERNEL_INV_R) return 1.0 / sqrt(r2);
-  if (KID == SMASH_KERNEL_LOG_R) return 0.5 * log(r2);
+  if (KID == SMASH_KERNEL_LOG_R) return 0.5 * log_pos(r2);
   return 1.0 / (x[0] - y[0]);
 }
 

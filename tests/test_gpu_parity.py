@@ -521,3 +521,37 @@ def test_autotuner_shape_keeps_the_product():
     g1 = api.Smash(dev(x), tuned=False, **kw, **shp)
     z0, z1 = g0.matvec(q).cpu().numpy(), g1.matvec(q).cpu().numpy()
     assert relerr(z1, z0) < 1e-13
+
+
+@pytest.mark.parametrize("scale", [1e-155, 1e140])
+def test_log_kernel_blocks_at_extreme_scales(scale):
+    """log|x - y| blocks where |x - y|^2 is subnormal (points in a box of side
+    1e-155) or near the top of the range (side 1e140), against numpy's log
+    of the same FP64 squared distance: the library's logarithm (argument
+    reduction and the atanh series) stays within a few units in the last
+    place there too."""
+    x = W.uniform(3000, 2, 21) * scale
+    g = api.Smash(dev(x), kernel="log_r", leaf=64, order=6, adm="strong", tol=1e-6, tau=0.7,
+                  root=((0.0, 0.0), scale), graphs=False)
+    print("scale", scale, flush=True)
+    L = g.export("L").reshape(-1, 2)
+    B = g.export("coupling")
+    rk = g.export("ranks").reshape(-1, 6)
+    px = g.export("perm_x")
+    per = _gpu_per_node(g, "row", rk.shape[0])
+    assert len(L) > 0
+    off, worst = 0, 0.0
+    for i, j in L:
+        ki, kj = rk[i, 1], rk[j, 1]
+        gi, si, _ = per[i]
+        gj, sj, _ = per[j]
+        rows = x[px[gi[si[:ki]]]]
+        cols = x[px[gj[sj[:kj]]]]
+        d = rows[:, None, :] - cols[None, :, :]
+        ref = 0.5 * np.log(d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1])
+        blk = B[off:off + ki * kj].reshape(kj, ki).T
+        worst = max(worst, float(np.max(np.abs(blk - ref) / np.abs(ref))))
+        off += ki * kj
+    g.close()
+    assert off == B.size
+    assert worst < 8 * np.finfo(np.float64).eps, worst
