@@ -157,6 +157,23 @@ int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int
 int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
                  void *Y, int64_t ldy, void *stream);
 
+/* Products of several handles in one call (Sec. 3.4 for each): Ys[c] =
+ * A-hat_c Xs[c] for c < count, enqueued on `stream` in order, each exactly as
+ * smash_matvec would (a captured-graph replay once its argument set repeats).
+ * For a serving loop that serves several resident matrices at once: one call
+ * and one validation pass for all of them.
+ *   hs, Xs, ldx, nrhs, Ys, ldy   host arrays of `count` entries with the
+ *                meaning of smash_matvec's arguments; a handle may repeat
+ *                (its products then run one after the other)
+ *   dtype        for every entry
+ * Every entry is validated before anything is enqueued: on an invalid one
+ * nothing runs and the message names its index.  count == 0 does nothing.
+ * Errors: SMASH_E_INVALID_ARG (count < 0, a NULL array, or an entry that
+ * smash_matvec would reject), then as smash_matvec. */
+int smash_matvec_batched(int32_t count, const smash_handle *hs, const void *const *Xs,
+                         const int64_t *ldx, const int32_t *nrhs, void *const *Ys,
+                         const int64_t *ldy, int32_t dtype, void *stream);
+
 /* Launch shape of the products of an existing handle (the options
  * mv_split_nodes and mv_xcd_run), as an autotuner sets it between timed
  * products.  The numbers are unchanged up to the summation order of the

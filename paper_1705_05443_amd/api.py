@@ -67,7 +67,7 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-            "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
+            "smash_matvec_batched", "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
             "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_last_error"]
 
 
@@ -87,6 +87,9 @@ def lib():
                                      C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                      C.POINTER(Options), vp, C.POINTER(vp)]
         L.smash_matvec.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, vp]
+        L.smash_matvec_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp),
+                                           C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                           C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, vp]
         L.smash_set_product_shape.argtypes = [vp, C.c_int32, C.c_int32]
         L.smash_estimate_footprint.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                                C.c_int32, C.c_int32, C.c_double, C.c_int32,
@@ -99,6 +102,7 @@ def lib():
         L.smash_destroy.argtypes = [vp]
         L.smash_last_error.restype = C.c_char_p
         for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
+                  "smash_matvec_batched",
                   "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
                   "smash_estimate_footprint", "smash_estimate_footprint_mode"):
             getattr(L, f).restype = C.c_int
@@ -127,6 +131,45 @@ def estimate_footprint(n, dim, kernel="inv_r", leaf=64, order=8, adm="strong", t
                                                PREC[apply_prec], COUPLING[coupling],
                                                C.byref(b)))
     return b.value
+
+
+def matvec_batched(handles, Xs, outs=None, stream=None):
+    """Products of several handles in one library call (smash_matvec_batched):
+    returns [h.matvec(X) for h, X in zip(handles, Xs)], 2-D (n, nrhs) tensors
+    of one vector precision; `outs` may give the result tensors."""
+    import torch
+    if len(handles) != len(Xs) or (outs is not None and len(outs) != len(Xs)):
+        raise ValueError("handles, Xs (and outs) must have the same length")
+    if not handles:
+        return []
+    precs = {h.apply_prec == "f64" for h in handles}
+    if len(precs) != 1:
+        raise TypeError("all handles must share the vector precision")
+    dt = torch.float64 if precs.pop() else torch.float32
+    Xc, Yc = [], []
+    for c, (h, X) in enumerate(zip(handles, Xs)):
+        if X.dim() != 2 or X.dtype != dt or not X.is_cuda:
+            raise TypeError("X must be a 2-D CUDA tensor of the vector precision")
+        X = X if X.stride(1) == 1 else X.contiguous()
+        Y = (torch.empty((h.nx, X.shape[1]), dtype=dt, device=X.device) if outs is None
+             else outs[c])
+        if (not Y.is_cuda or Y.dtype != dt or tuple(Y.shape) != (h.nx, X.shape[1])
+                or Y.stride(1) != 1):
+            raise TypeError("out must be a CUDA (nx, nrhs) tensor with unit column stride")
+        Xc.append(X)
+        Yc.append(Y)
+    n = len(handles)
+    vp = C.c_void_p
+    hs = (vp * n)(*[h._h.value for h in handles])
+    xs = (vp * n)(*[X.data_ptr() for X in Xc])
+    ys = (vp * n)(*[Y.data_ptr() for Y in Yc])
+    ldx = (C.c_int64 * n)(*[X.stride(0) for X in Xc])
+    ldy = (C.c_int64 * n)(*[Y.stride(0) for Y in Yc])
+    nr = (C.c_int32 * n)(*[X.shape[1] for X in Xc])
+    _check(lib().smash_matvec_batched(n, hs, xs, ldx, nr, ys, ldy,
+                                      PREC["f64" if dt == torch.float64 else "f32"],
+                                      _stream_ptr(stream)))
+    return Yc
 
 
 class Smash:

@@ -232,6 +232,36 @@ extern "C" int smash_matvec(smash_handle hv, const void *X, int64_t ldx, int32_t
   }
 }
 
+extern "C" int smash_matvec_batched(int32_t count, const smash_handle *hs,
+                                    const void *const *Xs, const int64_t *ldx,
+                                    const int32_t *nrhs, void *const *Ys, const int64_t *ldy,
+                                    int32_t dtype, void *stream) {
+  if (count < 0) return fail(SMASH_E_INVALID_ARG, "count must be >= 0");
+  if (count == 0) return SMASH_OK;
+  if (!hs || !Xs || !ldx || !nrhs || !Ys || !ldy)
+    return fail(SMASH_E_INVALID_ARG, "an argument array is NULL");
+  for (int32_t c = 0; c < count; c++) {
+    const Handle *h = (const Handle *)hs[c];
+    const std::string at = " (entry " + std::to_string(c) + ")";
+    if (!h) return fail(SMASH_E_INVALID_ARG, "handle is NULL" + at);
+    if (!Xs[c] || !Ys[c]) return fail(SMASH_E_INVALID_ARG, "X or Y is NULL" + at);
+    if (nrhs[c] < 1) return fail(SMASH_E_INVALID_ARG, "nrhs must be >= 1" + at);
+    if (ldx[c] < nrhs[c] || ldy[c] < nrhs[c])
+      return fail(SMASH_E_INVALID_ARG, "leading dimension < nrhs" + at);
+    if (dtype != (h->apply_prec == SMASH_F64 ? SMASH_F64 : SMASH_F32))
+      return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's vector precision" + at);
+  }
+  try {
+    for (int32_t c = 0; c < count; c++)
+      run_matvec(*(Handle *)hs[c], Xs[c], ldx[c], nrhs[c], Ys[c], ldy[c], (hipStream_t)stream);
+    return SMASH_OK;
+  } catch (const Error &e) {
+    return fail(e.code, e.msg);
+  } catch (...) {
+    return fail(SMASH_E_DEVICE, "unexpected failure");
+  }
+}
+
 extern "C" int smash_set_product_shape(smash_handle hv, int32_t mv_split_nodes,
                                        int32_t mv_xcd_run) {
   Handle *h = (Handle *)hv;

@@ -90,3 +90,19 @@ def test_footprint_estimate_by_coupling_form():
         assert b.value == s
     assert L.smash_estimate_footprint_mode(1000, 2, 0, 64, 8, 1, 1e-6, 0, 7, C.byref(b)) == -1
     assert L.smash_estimate_footprint_mode(1000, 2, 0, 64, 8, 1, 1e-6, 0, 2, None) == -1
+
+
+def test_batched_products_reject_bad_arguments_before_running():
+    L = api.lib()
+    vp = C.c_void_p
+    one = lambda t, v: (t * 1)(v)  # noqa: E731
+    args = dict(hs=one(vp, None), xs=one(vp, 16), ldx=one(C.c_int64, 4), nr=one(C.c_int32, 4),
+                ys=one(vp, 16), ldy=one(C.c_int64, 4))
+    call = lambda n, a: L.smash_matvec_batched(n, a["hs"], a["xs"], a["ldx"], a["nr"], a["ys"],  # noqa: E731
+                                               a["ldy"], 0, None)
+    assert call(-1, args) == -1
+    assert call(0, args) == 0  # nothing to do
+    assert call(1, args) == -1  # NULL handle
+    assert b"entry 0" in L.smash_last_error()
+    assert L.smash_matvec_batched(1, None, args["xs"], args["ldx"], args["nr"], args["ys"],
+                                  args["ldy"], 0, None) == -1

@@ -555,3 +555,30 @@ def test_log_kernel_blocks_at_extreme_scales(scale):
     g.close()
     assert off == B.size
     assert worst < 8 * np.finfo(np.float64).eps, worst
+
+
+def test_batched_products_equal_single_ones():
+    """smash_matvec_batched over several handles (one of them twice, the
+    second time with another right-hand side) gives each product bit for bit
+    as smash_matvec does."""
+    import torch
+    specs = [(W.uniform(4000, 2, 31), dict(kernel="log_r", leaf=64, order=8, adm="strong",
+                                            tol=1e-8, tau=0.7, root=((0.0, 0.0), 1.0))),
+             (W.uniform(3000, 1, 32), dict(kernel="inv_r", leaf=32, order=10, adm="weak",
+                                            tol=1e-9, tau=0.6, root=((0.0,), 1.0)))]
+    hs = [api.Smash(dev(x), **kw) for x, kw in specs]
+    rng = np.random.default_rng(5)
+    order = [0, 1, 0]
+    Xs = [torch.from_numpy(rng.standard_normal((hs[c].ny, r))).cuda()
+          for c, r in zip(order, (3, 16, 7))]
+    print("batched products of", [hs[c].ny for c in order], flush=True)
+    single = [hs[c].matvec(X).cpu().numpy() for c, X in zip(order, Xs)]
+    outs = [torch.empty((hs[c].nx, X.shape[1]), dtype=torch.float64, device="cuda")
+            for c, X in zip(order, Xs)]
+    for rep in range(3):  # eager, captured, replayed (same argument sets)
+        batched = api.matvec_batched([hs[c] for c in order], Xs, outs)
+        torch.cuda.synchronize()
+        for a, b in zip(single, batched):
+            assert np.array_equal(a, b.cpu().numpy())
+    for h in hs:
+        h.close()
