@@ -104,6 +104,21 @@ typedef struct smash_handle_s *smash_handle;
  *                workspace holds one chunk plus at most one node's blocks);
  *                0 (default): 256 MiB worth of the apply precision
  */
+/* Device allocator hooks (smash_options.alloc, .free, .alloc_ctx): when both
+ * are set, every device allocation of the handle -- its build temporaries,
+ * its arrays and its product workspaces -- comes from
+ * alloc(ctx, bytes, stream) and goes back through
+ * free(ctx, ptr, bytes, stream), with the stream it was allocated for, once
+ * no queued work uses it (temporaries at the end of the build, the rest in
+ * smash_destroy).  For a caller whose own allocator (e.g. torch's caching
+ * allocator) should hold one device-memory budget.  alloc returns device
+ * memory aligned to at least 256 bytes, or NULL (the call then fails with
+ * SMASH_E_OOM); the hooks are called on the calling host thread and must not
+ * call back into the library; ctx must outlive the handle.  The temporary
+ * copy buffer of smash_export uses the device allocator directly. */
+typedef void *(*smash_alloc_fn)(void *ctx, size_t bytes, void *stream);
+typedef void (*smash_free_fn)(void *ctx, void *ptr, size_t bytes, void *stream);
+
 typedef struct smash_options {
   uint32_t struct_size; /* sizeof(smash_options) */
   double tau;
@@ -123,6 +138,9 @@ typedef struct smash_options {
   int32_t mv_xcd_run;
   int32_t coupling_mode;
   int64_t coupling_chunk;
+  smash_alloc_fn alloc; /* both NULL (default): the library's own pool */
+  smash_free_fn free;
+  void *alloc_ctx;
 } smash_options;
 
 int smash_default_options(smash_options *opt);

@@ -42,7 +42,34 @@ class Options(C.Structure):
                 ("batched", C.c_int32), ("timing", C.c_int32),
                 ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32),
                 ("mv_xcd_run", C.c_int32), ("coupling_mode", C.c_int32),
-                ("coupling_chunk", C.c_int64)]
+                ("coupling_chunk", C.c_int64), ("alloc", C.c_void_p), ("free", C.c_void_p),
+                ("alloc_ctx", C.c_void_p)]
+
+# smash_alloc_fn / smash_free_fn
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
+
+
+def torch_allocator_hooks(device=None):
+    """(alloc, free) hooks that take a handle's device memory from torch's
+    caching allocator on the stream the library names, so torch accounts for
+    it (torch.cuda.memory_allocated) and one memory budget covers both."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+
+    def _alloc(ctx, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+        except Exception:
+            return None
+
+    def _free(ctx, ptr, nbytes, stream):
+        try:
+            torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    return ALLOC_FN(_alloc), FREE_FN(_free)
 
 
 class Info(C.Structure):
@@ -183,14 +210,16 @@ class Smash:
     win.  graphs: replay repeated products from captured HIP graphs.
     coupling: "auto", "stored" or "evaluated" (SMASH_COUPLING_*): keep the
     coupling blocks, or evaluate them inside every product in chunks of
-    coupling_chunk entries (0: 256 MiB worth).
+    coupling_chunk entries (0: 256 MiB worth).  allocator: None (the
+    library's own pool), "torch" (torch's caching allocator, see
+    torch_allocator_hooks) or an (alloc, free) pair of ALLOC_FN / FREE_FN.
     """
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
                  root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
                  mv_xcd_run=None, graphs=True, tuned=True, nrhs_hint=16, coupling="auto",
-                 coupling_chunk=0, stream=None):
+                 coupling_chunk=0, allocator=None, stream=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -240,6 +269,11 @@ class Smash:
             raise ValueError("coupling must be 'auto', 'stored' or 'evaluated'")
         opt.coupling_mode = COUPLING[coupling]
         opt.coupling_chunk = int(coupling_chunk)
+        self._hooks = None
+        if allocator is not None:
+            self._hooks = torch_allocator_hooks() if allocator == "torch" else tuple(allocator)
+            opt.alloc = C.cast(self._hooks[0], C.c_void_p)
+            opt.free = C.cast(self._hooks[1], C.c_void_p)
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
         self.ny = x.shape[0] if y is None else y.shape[0]

@@ -55,8 +55,26 @@ inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 // the device's default memory pool (kept cached across builds), so a build
 // makes a handful of pool calls instead of one per array.  release() returns
 // every chunk.
+// Caller's allocator hooks of a handle (smash_options.alloc/.free).
+struct AllocHooks {
+  smash_alloc_fn alloc = nullptr;
+  smash_free_fn free = nullptr;
+  void *ctx = nullptr;
+};
+// The hooks of the handle whose call runs on this host thread (null: the
+// library's pool).  An arena takes them at its first allocation and keeps
+// them for its release.
+const AllocHooks *current_hooks();
+struct HooksScope {
+  const AllocHooks *prev;
+  explicit HooksScope(const AllocHooks *h);
+  ~HooksScope();
+};
+
 struct DeviceArena {
   hipStream_t stream = nullptr;
+  const AllocHooks *hooks = nullptr;  // set at the first allocation
+  bool bound = false;
   std::vector<std::pair<void *, size_t>> blocks;  // (base, size) of each chunk
   char *cur = nullptr;
   size_t left = 0;
@@ -201,6 +219,7 @@ struct Handle {
   int64_t total_swaps = 0;
   // stage temporaries, released once the build has synchronised its stream
   std::vector<DeviceArena> spent;
+  AllocHooks hooks;  // caller's allocator (alloc == null: the library's pool)
   double build_ms = 0;
   // product workspaces
   // captured products (options.graphs): one executable graph per argument set

@@ -38,14 +38,35 @@ bool take_cached(int dev, size_t n, void **p, size_t *sz) {
 }
 }  // namespace
 
+namespace {
+thread_local const AllocHooks *tl_hooks = nullptr;
+}
+const AllocHooks *current_hooks() { return tl_hooks; }
+HooksScope::HooksScope(const AllocHooks *h) : prev(tl_hooks) {
+  tl_hooks = (h && h->alloc && h->free) ? h : nullptr;
+}
+HooksScope::~HooksScope() { tl_hooks = prev; }
+
 void *DeviceArena::alloc(size_t n) {
   n = (n + 255) & ~(size_t)255;
+  if (!bound) {
+    hooks = current_hooks();
+    bound = true;
+  }
   if (n > left) {
     size_t sz = n > chunk ? n : chunk;
     void *p = nullptr;
     int dev = 0;
     (void)hipGetDevice(&dev);
-    if (!take_cached(dev, sz, &p, &sz)) {
+    if (hooks) {
+      p = hooks->alloc(hooks->ctx, sz, (void *)stream);
+      if (!p) throw Error{SMASH_E_OOM, "allocator hook returned NULL for " + std::to_string(sz) +
+                                           " bytes"};
+      if ((uintptr_t)p & 255) {
+        hooks->free(hooks->ctx, p, sz, (void *)stream);
+        throw Error{SMASH_E_INVALID_ARG, "allocator hook returned memory not aligned to 256 bytes"};
+      }
+    } else if (!take_cached(dev, sz, &p, &sz)) {
       hipError_t e = hipMallocAsync(&p, sz, stream);
       if (e != hipSuccess || !p) {
         (void)hipGetLastError();
@@ -68,6 +89,10 @@ void DeviceArena::release(bool idle) {
   (void)hipGetDevice(&dev);
   ChunkCache &c = chunk_cache();
   for (auto &b : blocks) {
+    if (hooks) {
+      hooks->free(hooks->ctx, b.first, b.second, (void *)stream);
+      continue;
+    }
     bool kept = false;
     if (idle) {
       std::lock_guard<std::mutex> lk(c.mu);

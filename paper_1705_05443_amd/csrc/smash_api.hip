@@ -121,11 +121,17 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
       opt.coupling_mode != SMASH_COUPLING_EVALUATED)
     return fail(SMASH_E_INVALID_ARG, "coupling_mode must be SMASH_COUPLING_AUTO, _STORED or _EVALUATED");
   if (opt.coupling_chunk < 0) return fail(SMASH_E_INVALID_ARG, "coupling_chunk must be >= 0");
+  if ((opt.alloc == nullptr) != (opt.free == nullptr))
+    return fail(SMASH_E_INVALID_ARG, "set both allocator hooks or neither");
 
   Handle *h = nullptr;
   auto t0 = std::chrono::steady_clock::now();
   try {
     h = new Handle();
+    h->hooks.alloc = opt.alloc;
+    h->hooks.free = opt.free;
+    h->hooks.ctx = opt.alloc_ctx;
+    HooksScope hs(&h->hooks);
     h->stream = (hipStream_t)stream;
     h->mem.stream = h->stream;
     h->ws_mem.stream = h->stream;
@@ -223,6 +229,7 @@ extern "C" int smash_matvec(smash_handle hv, const void *X, int64_t ldx, int32_t
   if (dtype != (h->apply_prec == SMASH_F64 ? SMASH_F64 : SMASH_F32))
     return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's vector precision");
   try {
+    HooksScope hs(&h->hooks);
     run_matvec(*h, X, ldx, nrhs, Y, ldy, (hipStream_t)stream);
     return SMASH_OK;
   } catch (const Error &e) {
@@ -252,8 +259,10 @@ extern "C" int smash_matvec_batched(int32_t count, const smash_handle *hs,
       return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's vector precision" + at);
   }
   try {
-    for (int32_t c = 0; c < count; c++)
+    for (int32_t c = 0; c < count; c++) {
+      HooksScope scope(&((Handle *)hs[c])->hooks);
       run_matvec(*(Handle *)hs[c], Xs[c], ldx[c], nrhs[c], Ys[c], ldy[c], (hipStream_t)stream);
+    }
     return SMASH_OK;
   } catch (const Error &e) {
     return fail(e.code, e.msg);

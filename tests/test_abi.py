@@ -106,3 +106,17 @@ def test_batched_products_reject_bad_arguments_before_running():
     assert b"entry 0" in L.smash_last_error()
     assert L.smash_matvec_batched(1, None, args["xs"], args["ldx"], args["nr"], args["ys"],
                                   args["ldy"], 0, None) == -1
+
+
+def test_allocator_hooks_must_come_in_pairs():
+    L = api.lib()
+    opt = api.Options()
+    L.smash_default_options(C.byref(opt))
+    assert opt.alloc is None and opt.free is None and opt.alloc_ctx is None
+    hook = api.ALLOC_FN(lambda ctx, n, s: None)
+    opt.alloc = C.cast(hook, C.c_void_p)
+    h = C.c_void_p()
+    dummy = C.c_void_p(16)
+    assert L.smash_build(dummy, 10, 2, 0, 8, 4, 1, 1e-6, C.byref(opt), None, C.byref(h)) == -1
+    assert b"allocator hooks" in L.smash_last_error()
+    assert not h.value

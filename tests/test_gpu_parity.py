@@ -582,3 +582,43 @@ def test_batched_products_equal_single_ones():
             assert np.array_equal(a, b.cpu().numpy())
     for h in hs:
         h.close()
+
+
+def test_allocator_hooks_take_every_device_allocation():
+    """With torch's caching allocator as the hooks, a handle's memory shows in
+    torch's accounting while it lives, every allocation is given back at
+    destroy, and the product equals the one of a handle on the library's own
+    pool bit for bit."""
+    import ctypes as C
+    import torch
+    x = W.uniform(5000, 2, 41)
+    kw = dict(kernel="log_r", leaf=64, order=8, adm="strong", tol=1e-8, tau=0.7,
+              root=((0.0, 0.0), 1.0))
+    live = {}
+    talloc, tfree = api.torch_allocator_hooks()
+
+    def _alloc(ctx, n, s):
+        p = talloc(ctx, n, s)
+        if p:
+            live[p] = n
+        return p
+
+    def _free(ctx, p, n, s):
+        assert live.pop(p) == n
+        tfree(ctx, p, n, s)
+
+    hooks = (api.ALLOC_FN(_alloc), api.FREE_FN(_free))
+    q = torch.from_numpy(np.random.default_rng(2).standard_normal((5000, 4))).cuda()
+    print("hooks build", flush=True)
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    h = api.Smash(dev(x), allocator=hooks, **kw)
+    held = sum(live.values())
+    assert held >= h.info()["device_bytes"] > 0
+    z = h.matvec(q).cpu().numpy()
+    assert torch.cuda.memory_allocated() - before >= held
+    h.close()
+    assert not live  # every allocation went back through the hook
+    g = api.Smash(dev(x), **kw)
+    assert np.array_equal(g.matvec(q).cpu().numpy(), z)
+    g.close()
