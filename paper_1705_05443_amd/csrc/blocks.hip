@@ -281,17 +281,15 @@ static void side_stream(int dev, hipStream_t &st, hipEvent_t &ready, hipEvent_t 
 
 // Near-field blocks (eqs. (3.15), (3.20)): they need only the tree and L^-,
 // so they are evaluated on a second stream while the generators are built
-// (whose upper levels occupy few compute units).
-void build_near_blocks(Handle &h) {
+// (whose upper levels occupy few compute units).  near_offsets scans their
+// sizes; near_launch allocates them (given their total) and starts the
+// evaluation.
+void near_offsets(Handle &h) {
   hipStream_t s = h.stream;
   DeviceArena tmp;
   tmp.stream = s;
   try {
     const bool bf = h.apply_prec == SMASH_BF16;
-    size_t es = h.apply_prec == SMASH_F64 ? sizeof(double)
-                : bf                      ? sizeof(unsigned short)
-                                          : sizeof(float);
-    bool f32math = h.eval_prec == SMASH_F32;
     int64_t *ncnt = tmp.alloc_n<int64_t>(h.nLm);
     h.nboff = h.mem.alloc_n<int64_t>(h.nLm + 1);
     if (h.nLm > 0) {
@@ -300,46 +298,70 @@ void build_near_blocks(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     scan_i64(ncnt, h.nboff, h.nLm, nullptr, s, tmp);
-    h.n_entries = read_one(s, h.nboff + h.nLm);
-    h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
     int dev = 0;
     SMASH_HIP(hipGetDevice(&dev));
     hipEvent_t ready;
     side_stream(dev, h.side, ready, h.side_done);
-    // everything above (the lists, offsets and Bn) is ordered before the side work
-    SMASH_HIP(hipEventRecord(ready, s));
-    SMASH_HIP(hipStreamWaitEvent(h.side, ready, 0));
-    EvalArgs en{};
-    en.d = h.d;
-    en.kid = h.kid;
-    en.diag = h.diag;
-    en.Xp = h.Xp;
-    en.Yp = h.Yp;
-    en.npairs = h.nLm;
-    en.pi = h.Lmi;
-    en.pj = h.Lmj;
-    en.off = h.nboff;
-    en.rbeg32 = h.xb;
-    en.rend32 = h.xe;
-    en.cbeg32 = h.yb;
-    en.cend32 = h.ye;
-    {
-      PhaseTimer pt(h, SMASH_PHASE_BLOCKS, h.side);
-      if (h.apply_prec == SMASH_F64)
-        eval_launch(en, (double *)h.Bn, f32math, h.side);
-      else if (bf)
-        eval_launch_bf16(en, (unsigned short *)h.Bn, f32math, h.side);
-      else
-        eval_launch(en, (float *)h.Bn, f32math, h.side);
-    }
-    SMASH_HIP(hipEventRecord(h.side_done, h.side));
     defer_release(h, tmp);
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    if (h.side) (void)hipStreamSynchronize(h.side);
     tmp.release();
     throw;
   }
+}
+
+void near_launch(Handle &h, int64_t n_entries) {
+  hipStream_t s = h.stream;
+  const bool bf = h.apply_prec == SMASH_BF16;
+  size_t es = h.apply_prec == SMASH_F64 ? sizeof(double)
+              : bf                      ? sizeof(unsigned short)
+                                        : sizeof(float);
+  bool f32math = h.eval_prec == SMASH_F32;
+  h.n_entries = n_entries;
+  h.Bn = h.mem.alloc(es * (size_t)(h.n_entries > 0 ? h.n_entries : 1));
+  int dev = 0;
+  SMASH_HIP(hipGetDevice(&dev));
+  hipEvent_t ready;
+  side_stream(dev, h.side, ready, h.side_done);
+  // everything above (the lists, offsets and Bn) is ordered before the side work
+  SMASH_HIP(hipEventRecord(ready, s));
+  SMASH_HIP(hipStreamWaitEvent(h.side, ready, 0));
+  EvalArgs en{};
+  en.d = h.d;
+  en.kid = h.kid;
+  en.diag = h.diag;
+  en.Xp = h.Xp;
+  en.Yp = h.Yp;
+  en.npairs = h.nLm;
+  en.pi = h.Lmi;
+  en.pj = h.Lmj;
+  en.off = h.nboff;
+  en.rbeg32 = h.xb;
+  en.rend32 = h.xe;
+  en.cbeg32 = h.yb;
+  en.cend32 = h.ye;
+  {
+    PhaseTimer pt(h, SMASH_PHASE_BLOCKS, h.side);
+    if (h.apply_prec == SMASH_F64)
+      eval_launch(en, (double *)h.Bn, f32math, h.side);
+    else if (bf)
+      eval_launch_bf16(en, (unsigned short *)h.Bn, f32math, h.side);
+    else
+      eval_launch(en, (float *)h.Bn, f32math, h.side);
+  }
+  SMASH_HIP(hipEventRecord(h.side_done, h.side));
+}
+
+void coupling_offsets(Handle &h, DeviceArena &tmp) {
+  hipStream_t s = h.stream;
+  int64_t *cnt = tmp.alloc_n<int64_t>(h.nL);
+  h.boff = h.mem.alloc_n<int64_t>(h.nL + 1);
+  if (h.nL > 0) {
+    k_block_sizes<<<ceil_div(h.nL, 256), 256, 0, s>>>(h.nL, h.Li, h.Lj, h.row.k, h.col->k,
+                                                      h.apply_prec == SMASH_BF16 ? 1 : 0, cnt);
+    SMASH_CHECK_LAUNCH();
+  }
+  scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
 }
 
 void build_blocks(Handle &h) {
@@ -353,16 +375,10 @@ void build_blocks(Handle &h) {
                 : bf                      ? sizeof(unsigned short)
                                           : sizeof(float);
     bool f32math = h.eval_prec == SMASH_F32;
-    // coupling
-    int64_t *cnt = tmp.alloc_n<int64_t>(h.nL);
-    h.boff = h.mem.alloc_n<int64_t>(h.nL + 1);
-    if (h.nL > 0) {
-      k_block_sizes<<<ceil_div(h.nL, 256), 256, 0, s>>>(h.nL, h.Li, h.Lj, R.k, C.k, bf ? 1 : 0,
-                                                        cnt);
-      SMASH_CHECK_LAUNCH();
-    }
-    scan_i64(cnt, h.boff, h.nL, nullptr, s, tmp);
-    h.b_entries = read_one(s, h.boff + h.nL);
+    (void)R;
+    (void)C;
+    // coupling: offsets and total were set with the generators' last host
+    // read (coupling_offsets)
     // coupling blocks stored, or evaluated by each product in chunks
     bool evaluated = h.coupling_mode == SMASH_COUPLING_EVALUATED;
     if (h.coupling_mode == SMASH_COUPLING_AUTO) {

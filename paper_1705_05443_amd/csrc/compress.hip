@@ -1252,6 +1252,14 @@ __global__ void k_leaf_init(int nnodes, const int *nchild, const int *xb, const 
   }
 }
 
+// Leaf count (nodes without children) into *cnt (zeroed before).
+__global__ void k_count_leaves(int nnodes, const int *nchild, int *cnt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool leaf = i < nnodes && nchild[i] == 0;
+  const uint64_t b = __ballot(leaf);
+  if ((threadIdx.x & (WAVE - 1)) == 0 && b) atomicAdd(cnt, (int)__popcll(b));
+}
+
 __global__ void k_level_prep(PrepArgs A) {
   int i = A.nb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.ne) return;
@@ -1464,10 +1472,12 @@ void build_generators(Handle &h) {
       SMASH_CHECK_LAUNCH();
     }
     int *dmax = keep.alloc_n<int>(2);
-    int *dsw = keep.alloc_n<int>(2);
+    int *dsw = keep.alloc_n<int>(3);  // swaps, cap flag, leaves
     int64_t *dslots = keep.alloc_n<int64_t>(2);  // running slot count per side
     for (size_t q = 0; q < sides.size(); q++) set_i64(dslots + q, sides[q].S->nslots, s);
-    SMASH_HIP(hipMemsetAsync(dsw, 0, 2 * sizeof(int), s));
+    SMASH_HIP(hipMemsetAsync(dsw, 0, 3 * sizeof(int), s));
+    k_count_leaves<<<ceil_div(nn, 256), 256, 0, s>>>(nn, h.nchild, dsw + 2);
+    SMASH_CHECK_LAUNCH();
     int dev_cus = 256, dev_lds = 64 * 1024;
     if (hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, h.device) !=
         hipSuccess)
@@ -1674,11 +1684,20 @@ void build_generators(Handle &h) {
     }
     int herr[2] = {0, 0};
     {
-      const int64_t *pin =
-          pick_words(s, {{dsw, 4}, {dsw + 1, 4}, {dslots, 8}, {dslots + 1, 8}});
+      // the coupling blocks' sizes and offsets (their total comes with the
+      // same host read)
+      coupling_offsets(h, tmp);
+      const int64_t *pin = pick_words(s, {{dsw, 4},
+                                          {dsw + 1, 4},
+                                          {dslots, 8},
+                                          {dslots + 1, 8},
+                                          {dsw + 2, 4},
+                                          {h.boff + h.nL, 8}});
       herr[0] = (int)pin[0];
       herr[1] = (int)pin[1];
       for (size_t q = 0; q < sides.size(); q++) sides[q].S->nslots = pin[2 + q];
+      h.nleaves = (int)pin[4];
+      h.b_entries = pin[5];
     }
     if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
     h.total_swaps = herr[0];

@@ -279,8 +279,14 @@ void resolve_timers(Handle &h);
 void build_tree(Handle &h, const double *x, const double *y);
 void build_pairs(Handle &h);
 void build_generators(Handle &h);
-void build_near_blocks(Handle &h);  // launches the near-field blocks on h.side
-void build_blocks(Handle &h);       // coupling blocks; then waits for the near ones
+// Near-field blocks: sizes and offsets (h.nboff, nLm + 1 entries), then,
+// given their total, the allocation and the evaluation on h.side.
+void near_offsets(Handle &h);
+void near_launch(Handle &h, int64_t n_entries);
+void build_blocks(Handle &h);
+// Sizes and offsets of the coupling blocks (h.boff, nL + 1 entries) from the
+// final ranks of both sides; the total is read with the next host read.
+void coupling_offsets(Handle &h, DeviceArena &tmp);       // coupling blocks; then waits for the near ones
 // coupling blocks of pairs [p0, p1) written at base + boff[p] (apply
 // precision, the stored layout) on stream s
 void eval_coupling_range(Handle &h, int64_t p0, int64_t p1, void *base, hipStream_t s);

@@ -177,17 +177,15 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
       PhaseTimer pt(*h, SMASH_PHASE_PAIRS, h->stream);
       build_pairs(*h);
     }
-    build_near_blocks(*h);
+    // near-field blocks on the second stream from here on (they overlap the
+    // first levels' compression; started any later, they compete with it)
+    near_offsets(*h);
+    near_launch(*h, read_one(h->stream, h->nboff + h->nLm));
     build_generators(*h);
     build_blocks(*h);  // ends with the stream synchronised
     for (auto &a : h->spent) a.release();
     h->spent.clear();
-    // leaf count and statistics
-    std::vector<int> nch(h->nnodes);
-    SMASH_HIP(hipMemcpy(nch.data(), h->nchild, sizeof(int) * h->nnodes, hipMemcpyDeviceToHost));
-    h->nleaves = 0;
-    for (int v : nch) h->nleaves += v == 0;
-    SMASH_HIP(hipStreamSynchronize(h->stream));
+    // (the leaf count came with the generators' last host read)
     h->build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = (smash_handle)h;
