@@ -1284,6 +1284,89 @@ __global__ void k_level_prep(PrepArgs A) {
   atomicMax(A.mmax, m);
 }
 
+// One workgroup for a whole level of at most LV_NT * LV_PER nodes: the grid
+// sizes and G capacities (as k_level_prep), their exclusive scans into selo
+// and go (relative to the level), and the totals for the host read -- one
+// launch instead of a prep kernel, two scans and two offset writes.
+constexpr int LV_NT = 1024, LV_PER = 4;
+__device__ __forceinline__ int64_t level_cap(int64_t mm, int c0, int hss) {
+  if (hss) return mm * mm / 4;
+  return (2 * c0 >= mm) ? mm * mm / 4 : (mm - c0) * c0;
+}
+__global__ void __launch_bounds__(LV_NT) k_level_prep1(PrepArgs A, int64_t *selo, int64_t *go,
+                                                       int64_t *tot) {
+  __shared__ int64_t lds[LV_NT / WAVE + 1];
+  const int i0 = A.nb + threadIdx.x * LV_PER;
+  int64_t mv[LV_PER], cv[LV_PER], sm = 0, sg = 0;
+  int mx = 0;
+#pragma unroll
+  for (int u = 0; u < LV_PER; u++) {
+    const int i = i0 + u;
+    mv[u] = cv[u] = 0;
+    if (i < A.ne) {
+      int m;
+      if (A.nchild[i] > 0) {
+        const int fc = A.first_child[i];
+        m = 0;
+        for (int c = 0; c < A.nchild[i]; c++) m += A.k[fc + c];
+        A.m[i] = m;
+        A.gbeg[i] = A.hbeg[fc];
+      } else {
+        m = A.m[i];
+      }
+      mx = max(mx, m);
+      mv[u] = m;
+      cv[u] = level_cap(m, A.c0, A.hss);
+    }
+    sm += mv[u];
+    sg += cv[u];
+  }
+  int64_t tm, tg;
+  int64_t om = block_excl_scan_i64<LV_NT / WAVE>(sm, &tm, lds);
+  int64_t og = block_excl_scan_i64<LV_NT / WAVE>(sg, &tg, lds);
+#pragma unroll
+  for (int u = 0; u < LV_PER; u++) {
+    const int i = i0 + u;
+    if (i < A.ne) {
+      selo[i] = om;
+      go[i] = og;
+    }
+    om += mv[u];
+    og += cv[u];
+  }
+  if (mx > 0) atomicMax(A.mmax, mx);
+  if (threadIdx.x == 0) {
+    tot[0] = tm;
+    tot[1] = tg;
+  }
+}
+
+// One workgroup for a whole level (as above): the skeleton slots of the
+// level's nodes, hbeg = running slot count + exclusive scan of k, and the
+// running count advanced by the level's total (kept on the device).
+__global__ void __launch_bounds__(LV_NT) k_level_slots1(int nb, int ne, const int *k,
+                                                        int64_t *hbeg, int64_t *run) {
+  __shared__ int64_t lds[LV_NT / WAVE + 1];
+  const int i0 = nb + threadIdx.x * LV_PER;
+  int64_t kv[LV_PER], sk = 0;
+#pragma unroll
+  for (int u = 0; u < LV_PER; u++) {
+    const int i = i0 + u;
+    kv[u] = i < ne ? k[i] : 0;
+    sk += kv[u];
+  }
+  int64_t tk;
+  const int64_t base = *run;
+  int64_t o = base + block_excl_scan_i64<LV_NT / WAVE>(sk, &tk, lds);
+#pragma unroll
+  for (int u = 0; u < LV_PER; u++) {
+    const int i = i0 + u;
+    if (i < ne) hbeg[i] = o;
+    o += kv[u];
+  }
+  if (threadIdx.x == 0) *run = base + tk;
+}
+
 __global__ void k_kcopy(int nb, int ne, const int *k, int64_t *out) {
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
   if (i < ne) out[i - nb] = k[i];
@@ -1495,16 +1578,28 @@ void build_generators(Handle &h) {
         SMASH_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
         PrepArgs pa{nb, ne, h.nchild, h.first_child, sc.xb, sc.xe, S.m, S.gbeg, S.k, S.hbeg, c0,
                     hss ? 1 : 0, sc.cm, sc.cg, dmax};
-        k_level_prep<<<ceil_div(nl, 256), 256, 0, s>>>(pa);
-        SMASH_CHECK_LAUNCH();
-        int64_t *o1 = tmp.alloc_n<int64_t>(nl + 1), *o2 = tmp.alloc_n<int64_t>(nl + 1);
-        scan_i64(sc.cm, o1, nl, nullptr, s, tmp);
-        scan_i64(sc.cg, o2, nl, nullptr, s, tmp);
-        k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o1, S.selo);
-        SMASH_CHECK_LAUNCH();
-        k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o2, S.go);
-        SMASH_CHECK_LAUNCH();
-        const int64_t *pin = pick_words(s, {{o1 + nl, 8}, {o2 + nl, 8}, {dmax, 4}});
+        const int64_t *tot_m, *tot_g;
+        if (nl <= LV_NT * LV_PER) {
+          // the whole level in one workgroup
+          int64_t *tot = tmp.alloc_n<int64_t>(2);
+          k_level_prep1<<<1, LV_NT, 0, s>>>(pa, S.selo, S.go, tot);
+          SMASH_CHECK_LAUNCH();
+          tot_m = tot;
+          tot_g = tot + 1;
+        } else {
+          k_level_prep<<<ceil_div(nl, 256), 256, 0, s>>>(pa);
+          SMASH_CHECK_LAUNCH();
+          int64_t *o1 = tmp.alloc_n<int64_t>(nl + 1), *o2 = tmp.alloc_n<int64_t>(nl + 1);
+          scan_i64(sc.cm, o1, nl, nullptr, s, tmp);
+          scan_i64(sc.cg, o2, nl, nullptr, s, tmp);
+          k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o1, S.selo);
+          SMASH_CHECK_LAUNCH();
+          k_set_rel<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, o2, S.go);
+          SMASH_CHECK_LAUNCH();
+          tot_m = o1 + nl;
+          tot_g = o2 + nl;
+        }
+        const int64_t *pin = pick_words(s, {{tot_m, 8}, {tot_g, 8}, {dmax, 4}});
         const int64_t hv[2] = {pin[0], pin[1]};
         const int mx = (int)pin[2];
         sc.mmax = mx;
@@ -1661,13 +1756,18 @@ void build_generators(Handle &h) {
       for (size_t q = 0; q < sides.size(); q++) {
         SideCtx &sc = sides[q];
         Side &S = *sc.S;
-        int64_t *ck = tmp.alloc_n<int64_t>(nl), *ok = tmp.alloc_n<int64_t>(nl + 1);
-        k_kcopy<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.k, ck);
-        SMASH_CHECK_LAUNCH();
-        scan_i64(ck, ok, nl, dslots + q, s, tmp);
-        copy_i64(dslots + q, ok + nl, s);
-        k_set_hbeg<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, ok, S.hbeg);
-        SMASH_CHECK_LAUNCH();
+        if (nl <= LV_NT * LV_PER) {
+          k_level_slots1<<<1, LV_NT, 0, s>>>(nb, ne, S.k, S.hbeg, dslots + q);
+          SMASH_CHECK_LAUNCH();
+        } else {
+          int64_t *ck = tmp.alloc_n<int64_t>(nl), *ok = tmp.alloc_n<int64_t>(nl + 1);
+          k_kcopy<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.k, ck);
+          SMASH_CHECK_LAUNCH();
+          scan_i64(ck, ok, nl, dslots + q, s, tmp);
+          copy_i64(dslots + q, ok + nl, s);
+          k_set_hbeg<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, ok, S.hbeg);
+          SMASH_CHECK_LAUNCH();
+        }
         {
           PhaseTimer pt(h, SMASH_PHASE_SLOTS, s);
           k_slot_ids<<<nl, 64, 0, s>>>(nb, ne, S.k, S.hbeg, S.gbeg, S.selo, S.lv[l].sel,
