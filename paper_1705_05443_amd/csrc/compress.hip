@@ -53,6 +53,7 @@ struct IdArgs {
   int *swaps;    // total swap count (atomic)
   int *err;      // set to 1 when the swap cap is hit
   int gt_out;    // k_compr_w: write G^T (k x (m-k) row-major) instead of G
+  double *G2_out;  // k_compr_w: also the other orientation there (null: not)
 };
 
 // ---- lane exchanges (DPP) ------------------------------------------------
@@ -950,6 +951,9 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
           const int64_t row = J * cb + j - exj[j];
           double *Gr = A.G_out + A.go[i] + (A.gt_out ? row : row * k);
           const int64_t cs = A.gt_out ? (int64_t)nr : 1;
+          // the other orientation as well (no transposition pass after)
+          double *G2 = A.G2_out ? A.G2_out + A.go[i] + (A.gt_out ? row * k : row) : nullptr;
+          const int64_t cs2 = A.gt_out ? 1 : (int64_t)nr;
           const int base = (pa[j] - k) * k;
 #pragma unroll
           for (int u = 0; u < RL; u++) {
@@ -959,6 +963,7 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
               const double r2 = col[j][u] * col[j][u] + gw * gw;
               am = amax_pick(am, ArgMax{r2, base + ii});
               Gr[srank[ii] * cs] = col[j][u];
+              if (G2) G2[srank[ii] * cs2] = col[j][u];
             }
           }
         }
@@ -1423,20 +1428,6 @@ __global__ void k_transpose_G(int nb, int ne, const int *m, const int *k, const 
   }
 }
 
-// G^T k x (m-k)  ->  G (m-k) x k, one workgroup per node
-__global__ void k_transpose_Gt(int nb, int ne, const int *m, const int *k, const int64_t *go,
-                               const double *Gt, double *G) {
-  int i = nb + blockIdx.x;
-  if (i >= ne) return;
-  const int kk = k[i], nr = m[i] - kk;
-  const double *src = Gt + go[i];
-  double *dst = G + go[i];
-  for (int e = threadIdx.x; e < nr * kk; e += blockDim.x) {
-    int a = e / kk, t = e - a * kk;
-    dst[e] = src[(int64_t)t * nr + a];
-  }
-}
-
 // BF16 copies of G for the matrix-core product (layouts in LevelSide)
 __global__ void k_gb_sizes(int nb, int ne, const int *m, const int *k, int64_t *cu, int64_t *cd) {
   int i = nb + blockIdx.x * blockDim.x + threadIdx.x;
@@ -1710,7 +1701,10 @@ void build_generators(Handle &h) {
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1,
                   reg ? 1 : 0};
-        if (reg) ia.G_out = L.Gt;  // the register kernel writes G^T
+        if (reg) {
+          ia.G_out = L.Gt;  // the register kernel writes G^T, and G
+          ia.G2_out = L.G;
+        }
         sc.gt_first = reg;
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
         auto launch = [&](int grid) {
@@ -1746,10 +1740,8 @@ void build_generators(Handle &h) {
       for (auto &sc : sides) {
         Side &S = *sc.S;
         LevelSide &L = S.lv[l];
-        if (sc.gt_first)
-          k_transpose_Gt<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.Gt, L.G);
-        else
-          k_transpose_G<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, L.Gt);
+        if (sc.gt_first) continue;  // the register kernel wrote both
+        k_transpose_G<<<nl, 256, 0, s>>>(nb, ne, S.m, S.k, S.go, L.G, L.Gt);
         SMASH_CHECK_LAUNCH();
       }
       // (d) skeleton slots of this level (capacity reserved up front)
