@@ -1301,6 +1301,8 @@ __device__ __forceinline__ int64_t level_cap(int64_t mm, int c0, int hss) {
 __global__ void __launch_bounds__(LV_NT) k_level_prep1(PrepArgs A, int64_t *selo, int64_t *go,
                                                        int64_t *tot) {
   __shared__ int64_t lds[LV_NT / WAVE + 1];
+  __shared__ int smax;
+  if (threadIdx.x == 0) smax = 0;
   const int i0 = A.nb + threadIdx.x * LV_PER;
   int64_t mv[LV_PER], cv[LV_PER], sm = 0, sg = 0;
   int mx = 0;
@@ -1339,10 +1341,12 @@ __global__ void __launch_bounds__(LV_NT) k_level_prep1(PrepArgs A, int64_t *selo
     om += mv[u];
     og += cv[u];
   }
-  if (mx > 0) atomicMax(A.mmax, mx);
+  if (mx > 0) atomicMax(&smax, mx);  // smax was set before the scans' barriers
+  __syncthreads();
   if (threadIdx.x == 0) {
     tot[0] = tm;
     tot[1] = tg;
+    *A.mmax = smax;  // the level's largest grid (no zeroing needed before)
   }
 }
 
@@ -1464,6 +1468,14 @@ __global__ void k_to_f32(const double *in, float *out, int64_t n) {
 }
 
 // ------------------------------------------------------------------------
+__global__ void k_zero_side(int nn, int *m, int *k, int *ks, int64_t *hbeg, int64_t *selo,
+                            int64_t *go) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  m[i] = k[i] = ks[i] = 0;
+  hbeg[i] = selo[i] = go[i] = 0;
+}
+
 static void alloc_side(Handle &h, Side &S) {
   int nn = h.nnodes;
   S.m = h.mem.alloc_n<int>(nn);
@@ -1473,12 +1485,8 @@ static void alloc_side(Handle &h, Side &S) {
   S.hbeg = h.mem.alloc_n<int64_t>(nn);
   S.selo = h.mem.alloc_n<int64_t>(nn);
   S.go = h.mem.alloc_n<int64_t>(nn);
-  SMASH_HIP(hipMemsetAsync(S.m, 0, sizeof(int) * nn, h.stream));
-  SMASH_HIP(hipMemsetAsync(S.k, 0, sizeof(int) * nn, h.stream));
-  SMASH_HIP(hipMemsetAsync(S.ks, 0, sizeof(int) * nn, h.stream));
-  SMASH_HIP(hipMemsetAsync(S.hbeg, 0, sizeof(int64_t) * nn, h.stream));
-  SMASH_HIP(hipMemsetAsync(S.selo, 0, sizeof(int64_t) * nn, h.stream));
-  SMASH_HIP(hipMemsetAsync(S.go, 0, sizeof(int64_t) * nn, h.stream));
+  k_zero_side<<<ceil_div(nn, 256), 256, 0, h.stream>>>(nn, S.m, S.k, S.ks, S.hbeg, S.selo, S.go);
+  SMASH_CHECK_LAUNCH();
   S.lv.assign(h.nlevels + 1, LevelSide{});
 }
 
@@ -1566,7 +1574,6 @@ void build_generators(Handle &h) {
         Side &S = *sc.S;
         sc.cm = tmp.alloc_n<int64_t>(nl);
         sc.cg = tmp.alloc_n<int64_t>(nl);
-        SMASH_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
         PrepArgs pa{nb, ne, h.nchild, h.first_child, sc.xb, sc.xe, S.m, S.gbeg, S.k, S.hbeg, c0,
                     hss ? 1 : 0, sc.cm, sc.cg, dmax};
         const int64_t *tot_m, *tot_g;
@@ -1578,6 +1585,7 @@ void build_generators(Handle &h) {
           tot_m = tot;
           tot_g = tot + 1;
         } else {
+          SMASH_HIP(hipMemsetAsync(dmax, 0, sizeof(int), s));
           k_level_prep<<<ceil_div(nl, 256), 256, 0, s>>>(pa);
           SMASH_CHECK_LAUNCH();
           int64_t *o1 = tmp.alloc_n<int64_t>(nl + 1), *o2 = tmp.alloc_n<int64_t>(nl + 1);

@@ -373,8 +373,15 @@ void build_tree(Handle &h, const double *x, const double *y) {
       radix_sort_u64(k, perm, k2, v2, n, keybits, s, tmp, lo_bit);
     };
     int *deeper = tmp.alloc_n<int>(1);
+    // first capacity from the usual node count (a tree of n points in
+    // leaves of at most `leaf` holds about 2.5 n / leaf nodes), so that
+    // regrowth (a copy of every node array) is the exception
     int cap = 0;
-    grow_nodes(h, cap, 1024);
+    {
+      const int64_t np = std::max(h.nx, h.ny);
+      const int64_t guess = 4 * (np / std::max(1, h.leaf) + 1) * (h.bpl > 1 ? 2 : 1);
+      grow_nodes(h, cap, (int)std::min<int64_t>(std::max<int64_t>(1024, guess), 1 << 24));
+    }
     NodeArrays N;
     auto refresh = [&]() {
       N = NodeArrays{h.level, h.parent, h.first_child, h.nchild, h.xb, h.xe, h.yb, h.ye,
