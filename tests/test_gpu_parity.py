@@ -622,3 +622,25 @@ def test_allocator_hooks_take_every_device_allocation():
     g = api.Smash(dev(x), **kw)
     assert np.array_equal(g.matvec(q).cpu().numpy(), z)
     g.close()
+
+
+def test_levels_wider_than_one_workgroup():
+    """Tree levels of more than 4096 nodes take the multi-workgroup form of
+    the level bookkeeping (sizes, capacities, slot offsets) instead of the
+    one-workgroup form; both must give the oracle's ranks and product."""
+    x = W.uniform(80000, 2, 51)
+    kw = dict(kernel="log_r", leaf=8, order=4, adm="strong", tol=1e-6, tau=0.7,
+              root=((0.0, 0.0), 1.0))
+    o = O.Oracle(x, None, **_oracle_kwargs(kw))
+    lv = o.export(O.EX_LEVELS)
+    assert np.max(np.diff(lv)) > 4096 >= np.min(np.diff(lv))  # both forms run
+    print("level sizes", np.diff(lv).tolist(), flush=True)
+    g = api.Smash(dev(x), **kw)
+    assert np.array_equal(o.export(O.EX_LEVELS), g.export("levels"))
+    ro, rg = o.ranks(), g.export("ranks").reshape(-1, 6)
+    assert np.array_equal(ro[:, :2], rg[:, :2])
+    q = W.rhs(g.ny, 3, seed=4)
+    z_o = o.matvec(q)
+    z_g = g.matvec(dev(q)).cpu().numpy()
+    g.close()
+    assert relerr(z_g, z_o) < 1e-10
