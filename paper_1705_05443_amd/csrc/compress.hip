@@ -164,6 +164,19 @@ __device__ inline ArgMax wave_argmax(ArgMax x) {
   return ArgMax{v, argmax_index<WAVE>(x, v, true)};
 }
 
+// The same when every group of four consecutive lanes holds one candidate
+// (the same value and index in its four lanes): the two exchanges inside the
+// quads are skipped and the index is taken among the groups' first lanes.
+__device__ inline ArgMax wave_argmax_quad(ArgMax x) {
+  double v = x.v;
+  v = fmax(v, perm_f64<0x141>(v));      // row_half_mirror (lane i and 7 - i: other quads)
+  v = fmax(v, perm_f64<0x140>(v));      // row_mirror
+  v = fmax(v, dpp_f64<0x142, 0xA>(v));  // row_bcast:15 into rows 1, 3
+  v = fmax(v, dpp_f64<0x143, 0xC>(v));  // row_bcast:31 into rows 2, 3
+  v = readlane_f64(v, WAVE - 1);
+  return ArgMax{v, argmax_index<WAVE>(x, v, (threadIdx.x & 3) == 0)};
+}
+
 // the same over the first NL (<= 16) lanes (the per-wave results of a block)
 template <int NL>
 __device__ inline ArgMax lanes_argmax(ArgMax x) {
@@ -722,19 +735,20 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
             stop = true;
             break;
           }
+          // every lane of a group holds its group's candidate (norms and
+          // positions are the same in the group's lanes)
           ArgMax am{-1.0, -1};
-          if (h == 0) {
 #pragma unroll
-            for (int j = 0; j < J; j++)
-              if (act[j] && (pivoting ? pa[j] >= t : pa[j] == t))
-                am = amax_pick(am, ArgMax{nrm[j], pa[j]});
-          }
+          for (int j = 0; j < J; j++)
+            if (act[j] && (pivoting ? pa[j] >= t : pa[j] == t))
+              am = amax_pick(am, ArgMax{nrm[j], pa[j]});
           // each wavefront's own winner copies its column into the wave's
           // slot before the one barrier of the step, so the pivot column is
           // in LDS as soon as the block arg-max is known.  Slots and arg-max
           // entries alternate by step parity: a half is rewritten two steps
           // after it was read, with the barrier of the step in between.
-          const ArgMax wa = wave_argmax(am);
+          static_assert(LPC == 4, "the quad arg-max needs groups of four lanes");
+          const ArgMax wa = wave_argmax_quad(am);
           double *const slots = pv + (t & 1) * (NW * SL);
           ArgMax *const ah = ared2 + (t & 1) * NW;
 #pragma unroll
