@@ -231,11 +231,12 @@ class Engine:
                 done.append(req)
                 progressed = True
                 continue
-            need = self._need(req)
-            evaluated = False
+            asked = self._evaluated(req)  # the request itself may ask for that form
+            need = self._need(req, evaluated=asked)
+            evaluated = asked
             fits = need <= self.budget and (self.reserved + need <= self.budget or
                                             self._evict_for(need))
-            if need > self.budget and self.allow_evaluated:
+            if need > self.budget and self.allow_evaluated and not asked:
                 # the stored form can never fit: the coupling blocks are
                 # evaluated inside each product instead (slower products,
                 # no stored blocks); a stored form that only has to wait for
@@ -253,7 +254,7 @@ class Engine:
                 else:
                     idx += 1      # does not fit yet: let smaller ones pass
                 continue
-            if evaluated:
+            if evaluated and not asked:
                 req.params = dict(req.params, coupling="evaluated")
                 self.log.append(("evaluated", m))
             pending.remove(req)

@@ -153,3 +153,15 @@ def test_evaluated_coupling_admits_what_the_stored_form_cannot():
     eng2 = Engine(ex2, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0, allow_evaluated=False)
     d2 = eng2.run([_req(0, 0.0, "big", 2000)])
     assert d2[0].error and "budget" in d2[0].error
+
+
+def test_a_request_for_the_evaluated_form_is_reserved_as_such():
+    """A construction that asks for evaluated coupling blocks is reserved at
+    the evaluated footprint (here a quarter of the stored one) from the start."""
+    ex = FakeExecutor(slots=1)
+    eng = Engine(ex, budget_bytes=1200, slots=1, margin=1.0, ratio=1.0, allow_evaluated=False)
+    r = _req(0, 0.0, "e", 1000)
+    r.params = dict(r.params, coupling="evaluated")
+    done = eng.run([r])
+    assert done[0].error is None
+    assert eng.peak_reserved <= 1200
