@@ -203,20 +203,6 @@ __device__ inline ArgMax block_argmax(ArgMax x, ArgMax *lds) {
   return lanes_argmax<NW>(lane < NW ? lds[lane] : ArgMax{-1.0, -1});
 }
 
-// The same with one barrier: lds holds two halves of NW slots and
-// successive calls alternate (parity).  A half is rewritten two calls after
-// it was read, with the barrier of the call in between.
-template <int NW>
-__device__ inline ArgMax block_argmax_1b(ArgMax x, ArgMax *lds, int parity) {
-  x = wave_argmax(x);
-  if constexpr (NW == 1) return x;
-  const int wid = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  ArgMax *h = lds + parity * NW;
-  if (lane == 0) h[wid] = x;
-  __syncthreads();
-  return lanes_argmax<NW>(lane < NW ? h[lane] : ArgMax{-1.0, -1});
-}
-
 template <int NW>
 __device__ inline double block_sum(double v, double *lds) {
   for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
