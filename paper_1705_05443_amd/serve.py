@@ -289,14 +289,18 @@ def latency_stats(done):
 # ---------------------------------------------------------------- GPU executor
 class GpuExecutor:
     """Runs builds and products through the C library on `slots` worker
-    threads, each with its own HIP stream (default priority)."""
+    threads, each with its own HIP stream (default priority).  allocator
+    "torch": every handle takes its device memory from torch's caching
+    allocator (smash_options alloc/free hooks), so torch's accounting covers
+    the resident matrices as well as the vectors."""
 
-    def __init__(self, slots=4, prior_ratios=None):
+    def __init__(self, slots=4, prior_ratios=None, allocator=None):
         import torch
         self.torch = torch
         self.pool = ThreadPoolExecutor(max_workers=slots)
         self.local = threading.local()
         self.prior = prior_ratios or {}
+        self.allocator = allocator
 
     def _stream(self):
         s = getattr(self.local, "stream", None)
@@ -331,7 +335,7 @@ class GpuExecutor:
         p.pop("dim", None)
         with torch.cuda.stream(s):
             X = torch.from_numpy(np.ascontiguousarray(req.points)).to("cuda", non_blocking=False)
-            h = api.Smash(X, stream=s, nrhs_hint=req.rhs.shape[1], **p)
+            h = api.Smash(X, stream=s, nrhs_hint=req.rhs.shape[1], allocator=self.allocator, **p)
             dt = torch.float64 if h.apply_prec == "f64" else torch.float32
             Q = torch.from_numpy(np.ascontiguousarray(req.rhs)).to(dt).to("cuda")
             Z = h.matvec(Q, stream=s)

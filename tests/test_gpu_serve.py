@@ -12,10 +12,11 @@ torch = pytest.importorskip("torch")
 from paper_1705_05443_amd import api, serve  # noqa: E402
 
 
-def test_serving_mix_equals_alone():
+@pytest.mark.parametrize("allocator", [None, "torch"])
+def test_serving_mix_equals_alone(allocator):
     trace = serve.make_trace(12, rate_hz=400.0, n_range=(3000, 30000), nrhs_range=(1, 32),
                              seed=3, reuse=0.35)
-    ex = serve.GpuExecutor(slots=4)
+    ex = serve.GpuExecutor(slots=4, allocator=allocator)
     eng = serve.Engine(ex, budget_bytes=64 << 30, slots=4)
     done = eng.run(trace)
     stats = serve.latency_stats(done)
