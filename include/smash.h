@@ -265,7 +265,22 @@ int smash_info(smash_handle h, smash_info_t *info);
 #define SMASH_EX_COUPLING 18 /* entries of all B_ij over L in pair order, each block  */
                              /* column-major (row index fastest), F64 or F32 per the */
                              /* apply precision; a BF16 handle: SMASH_E_UNSUPPORTED  */
-#define SMASH_EX_NEAR 19     /* Admission model for a serving loop: an upper estimate of the device
+#define SMASH_EX_NEAR 19     /* the same for the near blocks over L^-                */
+
+/* Copy parts of the construction to host memory for inspection (parity
+ * tests, debugging).
+ *   what      SMASH_EX_*
+ *   host_buf  host memory, or NULL to query the size
+ *   count     with host_buf == NULL receives the number of ELEMENTS of the
+ *             export (not bytes; the element type is given per SMASH_EX_*);
+ *             otherwise holds the buffer capacity in elements on entry
+ * Synchronises the device.  Errors: SMASH_E_INVALID_ARG (NULL handle or
+ * count, unknown `what`, capacity too small), SMASH_E_UNSUPPORTED (an export
+ * that the handle does not hold, e.g. SMASH_EX_COUPLING of a BF16 or
+ * evaluated-coupling handle), SMASH_E_DEVICE. */
+int smash_export(smash_handle h, int32_t what, void *host_buf, int64_t *count);
+
+/* Admission model for a serving loop: an upper estimate of the device
  * bytes a handle built with these parameters holds (points, tree, lists,
  * G copies, coupling and near blocks, a 64-column product workspace), from
  * the point count alone.  The block counts assume every node carries the
@@ -290,9 +305,6 @@ int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kernel_id, int32_t 
 int smash_estimate_footprint_mode(int64_t n, int32_t dim, int32_t kernel_id, int32_t leaf_size,
                                   int32_t interp_order, int32_t admissibility, double tol,
                                   int32_t apply_prec, int32_t coupling_mode, int64_t *bytes);
-
-/* the same for the near blocks over L^-                */
-int smash_export(smash_handle h, int32_t what, void *host_buf, int64_t *count);
 
 int smash_destroy(smash_handle h);
 

@@ -27,8 +27,10 @@ KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3}
 EX_PERM_X, EX_PERM_Y, EX_NODES, EX_BOXES, EX_L, EX_LM = 1, 2, 3, 4, 5, 6
 EX_NEAR_PTR, EX_NEAR_IDX, EX_RANKS = 7, 8, 9
 EX_ROW_SEL, EX_ROW_G, EX_COL_SEL, EX_COL_G, EX_ROW_GRID, EX_COL_GRID = 10, 11, 12, 13, 14, 15
-EX_SIZES, EX_LEVELS, EX_SWAPS, EX_MARGINS = 16, 17, 18, 19
-_DOUBLE_EXPORTS = {EX_BOXES, EX_ROW_G, EX_COL_G, EX_MARGINS}
+EX_SIZES, EX_LEVELS, EX_SWAPS, EX_MARGINS, EX_DECISION_MARGINS = 16, 17, 18, 19, 20
+_DOUBLE_EXPORTS = {EX_BOXES, EX_ROW_G, EX_COL_G, EX_MARGINS, EX_DECISION_MARGINS}
+# columns of EX_DECISION_MARGINS per side (row side first, then column side)
+DECISIONS = ("pivot", "rank cutoff", "swap", "SVD cutoff")
 
 
 def build(force: bool = False) -> str:

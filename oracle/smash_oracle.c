@@ -128,6 +128,12 @@ typedef struct {
   int ks;         /* HSS: number of kept singular vectors               */
   int nsw;        /* Gu-Eisenstat swaps performed                       */
   double gap;     /* smallest relative margin of a pivot choice         */
+  double rgap;    /* relative margin of the rank cutoff (step k-1 kept,
+                     step k dropped against tol * |R_11|)               */
+  double sgap;    /* smallest relative margin of a swap decision: the
+                     arg-max of rho against the runner-up, and the
+                     winning rho against f                              */
+  double vgap;    /* HSS: relative margin of the SVD truncation          */
 } side_t;
 
 typedef struct {
@@ -643,10 +649,15 @@ static void householder_step(double *W, int c, int m, int t) {
   free(v);
 }
 
+/* margins (test diagnostics only, NULL to skip): [0] smallest relative gap
+ * between the chosen pivot norm and the runner-up; [1] relative distance of
+ * the norms at the rank cutoff from tol * |R_11|; [2] smallest relative gap
+ * of a swap decision (winning rho against the runner-up and against f).   */
 static int compr(const double *C, int m, int c, double tol, double f, int *k_out, int *sel,
-                 double *G, int *nswaps, double *min_gap) {
+                 double *G, int *nswaps, double *margins) {
   *nswaps = 0;
-  if (min_gap) *min_gap = 1.0;
+  double *min_gap = margins;
+  if (margins) margins[0] = margins[1] = margins[2] = 1.0;
   if (m == 0) {
     *k_out = 0;
     return OR_OK;
@@ -680,8 +691,10 @@ static int compr(const double *C, int m, int c, double tol, double f, int *k_out
     if (t == 0) {
       r00 = bn;
       if (r00 == 0.0) break;
-    } else if (bn <= tol * r00) {
-      break;
+    } else {
+      double cut = tol * r00;
+      if (margins && cut > 0.0 && fabs(bn - cut) / cut < margins[1]) margins[1] = fabs(bn - cut) / cut;
+      if (bn <= cut) break;
     }
     /* relative margin of this pivot choice (a test diagnostic only) */
     if (min_gap && b2 >= 0.0 && (bn - b2) / bn < *min_gap) *min_gap = (bn - b2) / bn;
@@ -733,7 +746,7 @@ static int compr(const double *C, int m, int c, double tol, double f, int *k_out
         for (int j = 0; j < k; j++) s += Ri[(size_t)i * k + j] * Ri[(size_t)i * k + j];
         rinv[i] = sqrt(s); /* = 1/omega_i */
       }
-      double best = -1.0;
+      double best = -1.0, second = -1.0;
       int bi = -1, bj = -1;
       for (int j = 0; j < nr; j++) {
         for (int i = 0; i < k; i++) {
@@ -741,11 +754,20 @@ static int compr(const double *C, int m, int c, double tol, double f, int *k_out
           double b = gam[j] * rinv[i];
           double rho = sqrt(a * a + b * b);
           if (rho > best) {
+            second = best;
             best = rho;
             bi = i;
             bj = j;
+          } else if (rho > second) {
+            second = rho;
           }
         }
+      }
+      if (margins) {
+        double gf = fabs(best - f) / f;
+        if (gf < margins[2]) margins[2] = gf;
+        if (best > f && second >= 0.0 && (best - second) / best < margins[2])
+          margins[2] = (best - second) / best;
       }
       if (!(best > f)) break;
       if (++(*nswaps) > 64 * k) {
@@ -881,15 +903,22 @@ static int compress_node(oracle_t *h, int i, int rowside) {
   const double *P = rowside ? h->X : h->Y;
   double *S = NULL;
   int ks = 0;
+  s->gap = s->rgap = s->sgap = s->vgap = 1.0;
   if (h->adm == 0 && m > 0) {
     int nc = 0;
     double *A = near_block(h, i, rowside, &nc);
     if (!A) return OR_ENOMEM;
     if (nc > 0) {
       S = (double *)malloc(sizeof(double) * ((size_t)m * m + 1));
-      if (!S) return OR_ENOMEM;
-      ks = left_svd_truncated(A, m, nc, h->eps_svd, S, m, NULL);
+      double *sig = (double *)malloc(sizeof(double) * ((size_t)m + 1));
+      if (!S || !sig) return OR_ENOMEM;
+      ks = left_svd_truncated(A, m, nc, h->eps_svd, S, m, sig);
       if (ks < 0) return OR_ENOMEM;
+      /* diagnostic: how close any singular value lies to the cutoff */
+      double cut = h->eps_svd * sig[0];
+      for (int a = 0; a < m && cut > 0.0; a++)
+        if (fabs(sig[a] - cut) / cut < s->vgap) s->vgap = fabs(sig[a] - cut) / cut;
+      free(sig);
     }
     free(A);
   }
@@ -919,7 +948,11 @@ static int compress_node(oracle_t *h, int i, int rowside) {
   s->G = (double *)malloc(sizeof(double) * ((size_t)m * c + 1));
   if (!s->G) return OR_ENOMEM;
   int nsw = 0;
-  int rc = compr(C, m, c, h->tol, h->f, &s->k, s->sel, s->G, &nsw, &s->gap);
+  double mg[3];
+  int rc = compr(C, m, c, h->tol, h->f, &s->k, s->sel, s->G, &nsw, mg);
+  s->gap = mg[0];
+  s->rgap = mg[1];
+  s->sgap = mg[2];
   s->nsw = nsw;
   free(C);
   free(pts);
@@ -1248,7 +1281,7 @@ enum {
   EX_PERM_X = 1, EX_PERM_Y = 2, EX_NODES = 3, EX_BOXES = 4, EX_L = 5, EX_LM = 6,
   EX_NEAR_PTR = 7, EX_NEAR_IDX = 8, EX_RANKS = 9, EX_ROW_SEL = 10, EX_ROW_G = 11,
   EX_COL_SEL = 12, EX_COL_G = 13, EX_ROW_GRID = 14, EX_COL_GRID = 15, EX_SIZES = 16,
-  EX_LEVELS = 17, EX_SWAPS = 18, EX_MARGINS = 19
+  EX_LEVELS = 17, EX_SWAPS = 18, EX_MARGINS = 19, EX_DECISION_MARGINS = 20
 };
 
 int oracle_export(void *hv, int what, void *buf, int64_t *count) {
@@ -1329,6 +1362,23 @@ int oracle_export(void *hv, int what, void *buf, int64_t *count) {
         for (int i = 0; i < nn; i++) {
           db[2 * i] = h->row[i].gap;
           db[2 * i + 1] = h->col[i].gap;
+        }
+      break;
+    case EX_DECISION_MARGINS: /* double x 8 per node: pivot, rank cutoff, swap,
+                                 SVD cutoff margins of the row side, then the
+                                 column side (1.0: no such decision) */
+      n = (int64_t)nn * 8;
+      if (buf)
+        for (int i = 0; i < nn; i++) {
+          const side_t *sd[2] = {&h->row[i], &h->col[i]};
+          for (int u = 0; u < 2; u++) {
+            double *o = db + (size_t)i * 8 + 4 * u;
+            int done = sd[u]->sel != NULL;
+            o[0] = done ? sd[u]->gap : 1.0;
+            o[1] = done ? sd[u]->rgap : 1.0;
+            o[2] = done ? sd[u]->sgap : 1.0;
+            o[3] = (done && h->adm == 0) ? sd[u]->vgap : 1.0;
+          }
         }
       break;
     case EX_SWAPS: /* int32 x 2: swaps of the row and column side per node */

@@ -71,6 +71,79 @@ def test_dense_diag_value_and_symmetry():
     assert abs(B3[0, 1] - np.log(d)) < 1e-15 * 10
 
 
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_kernel_values_off_diagonal_match_library_distances(d):
+    """Off the diagonal every kernel is a function of the Euclidean distance
+    (eq. (2.1) on the line for 1/(x-y)): compare with SciPy's pairwise
+    distances fed to NumPy's reciprocal, log and exp."""
+    import scipy.spatial.distance as sd
+    rng = np.random.default_rng(40 + d)
+    x = rng.random((23, d)) * 3.0 - 1.0
+    y = rng.random((17, d)) * 3.0 - 1.0
+    r = sd.cdist(x, y)
+    ref = {"inv_r": np.reciprocal(r), "log_r": np.log(r), "exp_r": np.exp(-r)}
+    for name, want in ref.items():
+        got = O.kernel_block(x, y, name, diag=0.0)
+        assert np.max(np.abs(got - want) / np.maximum(np.abs(want), 1e-300)) < 4e-16 * 8, name
+    if d == 1:
+        got = O.kernel_block(x, y, "cauchy", diag=0.0)
+        want = np.subtract.outer(x[:, 0], y[:, 0])
+        assert np.max(np.abs(got * want - 1.0)) < 4e-16 * 4
+        assert np.all(np.sign(got) == np.sign(want))
+
+
+def test_inv_r_mean_value_over_sphere():
+    """1/|x-y| is harmonic in y away from x, so its mean over a sphere of
+    radius rho around c equals 1/|x-c| when |x-c| > rho (Gauss's mean-value
+    theorem).  The sphere average is taken with Gauss-Legendre nodes in
+    cos(theta) and the trapezoid rule in phi; 1/r^2 or 1/r^3 would fail."""
+    c = np.array([0.2, -0.1, 0.3])
+    x = np.array([[1.4, 0.9, -0.8]])
+    rho = 0.5
+    ct, wt = np.polynomial.legendre.leggauss(48)
+    ph = np.arange(96) * (2 * np.pi / 96)
+    C, P = np.meshgrid(ct, ph, indexing="ij")
+    S = np.sqrt(1 - C ** 2)
+    pts = c + rho * np.stack([S * np.cos(P), S * np.sin(P), C], axis=-1).reshape(-1, 3)
+    w = (np.repeat(wt, 96) / 2.0) / 96.0
+    K = O.kernel_block(x, pts, "inv_r", diag=0.0)[0]
+    assert abs(np.dot(w, K) - 1.0 / np.linalg.norm(x[0] - c)) < 1e-13
+    K2 = K ** 2
+    assert abs(np.dot(w, K2) - 1.0 / np.linalg.norm(x[0] - c) ** 2) > 1e-3
+
+
+def test_log_r_mean_value_over_circle():
+    """log|x-y| is harmonic in the plane: its mean over a circle of radius rho
+    around c is log|x-c| for |x-c| > rho, and log(rho) for |x-c| < rho (the
+    logarithmic potential of a uniform ring).  Trapezoid rule on the circle."""
+    c = np.array([0.3, 0.6])
+    rho = 0.25
+    t = np.arange(256) * (2 * np.pi / 256)
+    pts = c + rho * np.stack([np.cos(t), np.sin(t)], axis=1)
+    xo = np.array([[1.1, -0.2]])
+    xi = np.array([[0.35, 0.55]])
+    Ko = O.kernel_block(xo, pts, "log_r", diag=0.0)[0]
+    Ki = O.kernel_block(xi, pts, "log_r", diag=0.0)[0]
+    assert abs(Ko.mean() - np.log(np.linalg.norm(xo[0] - c))) < 1e-13
+    assert abs(Ki.mean() - np.log(rho)) < 1e-13
+
+
+def test_exp_r_multiplicative_along_a_line():
+    """exp(-|x-y|) turns distances that add along a line into products:
+    K(a, b) K(b, c) = K(a, c) for b between a and c, and K(a, a+u) = e^{-|u|}.
+    exp(-r^2) or exp(-r)/r would break the first identity."""
+    rng = np.random.default_rng(8)
+    for d in (1, 2, 3):
+        u = rng.normal(size=d)
+        u /= np.linalg.norm(u)
+        a = rng.random(d)
+        s = np.array([0.0, 0.37, 1.21])
+        p = a + s[:, None] * u
+        K = O.kernel_block(p, p, "exp_r")
+        assert abs(K[0, 1] * K[1, 2] - K[0, 2]) < 1e-15
+        assert abs(K[0, 2] - np.exp(-1.21)) < 1e-15
+
+
 # --------------------------------------------------------------------------
 # adaptive partition (Sec. 3.1, Remark A.1)
 # --------------------------------------------------------------------------
