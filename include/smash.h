@@ -171,7 +171,9 @@ int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int
  *   Y  device, nx x nrhs, leading dimension ldy (>= nrhs); fully overwritten
  *   dtype  type of X and Y: SMASH_F64 for an FP64-apply handle, SMASH_F32 for
  *          an FP32- or BF16-apply handle
- * Asynchronous on `stream`; workspaces are owned by the handle. */
+ * Asynchronous on `stream`; workspaces are owned by the handle.  Products of
+ * one handle are ordered by the library: one enqueued on another stream than
+ * the handle's previous product waits (on the device) for that product. */
 int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
                  void *Y, int64_t ldy, void *stream);
 
@@ -195,7 +197,7 @@ int smash_matvec_batched(int32_t count, const smash_handle *hs, const void *cons
 /* Launch shape of the products of an existing handle (the options
  * mv_split_nodes and mv_xcd_run), as an autotuner sets it between timed
  * products.  The numbers are unchanged up to the summation order of the
- * split sweeps.  Drops captured graphs (synchronizes the device).
+ * split sweeps.  Drops captured graphs (waits for their last launches).
  * Errors: SMASH_E_INVALID_ARG for a NULL handle or out-of-range values. */
 int smash_set_product_shape(smash_handle h, int32_t mv_split_nodes, int32_t mv_xcd_run);
 

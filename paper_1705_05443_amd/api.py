@@ -295,6 +295,9 @@ class Smash:
     def matvec(self, X, out=None, stream=None):
         """Y = A-hat X, original point order; X: (ny, nrhs) or (ny,), float64 for an
         FP64-apply handle, float32 for FP32 and BF16 apply."""
+        return self._product(lib().smash_matvec, X, out, stream)
+
+    def _product(self, fn, X, out, stream):
         import torch
         dt = torch.float64 if self.apply_prec == "f64" else torch.float32
         vec = X.dim() == 1
@@ -311,10 +314,9 @@ class Smash:
               or tuple(out.shape) != (self.nx, R) or out.stride(1) != 1):
             raise TypeError("out must be a CUDA (nx, nrhs) tensor of the vector precision "
                             "with unit column stride")
-        _check(lib().smash_matvec(self._h, C.c_void_p(X.data_ptr()), X.stride(0), R,
-                                  PREC["f64" if self.apply_prec == "f64" else "f32"],
-                                  C.c_void_p(out.data_ptr()),
-                                  out.stride(0), _stream_ptr(stream)))
+        _check(fn(self._h, C.c_void_p(X.data_ptr()), X.stride(0), R,
+                  PREC["f64" if self.apply_prec == "f64" else "f32"], C.c_void_p(out.data_ptr()),
+                  out.stride(0), _stream_ptr(stream)))
         return out[:, 0] if vec else out
 
     def set_product_shape(self, mv_split_nodes, mv_xcd_run):

@@ -163,6 +163,7 @@ struct GraphEntry {
   int64_t ldy;
   int calls;
   hipGraphExec_t exec;
+  hipEvent_t done;  // recorded after each launch of exec (nullptr before the first)
 };
 
 struct Handle {
@@ -229,6 +230,12 @@ struct Handle {
   int64_t graph_captures = 0, graph_replays = 0;
   int ws_nrhs = 0;
   void *qbuf = nullptr, *zbuf = nullptr;
+  // recorded at the end of every smash_matvec product (created with the
+  // handle): the next product waits for it when it runs on another stream
+  // (products share the workspace), and the workspace is released only
+  // after it
+  hipEvent_t prod_done = nullptr;
+  hipStream_t prod_stream = nullptr;
   DeviceArena ws_mem;
   // phase timing (options.timing)
   bool timing = false;
@@ -292,6 +299,7 @@ void coupling_offsets(Handle &h, DeviceArena &tmp);       // coupling blocks; th
 void eval_coupling_range(Handle &h, int64_t p0, int64_t p1, void *base, hipStream_t s);
 void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                 hipStream_t s);
-void drop_graphs(Handle &h);  // destroys captured products (synchronizes the device)
+// destroys captured products (waits for each one's last launch)
+void drop_graphs(Handle &h);
 
 }  // namespace smash

@@ -981,7 +981,11 @@ static bool ensure_workspace(Handle &h, int nrhs, hipStream_t s) {
   const int chunk = nrhs < RC ? nrhs : RC;
   const int cp = (chunk + 15) / 16 * 16;
   if (h.ws_nrhs >= cp) return false;
-  h.ws_mem.release(false);  // stream-ordered: earlier products may still run
+  // earlier products (on any stream) may still read the old buffers: wait
+  // for the last of them (they are ordered by prod_done), then give the
+  // buffers back as idle memory
+  if (h.prod_done && h.ws_nrhs > 0) SMASH_HIP(hipEventSynchronize(h.prod_done));
+  h.ws_mem.release(true);
   h.ws_mem.stream = s;
   h.qbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.col->nslots * cp);
   h.zbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.row.nslots * cp);
@@ -990,11 +994,8 @@ static bool ensure_workspace(Handle &h, int nrhs, hipStream_t s) {
 }
 
 template <class T>
-static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t ldy,
-                     hipStream_t s) {
-  const int RC = 64;  // right-hand sides per pass through the tree
-  const int chunk = nrhs < RC ? nrhs : RC;
-  T *q = (T *)h.qbuf, *z = (T *)h.zbuf;
+static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t ldy, T *q, T *z,
+                     int chunk, hipStream_t s) {
   for (int c0 = 0; c0 < nrhs; c0 += chunk) {
     const int R = nrhs - c0 < chunk ? nrhs - c0 : chunk;
     if (h.apply_prec == SMASH_BF16)
@@ -1005,19 +1006,37 @@ static void matvec_t(Handle &h, const T *X, int64_t ldx, int nrhs, T *Y, int64_t
   }
 }
 
+// q and z (slot-space vectors of the column and row side) and the number of
+// right-hand sides per pass through the tree
+static void launch_sequence_in(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y,
+                               int64_t ldy, void *q, void *z, int chunk, hipStream_t s) {
+  if (h.apply_prec == SMASH_F64)
+    matvec_t<double>(h, (const double *)X, ldx, nrhs, (double *)Y, ldy, (double *)q,
+                     (double *)z, chunk, s);
+  else
+    matvec_t<float>(h, (const float *)X, ldx, nrhs, (float *)Y, ldy, (float *)q, (float *)z,
+                    chunk, s);
+}
+
 static void launch_sequence(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y,
                             int64_t ldy, hipStream_t s) {
-  if (h.apply_prec == SMASH_F64)
-    matvec_t<double>(h, (const double *)X, ldx, nrhs, (double *)Y, ldy, s);
-  else
-    matvec_t<float>(h, (const float *)X, ldx, nrhs, (float *)Y, ldy, s);
+  const int RC = 64;  // right-hand sides per pass through the tree
+  launch_sequence_in(h, X, ldx, nrhs, Y, ldy, h.qbuf, h.zbuf, nrhs < RC ? nrhs : RC, s);
+}
+
+// An executable graph is destroyed once its last launch has completed.
+static void destroy_graph(GraphEntry &g) {
+  if (g.done) {
+    (void)hipEventSynchronize(g.done);
+    (void)hipEventDestroy(g.done);
+  }
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  g.done = nullptr;
+  g.exec = nullptr;
 }
 
 void drop_graphs(Handle &h) {
-  if (h.graphs.empty()) return;
-  (void)hipDeviceSynchronize();  // a replay may still run on any stream
-  for (auto &g : h.graphs)
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  for (auto &g : h.graphs) destroy_graph(g);
   h.graphs.clear();
 }
 
@@ -1025,8 +1044,25 @@ void drop_graphs(Handle &h) {
 // -- the same launch sequence captured once into a HIP graph on the second
 // call with the same arguments and replayed from then on (one graph launch
 // instead of 2 + 2(levels - 1) + 2 kernel launches per 64 right-hand sides).
+static void run_matvec_on(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
+                          hipStream_t s);
+
+// Products of one handle share its workspace (and the evaluated form's
+// block chunks): one on another stream than the previous product first
+// waits for it; each records prod_done at its end.
 void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                 hipStream_t s) {
+  if (h.prod_done && h.prod_stream && h.prod_stream != s)
+    SMASH_HIP(hipStreamWaitEvent(s, h.prod_done, 0));
+  run_matvec_on(h, X, ldx, nrhs, Y, ldy, s);
+  if (h.prod_done) {
+    SMASH_HIP(hipEventRecord(h.prod_done, s));
+    h.prod_stream = s;
+  }
+}
+
+static void run_matvec_on(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
+                          hipStream_t s) {
   if (ensure_workspace(h, nrhs, s)) drop_graphs(h);
   if (!h.use_graphs || h.timing) {
     launch_sequence(h, X, ldx, nrhs, Y, ldy, s);
@@ -1037,11 +1073,10 @@ void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_
     if (g.X == X && g.ldx == ldx && g.nrhs == nrhs && g.Y == Y && g.ldy == ldy) e = &g;
   if (!e) {
     if (h.graphs.size() >= 8) {  // keep the eight most recent argument sets
-      (void)hipDeviceSynchronize();
-      if (h.graphs.front().exec) (void)hipGraphExecDestroy(h.graphs.front().exec);
+      destroy_graph(h.graphs.front());
       h.graphs.erase(h.graphs.begin());
     }
-    h.graphs.push_back(GraphEntry{X, ldx, nrhs, Y, ldy, 0, nullptr});
+    h.graphs.push_back(GraphEntry{X, ldx, nrhs, Y, ldy, 0, nullptr, nullptr});
     e = &h.graphs.back();
   }
   e->calls++;
@@ -1068,7 +1103,9 @@ void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_
     e->exec = ex;
     h.graph_captures++;
   }
+  if (!e->done) SMASH_HIP(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
   SMASH_HIP(hipGraphLaunch(e->exec, s));
+  SMASH_HIP(hipEventRecord(e->done, s));
   h.graph_replays++;
 }
 

@@ -60,6 +60,10 @@ static void free_handle(Handle *h) {
   if (!h) return;
   resolve_timers(*h);
   drop_graphs(*h);
+  if (h->prod_done) {
+    (void)hipEventSynchronize(h->prod_done);
+    (void)hipEventDestroy(h->prod_done);
+  }
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   (void)hipStreamSynchronize(h->stream);
   if (h->side) (void)hipStreamSynchronize(h->side);  // a failed build may leave work there
@@ -188,6 +192,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     // (the leaf count came with the generators' last host read)
     h->build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    SMASH_HIP(hipEventCreateWithFlags(&h->prod_done, hipEventDisableTiming));
     *out = (smash_handle)h;
     return SMASH_OK;
   } catch (const Error &e) {

@@ -103,13 +103,15 @@ class Engine:
             r = self.ex.prior_ratio(req)
         return int(est * min(1.0, r * self.margin))
 
-    def _evict_for(self, need):
-        """Evict idle resident matrices (LRU) until `need` more bytes fit."""
+    def _evict_for(self, need, wanted=()):
+        """Evict idle resident matrices (LRU) until `need` more bytes fit,
+        never one in `wanted` (matrices that waiting product requests name:
+        evicting it would fail them)."""
         for m in list(self.resident):
             if self.reserved + need <= self.budget:
                 break
             res = self.resident[m]
-            if res.busy:
+            if res.busy or m in wanted:
                 continue
             self.ex.release(res.handle)
             self.reserved -= res.bytes
@@ -184,15 +186,23 @@ class Engine:
         return progressed
 
     def _admit(self, pending, building, now, done):
+        """One admission pass over the waiting requests in arrival order.
+        Products on resident matrices are admitted wherever they wait (they
+        need no memory); constructions are considered among the first
+        `lookahead` waiting ones only."""
         progressed = False
         scanned = 0
         idx = 0
-        while idx < len(pending) and scanned < self.lookahead:
+        while idx < len(pending):
             if len(self.inflight) >= self.slots:
                 break
             req = pending[idx]
-            scanned += 1
             m = req.matrix
+            if req.points is not None:
+                if scanned >= self.lookahead:
+                    idx += 1
+                    continue
+                scanned += 1
             if m in building:        # its matrix is being built: wait for it
                 idx += 1
                 continue
@@ -234,8 +244,9 @@ class Engine:
             asked = self._evaluated(req)  # the request itself may ask for that form
             need = self._need(req, evaluated=asked)
             evaluated = asked
+            wanted = {r.matrix for r in pending if r.points is None}
             fits = need <= self.budget and (self.reserved + need <= self.budget or
-                                            self._evict_for(need))
+                                            self._evict_for(need, wanted))
             if need > self.budget and self.allow_evaluated and not asked:
                 # the stored form can never fit: the coupling blocks are
                 # evaluated inside each product instead (slower products,
@@ -244,7 +255,7 @@ class Engine:
                 need_e = self._need(req, evaluated=True)
                 if need_e <= self.budget:
                     need, evaluated = need_e, True
-                    fits = self.reserved + need <= self.budget or self._evict_for(need)
+                    fits = self.reserved + need <= self.budget or self._evict_for(need, wanted)
             if not fits:
                 if need > self.budget:
                     req.error, req.done = "footprint above the memory budget", now()
@@ -335,7 +346,11 @@ class GpuExecutor:
         p.pop("dim", None)
         with torch.cuda.stream(s):
             X = torch.from_numpy(np.ascontiguousarray(req.points)).to("cuda", non_blocking=False)
-            h = api.Smash(X, stream=s, nrhs_hint=req.rhs.shape[1], allocator=self.allocator, **p)
+            # graphs off: a graph replays only for a repeated argument set
+            # (the same X and Y buffers), which fresh per-request vectors
+            # never are
+            h = api.Smash(X, stream=s, nrhs_hint=req.rhs.shape[1], allocator=self.allocator,
+                          graphs=False, **p)
             dt = torch.float64 if h.apply_prec == "f64" else torch.float32
             Q = torch.from_numpy(np.ascontiguousarray(req.rhs)).to(dt).to("cuda")
             Z = h.matvec(Q, stream=s)

@@ -2,7 +2,8 @@
 
 Integer outputs (permutation, tree, pair lists, near sets, ranks, skeleton
 sets) must be bit-exact.  FP64 construction: H^2 interpolative-decomposition
-coefficients G within 1e-9 of the oracle's (relative to max(1, |G|) per node;
+coefficients G within 1e-10 of the oracle's (relative to max(1, |G|) per node,
+or within the forward-error bound of the node's skeleton conditioning;
 HSS G by the properties in _check_hss_ids) and products within 1e-10
 relative Frobenius.  FP32 apply: within
 1e-5 relative Frobenius of the oracle's FP64 product on the FP32-rounded
@@ -136,10 +137,14 @@ def _split(arr, sizes):
 
 
 # HSS: the near-field vectors in C = [U-hat, S] are fixed only to about
-# eps_mach / eps_svd by any SVD, so a pivot of compr whose oracle margin
-# (relative gap between the best and second-best residual norm) is below
-# this is a genuine near-tie: the two skeleton choices are equally valid.
+# eps_mach / eps_svd by any SVD (eps_svd = 1e-9 .. 1e-10 here, so to about
+# 1e-6), so a decision of compr or of the SVD truncation whose oracle margin
+# is below this is a genuine near-tie: the two skeleton choices are equally
+# valid.  The deciding quantity is named (pivot arg-max, rank cutoff against
+# tol*|R11|, swap arg-max or rho against f, singular value against
+# eps_svd*sigma_1), and the number of such nodes is bounded per case.
 HSS_TIE = 1e-5
+HSS_TIE_MAX_NODES = 3
 
 
 def _gpu_per_node(g, side, nn):
@@ -158,15 +163,17 @@ def _gpu_per_node(g, side, nn):
 
 def _hss_tie_subtrees(o, g, side, c):
     """Nodes whose results may differ from the oracle's: every node whose
-    own pivot decision is a near-tie (oracle margin < HSS_TIE) and differs,
-    and its ancestors (their grids are built from it).  Any other difference
-    fails."""
+    own result differs while one of its decisions is a near-tie in the
+    oracle (margin < HSS_TIE; the decision is named), and its ancestors
+    (their grids are built from it).  Any other difference fails, and so do
+    more than HSS_TIE_MAX_NODES near-tie nodes per side."""
     ro, rg = o.ranks(), g.export("ranks").reshape(-1, 6)
     nodes = g.export("nodes").reshape(-1, 8)
     nn = nodes.shape[0]
-    margin = o.export(O.EX_MARGINS).reshape(-1, 2)[:, 0 if side == "row" else 1]
+    dm = o.export(O.EX_DECISION_MARGINS).reshape(-1, 8)[:, (0 if side == "row" else 4):][:, :4]
     po, pg = O.Oracle.per_node(o, side), _gpu_per_node(g, side, nn)
     tainted = np.zeros(nn, bool)
+    ties = []
     for i in range(nn - 1, 0, -1):  # children come after their parents
         fc, nc_ = nodes[i, 2], nodes[i, 3]
         below = nc_ > 0 and tainted[fc:fc + nc_].any()
@@ -176,9 +183,14 @@ def _hss_tie_subtrees(o, g, side, c):
         if below:
             tainted[i] = True
         elif not same:
-            assert margin[i] < HSS_TIE, (side, "node", i, "differs with oracle margin", margin[i])
-            print("near-tie at node", i, side, "margin %.2e" % margin[i], flush=True)
+            d = int(np.argmin(dm[i]))
+            assert dm[i, d] < HSS_TIE, (side, "node", i, "differs; oracle margins",
+                                        dict(zip(O.DECISIONS, dm[i].tolist())))
+            ties.append((i, O.DECISIONS[d], float(dm[i, d])))
             tainted[i] = True
+    print("HSS near-tie nodes (%s side): %d %s; exempted with ancestors: %d of %d"
+          % (side, len(ties), ties, int(tainted.sum()), nn - 1), flush=True)
+    assert len(ties) <= HSS_TIE_MAX_NODES, ties
     return tainted
 
 
@@ -210,14 +222,44 @@ def test_ranks_skeletons_and_G(name):
         Go = _split(o.export(exg), (m_o - k_o) * k_o)
         Gg = _split(g.export(side + "_G"), (m_g - k_g) * k_g)
         if not weak:
-            worst = 0.0
-            for a, b in zip(Go, Gg):
-                if a.size:
-                    worst = max(worst, float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a)))))
-            assert worst < 1e-9, (side, worst)
+            _check_h2_G(x, y, g, side, m_g, k_g, Go, Gg, CASES[name][1]["order"])
         else:
             _check_hss_ids(x, y, g, side, m_g, k_g, g.export(side + "_sel"), Go, Gg,
                            CASES[name][1]["order"], keep)
+
+
+# H^2 G = (R11^-1 R12)^T against the oracle's, per node relative to
+# max(1, |G|): 1e-10, the FP64 rule.  G solves a triangular system with R11,
+# whose condition number equals that of the skeleton rows C_S of the basis
+# and may reach about 1/tol; rounding then perturbs G by up to a small
+# multiple of eps * cond(C_S) (the forward error of a backward-stable
+# solve).  A node above 1e-10 must stay within 64 * eps * cond(C_S), with
+# cond(C_S) computed here from the basis at the node's skeleton points.
+H2_G_TOL = 1e-10
+
+
+def _check_h2_G(x, y, g, side, m, k, Go, Gg, order):
+    P = x if side == "row" else (x if y is None else y)
+    perm = g.export("perm_x" if side == "row" else "perm_y")
+    grid = _split(g.export(side + "_grid"), m)
+    sels = _split(g.export(side + "_sel"), m)
+    bx = g.export("boxes").reshape(-1, 6)
+    d = P.shape[1]
+    worst, wide = 0.0, []
+    for i, (a, b) in enumerate(zip(Go, Gg)):
+        if not a.size:
+            continue
+        diff = float(np.max(np.abs(a - b)) / max(1.0, np.max(np.abs(a))))
+        worst = max(worst, diff)
+        if diff < H2_G_TOL:
+            continue
+        node = i + 1
+        U = O.interp_basis(P[perm[grid[i]]], bx[node, :d], bx[node, 3:3 + d], order)
+        cond = float(np.linalg.cond(U[sels[i][:int(k[i])]]))
+        wide.append((node, diff, cond))
+        assert diff <= 64 * np.finfo(np.float64).eps * cond, (side, node, diff, cond)
+    print("H2 G worst difference", side, "%.2e" % worst,
+          "; nodes above 1e-10 (node, diff, cond(C_S)):", wide, flush=True)
 
 
 def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep):
@@ -320,16 +362,45 @@ def test_plain_per_node_form_equals_batched(name):
 
 
 @pytest.mark.parametrize("name", ["h2_2d_log", "h2_3d_clusters", "hss_cauchy_xy"])
-def test_matvec_fp32_apply(name):
+@pytest.mark.parametrize("eval_prec", ["f64", "f32"])
+def test_matvec_fp32_apply(name, eval_prec):
+    """FP32 apply, with the blocks evaluated in FP64 (then rounded) or by the
+    FP32 kernel arithmetic on FP64 coordinate differences (the form the
+    large workloads run): within 1e-5 relative Frobenius of the FP64
+    oracle's product on the FP32-rounded right-hand sides."""
     mk, kw = CASES[name]
     x, y = mk()
     o = O.Oracle(x, y, **_oracle_kwargs(kw))
-    g = api.Smash(dev(x), None if y is None else dev(y), apply_prec="f32", **kw)
+    g = api.Smash(dev(x), None if y is None else dev(y), apply_prec="f32", eval_prec=eval_prec,
+                  **kw)
+    print("case", name, eval_prec, flush=True)
     for nrhs in (1, 16, 64):
         q32 = W.rhs(g.ny, nrhs, seed=3).astype(np.float32)
         z_o = o.matvec(q32.astype(np.float64))
         z_g = g.matvec(torch.from_numpy(q32).cuda()).cpu().numpy().astype(np.float64)
-        assert relerr(z_g, z_o) < 1e-5, nrhs
+        e = relerr(z_g, z_o)
+        print("  nrhs", nrhs, "rel. error vs FP64 oracle %.2e" % e, flush=True)
+        assert e < 1e-5, nrhs
+    g.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_evaluated_coupling_fp64_parity(name):
+    """The index-only form (coupling blocks re-evaluated from the skeleton
+    points inside each product, a chunk of pairs at a time) against the FP64
+    oracle, whose product evaluates every block on the fly: within 1e-10."""
+    x, y, o, _ = pair_for(name)
+    kw = CASES[name][1]
+    g = api.Smash(dev(x), None if y is None else dev(y), coupling="evaluated",
+                  coupling_chunk=5000, **kw)
+    print("case", name, flush=True)
+    for nrhs in (1, 16):
+        q = W.rhs(g.ny, nrhs, seed=30 + nrhs)
+        z_o = o.matvec(q)
+        for _ in range(2):  # eager, then captured
+            z_g = g.matvec(dev(q)).cpu().numpy()
+            assert relerr(z_g, z_o) < 1e-10, nrhs
+    g.close()
 
 
 @pytest.mark.parametrize("name", ["h2_2d_log", "h2_3d_clusters", "hss_cauchy_xy", "hss1d_cfg"])
@@ -644,3 +715,27 @@ def test_levels_wider_than_one_workgroup():
     z_g = g.matvec(dev(q)).cpu().numpy()
     g.close()
     assert relerr(z_g, z_o) < 1e-10
+
+
+def test_products_of_one_handle_on_two_streams_are_ordered():
+    """Products of one handle share its workspace.  Enqueued on two streams
+    with no synchronisation between them -- the second one needing a larger
+    workspace, which the library then grows -- each still equals the same
+    product run alone, because the library orders a handle's products."""
+    x, _ = CASES["h2_2d_log"][0]()
+    kw = CASES["h2_2d_log"][1]
+    ref_h = api.Smash(dev(x), graphs=False, **kw)
+    h = api.Smash(dev(x), **kw)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    Qs = [dev(W.rhs(len(x), r, seed=40 + r)) for r in (16, 80, 5, 16)]
+    refs = [ref_h.matvec(Q) for Q in Qs]
+    torch.cuda.synchronize()
+    for rep in range(3):
+        outs = [torch.empty_like(r) for r in refs]
+        for c, (Q, o) in enumerate(zip(Qs, outs)):
+            h.matvec(Q, out=o, stream=s1 if c % 2 == 0 else s2)
+        torch.cuda.synchronize()
+        for c, (o, r) in enumerate(zip(outs, refs)):
+            assert torch.equal(o, r), (rep, c)
+    h.close()
+    ref_h.close()

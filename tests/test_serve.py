@@ -165,3 +165,33 @@ def test_a_request_for_the_evaluated_form_is_reserved_as_such():
     done = eng.run([r])
     assert done[0].error is None
     assert eng.peak_reserved <= 1200
+
+
+def test_waiting_product_keeps_its_matrix_resident():
+    """A construction that needs memory must not evict a resident matrix that
+    a waiting product request names (that request would fail as 'not
+    resident'): the product is served first, then the matrix is evicted."""
+    ex = FakeExecutor(slots=1, build_s=0.03, prod_s=0.01, real_per_point=2)
+    eng = Engine(ex, budget_bytes=3000, slots=1, margin=1.0)
+    reqs = [_req(0, 0.0, "m0", 1000),            # 2000 bytes: m0 and m1 do not fit together
+            _req(1, 0.1, "m1", 1000),
+            _req(2, 0.1, "m0", 1000, build=False)]
+    done = eng.run(reqs)
+    assert len(done) == 3 and all(r.error is None for r in done), [r.error for r in done]
+    kinds = [e[:2] for e in eng.log]
+    assert kinds.index(("product", "m0")) < kinds.index(("evict", "m0"))
+    assert kinds.index(("evict", "m0")) < kinds.index(("build", "m1"))
+
+
+def test_products_beyond_the_lookahead_are_admitted():
+    """Products on resident matrices need no memory: they are admitted even
+    when they wait behind more constructions than the lookahead considers."""
+    ex = FakeExecutor(slots=2, build_s=0.02, prod_s=0.005)
+    eng = Engine(ex, budget_bytes=2500, slots=2, margin=1.0, lookahead=2)
+    reqs = [_req(0, 0.0, "m0", 1000)]
+    reqs += [_req(1 + i, 0.05, "b%d" % i, 1200) for i in range(4)]
+    reqs += [_req(9, 0.05, "m0", 1000, build=False)]
+    done = eng.run(reqs)
+    assert all(r.error is None for r in done), [r.error for r in done]
+    r9 = [r for r in done if r.rid == 9][0]
+    assert np.array_equal(r9.result, 2.0 * r9.rhs)
