@@ -177,6 +177,29 @@ int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int
 int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
                  void *Y, int64_t ldy, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * product as smash_matvec, same arguments and results, but it allocates
+ * nothing.  The product's slot-space vectors (q and z, the only device
+ * memory it needs beyond the handle, X and Y) come from one library-owned
+ * array of SMASH_NOALLOC_SCRATCH_BYTES per device, held by every device the
+ * library runs on until the process ends; the right-hand sides are taken in
+ * passes of 64, 48, 32 or 16 columns, the widest whose vectors fit.  Always
+ * eager launches (no graph capture, no phase timers).
+ * The array is shared by every such call on the device and keeps the last
+ * call's contents: calls that overlap on one device (on different streams or
+ * host threads, without ordering between them) race and give wrong results.
+ * Unlike smash_matvec, no ordering with the handle's other products is
+ * added (no event is recorded or waited for, so the call can be captured
+ * into a caller's graph): order them on the caller's streams.
+ * Errors: as smash_matvec; SMASH_E_INVALID_ARG, naming the sizes, when the
+ * handle's vectors for 16 columns exceed the array (row slots + column slots
+ * times 16 times 8 bytes for FP64 apply, 4 bytes otherwise);
+ * SMASH_E_DEVICE when the array's device address cannot be obtained. */
+#define SMASH_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+int smash_matvec_noalloc(smash_handle h, const void *X, int64_t ldx, int32_t nrhs,
+                         int32_t dtype, void *Y, int64_t ldy, void *stream);
+
 /* Products of several handles in one call (Sec. 3.4 for each): Ys[c] =
  * A-hat_c Xs[c] for c < count, enqueued on `stream` in order, each exactly as
  * smash_matvec would (a captured-graph replay once its argument set repeats).

@@ -32,6 +32,8 @@ class SmashError(RuntimeError):
 
 
 COUPLING = {"auto": 0, "stored": 1, "evaluated": 2}
+# size of the library's per-device array used by smash_matvec_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 class Options(C.Structure):
@@ -94,7 +96,7 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-            "smash_matvec_batched", "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
+            "smash_matvec_noalloc", "smash_matvec_batched", "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
             "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_last_error"]
 
 
@@ -114,6 +116,7 @@ def lib():
                                      C.c_int32, C.c_int32, C.c_int32, C.c_double,
                                      C.POINTER(Options), vp, C.POINTER(vp)]
         L.smash_matvec.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, vp]
+        L.smash_matvec_noalloc.argtypes = L.smash_matvec.argtypes
         L.smash_matvec_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                            C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, vp]
@@ -129,7 +132,7 @@ def lib():
         L.smash_destroy.argtypes = [vp]
         L.smash_last_error.restype = C.c_char_p
         for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-                  "smash_matvec_batched",
+                  "smash_matvec_noalloc", "smash_matvec_batched",
                   "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
                   "smash_estimate_footprint", "smash_estimate_footprint_mode"):
             getattr(L, f).restype = C.c_int
@@ -296,6 +299,13 @@ class Smash:
         """Y = A-hat X, original point order; X: (ny, nrhs) or (ny,), float64 for an
         FP64-apply handle, float32 for FP32 and BF16 apply."""
         return self._product(lib().smash_matvec, X, out, stream)
+
+    def matvec_noalloc(self, X, out=None, stream=None):
+        """The same product through smash_matvec_noalloc: no device allocation by
+        the library (its vectors live in the library's per-device array of
+        NOALLOC_SCRATCH_BYTES); `out` must be given by callers that cannot
+        allocate."""
+        return self._product(lib().smash_matvec_noalloc, X, out, stream)
 
     def _product(self, fn, X, out, stream):
         import torch

@@ -299,6 +299,10 @@ void coupling_offsets(Handle &h, DeviceArena &tmp);       // coupling blocks; th
 void eval_coupling_range(Handle &h, int64_t p0, int64_t p1, void *base, hipStream_t s);
 void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                 hipStream_t s);
+// the same product with its vectors in the library's per-device array of
+// SMASH_NOALLOC_SCRATCH_BYTES (no allocation, eager launches)
+void run_matvec_noalloc(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
+                        hipStream_t s);
 // destroys captured products (waits for each one's last launch)
 void drop_graphs(Handle &h);
 

@@ -21,6 +21,8 @@
 // for the FP64 one (e = 0..3; measured on gfx950).  A is stored with
 // consecutive rows consecutive in memory, so each wave load is four
 // 128-byte segments.
+#include <mutex>
+
 #include "common.cuh"
 
 namespace smash {
@@ -1107,6 +1109,81 @@ static void run_matvec_on(Handle &h, const void *X, int64_t ldx, int nrhs, void 
   SMASH_HIP(hipGraphLaunch(e->exec, s));
   SMASH_HIP(hipEventRecord(e->done, s));
   h.graph_replays++;
+}
+
+// ---------------------------------------------- product without allocation
+// The product's only device memory beyond the handle, X and Y is its pair of
+// slot-space vectors.  For callers that cannot allocate, they come from this
+// file-scope array instead of the handle's workspace: one copy per device,
+// held until the process ends, shared by every such call on that device.
+// In host code `scratch` names a host-side stand-in, not the device array:
+// its device address is obtained once per device (noalloc_scratch) and only
+// that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[SMASH_NOALLOC_SCRATCH_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Device address of `scratch` on device dev, looked up on the first call for
+// that device with the device current (the caller's device is restored).
+static void *noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    throw Error{SMASH_E_DEVICE, "device index outside the no-allocation product's table"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    int cur = -1;
+    SMASH_HIP(hipGetDevice(&cur));
+    if (cur != dev) SMASH_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p)
+      throw Error{SMASH_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e)};
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+// Columns per pass whose vectors fit in the array: 64, 48, 32 or 16, and no
+// more than the right-hand sides rounded up to 16; 0 if 16 do not fit.
+static int noalloc_chunk(const Handle &h, int nrhs, size_t *zoff) {
+  const size_t es = h.apply_prec == SMASH_F64 ? sizeof(double) : sizeof(float);
+  const int rp = (nrhs + 15) / 16 * 16;
+  for (int cw = 64; cw >= 16; cw -= 16) {
+    if (cw > rp && cw > 16) continue;
+    const size_t qb = ((size_t)h.col->nslots * cw * es + 255) / 256 * 256;
+    const size_t zb = (size_t)h.row.nslots * cw * es;
+    if (qb + zb <= (size_t)SMASH_NOALLOC_SCRATCH_BYTES) {
+      *zoff = qb;
+      return nrhs < cw ? nrhs : cw;
+    }
+  }
+  return 0;
+}
+
+void run_matvec_noalloc(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
+                        hipStream_t s) {
+  size_t zoff = 0;
+  const int chunk = noalloc_chunk(h, nrhs, &zoff);
+  if (chunk == 0) {
+    const size_t es = h.apply_prec == SMASH_F64 ? sizeof(double) : sizeof(float);
+    throw Error{SMASH_E_INVALID_ARG,
+                "the product's vectors need " +
+                    std::to_string((size_t)(h.col->nslots + h.row.nslots) * 16 * es) +
+                    " bytes at 16 columns; the no-allocation product holds at most " +
+                    std::to_string((long long)SMASH_NOALLOC_SCRATCH_BYTES)};
+  }
+  char *base = (char *)noalloc_scratch(h.device);
+  // eager launches only; phase timers would create events
+  struct NoTimers {
+    Handle &h;
+    int saved;
+    explicit NoTimers(Handle &h_) : h(h_), saved(h_.timing) { h.timing = 0; }
+    ~NoTimers() { h.timing = saved; }
+  } nt(h);
+  launch_sequence_in(h, X, ldx, nrhs, Y, ldy, base, base + zoff, chunk, s);
 }
 
 }  // namespace smash

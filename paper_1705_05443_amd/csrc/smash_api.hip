@@ -242,6 +242,25 @@ extern "C" int smash_matvec(smash_handle hv, const void *X, int64_t ldx, int32_t
   }
 }
 
+extern "C" int smash_matvec_noalloc(smash_handle hv, const void *X, int64_t ldx, int32_t nrhs,
+                                    int32_t dtype, void *Y, int64_t ldy, void *stream) {
+  Handle *h = (Handle *)hv;
+  if (!h) return fail(SMASH_E_INVALID_ARG, "handle is NULL");
+  if (!X || !Y) return fail(SMASH_E_INVALID_ARG, "X or Y is NULL");
+  if (nrhs < 1) return fail(SMASH_E_INVALID_ARG, "nrhs must be >= 1");
+  if (ldx < nrhs || ldy < nrhs) return fail(SMASH_E_INVALID_ARG, "leading dimension < nrhs");
+  if (dtype != (h->apply_prec == SMASH_F64 ? SMASH_F64 : SMASH_F32))
+    return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's vector precision");
+  try {
+    run_matvec_noalloc(*h, X, ldx, nrhs, Y, ldy, (hipStream_t)stream);
+    return SMASH_OK;
+  } catch (const Error &e) {
+    return fail(e.code, e.msg);
+  } catch (...) {
+    return fail(SMASH_E_DEVICE, "unexpected failure");
+  }
+}
+
 extern "C" int smash_matvec_batched(int32_t count, const smash_handle *hs,
                                     const void *const *Xs, const int64_t *ldx,
                                     const int32_t *nrhs, void *const *Ys, const int64_t *ldy,

@@ -62,6 +62,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert b"tau" in L.smash_last_error() or len(L.smash_last_error()) > 0
     # NULL handle everywhere
     assert L.smash_matvec(None, dummy, 1, 1, 0, dummy, 1, None) == -1
+    assert L.smash_matvec_noalloc(None, dummy, 1, 1, 0, dummy, 1, None) == -1
     info = api.Info()
     assert L.smash_info(None, C.byref(info)) == -1
     n = C.c_int64(0)
