@@ -249,7 +249,20 @@ typedef struct smash_info_t {
   int64_t graph_captures, graph_replays; /* products captured / replayed as graphs */
   int32_t coupling_evaluated; /* 1: coupling blocks are evaluated inside each product */
   int32_t coupling_chunks;    /* chunks of pairs per product in that case */
-  int64_t coupling_ws_entries; /* entries of the chunk workspace in that case */
+  int64_t coupling_ws_entries; /* entries of the chunk workspace in that case
+                                  (0 when the evaluation is fused into the
+                                  contraction: FP64 and FP32 apply) */
+  /* Storage comparison in the manner of Sec. 6.6 (Table 6.6), in bytes with
+   * every value in FP64 and every index in int32:
+   *   bytes_dense  the dense matrix, 8 nx ny;
+   *   bytes_hss0   generators stored as dense matrices: U_i (and V_i when the
+   *                column side is not the row side) as |i-bar| x k_i per
+   *                node, every B_ij over L, every near block over L^-;
+   *   bytes_smash  the storage of Sec. 2.3 (end): per node G_i and the index
+   *                lists of its grid (sel), the pair lists, and the near
+   *                blocks; a coupling block is fixed by its skeleton index
+   *                sets, so no B_ij is stored. */
+  int64_t bytes_dense, bytes_hss0, bytes_smash;
 } smash_info_t;
 
 #define SMASH_PHASE_TREE 0

@@ -88,7 +88,8 @@ class Info(C.Structure):
                 ("phase_ms", C.c_double * 16), ("phase_calls", C.c_int64 * 16),
                 ("graph_captures", C.c_int64), ("graph_replays", C.c_int64),
                 ("coupling_evaluated", C.c_int32), ("coupling_chunks", C.c_int32),
-                ("coupling_ws_entries", C.c_int64)]
+                ("coupling_ws_entries", C.c_int64), ("bytes_dense", C.c_int64),
+                ("bytes_hss0", C.c_int64), ("bytes_smash", C.c_int64)]
 
 PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", "mv_up",
           "mv_coupling", "mv_down", "mv_near_out"]

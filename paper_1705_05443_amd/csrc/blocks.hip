@@ -259,6 +259,15 @@ __global__ void k_chunk_bounds(int nnodes, const int *Lrow, const int64_t *boff,
   ent[c] = boff[Lrow[lo]];
 }
 
+// Coordinates of every slot of one side: out[s d + t] = P[slot_id[s] d + t].
+__global__ void k_slot_coords(int64_t nslots, int d, const int *slot_id, const double *P,
+                              double *out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nslots * d) return;
+  const int64_t sl = e / d;
+  out[e] = P[(int64_t)slot_id[sl] * d + (e - sl * d)];
+}
+
 // One second stream and completion event per device and host thread,
 // default priority, created on first use and kept for the process.
 static void side_stream(int dev, hipStream_t &st, hipEvent_t &ready, hipEvent_t &done) {
@@ -375,8 +384,7 @@ void build_blocks(Handle &h) {
                 : bf                      ? sizeof(unsigned short)
                                           : sizeof(float);
     bool f32math = h.eval_prec == SMASH_F32;
-    (void)R;
-    (void)C;
+    (void)f32math;
     // coupling: offsets and total were set with the generators' last host
     // read (coupling_offsets)
     // coupling blocks stored, or evaluated by each product in chunks
@@ -387,7 +395,24 @@ void build_blocks(Handle &h) {
         evaluated = (double)es * (double)h.b_entries > 0.75 * (double)fr;
     }
     h.coupling_eval = evaluated && h.nL > 0 && h.b_entries > 0;
-    if (h.coupling_eval) {
+    // FP64 and FP32 apply: the blocks are evaluated inside the contraction
+    // from the skeleton slots' coordinates; BF16 apply: a chunk of pairs at
+    // a time into a workspace, then the BF16 contraction
+    h.coupling_fused = h.coupling_eval && !bf;
+    if (h.coupling_fused) {
+      auto coords = [&](Side &S, const double *P) {
+        double *c = h.mem.alloc_n<double>((size_t)S.nslots * h.d);
+        if (S.nslots > 0) {
+          k_slot_coords<<<ceil_div(S.nslots * h.d, 256), 256, 0, s>>>(S.nslots, h.d, S.slot_id,
+                                                                      P, c);
+          SMASH_CHECK_LAUNCH();
+        }
+        return c;
+      };
+      h.xs_slot = coords(R, h.Xp);
+      h.ys_slot = h.col == &h.row && h.Yp == h.Xp ? h.xs_slot : coords(C, h.Yp);
+      h.B = nullptr;
+    } else if (h.coupling_eval) {
       const int64_t cap = h.coupling_chunk > 0
                               ? h.coupling_chunk
                               : std::max<int64_t>((int64_t)(256 << 20) / (int64_t)es, 1);

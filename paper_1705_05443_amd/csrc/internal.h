@@ -213,6 +213,11 @@ struct Handle {
   int coupling_mode = SMASH_COUPLING_AUTO;
   int64_t coupling_chunk = 0;
   bool coupling_eval = false;
+  // evaluated form fused into the contraction (FP64 and FP32 apply): the
+  // coordinates of every slot, D per slot, of the row side and the column
+  // side (the same array when the column side is the row side)
+  bool coupling_fused = false;
+  double *xs_slot = nullptr, *ys_slot = nullptr;
   std::vector<int> cchunk_node;
   std::vector<int64_t> cchunk_pair, cchunk_ent;
   void *Bws = nullptr;

@@ -302,6 +302,122 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
   }
 }
 
+// ---- coupling with the blocks evaluated inside the contraction -----------
+// The index-only form (Sec. 1.1: a block is fixed by its row and column
+// index sets; Sec. 2.3 end): no block is stored.  The same workgroup and
+// matrix-core layout as k_mv_coupling, but each lane computes the entry
+// B_ij(t, s) = kappa(x_t, y_s) it feeds to the matrix core, from the
+// coordinates of the skeleton slots (gathered once per construction), with
+// the same kernel-value function the stored form uses -- so the product is
+// the stored form's bit for bit.  Every entry is evaluated once per product
+// and feeds CT matrix-core steps (one per 16 right-hand sides).
+struct CouplingPts {
+  const double *xs, *ys;  // D coordinates per slot: row side (X), column side (Y)
+  double diag;
+  int f32math;
+};
+
+template <class T, int KID, int D>
+__device__ __forceinline__ T coupling_entry(const double *xp, const double *yp,
+                                            const CouplingPts &P) {
+  if (P.f32math) return (T)kernel_f32_t<KID, D>(xp, yp, (float)P.diag);
+  return (T)kernel_f64_t<KID, D>(xp, yp, P.diag);
+}
+
+template <class T, int TT, int CT, int KID, int D>
+__global__ void __launch_bounds__(MV_NT *MV_WAVES)
+    k_mv_coupling_eval(CouplingArgs A, CouplingPts P, const T *__restrict__ qh,
+                       T *__restrict__ zh, int RP, int nitems) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
+  const int it = item_of_block(blockIdx.x, nitems, A.xrun);
+  if (it >= nitems) return;
+  const int i = A.i0 + it;
+  const int ki = A.krow[i];
+  if (ki == 0) return;
+  const int w = threadIdx.x / MV_NT;
+  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
+  T *out = zh + A.hrow[i] * RP + lr;
+  const double *xi = P.xs + A.hrow[i] * D;
+  const int p0 = A.Lrow[i], p1 = A.Lrow[i + 1];
+  for (int t0 = 0; t0 < ki; t0 += 16 * TT) {
+    // coordinates of this lane's rows t = t0 + 16 tt + lr
+    double xr[TT][D];
+    bool tin[TT];
+#pragma unroll
+    for (int tt = 0; tt < TT; tt++) {
+      const int t = t0 + tt * 16 + lr;
+      tin[tt] = t < ki;
+#pragma unroll
+      for (int e = 0; e < D; e++) xr[tt][e] = tin[tt] ? xi[(int64_t)t * D + e] : 0.0;
+    }
+    acc_t acc[TT * CT];
+#pragma unroll
+    for (int x = 0; x < TT * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
+    for (int p = p0 + w; p < p1; p += MV_WAVES) {
+      const int j = A.Lj[p];
+      const int kj = A.kcol[j];
+      const T *qj = qh + A.hcol[j] * RP + lr;
+      const double *yj = P.ys + A.hcol[j] * D;
+      for (int s0 = 0; s0 < kj; s0 += 16) {
+        T bv[4][CT], av[4][TT];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int s = s0 + 4 * u + lk;
+          const bool ks = s < kj;
+#pragma unroll
+          for (int c = 0; c < CT; c++) bv[u][c] = ks ? qj[(int64_t)s * RP + 16 * c] : (T)0;
+          double yc[D];
+#pragma unroll
+          for (int e = 0; e < D; e++) yc[e] = ks ? yj[(int64_t)s * D + e] : 0.0;
+#pragma unroll
+          for (int tt = 0; tt < TT; tt++)
+            av[u][tt] = (ks && tin[tt]) ? coupling_entry<T, KID, D>(xr[tt], yc, P) : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+#pragma unroll
+          for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+            for (int c = 0; c < CT; c++)
+              acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
+      }
+    }
+    reduce_waves_n<T, MV_WAVES, TT * CT>(acc, red);
+    if (w == 0)
+#pragma unroll
+      for (int tt = 0; tt < TT; tt++)
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+          const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
+          if (t < ki)
+#pragma unroll
+            for (int c = 0; c < CT; c++) out[(int64_t)t * RP + 16 * c] = acc[tt * CT + c][e];
+        }
+  }
+}
+
+template <class T, int CT, int KID, int D>
+static void launch_coupling_eval_kd(const CouplingArgs &ca, const CouplingPts &pts, const T *q,
+                                    T *z, int RP, int nitems, hipStream_t s) {
+  constexpr int TT = MvShape<T, CT>::TT;
+  k_mv_coupling_eval<T, TT, CT, KID, D>
+      <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, pts, q, z, RP, nitems);
+  SMASH_CHECK_LAUNCH();
+}
+
+template <class T, int CT>
+static void launch_coupling_eval(const Handle &h, const CouplingArgs &ca, const CouplingPts &pts,
+                                 const T *q, T *z, int RP, int nitems, hipStream_t s) {
+#define SMASH_CE(KID, D)                                                           if (h.kid == KID && h.d == D) {                                                    launch_coupling_eval_kd<T, CT, KID, D>(ca, pts, q, z, RP, nitems, s);             return;                                                                        }
+  SMASH_CE(SMASH_KERNEL_INV_R, 1) SMASH_CE(SMASH_KERNEL_INV_R, 2) SMASH_CE(SMASH_KERNEL_INV_R, 3)
+  SMASH_CE(SMASH_KERNEL_LOG_R, 1) SMASH_CE(SMASH_KERNEL_LOG_R, 2) SMASH_CE(SMASH_KERNEL_LOG_R, 3)
+  SMASH_CE(SMASH_KERNEL_EXP_R, 1) SMASH_CE(SMASH_KERNEL_EXP_R, 2) SMASH_CE(SMASH_KERNEL_EXP_R, 3)
+  SMASH_CE(SMASH_KERNEL_CAUCHY, 1)
+#undef SMASH_CE
+  throw Error{SMASH_E_UNSUPPORTED, "kernel and dimension without an evaluated coupling form"};
+}
+
 // ---- downward pass: grid rows (=/+=) P [I; G] z-hat_i -----------------------
 // A[a][t] = G[a][t] at Gt[t*(m-k) + a]; Bv row t = z-hat row t.
 template <class T, int W>
@@ -915,17 +1031,38 @@ static void matvec_chunk(Handle &h, const T *X, int64_t ldx, int R, T *Y, int64_
           default: launch_coupling<T, 4>(ca, q, z, RP, nitems, s); break;
         }
       };
-      coupling_chunks(h, ca, sizeof(T), s, [&](int n0, int n1) {
+      if (h.coupling_fused) {
+        const CouplingPts pts{h.xs_slot, h.ys_slot, h.diag, h.eval_prec == SMASH_F32 ? 1 : 0};
+        auto fused = [&](int nitems) {
+          switch (ct) {
+            case 1: launch_coupling_eval<T, 1>(h, ca, pts, q, z, RP, nitems, s); break;
+            case 2: launch_coupling_eval<T, 2>(h, ca, pts, q, z, RP, nitems, s); break;
+            case 3: launch_coupling_eval<T, 3>(h, ca, pts, q, z, RP, nitems, s); break;
+            default: launch_coupling_eval<T, 4>(h, ca, pts, q, z, RP, nitems, s); break;
+          }
+        };
         if (h.batched) {
-          ca.i0 = n0;
-          coupling(n1 - n0);
+          ca.i0 = 1;
+          fused((int)h.nnodes - 1);
         } else {
-          for (int i = n0; i < n1; i++) {
+          for (int i = 1; i < h.nnodes; i++) {
             ca.i0 = i;
-            coupling(1);
+            fused(1);
           }
         }
-      });
+      } else {
+        coupling_chunks(h, ca, sizeof(T), s, [&](int n0, int n1) {
+          if (h.batched) {
+            ca.i0 = n0;
+            coupling(n1 - n0);
+          } else {
+            for (int i = n0; i < n1; i++) {
+              ca.i0 = i;
+              coupling(1);
+            }
+          }
+        });
+      }
     }
     PhaseTimer pt(h, SMASH_PHASE_MV_DOWN, s);
     for (int l = 2; l <= h.nlevels; l++) {

@@ -338,8 +338,9 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
     info->build_ms = h->build_ms;
     info->total_swaps = h->total_swaps;
     info->coupling_evaluated = h->coupling_eval ? 1 : 0;
-    info->coupling_chunks = h->coupling_eval ? (int32_t)h->cchunk_node.size() - 1 : 0;
-    info->coupling_ws_entries = h->coupling_eval ? h->bws_entries : 0;
+    const bool chunked = h->coupling_eval && !h->coupling_fused;
+    info->coupling_chunks = chunked ? (int32_t)h->cchunk_node.size() - 1 : 0;
+    info->coupling_ws_entries = chunked ? h->bws_entries : 0;
     info->device_bytes = h->mem.bytes + h->ws_mem.bytes;
     info->graph_captures = h->graph_captures;
     info->graph_replays = h->graph_replays;
@@ -348,7 +349,8 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
       info->phase_ms[q] = h->phase_ms[q];
       info->phase_calls[q] = h->phase_calls[q];
     }
-    auto side_stats = [&](Side &S, int64_t &sumk, int32_t &maxk, int64_t &gent) {
+    int64_t sum_mk[2] = {0, 0}, sum_m[2] = {0, 0};
+    auto side_stats = [&](Side &S, int64_t &sumk, int32_t &maxk, int64_t &gent, int q) {
       auto m = to_host(S.m, h->nnodes), k = to_host(S.k, h->nnodes);
       sumk = 0;
       maxk = 0;
@@ -357,10 +359,18 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
         sumk += k[i];
         maxk = k[i] > maxk ? k[i] : maxk;
         gent += (int64_t)(m[i] - k[i]) * k[i];
+        sum_mk[q] += (int64_t)m[i] * k[i];
+        sum_m[q] += m[i];
       }
     };
-    side_stats(h->row, info->sum_rank_row, info->max_rank_row, info->g_entries_row);
-    side_stats(*h->col, info->sum_rank_col, info->max_rank_col, info->g_entries_col);
+    side_stats(h->row, info->sum_rank_row, info->max_rank_row, info->g_entries_row, 0);
+    side_stats(*h->col, info->sum_rank_col, info->max_rank_col, info->g_entries_col, 1);
+    const int sides = h->reuse ? 1 : 2;
+    info->bytes_dense = 8 * h->nx * h->ny;
+    info->bytes_hss0 = 8 * (sum_mk[0] + (sides > 1 ? sum_mk[1] : 0) + h->b_entries + h->n_entries);
+    info->bytes_smash = 8 * (info->g_entries_row + (sides > 1 ? info->g_entries_col : 0) +
+                             h->n_entries) +
+                        4 * (sum_m[0] + (sides > 1 ? sum_m[1] : 0) + 2 * (h->nL + h->nLm));
     int64_t idx = 2 * h->nx + 2 * h->ny + 2 * (h->nL + h->nLm) + h->row.nslots;
     for (int l = 2; l <= h->nlevels; l++) idx += h->row.lv[l].sel_n;
     if (!h->reuse) {

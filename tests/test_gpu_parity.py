@@ -429,12 +429,14 @@ def test_matvec_bf16_apply(name):
 @pytest.mark.parametrize("name", ["h2_2d_log", "hss1d_cfg", "hss_cauchy_xy", "h2_3d_clusters"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_evaluated_coupling_equals_stored(name, prec):
-    """Coupling blocks evaluated inside each product, a chunk of pairs at a
-    time (chunks of 3000 entries here, so every product runs many chunks and
-    chunks end inside a row node's pair range), give the product of the
-    stored blocks bit for bit: the same block values enter the same
-    contraction.  Also checks the chunk bookkeeping through smash_info and
-    that the exported (re-evaluated) blocks equal the stored ones."""
+    """Coupling blocks evaluated inside each product -- by each lane right
+    before its matrix-core step (FP64, FP32 apply), or a chunk of pairs at a
+    time through a workspace (BF16 apply; chunks of 3000 entries here, so
+    every product runs many chunks and chunks end inside a row node's pair
+    range) -- give the product of the stored blocks bit for bit: the same
+    block values enter the same contraction.  Also checks the bookkeeping
+    through smash_info and that the exported (re-evaluated) blocks equal the
+    stored ones."""
     mk, kw = CASES[name]
     x, y = mk()
     ev = "f64" if prec == "f64" else "f32"
@@ -446,10 +448,14 @@ def test_evaluated_coupling_equals_stored(name, prec):
     assert is_["coupling_evaluated"] == 0
     if is_["coupling_entries"] > 0:
         assert ie["coupling_evaluated"] == 1
-        assert ie["coupling_chunks"] >= is_["coupling_entries"] // 3000
-        assert 3000 <= ie["coupling_ws_entries"] or ie["coupling_chunks"] == 1
-        if ie["coupling_chunks"] > 2:
-            assert ie["coupling_ws_entries"] < is_["coupling_entries"]
+        if prec == "bf16":  # a chunk of pairs at a time through a workspace
+            assert ie["coupling_chunks"] >= is_["coupling_entries"] // 3000
+            assert 3000 <= ie["coupling_ws_entries"] or ie["coupling_chunks"] == 1
+            if ie["coupling_chunks"] > 2:
+                assert ie["coupling_ws_entries"] < is_["coupling_entries"]
+        else:  # evaluated inside the contraction: no workspace
+            assert ie["coupling_chunks"] == 0 and ie["coupling_ws_entries"] == 0
+            assert ie["device_bytes"] < is_["device_bytes"]
     dt = torch.float64 if prec == "f64" else torch.float32
     for nrhs in (1, 16, 40):
         q = torch.from_numpy(W.rhs(gs.ny, nrhs, seed=6)).to(dt).cuda()
@@ -739,3 +745,25 @@ def test_products_of_one_handle_on_two_streams_are_ordered():
             assert torch.equal(o, r), (rep, c)
     h.close()
     ref_h.close()
+
+
+@pytest.mark.parametrize("name", ["h2_2d_log", "hss1d_cfg", "hss_cauchy_xy"])
+def test_storage_accounting(name):
+    """smash_info's storage comparison (Sec. 6.6, Table 6.6): recomputed here
+    from the exported ranks and lists -- the dense matrix, the generators as
+    dense matrices (HSS0), and G with the index sets (B fixed by the
+    skeletons) -- and SMASH below HSS0 below the dense matrix."""
+    x, y, o, g = pair_for(name)
+    inf = g.info()
+    rk = g.export("ranks").reshape(-1, 6)[1:]
+    sides = [(0, 1)] if inf["symmetric_reuse"] else [(0, 1), (2, 3)]
+    mk = sum(int(np.sum(rk[:, a].astype(np.int64) * rk[:, b])) for a, b in sides)
+    gk = sum(int(np.sum((rk[:, a] - rk[:, b]).astype(np.int64) * rk[:, b])) for a, b in sides)
+    sm = sum(int(np.sum(rk[:, a].astype(np.int64))) for a, _ in sides)
+    nL, nLm = len(g.export("L")) // 2, len(g.export("Lm")) // 2
+    assert inf["bytes_dense"] == 8 * inf["nx"] * inf["ny"]
+    assert inf["bytes_hss0"] == 8 * (mk + inf["coupling_entries"] + inf["near_entries"])
+    assert inf["bytes_smash"] == 8 * (gk + inf["near_entries"]) + 4 * (sm + 2 * (nL + nLm))
+    print(name, "storage MB: dense %.1f HSS0 %.2f SMASH %.2f" % (
+        inf["bytes_dense"] / 1e6, inf["bytes_hss0"] / 1e6, inf["bytes_smash"] / 1e6))
+    assert inf["bytes_smash"] < inf["bytes_hss0"] < inf["bytes_dense"]
