@@ -11,21 +11,20 @@
 //     G with U = P [I; G] (eq. (2.11)), stored canonically (both index sets
 //     ascending).
 //
-// One workgroup of NT threads owns one node at a time (persistent grid
-// striding over the level's nodes).  M = C^T lives in a per-workgroup tile
-// W (c rows x m columns, row-major, column a = grid point a) in global
-// memory that stays L2-resident; each thread owns grid columns a = tid,
-// tid + NT, ... so every row access is coalesced.  Column norms for the
-// pivot choice are recomputed from the transformed columns after each
-// Householder step (no downdating), the argmax is a wavefront shuffle
-// reduction, and ties go to the lowest position.  All arithmetic is FP64.
+// One workgroup owns one node at a time (persistent grid striding over the
+// level's nodes).  Two forms: the register form (k_compr_w) keeps the
+// columns of M = C^T in registers for grids of up to 256 points and c <= 64;
+// the wide form (k_compr_s) streams them from a column-major tile in LDS or
+// in a per-workgroup global scratch.  Column norms for the pivot choice are
+// recomputed from the transformed columns after each Householder step (no
+// downdating), the arg-max is a DPP reduction, and ties go to the lowest
+// position.  All arithmetic is FP64.
 #include <algorithm>
 
 #include "common.cuh"
 
 namespace smash {
 
-constexpr int ID_NT = 256;
 constexpr int ID_CMAX = 512;  // largest basis width c (p^d plus HSS near vectors)
 constexpr int ID_PMAX = 64;   // largest interpolation order
 
@@ -45,15 +44,13 @@ struct IdArgs {
   const int64_t *S_off;
   const int *ks;
   double tol, f;
-  double *scratch;  // per workgroup: W (c x ldw), F (d*p x ldw), Nrm (ldw), Ri (c*c)
-  int ldw;
-  int64_t wg_stride;
-  int *iscratch;  // per workgroup: perm (ldw), pos (ldw)
-  int64_t wg_istride;
   int *swaps;    // total swap count (atomic)
   int *err;      // set to 1 when the swap cap is hit
   int gt_out;    // k_compr_w: write G^T (k x (m-k) row-major) instead of G
   double *G2_out;  // k_compr_w: also the other orientation there (null: not)
+  // k_compr_w: with `order`, the nodes order[*ord_lo .. ne - nb) (the rest
+  // of a level whose largest grids went to the wide form); else nb .. ne-1
+  const int *order, *ord_lo;
 };
 
 // ---- lane exchanges (DPP) ------------------------------------------------
@@ -215,327 +212,6 @@ __device__ inline double block_sum(double v, double *lds) {
   return r;
 }
 
-// ---- interpolation basis column ----------------------------------------
-// Column a of M = C^T: the c0 tensor Lagrange values at grid point a
-// (barycentric form; an exact node hit gives the Kronecker delta), then the
-// ks near-field vector entries of row a.
-__device__ inline void basis_column(const IdArgs &A, int i, int a, int src_a, double *W,
-                                    double *F, int ldw, int ks, const double *xi,
-                                    const double *wk) {
-  const int d = A.d, p = A.p;
-  int64_t id = A.slot_id[A.gbeg[i] + src_a];
-  for (int t = 0; t < d; t++) {
-    double x = A.P[id * d + t];
-    double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
-    double *Ft = F + (int64_t)(t * p) * ldw + a;
-    if (hi - lo == 0.0) {
-      for (int k = 0; k < p; k++) Ft[(int64_t)k * ldw] = k == 0 ? 1.0 : 0.0;
-      continue;
-    }
-    int hit = -1;
-    double den = 0.0;
-    for (int k = 0; k < p; k++) {
-      double xk = xi[t * ID_PMAX + k];
-      if (x == xk) {
-        hit = k;
-        break;
-      }
-      double v = wk[k] / (x - xk);
-      Ft[(int64_t)k * ldw] = v;
-      den += v;
-    }
-    if (hit >= 0) {
-      for (int k = 0; k < p; k++) Ft[(int64_t)k * ldw] = k == hit ? 1.0 : 0.0;
-    } else {
-      for (int k = 0; k < p; k++) Ft[(int64_t)k * ldw] = Ft[(int64_t)k * ldw] / den;
-    }
-  }
-  for (int r = 0; r < A.c0; r++) {
-    int q = r;
-    double v = 1.0;
-    for (int t = d - 1; t >= 0; t--) {
-      v *= F[(int64_t)(t * p + q % p) * ldw + a];
-      q /= p;
-    }
-    W[(int64_t)r * ldw + a] = v;
-  }
-  if (ks > 0) {
-    const double *Sa = A.S + A.S_off[i - A.nb] + (int64_t)src_a * ks;
-    for (int q = 0; q < ks; q++) W[(int64_t)(A.c0 + q) * ldw + a] = Sa[q];
-  }
-}
-
-// ---- Householder step on column t (rows t..c-1), applied to columns
-// t+1..m-1; with `norms`, the new residual norms over rows t+1..c-1 are
-// stored in Nrm.  v lives in LDS.  alpha = residual norm of column t.
-__device__ inline void householder(double *W, int ldw, int c, int m, int t, double alpha,
-                                   double *v, double *red, double *Nrm, bool norms) {
-  const int tid = threadIdx.x;
-  double x0 = W[(int64_t)t * ldw + t];
-  double rtt = x0 >= 0.0 ? -alpha : alpha;
-  for (int r = t + 1 + tid; r < c; r += ID_NT) v[r - t] = W[(int64_t)r * ldw + t];
-  double part = 0.0;
-  for (int r = t + 1 + tid; r < c; r += ID_NT) {
-    double y = W[(int64_t)r * ldw + t];
-    part += y * y;
-  }
-  double rest = block_sum<ID_NT / WAVE>(part, red);  // ends with barriers
-  double v0 = x0 - rtt;
-  double vn = rest + v0 * v0;
-  if (tid == 0) v[0] = v0;
-  __syncthreads();
-  if (alpha != 0.0 && vn > 0.0) {
-    for (int a = t + 1 + tid; a < m; a += ID_NT) {
-      double w = 0.0;
-      for (int r = t; r < c; r++) w = fma(v[r - t], W[(int64_t)r * ldw + a], w);
-      double sc = 2.0 * w / vn;
-      double s2 = 0.0;
-      for (int r = t; r < c; r++) {
-        double y = fma(-sc, v[r - t], W[(int64_t)r * ldw + a]);
-        W[(int64_t)r * ldw + a] = y;
-        if (r > t) s2 = fma(y, y, s2);
-      }
-      if (norms) Nrm[a] = sqrt(s2);
-    }
-  } else if (norms) {
-    for (int a = t + 1 + tid; a < m; a += ID_NT) {
-      double s2 = 0.0;
-      for (int r = t + 1; r < c; r++) {
-        double y = W[(int64_t)r * ldw + a];
-        s2 = fma(y, y, s2);
-      }
-      Nrm[a] = sqrt(s2);
-    }
-  }
-  __syncthreads();
-  if (alpha != 0.0) {
-    for (int r = t + tid; r < c; r += ID_NT) W[(int64_t)r * ldw + t] = r == t ? rtt : 0.0;
-  }
-  __syncthreads();
-}
-
-// Steps 3-4 of compr on the workgroup tile W (c x m, columns in position
-// order, perm[pos] = grid index), after a pivoted QR that kept k columns:
-// the Gu-Eisenstat swap loop, then the canonical output (sel, G, k).
-__device__ void compr_tail(const IdArgs &A, int i, int m, int c, int ks, int k, double *W,
-                           double *F, double *Nrm, double *Ri, int *perm, int *pos, int ldw,
-                           const double *xi, const double *wk, double *v, double *rinv,
-                           double *red, ArgMax *ared, int64_t *sred) {
-  const int tid = threadIdx.x;
-  const int NTB = ID_NT;
-  // 3. Gu-Eisenstat swaps
-  const int nr = m - k;
-  int nsw = 0;
-  bool failed = false;
-  if (k > 0 && nr > 0) {
-    for (;;) {
-      // N = R11^{-1} R12 (over R12, in place) and gamma_j = |R22 column j|
-      for (int a = k + tid; a < m; a += NTB) {
-        for (int ii = k - 1; ii >= 0; ii--) {
-          double s = W[(int64_t)ii * ldw + a];
-          for (int q = ii + 1; q < k; q++)
-            s = fma(-W[(int64_t)ii * ldw + q], W[(int64_t)q * ldw + a], s);
-          W[(int64_t)ii * ldw + a] = s / W[(int64_t)ii * ldw + ii];
-        }
-        double g2 = 0.0;
-        for (int r = k; r < c; r++) {
-          double y = W[(int64_t)r * ldw + a];
-          g2 = fma(y, y, g2);
-        }
-        Nrm[a] = sqrt(g2);
-      }
-      // R11^{-1}, column j per thread
-      for (int j = tid; j < k; j += NTB) {
-        for (int ii = k - 1; ii >= 0; ii--) {
-          double s = ii == j ? 1.0 : 0.0;
-          for (int q = ii + 1; q < k; q++)
-            s = fma(-W[(int64_t)ii * ldw + q], Ri[(int64_t)q * k + j], s);
-          Ri[(int64_t)ii * k + j] = s / W[(int64_t)ii * ldw + ii];
-        }
-      }
-      __syncthreads();
-      for (int ii = tid; ii < k; ii += NTB) {
-        double s = 0.0;
-        for (int j = 0; j < k; j++) {
-          double y = Ri[(int64_t)ii * k + j];
-          s = fma(y, y, s);
-        }
-        rinv[ii] = sqrt(s);
-      }
-      __syncthreads();
-      // rho_ij = sqrt(N_ij^2 + (gamma_j / omega_i)^2); arg-max, ties:
-      // smallest j, then smallest i (pair index j*k + i)
-      ArgMax am{-1.0, -1};
-      for (int a = k + tid; a < m; a += NTB) {
-        double g = Nrm[a];
-        for (int ii = 0; ii < k; ii++) {
-          double nv = W[(int64_t)ii * ldw + a];
-          double b = g * rinv[ii];
-          double rho = sqrt(nv * nv + b * b);
-          am = amax_pick(am, ArgMax{rho, (a - k) * k + ii});
-        }
-      }
-      am = block_argmax<ID_NT / WAVE>(am, ared);
-      if (!(am.v > A.f)) break;
-      if (++nsw > 64 * k) {
-        failed = true;
-        break;
-      }
-      const int bj = am.a / k, bi = am.a % k;
-      __syncthreads();
-      if (tid == 0) {
-        int tp = perm[bi];
-        perm[bi] = perm[k + bj];
-        perm[k + bj] = tp;
-      }
-      __syncthreads();
-      // refactor the new column order without pivoting
-      for (int a = tid; a < m; a += NTB) basis_column(A, i, a, perm[a], W, F, ldw, ks, xi, wk);
-      __syncthreads();
-      for (int t = 0; t < k; t++) {
-        double part = 0.0;
-        for (int r = t + tid; r < c; r += NTB) {
-          double y = W[(int64_t)r * ldw + t];
-          part = fma(y, y, part);
-        }
-        double alpha = sqrt(block_sum<ID_NT / WAVE>(part, red));
-        householder(W, ldw, c, m, t, alpha, v, red, Nrm, false);
-      }
-    }
-  } else if (k > 0) {
-    // k == m: nothing to solve
-  }
-  if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
-  if (failed) {
-    if (tid == 0) atomicOr(A.err, 1);
-    k = 0;
-  }
-  // 4. canonical output: skeleton positions ascending, then the rest
-  __syncthreads();
-  for (int a = tid; a < m; a += NTB) pos[a] = 0;
-  __syncthreads();
-  for (int q = tid; q < k; q += NTB) pos[perm[q]] = 1;
-  __syncthreads();
-  {
-    const int chunk = (m + NTB - 1) / NTB;
-    const int a0 = tid * chunk;
-    int64_t cnt = 0;
-    for (int u = 0; u < chunk; u++)
-      if (a0 + u < m) cnt += pos[a0 + u];
-    int64_t tot;
-    int64_t ex = block_excl_scan_i64<ID_NT / WAVE>(cnt, &tot, sred);
-    int *sel = A.sel_out + A.selo[i];
-    for (int u = 0; u < chunk; u++) {
-      int a = a0 + u;
-      if (a >= m) break;
-      int fl = pos[a];
-      if (fl)
-        sel[ex] = a;
-      else
-        sel[k + (a - ex)] = a;
-      pos[a] = fl ? (int)ex : -(int)(a - ex) - 1;  // skeleton rank, or -(rest rank)-1
-      ex += fl;
-    }
-  }
-  __syncthreads();
-  if (k > 0 && nr > 0) {
-    double *G = A.G_out + A.go[i];
-    for (int a = k + tid; a < m; a += NTB) {
-      int row = -pos[perm[a]] - 1;
-      for (int ii = 0; ii < k; ii++) G[(int64_t)row * k + pos[perm[ii]]] = W[(int64_t)ii * ldw + a];
-    }
-  }
-  if (tid == 0) A.k_out[i] = k;
-}
-
-__global__ void __launch_bounds__(ID_NT) k_compr(IdArgs A) {
-  __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
-  __shared__ double v[ID_CMAX + 1], rinv[ID_CMAX];
-  __shared__ double red[ID_NT / WAVE + 1];
-  __shared__ ArgMax ared[ID_NT / WAVE + 1];
-  __shared__ int64_t sred[ID_NT / WAVE + 1];
-  const int tid = threadIdx.x;
-  const int p = A.p;
-  if (tid < p) {
-    double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
-    chc[tid] = cos(th);
-    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
-  }
-  double *W = A.scratch + (int64_t)blockIdx.x * A.wg_stride;
-  const int ldw = A.ldw;
-  int *perm = A.iscratch + (int64_t)blockIdx.x * A.wg_istride;
-  int *pos = perm + ldw;
-  for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
-    const int m = A.m[i];
-    const int ks = A.S ? A.ks[i] : 0;
-    const int c = A.c0 + ks;
-    double *F = W + (int64_t)c * ldw;
-    double *Nrm = F + (int64_t)A.d * p * ldw;
-    double *Ri = Nrm + ldw;
-    __syncthreads();
-    if (tid < A.d * p) {
-      int t = tid / p, k = tid % p;
-      double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
-      xi[t * ID_PMAX + k] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[k];
-    }
-    __syncthreads();
-    if (m == 0) {
-      if (tid == 0) A.k_out[i] = 0;
-      continue;
-    }
-    // 1. C^T into W, initial column norms
-    for (int a = tid; a < m; a += ID_NT) {
-      basis_column(A, i, a, a, W, F, ldw, ks, xi, wk);
-      perm[a] = a;
-      double s2 = 0.0;
-      for (int r = 0; r < c; r++) {
-        double y = W[(int64_t)r * ldw + a];
-        s2 = fma(y, y, s2);
-      }
-      Nrm[a] = sqrt(s2);
-    }
-    __syncthreads();
-    // 2. Householder QR with column pivoting; rank by tol * |R_11|
-    const int kmax = m < c ? m : c;
-    int k = 0;
-    double r00 = 0.0;
-    for (int t = 0; t < kmax; t++) {
-      ArgMax am{-1.0, -1};
-      for (int a = t + tid; a < m; a += ID_NT) am = amax_pick(am, ArgMax{Nrm[a], a});
-      am = block_argmax<ID_NT / WAVE>(am, ared);
-      double bn = am.v;
-      if (t == 0) {
-        r00 = bn;
-        if (!(r00 > 0.0)) break;
-      } else if (!(bn > A.tol * r00)) {
-        break;
-      }
-      int best = am.a;
-      if (best != t) {
-        for (int r = tid; r < c; r += ID_NT) {
-          double tmp = W[(int64_t)r * ldw + t];
-          W[(int64_t)r * ldw + t] = W[(int64_t)r * ldw + best];
-          W[(int64_t)r * ldw + best] = tmp;
-        }
-        __syncthreads();
-        if (tid == 0) {
-          int tp = perm[t];
-          perm[t] = perm[best];
-          perm[best] = tp;
-          double tn = Nrm[t];
-          Nrm[t] = Nrm[best];
-          Nrm[best] = tn;
-        }
-      }
-      __syncthreads();
-      householder(W, ldw, c, m, t, bn, v, red, Nrm, true);
-      k = t + 1;
-    }
-    compr_tail(A, i, m, c, ks, k, W, F, Nrm, Ri, perm, pos, ldw, xi, wk, v, rinv, red, ared,
-               sred);
-  }
-}
-
 // ------------------------------------------------------------------------
 // Register-resident compr for nodes whose grid fits one workgroup and whose
 // basis width fits CMAX.  Columns of M = C^T are held in registers for the
@@ -592,7 +268,9 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
     chc[tid] = cos(th);
     wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
   }
-  for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
+  const int e0 = A.order ? *A.ord_lo : 0;
+  for (int e = e0 + blockIdx.x; e < A.ne - A.nb; e += gridDim.x) {
+    const int i = A.order ? A.order[e] : A.nb + e;
     const int m = A.m[i];
     const int ks = A.S ? A.ks[i] : 0;
     const int c = A.c0 + ks;
@@ -1011,6 +689,557 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
     }
     if (tid == 0) A.k_out[i] = k;
   }
+}
+
+// ------------------------------------------------------------------------
+// compr for wide bases and large grids (beyond the register form's c <= 64
+// and m <= 256).  The algorithm and its conventions are those of k_compr_w:
+// positions are labels (a pivot or a Gu-Eisenstat swap relabels two
+// columns), the pivot is the largest squared residual norm with ties to the
+// lowest position, each Householder step has one barrier (every wavefront
+// stages its candidate column in LDS before it), the swap test solves R11
+// by column back substitution with the reciprocal diagonal, and the
+// canonical output comes from a block scan.  What differs is where the
+// columns of M = C^T live: in a column-major tile (column a at a * ldc,
+// rows contiguous) that every step streams through registers once -- in
+// LDS when the node's tile fits there, else in a per-workgroup global
+// scratch that stays in L2 and the infinity cache.  Groups of 16 lanes own
+// columns a = g, g + 32, ... (lane h holds rows h, h + 16, ...), so a
+// column slice is one 128-byte segment per 16 rows and a column sum is four
+// DPP exchanges inside the group.  A launch takes its nodes from a list
+// ordered by decreasing grid size, so the longest nodes start first.
+constexpr int CS_NT = 512;
+constexpr int CS_LPC = 16;
+constexpr int CS_NG = CS_NT / CS_LPC;  // column groups
+constexpr int CS_NW = CS_NT / WAVE;    // wavefronts
+
+struct CsArgs {
+  const int *order;  // node ids of the level, largest grid first
+  const int *cnt;    // device: the launch takes order[0, *cnt)
+  int ldc;           // column stride of the tile (a multiple of 16, >= c)
+  int lds_cols;      // grids of at most this many points keep the tile in LDS
+  int mmax;          // largest grid of the level
+  double *gscr;      // per workgroup: tile (mmax x ldc), norms (mmax), R11^-1 (CMAX^2)
+  int64_t gstride;
+  int *iscr;         // per workgroup: labels (mmax), skeleton counts (mmax)
+  int64_t istride;
+};
+
+// sums, maxima and broadcasts inside a group of 16 lanes (one DPP row);
+// every lane of the group ends with the same bits
+__device__ __forceinline__ double g16_sum(double x) {
+  x += perm_f64<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += perm_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += perm_f64<0x141>(x);  // row_half_mirror: the other quad of the half row
+  x += perm_f64<0x140>(x);  // row_mirror: the other half of the row
+  return x;
+}
+__device__ __forceinline__ int g16_max(int x) {
+  x = max(x, perm_i32<0xB1>(x));
+  x = max(x, perm_i32<0x4E>(x));
+  x = max(x, perm_i32<0x141>(x));
+  x = max(x, perm_i32<0x140>(x));
+  return x;
+}
+
+struct CsShared {
+  const double *xi, *wk;
+  double *slots, *Fg, *rdiag, *rdg, *rinv;
+  int *piv, *msrc;
+  ArgMax *meta, *ared;
+  int64_t *sred;
+};
+
+// One node: W (tile), nrm2 (squared residual norms), lab (position labels),
+// exs (skeleton columns before each grid index) in LDS (LT) or in the
+// workgroup's global scratch; Rinv (R11^-1, k x k by columns) global; Lr
+// (global tile only) LDS for rcap columns of R11 at a time.
+template <int CMAX, bool LT>
+__device__ __forceinline__ void compr_node_s(const IdArgs &A, const CsArgs &B, int i, int m,
+                                             double *W, double *nrm2, int *lab, int *exs,
+                                             double *Rinv, double *Lr, int rcap,
+                                             const CsShared &sh) {
+  constexpr int RL = CMAX / CS_LPC;    // rows per lane
+  constexpr int JB = RL <= 8 ? 4 : 2;  // columns per pass of a group (QR)
+  constexpr int JT = RL <= 8 ? 4 : RL <= 16 ? 2 : 1;  // (the back substitution)
+  const int tid = threadIdx.x, g = tid / CS_LPC, h = tid % CS_LPC;
+  const int wid = tid / WAVE, lane = tid & (WAVE - 1);
+  const int ks = A.S ? A.ks[i] : 0;
+  const int c = A.c0 + ks;
+  const int ldc = B.ldc;
+  const int d = A.d, p = A.p;
+
+  // the columns of C^T from the basis (barycentric tensor Lagrange values,
+  // then the near-field vector entries) and their squared norms; labels
+  // start as the grid index unless `keep` (a refactorization after a swap)
+  auto build = [&](bool keep) {
+    for (int a0 = 0; a0 < m; a0 += CS_NG) {
+      const int a = a0 + g;
+      const bool on = a < m;
+      double *F = sh.Fg + g * (d * p);
+      if (on) {
+        const int64_t id = A.slot_id[A.gbeg[i] + a];
+        for (int t = 0; t < d; t++) {
+          const double x = A.P[id * d + t];
+          const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+          int hit = -1;
+          double den = 0.0;
+          if (hi - lo == 0.0) {
+            hit = 0;
+          } else {
+            for (int q = h; q < p; q += CS_LPC) {
+              const double xq = sh.xi[t * ID_PMAX + q];
+              if (x == xq) {
+                hit = q;
+                break;
+              }
+              const double w = sh.wk[q] / (x - xq);
+              F[t * p + q] = w;
+              den += w;
+            }
+          }
+          hit = g16_max(hit);
+          den = g16_sum(den);
+          for (int q = h; q < p; q += CS_LPC)
+            F[t * p + q] = hit >= 0 ? (q == hit ? 1.0 : 0.0) : F[t * p + q] / den;
+        }
+      }
+      __syncthreads();
+      if (on) {
+        const double *Sa = ks > 0 ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
+        double s2 = 0.0;
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int r = CS_LPC * u + h;
+          if (r < c) {
+            double val;
+            if (r < A.c0) {
+              int q = r;
+              val = 1.0;
+              for (int t = d - 1; t >= 0; t--) {
+                val *= F[t * p + q % p];
+                q /= p;
+              }
+            } else {
+              val = Sa[r - A.c0];
+            }
+            W[(int64_t)a * ldc + r] = val;
+            s2 = fma(val, val, s2);
+          }
+        }
+        s2 = g16_sum(s2);
+        if (h == 0) {
+          nrm2[a] = s2;
+          if (!keep) lab[a] = a;
+        }
+      }
+      __syncthreads();
+    }
+  };
+
+  // Each wavefront's candidate for step t: the group holding the wave's
+  // arg-max copies its column into the wave's slot.  Every lane copies the
+  // rows it wrote itself in the last update (so it reads its own stores).
+  // Slots and entries alternate by step parity.
+  auto stage = [&](int t, ArgMax best, int bst) {
+    const ArgMax wa = wave_argmax(best);
+    const int e = (t & 1) * CS_NW + wid;
+    if (wa.a >= 0 && best.a == wa.a) {
+      double *slot = sh.slots + (int64_t)e * ldc;
+      const double *cp = W + (int64_t)bst * ldc;
+#pragma unroll
+      for (int u = 0; u < RL; u++) {
+        const int r = CS_LPC * u + h;
+        if (r >= t && r < c) slot[r] = cp[r];
+      }
+      if (h == 0) {
+        sh.meta[e] = wa;
+        sh.msrc[e] = bst;
+      }
+    }
+    if (wa.a < 0 && lane == 0) {
+      sh.meta[e] = ArgMax{-1.0, -1};
+      sh.msrc[e] = -1;
+    }
+  };
+
+  // Householder QR over positions 0..kend-1: with pivoting the pivot of
+  // step t is the largest remaining norm and the loop stops at the rank
+  // test (|R_tt| <= tol |R_00|); without, it is the column labelled t.
+  // Rows < t of a column are its column of R and stay in place; R_tt goes
+  // to rdiag and the storage index of position t to piv.
+  auto qr = [&](bool pivoting, int kend) -> int {
+    if (kend <= 0) return 0;
+    {
+      ArgMax best{-1.0, -1};
+      int bst = -1;
+      for (int a = g; a < m; a += CS_NG) {
+        const int la = lab[a];
+        if (pivoting || la == 0) {
+          const ArgMax y = amax_pick(best, ArgMax{nrm2[a], la});
+          if (y.a == la && best.a != la) {
+            best = y;
+            bst = a;
+          }
+        }
+      }
+      stage(0, best, bst);
+    }
+    int kk = 0;
+    double r00 = 0.0;
+    for (int t = 0; t < kend; t++) {
+      __syncthreads();
+      const int e0 = (t & 1) * CS_NW;
+      const ArgMax we = lane < CS_NW ? sh.meta[e0 + lane] : ArgMax{-1.0, -1};
+      const ArgMax am = lanes_argmax<CS_NW>(we);
+      const double bn = sqrt(am.v);
+      if (pivoting) {
+        if (t == 0) {
+          r00 = bn;
+          if (!(r00 > 0.0)) break;
+        } else if (!(bn > A.tol * r00)) {
+          break;
+        }
+      }
+      const int bp = am.a;
+      if (bp < 0) break;
+      const uint64_t wins = __ballot(lane < CS_NW && we.a == bp);
+      const int ws = (int)__ffsll((unsigned long long)wins) - 1;
+      const int b = sh.msrc[e0 + ws];
+      const double *src = sh.slots + (int64_t)(e0 + ws) * ldc;
+      const double xt = src[t];
+      const double rtt = xt >= 0.0 ? -bn : bn;
+      const double vn = 2.0 * bn * (bn + fabs(xt));
+      const double rv = 2.0 / vn;
+      if (tid == 0) {
+        sh.rdiag[t] = rtt;
+        sh.piv[t] = b;
+      }
+      // v: zero above row t, x_t - R_tt at row t, the column below
+      double v[RL];
+#pragma unroll
+      for (int u = 0; u < RL; u++) {
+        const int r = CS_LPC * u + h;
+        v[u] = (r < t || r >= c) ? 0.0 : (r == t ? src[r] - rtt : src[r]);
+      }
+      ArgMax best{-1.0, -1};
+      int bst = -1;
+      // JB columns per pass of the group: their loads are in flight together
+      for (int a0 = g; a0 < m; a0 += CS_NG * JB) {
+        int na[JB];
+        bool on[JB];
+        double col[JB][RL];
+#pragma unroll
+        for (int j = 0; j < JB; j++) {
+          const int a = a0 + CS_NG * j;
+          on[j] = a < m;
+          const int la = on[j] ? lab[a] : -1;
+          na[j] = a == b ? t : (la == t ? bp : la);  // positions t and bp swap
+          if (on[j] && na[j] != la && h == 0) lab[a] = na[j];
+          on[j] = on[j] && na[j] > t;  // not the pivot of this step or an earlier one
+          const double *cp = W + (int64_t)a * ldc;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int r = CS_LPC * u + h;
+            col[j][u] = (on[j] && r >= t && r < c) ? cp[r] : 0.0;
+          }
+        }
+        // two partial sums per column: half the chain of dependent multiply-adds
+        double sc[JB];
+#pragma unroll
+        for (int j = 0; j < JB; j++) {
+          double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+          for (int u = 0; u < RL; u += 2) {
+            w0 = fma(v[u], col[j][u], w0);
+            if (u + 1 < RL) w1 = fma(v[u + 1], col[j][u + 1], w1);
+          }
+          sc[j] = g16_sum(w0 + w1);
+        }
+#pragma unroll
+        for (int j = 0; j < JB; j++) {
+          const double scj = (on[j] && vn > 0.0) ? sc[j] * rv : 0.0;
+          double *cp = W + (int64_t)(a0 + CS_NG * j) * ldc;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int r = CS_LPC * u + h;
+            const double y = fma(-scj, v[u], col[j][u]);
+            col[j][u] = y;
+            if (on[j] && r >= t && r < c) cp[r] = y;
+            const double z = r > t ? y : 0.0;
+            if (u & 1)
+              s1 = fma(z, z, s1);
+            else
+              s0 = fma(z, z, s0);
+          }
+          sc[j] = s0 + s1;
+        }
+#pragma unroll
+        for (int j = 0; j < JB; j++) {
+          const double nn = g16_sum(sc[j]);
+          if (!on[j]) continue;
+          if (h == 0) nrm2[a0 + CS_NG * j] = nn;
+          if (pivoting || na[j] == t + 1) {
+            const ArgMax y = amax_pick(best, ArgMax{nn, na[j]});
+            if (y.a == na[j] && best.a != na[j]) {
+              best = y;
+              bst = a0 + CS_NG * j;
+            }
+          }
+        }
+      }
+      kk = t + 1;
+      if (t + 1 < kend) stage(t + 1, best, bst);
+    }
+    __syncthreads();
+    return kk;
+  };
+
+  build(false);
+  int k = qr(true, m < c ? m : c);
+  const int nr = m - k;
+  int nsw = 0;
+  bool failed = false;
+  for (;;) {
+    // skeleton columns before each grid index (grid order is storage order)
+    {
+      const int chunk = (m + CS_NT - 1) / CS_NT;
+      const int a0 = tid * chunk;
+      int cnt = 0;
+      for (int e = 0; e < chunk && a0 + e < m; e++) cnt += lab[a0 + e] < k ? 1 : 0;
+      int64_t tot;
+      int ex = (int)block_excl_scan_i64<CS_NW>(cnt, &tot, sh.sred);
+      for (int e = 0; e < chunk && a0 + e < m; e++) {
+        exs[a0 + e] = ex;
+        ex += lab[a0 + e] < k ? 1 : 0;
+      }
+      __syncthreads();
+    }
+    if (k == 0 || nr == 0) break;
+    if (tid < k) sh.rdg[tid] = 1.0 / sh.rdiag[tid];
+    __syncthreads();
+    // back substitution by columns of R11 (column j: rows < j of the tile
+    // column piv[j], diagonal rdiag[j]) in every column: a column at
+    // position j < k solves R11 x = e_j (a column of R11^-1, kept in Rinv),
+    // one at a position >= k solves R11 n = R12 e (a column of N, kept over
+    // its rows < k; R11's columns are never overwritten).  With the tile in
+    // LDS in one pass; otherwise R11 passes through LDS (Lr, rcols columns
+    // at a time, last columns first) and the vectors are reloaded per pass.
+    for (int a = g; a < m; a += CS_NG) {
+      const int la = lab[a];
+      if (la < k) {
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int r = CS_LPC * u + h;
+          if (r < k) Rinv[(int64_t)la * k + r] = r == la ? 1.0 : 0.0;
+        }
+      }
+    }
+    const int rcols = LT ? k : rcap;
+    for (int j1 = k; j1 > 0; j1 -= rcols) {
+      const int j0 = j1 - rcols > 0 ? j1 - rcols : 0;
+      __syncthreads();
+      if constexpr (!LT) {
+        for (int e = tid; e < (j1 - j0) * ldc; e += CS_NT) {
+          const int jc = e / ldc, r = e - jc * ldc;
+          if (r < j0 + jc) Lr[e] = W[(int64_t)sh.piv[j0 + jc] * ldc + r];
+        }
+        __syncthreads();
+      }
+      for (int a0 = g; a0 < m; a0 += CS_NG * JT) {
+        double *xp[JT];
+        double x[JT][RL];
+#pragma unroll
+        for (int j = 0; j < JT; j++) {
+          const int a = a0 + CS_NG * j;
+          const int la = a < m ? lab[a] : k;
+          xp[j] = a >= m ? nullptr : la >= k ? W + (int64_t)a * ldc : Rinv + (int64_t)la * k;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int r = CS_LPC * u + h;
+            x[j][u] = (xp[j] && r < j1) ? xp[j][r] : 0.0;
+          }
+        }
+        // blocks of 16 rows unrolled (register indices stay static), the
+        // rows of a block in a loop
+#pragma unroll
+        for (int ub = RL - 1; ub >= 0; ub--) {
+          const int jlo = CS_LPC * ub > j0 ? CS_LPC * ub : j0;
+          const int jhi = CS_LPC * ub + CS_LPC < j1 ? CS_LPC * ub + CS_LPC : j1;
+          if (jlo >= jhi) continue;
+#pragma unroll 1
+          for (int jj = jhi - 1; jj >= jlo; jj--) {
+            const int hj = jj - CS_LPC * ub;
+            const double rd = sh.rdg[jj];
+            double xv[JT];
+#pragma unroll
+            for (int j = 0; j < JT; j++) {
+              xv[j] = __shfl(x[j][ub], (lane & ~(CS_LPC - 1)) + hj, WAVE) * rd;
+              if (h == hj) x[j][ub] = xv[j];
+            }
+            const double *Rc = LT ? W + (int64_t)sh.piv[jj] * ldc : Lr + (int64_t)(jj - j0) * ldc;
+#pragma unroll
+            for (int u = 0; u <= ub; u++) {
+              const int r = CS_LPC * u + h;
+              if (r < jj) {
+                const double rr = Rc[r];
+#pragma unroll
+                for (int j = 0; j < JT; j++) x[j][u] = fma(-rr, xv[j], x[j][u]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < JT; j++) {
+          if (!xp[j]) continue;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int r = CS_LPC * u + h;
+            if (r < j1) xp[j][r] = x[j][u];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // row norms of R11^-1: a group per row, lane h summing the columns
+    // jc = h (mod 16), then the group sum
+    for (int ii = g; ii < k; ii += CS_NG) {
+      double sq = 0.0;
+      for (int jc = h; jc < k; jc += CS_LPC) {
+        const double y = Rinv[(int64_t)jc * k + ii];
+        sq = fma(y, y, sq);
+      }
+      sq = g16_sum(sq);
+      if (h == 0) sh.rinv[ii] = sqrt(sq);
+    }
+    __syncthreads();
+    // rho_ij^2 = N_ij^2 + (gamma_j / omega_i)^2; arg-max, ties: smallest j,
+    // then smallest i (pair index j*k + i).  G rows are written on every
+    // pass; the last pass leaves the final ones.
+    ArgMax am{-1.0, -1};
+    for (int a = g; a < m; a += CS_NG) {
+      const int la = lab[a];
+      if (la < k) continue;
+      const double gam = sqrt(nrm2[a]);  // norm of the column's rows >= k
+      double *Gr = A.G_out + A.go[i] + (int64_t)(a - exs[a]) * k;
+      const int base = (la - k) * k;
+      const double *cp = W + (int64_t)a * ldc;
+#pragma unroll
+      for (int u = 0; u < RL; u++) {
+        const int ii = CS_LPC * u + h;
+        if (ii < k) {
+          const double nv = cp[ii];
+          const double gw = gam * sh.rinv[ii];
+          const double r2 = nv * nv + gw * gw;
+          am = amax_pick(am, ArgMax{r2, base + ii});
+          Gr[exs[sh.piv[ii]]] = nv;
+        }
+      }
+    }
+    am = block_argmax<CS_NW>(am, sh.ared);
+    if (!(sqrt(am.v) > A.f)) break;
+    if (++nsw > 64 * k) {
+      failed = true;
+      break;
+    }
+    const int bj = am.a / k, bi = am.a % k;
+    for (int a = tid; a < m; a += CS_NT) {
+      const int la = lab[a];
+      if (la == bi)
+        lab[a] = k + bj;
+      else if (la == k + bj)
+        lab[a] = bi;
+    }
+    __syncthreads();
+    build(true);
+    qr(false, k);
+  }
+  if (tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+  // canonical output: skeleton indices ascending, then the rest
+  int *sel = A.sel_out + A.selo[i];
+  for (int a = tid; a < m; a += CS_NT) {
+    if (failed) {
+      sel[a] = a;
+    } else {
+      const int ex = exs[a];
+      if (lab[a] < k)
+        sel[ex] = a;
+      else
+        sel[k + (a - ex)] = a;
+    }
+  }
+  if (failed) {
+    if (tid == 0) atomicOr(A.err, 1);
+    k = 0;
+  }
+  if (tid == 0) A.k_out[i] = k;
+}
+
+template <int CMAX>
+__global__ void __launch_bounds__(CS_NT) k_compr_s(IdArgs A, CsArgs B) {
+  extern __shared__ double dyn[];
+  __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
+  __shared__ double rdiag[CMAX], rdg[CMAX], rinv[CMAX];
+  __shared__ int piv[CMAX], msrc[2 * CS_NW];
+  __shared__ ArgMax meta[2 * CS_NW], ared[CS_NW + 1];
+  __shared__ int64_t sred[CS_NW + 1];
+  const int tid = threadIdx.x;
+  const int p = A.p, d = A.d, ldc = B.ldc;
+  if (tid < p) {
+    const double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
+    chc[tid] = cos(th);
+    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
+  }
+  // dynamic LDS: the staging slots, the groups' one-dimensional factors,
+  // then the LDS tile with its norms, labels and counts
+  double *const slots = dyn;
+  double *const Fg = slots + 2 * CS_NW * ldc;
+  double *const Lw = Fg + CS_NG * d * p;
+  double *const Ln = Lw + (int64_t)B.lds_cols * ldc;
+  int *const Ll = (int *)(Ln + B.lds_cols);
+  int *const Le = Ll + B.lds_cols;
+  // the workgroup's global scratch
+  double *const Gw = B.gscr + (int64_t)blockIdx.x * B.gstride;
+  double *const Gn = Gw + (int64_t)B.mmax * ldc;
+  double *const Ri = Gn + B.mmax;
+  int *const Gl = B.iscr + (int64_t)blockIdx.x * B.istride;
+  int *const Ge = Gl + B.mmax;
+  const CsShared sh{xi, wk, slots, Fg, rdiag, rdg, rinv, piv, msrc, meta, ared, sred};
+  const int cnt = *B.cnt;
+  for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+    const int i = B.order ? B.order[e] : A.nb + e;
+    const int m = A.m[i];
+    __syncthreads();
+    if (tid < d * p) {
+      const int t = tid / p, q = tid % p;
+      const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+      xi[t * ID_PMAX + q] = 0.5 * (lo + hi) + 0.5 * (hi - lo) * chc[q];
+    }
+    __syncthreads();
+    if (m == 0) {
+      if (tid == 0) A.k_out[i] = 0;
+      continue;
+    }
+    if (m <= B.lds_cols)
+      compr_node_s<CMAX, true>(A, B, i, m, Lw, Ln, Ll, Le, Ri, nullptr, 0, sh);
+    else  // the LDS tile area takes columns of R11 in the back substitution
+      compr_node_s<CMAX, false>(A, B, i, m, Gw, Gn, Gl, Ge, Ri, Lw,
+                                (int)(((int64_t)B.lds_cols * (ldc + 2)) / ldc), sh);
+  }
+}
+
+// Node order of a level for the wide form: grids larger than `lim` first,
+// by decreasing size (a 16-bit key), then the rest; `big` counts the former.
+__global__ void k_order_keys(int nb, int ne, const int *m, int lim, uint64_t *keys, int *vals,
+                             int *big) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ne - nb) return;
+  const int mm = m[nb + e];
+  const uint64_t sz = (uint64_t)(65535 - (mm < 65535 ? mm : 65535));
+  keys[e] = (mm > lim ? 0ull : (1ull << 16)) | sz;
+  vals[e] = nb + e;
+  if (mm > lim) atomicAdd(big, 1);
 }
 
 // ------------------------------------------------------------------------
@@ -1683,64 +1912,121 @@ void build_generators(Handle &h) {
       for (auto &sc : sides) {
         Side &S = *sc.S;
         LevelSide &L = S.lv[l];
-        int cmax = c0 + (hss ? sc.mmax : 0);
+        const int cmax = c0 + (hss ? sc.mmax : 0);
         if (cmax > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
-        int ldw = (sc.mmax + 1) | 1;  // odd stride
-        // register-resident QR when the grid fits one workgroup (two lanes
-        // per grid point) and the basis width fits CMAX; otherwise the tile
-        // form
+        // The register form (k_compr_w: the grid in registers, two lanes per
+        // grid point) takes grids of up to 256 points when c <= 64; larger
+        // grids and wider bases take the wide form (k_compr_s), largest
+        // grids first.  A level may use both.
         constexpr int lpc = 4, cpg = 2;  // lanes per column group, columns per group
-        const int mw = sc.mmax * lpc / cpg;
-        const int nt = mw <= 64 ? 64 : mw <= 128 ? 128 : mw <= 256 ? 256 : mw <= 512 ? 512 : 0;
+        const int mreg = std::min(sc.mmax, 256);
+        const int mw = std::max(mreg, 1) * lpc / cpg;
+        const int nt = mw <= 64 ? 64 : mw <= 128 ? 128 : mw <= 256 ? 256 : 512;
         const int cm = cmax <= 32 ? 32 : cmax <= 64 ? 64 : 0;
-        const size_t sh = sizeof(double) * std::max((size_t)h.d * h.p * (nt > 0 ? nt / lpc * cpg : 1),
-                                                    (size_t)cm * (cm + 1));
+        const size_t shw = sizeof(double) * std::max((size_t)h.d * h.p * (nt / lpc * cpg),
+                                                     (size_t)cm * (cm + 1));
         // (dynamic LDS plus at most 8 KB of static LDS within the device limit)
-        const bool reg = nt > 0 && cm > 0 && cm <= nt && h.d * h.p <= nt && sh <= 64 * 1024 &&
-                         sh + 8 * 1024 <= (size_t)dev_lds;
-        const int wcap = reg ? 8 * dev_cus : 2 * dev_cus;
-        const int nwg = !h.batched ? 1 : nl < wcap ? nl : wcap;
-        int64_t wg_stride = (int64_t)cmax * ldw + (int64_t)h.d * h.p * ldw + ldw +
-                            (int64_t)cmax * cmax + 8;
-        // the tile form's per-workgroup scratch (the register form needs none)
-        double *scr = reg ? nullptr : tmp.alloc_n<double>((size_t)wg_stride * nwg);
-        int *iscr = reg ? nullptr : tmp.alloc_n<int>((size_t)2 * ldw * nwg);
+        const bool reg_ok = cm > 0 && cm <= nt && h.d * h.p <= nt && shw <= 64 * 1024 &&
+                            shw + 8 * 1024 <= (size_t)dev_lds;
+        const bool all_reg = reg_ok && sc.mmax <= 256;
+        // the wide form: basis rows up to cw, tile columns of ldc rows; the
+        // LDS left after its fixed parts holds the tile of grids of up to
+        // lds_cols points
+        const int cw = cmax <= 64 ? 64 : cmax <= 128 ? 128 : cmax <= 256 ? 256 : 512;
+        const int ldc = (cmax + 15) / 16 * 16;
+        const size_t st_lds = sizeof(double) * (5 * ID_PMAX + 3 * cw) +
+                              sizeof(int) * (cw + 2 * CS_NW) + sizeof(ArgMax) * (3 * CS_NW + 1) +
+                              sizeof(int64_t) * (CS_NW + 1) + 512;
+        const size_t fixed = sizeof(double) * (2 * CS_NW * (size_t)ldc + CS_NG * h.d * h.p);
+        const size_t per_col = sizeof(double) * ((size_t)ldc + 2);
+        int lds_cols = 0;
+        if ((size_t)dev_lds > st_lds + fixed)
+          lds_cols = (int)std::min<size_t>(((size_t)dev_lds - st_lds - fixed) / per_col,
+                                           (size_t)sc.mmax);
+        const size_t shs = fixed + per_col * (size_t)lds_cols;
         IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo, S.go,
                   L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
-                  h.tol, h.f, scr, ldw, wg_stride, iscr, 2 * (int64_t)ldw, dsw, dsw + 1,
-                  reg ? 1 : 0};
-        if (reg) {
-          ia.G_out = L.Gt;  // the register kernel writes G^T, and G
-          ia.G2_out = L.G;
+                  h.tol, h.f, dsw, dsw + 1, 0};
+        IdArgs ir = ia;  // the register form writes G^T, and G
+        ir.gt_out = 1;
+        ir.G_out = L.Gt;
+        ir.G2_out = L.G;
+        sc.gt_first = all_reg;
+        const int wgrid = !h.batched ? 1 : std::min(nl, 2 * dev_cus);
+        CsArgs cs{nullptr, nullptr, ldc, lds_cols, std::max(sc.mmax, 1), nullptr, 0, nullptr, 0};
+        if (!all_reg) {
+          cs.gstride = (int64_t)cs.mmax * ldc + cs.mmax + (int64_t)cw * cw;
+          cs.istride = 2 * (int64_t)cs.mmax;
+          cs.gscr = tmp.alloc_n<double>((size_t)cs.gstride * wgrid);
+          cs.iscr = tmp.alloc_n<int>((size_t)cs.istride * wgrid);
         }
-        sc.gt_first = reg;
-        PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
-        auto launch = [&](int grid) {
-          if (!reg) {
-            k_compr<<<grid, ID_NT, 0, s>>>(ia);
-          } else {
+        auto launch_reg = [&](const IdArgs &a, int grid) {
 #define SMASH_W_CASE(CM, NTV)                                                    \
-  if (cm == CM && nt == NTV) k_compr_w<CM, NTV, lpc, cpg><<<grid, NTV, sh, s>>>(ia);
-            SMASH_W_CASE(32, 64)
-            SMASH_W_CASE(32, 128)
-            SMASH_W_CASE(32, 256)
-            SMASH_W_CASE(32, 512)
-            SMASH_W_CASE(64, 64)
-            SMASH_W_CASE(64, 128)
-            SMASH_W_CASE(64, 256)
-            SMASH_W_CASE(64, 512)
+  if (cm == CM && nt == NTV) k_compr_w<CM, NTV, lpc, cpg><<<grid, NTV, shw, s>>>(a);
+          SMASH_W_CASE(32, 64)
+          SMASH_W_CASE(32, 128)
+          SMASH_W_CASE(32, 256)
+          SMASH_W_CASE(32, 512)
+          SMASH_W_CASE(64, 64)
+          SMASH_W_CASE(64, 128)
+          SMASH_W_CASE(64, 256)
+          SMASH_W_CASE(64, 512)
 #undef SMASH_W_CASE
+          SMASH_CHECK_LAUNCH();
+        };
+        auto launch_wide = [&](const IdArgs &a, const CsArgs &b, int grid) {
+          switch (cw) {
+            case 64: k_compr_s<64><<<grid, CS_NT, shs, s>>>(a, b); break;
+            case 128: k_compr_s<128><<<grid, CS_NT, shs, s>>>(a, b); break;
+            case 256: k_compr_s<256><<<grid, CS_NT, shs, s>>>(a, b); break;
+            default: k_compr_s<512><<<grid, CS_NT, shs, s>>>(a, b); break;
           }
           SMASH_CHECK_LAUNCH();
         };
+        PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
         if (h.batched) {
-          launch(nwg);
+          if (all_reg) {
+            launch_reg(ir, nl < 8 * dev_cus ? nl : 8 * dev_cus);
+          } else {
+            // order: the wide form's grids by decreasing size, then the rest
+            uint64_t *keys = tmp.alloc_n<uint64_t>(nl), *kalt = tmp.alloc_n<uint64_t>(nl);
+            int *vals = tmp.alloc_n<int>(nl), *valt = tmp.alloc_n<int>(nl);
+            int *big = tmp.alloc_n<int>(1);
+            SMASH_HIP(hipMemsetAsync(big, 0, sizeof(int), s));
+            k_order_keys<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, S.m, reg_ok ? 256 : -1, keys,
+                                                         vals, big);
+            SMASH_CHECK_LAUNCH();
+            radix_sort_u64(keys, vals, kalt, valt, nl, 17, s, tmp);
+            cs.order = vals;
+            cs.cnt = big;
+            launch_wide(ia, cs, wgrid);
+            if (reg_ok) {
+              ir.order = vals;
+              ir.ord_lo = big;
+              launch_reg(ir, nl < 8 * dev_cus ? nl : 8 * dev_cus);
+            }
+          }
         } else {
+          // the plain per-node form: the same choice per node
+          std::vector<int> mh((size_t)nl);
+          SMASH_HIP(hipMemcpyAsync(mh.data(), S.m + nb, sizeof(int) * nl, hipMemcpyDeviceToHost,
+                                   s));
+          SMASH_HIP(hipStreamSynchronize(s));
+          int *one = nullptr;
+          if (!all_reg) {
+            one = tmp.alloc_n<int>(1);
+            SMASH_HIP(hipMemsetD32Async((hipDeviceptr_t)one, 1, 1, s));
+          }
+          cs.cnt = one;
           for (int i = nb; i < ne; i++) {
-            ia.nb = i;
-            ia.ne = i + 1;
-            if (hss) ia.S_off = sc.S_off + (i - nb);
-            launch(1);
+            IdArgs a1 = (reg_ok && mh[i - nb] <= 256) ? ir : ia;
+            a1.nb = i;
+            a1.ne = i + 1;
+            if (hss) a1.S_off = sc.S_off + (i - nb);
+            if (reg_ok && mh[i - nb] <= 256)
+              launch_reg(a1, 1);
+            else
+              launch_wide(a1, cs, 1);
           }
         }
       }

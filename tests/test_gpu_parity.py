@@ -43,6 +43,11 @@ CASES = {
     "h2_3d_clusters": (lambda: (W.clusters(6000, 3, 6), None),
                        dict(kernel="inv_r", leaf=128, order=5, adm="strong", tol=1e-6, tau=0.7,
                             root=((0.0, 0.0, 0.0), 1.0))),
+    # c = 64 with parent grids of up to 512 points: a level splits between
+    # the register form (grids <= 256) and the wide form (the larger ones)
+    "h2_3d_p4_split": (lambda: (W.clusters(9000, 3, 9), None),
+                       dict(kernel="inv_r", leaf=128, order=4, adm="strong", tol=1e-7, tau=0.7,
+                            root=((0.0, 0.0, 0.0), 1.0))),
     "h2_1d_exp": (lambda: (W.uniform(3000, 1, 8), None),
                   dict(kernel="exp_r", leaf=40, order=9, adm="strong", tol=1e-10, tau=0.6)),
     "hss_cauchy_xy": (lambda: W.chebyshev_pair(3000, 4),
