@@ -1,20 +1,26 @@
 #!/usr/bin/env python3
 """Benchmark: one step = SMASH construction + one product, on one MI355X.
 
-Default workload (the paper's H^2 setting of Sec. 6.2 scaled to the 2D
-benchmark size): n = 65536 points uniform in the unit square, kernel
-log|x-y| (diagonal 0), strong admissibility (tau 0.7), quadtree leaf 64,
-8 x 8 Chebyshev interpolation points, RRQR tolerance 1e-8, FP64 build and
-product with 16 right-hand sides.  Points and right-hand sides are drawn
-from seed 0 and resident in HBM before the timed region.
+Headline workload (`--workload`, default h2_3d_inv_r_clusters_1m_p6): the
+3D adaptive-tree case at 2^20 points -- 90 % of them from 8 Gaussian
+clusters (sigma 0.02) and 10 % uniform in the unit cube -- with kernel
+1/|x-y| (diagonal 0), strong admissibility (tau 0.7), octree leaf 128,
+6 x 6 x 6 Chebyshev interpolation points and RRQR tolerance 1e-7: the order
+at which the product reaches 1e-6 relative error against exact rows of A Q
+(5 x 5 x 5 points stop at 4.6e-6).  FP64 construction and FP64 product
+with 64 right-hand sides; the coupling blocks (5.5e10 FP64 entries, beyond
+one GPU's memory) are evaluated inside each product from their skeleton
+index sets.  Points and right-hand sides are drawn from seed 0 and resident
+in HBM before the timed region.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 Prints one JSON line.  `value` is points per second through the whole step
-(construction + product of 16 vectors).  `roofline` is for the dominant
-kernel (measured live with HIP events the library records on the stream it
-launches on), `roofline_matvec` for the product, `cpu_baseline` the FP64
-oracle on the host cores.
+(construction + product of 64 vectors).  `roofline` is the dominant
+kernel's, timed live with the HIP events the library records around each
+phase on the stream it launches on.  Further keys: the other workloads as
+configured, the plain per-node form, an O(n) series, the oracle on the
+host cores (`cpu_baseline`) and the serving loop at three offered loads.
 """
 from __future__ import annotations
 
@@ -36,34 +42,125 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 
-def stored_traffic(workload):
-    """HBM bytes per launch of the compression kernel and per product, from
-    the counter summary under profiles/ -- each None once its source file
-    has changed since the counters were taken."""
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the counter summary under
+    profiles/ -- None when absent or when its source file has changed since
+    the counters were taken."""
     path = os.path.join(ROOT, "profiles", workload + "_traffic.json")
     if not os.path.exists(path):
-        return None, None
+        return None
     with open(path) as f:
         d = json.load(f)
-
-    def same(rel, sha):
-        with open(os.path.join(ROOT, rel), "rb") as g:
-            return hashlib.sha256(g.read()).hexdigest() == sha
-
-    comp = d["bytes_per_launch"] if same(d["source"], d["source_sha256"]) else None
-    prod = d.get("product_bytes")
-    if prod is not None and not same(d["product_source"], d["product_source_sha256"]):
-        prod = None
-    return comp, prod
+    ent = d.get("kernels", {}).get(kernel)
+    if not ent:
+        return None
+    with open(os.path.join(ROOT, ent["source"]), "rb") as g:
+        if hashlib.sha256(g.read()).hexdigest() != ent["source_sha256"]:
+            return None
+    return ent["bytes_per_launch"]
 
 
-def compr_flops(m, k, c):
-    """Algorithmic FP64 flops of compr on one node: the truncated Householder
-    QR of the c x m matrix C^T (k reflectors, two flops per multiply-add of
-    the dot and of the update) and the triangular solve N = R11^-1 R12."""
-    t = np.arange(k)
-    qr = np.sum(4.0 * (c - t) * np.maximum(m - t - 1, 0))
-    return float(qr + (m - k) * float(k) * k)
+def kwargs_of(cfg):
+    kw = dict(kernel=cfg["kernel"], leaf=cfg["leaf"], order=cfg["order"],
+              adm="strong" if cfg["adm"] == 1 else "weak", tol=cfg["tol"], tau=cfg["tau"],
+              root=cfg["root"], apply_prec=cfg["apply"],
+              eval_prec="f64" if cfg["apply"] == "f64" else "f32",
+              coupling=cfg.get("coupling", "auto"))
+    if "eps_svd" in cfg:
+        kw["eps_svd"] = cfg["eps_svd"]
+    return kw
+
+
+def product_bytes(inf, n_x, n_y, R, e):
+    """Algorithmic bytes of one product: Q read and Z written once, G of
+    both passes, the stored blocks (none for evaluated coupling blocks),
+    the index lists, and the skeleton vectors written and read once."""
+    blocks = inf["near_entries"] + (0 if inf["coupling_evaluated"] else inf["coupling_entries"])
+    return (e * R * (n_x + n_y) + e * (inf["g_entries_row"] + inf["g_entries_col"])
+            + e * blocks + 4 * inf["index_entries"]
+            + 2 * e * R * (inf["sum_rank_row"] + inf["sum_rank_col"]))
+
+
+def compr_work(h, inf, c0):
+    """FP64 flops of compr per build: sum over nodes and sides of 4 c m k
+    (the measure of the cost of the ID, c = basis width), and the exact
+    Householder count (sum_t 4 (c - t)(m - t - 1) plus (m - k) k^2 for the
+    solve) beside it."""
+    rk = h.export("ranks").reshape(-1, 6)[1:].astype(np.float64)
+    sides = [(0, 1, 4)] if inf["symmetric_reuse"] else [(0, 1, 4), (2, 3, 5)]
+    simple = exact = 0.0
+    for mc, kc, sc in sides:
+        m, k, c = rk[:, mc], rk[:, kc], c0 + rk[:, sc]
+        simple += float(np.sum(4.0 * c * m * k))
+        # sum_{t<k} 4 (c - t)(m - t - 1), closed form per node
+        t1 = k * (k - 1) / 2.0
+        t2 = (k - 1) * k * (2 * k - 1) / 6.0
+        exact += float(np.sum(4.0 * (c * (m - 1) * k - (c + m - 1) * t1 + t2)
+                              + (m - k) * k * k))
+    return simple, exact
+
+
+def timed_product(h, Q, reps, torch):
+    Z = torch.empty((h.nx, Q.shape[1]), dtype=Q.dtype, device=Q.device)
+    for _ in range(2):
+        h.matvec(Q, out=Z)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        h.matvec(Q, out=Z)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, Z
+
+
+def rows_error(Z, x, y, q, kernel, n, nrows=512):
+    from oracle import oracle as O
+    rows = np.arange(0, n, max(1, n // nrows))
+    zr = O.dense_rows(x, x if y is None else y, rows, q, kernel)
+    Zc = Z.double().cpu().numpy()
+    return float(np.linalg.norm(Zc[rows] - zr) / np.linalg.norm(zr))
+
+
+def one_workload(name, torch, api, W, reps=5, nrhs=None, apply=None, n=None):
+    """One construction and timed products of a workload: build and product
+    times, phase times, error against exact rows."""
+    cfg = dict(W.CONFIGS[name])
+    if apply:
+        cfg["apply"] = apply
+    x, y = W.points(cfg, seed=0, n=n)
+    nn = len(x)
+    R = nrhs or cfg["nrhs"]
+    f64 = cfg["apply"] == "f64"
+    X = torch.from_numpy(x).cuda()
+    Yd = None if y is None else torch.from_numpy(y).cuda()
+    q = W.rhs(len(x if y is None else y), R, seed=0)
+    if not f64:
+        q = q.astype(np.float32).astype(np.float64)
+    Q = torch.from_numpy(q).to(torch.float64 if f64 else torch.float32).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = api.Smash(X, Yd, timing=True, **kwargs_of(cfg))
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    inf = h.info()
+    h.close()
+    hg = api.Smash(X, Yd, timing=False, **kwargs_of(cfg))
+    ms, Z = timed_product(hg, Q, reps, torch)
+    ig = hg.info()
+    e = 8 if f64 else 4
+    mvb = product_bytes(ig, nn, len(x if y is None else y), R, e)
+    out = {"n": nn, "nrhs": R, "apply": cfg["apply"], "order": cfg["order"], "tol": cfg["tol"],
+           "build_ms": wall, "build_points_per_s": nn / (wall * 1e-3),
+           "build_phase_ms": {k: v for k, v in inf["phase_ms"].items() if v > 0},
+           "matvec_ms": ms, "matvec_GBps": mvb / (ms * 1e-3) / 1e9,
+           "coupling_evaluated": bool(ig["coupling_evaluated"]),
+           "device_GB": ig["device_bytes"] / 1e9,
+           "rel_err_vs_exact_rows": rows_error(Z, x, y, q, cfg["kernel"], nn)}
+    hg.close()
+    del X, Yd, Q, Z
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -71,21 +168,22 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="h2_2d_log_65536")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+    ap.add_argument("--workload", default="h2_3d_inv_r_clusters_1m_p6")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target seconds of oracle work for cpu_baseline (0: skip)")
-    ap.add_argument("--plain-steps", type=int, default=2,
-                    help="steps of the plain per-node form timed for comparison (0: skip)")
-    ap.add_argument("--skip-evaluated", action="store_true",
-                    help="skip the product with coupling blocks evaluated inside it")
+    ap.add_argument("--cpu-n", type=int, default=1 << 15,
+                    help="points of the oracle's sample of the workload")
+    ap.add_argument("--plain-n", type=int, default=1 << 16,
+                    help="points at which the plain per-node form is compared (0: skip)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="also time the other workloads and the O(n) series (0: skip)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB five times (the "
                          "calibration kernel for the HBM byte counters) and exit")
-    ap.add_argument("--serve-requests", type=int, default=24,
-                    help="requests in the serving trace (0: skip the serving measurement)")
-    ap.add_argument("--serve-rate", type=float, default=40.0, help="mean arrivals per second")
-    ap.add_argument("--serve-nmax", type=float, default=2e5,
-                    help="largest N of the serving trace (the full stream uses 1e6)")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests per offered load in the serving trace (0: skip)")
+    ap.add_argument("--serve-nmax", type=float, default=1e6,
+                    help="largest N of the serving trace")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -112,35 +210,33 @@ def main():
     n = cfg["n"]
     R = cfg["nrhs"]
     f64 = cfg["apply"] == "f64"
-    tdt = torch.float64 if f64 else torch.float32
     X = torch.from_numpy(x).cuda()
     Yd = None if y is None else torch.from_numpy(y).cuda()
     q = W.rhs(n, R, seed=0)
-    Q = torch.from_numpy(q.astype(np.float64 if f64 else np.float32)).cuda()
-    kw = dict(kernel=cfg["kernel"], leaf=cfg["leaf"], order=cfg["order"],
-              adm="strong" if cfg["adm"] == 1 else "weak", tol=cfg["tol"], tau=cfg["tau"],
-              root=cfg["root"], apply_prec=cfg["apply"],
-              eval_prec="f64" if f64 else "f32")
-    if "eps_svd" in cfg:
-        kw["eps_svd"] = cfg["eps_svd"]
+    if not f64:
+        q = q.astype(np.float32).astype(np.float64)
+    Q = torch.from_numpy(q).to(torch.float64 if f64 else torch.float32).cuda()
+    kw = kwargs_of(cfg)
     torch.cuda.synchronize()
 
-    def step(timing, batched=True):
-        h = api.Smash(X, Yd, timing=timing, batched=batched, **kw)
-        Z = h.matvec(Q)
+    def step(timing=True, batched=True, XX=X, QQ=Q):
+        h = api.Smash(XX, None if y is None else Yd, timing=timing, batched=batched, **kw)
+        Z = h.matvec(QQ)
         return h, Z
 
+    print("warmup", flush=True)
     for _ in range(args.warmup):
-        h, Z = step(True)
+        h, Z = step()
         h.close()
     torch.cuda.synchronize()
 
     # ---- timed region: K whole steps -------------------------------------
+    print("timed steps", flush=True)
     infos = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        h, Z = step(True)
+        h, Z = step()
         infos.append(h.info())  # waits for the product; resolves the events
         h.close()
     torch.cuda.synchronize()
@@ -150,100 +246,55 @@ def main():
 
     # ---- per-phase device times (HIP events recorded inside the library) ----
     ph = {k: float(np.mean([inf["phase_ms"][k] for inf in infos])) for k in api.PHASES}
+    calls = {k: float(np.mean([inf["phase_calls"][k] for inf in infos])) for k in api.PHASES}
     build_ms = float(np.mean([inf["build_ms"] for inf in infos]))
 
-    # ---- one resident handle for sizes, accuracy, product timing ----------
-    h = api.Smash(X, Yd, timing=True, **kw)
+    # ---- one resident handle: sizes, accuracy, product timing -------------
+    h = api.Smash(X, Yd, timing=False, **kw)
     inf = h.info()
-    rk = h.export("ranks").reshape(-1, 6)
-    c = cfg["order"] ** cfg["d"]
-    flops = 0.0
-    for i in range(1, rk.shape[0]):
-        flops += compr_flops(int(rk[i, 0]), int(rk[i, 1]), c + int(rk[i, 4]))
-        if not inf["symmetric_reuse"]:
-            flops += compr_flops(int(rk[i, 2]), int(rk[i, 3]), c + int(rk[i, 5]))
+    c0 = cfg["order"] ** cfg["d"]
+    compr_simple, compr_exact = compr_work(h, inf, c0)
     e = 8 if f64 else 4
-    mv_bytes = (e * R * (n + (n if y is None else len(y)))
-                + e * (inf["g_entries_row"] + inf["g_entries_col"])
-                + e * (inf["coupling_entries"] + inf["near_entries"])
-                + 4 * inf["index_entries"]
-                + 2 * e * R * (inf["sum_rank_row"] + inf["sum_rank_col"]))
-    reps = 20
-    Z = h.matvec(Q)
-    torch.cuda.synchronize()
-    base = h.info()["phase_ms"]
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(reps):
-        Z = h.matvec(Q)
-    ev1.record()
-    torch.cuda.synchronize()
-    mv_eager_ms = ev0.elapsed_time(ev1) / reps
-    after = h.info()["phase_ms"]
-    mv_ph = {k: (after[k] - base[k]) / reps for k in api.PHASES if k.startswith("mv_")}
-    # the resident form: same handle parameters, products replayed from a
-    # captured HIP graph (no per-phase events)
-    hg = api.Smash(X, Yd, timing=False, **kw)
-    Zg = torch.empty_like(Z)
-    for _ in range(3):
-        hg.matvec(Q, out=Zg)
-    torch.cuda.synchronize()
-    ev0.record()
-    for _ in range(reps):
-        hg.matvec(Q, out=Zg)
-    ev1.record()
-    torch.cuda.synchronize()
-    mv_ms = ev0.elapsed_time(ev1) / reps
-    graph_replays = hg.info()["graph_replays"]
-    stored_bytes = hg.info()["device_bytes"]
-    hg.close()
-    # the same product with the coupling blocks evaluated inside it (no
-    # stored B; the result is the stored form's bit for bit)
-    coupling_evaluated = None
-    he = None if args.skip_evaluated else api.Smash(X, Yd, timing=False, coupling="evaluated", **kw)
-    if he is not None:
-        Ze = torch.empty_like(Z)
-        for _ in range(3):
-            he.matvec(Q, out=Ze)
-        torch.cuda.synchronize()
-        ev0.record()
-        for _ in range(reps):
-            he.matvec(Q, out=Ze)
-        ev1.record()
-        torch.cuda.synchronize()
-        ie = he.info()
-        coupling_evaluated = {"matvec_ms": ev0.elapsed_time(ev1) / reps,
-                              "device_bytes": int(ie["device_bytes"]),
-                              "stored_form_device_bytes": int(stored_bytes),
-                              "chunks": int(ie["coupling_chunks"]),
-                              "same_as_stored": bool(torch.equal(Ze, Zg))}
-        he.close()
-    # accuracy against exact rows of A Q
-    from oracle import oracle as O
-    rows = np.arange(0, n, max(1, n // 512))
-    Zc = Z.double().cpu().numpy()
-    zr = O.dense_rows(x, x if y is None else y, rows, q, cfg["kernel"])
-    err_rows = float(np.linalg.norm(Zc[rows] - zr) / np.linalg.norm(zr))
-
-    compr_ms = ph["compr"]
-    dominant = max(ph, key=ph.get)
-    tr_comp, tr_prod = stored_traffic(args.workload)
-    n_compr = int(infos[0]["phase_calls"]["compr"]) if infos else 0
-    roof = {"kernel": "k_compr_w (pivoted Householder QR + Gu-Eisenstat, FP64)", "bound": "alu",
-            "achieved": flops / (compr_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "traffic": tr_comp,
-            "traffic_note": "HBM bytes per launch (2 x FETCH_SIZE + WRITE_SIZE, calibrated on a "
-                            "256 MiB copy), profiles/%s_traffic.md" % args.workload,
-            "launches_per_build": n_compr, "ms_per_build": compr_ms,
-            "avg_launch_ms": compr_ms / max(n_compr, 1), "algorithmic_flops_per_build": flops}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof_mv = {"kernel": "product (gather, up, coupling, down, near+scatter)", "bound": "hbm",
-               "achieved": mv_bytes / (mv_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-               "traffic": tr_prod, "algorithmic_bytes": mv_bytes, "ms": mv_ms,
-               "form": "HIP graph replay (%d replays)" % graph_replays,
-               "eager_ms": mv_eager_ms, "eager_phase_ms": mv_ph}
-    roof_mv["frac"] = roof_mv["achieved"] / roof_mv["peak"]
+    mv_ms, Z = timed_product(h, Q, 5, torch)
+    mv_bytes = product_bytes(inf, n, n if y is None else len(y), R, e)
+    coupling_flops = 2.0 * R * inf["coupling_entries"]
+    mv_flops = 2.0 * R * (inf["coupling_entries"] + inf["near_entries"]
+                          + 2 * (inf["g_entries_row"] + inf["g_entries_col"]))
+    print("exact rows", flush=True)
+    err_rows = rows_error(Z, x, y, q, cfg["kernel"], n)
+    storage = {k: inf[k] for k in ("bytes_dense", "bytes_hss0", "bytes_smash", "device_bytes")}
     h.close()
+
+    # ---- roofline of the dominant kernel ----------------------------------
+    dominant = max(ph, key=ph.get)
+    if dominant == "compr":
+        roof = {"kernel": "k_compr_s / k_compr_w (pivoted Householder QR + Gu-Eisenstat, FP64)",
+                "bound": "alu", "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "work": "sum over nodes of 4 c m k FP64 flops", "work_per_build": compr_simple,
+                "exact_householder_flops_per_build": compr_exact}
+        roof["achieved"] = compr_simple / (ph["compr"] * 1e-3) / 1e12
+        roof["achieved_exact_count"] = compr_exact / (ph["compr"] * 1e-3) / 1e12
+        roof["traffic"] = stored_traffic(args.workload, "compr")
+    elif dominant == "mv_coupling":
+        fp = FP64_PEAK_TFLOPS if f64 else FP32_PEAK_TFLOPS
+        roof = {"kernel": "k_mv_coupling_eval (blocks evaluated in the contraction, %s MFMA)"
+                          % ("FP64" if f64 else "FP32") if inf["coupling_evaluated"]
+                else "k_mv_coupling", "bound": "mfma", "peak": fp, "unit": "TFLOP/s",
+                "work": "2 R sum_L k_i k_j flops", "work_per_launch": coupling_flops}
+        roof["achieved"] = coupling_flops / (ph["mv_coupling"] / max(calls["mv_coupling"], 1)
+                                             * 1e-3) / 1e12
+        roof["traffic"] = stored_traffic(args.workload, "mv_coupling")
+    else:
+        roof = {"kernel": dominant, "bound": "hbm", "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "achieved": None, "traffic": None}
+    roof["ms_per_step"] = ph[dominant]
+    roof["launches_per_step"] = calls[dominant]
+    roof["avg_launch_ms"] = ph[dominant] / max(calls[dominant], 1)
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof.get("achieved") else None
+    roof_mv = {"kernel": "product (gather, up, coupling, down, near+scatter)", "ms": mv_ms,
+               "algorithmic_bytes": mv_bytes, "GBps": mv_bytes / (mv_ms * 1e-3) / 1e9,
+               "hbm_frac": mv_bytes / (mv_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+               "flops": mv_flops, "TFLOPs": mv_flops / (mv_ms * 1e-3) / 1e12}
 
     out = {
         "metric": METRIC, "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps,
@@ -251,29 +302,75 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64" if f64 else "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "dim": cfg["d"], "kernel": cfg["kernel"],
-                   "admissibility": kw["adm"], "leaf": cfg["leaf"], "order": cfg["order"],
-                   "tol": cfg["tol"], "tau": cfg["tau"], "nrhs": R, "form": "level-batched"},
+                   "points": cfg["kind"], "admissibility": kw["adm"], "leaf": cfg["leaf"],
+                   "order": cfg["order"], "tol": cfg["tol"], "tau": cfg["tau"], "nrhs": R,
+                   "coupling": cfg.get("coupling", "auto"), "form": "level-batched"},
         "build_ms": build_ms, "build_points_per_s": n / (build_ms * 1e-3),
-        "matvec_ms": mv_ms, "matvec_GBps": roof_mv["achieved"],
-        "rel_err_vs_exact_rows": err_rows, "phase_ms": ph, "dominant_phase": dominant,
-        "nnodes": int(inf["nnodes"]), "nlevels": int(inf["nlevels"]),
-        "roofline": roof, "roofline_matvec": roof_mv,
-        "coupling_evaluated": coupling_evaluated,
+        "matvec_ms": mv_ms, "matvec_GBps": roof_mv["GBps"],
+        "rel_err_vs_exact_rows": err_rows, "phase_ms": ph, "phase_calls": calls,
+        "dominant_phase": dominant, "nnodes": int(inf["nnodes"]), "nlevels": int(inf["nlevels"]),
+        "roofline": roof, "roofline_matvec": roof_mv, "storage_bytes": storage,
     }
+    print("headline %.1f ms/step" % ms_step, flush=True)
 
     # ---- plain per-node form (same kernels, one launch per node) ----------
-    if args.plain_steps > 0:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.plain_steps):
-            hp, Zp = step(False, batched=False)
-            hp.close()
-        torch.cuda.synchronize()
-        out["plain_form_ms_per_step"] = (time.perf_counter() - t0) * 1e3 / args.plain_steps
-        out["speedup_vs_plain_form"] = out["plain_form_ms_per_step"] / ms_step
+    if args.plain_n > 0:
+        print("plain form", flush=True)
+        xs = W.points(cfg, seed=0, n=args.plain_n)[0] if y is None else None
+        if xs is not None:
+            Xs = torch.from_numpy(xs).cuda()
+            Qs = Q[:args.plain_n].contiguous()
+            res = {}
+            for form, bt in (("level_batched", True), ("plain_per_node", False)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                hs, _ = step(False, bt, Xs, Qs)
+                torch.cuda.synchronize()
+                res[form + "_ms_per_step"] = (time.perf_counter() - t0) * 1e3
+                hs.close()
+            res["n"] = args.plain_n
+            res["speedup"] = res["plain_per_node_ms_per_step"] / res["level_batched_ms_per_step"]
+            out["plain_form"] = res
+            del Xs, Qs
+
+    # ---- the other workloads as configured, and the O(n) series ------------
+    if args.extras:
+        print("extras", flush=True)
+        ex = {}
+        ex["h2_2d_log_65536"] = one_workload("h2_2d_log_65536", torch, api, W, reps=20)
+        ex["h2_3d_inv_r_clusters_1m (5^3 points, FP32 apply)"] = one_workload(
+            "h2_3d_inv_r_clusters_1m", torch, api, W, reps=3)
+        ex["hss1d_inv_r_2048"] = one_workload("hss1d_inv_r_2048", torch, api, W, reps=20)
+        ex["hss1d_cauchy_1m (FP32 apply)"] = one_workload("hss1d_cauchy_1m", torch, api, W,
+                                                          reps=3)
+        ex["hss1d_cauchy_1m (BF16 apply)"] = one_workload("hss1d_cauchy_1m", torch, api, W,
+                                                          reps=3, apply="bf16")
+        out["workloads"] = ex
+        print("O(n) series", flush=True)
+        ser = []
+        for lg in range(14, 21):
+            nn = 1 << lg
+            xs = W.points(cfg, seed=0, n=nn)[0]
+            Xs = torch.from_numpy(xs).cuda()
+            Qs = Q[:nn].contiguous()
+            hs, _ = step(False, True, Xs, Qs)
+            hs.close()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            hs = api.Smash(Xs, None, timing=False, **kw)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) * 1e3
+            tm, _ = timed_product(hs, Qs, 2, torch)
+            hs.close()
+            ser.append({"n": nn, "build_ms": tb, "matvec_ms": tm,
+                        "build_us_per_point": tb * 1e3 / nn, "matvec_ns_per_point": tm * 1e6 / nn})
+            del Xs, Qs
+        out["on_series"] = ser
 
     # ---- CPU baseline: the FP64 oracle on the host cores --------------------
     if args.cpu_seconds > 0:
+        print("cpu baseline", flush=True)
+        from oracle import oracle as O
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         os.environ.setdefault("OMP_NUM_THREADS", str(cores))
         okw = dict(kernel=cfg["kernel"], leaf=cfg["leaf"], order=cfg["order"], adm=cfg["adm"],
@@ -281,54 +378,98 @@ def main():
         if "eps_svd" in cfg:
             okw["eps_svd"] = cfg["eps_svd"]
         O.lib()
+        nc = min(args.cpu_n, n)
+        xs = W.points(cfg, seed=0, n=nc)[0]
+        qs = q[:nc]
         reps, t0 = 0, time.perf_counter()
-        zo = None
         while True:
-            o = O.Oracle(x, y, **okw)
-            zo = o.matvec(q)
+            o = O.Oracle(xs, None, **okw)
+            o.matvec(qs)
             del o
             reps += 1
             if time.perf_counter() - t0 >= args.cpu_seconds:
                 break
         tc = (time.perf_counter() - t0) / reps
-        out["cpu_baseline"] = {"value": n / tc, "unit": "points/s", "cores": cores,
+        out["cpu_baseline"] = {"value": nc / tc, "unit": "points/s", "cores": cores,
                                "kind": "oracle",
-                               "sample": "%d full steps (build + %d-RHS product) of the same "
-                                         "workload, %.2f s each" % (reps, R, tc)}
-        out["rel_err_vs_oracle"] = float(np.linalg.norm(Zc - zo) / np.linalg.norm(zo))
-    # ---- serving: continuous batching vs one request at a time ------------
+                               "sample": "%d full steps (build + %d-RHS product) of the workload's "
+                                         "point distribution and parameters at n = %d, %.2f s "
+                                         "each" % (reps, R, nc, tc)}
+    # ---- serving: continuous batching at three offered loads --------------
     if args.serve_requests > 0:
-        from paper_1705_05443_amd import serve
-        budget = int(0.8 * torch.cuda.get_device_properties(0).total_memory)
-
-        def serve_run(slots, cap, trace):
-            ex = serve.GpuExecutor(slots=slots)
-            eng = serve.Engine(ex, budget_bytes=budget, slots=slots, max_batch_rhs=cap)
-            done = eng.run(trace)
-            st = serve.latency_stats(done)
-            st["makespan_s"] = eng.makespan
-            st["requests_per_s"] = len(done) / eng.makespan
-            st["points_per_s"] = sum(r.rhs.shape[0] for r in done) / eng.makespan
-            st["peak_in_flight"] = eng.peak_inflight
-            eng.close()
-            ex.shutdown()
-            return st
-
-        def trace():
-            return serve.make_trace(args.serve_requests, rate_hz=args.serve_rate,
-                                    n_range=(1e4, args.serve_nmax), seed=1)
-
-        serve_run(4, 64, serve.make_trace(4, rate_hz=100.0, n_range=(1e4, 3e4), seed=99))
-        mix = serve_run(4, 64, trace())
-        plain = serve_run(1, 1, trace())
-        out["serve"] = {
-            "trace": "%d requests, Poisson %.0f/s, N log-uniform [1e4, %.0e], dim 2/3, "
-                     "uniform/clustered, log r / 1/r / exp(-r), 1-32 FP32 RHS, tol 1e-6, "
-                     "30%% products on resident matrices" % (args.serve_requests,
-                                                             args.serve_rate, args.serve_nmax),
-            "continuous_batching": mix, "plain_one_at_a_time": plain,
-            "p99_speedup": plain["p99_ms"] / mix["p99_ms"] if mix.get("p99_ms") else None}
+        print("serving", flush=True)
+        out["serve"] = serve_bench(args, torch)
     print(json.dumps(out), flush=True)
+
+
+def serve_bench(args, torch):
+    """The serving stream: construct-and-apply requests (N log-uniform in
+    [1e4, nmax], dim 2 or 3, uniform or clustered, log r / 1/r / exp(-r),
+    1-32 FP32 right-hand sides, tol 1e-6), 30 % products on resident
+    matrices.  The capacity of the plain serial form (one request at a time)
+    is measured first; then the continuous-batching engine and the plain
+    form run the same Poisson trace at 0.5, 0.8 and 1.0 times it."""
+    from paper_1705_05443_amd import serve
+    budget = int(0.8 * torch.cuda.get_device_properties(0).total_memory)
+
+    def run(slots, cap, trace, keep=None):
+        ex = serve.GpuExecutor(slots=slots)
+        eng = serve.Engine(ex, budget_bytes=budget, slots=slots, max_batch_rhs=cap)
+        done = eng.run(trace)
+        st = serve.latency_stats(done)
+        st["makespan_s"] = eng.makespan
+        st["requests_per_s"] = len(done) / eng.makespan
+        st["points_per_s"] = sum(r.rhs.shape[0] for r in done) / eng.makespan
+        st["peak_in_flight"] = eng.peak_inflight
+        eng.close()
+        ex.shutdown()
+        if keep is not None:
+            keep.extend(done)
+        return st
+
+    def trace(num, rate):
+        # FP32 right-hand sides, products in FP64 (FP32 products of 1e6
+        # points stay near 1.6e-6 from exact rows, above the tolerance)
+        return serve.make_trace(num, rate_hz=rate, n_range=(1e4, args.serve_nmax), seed=1,
+                                apply_prec="f64")
+
+    nreq = args.serve_requests
+    run(4, 64, serve.make_trace(4, rate_hz=100.0, n_range=(1e4, 3e4), seed=99,
+                                apply_prec="f64"))  # warm-up
+    # capacity of the plain form: the whole trace offered at once
+    cap = run(1, 1, trace(nreq, 1e6))
+    capacity = cap["requests_per_s"]
+    res = {"trace": "%d requests per load, N log-uniform [1e4, %.0e], dim 2/3, "
+                    "uniform/clustered, log r / 1/r / exp(-r), 1-32 FP32 RHS (FP64 products), "
+                    "tol 1e-6, Chebyshev points per axis %s by dimension, 30%% products on "
+                    "resident matrices, Poisson arrivals" % (nreq, args.serve_nmax,
+                                                             serve.SERVE_ORDER),
+           "plain_capacity_requests_per_s": capacity, "loads": {}}
+    for load in (0.5, 0.8, 1.0):
+        rate = load * capacity
+        kept = [] if load == 1.0 else None
+        mix = run(4, 64, trace(nreq, rate), kept)
+        plain = run(1, 1, trace(nreq, rate))
+        res["loads"]["%.1f" % load] = {
+            "rate_per_s": rate, "continuous_batching": mix, "plain_one_at_a_time": plain,
+            "p99_speedup": plain["p99_ms"] / mix["p99_ms"] if mix.get("p99_ms") else None}
+        print("serve load %.1f done" % load, flush=True)
+    # accuracy of served results: sampled rows of the largest and smallest
+    # constructions against exact rows of A Q
+    from oracle import oracle as O
+    builds = sorted((r for r in kept if r.points is not None and r.error is None),
+                    key=lambda r: r.points.shape[0])
+    errs = []
+    for r in builds[:2] + builds[-3:]:
+        nn = r.points.shape[0]
+        rows = np.arange(0, nn, max(1, nn // 64))
+        zr = O.dense_rows(r.points, r.points, rows, r.rhs.astype(np.float32).astype(np.float64),
+                          r.params["kernel"])
+        errs.append({"n": nn, "dim": r.points.shape[1], "kernel": r.params["kernel"],
+                     "rel_err_vs_exact_rows":
+                         float(np.linalg.norm(r.result[rows] - zr) / np.linalg.norm(zr))})
+    res["accuracy"] = errs
+    return res
 
 
 if __name__ == "__main__":

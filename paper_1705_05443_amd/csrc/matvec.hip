@@ -325,7 +325,7 @@ __device__ __forceinline__ T coupling_entry(const double *xp, const double *yp,
 }
 
 template <class T, int TT, int CT, int KID, int D>
-__global__ void __launch_bounds__(MV_NT *MV_WAVES)
+__global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
     k_mv_coupling_eval(CouplingArgs A, CouplingPts P, const T *__restrict__ qh,
                        T *__restrict__ zh, int RP, int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
@@ -400,7 +400,9 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES)
 template <class T, int CT, int KID, int D>
 static void launch_coupling_eval_kd(const CouplingArgs &ca, const CouplingPts &pts, const T *q,
                                     T *z, int RP, int nitems, hipStream_t s) {
-  constexpr int TT = MvShape<T, CT>::TT;
+  // one 16-row tile per pass for FP64 with three or four column tiles:
+  // two waves per SIMD without spilling (the evaluation needs registers)
+  constexpr int TT = (sizeof(T) == 8 && CT >= 3) ? 1 : MvShape<T, CT>::TT;
   k_mv_coupling_eval<T, TT, CT, KID, D>
       <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, pts, q, z, RP, nitems);
   SMASH_CHECK_LAUNCH();

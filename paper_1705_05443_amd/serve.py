@@ -384,7 +384,10 @@ class GpuExecutor:
 
 
 # ---------------------------------------------------------------- traces
-SERVE_ORDER = {2: 8, 3: 5}
+# Chebyshev points per axis by dimension: the orders whose products stay
+# within 1e-6 of exact rows with FP64 apply (measured: 3D clustered 1/r at
+# 2^20 points, 6 per axis: 3.7e-7; 5 per axis: 4.4e-6)
+SERVE_ORDER = {2: 8, 3: 6}
 SERVE_LEAF = {2: 64, 3: 128}
 
 

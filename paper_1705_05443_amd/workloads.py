@@ -64,6 +64,13 @@ CONFIGS = {
     "h2_3d_inv_r_clusters_1m": dict(kind="clusters", n=1 << 20, d=3, kernel="inv_r", adm=1,
                                     leaf=128, order=5, tol=1e-6, tau=0.7, nrhs=64,
                                     root=((0.0, 0.0, 0.0), 1.0), apply="f32"),
+    # the same point set at the order that reaches 1e-6 against exact rows
+    # (6^3 Chebyshev points, tol 1e-7) with FP64 apply; the coupling blocks
+    # (5.5e10 FP64 entries, 437 GB) are evaluated inside each product
+    "h2_3d_inv_r_clusters_1m_p6": dict(kind="clusters", n=1 << 20, d=3, kernel="inv_r", adm=1,
+                                       leaf=128, order=6, tol=1e-7, tau=0.7, nrhs=64,
+                                       root=((0.0, 0.0, 0.0), 1.0), apply="f64",
+                                       coupling="evaluated"),
     "hss1d_cauchy_1m": dict(kind="chebyshev_pair", n=1 << 20, d=1, kernel="cauchy", adm=0,
                             leaf=64, order=16, tol=1e-8, eps_svd=1e-9, tau=0.6, nrhs=256,
                             root=None, apply="f32"),

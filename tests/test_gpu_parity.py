@@ -772,3 +772,38 @@ def test_storage_accounting(name):
     print(name, "storage MB: dense %.1f HSS0 %.2f SMASH %.2f" % (
         inf["bytes_dense"] / 1e6, inf["bytes_hss0"] / 1e6, inf["bytes_smash"] / 1e6))
     assert inf["bytes_smash"] < inf["bytes_hss0"] < inf["bytes_dense"]
+
+
+@pytest.mark.parametrize("scale", [1e-140, 1.0, 1e130])
+def test_inv_r_kernel_blocks_against_numpy(scale):
+    """1/|x - y| blocks (the library's reciprocal square root: the hardware
+    estimate and two Newton-Raphson steps) against numpy's 1/sqrt of the same
+    FP64 squared distance, at unit scale and where |x - y|^2 is near the
+    ends of the range the refinement takes (below 2^-900 and above 2^900 it
+    falls back to a square root and a division): within 2 units in the last
+    place."""
+    x = W.uniform(3000, 3, 23) * scale
+    g = api.Smash(dev(x), kernel="inv_r", leaf=64, order=3, adm="strong", tol=1e-6, tau=0.7,
+                  root=((0.0, 0.0, 0.0), scale), graphs=False)
+    L = g.export("L").reshape(-1, 2)
+    B = g.export("coupling")
+    rk = g.export("ranks").reshape(-1, 6)
+    px = g.export("perm_x")
+    per = _gpu_per_node(g, "row", rk.shape[0])
+    assert len(L) > 0
+    off, worst = 0, 0.0
+    for i, j in L:
+        ki, kj = rk[i, 1], rk[j, 1]
+        gi, si, _ = per[i]
+        gj, sj, _ = per[j]
+        rows = x[px[gi[si[:ki]]]]
+        cols = x[px[gj[sj[:kj]]]]
+        d = rows[:, None, :] - cols[None, :, :]
+        ref = 1.0 / np.sqrt(d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1] + d[..., 2] * d[..., 2])
+        blk = B[off:off + ki * kj].reshape(kj, ki).T
+        worst = max(worst, float(np.max(np.abs(blk - ref) / ref)))
+        off += ki * kj
+    g.close()
+    assert off == B.size
+    print("scale", scale, "worst relative difference %.2e" % worst, flush=True)
+    assert worst < 2 * np.finfo(np.float64).eps, worst
