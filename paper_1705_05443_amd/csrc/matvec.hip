@@ -233,84 +233,15 @@ struct NearShape {
   static constexpr int TT = sizeof(T) == 8 ? 2 : MvShape<T, CT>::TT;
 };
 
-// One workgroup per row node: MV_WAVES waves split its pairs, and each wave
-// covers TT 16-row tiles and all CT 16-column tiles of the right-hand sides
-// per pass, so a block B_ij is read once and every A operand it loads feeds
-// CT matrix-core steps (with many right-hand sides the product is bound by
-// the matrix cores, not by HBM).
-template <class T, int TT, int CT>
-__global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_coupling(CouplingArgs A,
-                                                                 const T *__restrict__ qh,
-                                                                 T *__restrict__ zh, int RP,
-                                                                 int nitems) {
-  typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
-  const int it = item_of_block(blockIdx.x, nitems, A.xrun);
-  if (it >= nitems) return;
-  const int i = A.i0 + it;
-  const int ki = A.krow[i];
-  if (ki == 0) return;
-  const int w = threadIdx.x / MV_NT;
-  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
-  T *out = zh + A.hrow[i] * RP + lr;
-  const T *Bv = (const T *)A.B;
-  const int p0 = A.Lrow[i], p1 = A.Lrow[i + 1];
-  for (int t0 = 0; t0 < ki; t0 += 16 * TT) {
-    acc_t acc[TT * CT];
-#pragma unroll
-    for (int x = 0; x < TT * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
-    for (int p = p0 + w; p < p1; p += MV_WAVES) {
-      const int j = A.Lj[p];
-      const int kj = A.kcol[j];
-      const T *Bp = Bv + A.boff[p];
-      const T *qj = qh + A.hcol[j] * RP + lr;
-      // K in chunks of 16: all loads of four MFMA steps are issued first
-      for (int s0 = 0; s0 < kj; s0 += 16) {
-        T bv[4][CT], av[4][TT];
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-          const int s = s0 + 4 * u + lk;
-          const bool ks = s < kj;
-#pragma unroll
-          for (int c = 0; c < CT; c++) bv[u][c] = ks ? qj[(int64_t)s * RP + 16 * c] : (T)0;
-#pragma unroll
-          for (int tt = 0; tt < TT; tt++) {
-            const int t = t0 + tt * 16 + lr;
-            av[u][tt] = (ks && t < ki) ? Bp[s * ki + t] : (T)0;
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < 4; u++)
-#pragma unroll
-          for (int tt = 0; tt < TT; tt++)
-#pragma unroll
-            for (int c = 0; c < CT; c++)
-              acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
-      }
-    }
-    reduce_waves_n<T, MV_WAVES, TT * CT>(acc, red);
-    if (w == 0)
-#pragma unroll
-      for (int tt = 0; tt < TT; tt++)
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-          const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
-          if (t < ki)
-#pragma unroll
-            for (int c = 0; c < CT; c++) out[(int64_t)t * RP + 16 * c] = acc[tt * CT + c][e];
-        }
-  }
-}
-
-// ---- coupling with the blocks evaluated inside the contraction -----------
-// The index-only form (Sec. 1.1: a block is fixed by its row and column
-// index sets; Sec. 2.3 end): no block is stored.  The same workgroup and
-// matrix-core layout as k_mv_coupling, but each lane computes the entry
-// B_ij(t, s) = kappa(x_t, y_s) it feeds to the matrix core, from the
-// coordinates of the skeleton slots (gathered once per construction), with
-// the same kernel-value function the stored form uses -- so the product is
-// the stored form's bit for bit.  Every entry is evaluated once per product
-// and feeds CT matrix-core steps (one per 16 right-hand sides).
+// ---- coupling: z-hat_i = sum over the L row of i of B_ij q-hat_j ---------
+// Stored blocks, or the index-only form (Sec. 1.1: a block is fixed by its
+// row and column index sets; Sec. 2.3 end) with no block stored: each lane
+// then computes the entry B_ij(t, s) = kappa(x_t, y_s) it feeds to the
+// matrix core, from the coordinates of the skeleton slots (gathered once
+// per construction), with the same kernel-value function the stored form
+// uses.  Both forms run the same kernel in the same order of summation, so
+// their products agree bit for bit.  Every entry is read or evaluated once
+// per product and feeds CT matrix-core steps (one per 16 right-hand sides).
 struct CouplingPts {
   const double *xs, *ys;  // D coordinates per slot: row side (X), column side (Y)
   double diag;
@@ -324,86 +255,210 @@ __device__ __forceinline__ T coupling_entry(const double *xp, const double *yp,
   return (T)kernel_f64_t<KID, D>(xp, yp, P.diag);
 }
 
-template <class T, int TT, int CT, int KID, int D>
+// One workgroup per row node i.  Its waves split the row tiles of i (wave
+// w: tiles w, w + 4, ..., RTW per pass) and walk every pair of i's L row
+// together, so a chunk of 16 rows of q-hat_j (all right-hand sides) and the
+// coordinates of its 16 column points are loaded once per workgroup into
+// LDS (two buffers; the next chunk's loads are in flight while the current
+// one is contracted) and every q-hat value read from LDS feeds RTW matrix-
+// core steps.  Each lane evaluates the entries of B_ij it feeds.
+template <class T, int RTW, int CT, bool EVAL, int KID, int D>
 __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
-    k_mv_coupling_eval(CouplingArgs A, CouplingPts P, const T *__restrict__ qh,
+    k_mv_coupling_rows(CouplingArgs A, CouplingPts P, const T *__restrict__ qh,
                        T *__restrict__ zh, int RP, int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T red[(MV_WAVES - 1) * TT * CT * 4 * MV_NT];
+  constexpr int QW = 16 * CT;                   // right-hand sides of a chunk row
+  constexpr int QE = 16 * QW;                   // values of a chunk
+  constexpr int NT = MV_NT * MV_WAVES;
+  constexpr int QPT = (QE + NT - 1) / NT;       // staged values per thread
+  // row tiles of the pair-split path (nodes of up to 16 TTS rows take it)
+  constexpr int TTS = (sizeof(T) == 8 && CT >= 3) ? 1 : MvShape<T, CT>::TT;
+  constexpr size_t SH_ROWS = sizeof(T) * 2 * QE + sizeof(double) * 2 * 16 * D;
+  constexpr size_t SH_PAIRS = sizeof(T) * (MV_WAVES - 1) * TTS * CT * 4 * MV_NT;
+  __shared__ __align__(16) unsigned char smem[SH_ROWS > SH_PAIRS ? SH_ROWS : SH_PAIRS];
   const int it = item_of_block(blockIdx.x, nitems, A.xrun);
   if (it >= nitems) return;
   const int i = A.i0 + it;
   const int ki = A.krow[i];
   if (ki == 0) return;
-  const int w = threadIdx.x / MV_NT;
-  const int l = threadIdx.x & (MV_NT - 1), lr = l & 15, lk = l >> 4;
+  const int tid = threadIdx.x;
+  const int w = tid / MV_NT;
+  const int l = tid & (MV_NT - 1), lr = l & 15, lk = l >> 4;
   T *out = zh + A.hrow[i] * RP + lr;
-  const double *xi = P.xs + A.hrow[i] * D;
+  const double *xi = EVAL ? P.xs + A.hrow[i] * D : nullptr;
+  const T *Bv = (const T *)A.B;
   const int p0 = A.Lrow[i], p1 = A.Lrow[i + 1];
-  for (int t0 = 0; t0 < ki; t0 += 16 * TT) {
-    // coordinates of this lane's rows t = t0 + 16 tt + lr
-    double xr[TT][D];
-    bool tin[TT];
+  const int nt = (ki + 15) / 16;
+  if (nt <= TTS) {
+    // small nodes: the waves split the pairs instead (each all row tiles),
+    // then their partial sums are added in LDS
+    T *red = (T *)smem;
+    double xr[TTS][D];
+    bool tin[TTS];
 #pragma unroll
-    for (int tt = 0; tt < TT; tt++) {
-      const int t = t0 + tt * 16 + lr;
+    for (int tt = 0; tt < TTS; tt++) {
+      const int t = 16 * tt + lr;
       tin[tt] = t < ki;
 #pragma unroll
-      for (int e = 0; e < D; e++) xr[tt][e] = tin[tt] ? xi[(int64_t)t * D + e] : 0.0;
+      for (int e = 0; e < D; e++) xr[tt][e] = (EVAL && tin[tt]) ? xi[(int64_t)t * D + e] : 0.0;
     }
-    acc_t acc[TT * CT];
+    acc_t acc[TTS * CT];
 #pragma unroll
-    for (int x = 0; x < TT * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
+    for (int x = 0; x < TTS * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
     for (int p = p0 + w; p < p1; p += MV_WAVES) {
       const int j = A.Lj[p];
       const int kj = A.kcol[j];
       const T *qj = qh + A.hcol[j] * RP + lr;
-      const double *yj = P.ys + A.hcol[j] * D;
+      const double *yj = EVAL ? P.ys + A.hcol[j] * D : nullptr;
+      const T *Bp = EVAL ? nullptr : Bv + A.boff[p];
+      // K in chunks of 16: the operands of four matrix-core steps are
+      // loaded (or evaluated) first, then the steps run
       for (int s0 = 0; s0 < kj; s0 += 16) {
-        T bv[4][CT], av[4][TT];
+        T bv[4][CT], av[4][TTS];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           const int s = s0 + 4 * u + lk;
           const bool ks = s < kj;
 #pragma unroll
           for (int c = 0; c < CT; c++) bv[u][c] = ks ? qj[(int64_t)s * RP + 16 * c] : (T)0;
-          double yc[D];
+          if constexpr (EVAL) {
+            double yc[D];
 #pragma unroll
-          for (int e = 0; e < D; e++) yc[e] = ks ? yj[(int64_t)s * D + e] : 0.0;
+            for (int e = 0; e < D; e++) yc[e] = ks ? yj[(int64_t)s * D + e] : 0.0;
 #pragma unroll
-          for (int tt = 0; tt < TT; tt++)
-            av[u][tt] = (ks && tin[tt]) ? coupling_entry<T, KID, D>(xr[tt], yc, P) : (T)0;
+            for (int tt = 0; tt < TTS; tt++)
+              av[u][tt] = (ks && tin[tt]) ? coupling_entry<T, KID, D>(xr[tt], yc, P) : (T)0;
+          } else {
+#pragma unroll
+            for (int tt = 0; tt < TTS; tt++)
+              av[u][tt] = (ks && tin[tt]) ? Bp[(int64_t)s * ki + 16 * tt + lr] : (T)0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < 4; u++)
 #pragma unroll
-          for (int tt = 0; tt < TT; tt++)
+          for (int tt = 0; tt < TTS; tt++)
 #pragma unroll
             for (int c = 0; c < CT; c++)
               acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
       }
     }
-    reduce_waves_n<T, MV_WAVES, TT * CT>(acc, red);
+    reduce_waves_n<T, MV_WAVES, TTS * CT>(acc, red);
     if (w == 0)
 #pragma unroll
-      for (int tt = 0; tt < TT; tt++)
+      for (int tt = 0; tt < TTS; tt++)
 #pragma unroll
         for (int e = 0; e < 4; e++) {
-          const int t = t0 + tt * 16 + Mfma<T>::row(lk, e);
+          const int t = 16 * tt + Mfma<T>::row(lk, e);
           if (t < ki)
 #pragma unroll
             for (int c = 0; c < CT; c++) out[(int64_t)t * RP + 16 * c] = acc[tt * CT + c][e];
         }
+    return;
+  }
+  T (*qs)[QE] = (T (*)[QE])smem;
+  double (*ys)[16 * D] = (double (*)[16 * D])(smem + sizeof(T) * 2 * QE);
+  for (int tb = 0; tb < nt; tb += MV_WAVES * RTW) {
+    // coordinates of this lane's rows t = 16 (tb + w + 4 tt) + lr
+    double xr[RTW][D];
+    bool tin[RTW];
+#pragma unroll
+    for (int tt = 0; tt < RTW; tt++) {
+      const int t = 16 * (tb + w + MV_WAVES * tt) + lr;
+      tin[tt] = t < ki;
+#pragma unroll
+      for (int e = 0; e < D; e++) xr[tt][e] = (EVAL && tin[tt]) ? xi[(int64_t)t * D + e] : 0.0;
+    }
+    acc_t acc[RTW * CT];
+#pragma unroll
+    for (int x = 0; x < RTW * CT; x++) acc[x] = acc_t{0, 0, 0, 0};
+    // the chunks of the L row: pair p, rows s0 .. s0 + 15 of q-hat_j
+    int p = p0, s0 = 0;
+    T qv[QPT];
+    double yv = 0.0;
+    auto fetch = [&](int pp, int ss) {
+      const int j = A.Lj[pp];
+      const int kj = A.kcol[j];
+      const T *qj = qh + A.hcol[j] * RP;
+#pragma unroll
+      for (int e = 0; e < QPT; e++) {
+        const int q = tid + NT * e;
+        const int r = q / QW, cc = q - r * QW;
+        qv[e] = (q < QE && ss + r < kj) ? qj[(int64_t)(ss + r) * RP + cc] : (T)0;
+      }
+      if (EVAL && tid < 16 * D) {
+        const int r = tid / D;
+        yv = ss + r < kj ? P.ys[(A.hcol[j] + ss + r) * D + (tid - r * D)] : 0.0;
+      }
+    };
+    if (p < p1) fetch(p, s0);
+    int buf = 0;
+    while (p < p1) {
+      const int kj = A.kcol[A.Lj[p]];
+#pragma unroll
+      for (int e = 0; e < QPT; e++) {
+        const int q = tid + NT * e;
+        if (q < QE) qs[buf][q] = qv[e];
+      }
+      if (EVAL && tid < 16 * D) ys[buf][tid] = yv;
+      __syncthreads();
+      const T *Bp = EVAL ? nullptr : Bv + A.boff[p];
+      // the next chunk's loads, in flight during this chunk's steps
+      int pn = p, sn = s0 + 16;
+      if (sn >= kj) {
+        pn = p + 1;
+        sn = 0;
+      }
+      if (pn < p1) fetch(pn, sn);
+      const T *qb = qs[buf];
+      const double *yb = ys[buf];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const int sr = 4 * u + lk;  // row of the chunk
+        const bool ks = s0 + sr < kj;
+        T bv[CT];
+#pragma unroll
+        for (int c = 0; c < CT; c++) bv[c] = qb[sr * QW + 16 * c + lr];
+        double yc[D];
+#pragma unroll
+        for (int e = 0; e < D; e++) yc[e] = yb[sr * D + e];
+#pragma unroll
+        for (int tt = 0; tt < RTW; tt++) {
+          if (tb + w + MV_WAVES * tt >= nt) break;  // no such tile (uniform in the wave)
+          T av = (T)0;
+          if (ks && tin[tt]) {
+            if constexpr (EVAL)
+              av = coupling_entry<T, KID, D>(xr[tt], yc, P);
+            else  // stored column-major: entry (t, s) at s ki + t
+              av = Bp[(int64_t)(s0 + sr) * ki + 16 * (tb + w + MV_WAVES * tt) + lr];
+          }
+#pragma unroll
+          for (int c = 0; c < CT; c++) acc[tt * CT + c] = Mfma<T>::op(av, bv[c], acc[tt * CT + c]);
+        }
+      }
+      buf ^= 1;
+      p = pn;
+      s0 = sn;
+    }
+#pragma unroll
+    for (int tt = 0; tt < RTW; tt++) {
+      const int t0 = 16 * (tb + w + MV_WAVES * tt);
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int t = t0 + Mfma<T>::row(lk, e);
+        if (t < ki)
+#pragma unroll
+          for (int c = 0; c < CT; c++) out[(int64_t)t * RP + 16 * c] = acc[tt * CT + c][e];
+      }
+    }
   }
 }
 
 template <class T, int CT, int KID, int D>
 static void launch_coupling_eval_kd(const CouplingArgs &ca, const CouplingPts &pts, const T *q,
                                     T *z, int RP, int nitems, hipStream_t s) {
-  // one 16-row tile per pass for FP64 with three or four column tiles:
-  // two waves per SIMD without spilling (the evaluation needs registers)
-  constexpr int TT = (sizeof(T) == 8 && CT >= 3) ? 1 : MvShape<T, CT>::TT;
-  k_mv_coupling_eval<T, TT, CT, KID, D>
+  // four row tiles per wave: one pass covers nodes of up to 256 skeleton points
+  k_mv_coupling_rows<T, 4, CT, true, KID, D>
       <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, pts, q, z, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
@@ -572,8 +627,11 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_near_out(NearArgs A,
 template <class T, int CT>
 static void launch_coupling(const CouplingArgs &ca, const T *q, T *z, int RP, int nitems,
                             hipStream_t s) {
-  k_mv_coupling<T, MvShape<T, CT>::TT, CT>
-      <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, q, z, RP, nitems);
+  // stored blocks: the same kernel, order of summation and result as the
+  // evaluated form
+  const CouplingPts none{nullptr, nullptr, 0.0, 0};
+  k_mv_coupling_rows<T, 4, CT, false, 0, 1>
+      <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, none, q, z, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
 
@@ -724,7 +782,8 @@ __global__ void __launch_bounds__(MV_NT *W) k_mvb_down(SweepArgsB A, const float
   }
 }
 
-// coupling: as k_mv_coupling, K in chunks of 32
+// coupling: one workgroup per row node, its waves splitting the pairs, K in
+// chunks of 32
 template <int TT, int CT>
 __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mvb_coupling(CouplingArgs A,
                                                                   const float *__restrict__ qh,
