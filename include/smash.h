@@ -45,6 +45,12 @@ extern "C" {
 #define SMASH_KERNEL_LOG_R 1  /* log|x-y|,  kappa(x,x) = diag_value          */
 #define SMASH_KERNEL_EXP_R 2  /* exp(-|x-y|), its own value 1 at x = y       */
 #define SMASH_KERNEL_CAUCHY 3 /* 1/(x-y) on the real line (dim 1 only), eq. (2.1) */
+/* Laplace double layer in Nystrom form (Sec. 6.4, eq. (6.9)), dim 2, X = Y:
+ * kappa(x, y) = -((y - x) . m_y) / (2 pi |x - y|^2) with m_y the column
+ * point's weighted normal (quadrature weight times speed times outer unit
+ * normal), and kappa(x, x) = the row point's own diagonal value.  Needs
+ * options.point_data.  Coupling blocks are stored (not evaluated). */
+#define SMASH_KERNEL_DOUBLE_LAYER 4
 
 /* ---- admissibility (Sec. 3.2) ---- */
 #define SMASH_ADM_WEAK 0   /* HSS: binary tree, (i,j) admissible iff i != j  */
@@ -141,6 +147,10 @@ typedef struct smash_options {
   smash_alloc_fn alloc; /* both NULL (default): the library's own pool */
   smash_free_fn free;
   void *alloc_ctx;
+  /* SMASH_KERNEL_DOUBLE_LAYER: device, n x 3 FP64 row-major in the points'
+   * order, per point (m_1, m_2, diagonal value); borrowed like the points.
+   * NULL for every other kernel. */
+  const double *point_data;
 } smash_options;
 
 int smash_default_options(smash_options *opt);

@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "smash_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3}
+KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3, "double_layer": 4}
 
 # export codes (mirrored from smash_oracle.c)
 EX_PERM_X, EX_PERM_Y, EX_NODES, EX_BOXES, EX_L, EX_LM = 1, 2, 3, 4, 5, 6
@@ -59,8 +59,12 @@ def lib():
         L.oracle_build.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int, C.c_int,
                                    C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                    C.c_double, C.c_double, C.c_double, C.c_int, dp,
-                                   C.c_double, C.c_int, C.POINTER(C.c_void_p)]
+                                   C.c_double, C.c_int, dp, C.POINTER(C.c_void_p)]
         L.oracle_build.restype = C.c_int
+        L.oracle_build_tree.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int, C.c_int,
+                                        C.c_int, C.c_int, C.c_double, C.c_int, dp, C.c_double,
+                                        C.c_int, dp, C.POINTER(C.c_void_p)]
+        L.oracle_build_tree.restype = C.c_int
         L.oracle_matvec.argtypes = [C.c_void_p, dp, C.c_int64, dp]
         L.oracle_matvec.restype = C.c_int
         L.oracle_export.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.POINTER(C.c_int64)]
@@ -68,14 +72,14 @@ def lib():
         L.oracle_destroy.argtypes = [C.c_void_p]
         L.oracle_destroy.restype = None
         L.oracle_dense_matvec.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int,
-                                          C.c_double, dp, C.c_int64, dp]
+                                          C.c_double, dp, dp, dp, C.c_int64, dp]
         L.oracle_dense_matvec.restype = None
         L.oracle_dense_rows.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int,
-                                        C.c_double, C.POINTER(C.c_int64), C.c_int64, dp,
-                                        C.c_int64, dp]
+                                        C.c_double, dp, dp, C.POINTER(C.c_int64), C.c_int64,
+                                        dp, C.c_int64, dp]
         L.oracle_dense_rows.restype = None
         L.oracle_kernel_block.argtypes = [dp, dp, C.c_int64, C.c_int64, C.c_int, C.c_int,
-                                          C.c_double, dp]
+                                          C.c_double, dp, dp, dp]
         L.oracle_kernel_block.restype = None
         L.oracle_compr.argtypes = [dp, C.c_int, C.c_int, C.c_double, C.c_double, ip, ip, dp, ip]
         L.oracle_compr.restype = C.c_int
@@ -94,7 +98,19 @@ def lib():
 
 
 def _dp(a):
+    if a is None:
+        return None
     return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _data(a, n):
+    """per-point data (n x 3: m_1, m_2, diagonal) of the double-layer kernel"""
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (n, 3):
+        raise ValueError("point data must be (n, 3)")
+    return a
 
 
 def _f64(a):
@@ -109,7 +125,8 @@ class Oracle:
     """An oracle construction: tree, pair lists, IDs; ``matvec`` applies it."""
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=32, order=10, adm=1, tol=1e-10,
-                 tau=None, eps_svd=None, f=2.0, diag=None, root=None, max_depth=0):
+                 tau=None, eps_svd=None, f=2.0, diag=None, root=None, max_depth=0,
+                 point_data=None, tree_only=False):
         x = _f64(x)
         if x.ndim == 1:
             x = x[:, None]
@@ -133,11 +150,19 @@ class Oracle:
             side = float(root[1])
         self.d, self.kid, self.adm, self.diag = d, kid, adm, diag
         self.x, self.y, self.same = x, y, same
+        self.point_data = _data(point_data, x.shape[0])
         h = C.c_void_p()
-        rc = lib().oracle_build(_dp(x), x.shape[0], _dp(y), y.shape[0], int(same), d, kid,
-                                int(leaf), int(order), int(adm), float(tol), float(tau),
-                                float(eps_svd), float(f), float(diag), int(has_root), _dp(rlo),
-                                side, int(max_depth), C.byref(h))
+        if tree_only:  # partition and pair lists only (no generators, no product)
+            rc = lib().oracle_build_tree(_dp(x), x.shape[0], _dp(y), y.shape[0], int(same), d,
+                                         kid, int(leaf), int(adm), float(tau), int(has_root),
+                                         _dp(rlo), side, int(max_depth), _dp(self.point_data),
+                                         C.byref(h))
+        else:
+            rc = lib().oracle_build(_dp(x), x.shape[0], _dp(y), y.shape[0], int(same), d, kid,
+                                    int(leaf), int(order), int(adm), float(tol), float(tau),
+                                    float(eps_svd), float(f), float(diag), int(has_root),
+                                    _dp(rlo), side, int(max_depth), _dp(self.point_data),
+                                    C.byref(h))
         if rc != 0:
             raise OracleError("oracle_build failed with code %d" % rc)
         self._h = h
@@ -216,9 +241,11 @@ def _pts(a):
     return a[:, None] if a.ndim == 1 else a
 
 
-def dense_matvec(x, y, Q, kernel="inv_r", diag=None):
-    """Exact A Q with A = [kappa(x, y)] (definition of A in Sec. 3)."""
+def dense_matvec(x, y, Q, kernel="inv_r", diag=None, data_x=None, data_y=None):
+    """Exact A Q with A = [kappa(x, y)] (definition of A in Sec. 3); data_x,
+    data_y: the points' data for the double-layer kernel."""
     x, y = _pts(x), _pts(y)
+    data_x, data_y = _data(data_x, x.shape[0]), _data(data_y, y.shape[0])
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     if diag is None:
         diag = 1.0 if kid == 2 else 0.0
@@ -227,13 +254,14 @@ def dense_matvec(x, y, Q, kernel="inv_r", diag=None):
     Q = np.ascontiguousarray(Q[:, None] if vec else Q)
     Z = np.zeros((x.shape[0], Q.shape[1]))
     lib().oracle_dense_matvec(_dp(x), x.shape[0], _dp(y), y.shape[0], x.shape[1], kid,
-                              float(diag), _dp(Q), Q.shape[1], _dp(Z))
+                              float(diag), _dp(data_x), _dp(data_y), _dp(Q), Q.shape[1], _dp(Z))
     return Z[:, 0] if vec else Z
 
 
-def dense_rows(x, y, rows, Q, kernel="inv_r", diag=None):
+def dense_rows(x, y, rows, Q, kernel="inv_r", diag=None, data_x=None, data_y=None):
     """Exact rows of A Q for the given original row indices."""
     x, y = _pts(x), _pts(y)
+    data_x, data_y = _data(data_x, x.shape[0]), _data(data_y, y.shape[0])
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     if diag is None:
         diag = 1.0 if kid == 2 else 0.0
@@ -243,19 +271,21 @@ def dense_rows(x, y, rows, Q, kernel="inv_r", diag=None):
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     Z = np.zeros((rows.shape[0], Q.shape[1]))
     lib().oracle_dense_rows(_dp(x), x.shape[0], _dp(y), y.shape[0], x.shape[1], kid,
-                            float(diag), rows.ctypes.data_as(C.POINTER(C.c_int64)),
+                            float(diag), _dp(data_x), _dp(data_y),
+                            rows.ctypes.data_as(C.POINTER(C.c_int64)),
                             rows.shape[0], _dp(Q), Q.shape[1], _dp(Z))
     return Z[:, 0] if vec else Z
 
 
-def kernel_block(P, Qp, kernel="inv_r", diag=None):
+def kernel_block(P, Qp, kernel="inv_r", diag=None, data_P=None, data_Q=None):
     P, Qp = _pts(P), _pts(Qp)
+    data_P, data_Q = _data(data_P, P.shape[0]), _data(data_Q, Qp.shape[0])
     kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     if diag is None:
         diag = 1.0 if kid == 2 else 0.0
     B = np.zeros((P.shape[0], Qp.shape[0]))
     lib().oracle_kernel_block(_dp(P), _dp(Qp), P.shape[0], Qp.shape[0], P.shape[1], kid,
-                              float(diag), _dp(B))
+                              float(diag), _dp(data_P), _dp(data_Q), _dp(B))
     return B
 
 

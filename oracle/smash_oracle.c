@@ -43,11 +43,18 @@
 
 /* ------------------------------------------------------------------ */
 /* Kernel functions.  Kernel 3 is eq. (2.1) restricted to the real line;
- * the others are the radial test kernels.  "x = y" means every coordinate
- * equal; then singular kernels return the chosen diagonal value d_x.      */
+ * kernels 0-2 are the radial test kernels.  Kernel 4 is the Laplace
+ * double layer of Sec. 6.4, eq. (6.9), in its Nystrom form: with
+ * Phi(x, y) = -log|x - y| / (2 pi), the normal derivative at y times the
+ * speed |r'| and the quadrature weight is grad_y Phi . m_y
+ * = -((y - x) . m_y) / (2 pi |x - y|^2), where the column point's data
+ * ay = (m_y1, m_y2, .) carries m_y = w (r2', -r1') (the outer normal of a
+ * counterclockwise curve times |r'| w).  "x = y" means every coordinate
+ * equal; then singular kernels return the chosen diagonal value d_x --
+ * for kernel 4 the row point's own (ax[2]).                              */
 /* ------------------------------------------------------------------ */
 static double kernel_value(int kid, const double *x, const double *y, int d,
-                           double diag) {
+                           double diag, const double *ax, const double *ay) {
   int same = 1;
   double r2 = 0.0;
   for (int t = 0; t < d; t++) {
@@ -56,12 +63,20 @@ static double kernel_value(int kid, const double *x, const double *y, int d,
     r2 += df * df;
   }
   if (kid == 2) return exp(-sqrt(r2));
+  if (kid == 4) {
+    if (same) return ax[2];
+    double proj = (y[0] - x[0]) * ay[0] + (y[1] - x[1]) * ay[1];
+    return -proj / (2.0 * M_PI * r2);
+  }
   if (same) return diag;
   if (kid == 0) return 1.0 / sqrt(r2);
   if (kid == 1) return log(sqrt(r2));
   /* kid == 3: 1/(x - y) on the real line */
   return 1.0 / (x[0] - y[0]);
 }
+
+/* per-point data of point i (kernel 4), or NULL */
+static const double *pd_at(const double *A, int64_t i) { return A ? A + 3 * i : NULL; }
 
 /* ------------------------------------------------------------------ */
 /* Adaptive partition (Sec. 3.1; Remark A.1 for the binary HSS tree).    */
@@ -141,6 +156,7 @@ typedef struct {
   double tol, tau, eps_svd, f, diag;
   int nx, ny;
   double *X, *Y;          /* permuted coordinates, n x d row-major */
+  double *AX;             /* kernel 4: permuted per-point data, n x 3 (X = Y) */
   int *perm_x, *perm_y;   /* perm[a] = original index of permuted point a */
   geom_t g;
   /* nodes, BFS order (level by level, Morton order inside a level) */
@@ -880,15 +896,11 @@ static double *near_block(oracle_t *h, int i, int rowside, int *ncols) {
     side_t *js = &ot[h->Ncol[a]];
     for (int b = 0; b < js->m; b++) {
       for (int r = 0; r < m; r++) {
-        const double *xp, *yp;
-        if (rowside) {
-          xp = h->X + (size_t)me[i].grid[r] * h->d;
-          yp = h->Y + (size_t)js->grid[b] * h->d;
-        } else {
-          xp = h->X + (size_t)js->grid[b] * h->d;
-          yp = h->Y + (size_t)me[i].grid[r] * h->d;
-        }
-        A[(size_t)r * n + o] = kernel_value(h->kid, xp, yp, h->d, h->diag);
+        const int xi = rowside ? me[i].grid[r] : js->grid[b];
+        const int yi = rowside ? js->grid[b] : me[i].grid[r];
+        A[(size_t)r * n + o] =
+            kernel_value(h->kid, h->X + (size_t)xi * h->d, h->Y + (size_t)yi * h->d, h->d,
+                         h->diag, pd_at(h->AX, xi), pd_at(h->AX, yi));
       }
       o++;
     }
@@ -898,7 +910,12 @@ static double *near_block(oracle_t *h, int i, int rowside, int *ncols) {
 
 static int compress_node(oracle_t *h, int i, int rowside) {
   side_t *s = rowside ? &h->row[i] : &h->col[i];
-  int d = h->d, c0 = ipow(h->p, d);
+  int d = h->d, pd = ipow(h->p, d);
+  /* kernel 4, column side: kappa(x, y) = m_y . grad_y Phi(x, y), a sum of
+   * two functions of y smooth away from x, each weighted by a component of
+   * m_y: the basis is [m_y1 U-hat(y), m_y2 U-hat(y)] (width 2 p^d)       */
+  const int dl_col = h->kid == 4 && !rowside;
+  int c0 = dl_col ? 2 * pd : pd;
   int m = s->m;
   const double *P = rowside ? h->X : h->Y;
   double *S = NULL;
@@ -943,6 +960,15 @@ static int compress_node(oracle_t *h, int i, int rowside) {
     hi[t] = h->hi[3 * i + t];
   }
   interp_basis(pts, m, d, lo, hi, h->p, C, c);
+  if (dl_col)
+    for (int a = 0; a < m; a++) {
+      const double *da = h->AX + (size_t)s->grid[a] * 3;
+      double *Ca = C + (size_t)a * c;
+      for (int q = 0; q < pd; q++) {
+        Ca[pd + q] = da[1] * Ca[q];
+        Ca[q] = da[0] * Ca[q];
+      }
+    }
   for (int a = 0; a < m; a++)
     for (int q = 0; q < ks; q++) C[(size_t)a * c + c0 + q] = S[(size_t)a * m + q];
   s->G = (double *)malloc(sizeof(double) * ((size_t)m * c + 1));
@@ -1019,6 +1045,7 @@ void oracle_destroy(void *hv) {
   free_side(h->row, h->nnodes);
   free(h->X);
   free(h->Y);
+  free(h->AX);
   free(h->perm_x);
   free(h->perm_y);
   free(h->level);
@@ -1047,15 +1074,47 @@ void oracle_destroy(void *hv) {
  * is X (then the column side is reused for symmetric kernels).  adm: 0 weak
  * (HSS, binary tree), 1 strong (H^2, 2^d-tree).  root: if has_root, the box
  * [root_lo, root_lo + root_side]^d, else the bounding cube of X and Y.     */
+/* data: kernel 4 only, the per-point data of the points (n x 3, original
+ * order: m_1, m_2, diagonal value); X = Y is required for kernel 4.      */
+static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
+                      int d, int kid, int leaf, int p, int adm, double tol, double tau,
+                      double eps_svd, double f, double diag, int has_root, const double *root_lo,
+                      double root_side, int max_depth, const double *data, int tree_only,
+                      void **out);
+
 int oracle_build(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
                  int d, int kid, int leaf, int p, int adm, double tol, double tau,
                  double eps_svd, double f, double diag, int has_root, const double *root_lo,
-                 double root_side, int max_depth, void **out) {
+                 double root_side, int max_depth, const double *data, void **out) {
+  return build_impl(x, nx, y, ny, same_xy, d, kid, leaf, p, adm, tol, tau, eps_svd, f, diag,
+                    has_root, root_lo, root_side, max_depth, data, 0, out);
+}
+
+/* The partition and the pair lists only (Sec. 3.1, eqs. (3.3)-(3.5), (A.1)):
+ * for tests that need the tree of a large case without its generators.
+ * Exports that need generators return OR_EUNSUP.                          */
+int oracle_build_tree(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
+                      int d, int kid, int leaf, int adm, double tau, int has_root,
+                      const double *root_lo, double root_side, int max_depth, const double *data,
+                      void **out) {
+  return build_impl(x, nx, y, ny, same_xy, d, kid, leaf, 1, adm, 0.0, tau, 0.0, 2.0, 0.0,
+                    has_root, root_lo, root_side, max_depth, data, 1, out);
+}
+
+static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
+                      int d, int kid, int leaf, int p, int adm, double tol, double tau,
+                      double eps_svd, double f, double diag, int has_root, const double *root_lo,
+                      double root_side, int max_depth, const double *data, int tree_only,
+                      void **out) {
   *out = NULL;
   if (d < 1 || d > 3 || nx < 1 || ny < 1 || leaf < 1 || p < 1 || p > 64 || tau <= 0.0 ||
-      tau >= 1.0 || f <= 1.0 || tol < 0.0 || (adm != 0 && adm != 1) || kid < 0 || kid > 3)
+      tau >= 1.0 || f <= 1.0 || tol < 0.0 || (adm != 0 && adm != 1) || kid < 0 || kid > 4)
     return OR_EINVAL;
   if (kid == 3 && d != 1) return OR_EUNSUP;
+  if (kid == 4 && (d != 2 || !same_xy || !data)) return OR_EUNSUP;
+  if (kid == 4)
+    for (int64_t a = 0; a < nx * 3; a++)
+      if (!isfinite(data[a])) return OR_ENUMERIC;
   oracle_t *h = (oracle_t *)calloc(1, sizeof(oracle_t));
   if (!h) return OR_ENOMEM;
   h->d = d;
@@ -1070,7 +1129,7 @@ int oracle_build(const double *x, int64_t nx, const double *y, int64_t ny, int s
   h->diag = diag;
   h->nx = (int)nx;
   h->ny = (int)ny;
-  h->symmetric_reuse = same_xy && kid != 3;
+  h->symmetric_reuse = same_xy && kid != 3 && kid != 4;
   h->g.d = d;
   h->g.hss = adm == 0;
   h->g.bpl = adm == 0 ? 1 : d;
@@ -1124,13 +1183,19 @@ int oracle_build(const double *x, int64_t nx, const double *y, int64_t ny, int s
     for (int t = 0; t < d; t++) h->g.hi[t] = h->g.lo[t] + side;
   }
   int rc = build_tree(h, x, y);
+  if (!rc && kid == 4) {
+    h->AX = (double *)malloc(sizeof(double) * (size_t)h->nx * 3);
+    if (!h->AX) rc = OR_ENOMEM;
+    for (int a = 0; !rc && a < h->nx; a++)
+      for (int c = 0; c < 3; c++) h->AX[(size_t)a * 3 + c] = data[(size_t)h->perm_x[a] * 3 + c];
+  }
   if (!rc) rc = adm == 1 ? h2_pairs(h) : hss_pairs(h);
   if (!rc) {
     h->Lrow = csr_rows(h->Li, h->nL, h->nnodes);
     h->Lmrow = csr_rows(h->Lmi, h->nLm, h->nnodes);
     if (!h->Lrow || !h->Lmrow) rc = OR_ENOMEM;
   }
-  if (!rc) rc = build_generators(h);
+  if (!rc && !tree_only) rc = build_generators(h);
   if (rc) {
     oracle_destroy(h);
     return rc;
@@ -1175,6 +1240,7 @@ static void apply_id(const side_t *s, const double *zh, int R, double *zbar) {
 
 int oracle_matvec(void *hv, const double *Q, int64_t R64, double *Z) {
   oracle_t *h = (oracle_t *)hv;
+  if (!h->row) return OR_EUNSUP; /* a tree-only build */
   int R = (int)R64;
   int d = h->d;
   double *q = (double *)malloc(sizeof(double) * ((size_t)h->ny * R + 1));
@@ -1217,10 +1283,12 @@ int oracle_matvec(void *hv, const double *Q, int64_t R64, double *Z) {
       int j = h->Lj[a];
       const side_t *sj = &h->col[j];
       for (int t = 0; t < si->k; t++) {
-        const double *xp = h->X + (size_t)si->grid[si->sel[t]] * d;
+        const int xi = si->grid[si->sel[t]];
+        const double *xp = h->X + (size_t)xi * d;
         for (int u = 0; u < sj->k; u++) {
-          const double *yp = h->Y + (size_t)sj->grid[sj->sel[u]] * d;
-          double b = kernel_value(h->kid, xp, yp, d, h->diag);
+          const int yi = sj->grid[sj->sel[u]];
+          const double *yp = h->Y + (size_t)yi * d;
+          double b = kernel_value(h->kid, xp, yp, d, h->diag, pd_at(h->AX, xi), pd_at(h->AX, yi));
           for (int r = 0; r < R; r++) zh[i][(size_t)t * R + r] += b * qh[j][(size_t)u * R + r];
         }
       }
@@ -1254,7 +1322,8 @@ int oracle_matvec(void *hv, const double *Q, int64_t R64, double *Z) {
       for (int u = h->xb[i]; u < h->xe[i]; u++) {
         const double *xp = h->X + (size_t)u * d;
         for (int v = h->yb[j]; v < h->ye[j]; v++) {
-          double b = kernel_value(h->kid, xp, h->Y + (size_t)v * d, d, h->diag);
+          double b = kernel_value(h->kid, xp, h->Y + (size_t)v * d, d, h->diag, pd_at(h->AX, u),
+                                  pd_at(h->AX, v));
           for (int r = 0; r < R; r++) z[(size_t)u * R + r] += b * q[(size_t)v * R + r];
         }
       }
@@ -1290,6 +1359,8 @@ int oracle_export(void *hv, int what, void *buf, int64_t *count) {
   int *ib = (int *)buf;
   double *db = (double *)buf;
   int nn = h->nnodes;
+  if (!h->row && what >= EX_RANKS && what != EX_SIZES && what != EX_LEVELS)
+    return OR_EUNSUP; /* generators of a tree-only build */
   switch (what) {
     case EX_SIZES: /* int32: nx, ny, nnodes, nlevels, nL, nLm, d, adm */
       n = 8;
@@ -1422,14 +1493,16 @@ int oracle_export(void *hv, int what, void *buf, int64_t *count) {
 /* Exact references and single-step entry points for the pins.        */
 /* ------------------------------------------------------------------ */
 /* Z = A Q with A = [kappa(x, y)] (x in X, y in Y), original order. */
+/* ax, ay: per-point data (n x 3, kernel 4) of X and Y, else NULL.      */
 void oracle_dense_matvec(const double *x, int64_t nx, const double *y, int64_t ny, int d,
-                         int kid, double diag, const double *Q, int64_t R, double *Z) {
+                         int kid, double diag, const double *ax, const double *ay,
+                         const double *Q, int64_t R, double *Z) {
 #pragma omp parallel for schedule(static)
   for (int64_t a = 0; a < nx; a++) {
     double *za = Z + a * R;
     for (int64_t r = 0; r < R; r++) za[r] = 0.0;
     for (int64_t b = 0; b < ny; b++) {
-      double v = kernel_value(kid, x + a * d, y + b * d, d, diag);
+      double v = kernel_value(kid, x + a * d, y + b * d, d, diag, pd_at(ax, a), pd_at(ay, b));
       for (int64_t r = 0; r < R; r++) za[r] += v * Q[b * R + r];
     }
   }
@@ -1437,8 +1510,9 @@ void oracle_dense_matvec(const double *x, int64_t nx, const double *y, int64_t n
 
 /* rows[0..nrows) of A Q (exact), for sampled checks at large n. */
 void oracle_dense_rows(const double *x, int64_t nx, const double *y, int64_t ny, int d,
-                       int kid, double diag, const int64_t *rows, int64_t nrows,
-                       const double *Q, int64_t R, double *Z) {
+                       int kid, double diag, const double *ax, const double *ay,
+                       const int64_t *rows, int64_t nrows, const double *Q, int64_t R,
+                       double *Z) {
   (void)nx;
 #pragma omp parallel for schedule(static)
   for (int64_t s = 0; s < nrows; s++) {
@@ -1446,7 +1520,7 @@ void oracle_dense_rows(const double *x, int64_t nx, const double *y, int64_t ny,
     double *za = Z + s * R;
     for (int64_t r = 0; r < R; r++) za[r] = 0.0;
     for (int64_t b = 0; b < ny; b++) {
-      double v = kernel_value(kid, xa, y + b * d, d, diag);
+      double v = kernel_value(kid, xa, y + b * d, d, diag, pd_at(ax, rows[s]), pd_at(ay, b));
       for (int64_t r = 0; r < R; r++) za[r] += v * Q[b * R + r];
     }
   }
@@ -1454,10 +1528,11 @@ void oracle_dense_rows(const double *x, int64_t nx, const double *y, int64_t ny,
 
 /* kernel block K(P[ri], Q[cj]) for given row/column points (n x d each). */
 void oracle_kernel_block(const double *P, const double *Qp, int64_t nr, int64_t nc, int d,
-                         int kid, double diag, double *B) {
+                         int kid, double diag, const double *aP, const double *aQ, double *B) {
   for (int64_t a = 0; a < nr; a++)
     for (int64_t b = 0; b < nc; b++)
-      B[a * nc + b] = kernel_value(kid, P + a * d, Qp + b * d, d, diag);
+      B[a * nc + b] = kernel_value(kid, P + a * d, Qp + b * d, d, diag, pd_at(aP, a),
+                                   pd_at(aQ, b));
 }
 
 int oracle_compr(const double *C, int m, int c, double tol, double f, int *k, int *sel,

@@ -15,7 +15,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsmash.so")
 
-KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3}
+KERNELS = {"inv_r": 0, "log_r": 1, "exp_r": 2, "cauchy": 3, "double_layer": 4}
 ADM = {"weak": 0, "hss": 0, "strong": 1, "h2": 1}
 PREC = {"f64": 0, "f32": 1, "bf16": 2}
 
@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32),
                 ("mv_xcd_run", C.c_int32), ("coupling_mode", C.c_int32),
                 ("coupling_chunk", C.c_int64), ("alloc", C.c_void_p), ("free", C.c_void_p),
-                ("alloc_ctx", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("point_data", C.c_void_p)]
 
 # smash_alloc_fn / smash_free_fn
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -223,7 +223,7 @@ class Smash:
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
                  root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
                  mv_xcd_run=None, graphs=True, tuned=True, nrhs_hint=16, coupling="auto",
-                 coupling_chunk=0, allocator=None, stream=None):
+                 coupling_chunk=0, allocator=None, stream=None, point_data=None):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -278,10 +278,16 @@ class Smash:
             self._hooks = torch_allocator_hooks() if allocator == "torch" else tuple(allocator)
             opt.alloc = C.cast(self._hooks[0], C.c_void_p)
             opt.free = C.cast(self._hooks[1], C.c_void_p)
+        if point_data is not None:  # the double-layer kernel's per-point data, n x 3
+            if not (isinstance(point_data, torch.Tensor) and point_data.is_cuda
+                    and point_data.dtype == torch.float64):
+                raise TypeError("point_data must be a CUDA float64 tensor")
+            point_data = point_data.contiguous()
+            opt.point_data = point_data.data_ptr()
         self.apply_prec = apply_prec
         self.nx = x.shape[0]
         self.ny = x.shape[0] if y is None else y.shape[0]
-        self._keep = (x, y)
+        self._keep = (x, y, point_data)
         h = C.c_void_p()
         kid = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         a = ADM[adm] if isinstance(adm, str) else int(adm)

@@ -44,6 +44,7 @@ struct EvalArgs {
   const double *Xp, *Yp;
   int d, kid;
   double diag;
+  const double *pd;  // double-layer kernel: per-point data by point id (X = Y)
 };
 
 // Coordinates of a block's rows and columns are staged in LDS (up to
@@ -76,7 +77,8 @@ __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
     T *B = out + A.off[e];
     const int tot = nr * nc;
     if (tot == 0) continue;
-    const bool staged = nr <= EV_STAGE && nc <= EV_STAGE;
+    // (the double-layer kernel also needs each point's data: not staged)
+    const bool staged = KID != SMASH_KERNEL_DOUBLE_LAYER && nr <= EV_STAGE && nc <= EV_STAGE;
     __syncthreads();  // the previous pair's readers are done with xs / ys
     if (staged) {
       for (int q = threadIdx.x; q < nr * d; q += blockDim.x) {
@@ -95,7 +97,7 @@ __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
     const int st = blockDim.x, sb = st / nr, sa = st - sb * nr;
     int b = threadIdx.x / nr, a = threadIdx.x - b * nr;
     for (int q = threadIdx.x; q < tot; q += st) {
-      const double *xp, *yp;
+      const double *xp, *yp, *ax = nullptr, *ay = nullptr;
       if (staged) {
         xp = xs + a * d;
         yp = ys + b * d;
@@ -104,11 +106,15 @@ __global__ void __launch_bounds__(256) k_eval_blocks(EvalArgs A, T *out) {
         const int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
         xp = A.Xp + xr * d;
         yp = A.Yp + yc * d;
+        if (KID == SMASH_KERNEL_DOUBLE_LAYER) {
+          ax = A.pd + 3 * xr;
+          ay = A.pd + 3 * yc;
+        }
       }
       if (F32MATH)
-        B[q] = (T)kernel_f32_t<KID, D>(xp, yp, (float)A.diag);
+        B[q] = (T)kernel_f32_t<KID, D>(xp, yp, (float)A.diag, ax, ay);
       else
-        B[q] = (T)kernel_f64_t<KID, D>(xp, yp, A.diag);
+        B[q] = (T)kernel_f64_t<KID, D>(xp, yp, A.diag, ax, ay);
       a += sa;
       b += sb;
       if (a >= nr) {
@@ -151,8 +157,9 @@ __global__ void __launch_bounds__(256) k_eval_blocks_bf16(EvalArgs A, unsigned s
         int64_t xr = A.rid ? A.rid[r0 + a] : r0 + a;
         int64_t yc = A.cid ? A.cid[c0 + b] : c0 + b;
         const double *xp = A.Xp + xr * A.d, *yp = A.Yp + yc * A.d;
-        v = F32MATH ? kernel_f32(A.kid, xp, yp, A.d, (float)A.diag)
-                    : (float)kernel_f64(A.kid, xp, yp, A.d, A.diag);
+        const double *ax = A.pd ? A.pd + 3 * xr : nullptr, *ay = A.pd ? A.pd + 3 * yc : nullptr;
+        v = F32MATH ? kernel_f32(A.kid, xp, yp, A.d, (float)A.diag, ax, ay)
+                    : (float)kernel_f64(A.kid, xp, yp, A.d, A.diag, ax, ay);
       }
       B[q] = bf16_bits(v);
     }
@@ -184,6 +191,9 @@ static void eval_launch_m(int nblk, EvalArgs &ea, T *out, hipStream_t s) {
     case SMASH_KERNEL_INV_R: eval_launch_k<T, F32MATH, SMASH_KERNEL_INV_R>(nblk, ea, out, s); break;
     case SMASH_KERNEL_LOG_R: eval_launch_k<T, F32MATH, SMASH_KERNEL_LOG_R>(nblk, ea, out, s); break;
     case SMASH_KERNEL_EXP_R: eval_launch_k<T, F32MATH, SMASH_KERNEL_EXP_R>(nblk, ea, out, s); break;
+    case SMASH_KERNEL_DOUBLE_LAYER:  // dim 2 only
+      k_eval_blocks<T, F32MATH, SMASH_KERNEL_DOUBLE_LAYER, 2><<<nblk, 256, 0, s>>>(ea, out);
+      break;
     default: eval_launch_k<T, F32MATH, SMASH_KERNEL_CAUCHY>(nblk, ea, out, s); break;
   }
 }
@@ -219,6 +229,7 @@ static EvalArgs coupling_args(Handle &h, int64_t p0, int64_t p1) {
   ea.cbeg = C.hbeg;
   ea.ccnt_k = C.k;
   ea.cid = C.slot_id;
+  ea.pd = h.Ap;
   return ea;
 }
 
@@ -349,6 +360,7 @@ void near_launch(Handle &h, int64_t n_entries) {
   en.rend32 = h.xe;
   en.cbeg32 = h.yb;
   en.cend32 = h.ye;
+  en.pd = h.Ap;
   {
     PhaseTimer pt(h, SMASH_PHASE_BLOCKS, h.side);
     if (h.apply_prec == SMASH_F64)

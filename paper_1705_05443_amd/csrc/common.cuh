@@ -131,8 +131,29 @@ __device__ __forceinline__ double inv_sqrt_pos(double x) {
   return y;
 }
 
+// Laplace double layer (Sec. 6.4, eq. (6.9)) in Nystrom form, dim 2:
+// grad_y Phi(x, y) . m_y with Phi = -log|x - y| / (2 pi), i.e.
+// -((y - x) . m_y) / (2 pi |x - y|^2); ay = the column point's data
+// (m_1, m_2, .), ax = the row point's (., ., diagonal value).
+__device__ __forceinline__ double double_layer_f64(const double *x, const double *y, double r2,
+                                                   bool same, const double *ax,
+                                                   const double *ay) {
+  if (same) return ax[2];
+  const double proj = (y[0] - x[0]) * ay[0] + (y[1] - x[1]) * ay[1];
+  return -proj / (2.0 * M_PI * r2);
+}
+__device__ __forceinline__ float double_layer_f32(const double *x, const double *y, float r2,
+                                                  bool same, const double *ax,
+                                                  const double *ay) {
+  if (same) return (float)ax[2];
+  const float proj = (float)(y[0] - x[0]) * (float)ay[0] + (float)(y[1] - x[1]) * (float)ay[1];
+  return -proj / ((float)(2.0 * M_PI) * r2);
+}
+
+// ax, ay: the row and column points' data (the double-layer kernel only)
 __device__ inline double kernel_f64(int kid, const double *x, const double *y, int d,
-                                    double diag) {
+                                    double diag, const double *ax = nullptr,
+                                    const double *ay = nullptr) {
   double r2 = 0.0;
   bool same = true;
   for (int t = 0; t < d; t++) {
@@ -141,6 +162,7 @@ __device__ inline double kernel_f64(int kid, const double *x, const double *y, i
     r2 += df * df;
   }
   if (kid == SMASH_KERNEL_EXP_R) return exp(-sqrt(r2));
+  if (kid == SMASH_KERNEL_DOUBLE_LAYER) return double_layer_f64(x, y, r2, same, ax, ay);
   if (same) return diag;
   if (kid == SMASH_KERNEL_INV_R) return inv_sqrt_pos(r2);
   if (kid == SMASH_KERNEL_LOG_R) return 0.5 * log_pos(r2);
@@ -150,7 +172,8 @@ __device__ inline double kernel_f64(int kid, const double *x, const double *y, i
 // FP32 evaluation: coordinate differences are formed in FP64 (points may be
 // closer than FP32 resolution), the rest in FP32.
 __device__ inline float kernel_f32(int kid, const double *x, const double *y, int d,
-                                   float diag) {
+                                   float diag, const double *ax = nullptr,
+                                   const double *ay = nullptr) {
   float r2 = 0.0f;
   bool same = true;
   float dx0 = 0.0f;
@@ -162,6 +185,7 @@ __device__ inline float kernel_f32(int kid, const double *x, const double *y, in
     r2 += f * f;
   }
   if (kid == SMASH_KERNEL_EXP_R) return __expf(-sqrtf(r2));
+  if (kid == SMASH_KERNEL_DOUBLE_LAYER) return double_layer_f32(x, y, r2, same, ax, ay);
   if (same) return diag;
   if (kid == SMASH_KERNEL_INV_R) return rsqrtf(r2);
   if (kid == SMASH_KERNEL_LOG_R) return 0.5f * __logf(r2);
@@ -172,7 +196,9 @@ __device__ inline float kernel_f32(int kid, const double *x, const double *y, in
 // compile time (identical operations in the same order, so identical
 // results); the block evaluation instantiates them per kernel and dim.
 template <int KID, int D>
-__device__ __forceinline__ double kernel_f64_t(const double *x, const double *y, double diag) {
+__device__ __forceinline__ double kernel_f64_t(const double *x, const double *y, double diag,
+                                               const double *ax = nullptr,
+                                               const double *ay = nullptr) {
   double r2 = 0.0;
   bool same = true;
 #pragma unroll
@@ -182,6 +208,7 @@ __device__ __forceinline__ double kernel_f64_t(const double *x, const double *y,
     r2 += df * df;
   }
   if (KID == SMASH_KERNEL_EXP_R) return exp(-sqrt(r2));
+  if (KID == SMASH_KERNEL_DOUBLE_LAYER) return double_layer_f64(x, y, r2, same, ax, ay);
   if (same) return diag;
   if (KID == SMASH_KERNEL_INV_R) return inv_sqrt_pos(r2);
   if (KID == SMASH_KERNEL_LOG_R) return 0.5 * log_pos(r2);
@@ -189,7 +216,9 @@ __device__ __forceinline__ double kernel_f64_t(const double *x, const double *y,
 }
 
 template <int KID, int D>
-__device__ __forceinline__ float kernel_f32_t(const double *x, const double *y, float diag) {
+__device__ __forceinline__ float kernel_f32_t(const double *x, const double *y, float diag,
+                                              const double *ax = nullptr,
+                                              const double *ay = nullptr) {
   float r2 = 0.0f;
   bool same = true;
   float dx0 = 0.0f;
@@ -202,6 +231,7 @@ __device__ __forceinline__ float kernel_f32_t(const double *x, const double *y, 
     r2 += f * f;
   }
   if (KID == SMASH_KERNEL_EXP_R) return __expf(-sqrtf(r2));
+  if (KID == SMASH_KERNEL_DOUBLE_LAYER) return double_layer_f32(x, y, r2, same, ax, ay);
   if (same) return diag;
   if (KID == SMASH_KERNEL_INV_R) return rsqrtf(r2);
   if (KID == SMASH_KERNEL_LOG_R) return 0.5f * __logf(r2);

@@ -51,6 +51,11 @@ struct IdArgs {
   // k_compr_w: with `order`, the nodes order[*ord_lo .. ne - nb) (the rest
   // of a level whose largest grids went to the wide form); else nb .. ne-1
   const int *order, *ord_lo;
+  // the column side of the double-layer kernel: basis rows r < c0 are the
+  // Lagrange values of row r mod pd times the point's m_1 (r < pd) or m_2
+  // (c0 = 2 pd); pd is p^d and pdat the per-point data by point id
+  int dlw, pd;
+  const double *pdat;
 };
 
 // ---- lane exchanges (DPP) ------------------------------------------------
@@ -352,6 +357,8 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
                 val = Fl[(p + k2) * NC + a] * Fl[k1 * NC + a];
               else
                 val = Fl[(2 * p + k2) * NC + a] * Fl[(p + k1) * NC + a] * Fl[k0 * NC + a];
+              if (A.dlw)
+                val = val * A.pdat[3 * (int64_t)A.slot_id[A.gbeg[i] + a] + (r < A.pd ? 0 : 1)];
             } else if (r < c) {
               val = Sa[r - A.c0];
             }
@@ -820,6 +827,8 @@ __device__ __forceinline__ void compr_node_s(const IdArgs &A, const CsArgs &B, i
                 val *= F[t * p + q % p];
                 q /= p;
               }
+              if (A.dlw)
+                val = val * A.pdat[3 * (int64_t)A.slot_id[A.gbeg[i] + a] + (r < A.pd ? 0 : 1)];
             } else {
               val = Sa[r - A.c0];
             }
@@ -1272,6 +1281,7 @@ struct SvdArgs {
   double *S;  // output
   const int64_t *S_off;
   int *ks_out;
+  const double *pd;  // double-layer kernel: per-point data by point id (X = Y)
 };
 
 // NCL / VCL > 0: a pair's two rows (nc <= 8 NCL entries) and two V columns
@@ -1313,10 +1323,13 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int ldl, int voff
           int b = e / mp, r = e % mp;
           double val = 0.0;
           if (r < m) {
-            const double *pme = A.P_me + (int64_t)A.slot_me[A.gbeg_me[i] + r] * A.d;
-            const double *pot = A.P_ot + (int64_t)A.slot_ot[gj + b] * A.d;
-            val = A.rowside ? kernel_f64(A.kid, pme, pot, A.d, A.diag)
-                            : kernel_f64(A.kid, pot, pme, A.d, A.diag);
+            const int64_t ime = A.slot_me[A.gbeg_me[i] + r], iot = A.slot_ot[gj + b];
+            const double *pme = A.P_me + ime * A.d;
+            const double *pot = A.P_ot + iot * A.d;
+            const double *dme = A.pd ? A.pd + 3 * ime : nullptr;
+            const double *dot = A.pd ? A.pd + 3 * iot : nullptr;
+            val = A.rowside ? kernel_f64(A.kid, pme, pot, A.d, A.diag, dme, dot)
+                            : kernel_f64(A.kid, pot, pme, A.d, A.diag, dot, dme);
           }
           Am[(int64_t)r * ldn + o + b] = val;
         }
@@ -1742,6 +1755,7 @@ struct SideCtx {
   double *Svec = nullptr;
   int64_t *S_off = nullptr;
   bool gt_first = false;  // compr wrote G^T (the register kernel)
+  int c0 = 0;             // basis width p^d, or 2 p^d (double-layer column side)
 };
 
 void build_generators(Handle &h) {
@@ -1750,13 +1764,15 @@ void build_generators(Handle &h) {
   tmp.stream = s;
   keep.stream = s;
   try {
-    const int c0 = [&] {
+    const int pd = [&] {
       int c = 1;
       for (int t = 0; t < h.d; t++) c *= h.p;
       return c;
     }();
+    const bool dl = h.kid == SMASH_KERNEL_DOUBLE_LAYER;
     if (h.p > ID_PMAX) throw Error{SMASH_E_INVALID_ARG, "interpolation order above 64"};
-    if (c0 > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width p^d above 512"};
+    if ((dl ? 2 * pd : pd) > ID_CMAX)
+      throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
     const bool hss = h.adm == SMASH_ADM_WEAK;
     alloc_side(h, h.row);
     h.col = h.reuse ? &h.row : &h.col_own;
@@ -1764,6 +1780,8 @@ void build_generators(Handle &h) {
     std::vector<SideCtx> sides;
     sides.push_back(SideCtx{&h.row, true, h.xb, h.xe, h.Xp, h.nx});
     if (!h.reuse) sides.push_back(SideCtx{&h.col_own, false, h.yb, h.ye, h.Yp, h.ny});
+    // the double layer's column basis: each Lagrange column times m_1 and m_2
+    for (auto &sc : sides) sc.c0 = (dl && !sc.rowside) ? 2 * pd : pd;
     int nn = h.nnodes;
     // slot capacity for every level at once: a level's grids are disjoint
     // sets of points, so it adds at most min(n, nodes * c) skeleton slots
@@ -1773,7 +1791,7 @@ void build_generators(Handle &h) {
       int64_t bound = sc.n + 1024;
       for (int l = 2; l <= h.nlevels; l++) {
         const int64_t nl = h.level_beg[l] - h.level_beg[l - 1];
-        bound += hss ? sc.n : std::min<int64_t>(sc.n, nl * c0);
+        bound += hss ? sc.n : std::min<int64_t>(sc.n, nl * sc.c0);
       }
       grow_slots(h, S, bound);
       k_iota<<<ceil_div(sc.n, 256), 256, 0, s>>>(S.slot_id, sc.n);
@@ -1803,7 +1821,7 @@ void build_generators(Handle &h) {
         Side &S = *sc.S;
         sc.cm = tmp.alloc_n<int64_t>(nl);
         sc.cg = tmp.alloc_n<int64_t>(nl);
-        PrepArgs pa{nb, ne, h.nchild, h.first_child, sc.xb, sc.xe, S.m, S.gbeg, S.k, S.hbeg, c0,
+        PrepArgs pa{nb, ne, h.nchild, h.first_child, sc.xb, sc.xe, S.m, S.gbeg, S.k, S.hbeg, sc.c0,
                     hss ? 1 : 0, sc.cm, sc.cg, dmax};
         const int64_t *tot_m, *tot_g;
         if (nl <= LV_NT * LV_PER) {
@@ -1866,7 +1884,7 @@ void build_generators(Handle &h) {
           double *scr = tmp.alloc_n<double>((size_t)wg_stride * nwg);
           SvdArgs sa{nb, ne, S.m, S.gbeg, S.slot_id, sc.P, O.m, O.gbeg, O.slot_id, ot.P, h.Nrow,
                      h.Ncol, sc.rowside ? 1 : 0, h.kid, h.d, h.diag, h.eps_svd, scr, ldn,
-                     wg_stride, sc.Svec, soff, S.ks};
+                     wg_stride, sc.Svec, soff, S.ks, h.Ap};
           PhaseTimer pt(h, SMASH_PHASE_NEAR_SVD, s);
           // register-staged rotations when a pair's rows and V columns fit
           const int ncl = ncmax <= 64 ? 8 : ncmax <= 128 ? 16 : ncmax <= 256 ? 32 : 0;
@@ -1912,7 +1930,7 @@ void build_generators(Handle &h) {
       for (auto &sc : sides) {
         Side &S = *sc.S;
         LevelSide &L = S.lv[l];
-        const int cmax = c0 + (hss ? sc.mmax : 0);
+        const int cmax = sc.c0 + (hss ? sc.mmax : 0);
         if (cmax > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
         // The register form (k_compr_w: the grid in registers, two lanes per
         // grid point) takes grids of up to 256 points when c <= 64; larger
@@ -1944,9 +1962,12 @@ void build_generators(Handle &h) {
           lds_cols = (int)std::min<size_t>(((size_t)dev_lds - st_lds - fixed) / per_col,
                                            (size_t)sc.mmax);
         const size_t shs = fixed + per_col * (size_t)lds_cols;
-        IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo, S.go,
-                  L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
+        IdArgs ia{nb, ne, h.lo, h.hi, h.d, h.p, sc.c0, S.m, S.gbeg, S.slot_id, sc.P, S.selo,
+                  S.go, L.sel, L.G, S.k, hss ? sc.Svec : nullptr, hss ? sc.S_off : nullptr, S.ks,
                   h.tol, h.f, dsw, dsw + 1, 0};
+        ia.dlw = (dl && !sc.rowside) ? 1 : 0;
+        ia.pd = pd;
+        ia.pdat = h.Ap;
         IdArgs ir = ia;  // the register form writes G^T, and G
         ir.gt_out = 1;
         ir.G_out = L.Gt;

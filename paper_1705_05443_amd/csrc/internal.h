@@ -179,6 +179,10 @@ struct Handle {
   DeviceArena mem;
   // permuted points
   double *Xp = nullptr, *Yp = nullptr;
+  // double-layer kernel: per-point data (m_1, m_2, diagonal), n x 3, as
+  // given (pdata_in, borrowed) and permuted with the points (Ap)
+  const double *pdata_in = nullptr;
+  double *Ap = nullptr;
   int *perm_x = nullptr, *perm_y = nullptr;
   // geometry
   bool has_root = false;

@@ -101,9 +101,19 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
   if (dim < 1 || dim > 3) return fail(SMASH_E_INVALID_ARG, "dim must be 1, 2 or 3");
   if (nx < 1 || ny < 1 || nx > INT32_MAX / 2 || ny > INT32_MAX / 2)
     return fail(SMASH_E_INVALID_ARG, "point count out of range");
-  if (kid < 0 || kid > 3) return fail(SMASH_E_INVALID_ARG, "unknown kernel id");
+  if (kid < 0 || kid > 4) return fail(SMASH_E_INVALID_ARG, "unknown kernel id");
   if (kid == SMASH_KERNEL_CAUCHY && dim != 1)
     return fail(SMASH_E_UNSUPPORTED, "the 1/(x-y) kernel needs dim == 1");
+  if (kid == SMASH_KERNEL_DOUBLE_LAYER) {
+    if (dim != 2 || !same)
+      return fail(SMASH_E_UNSUPPORTED, "the double-layer kernel needs dim == 2 and X = Y");
+    if (!opt.point_data)
+      return fail(SMASH_E_INVALID_ARG, "the double-layer kernel needs options.point_data");
+    if (opt.coupling_mode == SMASH_COUPLING_EVALUATED)
+      return fail(SMASH_E_UNSUPPORTED, "the double-layer kernel stores its coupling blocks");
+  } else if (opt.point_data) {
+    return fail(SMASH_E_INVALID_ARG, "options.point_data is for the double-layer kernel only");
+  }
   if (leaf < 1) return fail(SMASH_E_INVALID_ARG, "leaf_size must be >= 1");
   if (p < 1 || p > 64) return fail(SMASH_E_INVALID_ARG, "interp_order must be in [1, 64]");
   if (adm != SMASH_ADM_WEAK && adm != SMASH_ADM_STRONG)
@@ -163,7 +173,8 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->nx = nx;
     h->ny = ny;
     h->same_xy = same;
-    h->reuse = same && kid != SMASH_KERNEL_CAUCHY;
+    h->reuse = same && kid != SMASH_KERNEL_CAUCHY && kid != SMASH_KERNEL_DOUBLE_LAYER;
+    h->pdata_in = opt.point_data;
     h->bpl = adm == SMASH_ADM_WEAK ? 1 : dim;
     h->max_split = 63 / h->bpl;
     if (opt.max_depth > 0 && opt.max_depth - 1 < h->max_split) h->max_split = opt.max_depth - 1;

@@ -470,6 +470,11 @@ void build_tree(Handle &h, const double *x, const double *y) {
     h.Xp = h.mem.alloc_n<double>((size_t)h.nx * h.d);
     k_gather_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(x, px, h.nx, h.d, h.Xp);
     SMASH_CHECK_LAUNCH();
+    if (h.pdata_in) {  // per-point data, permuted with the points
+      h.Ap = h.mem.alloc_n<double>((size_t)h.nx * 3);
+      k_gather_points<<<ceil_div(h.nx, 256), 256, 0, s>>>(h.pdata_in, px, h.nx, 3, h.Ap);
+      SMASH_CHECK_LAUNCH();
+    }
     if (h.same_xy) {
       h.perm_y = h.perm_x;
       h.Yp = h.Xp;

@@ -47,6 +47,46 @@ def chebyshev_pair(n: int, seed: int = 0, shift: float = 1e-3, shift_x: bool = F
     return roots[:, None].copy(), moved[:, None].copy()
 
 
+def curve(name: str, n: int):
+    """Nystrom data of the Laplace double-layer operator on a closed curve
+    r(t), t in [0, 1), with the trapezoidal rule at t_k = k/n (weight 1/n):
+    the ram head r(t) = (2 cos 2 pi t, 1 + sin 2 pi t - 1.4 cos^4 4 pi t)
+    or the sunflower r(t) = rho(t) (cos 2 pi t, sin 2 pi t),
+    rho = 1.3 + 1.25 cos 40 pi t (both counterclockwise).
+    Returns points (n, 2) = r(t_k) and data (n, 3): the weighted normal
+    m_k = (r2'(t_k), -r1'(t_k)) / n and the diagonal entry of the
+    discretised operator K - I/2 at t_k, (1/n) (r1'' r2' - r2'' r1') /
+    (4 pi |r'|^2) - 1/2 (the limit of the kernel at s = t, minus 1/2).
+    These are the inputs of the problem, computed from the closed-form
+    derivatives of the curve."""
+    t = np.arange(n, dtype=np.float64) / n
+    tp = 2.0 * np.pi
+    if name == "ram_head":
+        a, b = tp * t, 2.0 * tp * t
+        r1, r2 = 2.0 * np.cos(a), 1.0 + np.sin(a) - 1.4 * np.cos(b) ** 4
+        d1 = -2.0 * tp * np.sin(a)
+        d2 = tp * np.cos(a) + 1.4 * 4.0 * np.cos(b) ** 3 * np.sin(b) * 2.0 * tp
+        e1 = -2.0 * tp * tp * np.cos(a)
+        e2 = (-tp * tp * np.sin(a)
+              + 1.4 * 4.0 * (2.0 * tp) ** 2 * (np.cos(b) ** 4 - 3.0 * np.cos(b) ** 2 * np.sin(b) ** 2))
+    elif name == "sunflower":
+        th, ph = tp * t, 20.0 * tp * t
+        rho, rp, rpp = 1.3 + 1.25 * np.cos(ph), -1.25 * 20.0 * tp * np.sin(ph), \
+            -1.25 * (20.0 * tp) ** 2 * np.cos(ph)
+        c, s_ = np.cos(th), np.sin(th)
+        r1, r2 = rho * c, rho * s_
+        d1, d2 = rp * c - tp * rho * s_, rp * s_ + tp * rho * c
+        e1 = rpp * c - 2.0 * tp * rp * s_ - tp * tp * rho * c
+        e2 = rpp * s_ + 2.0 * tp * rp * c - tp * tp * rho * s_
+    else:
+        raise ValueError(name)
+    pts = np.stack([r1, r2], axis=1)
+    sp2 = d1 * d1 + d2 * d2
+    data = np.stack([d2 / n, -d1 / n,
+                     (e1 * d2 - e2 * d1) / (4.0 * np.pi * sp2) / n - 0.5], axis=1)
+    return np.ascontiguousarray(pts), np.ascontiguousarray(data)
+
+
 def rhs(n: int, nrhs: int, seed: int = 0) -> np.ndarray:
     """Right-hand sides N(0,1), (n, nrhs) row-major, drawn from seed + 100."""
     return np.random.default_rng(seed + 100).standard_normal((n, nrhs))
@@ -71,6 +111,14 @@ CONFIGS = {
                                        leaf=128, order=6, tol=1e-7, tau=0.7, nrhs=64,
                                        root=((0.0, 0.0, 0.0), 1.0), apply="f64",
                                        coupling="evaluated"),
+    # Laplace double layer (Sec. 6.4): HSS on the curve points, 5 x 5
+    # interpolation points, tau 0.6, eps_svd 1e-11, leaf 50
+    "hss_dl_ram_head_10240": dict(kind="curve", curve="ram_head", n=10240, d=2,
+                                  kernel="double_layer", adm=0, leaf=50, order=5, tol=1e-10,
+                                  eps_svd=1e-11, tau=0.6, nrhs=1, root=None, apply="f64"),
+    "hss_dl_sunflower_10240": dict(kind="curve", curve="sunflower", n=10240, d=2,
+                                   kernel="double_layer", adm=0, leaf=50, order=5, tol=1e-10,
+                                   eps_svd=1e-11, tau=0.6, nrhs=1, root=None, apply="f64"),
     "hss1d_cauchy_1m": dict(kind="chebyshev_pair", n=1 << 20, d=1, kernel="cauchy", adm=0,
                             leaf=64, order=16, tol=1e-8, eps_svd=1e-9, tau=0.6, nrhs=256,
                             root=None, apply="f32"),
@@ -86,4 +134,6 @@ def points(cfg: dict, seed: int = 0, n: int | None = None):
         return clusters(n, cfg["d"], seed), None
     if cfg["kind"] == "chebyshev_pair":
         return chebyshev_pair(n, seed)
+    if cfg["kind"] == "curve":  # the curve's points; its data from curve()
+        return curve(cfg["curve"], n)[0], None
     raise ValueError(cfg["kind"])

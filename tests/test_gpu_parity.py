@@ -53,13 +53,30 @@ CASES = {
     "hss_cauchy_xy": (lambda: W.chebyshev_pair(3000, 4),
                       dict(kernel="cauchy", leaf=64, order=16, adm="weak", tol=1e-8,
                            eps_svd=1e-9, tau=0.6)),
+    # Laplace double layer on the curves of Sec. 6.4 (Nystrom data as point data)
+    "hss_dl_ram_head": (lambda: (W.curve("ram_head", 1280)[0], None),
+                        dict(kernel="double_layer", leaf=50, order=5, adm="weak", tol=1e-10,
+                             eps_svd=1e-11, tau=0.6,
+                             point_data=W.curve("ram_head", 1280)[1])),
+    "hss_dl_sunflower": (lambda: (W.curve("sunflower", 640)[0], None),
+                         dict(kernel="double_layer", leaf=50, order=5, adm="weak", tol=1e-10,
+                              eps_svd=1e-11, tau=0.6,
+                              point_data=W.curve("sunflower", 640)[1])),
 }
+DL = {k for k, v in CASES.items() if v[1]["kernel"] == "double_layer"}
 
 
 def _oracle_kwargs(kw):
     ok = dict(kw)
     ok["adm"] = api.ADM[kw["adm"]]
     return ok
+
+
+def _gpu_kwargs(kw):
+    gk = dict(kw)
+    if gk.get("point_data") is not None:
+        gk["point_data"] = dev(gk["point_data"])
+    return gk
 
 
 _cache = {}
@@ -70,7 +87,7 @@ def pair_for(name):
         mk, kw = CASES[name]
         x, y = mk()
         o = O.Oracle(x, y, **_oracle_kwargs(kw))
-        g = api.Smash(dev(x), None if y is None else dev(y), **kw)
+        g = api.Smash(dev(x), None if y is None else dev(y), **_gpu_kwargs(kw))
         _cache[name] = (x, y, o, g)
     return _cache[name]
 
@@ -205,7 +222,7 @@ def test_ranks_skeletons_and_G(name):
     print("case", name, flush=True)
     ro, rg = o.ranks(), g.export("ranks").reshape(-1, 6)
     sides = [("row", 0, O.EX_ROW_SEL, O.EX_ROW_G, O.EX_ROW_GRID)]
-    if not (y is None and CASES[name][1]["kernel"] != "cauchy"):
+    if not (y is None and CASES[name][1]["kernel"] not in ("cauchy", "double_layer")):
         sides.append(("col", 2, O.EX_COL_SEL, O.EX_COL_G, O.EX_COL_GRID))
     weak = CASES[name][1]["adm"] == "weak"
     for side, c, exs, exg, exgrid in sides:
@@ -230,7 +247,8 @@ def test_ranks_skeletons_and_G(name):
             _check_h2_G(x, y, g, side, m_g, k_g, Go, Gg, CASES[name][1]["order"])
         else:
             _check_hss_ids(x, y, g, side, m_g, k_g, g.export(side + "_sel"), Go, Gg,
-                           CASES[name][1]["order"], keep)
+                           CASES[name][1]["order"], keep,
+                           CASES[name][1].get("point_data") if side == "col" else None)
 
 
 # H^2 G = (R11^-1 R12)^T against the oracle's, per node relative to
@@ -267,7 +285,7 @@ def _check_h2_G(x, y, g, side, m, k, Go, Gg, order):
           "; nodes above 1e-10 (node, diff, cond(C_S)):", wide, flush=True)
 
 
-def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep):
+def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep, pdata=None):
     """HSS: C = [U-hat, S] contains near-field singular vectors whose trailing
     members (sigma near eps_svd * sigma_1) are fixed only to about
     eps_mach / eps_svd, so two correct implementations agree on the skeleton
@@ -288,7 +306,11 @@ def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep):
         node = i + 1
         assert np.max(np.abs(Gg[i])) <= 2.0 * (1 + 1e-8)
         pts = P[perm[grid[i]]]
-        U = O.interp_basis(pts, bx[node, :1], bx[node, 3:4], order)
+        dd = P.shape[1]
+        U = O.interp_basis(pts, bx[node, :dd], bx[node, 3:3 + dd], order)
+        if pdata is not None:  # double-layer column side: [m_1 U-hat, m_2 U-hat]
+            md = pdata[perm[grid[i]]]
+            U = np.concatenate([U * md[:, :1], U * md[:, 1:2]], axis=1)
         sk, rs = sels[i][:kk], sels[i][kk:]
         Gg_ = Gg[i].reshape(mm - kk, kk)
         nrm = np.linalg.norm(U)
@@ -313,7 +335,8 @@ def test_coupling_blocks_are_kernel_entries(name):
     px, py = g.export("perm_x"), g.export("perm_y")
     # at the library's own skeletons (they equal the oracle's, up to the
     # near-ties allowed above)
-    reuse = y is None and kw["kernel"] != "cauchy"
+    reuse = y is None and kw["kernel"] not in ("cauchy", "double_layer")
+    pdata = kw.get("point_data")
     per_r = _gpu_per_node(g, "row", rk.shape[0])
     per_c = per_r if reuse else _gpu_per_node(g, "col", rk.shape[0])
     off = 0
@@ -324,9 +347,11 @@ def test_coupling_blocks_are_kernel_entries(name):
         if e in pick:
             gi, si, _ = per_r[i]
             gj, sj, _ = per_c[j]
-            rows = x[px[gi[si[:ki]]]]
-            cols = yy[py[gj[sj[:kj]]]]
-            ref = O.kernel_block(rows, cols, kw["kernel"])
+            ir, jc = px[gi[si[:ki]]], py[gj[sj[:kj]]]
+            rows, cols = x[ir], yy[jc]
+            ref = O.kernel_block(rows, cols, kw["kernel"],
+                                 data_P=None if pdata is None else pdata[ir],
+                                 data_Q=None if pdata is None else pdata[jc])
             blk = B[off:off + ki * kj].reshape(kj, ki).T
             assert np.max(np.abs(blk - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
         off += ki * kj
@@ -389,7 +414,7 @@ def test_matvec_fp32_apply(name, eval_prec):
     g.close()
 
 
-@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("name", [c for c in CASES if c not in DL])
 def test_evaluated_coupling_fp64_parity(name):
     """The index-only form (coupling blocks re-evaluated from the skeleton
     points inside each product, a chunk of pairs at a time) against the FP64
@@ -752,7 +777,7 @@ def test_products_of_one_handle_on_two_streams_are_ordered():
     ref_h.close()
 
 
-@pytest.mark.parametrize("name", ["h2_2d_log", "hss1d_cfg", "hss_cauchy_xy"])
+@pytest.mark.parametrize("name", ["h2_2d_log", "hss1d_cfg", "hss_cauchy_xy", "hss_dl_ram_head"])
 def test_storage_accounting(name):
     """smash_info's storage comparison (Sec. 6.6, Table 6.6): recomputed here
     from the exported ranks and lists -- the dense matrix, the generators as
@@ -807,3 +832,25 @@ def test_inv_r_kernel_blocks_against_numpy(scale):
     assert off == B.size
     print("scale", scale, "worst relative difference %.2e" % worst, flush=True)
     assert worst < 2 * np.finfo(np.float64).eps, worst
+
+
+def test_double_layer_gpu_against_dense_and_gauss():
+    """The double-layer HSS matrix on the GPU (ram head, n = 2560): its
+    product reproduces the dense Nystrom matrix within Table 6.3's
+    ||A - A_hat||_max order, the rows of K - I/2 sum to -1 (Gauss's
+    integral), and coupling requests for the evaluated form are refused."""
+    pts, data = W.curve("ram_head", 2560)
+    kw = dict(kernel="double_layer", leaf=50, order=5, adm="weak", tol=1e-10, eps_svd=1e-11,
+              tau=0.6)
+    g = api.Smash(dev(pts), point_data=dev(data), **kw)
+    one = g.matvec(torch.ones(2560, 1, dtype=torch.float64, device="cuda")).cpu().numpy()
+    assert np.max(np.abs(one + 1.0)) < 1e-8
+    A = O.kernel_block(pts, pts, "double_layer", data_P=data, data_Q=data)
+    Ah = g.matvec(dev(np.eye(2560))).cpu().numpy()
+    err = float(np.max(np.abs(A - Ah)))
+    print("double layer ram head 2560: ||A - A_hat||_max %.2e" % err, flush=True)
+    assert err < 1e-9
+    g.close()
+    with pytest.raises(api.SmashError) as e:
+        api.Smash(dev(pts), point_data=dev(data), coupling="evaluated", **kw)
+    assert e.value.code == -2
