@@ -346,6 +346,8 @@ def main():
         ex["hss1d_cauchy_1m (BF16 apply)"] = one_workload("hss1d_cauchy_1m", torch, api, W,
                                                           reps=3, apply="bf16")
         out["workloads"] = ex
+        print("double layer", flush=True)
+        out["double_layer"] = double_layer_bench(torch, api, W)
         print("O(n) series", flush=True)
         ser = []
         for lg in range(14, 21):
@@ -400,6 +402,45 @@ def main():
         print("serving", flush=True)
         out["serve"] = serve_bench(args, torch)
     print(json.dumps(out), flush=True)
+
+
+def double_layer_bench(torch, api, W):
+    """Sec. 6.4's HSS constructions of the Nystrom double-layer matrix at the
+    size of Table 6.6 (n = 10240) on both curves, at the tolerances of that
+    table: build time, ||A - A_hat||_max against the dense matrix (Tables
+    6.3-6.4), the storage comparison of Table 6.6, and the skeleton sizes of
+    the root's children (the size(B_i) of Table 6.5)."""
+    from oracle import oracle as O
+    res = {}
+    n = 10240
+    eye = torch.eye(n, dtype=torch.float64, device="cuda")
+    for curve in ("ram_head", "sunflower"):
+        pts, data = W.curve(curve, n)
+        A = O.kernel_block(pts, pts, "double_layer", data_P=data, data_Q=data)
+        P, D = torch.from_numpy(pts).cuda(), torch.from_numpy(data).cuda()
+        for tol, eps in ((1e-4, 1e-5), (1e-10, 1e-11)):
+            kw = dict(kernel="double_layer", leaf=50, order=5, adm="weak", tol=tol,
+                      eps_svd=eps, tau=0.6)
+            h = api.Smash(P, point_data=D, **kw)  # warm
+            h.close()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = api.Smash(P, point_data=D, **kw)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) * 1e3
+            Ah = h.matvec(eye).cpu().numpy()
+            inf = h.info()
+            rk = h.export("ranks").reshape(-1, 6)
+            nodes = h.export("nodes").reshape(-1, 8)
+            kids = [int(nodes[0, 2]), int(nodes[0, 2]) + 1]
+            res["%s tol %.0e eps_svd %.0e" % (curve, tol, eps)] = {
+                "n": n, "build_ms": tb, "max_abs_err": float(np.max(np.abs(A - Ah))),
+                "storage_MB": {"dense": inf["bytes_dense"] / 1e6, "hss0": inf["bytes_hss0"] / 1e6,
+                               "smash": inf["bytes_smash"] / 1e6},
+                "root_children_skeletons_row_col": [[int(rk[c, 1]), int(rk[c, 3])] for c in kids],
+                "nlevels": int(inf["nlevels"])}
+            h.close()
+    return res
 
 
 def serve_bench(args, torch):

@@ -5,6 +5,9 @@ product of a kernel matrix with 1-32 right-hand sides; the matrix is either
 built from the request's points (a construction) or one already resident
 on the device (a product only).  The engine
 
+  * takes the waiting requests shortest estimated work first (less the
+    time they have waited, so none starves), and keeps at most one large
+    construction in flight;
   * admits a construction when a worker slot is free and its device
     footprint fits the memory budget beside everything resident or in
     flight -- the footprint is the library's upper estimate
@@ -67,7 +70,8 @@ class Resident:
 class Engine:
     def __init__(self, executor, budget_bytes: int, slots: int = 4, margin: float = 1.15,
                  ratio: float | None = None, max_batch_rhs: int = 64, lookahead: int = 8,
-                 allow_evaluated: bool = True):
+                 allow_evaluated: bool = True, shortest_first: bool = True,
+                 heavy_points: int = 200_000, max_heavy: int = 1, age_weight: float = 1.0):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = int(slots)
@@ -76,6 +80,11 @@ class Engine:
         self.max_batch_rhs = max_batch_rhs
         self.lookahead = lookahead
         self.allow_evaluated = allow_evaluated
+        # admission order and the limit on large constructions in flight
+        self.shortest_first = shortest_first
+        self.heavy_points = heavy_points
+        self.max_heavy = max_heavy
+        self.age_weight = age_weight
         self.resident: dict[str, Resident] = collections.OrderedDict()
         self.inflight = []            # (future, kind, requests, reserved bytes, matrix)
         self.reserved = 0             # bytes of resident matrices + builds in flight
@@ -185,31 +194,53 @@ class Engine:
         self.inflight = keep
         return progressed
 
+    @staticmethod
+    def _cost(req):
+        """Estimated device seconds of a request: a construction about half a
+        microsecond per point (plus its product), a product on a resident
+        matrix about a nanosecond per point and right-hand side."""
+        n = req.rhs.shape[0]
+        prod = 1e-9 * n * req.rhs.shape[1]
+        return (5e-7 * n + prod) if req.points is not None else prod
+
+    def _heavy(self, req):
+        return req.points is not None and req.points.shape[0] >= self.heavy_points
+
     def _admit(self, pending, building, now, done):
-        """One admission pass over the waiting requests in arrival order.
-        Products on resident matrices are admitted wherever they wait (they
-        need no memory); constructions are considered among the first
-        `lookahead` waiting ones only."""
+        """One admission pass over the waiting requests: shortest estimated
+        work first, less the time already waited times age_weight (so none
+        starves), or in arrival order.  Products on resident matrices are
+        admitted wherever they wait (they need no memory); constructions are
+        considered among the first `lookahead` candidates only, and at most
+        max_heavy constructions of heavy_points or more run at once (large
+        builds that overlap slow each other and everything behind them)."""
         progressed = False
         scanned = 0
-        idx = 0
-        while idx < len(pending):
+        t0 = now()
+        if self.shortest_first:
+            cands = sorted(pending, key=lambda r: self._cost(r)
+                           - self.age_weight * max(0.0, t0 - r.arrival))
+        else:
+            cands = list(pending)
+        heavy = sum(1 for f, kind, grp, _, _ in self.inflight
+                    if kind == "build" and self._heavy(grp[0]))
+        for req in cands:
             if len(self.inflight) >= self.slots:
                 break
-            req = pending[idx]
+            if req not in pending:  # served by an earlier product group
+                continue
             m = req.matrix
             if req.points is not None:
                 if scanned >= self.lookahead:
-                    idx += 1
                     continue
                 scanned += 1
+                if self._heavy(req) and heavy >= self.max_heavy:
+                    continue
             if m in building:        # its matrix is being built: wait for it
-                idx += 1
                 continue
             if m in self.resident:
                 res = self.resident[m]
                 if res.busy:
-                    idx += 1
                     continue
                 # merge every waiting product of this matrix (up to the
                 # right-hand-side cap) into one launch
@@ -234,8 +265,7 @@ class Engine:
                 continue
             if req.points is None:
                 if any(r.matrix == m and r.points is not None for r in pending):
-                    idx += 1      # its construction is still waiting
-                    continue
+                    continue      # its construction is still waiting
                 req.error, req.done = "matrix %s is not resident" % m, now()
                 pending.remove(req)
                 done.append(req)
@@ -262,8 +292,7 @@ class Engine:
                     pending.remove(req)
                     done.append(req)
                     progressed = True
-                else:
-                    idx += 1      # does not fit yet: let smaller ones pass
+                # else: does not fit yet; let smaller ones pass
                 continue
             if evaluated and not asked:
                 req.params = dict(req.params, coupling="evaluated")
@@ -276,6 +305,7 @@ class Engine:
             fut = self.ex.submit_build(req)
             self.inflight.append((fut, "build", [req], need, m))
             self.log.append(("build", m))
+            heavy += 1 if self._heavy(req) else 0
             progressed = True
         self.peak_inflight = max(self.peak_inflight, len(self.inflight))
         return progressed

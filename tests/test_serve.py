@@ -195,3 +195,44 @@ def test_products_beyond_the_lookahead_are_admitted():
     assert all(r.error is None for r in done), [r.error for r in done]
     r9 = [r for r in done if r.rid == 9][0]
     assert np.array_equal(r9.result, 2.0 * r9.rhs)
+
+
+def test_shortest_first_admission():
+    """With one slot and everything waiting at once, constructions run in
+    order of estimated work (their point counts), not of arrival."""
+    ex = FakeExecutor(slots=1, build_s=0.01)
+    eng = Engine(ex, budget_bytes=10**9, slots=1, margin=1.0, age_weight=0.0)
+    sizes = [5000, 1000, 3000, 2000, 4000]
+    reqs = [_req(i, 0.0, "m%d" % i, n) for i, n in enumerate(sizes)]
+    done = eng.run(reqs)
+    order = [e[1] for e in eng.log if e[0] == "build"]
+    assert order == ["m1", "m3", "m2", "m4", "m0"], order
+    assert all(r.error is None for r in done)
+
+
+def test_at_most_one_heavy_construction_in_flight():
+    """Constructions of heavy_points or more points never overlap each other;
+    smaller ones still run beside them."""
+    class Ex(FakeExecutor):
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.heavy_now = self.heavy_max = 0
+
+        def _build(self, req):
+            big = req.rhs.shape[0] >= 3000
+            with self.lock:
+                self.heavy_now += big
+                self.heavy_max = max(self.heavy_max, self.heavy_now)
+            out = super()._build(req)
+            with self.lock:
+                self.heavy_now -= big
+            return out
+
+    ex = Ex(slots=4, build_s=0.03)
+    eng = Engine(ex, budget_bytes=10**9, slots=4, margin=1.0, heavy_points=3000)
+    reqs = [_req(i, 0.0, "h%d" % i, 4000) for i in range(3)]
+    reqs += [_req(10 + i, 0.0, "s%d" % i, 500) for i in range(3)]
+    done = eng.run(reqs)
+    assert len(done) == 6 and all(r.error is None for r in done)
+    assert ex.heavy_max == 1
+    assert ex.max_running >= 2  # small constructions overlapped the heavy ones
