@@ -1252,14 +1252,28 @@ __global__ void k_order_keys(int nb, int ne, const int *m, int lim, uint64_t *ke
 }
 
 // ------------------------------------------------------------------------
-// HSS near-field SVD, one workgroup per node: one-sided (Hestenes) Jacobi
-// on the rows of A_i (m x nc), parallel round-robin pair ordering (m/2
-// disjoint rotations per round, SV_G threads per rotation), sweeps until no
-// pair has |a_p . a_q| > 1e-15 |a_p||a_q|.  The accumulated rotations are
-// the left singular vectors; the kept ones (sigma >= eps * sigma_1, by
-// decreasing sigma) are written as S (m x ks row-major).
+// HSS near-field SVD, one workgroup per node.  The kept left singular
+// vectors of the block row A_i (m x nc; rows = this side's grid points) are
+// the right singular vectors of B = A_i^T (nc x m), held row-major: B[t][c]
+// is the kernel between grid point c and near-field point t.
+//  (1) Householder QR of B with column pivoting: at step j the column with
+//      the largest remaining norm is reduced; column norms are recomputed
+//      exactly as the update writes them; columns stay in place, so the
+//      first kq = min(m, nc) rows end up holding R P^T.
+//  (2) One-sided (Hestenes) Jacobi on the rows of R P^T: parallel
+//      round-robin pairs, a rotation wherever |a_p . a_q| > 1e-15 |a_p||a_q|,
+//      sweeps until none rotates.  R P^T has B's right singular vectors, so
+//      the converged rows, normalised, are the wanted vectors in the grid's
+//      own point order and their norms are the singular values; no rotation
+//      matrix is accumulated.  The pivoted factor has graded rows, on which
+//      the sweeps settle in about a third of the count they need on A_i.
+//  (3) Vectors with sigma >= eps * sigma_1, by decreasing sigma (ties: row),
+//      are written as S (m x ks row-major).
+// Threads: the QR maps lanes to columns (coalesced rows of B) and, for
+// m <= 128, splits the rows t over G = 256 / CP segments whose partial dots
+// and norms meet in LDS; the Jacobi gives each pair SV_G lanes.
 // ------------------------------------------------------------------------
-constexpr int SV_NT = 256, SV_G = 8, SV_MMAX = 512;  // largest near-field row count
+constexpr int SV_NT = 256, SV_G = 8, SV_MMAX = 1024;  // largest grid of a node
 
 struct SvdArgs {
   int nb, ne;
@@ -1275,109 +1289,226 @@ struct SvdArgs {
   int rowside;
   int kid, d;
   double diag, eps;
-  double *scratch;  // per workgroup: A (mpad x ldn), V (mpad x mpad)
-  int ldn;
+  double *scratch;  // per workgroup: B ((ncmax + 1) x ldb) when it is not in LDS
   int64_t wg_stride;
   double *S;  // output
   const int64_t *S_off;
   int *ks_out;
+  int *ks_max;       // largest ks of the launch
   const double *pd;  // double-layer kernel: per-point data by point id (X = Y)
 };
 
-// NCL / VCL > 0: a pair's two rows (nc <= 8 NCL entries) and two V columns
-// (mp <= 8 VCL entries) are read into registers at once, rotated there and
-// written back -- the same arithmetic in the same order as the general
-// loops (NCL = VCL = 0), without a chain of dependent loads per entry.
-// LDS: the block lives in dynamic LDS with row stride ldl and V in columns
-// [voff, voff + mp) of the same rows (voff >= every nc of the level);
-// otherwise A and V are in the workgroup's global tile.  Same arithmetic.
-template <int NCL, int VCL, bool LDS>
-__global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int ldl, int voff) {
+// Small per-node arrays at the front of the dynamic LDS (in doubles):
+// norm partials (two buffers of NP), dot partials (SV_NT), beta (mp), then
+// pivot step and pivot column (mp ints each).  B follows when it is in LDS.
+__host__ __device__ inline int svd_np(int mp) { return mp > SV_NT ? mp : SV_NT; }
+__host__ __device__ inline int svd_small(int mp) { return 2 * svd_np(mp) + SV_NT + 2 * mp; }
+
+template <int NCL, bool LDS>
+__global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int mpx, int ldl) {
   extern __shared__ double dyn_svd[];
-  __shared__ double sg[SV_MMAX];
-  __shared__ int ord[SV_MMAX];
   __shared__ int any_rot;
-  const int tid = threadIdx.x;
-  double *Am = LDS ? dyn_svd : A.scratch + (int64_t)blockIdx.x * A.wg_stride;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int NP = svd_np(mpx);
+  double *pnrm = dyn_svd;                 // [2][NP]
+  double *pdot = dyn_svd + 2 * NP;        // [SV_NT]
+  double *beta = pdot + SV_NT;            // [mp]
+  int *piv = (int *)(beta + mpx);         // [mp]
+  int *pcol = piv + mpx;                  // [mp]
+  double *sg = pnrm;                      // after the QR: singular values
+  int *ord = (int *)beta;                 // after the QR: order by sigma
+  double *Bm = LDS ? dyn_svd + svd_small(mpx) : A.scratch + (int64_t)blockIdx.x * A.wg_stride;
   for (int i = A.nb + blockIdx.x; i < A.ne; i += gridDim.x) {
     const int m = A.m_me[i];
     int nc = 0;
     for (int q = A.Nrow[i]; q < A.Nrow[i + 1]; q++) nc += A.m_ot[A.Ncol[q]];
-    const int ldn = LDS ? ldl : A.ldn;
-    const int mp = m + (m & 1);  // even row count (a zero row pads odd m)
-    double *V = LDS ? Am + voff : Am + (int64_t)mp * ldn;
-    const int64_t ldv = LDS ? ldn : mp;
+    const int ldb = LDS ? ldl : m;
     __syncthreads();
     if (m == 0 || nc == 0) {
       if (tid == 0) A.ks_out[i] = 0;
       continue;
     }
-    // block row: column o <-> point of the other side's grid, N_i order
+    // columns per pass and row segments: G * CP = SV_NT
+    const int CP = m <= 64 ? 64 : m <= 128 ? 128 : SV_NT;
+    const int G = SV_NT / CP;
+    const int g = tid / CP, cl = tid % CP;
+    // B = A_i^T: row t <-> point of the other side's grid, N_i order
     {
       int o = 0;
       for (int q = A.Nrow[i]; q < A.Nrow[i + 1]; q++) {
-        int j = A.Ncol[q];
-        int mj = A.m_ot[j];
-        int64_t gj = A.gbeg_ot[j];
-        for (int e = tid; e < mj * mp; e += SV_NT) {
-          int b = e / mp, r = e % mp;
-          double val = 0.0;
-          if (r < m) {
-            const int64_t ime = A.slot_me[A.gbeg_me[i] + r], iot = A.slot_ot[gj + b];
-            const double *pme = A.P_me + ime * A.d;
-            const double *pot = A.P_ot + iot * A.d;
-            const double *dme = A.pd ? A.pd + 3 * ime : nullptr;
-            const double *dot = A.pd ? A.pd + 3 * iot : nullptr;
-            val = A.rowside ? kernel_f64(A.kid, pme, pot, A.d, A.diag, dme, dot)
-                            : kernel_f64(A.kid, pot, pme, A.d, A.diag, dot, dme);
-          }
-          Am[(int64_t)r * ldn + o + b] = val;
+        const int j = A.Ncol[q];
+        const int mj = A.m_ot[j];
+        const int64_t gj = A.gbeg_ot[j];
+        for (int e = tid; e < mj * m; e += SV_NT) {
+          const int b = e / m, c = e % m;
+          const int64_t ime = A.slot_me[A.gbeg_me[i] + c], iot = A.slot_ot[gj + b];
+          const double *pme = A.P_me + ime * A.d;
+          const double *pot = A.P_ot + iot * A.d;
+          const double *dme = A.pd ? A.pd + 3 * ime : nullptr;
+          const double *dot = A.pd ? A.pd + 3 * iot : nullptr;
+          Bm[(int64_t)(o + b) * ldb + c] = A.rowside
+                                               ? kernel_f64(A.kid, pme, pot, A.d, A.diag, dme, dot)
+                                               : kernel_f64(A.kid, pot, pme, A.d, A.diag, dot, dme);
         }
         o += mj;
       }
     }
+    for (int c = tid; c < m; c += SV_NT) piv[c] = -1;
     __syncthreads();
-    for (int e = tid; e < mp * mp; e += SV_NT) V[(e / mp) * ldv + e % mp] = (e / mp == e % mp) ? 1.0 : 0.0;
+    // column norm partials over rows t = g (mod G)
+    for (int c = cl; c < m; c += CP) {
+      double s = 0.0;
+      for (int t = g; t < nc; t += G) {
+        const double v = Bm[(int64_t)t * ldb + c];
+        s = fma(v, v, s);
+      }
+      pnrm[g * m + c] = s;
+    }
     __syncthreads();
-    // Jacobi sweeps
-    const int g = tid / SV_G, gl = tid % SV_G;
-    const int npairs = mp / 2;
-    for (int sweep = 0; sweep < 80; sweep++) {
+    // (1) pivoted Householder QR of B
+    const int kmax = m < nc ? m : nc;
+    int kq = kmax;
+    for (int j = 0; j < kmax; j++) {
+      const double *pn = pnrm + (j & 1) * NP;
+      double *pw = pnrm + ((j + 1) & 1) * NP;
+      // arg-max of the remaining column norms, the same in every wave
+      double best = -1.0;
+      int bi = 0x7fffffff;
+      for (int c = lane; c < m; c += 64) {
+        const int pv = piv[c];
+        if (pv >= 0 && pv < j) continue;
+        double v = 0.0;
+        for (int h = 0; h < G; h++) v += pn[h * m + c];
+        if (v > best) {
+          best = v;
+          bi = c;
+        }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (!(best > 0.0)) {  // every remaining column is zero
+        kq = j;
+        break;
+      }
+      const int p = bi;
+      const double al = Bm[(int64_t)j * ldb + p];
+      const double sig = sqrt(best);
+      const double be = al >= 0.0 ? -sig : sig;
+      const double u0 = al - be;
+      const double cf = 1.0 / (sig * (sig + fabs(al)));
+      if (tid == 0) {
+        beta[j] = be;
+        pcol[j] = p;
+      }
+      const int gj = j % G;
+      const int t0 = j + 1 + ((g - (j + 1) % G) + G) % G;  // first t > j with t = g (mod G)
+      double wr[SV_MMAX / SV_NT];  // this thread's dots when G == 1
+#pragma unroll
+      for (int u = 0; u < SV_MMAX / SV_NT; u++) {
+        const int c = cl + u * CP;
+        if (c >= m) break;
+        double w = 0.0;
+        if (c != p && piv[c] < 0) {
+          if (g == gj) w = u0 * Bm[(int64_t)j * ldb + c];
+          for (int t = t0; t < nc; t += G)
+            w = fma(Bm[(int64_t)t * ldb + p], Bm[(int64_t)t * ldb + c], w);
+        }
+        if (G > 1)
+          pdot[g * m + c] = w;
+        else
+          wr[u] = w;
+      }
+      if (G > 1) __syncthreads();
+#pragma unroll
+      for (int u = 0; u < SV_MMAX / SV_NT; u++) {
+        const int c = cl + u * CP;
+        if (c >= m) break;
+        if (c == p) {
+          if (g == 0) piv[p] = j;
+          continue;
+        }
+        if (piv[c] >= 0) continue;
+        double w;
+        if (G > 1) {
+          w = 0.0;
+          for (int h = 0; h < G; h++) w += pdot[h * m + c];
+        } else {
+          w = wr[u];
+        }
+        const double f = cf * w;
+        if (g == gj) Bm[(int64_t)j * ldb + c] = fma(-f, u0, Bm[(int64_t)j * ldb + c]);
+        double nr = 0.0;
+        for (int t = t0; t < nc; t += G) {
+          const double v = fma(-f, Bm[(int64_t)t * ldb + p], Bm[(int64_t)t * ldb + c]);
+          Bm[(int64_t)t * ldb + c] = v;
+          nr = fma(v, v, nr);
+        }
+        pw[g * m + c] = nr;
+      }
+      __syncthreads();
+    }
+    // R P^T in rows [0, kq): each pivot column holds beta at its step and
+    // zeros below it; an odd kq gets a zero pad row for the pairing
+    const int kp = kq + (kq & 1);
+    for (int e = tid; e < kq * kp; e += SV_NT) {
+      const int j = e / kp, t = e % kp;
+      const int pc = pcol[j];
+      if (t == j)
+        Bm[(int64_t)t * ldb + pc] = beta[j];
+      else if (t > j)
+        Bm[(int64_t)t * ldb + pc] = 0.0;
+    }
+    if (kq & 1)
+      for (int c = tid; c < m; c += SV_NT) {
+        int pv = piv[c];
+        if (pv < 0) Bm[(int64_t)kq * ldb + c] = 0.0;  // pivot columns are zeroed above
+      }
+    __syncthreads();
+    // (2) Jacobi sweeps on the rows of R P^T
+    const int gi = tid / SV_G, gl = tid % SV_G;
+    const int npairs = kp / 2;
+    for (int sweep = 0; sweep < 80 && kq > 1; sweep++) {
       if (tid == 0) any_rot = 0;
       __syncthreads();
-      for (int round = 0; round < mp - 1; round++) {
-        for (int pr = g; pr < npairs; pr += SV_NT / SV_G) {
-          // round-robin: position 0 fixed, others rotate
-          int a0 = pr, b0 = mp - 1 - pr;
-          auto rr = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + round) % (mp - 1); };
+      for (int round = 0; round < kp - 1; round++) {
+        for (int pr = gi; pr < npairs; pr += SV_NT / SV_G) {
+          // round-robin: position 0 fixed, the others rotate
+          const int a0 = pr, b0 = kp - 1 - pr;
+          auto rr = [&](int x) { return x == 0 ? 0 : 1 + (x - 1 + round) % (kp - 1); };
           int pp = rr(a0), qq = rr(b0);
           if (pp > qq) {
-            int t = pp;
+            const int t = pp;
             pp = qq;
             qq = t;
           }
-          double *ap = Am + (int64_t)pp * ldn, *aq = Am + (int64_t)qq * ldn;
+          double *ap = Bm + (int64_t)pp * ldb, *aq = Bm + (int64_t)qq * ldb;
           double al = 0.0, be = 0.0, ga = 0.0;
           double xr[NCL > 0 ? NCL : 1], yr[NCL > 0 ? NCL : 1];
           if constexpr (NCL > 0) {
 #pragma unroll
-            for (int u = 0; u < NCL; u++) {
-              const int t = gl + SV_G * u;
-              const int tc = t < nc ? t : 0;
-              xr[u] = ap[tc];
-              yr[u] = aq[tc];
+            for (int v = 0; v < NCL; v++) {
+              const int t = gl + SV_G * v;
+              const int tc = t < m ? t : 0;
+              xr[v] = ap[tc];
+              yr[v] = aq[tc];
             }
 #pragma unroll
-            for (int u = 0; u < NCL; u++) {
-              if (gl + SV_G * u < nc) {
-                al = fma(xr[u], xr[u], al);
-                be = fma(yr[u], yr[u], be);
-                ga = fma(xr[u], yr[u], ga);
+            for (int v = 0; v < NCL; v++) {
+              if (gl + SV_G * v < m) {
+                al = fma(xr[v], xr[v], al);
+                be = fma(yr[v], yr[v], be);
+                ga = fma(xr[v], yr[v], ga);
               }
             }
           } else {
-            for (int t = gl; t < nc; t += SV_G) {
-              double x = ap[t], y = aq[t];
+            for (int t = gl; t < m; t += SV_G) {
+              const double x = ap[t], y = aq[t];
               al = fma(x, x, al);
               be = fma(y, y, be);
               ga = fma(x, y, ga);
@@ -1391,48 +1522,24 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int ldl, int voff
           if (al == 0.0 || be == 0.0) continue;
           if (fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
           if (gl == 0) any_rot = 1;
-          double zeta = (be - al) / (2.0 * ga);
-          double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double cs = 1.0 / sqrt(1.0 + tt * tt);
-          double sn = cs * tt;
+          const double zeta = (be - al) / (2.0 * ga);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + tt * tt);
+          const double sn = cs * tt;
           if constexpr (NCL > 0) {
 #pragma unroll
-            for (int u = 0; u < NCL; u++) {
-              const int t = gl + SV_G * u;
-              if (t < nc) {
-                ap[t] = cs * xr[u] - sn * yr[u];
-                aq[t] = sn * xr[u] + cs * yr[u];
+            for (int v = 0; v < NCL; v++) {
+              const int t = gl + SV_G * v;
+              if (t < m) {
+                ap[t] = cs * xr[v] - sn * yr[v];
+                aq[t] = sn * xr[v] + cs * yr[v];
               }
             }
           } else {
-            for (int t = gl; t < nc; t += SV_G) {
-              double x = ap[t], y = aq[t];
+            for (int t = gl; t < m; t += SV_G) {
+              const double x = ap[t], y = aq[t];
               ap[t] = cs * x - sn * y;
               aq[t] = sn * x + cs * y;
-            }
-          }
-          if constexpr (VCL > 0) {
-            double vx[VCL], vy[VCL];
-#pragma unroll
-            for (int u = 0; u < VCL; u++) {
-              const int t = gl + SV_G * u;
-              const int tc = t < mp ? t : 0;
-              vx[u] = V[tc * ldv + pp];
-              vy[u] = V[tc * ldv + qq];
-            }
-#pragma unroll
-            for (int u = 0; u < VCL; u++) {
-              const int t = gl + SV_G * u;
-              if (t < mp) {
-                V[t * ldv + pp] = cs * vx[u] - sn * vy[u];
-                V[t * ldv + qq] = sn * vx[u] + cs * vy[u];
-              }
-            }
-          } else {
-            for (int t = gl; t < mp; t += SV_G) {
-              double x = V[t * ldv + pp], y = V[t * ldv + qq];
-              V[t * ldv + pp] = cs * x - sn * y;
-              V[t * ldv + qq] = sn * x + cs * y;
             }
           }
         }
@@ -1441,31 +1548,35 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int ldl, int voff
       if (!any_rot) break;
       __syncthreads();
     }
-    // singular values, order by decreasing sigma (ties: index)
-    for (int a = tid; a < mp; a += SV_NT) {
+    // (3) singular values = row norms; order by decreasing sigma (ties: row)
+    for (int a = tid; a < kq; a += SV_NT) {
       double s = 0.0;
-      for (int t = 0; t < nc; t++) s = fma(Am[(int64_t)a * ldn + t], Am[(int64_t)a * ldn + t], s);
-      sg[a] = a < m ? sqrt(s) : -1.0;
+      for (int t = 0; t < m; t++) s = fma(Bm[(int64_t)a * ldb + t], Bm[(int64_t)a * ldb + t], s);
+      sg[a] = sqrt(s);
     }
     __syncthreads();
-    for (int a = tid; a < mp; a += SV_NT) {
+    for (int a = tid; a < kq; a += SV_NT) {
       int rank = 0;
-      for (int b = 0; b < mp; b++)
+      for (int b = 0; b < kq; b++)
         if (sg[b] > sg[a] || (sg[b] == sg[a] && b < a)) rank++;
       ord[rank] = a;
     }
     __syncthreads();
-    double s1 = sg[ord[0]];
+    const double s1 = kq > 0 ? sg[ord[0]] : 0.0;
     int ks = 0;
     if (s1 > 0.0)
-      for (int a = 0; a < m; a++)
+      for (int a = 0; a < kq; a++)
         if (sg[ord[a]] >= A.eps * s1) ks = a + 1;
     double *S = A.S + A.S_off[i - A.nb];
     for (int e = tid; e < m * ks; e += SV_NT) {
-      int r = e / ks, q = e % ks;
-      S[e] = V[r * ldv + ord[q]];
+      const int r = e / ks, q = e % ks;
+      const int a = ord[q];
+      S[e] = Bm[(int64_t)a * ldb + r] / sg[a];
     }
-    if (tid == 0) A.ks_out[i] = ks;
+    if (tid == 0) {
+      A.ks_out[i] = ks;
+      atomicMax(A.ks_max, ks);
+    }
   }
 }
 
@@ -1756,6 +1867,7 @@ struct SideCtx {
   int64_t *S_off = nullptr;
   bool gt_first = false;  // compr wrote G^T (the register kernel)
   int c0 = 0;             // basis width p^d, or 2 p^d (double-layer column side)
+  int *ks_max = nullptr;  // HSS: device word, the level's largest SVD rank
 };
 
 void build_generators(Handle &h) {
@@ -1800,7 +1912,7 @@ void build_generators(Handle &h) {
       k_leaf_init<<<ceil_div(nn, 256), 256, 0, s>>>(nn, h.nchild, sc.xb, sc.xe, S.m, S.gbeg, S.k);
       SMASH_CHECK_LAUNCH();
     }
-    int *dmax = keep.alloc_n<int>(2);
+    int *dmax = keep.alloc_n<int>(4);  // largest grid, near width, SVD rank per side
     int *dsw = keep.alloc_n<int>(3);  // swaps, cap flag, leaves
     int64_t *dslots = keep.alloc_n<int64_t>(2);  // running slot count per side
     for (size_t q = 0; q < sides.size(); q++) set_i64(dslots + q, sides[q].S->nslots, s);
@@ -1864,7 +1976,9 @@ void build_generators(Handle &h) {
           Side &S = *sc.S;
           Side &O = *ot.S;
           int64_t *scap = tmp.alloc_n<int64_t>(nl), *soff = tmp.alloc_n<int64_t>(nl + 1);
+          sc.ks_max = dmax + 2 + (int)q;
           SMASH_HIP(hipMemsetAsync(dmax + 1, 0, sizeof(int), s));
+          SMASH_HIP(hipMemsetAsync(sc.ks_max, 0, sizeof(int), s));
           k_near_cols<<<ceil_div(nl, 256), 256, 0, s>>>(nb, ne, h.Nrow, h.Ncol, O.m, S.m, dmax + 1,
                                                         scap);
           SMASH_CHECK_LAUNCH();
@@ -1877,45 +1991,41 @@ void build_generators(Handle &h) {
                                                  " points (raise leaf resolution)"};
           sc.Svec = tmp.alloc_n<double>(stot);
           sc.S_off = soff;
-          int mp = sc.mmax + (sc.mmax & 1);
-          int ldn = ncmax > 0 ? ncmax : 1;
+          const int mp = sc.mmax + (sc.mmax & 1);
+          const int ncm = ncmax > 0 ? ncmax : 1;
+          // B ((ncmax + 1) rows, odd row stride) after the small arrays in
+          // LDS when it fits, else in a global tile per workgroup
+          const int ldl = (sc.mmax > 0 ? sc.mmax : 1) | 1;
+          const size_t sh_small = sizeof(double) * (size_t)svd_small(mp);
+          const size_t sh_all = sh_small + sizeof(double) * (size_t)(ncm + 1) * ldl;
+          const bool lds = sh_all <= (size_t)dev_lds;
+          const int64_t wg_stride = lds ? 0 : (int64_t)(ncm + 1) * (sc.mmax > 0 ? sc.mmax : 1) + 8;
           int nwg = nl < 4 * dev_cus ? nl : 4 * dev_cus;
-          int64_t wg_stride = (int64_t)mp * ldn + (int64_t)mp * mp + 8;
-          double *scr = tmp.alloc_n<double>((size_t)wg_stride * nwg);
+          if (!lds) {  // at most 2 GiB of tiles
+            const int64_t cap = ((int64_t)1 << 28) / wg_stride;
+            if (nwg > cap) nwg = cap > 0 ? (int)cap : 1;
+          }
+          double *scr = lds ? nullptr : tmp.alloc_n<double>((size_t)wg_stride * nwg);
           SvdArgs sa{nb, ne, S.m, S.gbeg, S.slot_id, sc.P, O.m, O.gbeg, O.slot_id, ot.P, h.Nrow,
-                     h.Ncol, sc.rowside ? 1 : 0, h.kid, h.d, h.diag, h.eps_svd, scr, ldn,
-                     wg_stride, sc.Svec, soff, S.ks, h.Ap};
+                     h.Ncol, sc.rowside ? 1 : 0, h.kid, h.d, h.diag, h.eps_svd, scr,
+                     wg_stride, sc.Svec, soff, S.ks, sc.ks_max, h.Ap};
           PhaseTimer pt(h, SMASH_PHASE_NEAR_SVD, s);
-          // register-staged rotations when a pair's rows and V columns fit
-          const int ncl = ncmax <= 64 ? 8 : ncmax <= 128 ? 16 : ncmax <= 256 ? 32 : 0;
-          const int vcl = mp <= 32 ? 4 : mp <= 64 ? 8 : mp <= 128 ? 16 : 0;
-          // whole block (and V beside it) in LDS when it fits
-          const int voff = ncmax;
-          const int ldl = (ncmax + mp + 1) | 1;
-          const size_t shl = sizeof(double) * (size_t)mp * ldl;
-          const bool lds = shl + 8 * 1024 <= (size_t)dev_lds;
+          // register-staged rotations when a pair's rows fit
+          const int ncl = mp <= 64 ? 8 : mp <= 128 ? 16 : mp <= 256 ? 32 : 0;
           auto svd = [&](int grid) {
-#define SMASH_SVD_CASE(NC, VC)                                              \
-  else if (ncl == NC && vcl == VC) {                                        \
-    if (lds)                                                                \
-      k_near_svd<NC, VC, true><<<grid, SV_NT, shl, s>>>(sa, ldl, voff);           \
-    else                                                                    \
-      k_near_svd<NC, VC, false><<<grid, SV_NT, 0, s>>>(sa, 0, 0);              \
+#define SMASH_SVD_CASE(NC)                                                          \
+  if (ncl == NC) {                                                                  \
+    if (lds)                                                                        \
+      k_near_svd<NC, true><<<grid, SV_NT, sh_all, s>>>(sa, mp, ldl);                \
+    else                                                                            \
+      k_near_svd<NC, false><<<grid, SV_NT, sh_small, s>>>(sa, mp, 0);               \
   }
-            if (ncl == 0 || vcl == 0) {
-              if (lds)
-                k_near_svd<0, 0, true><<<grid, SV_NT, shl, s>>>(sa, ldl, voff);
-              else
-                k_near_svd<0, 0, false><<<grid, SV_NT, 0, s>>>(sa, 0, 0);
-            }
-            SMASH_SVD_CASE(8, 4) SMASH_SVD_CASE(8, 8) SMASH_SVD_CASE(8, 16)
-            SMASH_SVD_CASE(16, 4) SMASH_SVD_CASE(16, 8) SMASH_SVD_CASE(16, 16)
-            SMASH_SVD_CASE(32, 4) SMASH_SVD_CASE(32, 8) SMASH_SVD_CASE(32, 16)
+            SMASH_SVD_CASE(0) SMASH_SVD_CASE(8) SMASH_SVD_CASE(16) SMASH_SVD_CASE(32)
 #undef SMASH_SVD_CASE
             SMASH_CHECK_LAUNCH();
           };
           if (h.batched) {
-            svd(lds ? std::min(nl, 2 * dev_cus) : nwg);
+            svd(lds ? std::min(nl, 4 * dev_cus) : nwg);
           } else {
             for (int i = nb; i < ne; i++) {
               sa.nb = i;
@@ -1930,7 +2040,11 @@ void build_generators(Handle &h) {
       for (auto &sc : sides) {
         Side &S = *sc.S;
         LevelSide &L = S.lv[l];
-        const int cmax = sc.c0 + (hss ? sc.mmax : 0);
+        // basis width: c0 interpolation columns plus, for HSS, the near
+        // vectors (at most the grid size; their actual count is read back
+        // only when that bound is above the limit)
+        int cmax = sc.c0 + (hss ? sc.mmax : 0);
+        if (hss && cmax > ID_CMAX) cmax = sc.c0 + (int)pick_words(s, {{sc.ks_max, 4}})[0];
         if (cmax > ID_CMAX) throw Error{SMASH_E_UNSUPPORTED, "basis width above 512"};
         // The register form (k_compr_w: the grid in registers, two lanes per
         // grid point) takes grids of up to 256 points when c <= 64; larger
