@@ -495,11 +495,19 @@ def serve_bench(args, torch):
     matrices.  The capacity of the plain serial form (one request at a time)
     is measured first; then the continuous-batching engine and the plain
     form run the same Poisson trace at 0.5, 0.8 and 1.0 times it."""
-    from paper_1705_05443_amd import serve
-    budget = int(0.8 * torch.cuda.get_device_properties(0).total_memory)
+    from paper_1705_05443_amd import api, serve
+    # the earlier sections' cached memory goes back to the device; the
+    # handles then take theirs from torch's caching allocator, which also
+    # holds the vectors (one allocator, which frees its cache and retries
+    # before it fails)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    api.trim()
+    free, total = torch.cuda.mem_get_info()
+    budget = int(min(0.8 * total, 0.85 * free))
 
     def run(slots, cap, trace, keep=None):
-        ex = serve.GpuExecutor(slots=slots)
+        ex = serve.GpuExecutor(slots=slots, allocator="torch")
         eng = serve.Engine(ex, budget_bytes=budget, slots=slots, max_batch_rhs=cap)
         done = eng.run(trace)
         st = serve.latency_stats(done)
@@ -535,7 +543,7 @@ def serve_bench(args, torch):
                     "tol 1e-6, Chebyshev points per axis %s by dimension, 30%% products on "
                     "resident matrices, Poisson arrivals" % (nreq, args.serve_nmax,
                                                              serve.SERVE_ORDER),
-           "plain_capacity_requests_per_s": capacity, "loads": {}}
+           "plain_capacity_requests_per_s": capacity, "budget_GB": budget / 1e9, "loads": {}}
     for load in (0.5, 0.8, 1.0):
         rate = load * capacity
         kept = [] if load == 1.0 else None

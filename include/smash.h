@@ -273,6 +273,11 @@ typedef struct smash_info_t {
    *                blocks; a coupling block is fixed by its skeleton index
    *                sets, so no B_ij is stored. */
   int64_t bytes_dense, bytes_hss0, bytes_smash;
+  /* Device bytes the construction held at its peak: the handle's arrays
+   * plus every temporary of the build (chunks of the library's pool, or of
+   * the allocator hooks).  A caller that admits constructions by memory
+   * reserves this much while one runs, and device_bytes once it is done. */
+  int64_t build_peak_bytes;
 } smash_info_t;
 
 #define SMASH_PHASE_TREE 0
@@ -353,6 +358,16 @@ int smash_estimate_footprint(int64_t n, int32_t dim, int32_t kernel_id, int32_t 
 int smash_estimate_footprint_mode(int64_t n, int32_t dim, int32_t kernel_id, int32_t leaf_size,
                                   int32_t interp_order, int32_t admissibility, double tol,
                                   int32_t apply_prec, int32_t coupling_mode, int64_t *bytes);
+
+/* Returns the library's cached device memory to the device: the idle chunks
+ * that constructions keep for the next one, and the free part of the
+ * device's default memory pool (which the library keeps from shrinking
+ * between constructions).  For a caller about to allocate through another
+ * allocator, e.g. a serving loop that moves handles onto torch's caching
+ * allocator after stand-alone constructions.  Handles keep their memory.
+ *   device  the device to trim; < 0: the calling thread's current device
+ * Synchronises that device.  Errors: SMASH_E_DEVICE. */
+int smash_trim(int32_t device);
 
 int smash_destroy(smash_handle h);
 

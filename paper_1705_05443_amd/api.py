@@ -89,7 +89,8 @@ class Info(C.Structure):
                 ("graph_captures", C.c_int64), ("graph_replays", C.c_int64),
                 ("coupling_evaluated", C.c_int32), ("coupling_chunks", C.c_int32),
                 ("coupling_ws_entries", C.c_int64), ("bytes_dense", C.c_int64),
-                ("bytes_hss0", C.c_int64), ("bytes_smash", C.c_int64)]
+                ("bytes_hss0", C.c_int64), ("bytes_smash", C.c_int64),
+                ("build_peak_bytes", C.c_int64)]
 
 PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", "mv_up",
           "mv_coupling", "mv_down", "mv_near_out"]
@@ -98,7 +99,8 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
             "smash_matvec_noalloc", "smash_matvec_batched", "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
-            "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_last_error"]
+            "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_trim",
+            "smash_last_error"]
 
 
 def lib():
@@ -131,11 +133,12 @@ def lib():
         L.smash_info.argtypes = [vp, C.POINTER(Info)]
         L.smash_export.argtypes = [vp, C.c_int32, vp, C.POINTER(C.c_int64)]
         L.smash_destroy.argtypes = [vp]
+        L.smash_trim.argtypes = [C.c_int32]
         L.smash_last_error.restype = C.c_char_p
         for f in ("smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
                   "smash_matvec_noalloc", "smash_matvec_batched",
                   "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
-                  "smash_estimate_footprint", "smash_estimate_footprint_mode"):
+                  "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_trim"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -150,6 +153,12 @@ def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def trim(device=-1):
+    """Return the library's cached device memory (idle build chunks and the
+    free part of the default memory pool) to the device (smash_trim)."""
+    _check(lib().smash_trim(int(device)))
 
 
 def estimate_footprint(n, dim, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,

@@ -24,6 +24,7 @@
 
 #include <string>
 #include <cstring>
+#include <atomic>
 #include <initializer_list>
 #include <utility>
 #include <vector>
@@ -71,9 +72,32 @@ struct HooksScope {
   ~HooksScope();
 };
 
+// Device bytes held by a construction's arenas (chunks, whatever their
+// source): live now and the most at any time.  An arena takes the account of
+// the construction running on its host thread at its first allocation.
+struct MemAcct {
+  std::atomic<int64_t> live{0}, peak{0};
+  void add(int64_t b) {
+    const int64_t v = live.fetch_add(b) + b;
+    int64_t p = peak.load();
+    while (v > p && !peak.compare_exchange_weak(p, v)) {
+    }
+  }
+};
+MemAcct *current_acct();
+struct AcctScope {
+  MemAcct *prev;
+  explicit AcctScope(MemAcct *a);
+  ~AcctScope();
+};
+
+// Frees the idle cached chunks of device `dev`.
+void trim_chunk_cache(int dev);
+
 struct DeviceArena {
   hipStream_t stream = nullptr;
   const AllocHooks *hooks = nullptr;  // set at the first allocation
+  MemAcct *acct = nullptr;            // set at the first allocation
   bool bound = false;
   std::vector<std::pair<void *, size_t>> blocks;  // (base, size) of each chunk
   char *cur = nullptr;
@@ -246,6 +270,8 @@ struct Handle {
   hipEvent_t prod_done = nullptr;
   hipStream_t prod_stream = nullptr;
   DeviceArena ws_mem;
+  MemAcct acct;              // the construction's arenas
+  int64_t build_peak = 0;    // acct.peak when the construction ended
   // phase timing (options.timing)
   bool timing = false;
   struct TimedEvent {

@@ -38,19 +38,38 @@ bool take_cached(int dev, size_t n, void **p, size_t *sz) {
 }
 }  // namespace
 
+void trim_chunk_cache(int dev) {
+  ChunkCache &c = chunk_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  for (auto it = c.idle.begin(); it != c.idle.end();) {
+    if (it->second.first == dev) {
+      (void)hipFree(it->second.second);
+      c.held -= it->first;
+      it = c.idle.erase(it);
+    } else {
+      ++it;
+    }
+  }
+}
+
 namespace {
 thread_local const AllocHooks *tl_hooks = nullptr;
+thread_local MemAcct *tl_acct = nullptr;
 }
 const AllocHooks *current_hooks() { return tl_hooks; }
 HooksScope::HooksScope(const AllocHooks *h) : prev(tl_hooks) {
   tl_hooks = (h && h->alloc && h->free) ? h : nullptr;
 }
 HooksScope::~HooksScope() { tl_hooks = prev; }
+MemAcct *current_acct() { return tl_acct; }
+AcctScope::AcctScope(MemAcct *a) : prev(tl_acct) { tl_acct = a; }
+AcctScope::~AcctScope() { tl_acct = prev; }
 
 void *DeviceArena::alloc(size_t n) {
   n = (n + 255) & ~(size_t)255;
   if (!bound) {
     hooks = current_hooks();
+    acct = current_acct();
     bound = true;
   }
   if (n > left) {
@@ -74,6 +93,7 @@ void *DeviceArena::alloc(size_t n) {
       }
     }
     blocks.emplace_back(p, sz);
+    if (acct) acct->add((int64_t)sz);
     cur = (char *)p;
     left = sz;
   }
@@ -89,6 +109,7 @@ void DeviceArena::release(bool idle) {
   (void)hipGetDevice(&dev);
   ChunkCache &c = chunk_cache();
   for (auto &b : blocks) {
+    if (acct) acct->add(-(int64_t)b.second);
     if (hooks) {
       hooks->free(hooks->ctx, b.first, b.second, (void *)stream);
       continue;

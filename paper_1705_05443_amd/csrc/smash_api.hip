@@ -146,6 +146,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->hooks.free = opt.free;
     h->hooks.ctx = opt.alloc_ctx;
     HooksScope hs(&h->hooks);
+    AcctScope as(&h->acct);
     h->stream = (hipStream_t)stream;
     h->mem.stream = h->stream;
     h->ws_mem.stream = h->stream;
@@ -200,6 +201,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     build_blocks(*h);  // ends with the stream synchronised
     for (auto &a : h->spent) a.release();
     h->spent.clear();
+    h->build_peak = h->acct.peak.load();
     // (the leaf count came with the generators' last host read)
     h->build_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -353,6 +355,7 @@ extern "C" int smash_info(smash_handle hv, smash_info_t *info) {
     info->coupling_chunks = chunked ? (int32_t)h->cchunk_node.size() - 1 : 0;
     info->coupling_ws_entries = chunked ? h->bws_entries : 0;
     info->device_bytes = h->mem.bytes + h->ws_mem.bytes;
+    info->build_peak_bytes = h->build_peak;
     info->graph_captures = h->graph_captures;
     info->graph_replays = h->graph_replays;
     resolve_timers(*h);
@@ -642,6 +645,25 @@ extern "C" int smash_estimate_footprint_mode(int64_t n, int32_t dim, int32_t kid
   b += 2.0 * (dn + sides * nodes * r) * 64.0 * vs;     // product workspace
   *bytes = (int64_t)std::min(b, 9.0e18);
   (void)tol;
+  return SMASH_OK;
+}
+
+extern "C" int smash_trim(int32_t device) {
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(SMASH_E_DEVICE, "hipGetDevice failed");
+  const int dev = device < 0 ? cur : device;
+  try {
+    if (dev != cur) SMASH_HIP(hipSetDevice(dev));
+    SMASH_HIP(hipDeviceSynchronize());
+    trim_chunk_cache(dev);
+    hipMemPool_t pool;
+    SMASH_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    SMASH_HIP(hipMemPoolTrimTo(pool, 0));
+    if (dev != cur) SMASH_HIP(hipSetDevice(cur));
+  } catch (const Error &e) {
+    (void)hipSetDevice(cur);
+    return fail(e.code, e.msg);
+  }
   return SMASH_OK;
 }
 

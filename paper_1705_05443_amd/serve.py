@@ -10,10 +10,14 @@ on the device (a product only).  The engine
     construction in flight;
   * admits a construction when a worker slot is free and its device
     footprint fits the memory budget beside everything resident or in
-    flight -- the footprint is the library's upper estimate
-    (smash_estimate_footprint) scaled by the ratio of real to estimated
-    bytes seen so far (seeded from the autotuner table), with a margin;
-  * evicts idle resident matrices, least recently used first, to make room;
+    flight -- while it runs, the footprint is the library's upper estimate
+    (smash_estimate_footprint) scaled by the largest ratio of a
+    construction's peak device bytes (temporaries included, from
+    smash_info) to the estimate seen so far (seeded from the autotuner
+    table), with a margin; once built, the matrix holds its resident bytes;
+  * evicts idle resident matrices, least recently used first, to make room,
+    and builds an evicted matrix again from its points when a product on
+    it arrives later;
   * admits a construction whose stored form exceeds the whole budget with
     its coupling blocks evaluated inside each product instead
     (SMASH_COUPLING_EVALUATED: the same results, no O(sum k_i k_j) storage,
@@ -76,7 +80,8 @@ class Engine:
         self.budget = int(budget_bytes)
         self.slots = int(slots)
         self.margin = margin
-        self.ratios = {} if ratio is None else {None: ratio}  # real / estimated bytes
+        self.ratios = {} if ratio is None else {None: ratio}  # resident / estimated bytes
+        self.peak_ratios = {}  # a construction's peak (temporaries included) / estimated bytes
         self.max_batch_rhs = max_batch_rhs
         self.lookahead = lookahead
         self.allow_evaluated = allow_evaluated
@@ -86,6 +91,7 @@ class Engine:
         self.max_heavy = max_heavy
         self.age_weight = age_weight
         self.resident: dict[str, Resident] = collections.OrderedDict()
+        self.sources = {}             # matrix -> (points, params) it was built from
         self.inflight = []            # (future, kind, requests, reserved bytes, matrix)
         self.reserved = 0             # bytes of resident matrices + builds in flight
         self.peak_reserved = 0
@@ -102,12 +108,15 @@ class Engine:
         return None if req.points is None else (req.points.shape[1], bool(evaluated))
 
     def _need(self, req, evaluated=False):
-        """Bytes reserved for a construction (stored or evaluated coupling
-        blocks): the estimate times the largest real/estimated ratio seen for
-        its dimension and form (before any: the executor's prior, else 1),
-        with the margin, never above 1."""
+        """Bytes reserved while a construction runs (stored or evaluated
+        coupling blocks): the estimate times the largest ratio of a
+        construction's peak device bytes (its temporaries included) to the
+        estimate seen for its dimension and form -- before any, the resident
+        ratio, the executor's prior, else 1 -- with the margin, never above
+        1.  Once built, the matrix holds its resident bytes only."""
         est = self.ex.estimate(req, evaluated=evaluated)
-        r = self.ratios.get(self._cls(req, evaluated), self.ratios.get(None))
+        c = self._cls(req, evaluated)
+        r = self.peak_ratios.get(c, self.ratios.get(c, self.ratios.get(None)))
         if r is None:
             r = self.ex.prior_ratio(req)
         return int(est * min(1.0, r * self.margin))
@@ -174,13 +183,17 @@ class Engine:
                     self.resident[m].busy = False
                 continue
             if kind == "build":
-                handle, nbytes, results = out
+                # (handle, resident bytes, results[, peak bytes of the build])
+                handle, nbytes, results = out[:3]
+                peak = out[3] if len(out) > 3 else nbytes
                 building.discard(m)
                 ev = self._evaluated(group[0])
                 est = self.ex.estimate(group[0], evaluated=ev)
                 if est > 0:
                     c = self._cls(group[0], ev)
                     self.ratios[c] = max(self.ratios.get(c, 0.0), nbytes / est)
+                    self.peak_ratios[c] = max(self.peak_ratios.get(c, 0.0),
+                                              max(peak, nbytes) / est)
                 self.reserved += nbytes - resv
                 self.resident[m] = Resident(m, handle, nbytes, False, t)
             else:
@@ -266,11 +279,17 @@ class Engine:
             if req.points is None:
                 if any(r.matrix == m and r.points is not None for r in pending):
                     continue      # its construction is still waiting
-                req.error, req.done = "matrix %s is not resident" % m, now()
-                pending.remove(req)
-                done.append(req)
-                progressed = True
-                continue
+                src = self.sources.get(m)
+                if src is None:
+                    req.error, req.done = "matrix %s is not resident" % m, now()
+                    pending.remove(req)
+                    done.append(req)
+                    progressed = True
+                    continue
+                # evicted earlier: built again from the points it was built
+                # from, with this product as the construction's own product
+                req.points, req.params = src
+                self.log.append(("rebuild", m))
             asked = self._evaluated(req)  # the request itself may ask for that form
             need = self._need(req, evaluated=asked)
             evaluated = asked
@@ -299,6 +318,7 @@ class Engine:
                 self.log.append(("evaluated", m))
             pending.remove(req)
             req.admitted = now()
+            self.sources[m] = (req.points, req.params)
             self.reserved += need
             self.peak_reserved = max(self.peak_reserved, self.reserved)
             building.add(m)
@@ -386,8 +406,8 @@ class GpuExecutor:
             Z = h.matvec(Q, stream=s)
             s.synchronize()
             z = Z.cpu().numpy()
-            nbytes = h.info()["device_bytes"]
-        return h, nbytes, [z]
+            inf = h.info()
+        return h, inf["device_bytes"], [z], inf["build_peak_bytes"]
 
     def _product(self, h, group):
         torch = self.torch

@@ -699,20 +699,23 @@ def test_batched_products_equal_single_ones():
 def test_allocator_hooks_take_every_device_allocation():
     """With torch's caching allocator as the hooks, a handle's memory shows in
     torch's accounting while it lives, every allocation is given back at
-    destroy, and the product equals the one of a handle on the library's own
-    pool bit for bit."""
+    destroy, the build's peak in smash_info equals the most the hooks held
+    during the construction, and the product equals the one of a handle on
+    the library's own pool bit for bit (also after smash_trim)."""
     import ctypes as C
     import torch
     x = W.uniform(5000, 2, 41)
     kw = dict(kernel="log_r", leaf=64, order=8, adm="strong", tol=1e-8, tau=0.7,
               root=((0.0, 0.0), 1.0))
     live = {}
+    most = [0]
     talloc, tfree = api.torch_allocator_hooks()
 
     def _alloc(ctx, n, s):
         p = talloc(ctx, n, s)
         if p:
             live[p] = n
+            most[0] = max(most[0], sum(live.values()))
         return p
 
     def _free(ctx, p, n, s):
@@ -726,11 +729,18 @@ def test_allocator_hooks_take_every_device_allocation():
     before = torch.cuda.memory_allocated()
     h = api.Smash(dev(x), allocator=hooks, **kw)
     held = sum(live.values())
-    assert held >= h.info()["device_bytes"] > 0
+    inf = h.info()
+    assert held >= inf["device_bytes"] > 0
+    assert inf["build_peak_bytes"] == most[0] >= held, (inf["build_peak_bytes"], most[0], held)
     z = h.matvec(q).cpu().numpy()
     assert torch.cuda.memory_allocated() - before >= held
     h.close()
     assert not live  # every allocation went back through the hook
+    g = api.Smash(dev(x), **kw)
+    assert np.array_equal(g.matvec(q).cpu().numpy(), z)
+    assert g.info()["build_peak_bytes"] >= g.info()["device_bytes"]
+    g.close()
+    api.trim()
     g = api.Smash(dev(x), **kw)
     assert np.array_equal(g.matvec(q).cpu().numpy(), z)
     g.close()

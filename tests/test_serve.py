@@ -119,6 +119,21 @@ def test_idle_residents_are_evicted_to_admit_new_builds():
     assert eng.peak_reserved <= 3000
 
 
+def test_a_product_on_an_evicted_matrix_rebuilds_it():
+    """A product that arrives after its matrix was evicted is served by
+    building the matrix again from the points it was built from (the
+    product rides on that construction), not failed."""
+    ex = FakeExecutor(slots=1, real_per_point=2)
+    eng = Engine(ex, budget_bytes=3000, slots=1, margin=1.0, ratio=1.0, allow_evaluated=False)
+    reqs = [_req(i, 0.01 * i, "m%d" % i, 1000) for i in range(3)]  # m0, m1 evicted
+    reqs.append(_req(9, 0.2, "m0", 1000, nrhs=3, build=False))
+    done = {r.rid: r for r in eng.run(reqs)}
+    assert all(r.error is None for r in done.values())
+    assert ("rebuild", "m0") in eng.log
+    assert np.array_equal(done[9].result, 2.0 * done[9].rhs)
+    assert [e[1] for e in eng.log if e[0] == "build"] == ["m0", "m1", "m2", "m0"]
+
+
 def test_a_request_that_can_never_fit_is_rejected():
     ex = FakeExecutor(slots=2)
     eng = Engine(ex, budget_bytes=1000, slots=2, ratio=1.0, margin=1.0)
@@ -236,3 +251,43 @@ def test_at_most_one_heavy_construction_in_flight():
     assert len(done) == 6 and all(r.error is None for r in done)
     assert ex.heavy_max == 1
     assert ex.max_running >= 2  # small constructions overlapped the heavy ones
+
+
+def test_constructions_reserve_their_peak_not_their_resident_size():
+    """A construction's temporaries make its peak larger than what the
+    finished matrix keeps: the engine learns that peak from the executor
+    and reserves it while a construction runs, so resident matrices plus
+    running constructions at their peak never exceed the budget."""
+    class Ex(FakeExecutor):
+        # estimate 2 per point; peak 1.5 per point; resident 0.5 per point
+        def __init__(self, *a, **k):
+            super().__init__(*a, **k)
+            self.live = self.live_max = 0
+            self.held = {}
+
+        def _build(self, req):
+            n = req.rhs.shape[0]
+            with self.lock:
+                self.live += 3 * n // 2
+                self.live_max = max(self.live_max, self.live)
+            self._enter()
+            time.sleep(self.build_s)
+            self._leave()
+            with self.lock:
+                self.live -= 3 * n // 2 - n // 2
+                self.held[req.matrix] = n // 2
+            return ("H", req.matrix), n // 2, [2.0 * req.rhs], 3 * n // 2
+
+        def release(self, h):
+            with self.lock:
+                self.live -= self.held.pop(h[1])
+            super().release(h)
+
+    ex = Ex(slots=4, build_s=0.02)
+    budget = 4000
+    eng = Engine(ex, budget_bytes=budget, slots=4, margin=1.0, heavy_points=10**9)
+    reqs = [_req(i, 0.001 * i, "m%d" % i, 1000) for i in range(16)]
+    done = eng.run(reqs)
+    assert len(done) == 16 and all(r.error is None for r in done)
+    assert ex.live_max <= budget, ex.live_max
+    assert eng.peak_ratios and max(eng.peak_ratios.values()) == 0.75
