@@ -143,11 +143,24 @@ def kernel_rows(torch, x, y, rows, kernel, pdata=None):
     return K
 
 
-def exact_rows(torch, x, y, rows, q, kernel, chunk=8):
-    """Rows of A Q for the given original row indices, in FP64."""
+def exact_rows(torch, x, y, rows, q, kernel, chunk=16, nb=256):
+    """Rows of A Q for the given original row indices, in FP64.  The long
+    inner dimension is split into nb batched products whose results are
+    summed (a product of 16 rows against 10^6 x 64 is one output tile and
+    would otherwise run on a single workgroup)."""
     Q = torch.as_tensor(np.asarray(q, np.float64).reshape(q.shape[0], -1), device="cuda")
-    out = [kernel_rows(torch, x, y, rows[a:a + chunk], kernel) @ Q
-           for a in range(0, len(rows), chunk)]
+    n, R = Q.shape
+    L = -(-n // nb)
+    Qb = torch.zeros((nb * L, R), dtype=torch.float64, device="cuda")
+    Qb[:n] = Q
+    Qb = Qb.view(nb, L, R)
+    out = []
+    for a in range(0, len(rows), chunk):
+        K = kernel_rows(torch, x, y, rows[a:a + chunk], kernel)
+        Kb = torch.zeros((K.shape[0], nb * L), dtype=torch.float64, device="cuda")
+        Kb[:, :n] = K
+        Kb = Kb.view(K.shape[0], nb, L).transpose(0, 1).contiguous()
+        out.append(torch.bmm(Kb, Qb).sum(0))
     return torch.cat(out).cpu().numpy()
 
 

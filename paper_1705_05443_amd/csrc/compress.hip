@@ -730,6 +730,7 @@ struct CsArgs {
   int64_t gstride;
   int *iscr;         // per workgroup: labels (mmax), skeleton counts (mmax)
   int64_t istride;
+  const int *first;  // device: the launch takes order[*first, *cnt) (null: from 0)
 };
 
 // sums, maxima and broadcasts inside a group of 16 lanes (one DPP row);
@@ -1216,7 +1217,8 @@ __global__ void __launch_bounds__(CS_NT) k_compr_s(IdArgs A, CsArgs B) {
   int *const Ge = Gl + B.mmax;
   const CsShared sh{xi, wk, slots, Fg, rdiag, rdg, rinv, piv, msrc, meta, ared, sred};
   const int cnt = *B.cnt;
-  for (int e = blockIdx.x; e < cnt; e += gridDim.x) {
+  const int e0 = B.first ? *B.first : 0;
+  for (int e = e0 + blockIdx.x; e < cnt; e += gridDim.x) {
     const int i = B.order ? B.order[e] : A.nb + e;
     const int m = A.m[i];
     __syncthreads();
@@ -1235,6 +1237,624 @@ __global__ void __launch_bounds__(CS_NT) k_compr_s(IdArgs A, CsArgs B) {
     else  // the LDS tile area takes columns of R11 in the back substitution
       compr_node_s<CMAX, false>(A, B, i, m, Gw, Gn, Gl, Ge, Ri, Lw,
                                 (int)(((int64_t)B.lds_cols * (ldc + 2)) / ldc), sh);
+  }
+}
+
+// ------------------------------------------------------------------------
+// compr with every grid column held in registers for the whole algorithm, a
+// node's columns split over nw workgroups (nw = 1, 2, 4, 8 or 16 by grid
+// size; DQ_CPW columns per workgroup, the grid range [w DQ_CPW, (w+1)
+// DQ_CPW) in workgroup w).  The algorithm and its arithmetic are the wide
+// form's above -- labels for positions, the pivot as the largest squared
+// residual norm with ties to the lowest position, the reflector from the
+// pivot norm, norms recomputed exactly in the update, the rank test
+// against tol |R_00|; the swap test by column back substitution against
+// R11 with the reciprocal diagonal, rho^2 = N_ij^2 + (gamma_j / omega_i)^2
+// with its arg-max over pair indices, a swap relabelling two columns and
+// refactoring from the rebuilt basis without pivoting; the canonical
+// output -- in the same order of summation.  With nw > 1 the workgroups of
+// a node meet where a step needs all of them: each publishes what it holds
+// (its best column and candidate, its columns of R11 and R11^-1, its
+// skeleton count, its rho candidate) through device-coherent atomic
+// accesses, and a counter per group of nw workgroups, incremented once a
+// workgroup's accesses have completed, tells when all have.  The launch is
+// cooperative (every workgroup resident) and the workgroups of a group sit
+// on one XCD; a wait longer than spin_limit ticks of the 100 MHz clock
+// gives up with the error flag instead of hanging.
+// ------------------------------------------------------------------------
+constexpr int DQ_CPG = 4;               // columns per 16-lane group
+constexpr int DQ_CPW = CS_NG * DQ_CPG;  // columns per workgroup
+constexpr int DQ_MAXW = 16;             // workgroups per node, at most
+
+struct DqMeta {
+  double v;  // candidate value (-1: none)
+  int lab;   // its label (or pair index)
+  int a;     // its storage (grid) index
+};
+
+struct DqArgs {
+  const int *order;  // the level's wide-form nodes, largest grid first
+  const int *range;  // device: positions [range[0], range[1]) of order for this launch
+  int nw;            // workgroups per node
+  int ldc;           // rows of an exchanged column (>= c)
+  int *exs;          // per node at selo: skeleton columns before each grid index
+  double *gslot;     // per group: [2][nw][ldc] published columns
+  DqMeta *gmeta;     // per group: [3][nw] published candidates (QR steps by
+                     // parity, the swap test)
+  double *gR;        // per group: R11 by columns (k x k), then R11^-1 by columns
+  double *gI;
+  int gr_stride;     // entries of one group's gR / gI
+  int *gcount;       // per group: [nw] skeleton counts
+  unsigned *gcnt;    // per group: arrivals
+  int64_t spin_limit;
+};
+
+template <int CMAX>
+__global__ void __launch_bounds__(CS_NT) k_compr_dq(IdArgs A, DqArgs D) {
+  extern __shared__ double dq_dyn[];  // the groups' one-dimensional factors, then R11 columns
+  constexpr int RL = CMAX / CS_LPC;
+  constexpr int RC = CMAX <= 224 ? 64 : 48;  // R11 columns staged in LDS at a time
+  __shared__ double xi[3 * ID_PMAX], wk[ID_PMAX], chc[ID_PMAX];
+  __shared__ double lslot[2][CS_NW][CMAX];
+  __shared__ double rdiag[CMAX], rdg[CMAX], rinv[CMAX];
+  __shared__ int piv[CMAX];
+  __shared__ ArgMax wbest[2 * CS_NW];
+  __shared__ int wsrc[2 * CS_NW];
+  __shared__ ArgMax ared[CS_NW + 1];
+  __shared__ int64_t sred[CS_NW + 1];
+  __shared__ int sflag, sbase;
+  const int tid = threadIdx.x, g = tid / CS_LPC, h = tid % CS_LPC;
+  const int wid = tid / WAVE, lane = tid & (WAVE - 1);
+  const int p = A.p, d = A.d, ldc = D.ldc, nw = D.nw;
+  // the workgroups of a group on one XCD (workgroups go to the eight XCDs
+  // round-robin), so their meetings stay within one L2
+  const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, gpx = gridDim.x / (8 * nw);
+  const int grp = xcd * gpx + slot / nw, w = slot % nw, ngrp = 8 * gpx;
+  if (tid < p) {
+    const double th = M_PI * (2.0 * tid + 1.0) / (2.0 * p);
+    chc[tid] = cos(th);
+    wk[tid] = ((tid & 1) ? -1.0 : 1.0) * sin(th);
+  }
+  double *const F = dq_dyn + g * (d * p);
+  double *const Lr = dq_dyn + CS_NG * d * p;  // RC columns of CMAX rows
+  double *const gs = D.gslot + (int64_t)grp * 2 * nw * ldc;
+  DqMeta *const gm = D.gmeta + (int64_t)grp * 3 * nw;
+  double *const gR = D.gR + (int64_t)grp * D.gr_stride;
+  double *const gI = D.gI + (int64_t)grp * D.gr_stride;
+  int *const gc = D.gcount + (int64_t)grp * nw;
+  unsigned nsync = 0;  // meetings of this group so far (the same in all its workgroups)
+  bool abort = false;
+
+  auto st = [&](double *q, double v) {
+    __hip_atomic_store(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto ld = [&](const double *q) -> double {
+    return __hip_atomic_load(const_cast<double *>(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto sti = [&](int *q, int v) {
+    __hip_atomic_store(q, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  auto ldi = [&](const int *q) -> int {
+    return __hip_atomic_load(const_cast<int *>(q), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // all workgroups of the group have passed this point with their shared
+  // writes complete (false: the wait timed out)
+  auto meet = [&]() -> bool {
+    if (nw == 1) {
+      __syncthreads();
+      return true;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    nsync++;
+    if (tid == 0) {
+      __hip_atomic_fetch_add(D.gcnt + grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned target = nsync * (unsigned)nw;
+      const uint64_t t0 = wall_clock64();
+      int to = 0;
+      while (__hip_atomic_load(D.gcnt + grp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             target) {
+        if ((int64_t)(wall_clock64() - t0) > D.spin_limit) {
+          to = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      sflag = to;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    if (sflag) {
+      if (tid == 0) atomicOr(A.err, 2);
+      return false;
+    }
+    return true;
+  };
+  // the group's arg-max of one candidate per workgroup (value, label;
+  // a = storage index), returned to every lane
+  auto group_argmax = [&](ArgMax mine, int mine_a, int par, int *win_w, int *win_a) -> ArgMax {
+    if (nw == 1) {
+      *win_w = 0;
+      *win_a = mine_a;
+      return mine;
+    }
+    if (tid == 0) {
+      DqMeta *me = gm + par * nw + w;
+      st(&me->v, mine.v);
+      sti(&me->lab, mine.a);
+      sti(&me->a, mine_a);
+    }
+    if (!meet()) {
+      abort = true;
+      return ArgMax{-1.0, -1};
+    }
+    double mv = -1.0;
+    int ml = -1, ma = -1;
+    if (lane < nw) {
+      DqMeta *mp = gm + par * nw + lane;
+      mv = ld(&mp->v);
+      ml = ldi(&mp->lab);
+      ma = ldi(&mp->a);
+    }
+    const ArgMax r = lanes_argmax<DQ_MAXW>(ArgMax{mv, ml});
+    const uint64_t gw = __ballot(lane < nw && r.a >= 0 && ml == r.a);
+    const int ws = gw ? (int)__ffsll((unsigned long long)gw) - 1 : 0;
+    *win_w = ws;
+    *win_a = r.a >= 0 ? __builtin_amdgcn_readlane(ma, ws) : -1;
+    return r;
+  };
+
+  const int lo = D.range[0], hi = D.range[1];
+  for (int e = lo + grp; e < hi; e += ngrp) {
+    const int i = D.order[e];
+    const int m = A.m[i];
+    __syncthreads();
+    if (tid < d * p) {
+      const int t = tid / p, q = tid % p;
+      const double blo = A.lo[3 * i + t], bhi = A.hi[3 * i + t];
+      xi[t * ID_PMAX + q] = 0.5 * (blo + bhi) + 0.5 * (bhi - blo) * chc[q];
+    }
+    __syncthreads();
+    if (m == 0) {
+      if (w == 0 && tid == 0) A.k_out[i] = 0;
+      continue;
+    }
+    const int ks = A.S ? A.ks[i] : 0;
+    const int c = A.c0 + ks;
+    double col[DQ_CPG][RL];
+    double nr[DQ_CPG];
+    int lb[DQ_CPG];
+
+    // the columns of C^T from the basis and their squared norms; labels
+    // start as the grid index unless `keep`
+    auto build = [&](bool keep) {
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        const int a = w * DQ_CPW + g + CS_NG * j;
+        const bool on = a < m;
+        if (on) {
+          const int64_t id = A.slot_id[A.gbeg[i] + a];
+          for (int t = 0; t < d; t++) {
+            const double x = A.P[id * d + t];
+            const double blo = A.lo[3 * i + t], bhi = A.hi[3 * i + t];
+            int hit = -1;
+            double den = 0.0;
+            if (bhi - blo == 0.0) {
+              hit = 0;
+            } else {
+              for (int q = h; q < p; q += CS_LPC) {
+                const double xq = xi[t * ID_PMAX + q];
+                if (x == xq) {
+                  hit = q;
+                  break;
+                }
+                const double wq = wk[q] / (x - xq);
+                F[t * p + q] = wq;
+                den += wq;
+              }
+            }
+            hit = g16_max(hit);
+            den = g16_sum(den);
+            for (int q = h; q < p; q += CS_LPC)
+              F[t * p + q] = hit >= 0 ? (q == hit ? 1.0 : 0.0) : F[t * p + q] / den;
+          }
+        }
+        __syncthreads();
+        double s2 = 0.0;
+        const double *Sa = (on && ks > 0) ? A.S + A.S_off[i - A.nb] + (int64_t)a * ks : nullptr;
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int r = CS_LPC * u + h;
+          double val = 0.0;
+          if (on && r < c) {
+            if (r < A.c0) {
+              int q = r;
+              val = 1.0;
+              for (int t = d - 1; t >= 0; t--) {
+                val *= F[t * p + q % p];
+                q /= p;
+              }
+              if (A.dlw)
+                val = val * A.pdat[3 * (int64_t)A.slot_id[A.gbeg[i] + a] + (r < A.pd ? 0 : 1)];
+            } else {
+              val = Sa[r - A.c0];
+            }
+            s2 = fma(val, val, s2);
+          }
+          col[j][u] = val;
+        }
+        nr[j] = g16_sum(s2);
+        if (!keep) lb[j] = on ? a : -1;
+        __syncthreads();
+      }
+    };
+
+    // Householder QR over positions 0..kend-1 (pivoting: the largest
+    // remaining norm, stop at the rank test; else the column labelled t);
+    // R_tt and the storage index of position t go to rdiag / piv (LDS)
+    auto qr = [&](bool pivoting, int kend) -> int {
+      ArgMax best{-1.0, -1};
+      int bst = -1;
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        if (lb[j] < 0 || !(pivoting || lb[j] == 0)) continue;
+        const ArgMax y = amax_pick(best, ArgMax{nr[j], lb[j]});
+        if (y.a == lb[j] && best.a != lb[j]) {
+          best = y;
+          bst = j;
+        }
+      }
+      int kk = 0;
+      double r00 = 0.0;
+      for (int t = 0; t < kend; t++) {
+        const int par = t & 1;
+        {  // each wavefront stages its best column (rows t..) and candidate
+          const ArgMax wa = wave_argmax(best);
+          const int ew = par * CS_NW + wid;
+          if (wa.a >= 0 && best.a == wa.a) {
+#pragma unroll
+            for (int j = 0; j < DQ_CPG; j++)
+              if (j == bst) {
+#pragma unroll
+                for (int u = 0; u < RL; u++) {
+                  const int r = CS_LPC * u + h;
+                  if (r >= t && r < c) lslot[par][wid][r] = col[j][u];
+                }
+              }
+            if (h == 0) {
+              wbest[ew] = wa;
+              wsrc[ew] = w * DQ_CPW + g + CS_NG * bst;
+            }
+          }
+          if (wa.a < 0 && lane == 0) {
+            wbest[ew] = ArgMax{-1.0, -1};
+            wsrc[ew] = -1;
+          }
+        }
+        __syncthreads();
+        const ArgMax we = lane < CS_NW ? wbest[par * CS_NW + lane] : ArgMax{-1.0, -1};
+        const ArgMax wb = lanes_argmax<CS_NW>(we);
+        const uint64_t wins = __ballot(lane < CS_NW && wb.a >= 0 && we.a == wb.a);
+        const int wsl = wins ? (int)__ffsll((unsigned long long)wins) - 1 : 0;
+        const int wa_idx = wb.a >= 0 ? wsrc[par * CS_NW + wsl] : -1;
+        const double *src = &lslot[par][wsl][0];
+        if (nw > 1 && wb.a >= 0) {
+          double *mys = gs + ((int64_t)par * nw + w) * ldc;
+          for (int r = t + tid; r < c; r += CS_NT) st(mys + r, src[r]);
+        }
+        int ws = 0, b = -1;
+        const ArgMax am = group_argmax(wb, wa_idx, par, &ws, &b);
+        if (abort) return kk;
+        const bool remote = nw > 1 && ws != w;
+        if (remote) src = gs + ((int64_t)par * nw + ws) * ldc;
+        const double bn = sqrt(am.v);
+        if (pivoting) {
+          if (t == 0) {
+            r00 = bn;
+            if (!(r00 > 0.0)) break;
+          } else if (!(bn > A.tol * r00)) {
+            break;
+          }
+        }
+        const int bp = am.a;
+        if (bp < 0) break;
+        auto rd = [&](int r) -> double { return remote ? ld(src + r) : src[r]; };
+        const double xt = rd(t);
+        const double rtt = xt >= 0.0 ? -bn : bn;
+        const double vn = 2.0 * bn * (bn + fabs(xt));
+        const double rv = 2.0 / vn;
+        if (tid == 0) {
+          rdiag[t] = rtt;
+          piv[t] = b;
+        }
+        double v[RL];
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int r = CS_LPC * u + h;
+          v[u] = (r < t || r >= c) ? 0.0 : (r == t ? rd(r) - rtt : rd(r));
+        }
+        best = ArgMax{-1.0, -1};
+        bst = -1;
+#pragma unroll
+        for (int j = 0; j < DQ_CPG; j++) {
+          const int a = w * DQ_CPW + g + CS_NG * j;
+          const int la = lb[j];
+          const bool on0 = la >= 0;
+          const int na = a == b ? t : (la == t ? bp : la);  // positions t and bp swap
+          if (on0) lb[j] = na;
+          const bool on = on0 && na > t;  // not the pivot of this step or an earlier one
+          double w0 = 0.0, w1 = 0.0;
+#pragma unroll
+          for (int u = 0; u < RL; u += 2) {
+            w0 = fma(v[u], col[j][u], w0);
+            if (u + 1 < RL) w1 = fma(v[u + 1], col[j][u + 1], w1);
+          }
+          const double sc = g16_sum(w0 + w1);
+          const double scj = (on && vn > 0.0) ? sc * rv : 0.0;
+          double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+          for (int u = 0; u < RL; u++) {
+            const int r = CS_LPC * u + h;
+            const double y = fma(-scj, v[u], col[j][u]);
+            col[j][u] = y;
+            const double z = r > t ? y : 0.0;
+            if (u & 1)
+              s1 = fma(z, z, s1);
+            else
+              s0 = fma(z, z, s0);
+          }
+          const double nn = g16_sum(s0 + s1);
+          if (on) {
+            nr[j] = nn;
+            if (pivoting || na == t + 1) {
+              const ArgMax y = amax_pick(best, ArgMax{nn, na});
+              if (y.a == na && best.a != na) {
+                best = y;
+                bst = j;
+              }
+            }
+          }
+        }
+        kk = t + 1;
+      }
+      __syncthreads();
+      return kk;
+    };
+
+    build(false);
+    int k = qr(true, m < c ? m : c);
+    if (abort) break;
+    const int nr_ = m - k;
+    int nsw = 0;
+    bool failed = false;
+    int skel_before = 0;  // skeleton columns in the workgroups before this one
+    for (;;) {
+      // skeleton counts: this workgroup's, then the prefix over the group
+      {
+        int cnt = 0;
+#pragma unroll
+        for (int j = 0; j < DQ_CPG; j++) cnt += (lb[j] >= 0 && lb[j] < k && h == 0) ? 1 : 0;
+        int64_t tot;
+        (void)block_excl_scan_i64<CS_NW>(cnt, &tot, sred);
+        if (nw > 1) {
+          if (tid == 0) sti(gc + w, (int)tot);
+          if (!meet()) {
+            abort = true;
+            break;
+          }
+          if (tid == 0) {
+            int s = 0;
+            for (int q = 0; q < w; q++) s += ldi(gc + q);
+            sbase = s;
+          }
+          __syncthreads();
+          skel_before = sbase;
+        }
+      }
+      // exs: skeleton columns before each grid index (grid order = storage order)
+      {
+        // the group's columns in grid order: a = w DQ_CPW + g + CS_NG j, so
+        // order within the workgroup is (j, g); a block scan over
+        // (j, g) pairs in that order
+        int run = skel_before;
+#pragma unroll
+        for (int j = 0; j < DQ_CPG; j++) {
+          const int a = w * DQ_CPW + g + CS_NG * j;
+          const int is = (a < m && lb[j] < k && h == 0) ? 1 : 0;
+          int64_t tot;
+          const int ex = (int)block_excl_scan_i64<CS_NW>(is, &tot, sred);
+          // (lane h = 0 of group g holds the column's flag: the scan over
+          // threads in order is the scan over the groups in order)
+          if (a < m && h == 0) sti(D.exs + A.selo[i] + a, run + ex);
+          run += (int)tot;
+        }
+      }
+      if (!meet()) {
+        abort = true;
+        break;
+      }
+      if (k == 0 || nr_ == 0) break;
+      // R11 by columns into gR (each skeleton column's rows above its
+      // position), R_tt and the pivot order are known to every workgroup
+      for (int t = tid; t < k; t += CS_NT) rdg[t] = 1.0 / rdiag[t];
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        const int la = lb[j];
+        if (la < 0 || la >= k) continue;
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int r = CS_LPC * u + h;
+          if (r < la) st(gR + (int64_t)la * k + r, col[j][u]);
+        }
+      }
+      if (!meet()) {
+        abort = true;
+        break;
+      }
+      // back substitution in every column at once: a column at position
+      // j < k solves R11 x = e_j (a column of R11^-1), one at a position
+      // >= k solves R11 n = R12 e (a column of N, over its rows < k); R11
+      // passes through LDS, RC columns at a time, last columns first
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        const int la = lb[j];
+        if (la >= 0 && la < k) {
+#pragma unroll
+          for (int u = 0; u < RL; u++) col[j][u] = (CS_LPC * u + h) == la ? 1.0 : 0.0;
+        }
+      }
+      for (int j1 = k; j1 > 0; j1 -= RC) {
+        const int j0 = j1 - RC > 0 ? j1 - RC : 0;
+        __syncthreads();
+        for (int e2 = tid; e2 < (j1 - j0) * CMAX; e2 += CS_NT) {
+          const int jc = e2 / CMAX, r = e2 - jc * CMAX;
+          Lr[e2] = r < j0 + jc ? ld(gR + (int64_t)(j0 + jc) * k + r) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ub = RL - 1; ub >= 0; ub--) {
+          const int jlo = CS_LPC * ub > j0 ? CS_LPC * ub : j0;
+          const int jhi = CS_LPC * ub + CS_LPC < j1 ? CS_LPC * ub + CS_LPC : j1;
+          if (jlo >= jhi) continue;
+#pragma unroll 1
+          for (int jj = jhi - 1; jj >= jlo; jj--) {
+            const int hj = jj - CS_LPC * ub;
+            const double rdj = rdg[jj];
+            const double *Rc = Lr + (int64_t)(jj - j0) * CMAX;
+            double xv[DQ_CPG];
+#pragma unroll
+            for (int j = 0; j < DQ_CPG; j++) {
+              xv[j] = __shfl(col[j][ub], (lane & ~(CS_LPC - 1)) + hj, WAVE) * rdj;
+              if (h == hj) col[j][ub] = xv[j];
+            }
+#pragma unroll
+            for (int u = 0; u <= ub; u++) {
+              const int r = CS_LPC * u + h;
+              if (r < jj) {
+                const double rr = Rc[r];
+#pragma unroll
+                for (int j = 0; j < DQ_CPG; j++) col[j][u] = fma(-rr, xv[j], col[j][u]);
+              }
+            }
+          }
+        }
+      }
+      // R11^-1 by columns into gI; rinv_i = |row i of R11^-1| (a group per
+      // row, lane h summing the columns jc = h (mod 16), then the group sum)
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        const int la = lb[j];
+        if (la < 0 || la >= k) continue;
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int r = CS_LPC * u + h;
+          if (r < k) st(gI + (int64_t)la * k + r, col[j][u]);
+        }
+      }
+      if (!meet()) {
+        abort = true;
+        break;
+      }
+      for (int ii = g; ii < k; ii += CS_NG) {
+        double sq = 0.0;
+        for (int jc = h; jc < k; jc += CS_LPC) {
+          const double y = ld(gI + (int64_t)jc * k + ii);
+          sq = fma(y, y, sq);
+        }
+        sq = g16_sum(sq);
+        if (h == 0) rinv[ii] = sqrt(sq);
+      }
+      __syncthreads();
+      // rho^2 arg-max over (i, j): ties smallest j, then i (pair j k + i);
+      // G rows are written on every pass, the last leaves the final ones
+      ArgMax am{-1.0, -1};
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        const int a = w * DQ_CPW + g + CS_NG * j;
+        const int la = lb[j];
+        if (la < k) continue;  // (also the columns beyond m: la = -1)
+        const double gam = sqrt(nr[j]);
+        double *Gr = A.G_out + A.go[i] + (int64_t)(a - ldi(D.exs + A.selo[i] + a)) * k;
+        const int base = (la - k) * k;
+#pragma unroll
+        for (int u = 0; u < RL; u++) {
+          const int ii = CS_LPC * u + h;
+          if (ii < k) {
+            const double nv = col[j][u];
+            const double gw = gam * rinv[ii];
+            const double r2 = nv * nv + gw * gw;
+            am = amax_pick(am, ArgMax{r2, base + ii});
+            Gr[ldi(D.exs + A.selo[i] + piv[ii])] = nv;
+          }
+        }
+      }
+      am = block_argmax<CS_NW>(am, ared);
+      int ws_ = 0, wa_ = -1;
+      am = group_argmax(am, -1, 2, &ws_, &wa_);
+      if (abort) break;
+      if (!(sqrt(am.v) > A.f)) break;
+      if (++nsw > 64 * k) {
+        failed = true;
+        break;
+      }
+      const int bj = am.a / k, bi = am.a % k;
+#pragma unroll
+      for (int j = 0; j < DQ_CPG; j++) {
+        const int la = lb[j];
+        if (la == bi)
+          lb[j] = k + bj;
+        else if (la == k + bj)
+          lb[j] = bi;
+      }
+      __syncthreads();
+      build(true);
+      qr(false, k);
+      if (abort) break;
+    }
+    if (abort) break;
+    if (w == 0 && tid == 0 && nsw > 0) atomicAdd(A.swaps, nsw);
+    // canonical output: skeleton indices ascending, then the rest
+    int *sel = A.sel_out + A.selo[i];
+#pragma unroll
+    for (int j = 0; j < DQ_CPG; j++) {
+      const int a = w * DQ_CPW + g + CS_NG * j;
+      if (a >= m || h != 0) continue;
+      if (failed) {
+        sel[a] = a;
+      } else {
+        const int ex = ldi(D.exs + A.selo[i] + a);
+        if (lb[j] < k)
+          sel[ex] = a;
+        else
+          sel[k + (a - ex)] = a;
+      }
+    }
+    if (failed && w == 0 && tid == 0) atomicOr(A.err, 1);
+    if (w == 0 && tid == 0) A.k_out[i] = failed ? 0 : k;
+  }
+}
+
+// Positions of the level's wide-form nodes (sorted by decreasing grid) per
+// class: out[2q], out[2q+1] = [lo, hi) for class q = 0 (grids above
+// DQ_MAXW * DQ_CPW, left to the streaming form) and q = 1 + s for nw =
+// DQ_MAXW >> s (grids in (DQ_CPW * nw / 2, DQ_CPW * nw]; nw = 1: up to DQ_CPW).
+__global__ void k_dq_ranges(const int *order, const int *cnt, const int *m, int *out) {
+  constexpr int NC = 6;
+  const int n = *cnt;
+  if (threadIdx.x != 0) return;
+  int e = 0;
+  for (int q = 0; q < NC; q++) {
+    // upper bound of class q's grids (class 0: none)
+    const int lim = q == 0 ? DQ_MAXW * DQ_CPW : (DQ_MAXW >> (q - 1)) * DQ_CPW / 2;
+    const int lo = e;
+    if (q == NC - 1) {
+      e = n;
+    } else {
+      while (e < n && m[order[e]] > lim) e++;
+    }
+    out[2 * q] = lo;
+    out[2 * q + 1] = e;
   }
 }
 
@@ -2064,7 +2684,8 @@ void build_generators(Handle &h) {
         // the wide form: basis rows up to cw, tile columns of ldc rows; the
         // LDS left after its fixed parts holds the tile of grids of up to
         // lds_cols points
-        const int cw = cmax <= 64 ? 64 : cmax <= 128 ? 128 : cmax <= 256 ? 256 : 512;
+        // (224: the 6^3-point basis of 3D p = 6 without a sixth of idle rows)
+        const int cw = cmax <= 64 ? 64 : cmax <= 128 ? 128 : cmax <= 224 ? 224 : cmax <= 256 ? 256 : 512;
         const int ldc = (cmax + 15) / 16 * 16;
         const size_t st_lds = sizeof(double) * (5 * ID_PMAX + 3 * cw) +
                               sizeof(int) * (cw + 2 * CS_NW) + sizeof(ArgMax) * (3 * CS_NW + 1) +
@@ -2113,10 +2734,51 @@ void build_generators(Handle &h) {
           switch (cw) {
             case 64: k_compr_s<64><<<grid, CS_NT, shs, s>>>(a, b); break;
             case 128: k_compr_s<128><<<grid, CS_NT, shs, s>>>(a, b); break;
+            case 224: k_compr_s<224><<<grid, CS_NT, shs, s>>>(a, b); break;
             case 256: k_compr_s<256><<<grid, CS_NT, shs, s>>>(a, b); break;
             default: k_compr_s<512><<<grid, CS_NT, shs, s>>>(a, b); break;
           }
           SMASH_CHECK_LAUNCH();
+        };
+        // the register QR of k_compr_dq: resident workgroups (cooperative
+        // launch) and the groups' exchange areas
+        const int dq_rc = cw <= 224 ? 64 : 48;  // (RC of k_compr_dq)
+        const size_t shd = sizeof(double) * ((size_t)CS_NG * h.d * h.p + (size_t)dq_rc * cw);
+        int dq_cap = 0;
+        double *dq_slot = nullptr, *dq_R = nullptr, *dq_I = nullptr;
+        DqMeta *dq_meta = nullptr;
+        int *dq_gc = nullptr;
+        unsigned *dq_cnt = nullptr;
+        auto dq_kernel = [&]() -> const void * {
+          switch (cw) {
+            case 64: return (const void *)k_compr_dq<64>;
+            case 128: return (const void *)k_compr_dq<128>;
+            case 224: return (const void *)k_compr_dq<224>;
+            case 256: return (const void *)k_compr_dq<256>;
+            default: return nullptr;
+          }
+        };
+        if (h.batched && !all_reg && dq_kernel()) {
+          int per_cu = 0;
+          if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, dq_kernel(), CS_NT, shd) ==
+                  hipSuccess &&
+              per_cu > 0 && per_cu * dev_cus >= 8 * DQ_MAXW) {
+            dq_cap = per_cu * dev_cus;
+            dq_slot = tmp.alloc_n<double>((size_t)2 * dq_cap * ldc);
+            dq_meta = tmp.alloc_n<DqMeta>((size_t)3 * dq_cap);
+            dq_R = tmp.alloc_n<double>((size_t)dq_cap * cw * cw);
+            dq_I = tmp.alloc_n<double>((size_t)dq_cap * cw * cw);
+            dq_gc = tmp.alloc_n<int>((size_t)dq_cap);
+            dq_cnt = tmp.alloc_n<unsigned>((size_t)dq_cap);
+          } else {
+            (void)hipGetLastError();
+          }
+        }
+        auto launch_dq = [&](const IdArgs &a, const DqArgs &b, int grid) {
+          IdArgs a1 = a;
+          DqArgs b1 = b;
+          void *args[] = {&a1, &b1};
+          SMASH_HIP(hipLaunchCooperativeKernel(dq_kernel(), dim3(grid), dim3(CS_NT), args, shd, s));
         };
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
         if (h.batched) {
@@ -2134,7 +2796,30 @@ void build_generators(Handle &h) {
             radix_sort_u64(keys, vals, kalt, valt, nl, 17, s, tmp);
             cs.order = vals;
             cs.cnt = big;
-            launch_wide(ia, cs, wgrid);
+            if (cw <= 256 && dq_cap > 0) {
+              // the strong RRQR with the columns in registers (grids of up to
+              // 2048 points, split over 1-16 workgroups by size); larger
+              // grids take the streaming form
+              int *exsv = tmp.alloc_n<int>((size_t)L.sel_n);
+              int *rng = tmp.alloc_n<int>(12);
+              k_dq_ranges<<<1, 64, 0, s>>>(vals, big, S.m, rng);
+              SMASH_CHECK_LAUNCH();
+              CsArgs c0 = cs;
+              c0.first = rng;
+              c0.cnt = rng + 1;
+              launch_wide(ia, c0, wgrid);
+              DqArgs da{vals, nullptr, 0, ldc, exsv, dq_slot, dq_meta, dq_R, dq_I, cw * cw,
+                        dq_gc, dq_cnt, (int64_t)200000000};
+              for (int q = 1; q <= 5; q++) {
+                da.nw = DQ_MAXW >> (q - 1);
+                da.range = rng + 2 * q;
+                const int ngrp = 8 * (dq_cap / (8 * da.nw));
+                SMASH_HIP(hipMemsetAsync(dq_cnt, 0, sizeof(unsigned) * ngrp, s));
+                launch_dq(ia, da, ngrp * da.nw);
+              }
+            } else {
+              launch_wide(ia, cs, wgrid);
+            }
             if (reg_ok) {
               ir.order = vals;
               ir.ord_lo = big;
@@ -2220,6 +2905,8 @@ void build_generators(Handle &h) {
       h.nleaves = (int)pin[4];
       h.b_entries = pin[5];
     }
+    if (herr[1] & 2)
+      throw Error{SMASH_E_DEVICE, "compr: the workgroups of a node did not meet in time"};
     if (herr[1]) throw Error{SMASH_E_NUMERIC, "strong RRQR swap cap reached"};
     h.total_swaps = herr[0];
     // apply copies
