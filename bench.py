@@ -42,10 +42,11 @@ FP64_PEAK_TFLOPS = 78.6
 FP32_PEAK_TFLOPS = 157.3
 
 
-def stored_traffic(workload, kernel):
+def stored_traffic(workload, kernel, calls=1.0):
     """HBM bytes per launch of `kernel` from the counter summary under
-    profiles/ -- None when absent or when its source file has changed since
-    the counters were taken."""
+    profiles/ (for compr, the bytes of one construction over its `calls`
+    launch groups) -- None when absent or when its source file has changed
+    since the counters were taken."""
     path = os.path.join(ROOT, "profiles", workload + "_traffic.json")
     if not os.path.exists(path):
         return None
@@ -57,7 +58,9 @@ def stored_traffic(workload, kernel):
     with open(os.path.join(ROOT, ent["source"]), "rb") as g:
         if hashlib.sha256(g.read()).hexdigest() != ent["source_sha256"]:
             return None
-    return ent["bytes_per_launch"]
+    if "bytes_per_launch" in ent:
+        return ent["bytes_per_launch"]
+    return ent["bytes_per_build"] / max(calls, 1.0)
 
 
 def kwargs_of(cfg):
@@ -324,7 +327,7 @@ def main():
                 "exact_householder_flops_per_build": compr_exact}
         roof["achieved"] = compr_simple / (ph["compr"] * 1e-3) / 1e12
         roof["achieved_exact_count"] = compr_exact / (ph["compr"] * 1e-3) / 1e12
-        roof["traffic"] = stored_traffic(args.workload, "compr")
+        roof["traffic"] = stored_traffic(args.workload, "compr", calls["compr"])
     elif dominant == "mv_coupling":
         fp = FP64_PEAK_TFLOPS if f64 else FP32_PEAK_TFLOPS
         roof = {"kernel": "k_mv_coupling_eval (blocks evaluated in the contraction, %s MFMA)"
