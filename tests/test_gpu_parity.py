@@ -48,6 +48,11 @@ CASES = {
     "h2_3d_p4_split": (lambda: (W.clusters(9000, 3, 9), None),
                        dict(kernel="inv_r", leaf=128, order=4, adm="strong", tol=1e-7, tau=0.7,
                             root=((0.0, 0.0, 0.0), 1.0))),
+    # swap bound f close to 1: Gu-Eisenstat swaps in many nodes, whose grids
+    # (up to 8 x 125 points) split over several workgroups in k_compr_dq
+    "h2_3d_swaps": (lambda: (W.clusters(6000, 3, 12), None),
+                    dict(kernel="inv_r", leaf=128, order=5, adm="strong", tol=1e-6, tau=0.7,
+                         f=1.05, root=((0.0, 0.0, 0.0), 1.0))),
     "h2_1d_exp": (lambda: (W.uniform(3000, 1, 8), None),
                   dict(kernel="exp_r", leaf=40, order=9, adm="strong", tol=1e-10, tau=0.6)),
     "hss_cauchy_xy": (lambda: W.chebyshev_pair(3000, 4),
@@ -90,6 +95,19 @@ def pair_for(name):
         g = api.Smash(dev(x), None if y is None else dev(y), **_gpu_kwargs(kw))
         _cache[name] = (x, y, o, g)
     return _cache[name]
+
+
+def test_swap_case_swaps_in_split_grids():
+    """The f = 1.05 case exercises the swap path of the register-resident
+    compr: swaps happen, and some grids exceed one workgroup's 128 columns
+    (its skeletons and G are checked against the oracle by the tests
+    parametrized over the cases)."""
+    x, y, o, g = pair_for("h2_3d_swaps")
+    inf = g.info()
+    m = g.export("ranks").reshape(-1, 6)[:, 0]
+    print("swaps", inf["total_swaps"], "largest grid", int(m.max()), flush=True)
+    assert inf["total_swaps"] > 0
+    assert m.max() > 128
 
 
 @pytest.mark.parametrize("name", list(CASES))
