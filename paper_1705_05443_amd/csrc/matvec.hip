@@ -1181,11 +1181,15 @@ static bool ensure_workspace(Handle &h, int nrhs, hipStream_t s) {
   const int chunk = nrhs < RC ? nrhs : RC;
   const int cp = (chunk + 15) / 16 * 16;
   if (h.ws_nrhs >= cp) return false;
+  // the captured products hold the old buffers: they go first
+  drop_graphs(h);
   // earlier products (on any stream) may still read the old buffers: wait
   // for the last of them (they are ordered by prod_done), then give the
   // buffers back as idle memory
   if (h.prod_done && h.ws_nrhs > 0) SMASH_HIP(hipEventSynchronize(h.prod_done));
   h.ws_mem.release(true);
+  h.ws_nrhs = 0;  // (a failed allocation below leaves no buffer behind)
+  h.qbuf = h.zbuf = nullptr;
   h.ws_mem.stream = s;
   h.qbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.col->nslots * cp);
   h.zbuf = h.ws_mem.alloc(sizeof(double) * (size_t)h.row.nslots * cp);
@@ -1263,7 +1267,7 @@ void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_
 
 static void run_matvec_on(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                           hipStream_t s) {
-  if (ensure_workspace(h, nrhs, s)) drop_graphs(h);
+  ensure_workspace(h, nrhs, s);
   if (!h.use_graphs || h.timing) {
     launch_sequence(h, X, ldx, nrhs, Y, ldy, s);
     return;

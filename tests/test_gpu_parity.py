@@ -764,6 +764,62 @@ def test_allocator_hooks_take_every_device_allocation():
     g.close()
 
 
+def test_allocation_failure_reports_oom_and_frees_everything():
+    """A device allocation that fails in the middle of a construction (the
+    allocator hook returns NULL at its first, a middle and its last call)
+    ends the build with SMASH_E_OOM, and every allocation granted before it
+    is given back; a product whose workspace allocation fails reports the
+    same and leaves the handle usable."""
+    import torch
+    x = W.clusters(6000, 3, 12)
+    kw = dict(kernel="inv_r", leaf=128, order=5, adm="strong", tol=1e-6, tau=0.7,
+              root=((0.0, 0.0, 0.0), 1.0))
+    talloc, tfree = api.torch_allocator_hooks()
+    state = {"calls": 0, "fail_at": -1, "live": {}}
+
+    def _alloc(ctx, n, s):
+        state["calls"] += 1
+        if state["calls"] == state["fail_at"]:
+            return None
+        p = talloc(ctx, n, s)
+        if p:
+            state["live"][p] = n
+        return p
+
+    def _free(ctx, p, n, s):
+        assert state["live"].pop(p) == n
+        tfree(ctx, p, n, s)
+
+    hooks = (api.ALLOC_FN(_alloc), api.FREE_FN(_free))
+    X = dev(x)
+    h = api.Smash(X, allocator=hooks, **kw)  # count the calls of a whole build
+    total = state["calls"]
+    q = torch.from_numpy(np.random.default_rng(3).standard_normal((6000, 8))).cuda()
+    z_ok = h.matvec(q).cpu().numpy()
+    h.close()
+    assert not state["live"] and total > 2
+    for fail_at in (1, total // 2, total):
+        state.update(calls=0, fail_at=fail_at)
+        print("build, allocation %d of %d fails" % (fail_at, total), flush=True)
+        with pytest.raises(api.SmashError) as e:
+            api.Smash(X, allocator=hooks, **kw)
+        assert e.value.code == -3, str(e.value)  # SMASH_E_OOM
+        torch.cuda.synchronize()
+        assert not state["live"], len(state["live"])
+    # a product whose workspace allocation fails
+    state.update(calls=0, fail_at=-1)
+    h = api.Smash(X, allocator=hooks, **kw)
+    state.update(calls=0, fail_at=1)
+    with pytest.raises(api.SmashError) as e:
+        h.matvec(torch.from_numpy(np.random.default_rng(4).standard_normal((6000, 40))).cuda())
+    assert e.value.code == -3, str(e.value)
+    state.update(fail_at=-1)
+    assert np.array_equal(h.matvec(q).cpu().numpy(), z_ok)
+    h.close()
+    torch.cuda.synchronize()
+    assert not state["live"]
+
+
 def test_levels_wider_than_one_workgroup():
     """Tree levels of more than 4096 nodes take the multi-workgroup form of
     the level bookkeeping (sizes, capacities, slot offsets) instead of the

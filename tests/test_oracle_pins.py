@@ -786,3 +786,32 @@ def test_double_layer_hss_oracle_matches_dense():
         for _, _, G in o.per_node(side):
             if G.size:
                 assert np.max(np.abs(G)) <= 2.0 * (1 + 1e-12)
+
+
+def test_oracle_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path):
+    """The oracle compiled with AddressSanitizer (leak detection on) and
+    UndefinedBehaviorSanitizer runs every kernel, both admissibilities,
+    distinct sets, the double-layer data and a swap-heavy bound with no
+    report, and each product matches the dense one
+    (tests/oracle_sanitize_driver.c)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = str(tmp_path / "oracle_asan")
+    cmd = [gcc, "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-ffp-contract=off", "-fopenmp",
+           os.path.join(here, "..", "oracle", "smash_oracle.c"),
+           os.path.join(here, "oracle_sanitize_driver.c"), "-o", exe, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and "asan" in (r.stderr or "").lower():
+        pytest.skip("sanitizer runtime not available: " + r.stderr[-200:])
+    assert r.returncode == 0, r.stderr
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1", OMP_NUM_THREADS="2")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=600)
+    print(r.stdout)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "all cases clean" in r.stdout
+    assert "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stderr
