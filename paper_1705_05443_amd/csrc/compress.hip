@@ -733,6 +733,14 @@ struct CsArgs {
   const int *first;  // device: the launch takes order[*first, *cnt) (null: from 0)
 };
 
+// the same inside a group of 8 lanes (a DPP half row)
+__device__ __forceinline__ double g8_sum(double x) {
+  x += perm_f64<0xB1>(x);   // quad_perm [1,0,3,2]
+  x += perm_f64<0x4E>(x);   // quad_perm [2,3,0,1]
+  x += perm_f64<0x141>(x);  // row_half_mirror: the other quad of the half row
+  return x;
+}
+
 // sums, maxima and broadcasts inside a group of 16 lanes (one DPP row);
 // every lane of the group ends with the same bits
 __device__ __forceinline__ double g16_sum(double x) {
@@ -2134,11 +2142,10 @@ __global__ void __launch_bounds__(SV_NT) k_near_svd(SvdArgs A, int mpx, int ldl)
               ga = fma(x, y, ga);
             }
           }
-          for (int o = SV_G / 2; o > 0; o >>= 1) {
-            al += __shfl_xor(al, o, SV_G);
-            be += __shfl_xor(be, o, SV_G);
-            ga += __shfl_xor(ga, o, SV_G);
-          }
+          static_assert(SV_G == 8, "pair sums are 8-lane DPP sums");
+          al = g8_sum(al);
+          be = g8_sum(be);
+          ga = g8_sum(ga);
           if (al == 0.0 || be == 0.0) continue;
           if (fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
           if (gl == 0) any_rot = 1;
