@@ -237,6 +237,9 @@ def main():
                     help="requests per offered load in the serving trace (0: skip)")
     ap.add_argument("--serve-nmax", type=float, default=1e6,
                     help="largest N of the serving trace")
+    ap.add_argument("--serve-only", default="",
+                    help="only run the serving section and write its results as JSON to "
+                         "this path (the main run starts itself this way)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -244,6 +247,12 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.serve_only:
+        res = serve_bench(args, torch)
+        with open(args.serve_only, "w") as f:
+            json.dump(res, f)
+        return
 
     if args.copy_mib > 0:
         a = torch.empty(args.copy_mib << 17, dtype=torch.float64, device="cuda").fill_(1.0)
@@ -453,8 +462,33 @@ def main():
     # ---- serving: continuous batching at three offered loads --------------
     if args.serve_requests > 0:
         print("serving", flush=True)
-        out["serve"] = serve_bench(args, torch)
+        out["serve"] = serve_in_child(args, torch, api)
     print(json.dumps(out), flush=True)
+
+
+def serve_in_child(args, torch, api):
+    """The serving section in a process of its own (it runs several streams
+    of constructions and products at once): its results, or, if it fails,
+    its exit status, without ending the measurement above."""
+    import subprocess
+    import tempfile
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    api.trim()
+    fd, path = tempfile.mkstemp(suffix=".json")
+    os.close(fd)
+    cmd = [sys.executable, "-u", os.path.abspath(__file__), "--serve-only", path,
+           "--serve-requests", str(args.serve_requests), "--serve-nmax", repr(args.serve_nmax)]
+    try:
+        rc = subprocess.run(cmd, timeout=1500).returncode
+        if rc != 0:
+            return {"error": "serving process exited with status %d" % rc}
+        with open(path) as f:
+            return json.load(f)
+    except subprocess.TimeoutExpired:
+        return {"error": "serving process exceeded 1500 s"}
+    finally:
+        os.unlink(path)
 
 
 def double_layer_bench(torch, api, W):
@@ -521,9 +555,14 @@ def serve_bench(args, torch):
     api.trim()
     free, total = torch.cuda.mem_get_info()
     budget = int(min(0.8 * total, 0.85 * free))
+    # torch's allocator (handles and vectors, its cache of freed blocks
+    # included) stays within this share of the device; the rest is left to
+    # the runtime (scratch memory of the kernels that spill, queues, events)
+    fraction = min(0.85, 0.9 * free / total)
+    torch.cuda.reset_peak_memory_stats()
 
     def run(slots, cap, trace, keep=None):
-        ex = serve.GpuExecutor(slots=slots, allocator="torch")
+        ex = serve.GpuExecutor(slots=slots, allocator="torch", memory_fraction=fraction)
         eng = serve.Engine(ex, budget_bytes=budget, slots=slots, max_batch_rhs=cap)
         done = eng.run(trace)
         st = serve.latency_stats(done)
@@ -551,15 +590,18 @@ def serve_bench(args, torch):
     nreq = args.serve_requests
     run(4, 64, serve.make_trace(4, rate_hz=100.0, n_range=(1e4, 3e4), seed=99,
                                 apply_prec="f64"))  # warm-up
+    print("serve warm-up done", flush=True)
     # capacity of the plain form: the whole trace offered at once
     cap = run(1, 1, trace(nreq, 1e6))
     capacity = cap["requests_per_s"]
+    print("serve capacity %.2f requests/s" % capacity, flush=True)
     res = {"trace": "%d requests per load, N log-uniform [1e4, %.0e], dim 2/3, "
                     "uniform/clustered, log r / 1/r / exp(-r), 1-32 FP32 RHS (FP64 products), "
                     "tol 1e-6, Chebyshev points per axis %s by dimension, 30%% products on "
                     "resident matrices, Poisson arrivals" % (nreq, args.serve_nmax,
                                                              serve.SERVE_ORDER),
-           "plain_capacity_requests_per_s": capacity, "budget_GB": budget / 1e9, "loads": {}}
+           "plain_capacity_requests_per_s": capacity, "budget_GB": budget / 1e9,
+           "torch_memory_fraction": fraction, "loads": {}}
     for load in (0.5, 0.8, 1.0):
         rate = load * capacity
         kept = [] if load == 1.0 else None
@@ -583,6 +625,7 @@ def serve_bench(args, torch):
                      "rel_err_vs_exact_rows":
                          float(np.linalg.norm(r.result[rows] - zr) / np.linalg.norm(zr))})
     res["accuracy"] = errs
+    res["torch_peak_reserved_GB"] = torch.cuda.max_memory_reserved() / 1e9
     return res
 
 

@@ -20,6 +20,7 @@
 // downdating), the arg-max is a DPP reduction, and ties go to the lowest
 // position.  All arithmetic is FP64.
 #include <algorithm>
+#include <mutex>
 
 #include "common.cuh"
 
@@ -1265,14 +1266,47 @@ __global__ void __launch_bounds__(CS_NT) k_compr_s(IdArgs A, CsArgs B) {
 // (its best column and candidate, its columns of R11 and R11^-1, its
 // skeleton count, its rho candidate) through device-coherent atomic
 // accesses, and a counter per group of nw workgroups, incremented once a
-// workgroup's accesses have completed, tells when all have.  The launch is
-// cooperative (every workgroup resident) and the workgroups of a group sit
-// on one XCD; a wait longer than spin_limit ticks of the 100 MHz clock
-// gives up with the error flag instead of hanging.
+// workgroup's accesses have completed, tells when all have.  A grid holds
+// at most the workgroups the device keeps resident, the workgroups of a
+// group sit on one XCD, consecutive in its dispatch order, and one grid runs
+// at a time (launch_dq_chained); a wait longer than spin_limit ticks of the
+// 100 MHz clock gives up with the error flag instead of hanging.
 // ------------------------------------------------------------------------
 constexpr int DQ_CPG = 4;               // columns per 16-lane group
 constexpr int DQ_CPW = CS_NG * DQ_CPG;  // columns per workgroup
 constexpr int DQ_MAXW = 16;             // workgroups per node, at most
+
+// The workgroups of a group wait for each other, so each group must be
+// resident as a whole.  A grid holds at most as many workgroups as the
+// device keeps resident at once, a group's workgroups are consecutive in the
+// dispatch order of one XCD, and workgroups are dispatched in order: only the
+// last dispatched group can be partly resident, every group before it is
+// whole and finishes, and its slots go to the rest.  That holds while no
+// other grid of k_compr_dq occupies the device, which constructions on
+// several streams would otherwise do; so every such launch of the process on
+// a device waits for the previous one (an event recorded after each, waited
+// on by the next launch's stream), whatever stream it comes from.  Other
+// kernels on other streams only delay a group: they never wait for it.
+struct LaunchChain {
+  std::mutex mu;
+  hipEvent_t last[64] = {};
+};
+static LaunchChain dq_chain;
+
+// launches `kernel` on s after every earlier launch through this function on
+// `device` (the caller's current device)
+static void launch_dq_chained(int device, const void *kernel, int grid, int threads, void **args,
+                              size_t shmem, hipStream_t s) {
+  if (device < 0 || device >= 64) throw Error{SMASH_E_UNSUPPORTED, "device index above 63"};
+  std::lock_guard<std::mutex> lock(dq_chain.mu);
+  hipEvent_t &ev = dq_chain.last[device];
+  if (!ev)
+    SMASH_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  else
+    SMASH_HIP(hipStreamWaitEvent(s, ev, 0));
+  SMASH_HIP(hipLaunchKernel(kernel, dim3(grid), dim3(threads), args, shmem, s));
+  SMASH_HIP(hipEventRecord(ev, s));
+}
 
 struct DqMeta {
   double v;  // candidate value (-1: none)
@@ -2747,8 +2781,8 @@ void build_generators(Handle &h) {
           }
           SMASH_CHECK_LAUNCH();
         };
-        // the register QR of k_compr_dq: resident workgroups (cooperative
-        // launch) and the groups' exchange areas
+        // the register QR of k_compr_dq: at most the resident workgroups of
+        // the device per launch, and the groups' exchange areas
         const int dq_rc = cw <= 224 ? 64 : 48;  // (RC of k_compr_dq)
         const size_t shd = sizeof(double) * ((size_t)CS_NG * h.d * h.p + (size_t)dq_rc * cw);
         int dq_cap = 0;
@@ -2785,7 +2819,7 @@ void build_generators(Handle &h) {
           IdArgs a1 = a;
           DqArgs b1 = b;
           void *args[] = {&a1, &b1};
-          SMASH_HIP(hipLaunchCooperativeKernel(dq_kernel(), dim3(grid), dim3(CS_NT), args, shd, s));
+          launch_dq_chained(h.device, dq_kernel(), grid, CS_NT, args, shd, s);
         };
         PhaseTimer pt(h, SMASH_PHASE_COMPR, s);
         if (h.batched) {

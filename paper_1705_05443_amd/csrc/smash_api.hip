@@ -14,6 +14,7 @@ static thread_local std::string g_last_error;
 
 static int fail(int code, const std::string &msg) {
   g_last_error = msg;
+  (void)hipGetLastError();  // a failed HIP call stays this thread's last error otherwise
   return code;
 }
 

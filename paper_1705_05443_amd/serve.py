@@ -353,11 +353,17 @@ class GpuExecutor:
     threads, each with its own HIP stream (default priority).  allocator
     "torch": every handle takes its device memory from torch's caching
     allocator (smash_options alloc/free hooks), so torch's accounting covers
-    the resident matrices as well as the vectors."""
+    the resident matrices as well as the vectors.  memory_fraction: the
+    share of the device torch's allocator may hold, freed blocks it keeps
+    cached included (the engine's budget counts only what the handles and
+    vectors use); the rest stays free for the runtime's own allocations,
+    such as the scratch memory of kernels that spill registers."""
 
-    def __init__(self, slots=4, prior_ratios=None, allocator=None):
+    def __init__(self, slots=4, prior_ratios=None, allocator=None, memory_fraction=None):
         import torch
         self.torch = torch
+        if memory_fraction is not None:
+            torch.cuda.set_per_process_memory_fraction(float(memory_fraction))
         self.pool = ThreadPoolExecutor(max_workers=slots)
         self.local = threading.local()
         self.prior = prior_ratios or {}

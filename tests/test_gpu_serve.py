@@ -70,3 +70,52 @@ def test_serving_falls_back_to_evaluated_coupling():
         err = np.linalg.norm(r.result - z) / np.linalg.norm(z)
         assert err < 1e-5, (r.rid, err)
     h.close()
+
+
+def test_concurrent_constructions_match_one_stream():
+    """Four constructions at once, each on a stream of its own (the register
+    compr of every level is a grid of up to the device's resident workgroups
+    whose groups wait for each other, so these launches are ordered across
+    the streams), give the skeletons, ranks and product of the same
+    construction made alone, bit for bit, over three rounds."""
+    import threading
+
+    from paper_1705_05443_amd import workloads as W
+    kw = dict(kernel="inv_r", leaf=128, order=6, adm="strong", tol=1e-7, tau=0.7,
+              root=((0.0, 0.0, 0.0), 1.0), graphs=False)
+    sets = [W.clusters(12000 + 4000 * j, 3, seed=20 + j) for j in range(4)]
+    qs = [W.rhs(x.shape[0], 4, seed=j) for j, x in enumerate(sets)]
+
+    def one(j, stream):
+        with torch.cuda.stream(stream):
+            h = api.Smash(torch.from_numpy(sets[j]).cuda(), stream=stream, **kw)
+            z = h.matvec(torch.from_numpy(qs[j]).cuda(), stream=stream)
+            stream.synchronize()
+            out = (h.export("ranks").copy(), h.export("row_sel").copy(), z.cpu().numpy())
+            h.close()
+        return out
+
+    alone = [one(j, torch.cuda.current_stream()) for j in range(4)]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    for rnd in range(3):
+        got = [None] * 4
+        errs = []
+        start = threading.Barrier(4)
+
+        def work(j):
+            try:
+                start.wait()
+                got[j] = one(j, streams[j])
+            except Exception as e:  # reported below
+                errs.append((j, repr(e)))
+
+        ts = [threading.Thread(target=work, args=(j,)) for j in range(4)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        print("round", rnd, "errors", errs, flush=True)
+        assert not errs, errs
+        for j in range(4):
+            for a, b in zip(alone[j], got[j]):
+                assert np.array_equal(a, b), (rnd, j)
