@@ -74,6 +74,11 @@ def lib():
         L.oracle_dense_matvec.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int,
                                           C.c_double, dp, dp, dp, C.c_int64, dp]
         L.oracle_dense_matvec.restype = None
+        L.oracle_cauchy_like_dense.argtypes = [dp, C.c_int64, dp, C.c_int64, dp, dp, C.c_int,
+                                               dp, C.c_int64, dp]
+        L.oracle_cauchy_like_dense.restype = None
+        L.oracle_cauchy_like_matvec.argtypes = [C.c_void_p, dp, dp, C.c_int, dp, C.c_int64, dp]
+        L.oracle_cauchy_like_matvec.restype = C.c_int
         L.oracle_dense_rows.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int,
                                         C.c_double, dp, dp, C.POINTER(C.c_int64), C.c_int64,
                                         dp, C.c_int64, dp]
@@ -217,6 +222,21 @@ class Oracle:
             raise OracleError("oracle_matvec failed with code %d" % rc)
         return Z[:, 0] if vec else Z
 
+    def cauchy_like_matvec(self, w, v, Q):
+        """sum_l w_l o (C-hat (v_l o Q)) over the generator columns l (eq. (6.2)),
+        C-hat this handle's approximation; w: (nx, p), v: (ny, p)."""
+        w, v = np.ascontiguousarray(_f64(w)), np.ascontiguousarray(_f64(v))
+        Q = _f64(Q)
+        vec = Q.ndim == 1
+        Q = np.ascontiguousarray(Q[:, None] if vec else Q)
+        p = w.shape[1]
+        Z = np.zeros((self.x.shape[0], Q.shape[1]))
+        rc = lib().oracle_cauchy_like_matvec(self._h, _dp(w), _dp(v), p, _dp(Q), Q.shape[1],
+                                             _dp(Z))
+        if rc != 0:
+            raise OracleError("oracle_cauchy_like_matvec failed with code %d" % rc)
+        return Z[:, 0] if vec else Z
+
     def per_node(self, side="row"):
         """List of (grid, sel, G) per node (root entry is empty)."""
         rk = self.ranks()
@@ -255,6 +275,20 @@ def dense_matvec(x, y, Q, kernel="inv_r", diag=None, data_x=None, data_y=None):
     Z = np.zeros((x.shape[0], Q.shape[1]))
     lib().oracle_dense_matvec(_dp(x), x.shape[0], _dp(y), y.shape[0], x.shape[1], kid,
                               float(diag), _dp(data_x), _dp(data_y), _dp(Q), Q.shape[1], _dp(Z))
+    return Z[:, 0] if vec else Z
+
+
+def cauchy_like_dense(x, y, w, v, Q):
+    """Exact A Q for the Cauchy-like matrix of eq. (6.1): a_ij = sum_l w_il v_jl /
+    (x_i - y_j), points on the real line; w: (nx, p), v: (ny, p)."""
+    x, y = np.ascontiguousarray(_f64(x).ravel()), np.ascontiguousarray(_f64(y).ravel())
+    w, v = np.ascontiguousarray(_f64(w)), np.ascontiguousarray(_f64(v))
+    Q = _f64(Q)
+    vec = Q.ndim == 1
+    Q = np.ascontiguousarray(Q[:, None] if vec else Q)
+    Z = np.zeros((x.shape[0], Q.shape[1]))
+    lib().oracle_cauchy_like_dense(_dp(x), x.shape[0], _dp(y), y.shape[0], _dp(w), _dp(v),
+                                   w.shape[1], _dp(Q), Q.shape[1], _dp(Z))
     return Z[:, 0] if vec else Z
 
 

@@ -21,6 +21,7 @@
  *                               (3.16)-(3.18)
  *   coupling / near blocks      eqs. (3.15), (3.19), (3.20)
  *   matrix-vector product       Sec. 3.4, node-wise steps 1-3
+ *   Cauchy-like product         eqs. (6.1), (6.2)
  *
  * Readings of points the paper leaves open are fixed here and listed with
  * the repository's design notes; each is named where it is used.
@@ -1506,6 +1507,53 @@ void oracle_dense_matvec(const double *x, int64_t nx, const double *y, int64_t n
       for (int64_t r = 0; r < R; r++) za[r] += v * Q[b * R + r];
     }
   }
+}
+
+/* Cauchy-like matrix with generators w (nx x p) and v (ny x p), row-major,
+ * eq. (6.1): a_ij = kappa(x_i, y_j) * sum_l w_il v_jl with the 1/(x - y)
+ * kernel (kid 3, d = 1) on the real line; Z = A Q (original order). */
+void oracle_cauchy_like_dense(const double *x, int64_t nx, const double *y, int64_t ny,
+                              const double *w, const double *v, int p, const double *Q,
+                              int64_t R, double *Z) {
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < nx; a++) {
+    double *za = Z + a * R;
+    for (int64_t r = 0; r < R; r++) za[r] = 0.0;
+    for (int64_t b = 0; b < ny; b++) {
+      double g = 0.0;
+      for (int l = 0; l < p; l++) g += w[a * p + l] * v[b * p + l];
+      const double e = kernel_value(3, x + a, y + b, 1, 0.0, NULL, NULL) * g;
+      for (int64_t r = 0; r < R; r++) za[r] += e * Q[b * R + r];
+    }
+  }
+}
+
+/* The same product through the SMASH approximation C-hat of the Cauchy
+ * matrix held by hv, by eq. (6.2): A = sum_l diag(w_l) C diag(v_l), so
+ * Z = sum_l w_l o (C-hat (v_l o Q)), the terms added for l = 0, 1, ... */
+int oracle_cauchy_like_matvec(void *hv, const double *w, const double *v, int p,
+                              const double *Q, int64_t R, double *Z) {
+  oracle_t *h = (oracle_t *)hv;
+  double *ql = (double *)malloc(sizeof(double) * ((size_t)h->ny * R + 1));
+  double *zl = (double *)malloc(sizeof(double) * ((size_t)h->nx * R + 1));
+  if (!ql || !zl) {
+    free(ql);
+    free(zl);
+    return OR_ENOMEM;
+  }
+  for (int64_t a = 0; a < (int64_t)h->nx * R; a++) Z[a] = 0.0;
+  int rc = 0;
+  for (int l = 0; l < p && rc == 0; l++) {
+    for (int64_t b = 0; b < h->ny; b++)
+      for (int64_t r = 0; r < R; r++) ql[b * R + r] = v[b * p + l] * Q[b * R + r];
+    rc = oracle_matvec(hv, ql, R, zl);
+    if (rc != 0) break;
+    for (int64_t a = 0; a < h->nx; a++)
+      for (int64_t r = 0; r < R; r++) Z[a * R + r] = Z[a * R + r] + w[a * p + l] * zl[a * R + r];
+  }
+  free(ql);
+  free(zl);
+  return rc;
 }
 
 /* rows[0..nrows) of A Q (exact), for sampled checks at large n. */

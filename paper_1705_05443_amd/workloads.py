@@ -47,6 +47,22 @@ def chebyshev_pair(n: int, seed: int = 0, shift: float = 1e-3, shift_x: bool = F
     return roots[:, None].copy(), moved[:, None].copy()
 
 
+def interlaced_pair(n: int, seed: int = 0, shift: float = 1e-7):
+    """(x, y) in 1D as in eq. (6.3): x_k = k/(n+1), y_k = x_k + shift*U(0,1),
+    k = 1..n, so each x_k has a y_k within shift of it."""
+    rng = np.random.default_rng(seed)
+    x = np.arange(1, n + 1, dtype=np.float64) / (n + 1)
+    y = x + shift * rng.random(n)
+    return x[:, None].copy(), y[:, None].copy()
+
+
+def cauchy_like_generators(nx: int, ny: int, p: int = 2, seed: int = 0):
+    """Generators (w, v) of a Cauchy-like matrix (eq. (6.1)), entries U(0,1) as in
+    Sec. 6.3: w is (nx, p), v is (ny, p), row-major."""
+    rng = np.random.default_rng(seed + 200)
+    return rng.random((nx, p)), rng.random((ny, p))
+
+
 def curve(name: str, n: int):
     """Nystrom data of the Laplace double-layer operator on a closed curve
     r(t), t in [0, 1), with the trapezoidal rule at t_k = k/n (weight 1/n):

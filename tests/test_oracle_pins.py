@@ -815,3 +815,52 @@ def test_oracle_clean_under_address_and_undefined_behaviour_sanitizers(tmp_path)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "all cases clean" in r.stdout
     assert "ERROR" not in r.stderr and "runtime error" not in r.stderr, r.stderr
+
+
+# --------------------------------------------------------------------------
+# Cauchy-like matrices (Sec. 6.3, eqs. (6.1)-(6.2))
+# --------------------------------------------------------------------------
+def test_cauchy_like_displacement_identity():
+    """A Cauchy-like matrix with generators w, v (eq. (6.1)) is characterised
+    by its displacement: diag(x) A - A diag(y) = w v^T, so
+    x o (A q) - A (y o q) = w (v^T q).  A sign slip in the kernel, a dropped
+    generator column or w and v swapped breaks it."""
+    n = 300
+    x = (np.arange(1, n + 1) / (n + 1.0))[:, None]
+    y = x + 0.3 / (n + 1.0)
+    w, v = W.cauchy_like_generators(n, n, 2, seed=5)
+    q = W.rhs(n, 3, seed=6)
+    lhs = x * O.cauchy_like_dense(x, y, w, v, q) - O.cauchy_like_dense(x, y, w, v, y * q)
+    rhs = w @ (v.T @ q)
+    assert _relerr(lhs, rhs) < 1e-11
+    # with three generator columns and distinct point counts
+    m = 170
+    x3 = (np.arange(1, m + 1) / (m + 1.0))[:, None]
+    w3, v3 = W.cauchy_like_generators(m, n, 3, seed=7)
+    lhs3 = x3 * O.cauchy_like_dense(x3, y, w3, v3, q) - O.cauchy_like_dense(x3, y, w3, v3, y * q)
+    assert _relerr(lhs3, w3 @ (v3.T @ q)) < 1e-11
+
+
+def test_cauchy_like_unit_generators_closed_form():
+    """Generators with sum_l w_il v_jl = 1 give the Cauchy matrix itself, whose
+    row sums over the Chebyshev roots are T_N'(x)/T_N(x)."""
+    N = 257
+    x, y = W.chebyshev_pair(N, seed=3, shift=1e-3, shift_x=True)
+    w = np.ones((N, 2))
+    v = np.tile([0.25, 0.75], (N, 1))
+    z = O.cauchy_like_dense(x, y, w, v, np.ones(N))
+    assert np.max(np.abs(z - _cheb_logderiv(x, N)) / np.abs(_cheb_logderiv(x, N))) < 1e-9
+
+
+def test_cauchy_like_through_smash_matches_definition():
+    """The product by eq. (6.2) over the oracle's HSS approximation of the
+    Cauchy matrix matches the dense definition (6.1) within the construction's
+    accuracy, on the Chebyshev pair and on the interlaced points of eq. (6.3)."""
+    n = 3000
+    for pts in (W.chebyshev_pair(n, 1), W.interlaced_pair(n, 1)):
+        x, y = pts
+        w, v = W.cauchy_like_generators(n, n, 2, seed=2)
+        q = W.rhs(n, 2, seed=3)
+        o = O.Oracle(x, y, kernel="cauchy", leaf=50, order=16, adm=0, tol=1e-8, eps_svd=1e-9,
+                     tau=0.6)
+        assert _relerr(o.cauchy_like_matvec(w, v, q), O.cauchy_like_dense(x, y, w, v, q)) < 1e-8
