@@ -216,6 +216,57 @@ def one_workload(name, torch, api, W, reps=5, nrhs=None, apply=None, n=None):
     return out
 
 
+def cauchy_like_bench(torch, api, W, n=1 << 20, p=2, nrhs=16, reps=5):
+    """Sec. 6.3's Cauchy-like matrix (eq. (6.1), p generator columns of
+    U(0,1) entries) on the interlaced points of eq. (6.3): the HSS
+    construction of the Cauchy matrix (tau 0.6, leaf 50, eps_SVD 1e-9, as in
+    Sec. 6.3; 16 Chebyshev points and tol 1e-8 in place of the Taylor basis),
+    the Cauchy-like product by eq. (6.2) against the plain product of the
+    same handle, and its error against exact rows of (6.1)."""
+    x, y = W.interlaced_pair(n, seed=0)
+    w, v = W.cauchy_like_generators(n, n, p, seed=0)
+    q = W.rhs(n, nrhs, seed=0)
+    X, Yd = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+    Q, Wd, Vd = (torch.from_numpy(a).cuda() for a in (q, w, v))
+    kw = dict(kernel="cauchy", leaf=50, order=16, adm="weak", tol=1e-8, eps_svd=1e-9, tau=0.6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h = api.Smash(X, Yd, timing=True, **kw)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3
+    inf = h.info()
+    h.close()
+    hg = api.Smash(X, Yd, **kw)
+    Z = torch.empty((n, nrhs), dtype=torch.float64, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(2):
+        hg.matvec_cauchy_like(Q, Wd, Vd, out=Z)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        hg.matvec_cauchy_like(Q, Wd, Vd, out=Z)
+    ev[1].record()
+    Zp = hg.matvec(Q)
+    ev[2].record()
+    for _ in range(reps):
+        hg.matvec(Q, out=Zp)
+    ev[3].record()
+    torch.cuda.synchronize()
+    rows = np.arange(0, n, n // 256)
+    zr = sum(w[rows, l:l + 1] * exact_rows(torch, x, y, rows, v[:, l:l + 1] * q, "cauchy")
+             for l in range(p))
+    err = float(np.linalg.norm(Z.cpu().numpy()[rows] - zr) / np.linalg.norm(zr))
+    out = {"n": n, "p": p, "nrhs": nrhs, "points": "eq. (6.3), shift 1e-7", "build_ms": wall,
+           "build_phase_ms": {k: v for k, v in inf["phase_ms"].items() if v > 0},
+           "cauchy_like_product_ms": ev[0].elapsed_time(ev[1]) / reps,
+           "plain_product_ms": ev[2].elapsed_time(ev[3]) / reps,
+           "rel_err_vs_exact_rows": err, "max_rank": int(inf["max_rank_row"])}
+    hg.close()
+    del X, Yd, Q, Wd, Vd, Z, Zp
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,6 +461,8 @@ def main():
         out["workloads"] = ex
         print("double layer", flush=True)
         out["double_layer"] = double_layer_bench(torch, api, W)
+        print("Cauchy-like", flush=True)
+        out["cauchy_like"] = cauchy_like_bench(torch, api, W)
         print("O(n) series", flush=True)
         ser = []
         for lg in range(14, 21):

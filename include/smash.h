@@ -187,6 +187,30 @@ int smash_build_xy(const double *x, int64_t nx, const double *y, int64_t ny, int
 int smash_matvec(smash_handle h, const void *X, int64_t ldx, int32_t nrhs, int32_t dtype,
                  void *Y, int64_t ldy, void *stream);
 
+/* Product with a Cauchy-like matrix (Sec. 6.3, eqs. (6.1)-(6.2)):
+ * a_ij = kappa(x_i, y_j) sum_l w_il v_jl, i.e. A = sum_l diag(w_l) C diag(v_l)
+ * with C = [kappa(x_i, y_j)] the handle's matrix (for SMASH_KERNEL_CAUCHY the
+ * Cauchy matrix, which makes A the Cauchy-like matrix of (6.1)).  Computes
+ * Y = sum_l w_l o (C-hat (v_l o X)) with C-hat the handle's approximation:
+ * the HSS/H^2 generators of each term are the handle's with U, D and V scaled
+ * by the generator columns, and their sum is the merged representation of
+ * A-hat, applied here as one product with the p * nrhs columns v_l o X side
+ * by side, followed by the weighted sum over l (in the order l = 0, 1, ...).
+ *   X, Y, ldx, ldy, nrhs, dtype  as smash_matvec
+ *   w  device FP64, nx x p, row-major (w[i * p + l]): the row generators
+ *   v  device FP64, ny x p, row-major: the column generators
+ *   p  generator columns, 1 <= p <= SMASH_CAUCHY_LIKE_MAX_P
+ * Takes 8 (FP64 apply) or 4 bytes x p x nrhs x (nx + ny) of device memory for
+ * the stacked vectors while it runs (through the handle's allocator hooks if
+ * set), given back stream-ordered.  Asynchronous on `stream`, ordered with
+ * the handle's other products as smash_matvec is.
+ * Errors: as smash_matvec; SMASH_E_INVALID_ARG for a NULL w or v or p out of
+ * range; SMASH_E_OOM when the stacked vectors cannot be allocated. */
+#define SMASH_CAUCHY_LIKE_MAX_P 16
+int smash_matvec_cauchy_like(smash_handle h, const void *X, int64_t ldx, int32_t nrhs,
+                             int32_t dtype, const double *w, const double *v, int32_t p,
+                             void *Y, int64_t ldy, void *stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * product as smash_matvec, same arguments and results, but it allocates

@@ -98,7 +98,7 @@ PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", 
 
 _lib = None
 EXPORTED = ["smash_default_options", "smash_build", "smash_build_xy", "smash_matvec",
-            "smash_matvec_noalloc", "smash_matvec_batched", "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
+            "smash_matvec_noalloc", "smash_matvec_cauchy_like", "smash_matvec_batched", "smash_set_product_shape", "smash_info", "smash_export", "smash_destroy",
             "smash_estimate_footprint", "smash_estimate_footprint_mode", "smash_trim",
             "smash_last_error"]
 
@@ -120,6 +120,8 @@ def lib():
                                      C.POINTER(Options), vp, C.POINTER(vp)]
         L.smash_matvec.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, C.c_int64, vp]
         L.smash_matvec_noalloc.argtypes = L.smash_matvec.argtypes
+        L.smash_matvec_cauchy_like.argtypes = [vp, vp, C.c_int64, C.c_int32, C.c_int32, vp, vp,
+                                               C.c_int32, vp, C.c_int64, vp]
         L.smash_matvec_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(vp),
                                            C.POINTER(C.c_int64), C.POINTER(C.c_int32),
                                            C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32, vp]
@@ -344,6 +346,25 @@ class Smash:
                   PREC["f64" if self.apply_prec == "f64" else "f32"], C.c_void_p(out.data_ptr()),
                   out.stride(0), _stream_ptr(stream)))
         return out[:, 0] if vec else out
+
+    def matvec_cauchy_like(self, X, w, v, out=None, stream=None):
+        """Y = sum_l w_l o (A-hat (v_l o X)) through smash_matvec_cauchy_like: the
+        Cauchy-like matrix with generators w (nx, p) and v (ny, p), CUDA float64
+        tensors (eqs. (6.1)-(6.2)); X and out as for matvec."""
+        import torch
+        for g, n in ((w, self.nx), (v, self.ny)):
+            if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.float64
+                    and g.dim() == 2 and g.shape[0] == n):
+                raise TypeError("w and v must be CUDA float64 tensors of shape (nx, p), (ny, p)")
+        if w.shape[1] != v.shape[1]:
+            raise ValueError("w and v must have the same number of columns")
+        w, v = w.contiguous(), v.contiguous()
+        p = w.shape[1]
+
+        def fn(h, X, ldx, R, dt, Y, ldy, s):
+            return lib().smash_matvec_cauchy_like(h, X, ldx, R, dt, C.c_void_p(w.data_ptr()),
+                                                  C.c_void_p(v.data_ptr()), p, Y, ldy, s)
+        return self._product(fn, X, out, stream)
 
     def set_product_shape(self, mv_split_nodes, mv_xcd_run):
         """Launch shape of the products (see smash_set_product_shape)."""

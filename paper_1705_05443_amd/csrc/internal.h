@@ -338,6 +338,10 @@ void run_matvec(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_
 // SMASH_NOALLOC_SCRATCH_BYTES (no allocation, eager launches)
 void run_matvec_noalloc(Handle &h, const void *X, int64_t ldx, int nrhs, void *Y, int64_t ldy,
                         hipStream_t s);
+// Y = sum_l w_l o (A-hat (v_l o X)) for generators w (nx x p) and v (ny x p)
+// of a Cauchy-like matrix (eqs. (6.1)-(6.2)), on stream s
+void run_cauchy_like(Handle &h, const void *X, int64_t ldx, int nrhs, const double *w,
+                     const double *v, int p, void *Y, int64_t ldy, hipStream_t s);
 // destroys captured products (waits for each one's last launch)
 void drop_graphs(Handle &h);
 

@@ -1313,6 +1313,68 @@ static void run_matvec_on(Handle &h, const void *X, int64_t ldx, int nrhs, void 
   h.graph_replays++;
 }
 
+// ------------------------------------------- Cauchy-like generators
+// A Cauchy-like matrix with generators w (nx x p) and v (ny x p) is
+// sum_l diag(w_l) C diag(v_l) (eqs. (6.1)-(6.2)).  Each term's HSS generators
+// are the handle's with U, D and V scaled by the generator columns, and the
+// product of their merged sum is taken here as one product of the handle's
+// approximation with the p R columns v_l o X side by side (column l R + r
+// holds v_l o X_r), then Y = sum_l w_l o Z_l, the terms added in the order
+// l = 0, 1, ...; every column of the stacked product is computed as it
+// would be alone.
+template <class T>
+__global__ void k_cl_stack(const T *X, int64_t ldx, int R, const double *v, int p, int64_t ny,
+                           T *Xs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t pr = (int64_t)p * R;
+  if (e >= ny * pr) return;
+  const int64_t j = e / pr;
+  const int c = (int)(e - j * pr), l = c / R, r = c - l * R;
+  Xs[e] = (T)(v[j * p + l] * (double)X[j * ldx + r]);
+}
+
+template <class T>
+__global__ void k_cl_combine(const T *Z, int R, const double *w, int p, int64_t nx, T *Y,
+                             int64_t ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nx * R) return;
+  const int64_t i = e / R;
+  const int r = (int)(e - i * R);
+  const T *zi = Z + i * (int64_t)p * R + r;
+  double acc = w[i * p] * (double)zi[0];
+  for (int l = 1; l < p; l++) acc = acc + w[i * p + l] * (double)zi[(int64_t)l * R];
+  Y[i * ldy + r] = (T)acc;
+}
+
+template <class T>
+static void cauchy_like_t(Handle &h, const T *X, int64_t ldx, int nrhs, const double *w,
+                          const double *v, int p, T *Y, int64_t ldy, hipStream_t s) {
+  const int pr = p * nrhs;
+  DeviceArena tmp;
+  tmp.stream = s;
+  try {
+    T *Xs = tmp.alloc_n<T>((size_t)h.ny * pr);
+    T *Zs = tmp.alloc_n<T>((size_t)h.nx * pr);
+    k_cl_stack<T><<<ceil_div(h.ny * pr, 256), 256, 0, s>>>(X, ldx, nrhs, v, p, h.ny, Xs);
+    SMASH_CHECK_LAUNCH();
+    run_matvec(h, Xs, pr, pr, Zs, pr, s);
+    k_cl_combine<T><<<ceil_div(h.nx * nrhs, 256), 256, 0, s>>>(Zs, nrhs, w, p, h.nx, Y, ldy);
+    SMASH_CHECK_LAUNCH();
+  } catch (...) {
+    tmp.release(false);
+    throw;
+  }
+  tmp.release(false);  // stream-ordered: after the combine
+}
+
+void run_cauchy_like(Handle &h, const void *X, int64_t ldx, int nrhs, const double *w,
+                     const double *v, int p, void *Y, int64_t ldy, hipStream_t s) {
+  if (h.apply_prec == SMASH_F64)
+    cauchy_like_t<double>(h, (const double *)X, ldx, nrhs, w, v, p, (double *)Y, ldy, s);
+  else
+    cauchy_like_t<float>(h, (const float *)X, ldx, nrhs, w, v, p, (float *)Y, ldy, s);
+}
+
 // ---------------------------------------------- product without allocation
 // The product's only device memory beyond the handle, X and Y is its pair of
 // slot-space vectors.  For callers that cannot allocate, they come from this

@@ -256,6 +256,31 @@ extern "C" int smash_matvec(smash_handle hv, const void *X, int64_t ldx, int32_t
   }
 }
 
+extern "C" int smash_matvec_cauchy_like(smash_handle hv, const void *X, int64_t ldx,
+                                        int32_t nrhs, int32_t dtype, const double *w,
+                                        const double *v, int32_t p, void *Y, int64_t ldy,
+                                        void *stream) {
+  Handle *h = (Handle *)hv;
+  if (!h) return fail(SMASH_E_INVALID_ARG, "handle is NULL");
+  if (!X || !Y || !w || !v) return fail(SMASH_E_INVALID_ARG, "X, Y, w or v is NULL");
+  if (nrhs < 1) return fail(SMASH_E_INVALID_ARG, "nrhs must be >= 1");
+  if (p < 1 || p > SMASH_CAUCHY_LIKE_MAX_P)
+    return fail(SMASH_E_INVALID_ARG, "generator count p out of range");
+  if ((int64_t)p * nrhs > INT32_MAX / 2) return fail(SMASH_E_INVALID_ARG, "p * nrhs too large");
+  if (ldx < nrhs || ldy < nrhs) return fail(SMASH_E_INVALID_ARG, "leading dimension < nrhs");
+  if (dtype != (h->apply_prec == SMASH_F64 ? SMASH_F64 : SMASH_F32))
+    return fail(SMASH_E_INVALID_ARG, "dtype differs from the handle's vector precision");
+  try {
+    HooksScope hs(&h->hooks);
+    run_cauchy_like(*h, X, ldx, nrhs, w, v, p, Y, ldy, (hipStream_t)stream);
+    return SMASH_OK;
+  } catch (const Error &e) {
+    return fail(e.code, e.msg);
+  } catch (...) {
+    return fail(SMASH_E_DEVICE, "unexpected failure");
+  }
+}
+
 extern "C" int smash_matvec_noalloc(smash_handle hv, const void *X, int64_t ldx, int32_t nrhs,
                                     int32_t dtype, void *Y, int64_t ldy, void *stream) {
   Handle *h = (Handle *)hv;
