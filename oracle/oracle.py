@@ -61,6 +61,11 @@ def lib():
                                    C.c_double, C.c_double, C.c_double, C.c_int, dp,
                                    C.c_double, C.c_int, dp, C.POINTER(C.c_void_p)]
         L.oracle_build.restype = C.c_int
+        L.oracle_build_basis.argtypes = list(L.oracle_build.argtypes[:-1]) + [
+            C.c_int, C.POINTER(C.c_void_p)]
+        L.oracle_build_basis.restype = C.c_int
+        L.oracle_taylor_basis.argtypes = [dp, C.c_int, C.c_double, C.c_double, C.c_int, dp]
+        L.oracle_taylor_basis.restype = None
         L.oracle_build_tree.argtypes = [dp, C.c_int64, dp, C.c_int64, C.c_int, C.c_int, C.c_int,
                                         C.c_int, C.c_int, C.c_double, C.c_int, dp, C.c_double,
                                         C.c_int, dp, C.POINTER(C.c_void_p)]
@@ -131,7 +136,7 @@ class Oracle:
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=32, order=10, adm=1, tol=1e-10,
                  tau=None, eps_svd=None, f=2.0, diag=None, root=None, max_depth=0,
-                 point_data=None, tree_only=False):
+                 point_data=None, tree_only=False, basis="chebyshev"):
         x = _f64(x)
         if x.ndim == 1:
             x = x[:, None]
@@ -163,11 +168,14 @@ class Oracle:
                                          _dp(rlo), side, int(max_depth), _dp(self.point_data),
                                          C.byref(h))
         else:
-            rc = lib().oracle_build(_dp(x), x.shape[0], _dp(y), y.shape[0], int(same), d, kid,
-                                    int(leaf), int(order), int(adm), float(tol), float(tau),
-                                    float(eps_svd), float(f), float(diag), int(has_root),
-                                    _dp(rlo), side, int(max_depth), _dp(self.point_data),
-                                    C.byref(h))
+            if basis not in ("chebyshev", "taylor"):
+                raise ValueError("basis must be 'chebyshev' or 'taylor'")
+            rc = lib().oracle_build_basis(_dp(x), x.shape[0], _dp(y), y.shape[0], int(same), d,
+                                          kid, int(leaf), int(order), int(adm), float(tol),
+                                          float(tau), float(eps_svd), float(f), float(diag),
+                                          int(has_root), _dp(rlo), side, int(max_depth),
+                                          _dp(self.point_data), int(basis == "taylor"),
+                                          C.byref(h))
         if rc != 0:
             raise OracleError("oracle_build failed with code %d" % rc)
         self._h = h
@@ -349,6 +357,15 @@ def interp_basis(pts, lo, hi, p):
     out = np.zeros((m, p ** d))
     lib().oracle_interp_basis(_dp(pts), m, d, _dp(lo3), _dp(hi3), p, _dp(out))
     return out
+
+
+def taylor_basis(pts, lo, hi, p):
+    """The Taylor basis (2.4)-(2.5) with r = p terms of the interval [lo, hi] at
+    the given points (m x p)."""
+    pts = np.ascontiguousarray(_f64(pts).ravel())
+    Cm = np.zeros((pts.shape[0], p))
+    lib().oracle_taylor_basis(_dp(pts), pts.shape[0], float(lo), float(hi), int(p), _dp(Cm))
+    return Cm
 
 
 def left_svd(A, eps):

@@ -14,7 +14,7 @@
  *   well-separated test         Def. 2.1, eq. (2.3), on the boxes Omega_i
  *   admissible leaves L, L^-    eqs. (3.3), (3.4); HSS form eq. (3.5)
  *   near-field sets N_i         eq. (A.1)
- *   interpolation basis U-hat   eq. (2.2)
+ *   interpolation basis U-hat   eq. (2.2); Taylor basis eqs. (2.4)-(2.5)
  *   near-field truncated SVD    eqs. (3.7)-(3.8), (3.11)-(3.12), Def. 6.1
  *   compr (strong RRQR ID)      Thm. 2.4, eqs. (2.10)-(2.14)
  *   generators, parent grids    eqs. (3.6), (3.9)-(3.10), (3.13)-(3.14),
@@ -155,6 +155,7 @@ typedef struct {
 typedef struct {
   int d, kid, adm, leaf, p, symmetric_reuse;
   double tol, tau, eps_svd, f, diag;
+  double taylor_g; /* > 0: the Taylor basis of eqs. (2.4)-(2.5) (d = 1), g as there */
   int nx, ny;
   double *X, *Y;          /* permuted coordinates, n x d row-major */
   double *AX;             /* kernel 4: permuted per-point data, n x 3 (X = Y) */
@@ -524,14 +525,47 @@ static void lagrange_1d(double x, double lo, double hi, int p, double *out) {
   for (int k = 0; k < p; k++) out[k] = out[k] / den;
 }
 
-/* C = U-hat (m x p^d) row-major for the m points pts (m x d) in the box. */
+/* ------------------------------------------------------------------ */
+/* Far-field basis by the Taylor expansion, eqs. (2.4)-(2.5), on the line:
+ * the r = p functions phi_{a,l}(x - a) = eta_{a,l} (x - a)^l / l! of the box
+ * [lo, hi], whose center a and radius delta (half its width) stand for
+ * those of the set (Def. 2.1), with eta_{a,0} = 1 and
+ * eta_{a,l} = (l g / delta)^l, g = (2 pi r)^{1/(2r)} / e, for l >= 1.  So
+ * phi_l = (u l g)^l / l! with u = (x - a) / delta, taken as the running
+ * product of (u l g) / k over k = 1..l.                                   */
+/* ------------------------------------------------------------------ */
+static double taylor_g_of(int r) { return pow(2.0 * M_PI * r, 1.0 / (2.0 * r)) / exp(1.0); }
+
+static void taylor_1d(double x, double lo, double hi, int p, double g, double *out) {
+  if (hi - lo == 0.0) { /* degenerate box: constant basis */
+    for (int l = 0; l < p; l++) out[l] = l == 0 ? 1.0 : 0.0;
+    return;
+  }
+  const double a = 0.5 * (lo + hi), del = 0.5 * (hi - lo);
+  const double u = (x - a) / del;
+  out[0] = 1.0;
+  for (int l = 1; l < p; l++) {
+    const double w = u * ((double)l * g);
+    double v = 1.0;
+    for (int k = 1; k <= l; k++) v = v * w / k;
+    out[l] = v;
+  }
+}
+
+/* C = U-hat (m x p^d) row-major for the m points pts (m x d) in the box:
+ * the interpolation basis (2.2), or with g > 0 (d = 1) the Taylor basis. */
 static void interp_basis(const double *pts, int m, int d, const double *lo,
-                         const double *hi, int p, double *C, int ldc) {
+                         const double *hi, int p, double g, double *C, int ldc) {
   double f[3][64];
   int c = 1;
   for (int t = 0; t < d; t++) c *= p;
   for (int a = 0; a < m; a++) {
-    for (int t = 0; t < d; t++) lagrange_1d(pts[(size_t)a * d + t], lo[t], hi[t], p, f[t]);
+    for (int t = 0; t < d; t++) {
+      if (g > 0.0)
+        taylor_1d(pts[(size_t)a * d + t], lo[t], hi[t], p, g, f[t]);
+      else
+        lagrange_1d(pts[(size_t)a * d + t], lo[t], hi[t], p, f[t]);
+    }
     for (int col = 0; col < c; col++) {
       int r = col;
       double v = 1.0;
@@ -960,7 +994,7 @@ static int compress_node(oracle_t *h, int i, int rowside) {
     lo[t] = h->lo[3 * i + t];
     hi[t] = h->hi[3 * i + t];
   }
-  interp_basis(pts, m, d, lo, hi, h->p, C, c);
+  interp_basis(pts, m, d, lo, hi, h->p, h->taylor_g, C, c);
   if (dl_col)
     for (int a = 0; a < m; a++) {
       const double *da = h->AX + (size_t)s->grid[a] * 3;
@@ -1081,14 +1115,25 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
                       int d, int kid, int leaf, int p, int adm, double tol, double tau,
                       double eps_svd, double f, double diag, int has_root, const double *root_lo,
                       double root_side, int max_depth, const double *data, int tree_only,
-                      void **out);
+                      int basis, void **out);
 
 int oracle_build(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
                  int d, int kid, int leaf, int p, int adm, double tol, double tau,
                  double eps_svd, double f, double diag, int has_root, const double *root_lo,
                  double root_side, int max_depth, const double *data, void **out) {
   return build_impl(x, nx, y, ny, same_xy, d, kid, leaf, p, adm, tol, tau, eps_svd, f, diag,
-                    has_root, root_lo, root_side, max_depth, data, 0, out);
+                    has_root, root_lo, root_side, max_depth, data, 0, 0, out);
+}
+
+/* The same with a choice of far-field basis: 0 the interpolation basis
+ * (2.2), 1 the Taylor basis (2.4)-(2.5) with r = p terms (d = 1 only). */
+int oracle_build_basis(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
+                       int d, int kid, int leaf, int p, int adm, double tol, double tau,
+                       double eps_svd, double f, double diag, int has_root,
+                       const double *root_lo, double root_side, int max_depth,
+                       const double *data, int basis, void **out) {
+  return build_impl(x, nx, y, ny, same_xy, d, kid, leaf, p, adm, tol, tau, eps_svd, f, diag,
+                    has_root, root_lo, root_side, max_depth, data, 0, basis, out);
 }
 
 /* The partition and the pair lists only (Sec. 3.1, eqs. (3.3)-(3.5), (A.1)):
@@ -1099,20 +1144,21 @@ int oracle_build_tree(const double *x, int64_t nx, const double *y, int64_t ny, 
                       const double *root_lo, double root_side, int max_depth, const double *data,
                       void **out) {
   return build_impl(x, nx, y, ny, same_xy, d, kid, leaf, 1, adm, 0.0, tau, 0.0, 2.0, 0.0,
-                    has_root, root_lo, root_side, max_depth, data, 1, out);
+                    has_root, root_lo, root_side, max_depth, data, 1, 0, out);
 }
 
 static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
                       int d, int kid, int leaf, int p, int adm, double tol, double tau,
                       double eps_svd, double f, double diag, int has_root, const double *root_lo,
                       double root_side, int max_depth, const double *data, int tree_only,
-                      void **out) {
+                      int basis, void **out) {
   *out = NULL;
   if (d < 1 || d > 3 || nx < 1 || ny < 1 || leaf < 1 || p < 1 || p > 64 || tau <= 0.0 ||
       tau >= 1.0 || f <= 1.0 || tol < 0.0 || (adm != 0 && adm != 1) || kid < 0 || kid > 4)
     return OR_EINVAL;
   if (kid == 3 && d != 1) return OR_EUNSUP;
   if (kid == 4 && (d != 2 || !same_xy || !data)) return OR_EUNSUP;
+  if (basis != 0 && (basis != 1 || d != 1 || kid == 4)) return OR_EUNSUP;
   if (kid == 4)
     for (int64_t a = 0; a < nx * 3; a++)
       if (!isfinite(data[a])) return OR_ENUMERIC;
@@ -1123,6 +1169,7 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
   h->adm = adm;
   h->leaf = leaf;
   h->p = p;
+  h->taylor_g = basis == 1 ? taylor_g_of(p) : 0.0;
   h->tol = tol;
   h->tau = tau;
   h->eps_svd = eps_svd;
@@ -1590,7 +1637,13 @@ int oracle_compr(const double *C, int m, int c, double tol, double f, int *k, in
 
 void oracle_interp_basis(const double *pts, int m, int d, const double *lo, const double *hi,
                          int p, double *C) {
-  interp_basis(pts, m, d, lo, hi, p, C, ipow(p, d));
+  interp_basis(pts, m, d, lo, hi, p, 0.0, C, ipow(p, d));
+}
+
+/* The Taylor basis (2.4)-(2.5) of the interval [lo, hi] with r = p terms at
+ * m points (m x p row-major), for the pins. */
+void oracle_taylor_basis(const double *pts, int m, double lo, double hi, int p, double *C) {
+  interp_basis(pts, m, 1, &lo, &hi, p, taylor_g_of(p), C, p);
 }
 
 int oracle_left_svd(const double *A, int m, int n, double eps, double *S, double *sig) {

@@ -1,8 +1,8 @@
 /* Runs the FP64 oracle (compiled into this program with AddressSanitizer and
  * UndefinedBehaviorSanitizer by tests/test_oracle_pins.py) through every
  * kernel, both admissibilities, distinct point sets, the double-layer data,
- * a swap-heavy bound and the Cauchy-like generators, and checks each product
- * against the dense one.
+ * a swap-heavy bound, the Taylor basis and the Cauchy-like generators, and
+ * checks each product against the dense one.
  * Any sanitizer report or a failed check ends the program with a nonzero
  * status.  Test infrastructure only. */
 #include <math.h>
@@ -17,6 +17,11 @@ int oracle_build(const double *x, int64_t nx, const double *y, int64_t ny, int s
 int oracle_matvec(void *hv, const double *Q, int64_t R64, double *Z);
 int oracle_export(void *hv, int what, void *buf, int64_t *count);
 void oracle_destroy(void *hv);
+int oracle_build_basis(const double *x, int64_t nx, const double *y, int64_t ny, int same_xy,
+                       int d, int kid, int leaf, int p, int adm, double tol, double tau,
+                       double eps_svd, double f, double diag, int has_root,
+                       const double *root_lo, double root_side, int max_depth,
+                       const double *data, int basis, void **out);
 void oracle_cauchy_like_dense(const double *x, int64_t nx, const double *y, int64_t ny,
                               const double *w, const double *v, int p, const double *Q,
                               int64_t R, double *Z);
@@ -109,6 +114,29 @@ int main(void) {
   bad += run("Cauchy HSS X != Y", cx, nc, cy, nc, 1, 3, 32, 12, 0, 1e-8, 1e-9, 2.0, 0.0, NULL,
              1e-5);
   bad += run("double layer HSS", dp, nd, NULL, 0, 2, 4, 40, 5, 0, 1e-8, 1e-9, 2.0, 0.0, dd, 1e-5);
+  {  /* the Taylor basis (eqs. (2.4)-(2.5)) in place of interpolation */
+    const int R = 2;
+    double *Q = malloc(sizeof(double) * nc * R), *Z = malloc(sizeof(double) * nc * R),
+           *Zd = malloc(sizeof(double) * nc * R);
+    for (int a = 0; a < nc * R; a++) Q[a] = urand() - 0.5;
+    void *h = NULL;
+    int rc = oracle_build_basis(cx, nc, cy, nc, 0, 1, 3, 32, 12, 0, 1e-8, 0.6, 1e-9, 2.0, 0.0, 0,
+                                NULL, 0.0, 0, NULL, 1, &h);
+    if (rc == 0) rc = oracle_matvec(h, Q, R, Z);
+    oracle_dense_matvec(cx, nc, cy, nc, 1, 3, 0.0, NULL, NULL, Q, R, Zd);
+    double num = 0.0, den = 0.0;
+    for (int a = 0; a < nc * R; a++) {
+      num += (Z[a] - Zd[a]) * (Z[a] - Zd[a]);
+      den += Zd[a] * Zd[a];
+    }
+    const double err = sqrt(num / (den > 0 ? den : 1.0));
+    printf("Taylor-basis HSS: rc %d, relative error %.2e\n", rc, err);
+    bad += rc != 0 || !(err < 1e-6);
+    if (h) oracle_destroy(h);
+    free(Q);
+    free(Z);
+    free(Zd);
+  }
   {  /* Cauchy-like generators (eqs. (6.1)-(6.2)) over the Cauchy HSS */
     const int p = 2, R = 2;
     double *w = malloc(sizeof(double) * nc * p), *v = malloc(sizeof(double) * nc * p),

@@ -864,3 +864,58 @@ def test_cauchy_like_through_smash_matches_definition():
         o = O.Oracle(x, y, kernel="cauchy", leaf=50, order=16, adm=0, tol=1e-8, eps_svd=1e-9,
                      tau=0.6)
         assert _relerr(o.cauchy_like_matvec(w, v, q), O.cauchy_like_dense(x, y, w, v, q)) < 1e-8
+
+
+# --------------------------------------------------------------------------
+# Taylor far-field basis (eqs. (2.4)-(2.6))
+# --------------------------------------------------------------------------
+def test_taylor_basis_scaling_against_stirling():
+    """The scaling eta of (2.5) makes the largest |phi_l| on the box, at its
+    ends, (l g)^l / l! with g = (2 pi r)^(1/(2r)) / e; by Stirling's series
+    l! = sqrt(2 pi l)(l/e)^l (1 + 1/(12 l) + 1/(288 l^2) + ...) that is
+    (2 pi r)^(l/(2r)) / sqrt(2 pi l) over the bracket."""
+    for r in (4, 10, 22):
+        B = O.taylor_basis(np.array([-1.0, 3.0]), -1.0, 3.0, r)  # box ends, delta = 2
+        assert np.all(B[:, 0] == 1.0)
+        for l in range(1, r):
+            st = (2 * np.pi * r) ** (l / (2.0 * r)) / np.sqrt(2 * np.pi * l) / (
+                1 + 1 / (12.0 * l) + 1 / (288.0 * l * l))
+            assert abs(abs(B[1, l]) - st) < 3e-3 * st, (r, l)
+            assert B[1, l] > 0 and (B[0, l] > 0) == (l % 2 == 0)  # sign of (x - a)^l
+
+
+def test_taylor_basis_spans_far_field_within_bound():
+    """For X and Y well separated with ratio tau (eq. (2.3)), 1/(x - y) over X
+    lies in the span of the r functions phi_l of X's box within the bound
+    (2.6) on the expansion's error: least squares over the basis leaves a
+    residual at most (1 + tau) tau^r / (1 - tau) times the column's size."""
+    rng = np.random.default_rng(9)
+    lo, hi = 0.2, 0.6  # a = 0.4, delta_a = 0.2
+    xs = np.sort(rng.uniform(lo, hi, 400))
+    for tau in (0.3, 0.5):
+        db = 0.05
+        b = 0.4 + (0.2 + db) / tau  # delta_a + delta_b = tau |a - b|
+        ys = rng.uniform(b - db, b + db, 40)
+        K = 1.0 / (xs[:, None] - ys[None, :])
+        for r in (4, 8, 12):
+            U = O.taylor_basis(xs, lo, hi, r)
+            coef = np.linalg.lstsq(U, K, rcond=None)[0]
+            res = np.abs(U @ coef - K).max(axis=0)
+            bound = (1 + tau) * tau ** r / (1 - tau) * np.abs(K).max(axis=0)
+            assert np.all(res <= bound), (tau, r, float((res / bound).max()))
+
+
+def test_taylor_basis_hss_closed_form():
+    """With the Taylor basis in place of interpolation, the HSS approximation
+    of the Cauchy matrix still reproduces K.1 = T_N'(x)/T_N(x)."""
+    N = 4096
+    x, y = W.chebyshev_pair(N, seed=0, shift_x=True)
+    o = O.Oracle(x, y, kernel="cauchy", leaf=64, order=16, adm=0, tol=1e-8, eps_svd=1e-9,
+                 tau=0.6, basis="taylor")
+    assert _relerr(o.matvec(np.ones(N)), _cheb_logderiv(x, N, dps=30)) < 1e-7
+    # and an H^2 build on the line with 1/|x - y|
+    xu = W.uniform(3000, 1, 21)
+    q = W.rhs(3000, 2, 4)
+    o2 = O.Oracle(xu, kernel="inv_r", leaf=32, order=12, adm=1, tol=1e-10, tau=0.6,
+                  root=((0.0,), 1.0), basis="taylor")
+    assert _relerr(o2.matvec(q), O.dense_matvec(xu, xu, q, "inv_r")) < 1e-8
