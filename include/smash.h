@@ -151,7 +151,16 @@ typedef struct smash_options {
    * order, per point (m_1, m_2, diagonal value); borrowed like the points.
    * NULL for every other kernel. */
   const double *point_data;
+  /* far-field basis: SMASH_BASIS_CHEBYSHEV (default), the interpolation
+   * basis (2.2) on interp_order Chebyshev points per axis; or
+   * SMASH_BASIS_TAYLOR (dim 1 only, not the double-layer kernel), the
+   * Taylor basis (2.4)-(2.5) with r = interp_order terms, scaled by the box's
+   * center and half width (Def. 2.1). */
+  int32_t basis;
 } smash_options;
+
+#define SMASH_BASIS_CHEBYSHEV 0
+#define SMASH_BASIS_TAYLOR 1
 
 int smash_default_options(smash_options *opt);
 

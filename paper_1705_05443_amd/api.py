@@ -45,7 +45,7 @@ class Options(C.Structure):
                 ("mv_split_nodes", C.c_int32), ("graphs", C.c_int32),
                 ("mv_xcd_run", C.c_int32), ("coupling_mode", C.c_int32),
                 ("coupling_chunk", C.c_int64), ("alloc", C.c_void_p), ("free", C.c_void_p),
-                ("alloc_ctx", C.c_void_p), ("point_data", C.c_void_p)]
+                ("alloc_ctx", C.c_void_p), ("point_data", C.c_void_p), ("basis", C.c_int32)]
 
 # smash_alloc_fn / smash_free_fn
 ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p)
@@ -91,6 +91,8 @@ class Info(C.Structure):
                 ("coupling_ws_entries", C.c_int64), ("bytes_dense", C.c_int64),
                 ("bytes_hss0", C.c_int64), ("bytes_smash", C.c_int64),
                 ("build_peak_bytes", C.c_int64)]
+
+BASES = {"chebyshev": 0, "taylor": 1}  # SMASH_BASIS_*
 
 PHASES = ["tree", "pairs", "near_svd", "compr", "slots", "blocks", "mv_gather", "mv_up",
           "mv_coupling", "mv_down", "mv_near_out"]
@@ -228,13 +230,16 @@ class Smash:
     coupling_chunk entries (0: 256 MiB worth).  allocator: None (the
     library's own pool), "torch" (torch's caching allocator, see
     torch_allocator_hooks) or an (alloc, free) pair of ALLOC_FN / FREE_FN.
+    basis: "chebyshev" (interpolation, eq. (2.2)) or "taylor" (eqs. (2.4)-(2.5),
+    order = the number of terms r; points on the line only).
     """
 
     def __init__(self, x, y=None, *, kernel="inv_r", leaf=64, order=8, adm="strong", tol=1e-8,
                  tau=None, eps_svd=None, f=2.0, diag=0.0, eval_prec="f64", apply_prec="f64",
                  root=None, max_depth=0, batched=True, timing=False, mv_split_nodes=None,
                  mv_xcd_run=None, graphs=True, tuned=True, nrhs_hint=16, coupling="auto",
-                 coupling_chunk=0, allocator=None, stream=None, point_data=None):
+                 coupling_chunk=0, allocator=None, stream=None, point_data=None,
+                 basis="chebyshev"):
         import torch
         if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64):
             raise TypeError("x must be a CUDA float64 tensor")
@@ -284,6 +289,9 @@ class Smash:
             raise ValueError("coupling must be 'auto', 'stored' or 'evaluated'")
         opt.coupling_mode = COUPLING[coupling]
         opt.coupling_chunk = int(coupling_chunk)
+        if basis not in BASES:
+            raise ValueError("basis must be 'chebyshev' or 'taylor'")
+        opt.basis = BASES[basis]
         self._hooks = None
         if allocator is not None:
             self._hooks = torch_allocator_hooks() if allocator == "torch" else tuple(allocator)

@@ -57,7 +57,23 @@ struct IdArgs {
   // (c0 = 2 pd); pd is p^d and pdat the per-point data by point id
   int dlw, pd;
   const double *pdat;
+  // > 0: the Taylor basis of eqs. (2.4)-(2.5) (d = 1) with this g in place
+  // of the Lagrange basis (see taylor_phi)
+  double taylor_g;
 };
+
+// phi_q of the Taylor basis (2.4)-(2.5) at x for the box [lo, hi] with
+// hi > lo: eta_q (x - a)^q / q! with a the box's center, delta its half
+// width and eta_q = (q g / delta)^q, i.e. (u q g)^q / q! for
+// u = (x - a) / delta, taken as the running product of (u q g) / k
+__device__ __forceinline__ double taylor_phi(double x, double lo, double hi, int q, double g) {
+  const double a = 0.5 * (lo + hi), del = 0.5 * (hi - lo);
+  const double u = (x - a) / del;
+  const double w = u * ((double)q * g);
+  double v = 1.0;
+  for (int k = 1; k <= q; k++) v = v * w / (double)k;
+  return v;
+}
 
 // ---- lane exchanges (DPP) ------------------------------------------------
 // update_dpp with old = the lane's own value: lanes outside row_mask keep it
@@ -315,6 +331,11 @@ __global__ void __launch_bounds__(NT, 2) k_compr_w(IdArgs A) {
           const double x = A.P[id * d + t];
           const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
           double *Ft = Fl + (t * p) * NC + a;
+          if (A.taylor_g > 0.0) {  // (uniform over the workgroup)
+            for (int q = h; q < p; q += LPC)
+              Ft[q * NC] = hi - lo == 0.0 ? (q == 0 ? 1.0 : 0.0) : taylor_phi(x, lo, hi, q, A.taylor_g);
+            continue;
+          }
           int hit = -1;
           double den = 0.0;
           if (hi - lo == 0.0) {
@@ -799,6 +820,11 @@ __device__ __forceinline__ void compr_node_s(const IdArgs &A, const CsArgs &B, i
         for (int t = 0; t < d; t++) {
           const double x = A.P[id * d + t];
           const double lo = A.lo[3 * i + t], hi = A.hi[3 * i + t];
+          if (A.taylor_g > 0.0) {  // (uniform over the workgroup)
+            for (int q = h; q < p; q += CS_LPC)
+              F[t * p + q] = hi - lo == 0.0 ? (q == 0 ? 1.0 : 0.0) : taylor_phi(x, lo, hi, q, A.taylor_g);
+            continue;
+          }
           int hit = -1;
           double den = 0.0;
           if (hi - lo == 0.0) {
@@ -1480,6 +1506,12 @@ __global__ void __launch_bounds__(CS_NT) k_compr_dq(IdArgs A, DqArgs D) {
           for (int t = 0; t < d; t++) {
             const double x = A.P[id * d + t];
             const double blo = A.lo[3 * i + t], bhi = A.hi[3 * i + t];
+            if (A.taylor_g > 0.0) {  // (uniform over the workgroup)
+              for (int q = h; q < p; q += CS_LPC)
+                F[t * p + q] = bhi - blo == 0.0 ? (q == 0 ? 1.0 : 0.0)
+                                                : taylor_phi(x, blo, bhi, q, A.taylor_g);
+              continue;
+            }
             int hit = -1;
             double den = 0.0;
             if (bhi - blo == 0.0) {
@@ -2744,6 +2776,7 @@ void build_generators(Handle &h) {
         ia.dlw = (dl && !sc.rowside) ? 1 : 0;
         ia.pd = pd;
         ia.pdat = h.Ap;
+        ia.taylor_g = h.taylor_g;
         IdArgs ir = ia;  // the register form writes G^T, and G
         ir.gt_out = 1;
         ir.G_out = L.Gt;

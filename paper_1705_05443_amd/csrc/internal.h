@@ -197,6 +197,7 @@ struct Handle {
   int eval_prec = SMASH_F64, apply_prec = SMASH_F64, batched = 1, mv_split_nodes = 1024;
   int mv_xcd_run = 16;
   int64_t nx = 0, ny = 0;
+  double taylor_g = 0.0;  // > 0: Taylor basis (2.4)-(2.5) with this g, else interpolation (2.2)
   bool same_xy = false, reuse = false;
   int device = 0;
   hipStream_t stream = nullptr;

@@ -115,6 +115,10 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
   } else if (opt.point_data) {
     return fail(SMASH_E_INVALID_ARG, "options.point_data is for the double-layer kernel only");
   }
+  if (opt.basis != SMASH_BASIS_CHEBYSHEV && opt.basis != SMASH_BASIS_TAYLOR)
+    return fail(SMASH_E_INVALID_ARG, "unknown options.basis");
+  if (opt.basis == SMASH_BASIS_TAYLOR && (dim != 1 || kid == SMASH_KERNEL_DOUBLE_LAYER))
+    return fail(SMASH_E_UNSUPPORTED, "the Taylor basis needs dim == 1 (and not the double layer)");
   if (leaf < 1) return fail(SMASH_E_INVALID_ARG, "leaf_size must be >= 1");
   if (p < 1 || p > 64) return fail(SMASH_E_INVALID_ARG, "interp_order must be in [1, 64]");
   if (adm != SMASH_ADM_WEAK && adm != SMASH_ADM_STRONG)
@@ -177,6 +181,9 @@ static int build_impl(const double *x, int64_t nx, const double *y, int64_t ny, 
     h->same_xy = same;
     h->reuse = same && kid != SMASH_KERNEL_CAUCHY && kid != SMASH_KERNEL_DOUBLE_LAYER;
     h->pdata_in = opt.point_data;
+    // g of the Taylor basis (2.5): (2 pi r)^(1/(2r)) / e with r = p terms
+    if (opt.basis == SMASH_BASIS_TAYLOR)
+      h->taylor_g = std::pow(2.0 * M_PI * p, 1.0 / (2.0 * p)) / std::exp(1.0);
     h->bpl = adm == SMASH_ADM_WEAK ? 1 : dim;
     h->max_split = 63 / h->bpl;
     if (opt.max_depth > 0 && opt.max_depth - 1 < h->max_split) h->max_split = opt.max_depth - 1;

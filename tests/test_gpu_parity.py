@@ -58,6 +58,13 @@ CASES = {
     "hss_cauchy_xy": (lambda: W.chebyshev_pair(3000, 4),
                       dict(kernel="cauchy", leaf=64, order=16, adm="weak", tol=1e-8,
                            eps_svd=1e-9, tau=0.6)),
+    # the Taylor basis of eqs. (2.4)-(2.5) in place of interpolation
+    "hss_cauchy_taylor": (lambda: W.chebyshev_pair(3000, 4),
+                          dict(kernel="cauchy", leaf=64, order=16, adm="weak", tol=1e-8,
+                               eps_svd=1e-9, tau=0.6, basis="taylor")),
+    "h2_1d_inv_r_taylor": (lambda: (W.uniform(3000, 1, 11), None),
+                           dict(kernel="inv_r", leaf=40, order=12, adm="strong", tol=1e-10,
+                                tau=0.6, root=((0.0,), 1.0), basis="taylor")),
     # Laplace double layer on the curves of Sec. 6.4 (Nystrom data as point data)
     "hss_dl_ram_head": (lambda: (W.curve("ram_head", 1280)[0], None),
                         dict(kernel="double_layer", leaf=50, order=5, adm="weak", tol=1e-10,
@@ -267,11 +274,13 @@ def test_ranks_skeletons_and_G(name):
         Go = _split(o.export(exg), (m_o - k_o) * k_o)
         Gg = _split(g.export(side + "_G"), (m_g - k_g) * k_g)
         if not weak:
-            _check_h2_G(x, y, g, side, m_g, k_g, Go, Gg, CASES[name][1]["order"])
+            _check_h2_G(x, y, g, side, m_g, k_g, Go, Gg, CASES[name][1]["order"],
+                        CASES[name][1].get("basis", "chebyshev"))
         else:
             _check_hss_ids(x, y, g, side, m_g, k_g, g.export(side + "_sel"), Go, Gg,
                            CASES[name][1]["order"], keep,
-                           CASES[name][1].get("point_data") if side == "col" else None)
+                           CASES[name][1].get("point_data") if side == "col" else None,
+                           CASES[name][1].get("basis", "chebyshev"))
 
 
 # H^2 G = (R11^-1 R12)^T against the oracle's, per node relative to
@@ -284,7 +293,15 @@ def test_ranks_skeletons_and_G(name):
 H2_G_TOL = 1e-10
 
 
-def _check_h2_G(x, y, g, side, m, k, Go, Gg, order):
+def _basis(pts, lo, hi, order, basis):
+    """The far-field basis the construction used: interpolation (2.2) or, on
+    the line, the Taylor basis (2.4)-(2.5)."""
+    if basis == "taylor":
+        return O.taylor_basis(pts, float(lo[0]), float(hi[0]), order)
+    return O.interp_basis(pts, lo, hi, order)
+
+
+def _check_h2_G(x, y, g, side, m, k, Go, Gg, order, basis="chebyshev"):
     P = x if side == "row" else (x if y is None else y)
     perm = g.export("perm_x" if side == "row" else "perm_y")
     grid = _split(g.export(side + "_grid"), m)
@@ -300,7 +317,7 @@ def _check_h2_G(x, y, g, side, m, k, Go, Gg, order):
         if diff < H2_G_TOL:
             continue
         node = i + 1
-        U = O.interp_basis(P[perm[grid[i]]], bx[node, :d], bx[node, 3:3 + d], order)
+        U = _basis(P[perm[grid[i]]], bx[node, :d], bx[node, 3:3 + d], order, basis)
         cond = float(np.linalg.cond(U[sels[i][:int(k[i])]]))
         wide.append((node, diff, cond))
         assert diff <= 64 * np.finfo(np.float64).eps * cond, (side, node, diff, cond)
@@ -308,7 +325,8 @@ def _check_h2_G(x, y, g, side, m, k, Go, Gg, order):
           "; nodes above 1e-10 (node, diff, cond(C_S)):", wide, flush=True)
 
 
-def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep, pdata=None):
+def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep, pdata=None,
+                   basis="chebyshev"):
     """HSS: C = [U-hat, S] contains near-field singular vectors whose trailing
     members (sigma near eps_svd * sigma_1) are fixed only to about
     eps_mach / eps_svd, so two correct implementations agree on the skeleton
@@ -330,7 +348,7 @@ def _check_hss_ids(x, y, g, side, m, k, sel, Go, Gg, order, keep, pdata=None):
         assert np.max(np.abs(Gg[i])) <= 2.0 * (1 + 1e-8)
         pts = P[perm[grid[i]]]
         dd = P.shape[1]
-        U = O.interp_basis(pts, bx[node, :dd], bx[node, 3:3 + dd], order)
+        U = _basis(pts, bx[node, :dd], bx[node, 3:3 + dd], order, basis)
         if pdata is not None:  # double-layer column side: [m_1 U-hat, m_2 U-hat]
             md = pdata[perm[grid[i]]]
             U = np.concatenate([U * md[:, :1], U * md[:, 1:2]], axis=1)
@@ -943,3 +961,15 @@ def test_double_layer_gpu_against_dense_and_gauss():
     with pytest.raises(api.SmashError) as e:
         api.Smash(dev(pts), point_data=dev(data), coupling="evaluated", **kw)
     assert e.value.code == -2
+
+
+def test_taylor_basis_needs_points_on_the_line():
+    """The Taylor basis of eqs. (2.4)-(2.5) is defined here for points on the
+    line only: a 2D build asking for it is refused with SMASH_E_UNSUPPORTED."""
+    x = W.uniform(500, 2, 1)
+    with pytest.raises(api.SmashError) as e:
+        api.Smash(dev(x), kernel="log_r", leaf=32, order=6, adm="strong", tol=1e-8,
+                  basis="taylor")
+    assert e.value.code == -2
+    with pytest.raises(ValueError):
+        api.Smash(dev(W.uniform(500, 1, 1)), basis="legendre")
