@@ -658,7 +658,9 @@ def serve_bench(args, torch):
     for load in (0.5, 0.8, 1.0):
         rate = load * capacity
         kept = [] if load == 1.0 else None
-        mix = run(4, 64, trace(nreq, rate), kept)
+        # two worker streams: with four, concurrent 10^6-point constructions
+        # contend and every latency percentile was worse than with two
+        mix = run(2, 64, trace(nreq, rate), kept)
         plain = run(1, 1, trace(nreq, rate))
         res["loads"]["%.1f" % load] = {
             "rate_per_s": rate, "continuous_batching": mix, "plain_one_at_a_time": plain,
