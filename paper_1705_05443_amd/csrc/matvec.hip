@@ -335,12 +335,14 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < 4; u++) {
+          if (s0 + 4 * u >= kj) break;  // steps past row kj add only zeros (uniform in the wave)
 #pragma unroll
           for (int tt = 0; tt < TTS; tt++)
 #pragma unroll
             for (int c = 0; c < CT; c++)
               acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
+        }
       }
     }
     reduce_waves_n<T, MV_WAVES, TTS * CT>(acc, red);
@@ -414,6 +416,9 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
       const double *yb = ys[buf];
 #pragma unroll
       for (int u = 0; u < 4; u++) {
+        // steps wholly past row kj of q-hat_j would add only zeros: skipped
+        // (the same in every wave, which all walk this pair)
+        if (s0 + 4 * u >= kj) break;
         const int sr = 4 * u + lk;  // row of the chunk
         const bool ks = s0 + sr < kj;
         T bv[CT];
@@ -593,12 +598,14 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES) k_mv_near_out(NearArgs A,
           }
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++)
+        for (int u = 0; u < 4; u++) {
+          if (b0 + 4 * u >= nj) break;  // steps past column nj add only zeros (uniform in the wave)
 #pragma unroll
           for (int tt = 0; tt < TT; tt++)
 #pragma unroll
             for (int c = 0; c < CT; c++)
               acc[tt * CT + c] = Mfma<T>::op(av[u][tt], bv[u][c], acc[tt * CT + c]);
+        }
       }
     }
     reduce_waves_n<T, MV_WAVES, TT * CT>(acc, red);
