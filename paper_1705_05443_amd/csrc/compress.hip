@@ -2881,7 +2881,9 @@ void build_generators(Handle &h) {
               CsArgs c0 = cs;
               c0.first = rng;
               c0.cnt = rng + 1;
-              launch_wide(ia, c0, wgrid);
+              // (grids above DQ_MAXW * DQ_CPW points: none when the level's
+              // largest grid is at most that)
+              if (sc.mmax > DQ_MAXW * DQ_CPW) launch_wide(ia, c0, wgrid);
               DqArgs da{vals, nullptr, 0, ldc, exsv, dq_slot, dq_meta, dq_R, dq_I, cw * cw,
                         dq_gc, dq_cnt, (int64_t)200000000};
               for (int q = 1; q <= 5; q++) {
