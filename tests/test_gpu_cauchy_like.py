@@ -80,3 +80,26 @@ def test_cauchy_like_argument_errors():
     z = g.matvec_cauchy_like(q, dev(w), dev(v)).cpu().numpy()
     assert np.isfinite(z).all()
     g.close()
+
+
+@pytest.mark.parametrize("basis", ["chebyshev", "taylor"])
+def test_cauchy_like_distinct_counts_max_p_and_vector(basis):
+    """nx != ny, the largest generator count (SMASH_CAUCHY_LIKE_MAX_P = 16), a
+    single right-hand side passed as a vector, and the Taylor basis
+    (eqs. (2.4)-(2.5)) under the Cauchy matrix: still within 1e-10 of the
+    oracle's (6.2) product and within the construction's accuracy of (6.1)."""
+    nx, ny, p = 2000, 2600, 16
+    rng = np.random.default_rng(31)
+    x = np.sort(rng.random(nx))[:, None]
+    y = np.sort(rng.random(ny))[:, None] + 0.5 / ny
+    w, v = W.cauchy_like_generators(nx, ny, p, seed=8)
+    q = W.rhs(ny, 1, seed=9)[:, 0]
+    kw = dict(KW, basis=basis)
+    o = O.Oracle(x, y, kernel="cauchy", leaf=50, order=16, adm=0, tol=1e-8, eps_svd=1e-9,
+                 tau=0.6, basis=basis)
+    g = api.Smash(dev(x), dev(y), **kw)
+    z = g.matvec_cauchy_like(dev(q), dev(w), dev(v)).cpu().numpy()
+    assert z.shape == (nx,)
+    assert relerr(z, o.cauchy_like_matvec(w, v, q)) < 1e-10
+    assert relerr(z, O.cauchy_like_dense(x, y, w, v, q)) < 1e-7
+    g.close()
