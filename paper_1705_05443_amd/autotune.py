@@ -13,7 +13,9 @@ of one knob at a time (the others held at their best so far), with HIP
 events on the stream the product runs on, and returns the fastest shape.
 `main` runs it over workloads and writes the table `tuning.json` beside this
 file, keyed by a size bin; `Smash(..., tuned=True)` (the default) takes the
-launch shape of the nearest bin from it.
+launch shape of the nearest bin from it.  `order_for` picks the interpolation
+order for a tolerance: the smallest whose construction of a sample of the
+workload reaches it against exact rows.
 
     python -m paper_1705_05443_amd.autotune --write [--workloads a,b,...] [--apply p]
 """
@@ -110,6 +112,69 @@ def tune(x, y=None, nrhs=16, reps=10, seed=0, **kw):
         shape[knob] = best_v
     h.close()
     return {"shape": shape, "ms": best_ms, "trials": trials}
+
+
+def exact_rows(x, y, rows, Q, kernel, diag=0.0):
+    """Rows of A Q (original order) straight from the kernel's definition, in
+    FP64 on the device: 1/|x - y|, log|x - y|, exp(-|x - y|) or 1/(x - y) on
+    the line; points that coincide take `diag` (exp(-r): its value 1)."""
+    import torch
+    X = torch.as_tensor(x, dtype=torch.float64, device="cuda").reshape(len(x), -1)
+    Yp = X if y is None else torch.as_tensor(y, dtype=torch.float64,
+                                             device="cuda").reshape(len(y), -1)
+    Qd = torch.as_tensor(Q, dtype=torch.float64, device="cuda")
+    out = []
+    for a in range(0, len(rows), 16):
+        idx = torch.as_tensor(rows[a:a + 16], device="cuda")
+        D = X[idx][:, None, :] - Yp[None, :, :]
+        r = torch.sqrt((D * D).sum(-1))
+        same = r == 0
+        if kernel == "inv_r":
+            K = torch.where(same, diag, 1.0 / torch.where(same, 1.0, r))
+        elif kernel == "log_r":
+            K = torch.where(same, diag, torch.log(torch.where(same, 1.0, r)))
+        elif kernel == "exp_r":
+            K = torch.exp(-r)
+        elif kernel == "cauchy":
+            dd = D[..., 0]
+            K = torch.where(dd == 0, diag, 1.0 / torch.where(dd == 0, 1.0, dd))
+        else:
+            raise ValueError("exact rows: kernel %r not supported" % (kernel,))
+        out.append(K @ Qd)
+    return torch.cat(out).cpu().numpy()
+
+
+def order_for(x, y=None, *, kernel, tol, orders=range(3, 17), nrhs=4, nrows=256, seed=0,
+              **kw):
+    """Smallest interpolation order (Chebyshev points per axis, eq. (2.2)) whose
+    construction at relative rank tolerance `tol` gives a product within `tol`
+    of the exact one, relative Frobenius over `nrows` sampled rows and `nrhs`
+    N(0,1) right-hand sides: the order is taken from a measured accuracy, as the
+    paper ties the expansion order to the target accuracy (Sec. 6.1; the
+    far-field bound (2.9)).  Returns (order, error at that order, [(order,
+    error), ...] of the orders tried); if none reaches `tol`, the last one."""
+    import numpy as np
+    import torch
+
+    from . import api
+    X = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    Y = None if y is None else torch.from_numpy(np.ascontiguousarray(y)).cuda()
+    ny = len(x) if y is None else len(y)
+    q = np.random.default_rng(seed).standard_normal((ny, nrhs))
+    Q = torch.from_numpy(q).cuda()
+    rows = np.arange(0, len(x), max(1, len(x) // nrows))
+    zr = exact_rows(x, y, rows, q, kernel, diag=1.0 if kernel == "exp_r" else 0.0)
+    tried = []
+    for p in orders:
+        h = api.Smash(X, Y, kernel=kernel, order=int(p), tol=tol, apply_prec="f64",
+                      graphs=False, tuned=False, **kw)
+        z = h.matvec(Q).cpu().numpy()[rows]
+        h.close()
+        err = float(np.linalg.norm(z - zr) / np.linalg.norm(zr))
+        tried.append((int(p), err))
+        if err <= tol:
+            break
+    return tried[-1][0], tried[-1][1], tried
 
 
 def main(argv=None):

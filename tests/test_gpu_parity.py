@@ -973,3 +973,30 @@ def test_taylor_basis_needs_points_on_the_line():
     assert e.value.code == -2
     with pytest.raises(ValueError):
         api.Smash(dev(W.uniform(500, 1, 1)), basis="legendre")
+
+
+def test_order_for_a_tolerance_is_the_smallest_that_reaches_it():
+    """autotune.order_for: the returned order's product is within the tolerance
+    of exact rows and every smaller order tried is not; its exact rows equal
+    the oracle's dense rows (1/r in 3D, log r in 2D, 1/(x - y) on the line)."""
+    from paper_1705_05443_amd import autotune
+    x2 = W.uniform(6000, 2, 3)
+    p, err, tried = autotune.order_for(x2, kernel="log_r", tol=1e-6, leaf=64, adm="strong",
+                                       tau=0.7, root=((0.0, 0.0), 1.0))
+    print("log r 2D orders tried", tried, flush=True)
+    assert err <= 1e-6 and len(tried) >= 2
+    assert all(e > 1e-6 for _, e in tried[:-1])
+    x3 = W.clusters(6000, 3, 4)
+    p3, err3, tried3 = autotune.order_for(x3, kernel="inv_r", tol=1e-6, leaf=128,
+                                          adm="strong", tau=0.7, root=((0.0, 0.0, 0.0), 1.0),
+                                          orders=range(3, 9))  # p^3 <= 512 basis columns
+    print("1/r 3D orders tried", tried3, flush=True)
+    assert err3 <= 1e-6 and all(e > 1e-6 for _, e in tried3[:-1])
+    q = W.rhs(6000, 2, seed=5)
+    rows = np.arange(0, 6000, 97)
+    for xx, yy, kern in ((x3, None, "inv_r"), (x2, None, "log_r"),
+                         (*W.chebyshev_pair(6000, 2), "cauchy")):
+        zr = autotune.exact_rows(xx, yy, rows, q, kern)
+        zo = O.dense_rows(xx, xx if yy is None else yy, rows, q, kern)
+        assert relerr(zr, zo) < 1e-12, kern
+
