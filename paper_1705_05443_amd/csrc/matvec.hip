@@ -262,18 +262,19 @@ __device__ __forceinline__ T coupling_entry(const double *xp, const double *yp,
 // LDS (two buffers; the next chunk's loads are in flight while the current
 // one is contracted) and every q-hat value read from LDS feeds RTW matrix-
 // core steps.  Each lane evaluates the entries of B_ij it feeds.
-template <class T, int RTW, int CT, bool EVAL, int KID, int D>
+template <class T, int RTW, int CT, bool EVAL, int KID, int D, int KC = 16>
 __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
     k_mv_coupling_rows(CouplingArgs A, CouplingPts P, const T *__restrict__ qh,
                        T *__restrict__ zh, int RP, int nitems) {
   typedef typename Mfma<T>::acc_t acc_t;
+  static_assert(KC % 16 == 0, "chunks of whole 16-row groups");
   constexpr int QW = 16 * CT;                   // right-hand sides of a chunk row
-  constexpr int QE = 16 * QW;                   // values of a chunk
+  constexpr int QE = KC * QW;                   // values of a chunk (KC rows)
   constexpr int NT = MV_NT * MV_WAVES;
   constexpr int QPT = (QE + NT - 1) / NT;       // staged values per thread
   // row tiles of the pair-split path (nodes of up to 16 TTS rows take it)
   constexpr int TTS = (sizeof(T) == 8 && CT >= 3) ? 1 : MvShape<T, CT>::TT;
-  constexpr size_t SH_ROWS = sizeof(T) * 2 * QE + sizeof(double) * 2 * 16 * D;
+  constexpr size_t SH_ROWS = sizeof(T) * 2 * QE + sizeof(double) * 2 * KC * D;
   constexpr size_t SH_PAIRS = sizeof(T) * (MV_WAVES - 1) * TTS * CT * 4 * MV_NT;
   __shared__ __align__(16) unsigned char smem[SH_ROWS > SH_PAIRS ? SH_ROWS : SH_PAIRS];
   const int it = item_of_block(blockIdx.x, nitems, A.xrun);
@@ -359,7 +360,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
     return;
   }
   T (*qs)[QE] = (T (*)[QE])smem;
-  double (*ys)[16 * D] = (double (*)[16 * D])(smem + sizeof(T) * 2 * QE);
+  double (*ys)[KC * D] = (double (*)[KC * D])(smem + sizeof(T) * 2 * QE);
   for (int tb = 0; tb < nt; tb += MV_WAVES * RTW) {
     // coordinates of this lane's rows t = 16 (tb + w + 4 tt) + lr
     double xr[RTW][D];
@@ -388,7 +389,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
         const int r = q / QW, cc = q - r * QW;
         qv[e] = (q < QE && ss + r < kj) ? qj[(int64_t)(ss + r) * RP + cc] : (T)0;
       }
-      if (EVAL && tid < 16 * D) {
+      if (EVAL && tid < KC * D) {
         const int r = tid / D;
         yv = ss + r < kj ? P.ys[(A.hcol[j] + ss + r) * D + (tid - r * D)] : 0.0;
       }
@@ -402,11 +403,11 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
         const int q = tid + NT * e;
         if (q < QE) qs[buf][q] = qv[e];
       }
-      if (EVAL && tid < 16 * D) ys[buf][tid] = yv;
+      if (EVAL && tid < KC * D) ys[buf][tid] = yv;
       __syncthreads();
       const T *Bp = EVAL ? nullptr : Bv + A.boff[p];
       // the next chunk's loads, in flight during this chunk's steps
-      int pn = p, sn = s0 + 16;
+      int pn = p, sn = s0 + KC;
       if (sn >= kj) {
         pn = p + 1;
         sn = 0;
@@ -415,7 +416,7 @@ __global__ void __launch_bounds__(MV_NT *MV_WAVES, 2)
       const T *qb = qs[buf];
       const double *yb = ys[buf];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+      for (int u = 0; u < KC / 4; u++) {
         // steps wholly past row kj of q-hat_j would add only zeros: skipped
         // (the same in every wave, which all walk this pair)
         if (s0 + 4 * u >= kj) break;
@@ -463,7 +464,11 @@ template <class T, int CT, int KID, int D>
 static void launch_coupling_eval_kd(const CouplingArgs &ca, const CouplingPts &pts, const T *q,
                                     T *z, int RP, int nitems, hipStream_t s) {
   // four row tiles per wave: one pass covers nodes of up to 256 skeleton points
-  k_mv_coupling_rows<T, 4, CT, true, KID, D>
+  // chunks of 32 rows of q-hat_j per barrier where the registers allow it
+  // (the FP64 1/r and all FP32 forms); 16 otherwise.  Each accumulator adds
+  // its rows in the same order either way.
+  constexpr int KC = (KID == SMASH_KERNEL_INV_R || sizeof(T) == 4) ? 32 : 16;
+  k_mv_coupling_rows<T, 4, CT, true, KID, D, KC>
       <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, pts, q, z, RP, nitems);
   SMASH_CHECK_LAUNCH();
 }
