@@ -464,10 +464,10 @@ template <class T, int CT, int KID, int D>
 static void launch_coupling_eval_kd(const CouplingArgs &ca, const CouplingPts &pts, const T *q,
                                     T *z, int RP, int nitems, hipStream_t s) {
   // four row tiles per wave: one pass covers nodes of up to 256 skeleton points
-  // chunks of 32 rows of q-hat_j per barrier where the registers allow it
-  // (the FP64 1/r and all FP32 forms); 16 otherwise.  Each accumulator adds
-  // its rows in the same order either way.
-  constexpr int KC = (KID == SMASH_KERNEL_INV_R || sizeof(T) == 4) ? 32 : 16;
+  // chunks of 32 rows of q-hat_j per barrier where that costs no occupancy
+  // (the FP64 1/r form); 16 otherwise.  Each accumulator adds its rows in
+  // the same order either way.
+  constexpr int KC = (KID == SMASH_KERNEL_INV_R && sizeof(T) == 8) ? 32 : 16;
   k_mv_coupling_rows<T, 4, CT, true, KID, D, KC>
       <<<xcd_grid(nitems, ca.xrun), MV_NT * MV_WAVES, 0, s>>>(ca, pts, q, z, RP, nitems);
   SMASH_CHECK_LAUNCH();

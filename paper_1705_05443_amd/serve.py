@@ -46,6 +46,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 
+SMASH_E_OOM = -3  # the library's out-of-memory code
+
+
 @dataclass
 class Request:
     rid: int
@@ -60,6 +63,7 @@ class Request:
     result: np.ndarray | None = None
     error: str | None = None
     batch: int = 0                 # requests served by the same product launch
+    retries: int = 0               # constructions re-queued after running out of memory
 
 
 @dataclass
@@ -75,7 +79,8 @@ class Engine:
     def __init__(self, executor, budget_bytes: int, slots: int = 4, margin: float = 1.15,
                  ratio: float | None = None, max_batch_rhs: int = 64, lookahead: int = 8,
                  allow_evaluated: bool = True, shortest_first: bool = True,
-                 heavy_points: int = 200_000, max_heavy: int = 1, age_weight: float = 1.0):
+                 heavy_points: int = 200_000, max_heavy: int = 1, age_weight: float = 1.0,
+                 oom_retries: int = 2):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = int(slots)
@@ -90,6 +95,11 @@ class Engine:
         self.heavy_points = heavy_points
         self.max_heavy = max_heavy
         self.age_weight = age_weight
+        # a construction that fails for want of memory (SMASH_E_OOM: the
+        # reservation was met but the allocator could not place a block) is
+        # queued again, up to oom_retries times, and runs when memory frees up
+        self.oom_retries = oom_retries
+        self.requeue = []
         self.resident: dict[str, Resident] = collections.OrderedDict()
         self.sources = {}             # matrix -> (points, params) it was built from
         self.inflight = []            # (future, kind, requests, reserved bytes, matrix)
@@ -152,6 +162,8 @@ class Engine:
                 pending.append(reqs[i])
                 i += 1
             progressed = self._reap(done, building, now)
+            while self.requeue:
+                pending.appendleft(self.requeue.pop())
             progressed |= self._admit(pending, building, now, done)
             if not progressed:
                 if self.inflight or pending:
@@ -173,6 +185,15 @@ class Engine:
             try:
                 out = fut.result()
             except Exception as e:  # a failed request frees what it held
+                if (kind == "build" and getattr(e, "code", None) == SMASH_E_OOM
+                        and all(r.retries < self.oom_retries for r in group)):
+                    self.reserved -= resv
+                    building.discard(m)
+                    for r in group:
+                        r.retries += 1
+                    self.requeue.extend(group)
+                    self.log.append(("requeue", m))
+                    continue
                 for r in group:
                     r.error, r.done = str(e), t
                     done.append(r)
@@ -405,8 +426,13 @@ class GpuExecutor:
             # graphs off: a graph replays only for a repeated argument set
             # (the same X and Y buffers), which fresh per-request vectors
             # never are
-            h = api.Smash(X, stream=s, nrhs_hint=req.rhs.shape[1], allocator=self.allocator,
-                          graphs=False, **p)
+            try:
+                h = api.Smash(X, stream=s, nrhs_hint=req.rhs.shape[1],
+                              allocator=self.allocator, graphs=False, **p)
+            except api.SmashError as e:
+                if e.code == SMASH_E_OOM:
+                    torch.cuda.empty_cache()  # cached blocks back before a retry
+                raise
             dt = torch.float64 if h.apply_prec == "f64" else torch.float32
             Q = torch.from_numpy(np.ascontiguousarray(req.rhs)).to(dt).to("cuda")
             Z = h.matvec(Q, stream=s)

@@ -291,3 +291,48 @@ def test_constructions_reserve_their_peak_not_their_resident_size():
     assert len(done) == 16 and all(r.error is None for r in done)
     assert ex.live_max <= budget, ex.live_max
     assert eng.peak_ratios and max(eng.peak_ratios.values()) == 0.75
+
+
+class _Oom(RuntimeError):
+    code = -3  # SMASH_E_OOM
+
+
+class OomOnceExecutor(FakeExecutor):
+    """The first `fails` construction attempts of each matrix fail as the
+    library does when an allocation fails (an error whose code is
+    SMASH_E_OOM)."""
+
+    def __init__(self, slots, fails=1, **kw):
+        super().__init__(slots, **kw)
+        self.fails = fails
+        self.attempts = {}
+
+    def _build(self, req):
+        with self.lock:
+            a = self.attempts.get(req.matrix, 0)
+            self.attempts[req.matrix] = a + 1
+        if a < self.fails:
+            raise _Oom("allocator hook returned NULL")
+        return super()._build(req)
+
+
+def test_a_construction_that_runs_out_of_memory_is_queued_again():
+    ex = OomOnceExecutor(slots=2, fails=1)
+    eng = Engine(ex, budget_bytes=10**9, slots=2, margin=1.0)
+    done = eng.run([_req(0, 0.0, "m0", 100), _req(1, 0.0, "m1", 120)])
+    assert all(r.error is None for r in done) and len(done) == 2, [r.error for r in done]
+    assert all(r.retries == 1 for r in done)
+    assert ex.attempts == {"m0": 2, "m1": 2}
+    assert sum(1 for e in eng.log if e[0] == "requeue") == 2
+    assert eng.reserved == sum(r.bytes for r in eng.resident.values())
+    eng.close()
+
+
+def test_a_construction_that_keeps_running_out_of_memory_fails_after_the_retries():
+    ex = OomOnceExecutor(slots=1, fails=10)
+    eng = Engine(ex, budget_bytes=10**9, slots=1, margin=1.0, oom_retries=2)
+    done = eng.run([_req(0, 0.0, "m0", 100)])
+    assert len(done) == 1 and done[0].error is not None and done[0].retries == 2
+    assert ex.attempts["m0"] == 3
+    assert eng.reserved == 0
+    eng.close()
